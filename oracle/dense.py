@@ -1,0 +1,101 @@
+"""Dense brute force for tiny registers (n <= 4): a second, independent route.
+
+TEST INFRASTRUCTURE ONLY.  Every gate is tensored up to a full 2^n x 2^n
+matrix with Kronecker products and the ansatz unitary is formed by matrix
+products -- the O(2^{3n}) route the paper's appendix introduction rules out for
+real sizes, which makes it a good independent check at n <= 4.
+
+* rotation: scipy's matrix exponential of +i theta sigma / 2 (the paper's
+  convention, Sec. 2 rotation example);
+* its derivative: (i/2) sigma R(theta) (Sec. 2, Pauli-generator form);
+* CNOT and CZ: permutation / diagonal matrices written from their action on
+  basis states;
+* G, T from the definition (Sec. 1), E = <psi|H|psi>, grad E by its
+  definition as a vector of partial derivatives of <E> (Sec. 1).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg
+
+_PAULI = {
+    0: np.eye(2, dtype=np.complex128),
+    1: np.array([[0, 1], [1, 0]], dtype=np.complex128),
+    2: np.array([[0, -1j], [1j, 0]], dtype=np.complex128),
+    3: np.array([[1, 0], [0, -1]], dtype=np.complex128),
+}
+_KIND_TO_LETTER = {0: 1, 1: 2, 2: 3}
+
+
+def embed_1q(n: int, q: int, m: np.ndarray) -> np.ndarray:
+    """m acting on qubit q (bit q of the index; qubit n-1 is the leftmost factor)."""
+    out = np.ones((1, 1), dtype=np.complex128)
+    for k in reversed(range(n)):
+        out = np.kron(out, m if k == q else np.eye(2, dtype=np.complex128))
+    return out
+
+
+def gate_unitary(n: int, gate, theta, derivative: bool = False) -> np.ndarray:
+    kind, q0, q1, p = (int(v) for v in gate)
+    dim = 2 ** n
+    if kind == 3:   # CNOT control q0 target q1
+        m = np.zeros((dim, dim), dtype=np.complex128)
+        for x in range(dim):
+            y = x ^ ((1 << q1) if (x >> q0) & 1 else 0)
+            m[y, x] = 1.0
+        return m
+    if kind == 4:   # CZ
+        return np.diag([(-1.0) ** (((x >> q0) & 1) * ((x >> q1) & 1)) for x in range(dim)]).astype(np.complex128)
+    sigma = _PAULI[_KIND_TO_LETTER[kind]]
+    r = scipy.linalg.expm(0.5j * float(theta[p]) * sigma)
+    if derivative:
+        r = 0.5j * sigma @ r
+    return embed_1q(n, q0, r)
+
+
+def pauli_string(n: int, letters) -> np.ndarray:
+    out = np.ones((1, 1), dtype=np.complex128)
+    for k in reversed(range(n)):
+        out = np.kron(out, _PAULI[int(letters[k])])
+    return out
+
+
+def hamiltonian(problem) -> np.ndarray:
+    n = problem.n_qubits
+    h = np.zeros((2 ** n, 2 ** n), dtype=np.complex128)
+    for t in range(problem.n_terms):
+        h += problem.coeff[t] * pauli_string(n, problem.pauli[t])
+    return h
+
+
+def _input(problem) -> np.ndarray:
+    if problem.in_state is not None:
+        return np.asarray(problem.in_state, dtype=np.complex128)
+    v = np.zeros(2 ** problem.n_qubits, dtype=np.complex128)
+    v[0] = 1.0
+    return v
+
+
+def unitary(problem, deriv_param: int = -1) -> np.ndarray:
+    """U = G_M ... G_1 (or dU/dtheta_p when deriv_param = p)."""
+    n = problem.n_qubits
+    u = np.eye(2 ** n, dtype=np.complex128)
+    for g in problem.gates:
+        u = gate_unitary(n, g, problem.theta, derivative=(int(g[3]) == deriv_param and deriv_param >= 0)) @ u
+    return u
+
+
+def brute_force(problem):
+    """dict(psi, G, T, E, grad) by dense linear algebra."""
+    vin = _input(problem)
+    psi = unitary(problem) @ vin
+    P = problem.n_params
+    D = np.stack([unitary(problem, p) @ vin for p in range(P)]) if P else np.zeros((0, psi.shape[0]))
+    L = D.conj() @ D.T
+    T = D @ psi.conj()
+    G = L - np.outer(T.conj(), T)
+    H = hamiltonian(problem)
+    E = float(np.vdot(psi, H @ psi).real)
+    # d<psi|H|psi>/d theta_p = <d_p psi|H|psi> + <psi|H|d_p psi>
+    grad = np.array([(np.vdot(D[p], H @ psi) + np.vdot(psi, H @ D[p])).real for p in range(P)])
+    return {"psi": psi, "G": G, "T": T, "L": L, "E": E, "grad": grad}

@@ -1,0 +1,316 @@
+"""Pins of the FP64 CPU oracle to facts fixed by the paper and by mathematics.
+
+None of these tests retypes the oracle's own formulas: each compares it with a
+closed form derived by hand from the definitions, with an independent dense
+route (scipy matrix exponential + Kronecker products), with an exact identity
+(parameter shift), with finite differences, or with a structural invariant.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import dense
+import workloads as W
+
+
+def _problem(n, gates, theta, in_state=None, pauli=None, coeff=None):
+    gates = np.asarray(gates, dtype=np.int32).reshape(-1, 4)
+    if pauli is None:
+        pauli = np.zeros((1, n), dtype=np.uint8)
+        coeff = np.zeros(1)
+    return W.Problem(name="t", n_qubits=n, gates=gates, theta=np.asarray(theta, dtype=np.float64),
+                     pauli=np.asarray(pauli, dtype=np.uint8), coeff=np.asarray(coeff, dtype=np.float64),
+                     in_state=in_state)
+
+
+# ------------------------------------------------------------------ conventions
+
+def test_rotation_convention_matches_matrix_exponential():
+    """R_sigma(theta) = exp(+i theta sigma/2) (Sec. 2 rotation example): compare
+    the oracle's gate on every basis state with scipy's expm route."""
+    rng = np.random.default_rng(5)
+    for kind in (W.RX, W.RY, W.RZ):
+        th = rng.uniform(0, 2 * np.pi, size=1)
+        for q in range(3):
+            for deriv in (False, True):
+                u = dense.gate_unitary(3, (kind, q, -1, 0), th, derivative=deriv)
+                for x in range(8):
+                    e = np.zeros(8, dtype=np.complex128)
+                    e[x] = 1
+                    got = oracle.apply_gate(3, (kind, q, -1, 0), th, e, derivative=deriv)
+                    np.testing.assert_allclose(got, u[:, x], atol=1e-15)
+
+
+def test_rx_on_zero_closed_form():
+    """exp(i t X/2)|0> = cos(t/2)|0> + i sin(t/2)|1> (hand expansion of the exponential)."""
+    t = 0.7
+    e = np.array([1, 0], dtype=np.complex128)
+    got = oracle.apply_gate(1, (W.RX, 0, -1, 0), [t], e)
+    np.testing.assert_allclose(got, [math.cos(t / 2), 1j * math.sin(t / 2)], atol=1e-15)
+
+
+def test_fixed_gates_on_basis_states():
+    """CNOT flips the target iff the control is 1; CZ negates |11>; qubit q = bit q."""
+    for x in range(8):
+        e = np.zeros(8, dtype=np.complex128)
+        e[x] = 1
+        got = oracle.apply_gate(3, (W.CNOT, 0, 2, -1), [0.0], e)
+        y = x ^ (4 if x & 1 else 0)
+        assert got[y] == 1 and np.count_nonzero(got) == 1
+        got = oracle.apply_gate(3, (W.CZ, 1, 2, -1), [0.0], e)
+        assert got[x] == (-1 if (x & 2) and (x & 4) else 1)
+
+
+def test_pauli_sum_matches_dense_kronecker():
+    rng = np.random.default_rng(3)
+    for n in (1, 2, 3, 4):
+        pr = W.random_circuit(n, 4, seed=10 + n, n_terms=5)
+        pr.in_state = W.random_state(n, 20 + n)
+        got = oracle.apply_hamiltonian(pr, pr.in_state)
+        want = dense.hamiltonian(pr) @ pr.in_state
+        np.testing.assert_allclose(got, want, atol=1e-13)
+    del rng
+
+
+# --------------------------------------------------------- dense brute force
+
+@pytest.mark.parametrize("n,ngates,seed", [(1, 5, 1), (2, 9, 2), (3, 14, 3), (4, 18, 4), (4, 25, 5), (3, 30, 6)])
+def test_oracle_matches_dense_brute_force(n, ngates, seed):
+    pr = W.random_circuit(n, ngates, seed, n_terms=6)
+    if seed % 2 == 0:
+        pr.in_state = W.random_state(n, seed + 100)
+    bf = dense.brute_force(pr)
+    st = oracle.step(pr)
+    np.testing.assert_allclose(st["psi"], bf["psi"], atol=1e-13)
+    np.testing.assert_allclose(st["G"], bf["G"], atol=1e-13)
+    np.testing.assert_allclose(st["T"], bf["T"], atol=1e-13)
+    assert abs(st["E"] - bf["E"]) < 1e-12
+    np.testing.assert_allclose(st["grad"], bf["grad"], atol=1e-12)
+
+
+def test_oracle_matches_dense_on_small_hea():
+    pr = W.scaled(W.config1, 4, 2, n_terms=8)
+    bf = dense.brute_force(pr)
+    st = oracle.step(pr)
+    np.testing.assert_allclose(st["G"], bf["G"], atol=1e-13)
+    np.testing.assert_allclose(st["grad"], bf["grad"], atol=1e-12)
+    pr = W.scaled(W.config5, 3, 2, n_terms=8)
+    bf = dense.brute_force(pr)
+    st = oracle.step(pr)
+    np.testing.assert_allclose(st["G"], bf["G"], atol=1e-13)
+    np.testing.assert_allclose(st["grad"], bf["grad"], atol=1e-12)
+
+
+# ------------------------------------------------------------- closed forms
+# Single layers on |0...0> with no entanglers give product states, so G is
+# block diagonal over qubits.  Per qubit (paper's +i convention):
+#   RY(a): psi = (c, -s), d_a psi = (-s/2, -c/2)          -> G_aa = 1/4, T_a = 0
+#   RY(a) then RZ(b): psi = (c e^{ib/2}, -s e^{-ib/2})
+#       d_b psi = (i/2)(c e^{ib/2}, s e^{-ib/2})          -> T_b = (i/2) cos a,
+#       G_bb = 1/4 - |T_b|^2 = sin^2(a)/4,  G_ab = <d_a|d_b> = -(i/4) sin a
+#   RX(a) then RY(b): T_a = 0, T_b = (i/2) sin a, G_bb = cos^2(a)/4,
+#       G_ab = (1/4)<phi|XY|phi> = (i/4) cos a,  phi = RX(a)|0> = (c, i s)
+# (c = cos(a/2), s = sin(a/2)).
+
+def test_closed_form_ry_layer_and_rx_layer():
+    n = 5
+    rng = np.random.default_rng(7)
+    for kind in (W.RY, W.RX):
+        gates = [(kind, q, -1, q) for q in range(n)]
+        pr = _problem(n, gates, rng.uniform(0, 2 * np.pi, n))
+        G, T = oracle.metric(pr)
+        np.testing.assert_allclose(G, 0.25 * np.eye(n), atol=1e-15)
+        np.testing.assert_allclose(T, 0, atol=1e-15)
+
+
+def test_closed_form_ry_then_rz():
+    n = 4
+    rng = np.random.default_rng(8)
+    a = rng.uniform(0, 2 * np.pi, n)
+    b = rng.uniform(0, 2 * np.pi, n)
+    gates = [(W.RY, q, -1, q) for q in range(n)] + [(W.RZ, q, -1, n + q) for q in range(n)]
+    pr = _problem(n, gates, np.concatenate([a, b]))
+    G, T = oracle.metric(pr)
+    want = np.zeros((2 * n, 2 * n), dtype=np.complex128)
+    for q in range(n):
+        want[q, q] = 0.25
+        want[n + q, n + q] = 0.25 * math.sin(a[q]) ** 2
+        want[q, n + q] = -0.25j * math.sin(a[q])
+        want[n + q, q] = 0.25j * math.sin(a[q])
+    np.testing.assert_allclose(G, want, atol=1e-15)
+    np.testing.assert_allclose(T[n:], 0.5j * np.cos(a), atol=1e-15)
+    np.testing.assert_allclose(T[:n], 0, atol=1e-15)
+
+
+def test_closed_form_rx_then_ry():
+    n = 3
+    rng = np.random.default_rng(9)
+    a = rng.uniform(0, 2 * np.pi, n)
+    b = rng.uniform(0, 2 * np.pi, n)
+    gates = [(W.RX, q, -1, q) for q in range(n)] + [(W.RY, q, -1, n + q) for q in range(n)]
+    pr = _problem(n, gates, np.concatenate([a, b]))
+    G, T = oracle.metric(pr)
+    want = np.zeros((2 * n, 2 * n), dtype=np.complex128)
+    for q in range(n):
+        want[q, q] = 0.25
+        want[n + q, n + q] = 0.25 * math.cos(a[q]) ** 2
+        want[q, n + q] = 0.25j * math.cos(a[q])
+        want[n + q, q] = -0.25j * math.cos(a[q])
+    np.testing.assert_allclose(G, want, atol=1e-15)
+    np.testing.assert_allclose(T[n:], 0.5j * np.sin(a), atol=1e-15)
+
+
+def test_leading_rz_on_zero_state_has_zero_row():
+    """RZ first on |0>: only the global phase moves, so its G row and column vanish;
+    G_jj = 1/4 - |T_j|^2 with |T_j| = 1/2."""
+    pr = W.scaled(W.config3, 4, 1)
+    gates = np.concatenate([[[W.RZ, 2, -1, pr.n_params]], pr.gates]).astype(np.int32)
+    pr2 = _problem(4, gates, np.concatenate([pr.theta, [1.234]]))
+    G, T = oracle.metric(pr2)
+    p = pr.n_params
+    np.testing.assert_allclose(G[p, :], 0, atol=1e-15)
+    np.testing.assert_allclose(G[:, p], 0, atol=1e-15)
+    assert abs(abs(T[p]) - 0.5) < 1e-15
+
+
+# ---------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("cfg,n,layers", [(W.config1, 6, 3), (W.config2, 5, 3), (W.config5, 5, 2), (W.config3, 7, 2)])
+def test_metric_invariants(cfg, n, layers):
+    pr = W.scaled(cfg, n, layers)
+    G, T = oracle.metric(pr)
+    np.testing.assert_allclose(G, G.conj().T, atol=1e-14)            # Hermitian
+    assert np.linalg.eigvalsh(G).min() > -1e-12                       # PSD
+    assert np.linalg.eigvalsh(G.real).min() > -1e-12                  # Re G PSD
+    np.testing.assert_allclose(T.real, 0, atol=1e-14)                 # <psi|psi>=1 => Re T = 0
+    assert np.abs(T).max() <= 0.5 + 1e-14
+    np.testing.assert_allclose(np.diag(G).real, 0.25 - np.abs(T) ** 2, atol=1e-14)  # L_ii = 1/4
+    np.testing.assert_allclose(np.diag(G).imag, 0, atol=1e-14)
+
+
+def test_trailing_fixed_gates_leave_G_unchanged():
+    pr = W.scaled(W.config1, 5, 2)
+    G0, T0 = oracle.metric(pr)
+    extra = np.array([[W.CNOT, 0, 3, -1], [W.CZ, 1, 4, -1], [W.CNOT, 4, 2, -1]], dtype=np.int32)
+    pr2 = _problem(5, np.concatenate([pr.gates, extra]), pr.theta)
+    G1, T1 = oracle.metric(pr2)
+    np.testing.assert_allclose(G1, G0, atol=1e-14)
+
+
+def test_two_pi_shift_and_global_phase_invariance():
+    pr = W.scaled(W.config5, 4, 2, n_terms=6)
+    pr.in_state = W.random_state(4, 77)
+    st0 = oracle.step(pr)
+    th = pr.theta.copy()
+    th[[1, 5, 9]] += 2 * np.pi
+    pr2 = W.Problem(**{**pr.__dict__, "theta": th})
+    st1 = oracle.step(pr2)
+    np.testing.assert_allclose(st1["G"], st0["G"], atol=1e-13)
+    assert abs(st1["E"] - st0["E"]) < 1e-13
+    pr3 = W.Problem(**{**pr.__dict__, "in_state": pr.in_state * np.exp(0.83j)})
+    st3 = oracle.step(pr3)
+    np.testing.assert_allclose(st3["G"], st0["G"], atol=1e-13)
+    np.testing.assert_allclose(st3["grad"], st0["grad"], atol=1e-13)
+    assert abs(st3["E"] - st0["E"]) < 1e-13
+
+
+def test_zero_angles_z_hamiltonian_energy():
+    """theta = 0 on |0..0> leaves the state |0..0> (up to CNOTs acting trivially),
+    so a Z-only Hamiltonian has E = sum of coefficients."""
+    pr = W.scaled(W.config3, 5, 2, n_terms=7)
+    pr.theta[:] = 0.0
+    pr.pauli[:] = np.where(pr.pauli == 0, 0, 3)
+    assert abs(oracle.energy(pr) - pr.coeff.sum()) < 1e-14
+
+
+# -------------------------------------------------------------- gradient pins
+
+@pytest.mark.parametrize("cfg,n,layers", [(W.config1, 5, 2), (W.config2, 4, 3), (W.config5, 4, 2)])
+def test_gradient_parameter_shift_exact(cfg, n, layers):
+    """For single-Pauli rotations dE/dtheta_p = [E(theta + pi/2 e_p) - E(theta - pi/2 e_p)]/2."""
+    pr = W.scaled(cfg, n, layers, n_terms=9)
+    E, grad = oracle.energy_grad(pr)
+    shift = np.empty_like(grad)
+    for p in range(pr.n_params):
+        vals = []
+        for s in (+1, -1):
+            th = pr.theta.copy()
+            th[p] += s * np.pi / 2
+            vals.append(oracle.energy(W.Problem(**{**pr.__dict__, "theta": th})))
+        shift[p] = 0.5 * (vals[0] - vals[1])
+    np.testing.assert_allclose(grad, shift, atol=1e-12)
+
+
+def test_gradient_central_finite_difference():
+    pr = W.scaled(W.config3, 4, 2, n_terms=6)
+    E, grad = oracle.energy_grad(pr)
+    h = 1e-6
+    fd = np.empty_like(grad)
+    for p in range(pr.n_params):
+        th = pr.theta.copy(); th[p] += h
+        ep = oracle.energy(W.Problem(**{**pr.__dict__, "theta": th}))
+        th[p] -= 2 * h
+        em = oracle.energy(W.Problem(**{**pr.__dict__, "theta": th}))
+        fd[p] = (ep - em) / (2 * h)
+    np.testing.assert_allclose(grad, fd, atol=1e-8 * max(1.0, abs(E)))
+
+
+def test_metric_is_fubini_study_second_order():
+    """Re G is the Fubini-Study metric: 1 - |<psi(t)|psi(t+d)>|^2 = d^T (Re G) d + O(|d|^3)."""
+    pr = W.scaled(W.config2, 4, 2)
+    G, _ = oracle.metric(pr)
+    psi0 = oracle.forward(pr)
+    rng = np.random.default_rng(11)
+    d = rng.standard_normal(pr.n_params)
+    d /= np.linalg.norm(d)
+    for eps in (1e-3, 5e-4):
+        psi1 = oracle.forward(W.Problem(**{**pr.__dict__, "theta": pr.theta + eps * d}))
+        lhs = 1 - abs(np.vdot(psi0, psi1)) ** 2
+        rhs = eps ** 2 * d @ G.real @ d
+        assert abs(lhs - rhs) < 5 * eps ** 3
+
+
+# ------------------------------------------------------------------ the step
+
+def test_step_on_flat_metric_is_scaled_gradient():
+    """RY layer on |0..0>: G = I/4, so dtheta = -dt grad / (1/4 + eps) exactly."""
+    n = 5
+    pr = W.make_problem("ry", n, 1, (W.RY,), "none", 6, seed=3)
+    st = oracle.step(pr)
+    np.testing.assert_allclose(st["dtheta"], -pr.dt * st["grad"] / (0.25 + pr.tikhonov), rtol=1e-13, atol=1e-16)
+
+
+def test_step_descends_and_predicts_energy_change():
+    pr = W.scaled(W.config1, 5, 2, n_terms=10)
+    pr.dt = 1e-3
+    st = oracle.step(pr)
+    assert st["grad"] @ st["dtheta"] < 0
+    E1 = oracle.energy(W.Problem(**{**pr.__dict__, "theta": pr.theta + st["dtheta"]}))
+    lin = st["grad"] @ st["dtheta"]
+    assert abs((E1 - st["E"]) - lin) < 50 * np.linalg.norm(st["dtheta"]) ** 2 * (1 + np.abs(pr.coeff).sum())
+
+
+# ---------------------------------------------------- sampled entries route
+
+def test_selected_entries_match_full_metric():
+    """The column-subset route (derivative states for a few parameters) gives the
+    same entries as the full P x P evaluation."""
+    pr = W.scaled(W.config3, 6, 2)
+    G, T = oracle.metric(pr)
+    sel = [0, 5, 6, 11, 17, pr.n_params - 1]
+    Gs, Ts = oracle.metric(pr, sel)
+    np.testing.assert_allclose(Gs, G[np.ix_(sel, sel)], atol=1e-15)
+    np.testing.assert_allclose(Ts, T[sel], atol=1e-15)
+
+
+def test_parameter_relabelling_permutes_outputs():
+    pr = W.scaled(W.config5, 4, 1)
+    pp = W.permute_params(pr, 5)
+    G, T = oracle.metric(pr)
+    Gp, Tp = oracle.metric(pp)
+    rng = np.random.default_rng(5)
+    perm = rng.permutation(pr.n_params)
+    np.testing.assert_allclose(Gp[np.ix_(perm, perm)], G, atol=1e-15)
+    np.testing.assert_allclose(Tp[perm], T, atol=1e-15)

@@ -1,0 +1,219 @@
+"""Seeded synthetic inputs shared by the oracle side and the HIP side.
+
+This module only *describes* problems: gate lists, angles, Pauli-sum
+Hamiltonians and input states.  It applies no gate, evaluates no inner
+product and holds none of the method's arithmetic, so that the oracle
+(``oracle/``) and the GPU library (``paper_2011_02991_amd``) can both consume
+the same inputs while sharing no code.
+
+Problem statement (Jones, "Efficient classical calculation of the Quantum
+Natural Gradient", Sec. 2, problem statement of the ansatz): an ansatz is a
+product of P gates, each with its own parameter, acting on a fixed input state.
+The workloads below are "hardware-efficient" layered ansaetze: each layer is a
+set of single-qubit rotation sweeps followed by a fixed entangler.  Fixed
+entangling gates carry parameter index -1.
+
+Gate encoding (one row per gate, int32): ``(kind, q0, q1, param)``
+
+* kind 0/1/2 = RX/RY/RZ on qubit q0 (q1 = -1), rotation exp(+i theta sigma/2)
+  as written in Sec. 2 of the paper;
+* kind 3 = CNOT with control q0 and target q1;
+* kind 4 = CZ on qubits q0, q1.
+
+Qubit q is bit q of the amplitude index (qubit 0 is the least significant bit).
+Pauli letters are 0=I, 1=X, 2=Y, 3=Z, stored row-major as ``pauli[t, q]``.
+
+Draw order for every seeded problem, from ``numpy.random.Generator(PCG64(seed))``:
+angles (P values, uniform [0, 2 pi)), then Pauli letters (terms x n, uniform in
+{0,1,2,3}), then coefficients (terms values, standard normal).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+RX, RY, RZ, CNOT, CZ = 0, 1, 2, 3, 4
+KIND_NAMES = {RX: "RX", RY: "RY", RZ: "RZ", CNOT: "CNOT", CZ: "CZ"}
+ROTATION_KINDS = (RX, RY, RZ)
+
+
+@dataclasses.dataclass
+class Problem:
+    """One QNG problem instance: circuit, angles, Hamiltonian, input state."""
+
+    name: str
+    n_qubits: int
+    gates: np.ndarray            # (n_gates, 4) int32: kind, q0, q1, param
+    theta: np.ndarray            # (P,) float64
+    pauli: np.ndarray            # (terms, n) uint8 in {0,1,2,3}
+    coeff: np.ndarray            # (terms,) float64
+    in_state: Optional[np.ndarray] = None   # (2^n,) complex128, None = |0...0>
+    dt: float = 0.1
+    tikhonov: float = 1e-4
+    seed: int = 0
+
+    @property
+    def n_params(self) -> int:
+        return int(self.theta.shape[0])
+
+    @property
+    def n_gates(self) -> int:
+        return int(self.gates.shape[0])
+
+    @property
+    def n_terms(self) -> int:
+        return int(self.coeff.shape[0])
+
+
+def hea_gates(n: int, layers: int, rotations: Sequence[int], entangler: str) -> np.ndarray:
+    """Gate list of a layered hardware-efficient ansatz.
+
+    Each layer: for each rotation kind r in ``rotations``, r on every qubit
+    0..n-1 in increasing order; then the entangler.  ``entangler`` is
+    ``"cnot_chain"`` (CNOT q -> q+1 for q = 0..n-2, in that order),
+    ``"cz_ring"`` (CZ(q, (q+1) mod n) for q = 0..n-1) or ``"none"``.
+    Parameter indices follow the order in which rotations appear.
+    """
+    rows: List[List[int]] = []
+    p = 0
+    for _ in range(layers):
+        for r in rotations:
+            for q in range(n):
+                rows.append([int(r), q, -1, p])
+                p += 1
+        if entangler == "cnot_chain":
+            for q in range(n - 1):
+                rows.append([CNOT, q, q + 1, -1])
+        elif entangler == "cz_ring":
+            if n == 2:
+                rows.append([CZ, 0, 1, -1])
+            elif n > 2:
+                for q in range(n):
+                    rows.append([CZ, q, (q + 1) % n, -1])
+        elif entangler != "none":
+            raise ValueError(f"unknown entangler {entangler!r}")
+    return np.asarray(rows, dtype=np.int32).reshape(-1, 4)
+
+
+def draw_problem_data(seed: int, n_params: int, n_qubits: int, n_terms: int):
+    """Angles, Pauli letters and coefficients in the documented draw order."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    theta = rng.uniform(0.0, 2.0 * math.pi, size=n_params)
+    pauli = rng.integers(0, 4, size=(n_terms, n_qubits)).astype(np.uint8)
+    coeff = rng.standard_normal(n_terms)
+    return theta.astype(np.float64), pauli, coeff.astype(np.float64)
+
+
+def make_problem(name: str, n: int, layers: int, rotations: Sequence[int], entangler: str,
+                 n_terms: int, seed: int, dt: float = 0.1, tikhonov: float = 1e-4) -> Problem:
+    gates = hea_gates(n, layers, rotations, entangler)
+    n_params = int((gates[:, 3] >= 0).sum())
+    theta, pauli, coeff = draw_problem_data(seed, n_params, n, n_terms)
+    return Problem(name=name, n_qubits=n, gates=gates, theta=theta, pauli=pauli,
+                   coeff=coeff, dt=dt, tikhonov=tikhonov, seed=seed)
+
+
+# ----------------------------------------------------------------------------
+# The five workloads.  Sizes follow the synthetic hardware-efficient ansaetze
+# used to exercise the method; the paper itself runs no experiments.
+# ----------------------------------------------------------------------------
+
+def config1() -> Problem:
+    """n=10, 4 layers x [RY all, RZ all, CNOT chain], P=80, 20 terms."""
+    return make_problem("cfg1_n10_P80", 10, 4, (RY, RZ), "cnot_chain", 20, 1001)
+
+
+def config2() -> Problem:
+    """n=20, 10 layers x [RX all, RY all, CZ ring], P=400, 50 terms."""
+    return make_problem("cfg2_n20_P400", 20, 10, (RX, RY), "cz_ring", 50, 1002)
+
+
+def config3() -> Problem:
+    """n=26, 8 layers x [RY all, RZ all, CNOT chain], P=416, 100 terms."""
+    return make_problem("cfg3_n26_P416", 26, 8, (RY, RZ), "cnot_chain", 100, 1003)
+
+
+def config4() -> List[Problem]:
+    """64 ansaetze: n_b ~ U{12..22}, L_b ~ U{2..8}, [RY, RZ, CNOT chain], 30 terms.
+
+    The (n_b, L_b) pairs come from seed 1004 (all 64 qubit counts, then all 64
+    depths); ansatz b draws its angles and Hamiltonian from seed 40000 + b.
+    """
+    rng = np.random.Generator(np.random.PCG64(1004))
+    ns = rng.integers(12, 23, size=64)
+    ls = rng.integers(2, 9, size=64)
+    return [make_problem(f"cfg4_b{b}_n{int(ns[b])}_L{int(ls[b])}", int(ns[b]), int(ls[b]),
+                         (RY, RZ), "cnot_chain", 30, 40000 + b) for b in range(64)]
+
+
+def config5() -> Problem:
+    """n=24, 6 layers x [RX all, RY all, RZ all, CZ ring], P=432, 80 terms, dt=0.05."""
+    return make_problem("cfg5_n24_P432", 24, 6, (RX, RY, RZ), "cz_ring", 80, 1005, dt=0.05)
+
+
+CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
+
+
+def scaled(problem_fn, n: int, layers: int, n_terms: Optional[int] = None, seed: Optional[int] = None) -> Problem:
+    """A smaller instance with the same layer recipe as a named workload."""
+    base = {config1: ((RY, RZ), "cnot_chain", 20, 1001),
+            config2: ((RX, RY), "cz_ring", 50, 1002),
+            config3: ((RY, RZ), "cnot_chain", 100, 1003),
+            config5: ((RX, RY, RZ), "cz_ring", 80, 1005)}[problem_fn]
+    rots, ent, terms, s = base
+    return make_problem(f"{problem_fn.__name__}_scaled_n{n}_L{layers}", n, layers, rots, ent,
+                        n_terms if n_terms is not None else terms,
+                        seed if seed is not None else s)
+
+
+def random_circuit(n: int, n_gates: int, seed: int, fixed_fraction: float = 0.3,
+                   n_terms: int = 6) -> Problem:
+    """A random gate list over all five gate kinds (for small cross-checks).
+
+    Rotations get consecutive parameter indices; fixed gates pick random
+    distinct qubit pairs.  The angle/Hamiltonian draw order is the documented
+    one, using a second stream (seed + 1) for the gate structure.
+    """
+    srng = np.random.Generator(np.random.PCG64(seed + 1))
+    rows = []
+    p = 0
+    for _ in range(n_gates):
+        if n >= 2 and srng.uniform() < fixed_fraction:
+            kind = int(srng.integers(CNOT, CZ + 1))
+            a, b = srng.choice(n, size=2, replace=False)
+            rows.append([kind, int(a), int(b), -1])
+        else:
+            kind = int(srng.integers(RX, RZ + 1))
+            rows.append([kind, int(srng.integers(0, n)), -1, p])
+            p += 1
+    gates = np.asarray(rows, dtype=np.int32).reshape(-1, 4)
+    theta, pauli, coeff = draw_problem_data(seed, p, n, n_terms)
+    return Problem(name=f"random_n{n}_g{n_gates}_s{seed}", n_qubits=n, gates=gates,
+                   theta=theta, pauli=pauli, coeff=coeff, seed=seed)
+
+
+def permute_params(problem: Problem, seed: int) -> Problem:
+    """Same circuit with parameter indices relabelled by a random permutation.
+
+    theta is permuted consistently, so the ansatz state is unchanged and G is
+    only relabelled.  Used to test that outputs are indexed by parameter.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    P = problem.n_params
+    perm = rng.permutation(P)          # old index -> new index
+    gates = problem.gates.copy()
+    mask = gates[:, 3] >= 0
+    gates[mask, 3] = perm[gates[mask, 3]]
+    theta = np.empty_like(problem.theta)
+    theta[perm] = problem.theta
+    return dataclasses.replace(problem, name=problem.name + f"_perm{seed}", gates=gates, theta=theta)
+
+
+def random_state(n: int, seed: int) -> np.ndarray:
+    """A normalised random complex128 input state (Gaussian amplitudes)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    v = rng.standard_normal(2 ** n) + 1j * rng.standard_normal(2 ** n)
+    return (v / np.linalg.norm(v)).astype(np.complex128)
