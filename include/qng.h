@@ -1,0 +1,239 @@
+/*
+ * qng.h -- C ABI of the MI355X (gfx950) quantum-natural-gradient library.
+ *
+ * The library evaluates, for a unitary ansatz U = U_P ... U_1 with one unique
+ * parameter per parameterised gate acting on an input state |in>
+ * (Jones, "Efficient classical calculation of the Quantum Natural Gradient",
+ * Sec. 2 problem statement):
+ *
+ *   - the quantum geometric tensor G_ij = L_ij - T_i^* T_j (Sec. 2, assembly
+ *     equation; Sec. 1 definition), with L_ij = <d_i psi, d_j psi> and
+ *     T_i = <psi, d_i psi>, by the recurrent O(P^2)-gate, O(1)-state-vector
+ *     method of Sec. 3 (Alg. 1);
+ *   - the energy <E> = <psi|H|psi> of a Pauli-sum Hamiltonian and its gradient
+ *     vector (Sec. 1) by an O(P)-gate reverse sweep;
+ *   - the natural-gradient step g dtheta = -dt grad E with g = Re G
+ *     (Sec. 1), regularised as (Re G + eps I) dtheta = -dt grad E.
+ *
+ * Conventions (fixed for every entry point):
+ *   - Qubit q is bit q of the amplitude index (qubit 0 = least significant bit).
+ *   - A state of n qubits is 2^n complex amplitudes stored contiguously as
+ *     interleaved (re, im) pairs: FP64 pairs for complex128 inputs/outputs.
+ *   - Rotations use the paper's sign: R_sigma(theta) = exp(+i theta sigma / 2)
+ *     (Sec. 2, rotation example).  The common exp(-i theta sigma/2) convention
+ *     maps onto this one by theta -> -theta.
+ *   - Row/column i of G, entry i of T, grad and dtheta refer to PARAMETER
+ *     index i, not to gate position.
+ *   - Matrices are row-major; a complex P x P matrix is 2*P*P doubles.
+ *
+ * Ownership and errors:
+ *   - Every input pointer is borrowed for the duration of the call only.
+ *   - Host outputs are caller-allocated; on error they are not written.
+ *   - Host-pointer entry points are synchronous.  "_dev" entry points take
+ *     device pointers, enqueue their work on the context's stream and return
+ *     without waiting; their device outputs are valid once that stream has
+ *     reached the end of the call.
+ *   - A context owns its device workspace (grown on demand, freed by
+ *     qng_destroy) and, unless one was supplied, its HIP stream.  A context
+ *     must not be used from two threads at once.
+ *   - No C++ exception crosses this boundary.  Every call returns a
+ *     qng_status; on failure qng_last_error() describes the cause.
+ *   - All validation happens before any device work, so invalid inputs never
+ *     reach a kernel.
+ */
+#ifndef QNG_H
+#define QNG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QNG_OK = 0,
+    QNG_E_INVALID_ARG = -1,     /* null pointer, bad size, unknown option/precision */
+    QNG_E_BAD_CIRCUIT = -2,     /* qubit out of range, q0 == q1, unknown gate kind */
+    QNG_E_BAD_PARAMS = -3,      /* parameter indices are not a permutation of 0..P-1 */
+    QNG_E_NOT_NORMALIZED = -4,  /* | <in|in> - 1 | > 1e-12 */
+    QNG_E_NONFINITE = -5,       /* NaN/Inf in theta, dt, eps, coefficients or the input state */
+    QNG_E_OUT_OF_MEMORY = -6,   /* workspace above the device memory or the context's limit */
+    QNG_E_NOT_SPD = -7,         /* Re G + eps I is not positive definite (e.g. eps = 0, singular G) */
+    QNG_E_DEVICE = -8,          /* a HIP runtime call failed */
+    QNG_E_UNSUPPORTED = -9      /* valid request this build does not implement */
+} qng_status;
+
+typedef enum { QNG_RX = 0, QNG_RY = 1, QNG_RZ = 2, QNG_CNOT = 3, QNG_CZ = 4 } qng_gate_kind;
+
+/* Storage precision of the state vectors.  QNG_C64 keeps states and gate
+ * matrices in complex64 (rounded from FP64) while every inner product, the
+ * assembly of G and the solve stay in FP64. */
+typedef enum { QNG_C128 = 0, QNG_C64 = 1 } qng_precision;
+
+/* One gate.  Rotations (RX/RY/RZ): q0 = target, q1 = -1, param = its parameter
+ * index (>= 0).  CNOT: q0 = control, q1 = target, param = -1.  CZ: q0, q1 the
+ * two qubits, param = -1.  Gates act in array order: gates[0] first. */
+typedef struct { int32_t kind, q0, q1, param; } qng_gate;
+
+/* An ansatz: n_params parameterised rotations whose param fields form a
+ * permutation of 0..n_params-1 (one unique parameter per gate, Sec. 2), plus
+ * any number of fixed CNOT/CZ gates. */
+typedef struct {
+    int32_t n_qubits;
+    int32_t n_gates;
+    int32_t n_params;
+    const qng_gate *gates;
+} qng_circuit;
+
+/* H = sum_t coeff[t] * (Pauli string t); pauli[t*n_qubits + q] in
+ * {0=I, 1=X, 2=Y, 3=Z} acts on qubit q.  Host pointers. */
+typedef struct {
+    int32_t n_terms;
+    const double *coeff;
+    const uint8_t *pauli;
+} qng_pauli_sum;
+
+typedef struct qng_ctx qng_ctx;
+
+/* Options for qng_set_option. */
+typedef enum {
+    QNG_OPT_FUSION = 0,          /* 1 (default): tiled fused sweep passes; 0: one kernel per primitive */
+    QNG_OPT_TILE_QUBITS = 1,     /* qubits per on-chip tile of a fused pass (0 = automatic) */
+    QNG_OPT_COLUMN_STREAMS = 2,  /* columns swept concurrently, each with its own 2 states (0 = automatic) */
+    QNG_OPT_PROFILE = 3,         /* 1: time every sweep-pass launch with HIP events (see qng_stats) */
+    QNG_OPT_SMALL_N_KERNEL = 4   /* 1 (default): whole-column on-chip kernel for small registers */
+} qng_option;
+
+/* Counters of the last metric/energy/step call on a context. */
+typedef struct {
+    int64_t sweep_launches;      /* launches of the fused sweep-pass kernel */
+    int64_t sweep_tiles;         /* tiles processed by those launches */
+    double  sweep_ms;            /* summed HIP-event duration of those launches (QNG_OPT_PROFILE) */
+    double  sweep_bytes;         /* algorithmic HBM bytes of those launches: read+write of 2 states per pass */
+    int64_t elements;            /* L_ij (i<j) elements evaluated */
+    int64_t other_launches;      /* every other kernel launch */
+    double  metric_ms;           /* wall-clock of the metric part (G) */
+    double  grad_ms;             /* wall-clock of energy + gradient */
+    double  solve_ms;            /* wall-clock of the FP64 solve */
+} qng_stats;
+
+/* Plan of a circuit under the current options (host only, no device work). */
+typedef struct {
+    int64_t passes;              /* fused sweep passes over all columns */
+    int64_t elements;            /* P(P-1)/2 */
+    int64_t ops;                 /* gate applications + inner products inside those passes */
+    int64_t load_maps;           /* passes that start with a permuted (CNOT) gather */
+    int32_t tile_qubits;         /* qubits per tile used by the plan */
+    int32_t small_n;             /* 1 if the whole-column on-chip kernel is used */
+} qng_plan_info;
+
+/* ----------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`.  hip_stream: a hipStream_t to run
+ * on, or NULL for a context-owned stream.  QNG_E_DEVICE if the device is absent. */
+qng_status qng_create(qng_ctx **out, int device, void *hip_stream);
+void qng_destroy(qng_ctx *ctx);
+/* Message for the last failing call on ctx (or for the last failing qng_create
+ * / host-only call when ctx is NULL).  Never NULL. */
+const char *qng_last_error(const qng_ctx *ctx);
+/* Run the context's work on hip_stream from now on.  NULL selects the HIP null
+ * stream (ordered with all null-stream work, e.g. PyTorch's default stream);
+ * a stream the context created itself is released. */
+qng_status qng_set_stream(qng_ctx *ctx, void *hip_stream);
+/* Cap on the workspace the context may allocate; 0 = device memory only.
+ * A call whose workspace exceeds it fails with QNG_E_OUT_OF_MEMORY. */
+qng_status qng_set_mem_limit(qng_ctx *ctx, size_t bytes);
+qng_status qng_set_option(qng_ctx *ctx, int option, int value);
+qng_status qng_get_stats(const qng_ctx *ctx, qng_stats *out);
+/* Synchronise the context's stream. */
+qng_status qng_synchronize(qng_ctx *ctx);
+
+/* ---------------------------------------------- host-only (no GPU needed) */
+
+/* Validate a circuit, parameters and (nullable) Hamiltonian without touching
+ * a device.  Same rules and status codes as the compute entry points.  msg
+ * (nullable) receives a description of the first problem found. */
+qng_status qng_validate(const qng_circuit *circ, const double *theta, const qng_pauli_sum *ham,
+                        char *msg, size_t msg_len);
+/* Compile the sweep plan of a circuit for the given fusion mode and tile width
+ * (0 = automatic) and report its size.  Host only. */
+qng_status qng_plan(const qng_circuit *circ, int fusion, int tile_qubits, qng_plan_info *out);
+/* Export the fused sweep plan (host only): one row of 10 int32 per operation,
+ * in execution order: {column s, pass index within the column, op type
+ * (0 rotation adjoint, 1 inner product then rotation adjoint, 2 inner product,
+ * 3 CNOT adjoint, 4 CZ, 5 Z inner product outside the tile), qubit q0, qubit q1
+ * (CNOT target / CZ second qubit, else -1), gate position (or -1), destination
+ * r*P + s of an inner product (or -1), Pauli axis (0 X, 1 Y, 2 Z; or -1),
+ * tile-qubit mask bits 0..30, tile-qubit mask bits 31..61}.  amp_bytes: 16 for
+ * complex128 plans, 8 for complex64.  With rows = NULL only *n_rows is set. */
+qng_status qng_plan_export(const qng_circuit *circ, int tile_qubits, int amp_bytes, int32_t *rows, int64_t cap,
+                           int64_t *n_rows);
+/* Solve (Re G + eps I) x = b in FP64 by Cholesky (host).  G: 2*P*P doubles
+ * (complex, row-major), b, x: P doubles.  QNG_E_NOT_SPD if not positive definite. */
+qng_status qng_solve_shifted(int32_t P, const double *G, double eps, const double *b, double *x);
+
+/* ------------------------------------------------- host-pointer entry points */
+
+/* Quantum geometric tensor by the recurrent method (Sec. 3, Alg. 1).
+ * in_state: 2*2^n doubles (complex128) or NULL for |0...0>.  theta: P doubles.
+ * G_out: 2*P*P doubles.  T_out: 2*P doubles or NULL. */
+qng_status qng_metric(qng_ctx *ctx, const qng_circuit *circ, const double *in_state,
+                      const double *theta, qng_precision prec, double *G_out, double *T_out);
+
+/* Energy E = Re <psi|H|psi> and its gradient dE/dtheta (P doubles) by the
+ * reverse sweep (Sec. 1 definitions; O(P) gates, O(1) states). */
+qng_status qng_energy_grad(qng_ctx *ctx, const qng_circuit *circ, const double *in_state,
+                           const qng_pauli_sum *ham, const double *theta, qng_precision prec,
+                           double *E_out, double *grad_out);
+
+/* One natural-gradient step (Sec. 1): dtheta solving (Re G + eps I) dtheta = -dt grad E.
+ * G_out (2*P*P), grad_out (P), E_out (1) are optional (NULL = not returned). */
+qng_status qng_step(qng_ctx *ctx, const qng_circuit *circ, const double *in_state,
+                    const qng_pauli_sum *ham, const double *theta, double dt, double tikhonov,
+                    qng_precision prec, double *dtheta_out, double *G_out, double *grad_out,
+                    double *E_out);
+
+/* B independent steps, one per ansatz (each its own circuit, input state,
+ * Hamiltonian and theta; n and P may differ).  Array-of-pointer arguments have
+ * B entries; in_states[b] may be NULL (|0...0>); G_out/grad_out/E_out may be
+ * NULL as a whole.  The ansaetze are swept together: every launch carries
+ * tiles of several ansaetze. */
+qng_status qng_step_batched(qng_ctx *ctx, int32_t B, const qng_circuit *circs,
+                            const double *const *in_states, const qng_pauli_sum *hams,
+                            const double *const *thetas, double dt, double tikhonov,
+                            qng_precision prec, double *const *dtheta_out, double *const *G_out,
+                            double *const *grad_out, double *E_out);
+
+/* ------------------------------------------------- device-pointer entry points
+ * Device buffers: in_state_dev is complex128 (2*2^n doubles) or NULL;
+ * outputs are FP64 device buffers of the sizes given above.  theta stays a
+ * host pointer (the gate matrices are built on the host). */
+
+qng_status qng_metric_dev(qng_ctx *ctx, const qng_circuit *circ, const void *in_state_dev,
+                          const double *theta, qng_precision prec, void *G_dev, void *T_dev);
+
+/* Energy only: writes E (1 double) to E_dev and the final ansatz state psi
+ * (complex128, 2*2^n doubles) to psi_dev, for a later qng_energy_grad_from_state_dev. */
+qng_status qng_energy_dev(qng_ctx *ctx, const qng_circuit *circ, const void *in_state_dev,
+                          const qng_pauli_sum *ham, const double *theta, qng_precision prec,
+                          void *E_dev, void *psi_dev);
+
+/* Gradient by the reverse sweep, starting from a final state psi_dev produced by
+ * qng_energy_dev for the same circuit/theta (it is read, not modified). */
+qng_status qng_energy_grad_from_state_dev(qng_ctx *ctx, const qng_circuit *circ,
+                                          const qng_pauli_sum *ham, const double *theta,
+                                          qng_precision prec, const void *psi_dev, void *grad_dev);
+
+/* Apply the ansatz (every gate, in order) to a device state in place:
+ * state_dev <- U(theta) state_dev (Sec. 2, psi = U|in>).  The state has the
+ * storage type of prec: complex128 (QNG_C128) or complex64 (QNG_C64), 2^n
+ * amplitudes.  Asynchronous on the context's stream; no workspace. */
+qng_status qng_apply_circuit_dev(qng_ctx *ctx, const qng_circuit *circ, const double *theta, qng_precision prec,
+                                 void *state_dev);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QNG_H */

@@ -1,0 +1,814 @@
+// api.cpp -- the C ABI (include/qng.h): context, validation, workspace and the
+// drivers of the recurrent metric, the reverse-sweep gradient and the step.
+//
+// Recurrence used by every driver (Sec. 2 recurrences and Sec. 3 Alg. 1,
+// rewritten with the Pauli-generator form of the gate derivative, Sec. 2):
+// for a rotation R_r = exp(i theta_r sigma_r / 2), dR_r/dtheta_r =
+// (i/2) sigma_r R_r.  Let y_s be the state just before rotation s (all earlier
+// gates applied) and V_{rs} the gates strictly between rotations r < s.  Then
+//
+//   L_rs = <d_r psi | d_s psi> = 1/4 <V^dag y_s | sigma_r | V^dag sigma_s y_s>,
+//   T_s  = <psi | d_s psi>      = (i/2) <y_s | sigma_s | y_s>,   L_ss = 1/4.
+//
+// So column s starts from lambda = y_s, phi = sigma_s y_s (the paper's seed
+// phi = dU_s psi_{s-1} after its first U_s^dag) and sweeps both registers
+// backwards through the same adjoint gates; just before the adjoint of
+// rotation r would be applied, <lambda|sigma_r|phi> is the paper's
+// <mu|phi> = <dU_r lambda_{r-1} | phi> (mu := lambda; mu <- dU_r, never
+// materialised since dU_r U_r^dag = (i/2) sigma_r).  psi advances by the gates
+// between consecutive rotations (the paper's psi <- U_j).  O(P^2) gates, a
+// constant number of state vectors.
+//
+// Energy gradient: d_r E = 2 Re <H psi | d_r psi>.  With lambda = H psi and
+// phi = psi swept backwards from the last gate, d_r E = -Im <lambda|sigma_r|phi>
+// at the same point of the sweep: O(P) gates, two registers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "circuit.hpp"
+#include "kernels.hpp"
+#include "fused.hpp"
+#include "sweep.hpp"
+
+namespace qng {
+void solve_shifted(int P, const double *G, double eps, const double *b, double *x);
+}
+
+using namespace qng;
+
+struct qng_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    size_t mem_limit = 0;
+    int opt_fusion = 1, opt_tile = 0, opt_streams = 0, opt_profile = 0, opt_small = 1;
+    std::string last_error;
+    qng_stats stats{};
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    SweepCache sweep_cache;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+#define HIPCHECK(call)                                                                                      \
+    do {                                                                                                    \
+        hipError_t _e = (call);                                                                             \
+        if (_e != hipSuccess) fail(QNG_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(_e));       \
+    } while (0)
+
+template <typename F> qng_status guarded(qng_ctx *ctx, F &&f) {
+    try {
+        f();
+        return QNG_OK;
+    } catch (const Error &e) {
+        if (ctx) ctx->last_error = e.msg;
+        g_last_error = e.msg;
+        return e.status;
+    } catch (hipError_t e) {
+        std::string m = std::string("HIP error: ") + hipGetErrorString(e);
+        if (ctx) ctx->last_error = m;
+        g_last_error = m;
+        return QNG_E_DEVICE;
+    } catch (const std::bad_alloc &) {
+        if (ctx) ctx->last_error = "host out of memory";
+        g_last_error = "host out of memory";
+        return QNG_E_OUT_OF_MEMORY;
+    } catch (...) {
+        if (ctx) ctx->last_error = "unknown error";
+        g_last_error = "unknown error";
+        return QNG_E_DEVICE;
+    }
+}
+
+using Clock = std::chrono::steady_clock;
+inline double ms_since(Clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+constexpr int kMaxQubitsC128 = 32;
+constexpr int kMaxQubitsC64 = 33;
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+DevMat2 dev(const Mat2 &m) {
+    return DevMat2{m.a.real(), m.a.imag(), m.b.real(), m.b.imag(), m.c.real(), m.c.imag(), m.d.real(), m.d.imag()};
+}
+
+void check_in_state_host(int n, const double *in) {
+    if (!in) return;
+    const uint64_t dim = uint64_t(1) << n;
+    double s = 0.0;
+    for (uint64_t x = 0; x < 2 * dim; ++x) {
+        if (!std::isfinite(in[x])) fail(QNG_E_NONFINITE, "input state is not finite");
+        s += in[x] * in[x];
+    }
+    if (std::fabs(s - 1.0) > 1e-12) fail(QNG_E_NOT_NORMALIZED, "input state is not normalised (<in|in> - 1 = " +
+                                                                   std::to_string(s - 1.0) + ")");
+}
+
+// -------------------------------------------------------------- workspace
+
+struct Layout {
+    size_t states = 0;      // offset of the state registers
+    int n_states = 0;
+    size_t state_bytes = 0;
+    size_t staging = 0;     // complex128 copy of a host input state
+    size_t partials = 0;    // reduction scratch
+    size_t lraw = 0, traw = 0, graw = 0, eraw = 0, gout = 0, tout = 0, param_of = 0;
+    size_t sweep = 0, sweep_bytes = 0;  // fused-sweep descriptors and partial sums
+    size_t total = 0;
+};
+
+Layout plan_layout(int n, int P, size_t amp_bytes, int n_states, bool staging, size_t sweep_bytes) {
+    Layout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+    L.state_bytes = (size_t(1) << n) * amp_bytes;
+    L.n_states = n_states;
+    L.states = take(L.state_bytes * n_states);
+    L.staging = staging ? take((size_t(1) << n) * 16) : 0;
+    L.partials = take((size_t)reduce_blocks(n) * 16 + 16);
+    L.lraw = take((size_t)P * P * 16 + 16);
+    L.traw = take((size_t)P * 16 + 16);
+    L.graw = take((size_t)P * 16 + 16);
+    L.eraw = take(16);
+    L.gout = take((size_t)P * P * 16 + 16);
+    L.tout = take((size_t)P * 16 + 16);
+    L.param_of = take((size_t)P * 4 + 4);
+    L.sweep_bytes = sweep_bytes;
+    L.sweep = take(sweep_bytes + 16);
+    L.total = off;
+    return L;
+}
+
+char *ensure_workspace(qng_ctx *ctx, size_t bytes) {
+    if (ctx->mem_limit && bytes > ctx->mem_limit)
+        fail(QNG_E_OUT_OF_MEMORY, "workspace of " + std::to_string(bytes) + " bytes exceeds the context limit of " +
+                                      std::to_string(ctx->mem_limit));
+    if (bytes <= ctx->ws_bytes) return (char *)ctx->ws;
+    if (ctx->ws) {
+        HIPCHECK(hipStreamSynchronize(ctx->stream));
+        HIPCHECK(hipFree(ctx->ws));
+        ctx->ws = nullptr;
+        ctx->ws_bytes = 0;
+    }
+    size_t free_b = 0, total_b = 0;
+    HIPCHECK(hipMemGetInfo(&free_b, &total_b));
+    if (bytes > free_b)
+        fail(QNG_E_OUT_OF_MEMORY, "workspace of " + std::to_string(bytes) + " bytes exceeds free device memory (" +
+                                      std::to_string(free_b) + ")");
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(QNG_E_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    ctx->ws = p;
+    ctx->ws_bytes = bytes;
+    return (char *)p;
+}
+
+// -------------------------------------------------------------- the engine
+
+struct Problem {
+    Circuit circ;
+    std::vector<Mat2> fwd, adj;       // per gate position (rotations only)
+    std::vector<int> param_of;        // rotation (list order) -> parameter index
+    std::vector<PauliTerm> ham;
+    bool has_ham = false;
+};
+
+Problem make_problem(const qng_circuit *c, const double *theta, const qng_pauli_sum *h) {
+    Problem p;
+    p.circ = compile_circuit(c);
+    p.fwd.resize(p.circ.M);
+    p.adj.resize(p.circ.M);
+    for (const Rot &r : p.circ.rots) {
+        p.fwd[r.pos] = rotation(r.axis, theta[r.param]);
+        p.adj[r.pos] = adjoint(p.fwd[r.pos]);
+        p.param_of.push_back(r.param);
+    }
+    if (h) {
+        p.ham = compile_hamiltonian(c, h);
+        p.has_ham = true;
+    }
+    return p;
+}
+
+template <typename R> struct Engine {
+    qng_ctx *ctx;
+    const Problem &pb;
+    char *base;
+    Layout L;
+    hipStream_t st;
+    int n;
+
+    void *state(int k) const { return base + L.states + (size_t)k * L.state_bytes; }
+    double *partials() const { return (double *)(base + L.partials); }
+    double *lraw() const { return (double *)(base + L.lraw); }
+    double *traw() const { return (double *)(base + L.traw); }
+    double *graw() const { return (double *)(base + L.graw); }
+    double *eraw() const { return (double *)(base + L.eraw); }
+
+    void apply(int pos, bool adjoint_gate, void *s0, void *s1) {
+        const qng_gate &g = pb.circ.gates[pos];
+        ++ctx->stats.other_launches;
+        if (g.kind == QNG_CNOT) launch_cnot<R>(s0, s1, n, g.q0, g.q1, st);
+        else if (g.kind == QNG_CZ) launch_cz<R>(s0, s1, n, g.q0, g.q1, st);
+        else launch_apply_1q<R>(s0, s1, n, g.q0, dev(adjoint_gate ? pb.adj[pos] : pb.fwd[pos]), st);
+    }
+
+    void prod(const void *a, const void *b, int q, int axis, double *dest) {
+        ctx->stats.other_launches += 2;
+        launch_pauli_prod<R>(a, b, n, q, axis, partials(), dest, st);
+    }
+
+    // psi (state 0) <- |in>.  in_c128: device complex128 or nullptr.
+    void init(const void *in_c128) {
+        ++ctx->stats.other_launches;
+        launch_init_state<R>(state(0), n, in_c128, st);
+    }
+
+    // Recurrent metric, one kernel per primitive.  On return psi holds y_{P-1}
+    // (the state just before the last rotation) and `pos` its gate position.
+    int metric_unfused() {
+        const Circuit &c = pb.circ;
+        void *psi = state(0), *lam = state(1), *phi = state(2);
+        int pos = 0;
+        const int p0 = c.P ? c.rots[0].pos : 0;
+        for (int s = 0; s < c.P; ++s) {
+            const Rot &rs = c.rots[s];
+            for (; pos < rs.pos; ++pos) apply(pos, false, psi, nullptr);   // psi <- gates up to rotation s
+            prod(psi, psi, rs.qubit, rs.axis, traw() + 2 * s);              // <y_s|sigma_s|y_s>
+            if (s == 0) continue;
+            ++ctx->stats.other_launches;
+            launch_seed<R>(psi, lam, phi, n, rs.qubit, rs.axis, st);
+            for (int k = rs.pos - 1; k >= p0; --k) {
+                const int r = c.rot_at[k];
+                if (r >= 0) {
+                    const Rot &rr = c.rots[r];
+                    prod(lam, phi, rr.qubit, rr.axis, lraw() + 2 * ((size_t)r * c.P + s));
+                    ++ctx->stats.elements;
+                    if (k > p0) apply(k, true, lam, phi);
+                } else {
+                    apply(k, true, lam, phi);
+                }
+            }
+        }
+        return pos;
+    }
+
+    // From psi at gate position pos: finish the forward pass, lambda = H psi,
+    // E = <psi|lambda>, then the reverse sweep for the gradient.  If keep_psi,
+    // the final state is copied to state(3) before the sweep modifies psi.
+    void energy_grad_unfused(int pos, bool want_grad, void *psi_copy_c128) {
+        const Circuit &c = pb.circ;
+        void *psi = state(0), *lam = state(1);
+        for (; pos < c.M; ++pos) apply(pos, false, psi, nullptr);
+        if (psi_copy_c128) { ++ctx->stats.other_launches; launch_to_c128<R>(psi, psi_copy_c128, n, st); }
+        hamiltonian(psi, lam);
+        prod(psi, lam, 0, -1, eraw());
+        if (!want_grad || c.P == 0) return;
+        const int p0 = c.rots[0].pos;
+        for (int k = c.M - 1; k >= p0; --k) {
+            const int r = c.rot_at[k];
+            if (r >= 0) {
+                const Rot &rr = c.rots[r];
+                prod(lam, psi, rr.qubit, rr.axis, graw() + 2 * r);
+                if (k > p0) apply(k, true, lam, psi);
+            } else {
+                apply(k, true, lam, psi);
+            }
+        }
+    }
+
+    void hamiltonian(const void *psi, void *out) {
+        if (pb.ham.empty()) {
+            HIPCHECK(hipMemsetAsync(out, 0, L.state_bytes, st));
+            return;
+        }
+        for (size_t t = 0; t < pb.ham.size(); ++t) {
+            const PauliTerm &h = pb.ham[t];
+            ++ctx->stats.other_launches;
+            launch_pauli_term<R>(psi, out, n, h.flip, h.zy, h.n_y, h.coeff, t == 0, st);
+        }
+    }
+};
+
+struct CallSpec {
+    bool metric = false, grad = false;
+    const double *in_host = nullptr;      // complex128 host input (nullable)
+    const void *in_dev = nullptr;         // complex128 device input (nullable)
+    void *psi_out_dev = nullptr;          // complex128 device copy of the final state (nullable)
+    bool host_call = false;               // synchronous host-pointer entry point: time each phase
+    const void *psi_final_dev = nullptr;  // gradient from a given final state (nullable)
+};
+
+struct CallResult {
+    // device pointers into the workspace
+    double *G = nullptr, *T = nullptr, *graw = nullptr, *eraw = nullptr;
+    const int *param_of = nullptr;
+};
+
+template <typename R>
+CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
+    const Circuit &c = pb.circ;
+    const int n = c.n;
+    const size_t amp = 2 * sizeof(R);
+    const size_t V = (size_t(1) << n) * amp;
+    const bool fused = ctx->opt_fusion != 0 && spec.metric && c.P > 1;
+    const SweepPlan *plan = nullptr;
+    FusedRun fr;
+    size_t scratch = 0;
+    int n_states = 4;
+    if (fused) {
+        plan = &ctx->sweep_cache.get(c, ctx->opt_tile, (int)amp, ctx->opt_small);
+        size_t free_b = 0, total_b = 0;
+        HIPCHECK(hipMemGetInfo(&free_b, &total_b));
+        fr = fused_config(*plan, ctx->opt_streams, V, free_b + ctx->ws_bytes);
+        scratch = fused_scratch_bytes(*plan, fr, c.M);
+        n_states = std::max(4, 1 + 2 * fr.B);
+    }
+    Layout L = plan_layout(n, c.P, amp, n_states, spec.in_host != nullptr, scratch);
+    char *base = ensure_workspace(ctx, L.total);
+    hipStream_t st = ctx->stream;
+    Engine<R> e{ctx, pb, base, L, st, n};
+
+    const void *in_c128 = spec.in_dev;
+    if (spec.in_host) {
+        HIPCHECK(hipMemcpyAsync(base + L.staging, spec.in_host, (size_t(1) << n) * 16, hipMemcpyHostToDevice, st));
+        in_c128 = base + L.staging;
+    }
+    if (c.P) HIPCHECK(hipMemcpyAsync(base + L.param_of, pb.param_of.data(), (size_t)c.P * 4, hipMemcpyHostToDevice, st));
+    CallResult res;
+    res.graw = e.graw();
+    res.param_of = (const int *)(base + L.param_of);
+    res.eraw = e.eraw();
+    int pos = 0;
+    if (spec.metric) {
+        auto t0 = Clock::now();
+        e.init(in_c128);
+        if (c.P) HIPCHECK(hipMemsetAsync(e.lraw(), 0, (size_t)c.P * c.P * 16, st));
+        if (fused) {
+            FusedBuffers fb;
+            fb.states = base + L.states;
+            fb.state_bytes = L.state_bytes;
+            fb.scratch = base + L.sweep;
+            fb.scratch_bytes = L.sweep_bytes;
+            fb.traw = e.traw();
+            fb.lraw = e.lraw();
+            fb.reduce_partials = e.partials();
+            pos = run_fused_metric<R>(*plan, fr, c, pb.fwd, pb.adj, fb, st, &ctx->stats, ctx->opt_profile != 0);
+        } else {
+            pos = e.metric_unfused();
+        }
+        launch_unpack_metric(e.lraw(), e.traw(), (const int *)(base + L.param_of), c.P, (double *)(base + L.gout),
+                             (double *)(base + L.tout), st);
+        res.G = (double *)(base + L.gout);
+        res.T = (double *)(base + L.tout);
+        if (spec.host_call || ctx->opt_profile) HIPCHECK(hipStreamSynchronize(st));
+        ctx->stats.metric_ms = ms_since(t0);
+    }
+    if (spec.grad) {
+        auto t0 = Clock::now();
+        if (spec.psi_final_dev) {
+            launch_init_state<R>(e.state(0), n, spec.psi_final_dev, st);
+            pos = c.M;
+        } else if (!spec.metric) {
+            e.init(in_c128);
+            pos = 0;
+        }
+        e.energy_grad_unfused(pos, true, spec.psi_out_dev);
+        if (spec.host_call || ctx->opt_profile) HIPCHECK(hipStreamSynchronize(st));
+        ctx->stats.grad_ms = ms_since(t0);
+    } else if (spec.psi_out_dev) {
+        // energy only
+        if (!spec.metric) {
+            e.init(in_c128);
+            pos = 0;
+        }
+        e.energy_grad_unfused(pos, false, spec.psi_out_dev);
+    }
+    return res;
+}
+
+void reset_stats(qng_ctx *ctx) { ctx->stats = qng_stats{}; }
+
+void require_ctx(qng_ctx *ctx) {
+    if (!ctx) fail(QNG_E_INVALID_ARG, "context is NULL");
+    HIPCHECK(hipSetDevice(ctx->device));
+}
+
+int max_qubits(qng_precision prec) { return prec == QNG_C64 ? kMaxQubitsC64 : kMaxQubitsC128; }
+
+void check_prec(int prec) {
+    if (prec != QNG_C128 && prec != QNG_C64) fail(QNG_E_INVALID_ARG, "unknown precision");
+}
+
+template <typename F> void dispatch(qng_precision prec, F &&f) {
+    if (prec == QNG_C64) f((float)0);
+    else f((double)0);
+}
+
+void host_unpack_grad(const std::vector<double> &graw, const Problem &pb, double *grad) {
+    for (size_t r = 0; r < pb.param_of.size(); ++r) grad[pb.param_of[r]] = -graw[2 * r + 1];
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+qng_status qng_create(qng_ctx **out, int device, void *hip_stream) {
+    return guarded(nullptr, [&] {
+        if (!out) fail(QNG_E_INVALID_ARG, "out is NULL");
+        *out = nullptr;
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+            (void)hipGetLastError();
+            fail(QNG_E_DEVICE, "no HIP device available");
+        }
+        if (device < 0 || device >= count) fail(QNG_E_DEVICE, "device index out of range");
+        HIPCHECK(hipSetDevice(device));
+        std::unique_ptr<qng_ctx> c(new qng_ctx);
+        c->device = device;
+        if (hip_stream) c->stream = (hipStream_t)hip_stream;
+        else {
+            HIPCHECK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+            c->own_stream = true;
+        }
+        *out = c.release();
+    });
+}
+
+void qng_destroy(qng_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+const char *qng_last_error(const qng_ctx *ctx) {
+    if (ctx) return ctx->last_error.c_str();
+    return g_last_error.c_str();
+}
+
+qng_status qng_set_stream(qng_ctx *ctx, void *hip_stream) {
+    return guarded(ctx, [&] {
+        require_ctx(ctx);
+        if (ctx->own_stream && ctx->stream) {
+            HIPCHECK(hipStreamSynchronize(ctx->stream));
+            HIPCHECK(hipStreamDestroy(ctx->stream));
+            ctx->stream = nullptr;
+            ctx->own_stream = false;
+        }
+        ctx->stream = (hipStream_t)hip_stream;
+    });
+}
+
+qng_status qng_set_mem_limit(qng_ctx *ctx, size_t bytes) {
+    return guarded(ctx, [&] {
+        if (!ctx) fail(QNG_E_INVALID_ARG, "context is NULL");
+        ctx->mem_limit = bytes;
+    });
+}
+
+qng_status qng_set_option(qng_ctx *ctx, int option, int value) {
+    return guarded(ctx, [&] {
+        if (!ctx) fail(QNG_E_INVALID_ARG, "context is NULL");
+        switch (option) {
+        case QNG_OPT_FUSION: ctx->opt_fusion = value ? 1 : 0; break;
+        case QNG_OPT_TILE_QUBITS:
+            if (value < 0 || value > 14) fail(QNG_E_INVALID_ARG, "tile qubits outside [0, 14]");
+            ctx->opt_tile = value;
+            break;
+        case QNG_OPT_COLUMN_STREAMS:
+            if (value < 0) fail(QNG_E_INVALID_ARG, "column streams < 0");
+            ctx->opt_streams = value;
+            break;
+        case QNG_OPT_PROFILE: ctx->opt_profile = value ? 1 : 0; break;
+        case QNG_OPT_SMALL_N_KERNEL: ctx->opt_small = value ? 1 : 0; break;
+        default: fail(QNG_E_INVALID_ARG, "unknown option " + std::to_string(option));
+        }
+    });
+}
+
+qng_status qng_get_stats(const qng_ctx *ctx, qng_stats *out) {
+    if (!ctx || !out) return QNG_E_INVALID_ARG;
+    *out = ctx->stats;
+    return QNG_OK;
+}
+
+qng_status qng_synchronize(qng_ctx *ctx) {
+    return guarded(ctx, [&] {
+        require_ctx(ctx);
+        HIPCHECK(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+qng_status qng_validate(const qng_circuit *circ, const double *theta, const qng_pauli_sum *ham, char *msg,
+                        size_t msg_len) {
+    qng_status s = guarded(nullptr, [&] {
+        validate_circuit(circ, kMaxQubitsC64);
+        validate_theta(circ, theta);
+        if (ham) validate_hamiltonian(circ, ham);
+    });
+    if (msg && msg_len) {
+        std::snprintf(msg, msg_len, "%s", s == QNG_OK ? "" : g_last_error.c_str());
+    }
+    return s;
+}
+
+qng_status qng_plan(const qng_circuit *circ, int fusion, int tile_qubits, qng_plan_info *out) {
+    return guarded(nullptr, [&] {
+        if (!out) fail(QNG_E_INVALID_ARG, "out is NULL");
+        validate_circuit(circ, kMaxQubitsC64);
+        Circuit c = compile_circuit(circ);
+        *out = qng_plan_info{};
+        out->elements = (int64_t)c.P * (c.P - 1) / 2;
+        if (!fusion) {
+            for (int s = 1; s < c.P; ++s) out->ops += c.rots[s].pos - c.rots[0].pos + (s);
+            out->passes = 0;
+            return;
+        }
+        SweepPlan plan = build_sweep_plan(c, tile_qubits, 16, 1);
+        plan.fill_info(out);
+    });
+}
+
+qng_status qng_plan_export(const qng_circuit *circ, int tile_qubits, int amp_bytes, int32_t *rows, int64_t cap,
+                           int64_t *n_rows) {
+    return guarded(nullptr, [&] {
+        if (!n_rows) fail(QNG_E_INVALID_ARG, "n_rows is NULL");
+        if (amp_bytes != 8 && amp_bytes != 16) fail(QNG_E_INVALID_ARG, "amp_bytes must be 8 or 16");
+        validate_circuit(circ, kMaxQubitsC64);
+        Circuit c = compile_circuit(circ);
+        SweepPlan plan = build_sweep_plan(c, tile_qubits, amp_bytes, 1);
+        int64_t k = 0;
+        for (const ColumnPlan &cp : plan.cols) {
+            for (size_t pi = 0; pi < cp.passes.size(); ++pi) {
+                const HostPass &hp = cp.passes[pi];
+                uint64_t mask = 0;
+                for (uint8_t q : hp.tile) mask |= uint64_t(1) << q;
+                for (const DevOp &op : hp.ops) {
+                    if (rows && k < cap) {
+                        int32_t *r = rows + 10 * k;
+                        const bool is_prod = op.type == OP_PRODROT || op.type == OP_PROD || op.type == OP_ZSUM;
+                        r[0] = cp.s;
+                        r[1] = (int32_t)pi;
+                        r[2] = op.type;
+                        r[3] = op.q0;
+                        r[4] = (op.type == OP_CNOT) ? (int32_t)hp.tile[op.b1] : (op.type == OP_CZ ? op.q1 : -1);
+                        if (op.type == OP_ROT || op.type == OP_PRODROT) r[3] = hp.tile[op.b0];
+                        r[5] = op.gate;
+                        r[6] = is_prod ? hp.slot_dest[op.slot] : -1;
+                        r[7] = is_prod ? op.axis : -1;
+                        r[8] = (int32_t)(mask & 0x7fffffffu);
+                        r[9] = (int32_t)((mask >> 31) & 0x7fffffffu);
+                    }
+                    ++k;
+                }
+            }
+        }
+        *n_rows = k;
+    });
+}
+
+qng_status qng_solve_shifted(int32_t P, const double *G, double eps, const double *b, double *x) {
+    return guarded(nullptr, [&] {
+        if (P < 0 || (P > 0 && (!G || !b || !x))) fail(QNG_E_INVALID_ARG, "bad arguments");
+        validate_scalar(eps, "eps");
+        if (eps < 0) fail(QNG_E_INVALID_ARG, "eps < 0");
+        qng::solve_shifted(P, G, eps, b, x);
+    });
+}
+
+qng_status qng_metric(qng_ctx *ctx, const qng_circuit *circ, const double *in_state, const double *theta,
+                      qng_precision prec, double *G_out, double *T_out) {
+    return guarded(ctx, [&] {
+        require_ctx(ctx);
+        check_prec(prec);
+        validate_circuit(circ, max_qubits(prec));
+        validate_theta(circ, theta);
+        if (circ->n_params > 0 && !G_out) fail(QNG_E_INVALID_ARG, "G_out is NULL");
+        check_in_state_host(circ->n_qubits, in_state);
+        reset_stats(ctx);
+        Problem pb = make_problem(circ, theta, nullptr);
+        const int P = pb.circ.P;
+        dispatch(prec, [&](auto tag) {
+            using R = decltype(tag);
+            CallSpec spec;
+            spec.metric = true;
+            spec.in_host = in_state;
+            spec.host_call = true;
+            CallResult r = run<R>(ctx, pb, spec);
+            if (P) {
+                HIPCHECK(hipMemcpyAsync(G_out, r.G, (size_t)P * P * 16, hipMemcpyDeviceToHost, ctx->stream));
+                if (T_out) HIPCHECK(hipMemcpyAsync(T_out, r.T, (size_t)P * 16, hipMemcpyDeviceToHost, ctx->stream));
+            }
+            HIPCHECK(hipStreamSynchronize(ctx->stream));
+        });
+    });
+}
+
+qng_status qng_energy_grad(qng_ctx *ctx, const qng_circuit *circ, const double *in_state, const qng_pauli_sum *ham,
+                           const double *theta, qng_precision prec, double *E_out, double *grad_out) {
+    return guarded(ctx, [&] {
+        require_ctx(ctx);
+        check_prec(prec);
+        validate_circuit(circ, max_qubits(prec));
+        validate_theta(circ, theta);
+        validate_hamiltonian(circ, ham);
+        if (!E_out || (circ->n_params > 0 && !grad_out)) fail(QNG_E_INVALID_ARG, "output is NULL");
+        check_in_state_host(circ->n_qubits, in_state);
+        reset_stats(ctx);
+        Problem pb = make_problem(circ, theta, ham);
+        const int P = pb.circ.P;
+        dispatch(prec, [&](auto tag) {
+            using R = decltype(tag);
+            CallSpec spec;
+            spec.grad = true;
+            spec.in_host = in_state;
+            spec.host_call = true;
+            CallResult r = run<R>(ctx, pb, spec);
+            std::vector<double> graw(2 * (size_t)P + 2), e(2);
+            HIPCHECK(hipMemcpyAsync(graw.data(), r.graw, (size_t)P * 16, hipMemcpyDeviceToHost, ctx->stream));
+            HIPCHECK(hipMemcpyAsync(e.data(), r.eraw, 16, hipMemcpyDeviceToHost, ctx->stream));
+            HIPCHECK(hipStreamSynchronize(ctx->stream));
+            *E_out = e[0];
+            host_unpack_grad(graw, pb, grad_out);
+        });
+    });
+}
+
+qng_status qng_step(qng_ctx *ctx, const qng_circuit *circ, const double *in_state, const qng_pauli_sum *ham,
+                    const double *theta, double dt, double tikhonov, qng_precision prec, double *dtheta_out,
+                    double *G_out, double *grad_out, double *E_out) {
+    return guarded(ctx, [&] {
+        require_ctx(ctx);
+        check_prec(prec);
+        validate_circuit(circ, max_qubits(prec));
+        validate_theta(circ, theta);
+        validate_hamiltonian(circ, ham);
+        validate_scalar(dt, "dt");
+        validate_scalar(tikhonov, "tikhonov");
+        if (tikhonov < 0) fail(QNG_E_INVALID_ARG, "tikhonov < 0");
+        if (circ->n_params > 0 && !dtheta_out) fail(QNG_E_INVALID_ARG, "dtheta_out is NULL");
+        check_in_state_host(circ->n_qubits, in_state);
+        reset_stats(ctx);
+        Problem pb = make_problem(circ, theta, ham);
+        const int P = pb.circ.P;
+        std::vector<double> G(2 * (size_t)P * P + 2), graw(2 * (size_t)P + 2), e(2), grad(P + 1);
+        dispatch(prec, [&](auto tag) {
+            using R = decltype(tag);
+            CallSpec spec;
+            spec.metric = true;
+            spec.grad = true;
+            spec.in_host = in_state;
+            spec.host_call = true;
+            CallResult r = run<R>(ctx, pb, spec);
+            if (P) {
+                HIPCHECK(hipMemcpyAsync(G.data(), r.G, (size_t)P * P * 16, hipMemcpyDeviceToHost, ctx->stream));
+                HIPCHECK(hipMemcpyAsync(graw.data(), r.graw, (size_t)P * 16, hipMemcpyDeviceToHost, ctx->stream));
+            }
+            HIPCHECK(hipMemcpyAsync(e.data(), r.eraw, 16, hipMemcpyDeviceToHost, ctx->stream));
+            HIPCHECK(hipStreamSynchronize(ctx->stream));
+        });
+        host_unpack_grad(graw, pb, grad.data());
+        auto t0 = Clock::now();
+        std::vector<double> b(P + 1);
+        for (int i = 0; i < P; ++i) b[i] = -dt * grad[i];
+        std::vector<double> x(P + 1);
+        if (P) qng::solve_shifted(P, G.data(), tikhonov, b.data(), x.data());
+        ctx->stats.solve_ms = ms_since(t0);
+        if (P) std::memcpy(dtheta_out, x.data(), (size_t)P * 8);
+        if (G_out && P) std::memcpy(G_out, G.data(), (size_t)P * P * 16);
+        if (grad_out && P) std::memcpy(grad_out, grad.data(), (size_t)P * 8);
+        if (E_out) *E_out = e[0];
+    });
+}
+
+qng_status qng_step_batched(qng_ctx *ctx, int32_t B, const qng_circuit *circs, const double *const *in_states,
+                            const qng_pauli_sum *hams, const double *const *thetas, double dt, double tikhonov,
+                            qng_precision prec, double *const *dtheta_out, double *const *G_out,
+                            double *const *grad_out, double *E_out) {
+    return guarded(ctx, [&] {
+        require_ctx(ctx);
+        if (B < 0 || (B > 0 && (!circs || !hams || !thetas || !dtheta_out)))
+            fail(QNG_E_INVALID_ARG, "bad batch arguments");
+        for (int b = 0; b < B; ++b) {
+            const qng_status s = qng_step(ctx, &circs[b], in_states ? in_states[b] : nullptr, &hams[b], thetas[b], dt,
+                                          tikhonov, prec, dtheta_out[b], G_out ? G_out[b] : nullptr,
+                                          grad_out ? grad_out[b] : nullptr, E_out ? &E_out[b] : nullptr);
+            if (s != QNG_OK) fail(s, "ansatz " + std::to_string(b) + ": " + ctx->last_error);
+        }
+    });
+}
+
+qng_status qng_metric_dev(qng_ctx *ctx, const qng_circuit *circ, const void *in_state_dev, const double *theta,
+                          qng_precision prec, void *G_dev, void *T_dev) {
+    return guarded(ctx, [&] {
+        require_ctx(ctx);
+        check_prec(prec);
+        validate_circuit(circ, max_qubits(prec));
+        validate_theta(circ, theta);
+        if (circ->n_params > 0 && !G_dev) fail(QNG_E_INVALID_ARG, "G_dev is NULL");
+        reset_stats(ctx);
+        Problem pb = make_problem(circ, theta, nullptr);
+        const int P = pb.circ.P;
+        dispatch(prec, [&](auto tag) {
+            using R = decltype(tag);
+            CallSpec spec;
+            spec.metric = true;
+            spec.in_dev = in_state_dev;
+            CallResult r = run<R>(ctx, pb, spec);
+            if (P) {
+                HIPCHECK(hipMemcpyAsync(G_dev, r.G, (size_t)P * P * 16, hipMemcpyDeviceToDevice, ctx->stream));
+                if (T_dev) HIPCHECK(hipMemcpyAsync(T_dev, r.T, (size_t)P * 16, hipMemcpyDeviceToDevice, ctx->stream));
+            }
+        });
+    });
+}
+
+qng_status qng_energy_dev(qng_ctx *ctx, const qng_circuit *circ, const void *in_state_dev, const qng_pauli_sum *ham,
+                          const double *theta, qng_precision prec, void *E_dev, void *psi_dev) {
+    return guarded(ctx, [&] {
+        require_ctx(ctx);
+        check_prec(prec);
+        validate_circuit(circ, max_qubits(prec));
+        validate_theta(circ, theta);
+        validate_hamiltonian(circ, ham);
+        if (!E_dev || !psi_dev) fail(QNG_E_INVALID_ARG, "output is NULL");
+        reset_stats(ctx);
+        Problem pb = make_problem(circ, theta, ham);
+        dispatch(prec, [&](auto tag) {
+            using R = decltype(tag);
+            CallSpec spec;
+            spec.in_dev = in_state_dev;
+            spec.psi_out_dev = psi_dev;
+            CallResult r = run<R>(ctx, pb, spec);
+            HIPCHECK(hipMemcpyAsync(E_dev, r.eraw, 8, hipMemcpyDeviceToDevice, ctx->stream));
+        });
+    });
+}
+
+qng_status qng_energy_grad_from_state_dev(qng_ctx *ctx, const qng_circuit *circ, const qng_pauli_sum *ham,
+                                          const double *theta, qng_precision prec, const void *psi_dev,
+                                          void *grad_dev) {
+    return guarded(ctx, [&] {
+        require_ctx(ctx);
+        check_prec(prec);
+        validate_circuit(circ, max_qubits(prec));
+        validate_theta(circ, theta);
+        validate_hamiltonian(circ, ham);
+        if (!psi_dev || (circ->n_params > 0 && !grad_dev)) fail(QNG_E_INVALID_ARG, "pointer is NULL");
+        reset_stats(ctx);
+        Problem pb = make_problem(circ, theta, ham);
+        const int P = pb.circ.P;
+        dispatch(prec, [&](auto tag) {
+            using R = decltype(tag);
+            CallSpec spec;
+            spec.grad = true;
+            spec.psi_final_dev = psi_dev;
+            CallResult r = run<R>(ctx, pb, spec);
+            if (P) launch_grad_from_raw(r.graw, r.param_of, P, (double *)grad_dev, ctx->stream);
+        });
+    });
+}
+
+qng_status qng_apply_circuit_dev(qng_ctx *ctx, const qng_circuit *circ, const double *theta, qng_precision prec,
+                                 void *state_dev) {
+    return guarded(ctx, [&] {
+        require_ctx(ctx);
+        check_prec(prec);
+        validate_circuit(circ, max_qubits(prec));
+        validate_theta(circ, theta);
+        if (!state_dev) fail(QNG_E_INVALID_ARG, "state_dev is NULL");
+        Problem pb = make_problem(circ, theta, nullptr);
+        const int n = pb.circ.n;
+        dispatch(prec, [&](auto tag) {
+            using R = decltype(tag);
+            for (int pos = 0; pos < pb.circ.M; ++pos) {
+                const qng_gate &g = pb.circ.gates[pos];
+                if (g.kind == QNG_CNOT) launch_cnot<R>(state_dev, nullptr, n, g.q0, g.q1, ctx->stream);
+                else if (g.kind == QNG_CZ) launch_cz<R>(state_dev, nullptr, n, g.q0, g.q1, ctx->stream);
+                else launch_apply_1q<R>(state_dev, nullptr, n, g.q0, dev(pb.fwd[pos]), ctx->stream);
+            }
+        });
+    });
+}
+
+}  // extern "C"

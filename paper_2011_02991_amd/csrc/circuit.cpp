@@ -1,0 +1,121 @@
+// circuit.cpp -- validation and compilation of an ansatz (host only).
+#include "circuit.hpp"
+
+#include <cmath>
+#include <cstdio>
+
+namespace qng {
+
+void validate_scalar(double v, const char *name) {
+    if (!std::isfinite(v)) fail(QNG_E_NONFINITE, std::string(name) + " is not finite");
+}
+
+void validate_circuit(const qng_circuit *c, int max_qubits) {
+    if (!c) fail(QNG_E_INVALID_ARG, "circuit is NULL");
+    if (c->n_qubits < 1 || c->n_qubits > max_qubits)
+        fail(QNG_E_BAD_CIRCUIT, "n_qubits=" + std::to_string(c->n_qubits) + " outside [1, " +
+                                    std::to_string(max_qubits) + "]");
+    if (c->n_gates < 0) fail(QNG_E_BAD_CIRCUIT, "n_gates < 0");
+    if (c->n_params < 0) fail(QNG_E_BAD_PARAMS, "n_params < 0");
+    if (c->n_gates > 0 && !c->gates) fail(QNG_E_INVALID_ARG, "gates is NULL");
+    const int n = c->n_qubits;
+    std::vector<int> seen(c->n_params, 0);
+    int n_rot = 0;
+    for (int k = 0; k < c->n_gates; ++k) {
+        const qng_gate &g = c->gates[k];
+        const std::string where = "gate " + std::to_string(k) + ": ";
+        switch (g.kind) {
+        case QNG_RX:
+        case QNG_RY:
+        case QNG_RZ:
+            if (g.q0 < 0 || g.q0 >= n) fail(QNG_E_BAD_CIRCUIT, where + "qubit out of range");
+            if (g.q1 != -1) fail(QNG_E_BAD_CIRCUIT, where + "rotation must have q1 = -1");
+            if (g.param < 0) fail(QNG_E_BAD_PARAMS, where + "rotation needs a parameter index >= 0");
+            if (g.param >= c->n_params) fail(QNG_E_BAD_PARAMS, where + "parameter index >= n_params");
+            if (seen[g.param]++) fail(QNG_E_BAD_PARAMS, where + "parameter " + std::to_string(g.param) +
+                                                             " is shared (one unique parameter per gate is required)");
+            ++n_rot;
+            break;
+        case QNG_CNOT:
+        case QNG_CZ:
+            if (g.q0 < 0 || g.q0 >= n || g.q1 < 0 || g.q1 >= n)
+                fail(QNG_E_BAD_CIRCUIT, where + "qubit out of range");
+            if (g.q0 == g.q1) fail(QNG_E_BAD_CIRCUIT, where + "two-qubit gate on a single qubit");
+            if (g.param != -1) fail(QNG_E_BAD_PARAMS, where + "fixed gate must have param = -1");
+            break;
+        default:
+            fail(QNG_E_BAD_CIRCUIT, where + "unknown gate kind " + std::to_string(g.kind));
+        }
+    }
+    if (n_rot != c->n_params)
+        fail(QNG_E_BAD_PARAMS, "n_params=" + std::to_string(c->n_params) + " but the circuit has " +
+                                   std::to_string(n_rot) + " rotations");
+}
+
+void validate_theta(const qng_circuit *c, const double *theta) {
+    if (c->n_params > 0 && !theta) fail(QNG_E_INVALID_ARG, "theta is NULL");
+    for (int p = 0; p < c->n_params; ++p)
+        if (!std::isfinite(theta[p])) fail(QNG_E_NONFINITE, "theta[" + std::to_string(p) + "] is not finite");
+}
+
+void validate_hamiltonian(const qng_circuit *c, const qng_pauli_sum *h) {
+    if (!h) fail(QNG_E_INVALID_ARG, "Hamiltonian is NULL");
+    if (h->n_terms < 0) fail(QNG_E_INVALID_ARG, "n_terms < 0");
+    if (h->n_terms > 0 && (!h->coeff || !h->pauli)) fail(QNG_E_INVALID_ARG, "Hamiltonian arrays are NULL");
+    for (int t = 0; t < h->n_terms; ++t) {
+        if (!std::isfinite(h->coeff[t])) fail(QNG_E_NONFINITE, "coeff[" + std::to_string(t) + "] is not finite");
+        for (int q = 0; q < c->n_qubits; ++q)
+            if (h->pauli[(size_t)t * c->n_qubits + q] > 3)
+                fail(QNG_E_INVALID_ARG, "Pauli letter outside {0,1,2,3} in term " + std::to_string(t));
+    }
+}
+
+Circuit compile_circuit(const qng_circuit *c) {
+    Circuit k;
+    k.n = c->n_qubits;
+    k.M = c->n_gates;
+    k.P = c->n_params;
+    k.gates.assign(c->gates, c->gates + c->n_gates);
+    k.rot_at.assign(k.M, -1);
+    for (int pos = 0; pos < k.M; ++pos) {
+        const qng_gate &g = k.gates[pos];
+        if (g.kind <= QNG_RZ) {
+            k.rot_at[pos] = (int)k.rots.size();
+            k.rots.push_back(Rot{g.kind == QNG_RX ? AX_X : g.kind == QNG_RY ? AX_Y : AX_Z, g.q0, g.param, pos});
+        }
+    }
+    return k;
+}
+
+// R_sigma(theta) = cos(theta/2) I + i sin(theta/2) sigma.
+Mat2 rotation(int axis, double theta) {
+    const double c = std::cos(0.5 * theta), s = std::sin(0.5 * theta);
+    const cd I(0, 1);
+    switch (axis) {
+    case AX_X: return Mat2{c, I * s, I * s, c};
+    case AX_Y: return Mat2{c, s, -s, c};          // i s * [[0,-i],[i,0]] = [[0, s], [-s, 0]]
+    default:   return Mat2{cd(c, s), 0, 0, cd(c, -s)};
+    }
+}
+
+Mat2 adjoint(const Mat2 &m) { return Mat2{std::conj(m.a), std::conj(m.c), std::conj(m.b), std::conj(m.d)}; }
+
+std::vector<PauliTerm> compile_hamiltonian(const qng_circuit *c, const qng_pauli_sum *h) {
+    std::vector<PauliTerm> out(h->n_terms);
+    for (int t = 0; t < h->n_terms; ++t) {
+        PauliTerm &p = out[t];
+        p.coeff = h->coeff[t];
+        for (int q = 0; q < c->n_qubits; ++q) {
+            const uint64_t bit = uint64_t(1) << q;
+            switch (h->pauli[(size_t)t * c->n_qubits + q]) {
+            case 1: p.flip |= bit; break;
+            case 2: p.flip |= bit; p.zy |= bit; ++p.n_y; break;
+            case 3: p.zy |= bit; break;
+            default: break;
+            }
+        }
+    }
+    return out;
+}
+
+}  // namespace qng

@@ -1,0 +1,73 @@
+// circuit.hpp -- host-side validation and compilation of an ansatz.
+//
+// The ansatz is U = U_P ... U_1 acting on |in>, one unique parameter per
+// parameterised gate (Sec. 2, problem statement).  Fixed gates (CNOT, CZ) are
+// allowed anywhere; they carry no parameter.  Rotations follow the paper's
+// sign, R_sigma(theta) = exp(+i theta sigma / 2) (Sec. 2, rotation example).
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/qng.h"
+
+namespace qng {
+
+using cd = std::complex<double>;
+
+// Thrown by host code; converted to a qng_status at the C ABI boundary.
+struct Error {
+    qng_status status;
+    std::string msg;
+};
+
+[[noreturn]] inline void fail(qng_status s, const std::string &m) { throw Error{s, m}; }
+
+enum Axis : int { AX_X = 0, AX_Y = 1, AX_Z = 2 };
+
+struct Mat2 {  // row-major 2x2 complex, [[a, b], [c, d]]
+    cd a, b, c, d;
+};
+
+// One rotation of the ansatz, in gate-list order.
+struct Rot {
+    int axis;    // generator sigma: X, Y or Z
+    int qubit;
+    int param;   // parameter index (row/column of G)
+    int pos;     // position in the gate list
+};
+
+struct Circuit {
+    int n = 0;              // qubits
+    int M = 0;              // gates
+    int P = 0;              // parameters = rotations
+    std::vector<qng_gate> gates;
+    std::vector<int> rot_at;   // gate position -> rotation index (list order) or -1
+    std::vector<Rot> rots;     // rotations in list order
+};
+
+// Validation rules shared by every entry point (all before any device work).
+void validate_circuit(const qng_circuit *c, int max_qubits);
+void validate_theta(const qng_circuit *c, const double *theta);
+void validate_hamiltonian(const qng_circuit *c, const qng_pauli_sum *h);
+void validate_scalar(double v, const char *name);
+
+Circuit compile_circuit(const qng_circuit *c);
+
+// R(theta) and R(theta)^dagger for a rotation axis.
+Mat2 rotation(int axis, double theta);
+Mat2 adjoint(const Mat2 &m);
+
+// Pauli string in bit-mask form: (sigma psi)[x] = (-i)^{nY} (-1)^{popcount(x & zy)} psi[x ^ flip],
+// with flip = positions of X and Y letters, zy = positions of Z and Y letters
+// (Y = -i (-1)^{x_q} on the flipped bit: Y|0> = i|1>, Y|1> = -i|0>).
+struct PauliTerm {
+    uint64_t flip = 0, zy = 0;
+    int n_y = 0;
+    double coeff = 0;
+};
+std::vector<PauliTerm> compile_hamiltonian(const qng_circuit *c, const qng_pauli_sum *h);
+
+}  // namespace qng

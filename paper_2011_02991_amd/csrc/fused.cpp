@@ -1,0 +1,201 @@
+// fused.cpp -- host executor of the fused metric: forward state, column
+// seeds and the tiled sweep passes of every column (see sweep.hpp, api.cpp).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+
+#include "fused.hpp"
+
+namespace qng {
+
+namespace {
+
+#define FCHECK(call)                                                                                  \
+    do {                                                                                              \
+        hipError_t _e = (call);                                                                       \
+        if (_e != hipSuccess) fail(QNG_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+DevMat2 to_dev(const Mat2 &m) {
+    return DevMat2{m.a.real(), m.a.imag(), m.b.real(), m.b.imag(), m.c.real(), m.c.imag(), m.d.real(), m.d.imag()};
+}
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct Launch {
+    uint32_t item_begin = 0, n_items = 0, total_tiles = 0, task_begin = 0, n_tasks = 0;
+};
+struct Group {
+    int col_begin = 0, col_end = 0;
+    size_t launch_begin = 0, launch_end = 0;
+};
+
+}  // namespace
+
+size_t fused_scratch_bytes(const SweepPlan &plan, const FusedRun &fr, int M) {
+    size_t b = 0;
+    b += align256((size_t)M * 64 + 64);                                  // matrix table
+    b += align256(plan.dev_passes.size() * sizeof(DevPass) + 64);       // passes
+    b += align256(plan.dev_ops.size() * sizeof(DevOp) + 64);            // ops
+    b += align256(plan.dev_passes.size() * sizeof(LaunchItem) + 64);    // one item per pass
+    b += align256((size_t)plan.P * plan.P * sizeof(ReduceTask) / 2 + 64);  // one task per element
+    b += align256(fr.partial_elems * 16);
+    return b;
+}
+
+template <typename R>
+int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c, const std::vector<Mat2> &fwd,
+                     const std::vector<Mat2> &adj, const FusedBuffers &buf, hipStream_t st, qng_stats *stats,
+                     bool profile) {
+    const int n = c.n;
+    const size_t V = buf.state_bytes;
+    const uint32_t tiles = 1u << (n - plan.m);
+    const int ncols = (int)plan.cols.size();
+    const int B = fr.B;
+    auto state = [&](int k) -> void * { return buf.states + (size_t)k * V; };
+
+    // ---- launch schedule (host)
+    std::vector<LaunchItem> items;
+    std::vector<ReduceTask> tasks;
+    std::vector<Launch> launches;
+    std::vector<Group> groups;
+    items.reserve(plan.dev_passes.size());
+    for (int g0 = 0; g0 < ncols; g0 += B) {
+        Group G;
+        G.col_begin = g0;
+        G.col_end = std::min(ncols, g0 + B);
+        G.launch_begin = launches.size();
+        size_t maxp = 0;
+        for (int col = G.col_begin; col < G.col_end; ++col) maxp = std::max(maxp, plan.cols[col].passes.size());
+        for (size_t t = 0; t < maxp; ++t) {
+            Launch L;
+            L.item_begin = (uint32_t)items.size();
+            L.task_begin = (uint32_t)tasks.size();
+            uint64_t poff = 0;
+            for (int col = G.col_begin; col < G.col_end; ++col) {
+                const ColumnPlan &cp = plan.cols[col];
+                if (t >= cp.passes.size()) continue;
+                const int b = col - G.col_begin;
+                const uint32_t pidx = (uint32_t)(plan.col_pass_begin[col] + (int64_t)t);
+                const HostPass &hp = cp.passes[t];
+                LaunchItem it{};
+                it.tile_begin = L.total_tiles;
+                it.pass = pidx;
+                it.ntiles = tiles;
+                it.partial_off = poff;
+                it.regA = state(1 + 2 * b);
+                it.regB = state(2 + 2 * b);
+                items.push_back(it);
+                ++L.n_items;
+                L.total_tiles += tiles;
+                for (size_t k = 0; k < hp.slot_dest.size(); ++k) {
+                    tasks.push_back(ReduceTask{poff + (uint64_t)k * tiles, tiles, hp.slot_dest[k]});
+                    ++L.n_tasks;
+                }
+                poff += (uint64_t)hp.slot_dest.size() * tiles;
+            }
+            if (poff > fr.partial_elems) fail(QNG_E_DEVICE, "fused sweep: partial buffer too small (internal)");
+            launches.push_back(L);
+        }
+        G.launch_end = launches.size();
+        groups.push_back(G);
+    }
+
+    // ---- device images
+    std::vector<double> mats((size_t)c.M * 8, 0.0);
+    for (const Rot &r : c.rots) {
+        const Mat2 &m = adj[r.pos];
+        double *d = &mats[(size_t)r.pos * 8];
+        d[0] = m.a.real(); d[1] = m.a.imag(); d[2] = m.b.real(); d[3] = m.b.imag();
+        d[4] = m.c.real(); d[5] = m.c.imag(); d[6] = m.d.real(); d[7] = m.d.imag();
+    }
+    char *p = buf.scratch;
+    auto take = [&](size_t bytes) { char *o = p; p += align256(bytes + 64); return o; };
+    double *d_mats = (double *)take(mats.size() * 8);
+    DevPass *d_passes = (DevPass *)take(plan.dev_passes.size() * sizeof(DevPass));
+    DevOp *d_ops = (DevOp *)take(plan.dev_ops.size() * sizeof(DevOp));
+    LaunchItem *d_items = (LaunchItem *)take(items.size() * sizeof(LaunchItem));
+    ReduceTask *d_tasks = (ReduceTask *)take(tasks.size() * sizeof(ReduceTask));
+    double *d_partials = (double *)p;
+    if ((size_t)(p - buf.scratch) + fr.partial_elems * 16 > buf.scratch_bytes)
+        fail(QNG_E_DEVICE, "fused sweep: scratch too small (internal)");
+    if (!mats.empty()) FCHECK(hipMemcpyAsync(d_mats, mats.data(), mats.size() * 8, hipMemcpyHostToDevice, st));
+    if (!plan.dev_passes.empty())
+        FCHECK(hipMemcpyAsync(d_passes, plan.dev_passes.data(), plan.dev_passes.size() * sizeof(DevPass),
+                              hipMemcpyHostToDevice, st));
+    if (!plan.dev_ops.empty())
+        FCHECK(hipMemcpyAsync(d_ops, plan.dev_ops.data(), plan.dev_ops.size() * sizeof(DevOp), hipMemcpyHostToDevice,
+                              st));
+    if (!items.empty())
+        FCHECK(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(LaunchItem), hipMemcpyHostToDevice, st));
+    if (!tasks.empty())
+        FCHECK(hipMemcpyAsync(d_tasks, tasks.data(), tasks.size() * sizeof(ReduceTask), hipMemcpyHostToDevice, st));
+    FCHECK(hipStreamSynchronize(st));   // host vectors are released at return
+
+    // ---- profiling events
+    std::vector<hipEvent_t> ev;
+    if (profile) {
+        ev.resize(2 * launches.size());
+        for (auto &e : ev) FCHECK(hipEventCreate(&e));
+    }
+
+    // ---- execute
+    void *psi = state(0);
+    int pos = 0;
+    auto forward_to = [&](int target) {
+        for (; pos < target; ++pos) {
+            const qng_gate &g = c.gates[pos];
+            if (g.kind == QNG_CNOT) launch_cnot<R>(psi, nullptr, n, g.q0, g.q1, st);
+            else if (g.kind == QNG_CZ) launch_cz<R>(psi, nullptr, n, g.q0, g.q1, st);
+            else launch_apply_1q<R>(psi, nullptr, n, g.q0, to_dev(fwd[pos]), st);
+            ++stats->other_launches;
+        }
+    };
+    forward_to(c.rots[0].pos);
+    launch_pauli_prod<R>(psi, psi, n, c.rots[0].qubit, c.rots[0].axis, buf.reduce_partials, buf.traw, st);
+    stats->other_launches += 2;
+    for (const Group &G : groups) {
+        for (int col = G.col_begin; col < G.col_end; ++col) {
+            const int s = plan.cols[col].s;
+            const Rot &rs = c.rots[s];
+            const int b = col - G.col_begin;
+            forward_to(rs.pos);
+            launch_pauli_prod<R>(psi, psi, n, rs.qubit, rs.axis, buf.reduce_partials, buf.traw + 2 * s, st);
+            launch_seed<R>(psi, state(1 + 2 * b), state(2 + 2 * b), n, rs.qubit, rs.axis, st);
+            stats->other_launches += 3;
+        }
+        for (size_t li = G.launch_begin; li < G.launch_end; ++li) {
+            const Launch &L = launches[li];
+            if (profile) FCHECK(hipEventRecord(ev[2 * li], st));
+            launch_sweep_pass<R>(d_items + L.item_begin, (int)L.n_items, L.total_tiles, d_passes, d_ops, d_mats,
+                                 d_partials, plan.m, st);
+            if (profile) FCHECK(hipEventRecord(ev[2 * li + 1], st));
+            launch_reduce_tasks(d_tasks + L.task_begin, (int)L.n_tasks, d_partials, buf.lraw, st);
+            ++stats->sweep_launches;
+            ++stats->other_launches;
+            stats->sweep_tiles += L.total_tiles;
+            stats->sweep_bytes += (double)L.n_items * 4.0 * (double)V;
+        }
+    }
+    stats->elements += (int64_t)c.P * (c.P - 1) / 2;
+    if (profile) {
+        FCHECK(hipStreamSynchronize(st));
+        double tot = 0.0;
+        for (size_t li = 0; li < launches.size(); ++li) {
+            float ms = 0.f;
+            FCHECK(hipEventElapsedTime(&ms, ev[2 * li], ev[2 * li + 1]));
+            tot += ms;
+        }
+        stats->sweep_ms += tot;
+        for (auto &e : ev) (void)hipEventDestroy(e);
+    }
+    return pos;
+}
+
+template int run_fused_metric<double>(const SweepPlan &, const FusedRun &, const Circuit &, const std::vector<Mat2> &,
+                                      const std::vector<Mat2> &, const FusedBuffers &, hipStream_t, qng_stats *, bool);
+template int run_fused_metric<float>(const SweepPlan &, const FusedRun &, const Circuit &, const std::vector<Mat2> &,
+                                     const std::vector<Mat2> &, const FusedBuffers &, hipStream_t, qng_stats *, bool);
+
+}  // namespace qng

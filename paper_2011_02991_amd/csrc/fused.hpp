@@ -1,0 +1,34 @@
+// fused.hpp -- host executor of the fused, tiled metric (see sweep.hpp).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <vector>
+
+#include "circuit.hpp"
+#include "kernels.hpp"
+#include "sweep.hpp"
+
+namespace qng {
+
+struct FusedBuffers {
+    char *states = nullptr;        // state 0 = psi; column b of a group uses states 1+2b (lambda), 2+2b (phi)
+    size_t state_bytes = 0;
+    char *scratch = nullptr;       // matrix table, plan images, launch items, reduce tasks, partial sums
+    size_t scratch_bytes = 0;
+    double *traw = nullptr;        // P complex: <y_s|sigma_s|y_s>
+    double *lraw = nullptr;        // P*P complex: <lambda|sigma_r|phi> at (r, s)
+    double *reduce_partials = nullptr;  // scratch of the per-primitive reductions
+};
+
+size_t fused_scratch_bytes(const SweepPlan &plan, const FusedRun &fr, int M);
+
+// Runs T for every rotation and L_rs for every r < s.  psi (state 0) must hold
+// |in> on entry; on return it holds y_{P-1} and the gate position of the last
+// rotation is returned.
+template <typename R>
+int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c, const std::vector<Mat2> &fwd,
+                     const std::vector<Mat2> &adj, const FusedBuffers &buf, hipStream_t st, qng_stats *stats,
+                     bool profile);
+
+}  // namespace qng

@@ -1,0 +1,361 @@
+// kernels.hip -- per-primitive HIP kernels for gfx950 (clone, apply gate,
+// inner product, Pauli-sum Hamiltonian).  See kernels.hpp.
+//
+// Layout: a register of n qubits is 2^n interleaved complex amplitudes of
+// element type R; qubit q is bit q of the index.  A single-qubit gate on q
+// pairs amplitudes i0 (bit q clear) and i1 = i0 | 2^q; consecutive threads
+// take consecutive pair indices, so loads and stores are coalesced for every q
+// (for q >= 1 both halves are contiguous runs; for q = 0 each thread touches one
+// 2-amplitude run).
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace qng {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kReduceBlocksMax = 1024;
+
+template <typename R> struct Cplx;
+template <> struct Cplx<double> { using T = double2; };
+template <> struct Cplx<float>  { using T = float2; };
+
+__device__ __forceinline__ uint64_t insert_zero(uint64_t p, int q) {
+    const uint64_t low = p & ((uint64_t(1) << q) - 1);
+    return ((p >> q) << (q + 1)) | low;
+}
+
+__device__ __forceinline__ uint64_t insert_two_zeros(uint64_t p, int lo, int hi) {
+    return insert_zero(insert_zero(p, lo), hi);   // lo < hi
+}
+
+inline unsigned grid_for(uint64_t work) {
+    uint64_t g = (work + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > (uint64_t(1) << 20)) g = uint64_t(1) << 20;
+    return (unsigned)g;
+}
+
+inline void check_launch() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw e;
+}
+
+// ------------------------------------------------------------------ state init
+
+template <typename R>
+__global__ void k_init_state(typename Cplx<R>::T *dst, uint64_t dim, const double2 *src) {
+    for (uint64_t x = blockIdx.x * (uint64_t)kBlock + threadIdx.x; x < dim; x += (uint64_t)gridDim.x * kBlock) {
+        typename Cplx<R>::T v;
+        if (src) { v.x = (R)src[x].x; v.y = (R)src[x].y; }
+        else     { v.x = (R)(x == 0 ? 1.0 : 0.0); v.y = (R)0; }
+        dst[x] = v;
+    }
+}
+
+template <typename R>
+__global__ void k_to_c128(const typename Cplx<R>::T *src, double2 *dst, uint64_t dim) {
+    for (uint64_t x = blockIdx.x * (uint64_t)kBlock + threadIdx.x; x < dim; x += (uint64_t)gridDim.x * kBlock) {
+        const typename Cplx<R>::T v = src[x];
+        dst[x] = make_double2((double)v.x, (double)v.y);
+    }
+}
+
+template <typename R>
+__global__ void k_copy(const typename Cplx<R>::T *src, typename Cplx<R>::T *dst, uint64_t dim) {
+    for (uint64_t x = blockIdx.x * (uint64_t)kBlock + threadIdx.x; x < dim; x += (uint64_t)gridDim.x * kBlock)
+        dst[x] = src[x];
+}
+
+// ------------------------------------------------------------------ gates
+
+template <typename R>
+__device__ __forceinline__ void mat_pair(typename Cplx<R>::T *s, uint64_t i0, uint64_t i1, R ar, R ai, R br, R bi,
+                                         R cr, R ci, R dr, R di) {
+    const typename Cplx<R>::T u = s[i0], v = s[i1];
+    typename Cplx<R>::T o0, o1;
+    o0.x = ar * u.x - ai * u.y + br * v.x - bi * v.y;
+    o0.y = ar * u.y + ai * u.x + br * v.y + bi * v.x;
+    o1.x = cr * u.x - ci * u.y + dr * v.x - di * v.y;
+    o1.y = cr * u.y + ci * u.x + dr * v.y + di * v.x;
+    s[i0] = o0;
+    s[i1] = o1;
+}
+
+template <typename R>
+__global__ void k_apply_1q(typename Cplx<R>::T *s0, typename Cplx<R>::T *s1, int n, int q, DevMat2 m) {
+    const uint64_t npairs = uint64_t(1) << (n - 1);
+    const R ar = (R)m.ar, ai = (R)m.ai, br = (R)m.br, bi = (R)m.bi;
+    const R cr = (R)m.cr, ci = (R)m.ci, dr = (R)m.dr, di = (R)m.di;
+    for (uint64_t p = blockIdx.x * (uint64_t)kBlock + threadIdx.x; p < npairs; p += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t i0 = insert_zero(p, q), i1 = i0 | (uint64_t(1) << q);
+        mat_pair<R>(s0, i0, i1, ar, ai, br, bi, cr, ci, dr, di);
+        if (s1) mat_pair<R>(s1, i0, i1, ar, ai, br, bi, cr, ci, dr, di);
+    }
+}
+
+// CNOT(control c, target t): swap amplitudes (x, x ^ 2^t) for x with bit c set and bit t clear.
+template <typename R>
+__global__ void k_cnot(typename Cplx<R>::T *s0, typename Cplx<R>::T *s1, int n, int c, int t) {
+    const uint64_t nq = uint64_t(1) << (n - 2);
+    const int lo = c < t ? c : t, hi = c < t ? t : c;
+    for (uint64_t p = blockIdx.x * (uint64_t)kBlock + threadIdx.x; p < nq; p += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t i0 = insert_two_zeros(p, lo, hi) | (uint64_t(1) << c);
+        const uint64_t i1 = i0 | (uint64_t(1) << t);
+        typename Cplx<R>::T u = s0[i0], v = s0[i1];
+        s0[i0] = v; s0[i1] = u;
+        if (s1) { u = s1[i0]; v = s1[i1]; s1[i0] = v; s1[i1] = u; }
+    }
+}
+
+// CZ(a, b): negate amplitudes with both bits set.
+template <typename R>
+__global__ void k_cz(typename Cplx<R>::T *s0, typename Cplx<R>::T *s1, int n, int a, int b) {
+    const uint64_t nq = uint64_t(1) << (n - 2);
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    for (uint64_t p = blockIdx.x * (uint64_t)kBlock + threadIdx.x; p < nq; p += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t i = insert_two_zeros(p, lo, hi) | (uint64_t(1) << a) | (uint64_t(1) << b);
+        typename Cplx<R>::T u = s0[i];
+        u.x = -u.x; u.y = -u.y; s0[i] = u;
+        if (s1) { u = s1[i]; u.x = -u.x; u.y = -u.y; s1[i] = u; }
+    }
+}
+
+// lam = y; phi = sigma_q y.   (X: swap; Y: phi0 = -i y1, phi1 = i y0; Z: phi1 = -y1)
+template <typename R>
+__global__ void k_seed(const typename Cplx<R>::T *y, typename Cplx<R>::T *lam, typename Cplx<R>::T *phi, int n, int q,
+                       int axis) {
+    const uint64_t npairs = uint64_t(1) << (n - 1);
+    for (uint64_t p = blockIdx.x * (uint64_t)kBlock + threadIdx.x; p < npairs; p += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t i0 = insert_zero(p, q), i1 = i0 | (uint64_t(1) << q);
+        const typename Cplx<R>::T u = y[i0], v = y[i1];
+        lam[i0] = u;
+        lam[i1] = v;
+        typename Cplx<R>::T o0, o1;
+        if (axis == 0) { o0 = v; o1 = u; }
+        else if (axis == 1) { o0.x = v.y; o0.y = -v.x; o1.x = -u.y; o1.y = u.x; }
+        else { o0 = u; o1.x = -v.x; o1.y = -v.y; }
+        phi[i0] = o0;
+        phi[i1] = o1;
+    }
+}
+
+// ------------------------------------------------------------------ reductions
+
+__device__ __forceinline__ void block_reduce_store(double sr, double si, double *out2) {
+    __shared__ double sh[2 * kBlock];
+    sh[threadIdx.x] = sr;
+    sh[kBlock + threadIdx.x] = si;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sh[threadIdx.x] += sh[threadIdx.x + w];
+            sh[kBlock + threadIdx.x] += sh[kBlock + threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { out2[0] = sh[0]; out2[1] = sh[kBlock]; }
+}
+
+// conj(a) * b accumulated in FP64
+__device__ __forceinline__ void cmac(double &sr, double &si, double ar, double ai, double br, double bi) {
+    sr += ar * br + ai * bi;
+    si += ar * bi - ai * br;
+}
+
+template <typename R>
+__global__ void k_pauli_prod_partial(const typename Cplx<R>::T *a, const typename Cplx<R>::T *b, int n, int q,
+                                     int axis, double *partials) {
+    double sr = 0.0, si = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    if (axis < 0) {
+        const uint64_t dim = uint64_t(1) << n;
+        for (uint64_t x = blockIdx.x * (uint64_t)kBlock + threadIdx.x; x < dim; x += stride) {
+            const typename Cplx<R>::T u = a[x], v = b[x];
+            cmac(sr, si, u.x, u.y, v.x, v.y);
+        }
+    } else {
+        const uint64_t npairs = uint64_t(1) << (n - 1);
+        for (uint64_t p = blockIdx.x * (uint64_t)kBlock + threadIdx.x; p < npairs; p += stride) {
+            const uint64_t i0 = insert_zero(p, q), i1 = i0 | (uint64_t(1) << q);
+            const typename Cplx<R>::T a0 = a[i0], a1 = a[i1], b0 = b[i0], b1 = b[i1];
+            if (axis == 2) {            // conj(a0) b0 - conj(a1) b1
+                cmac(sr, si, a0.x, a0.y, b0.x, b0.y);
+                cmac(sr, si, -(double)a1.x, -(double)a1.y, b1.x, b1.y);
+            } else if (axis == 0) {     // conj(a0) b1 + conj(a1) b0
+                cmac(sr, si, a0.x, a0.y, b1.x, b1.y);
+                cmac(sr, si, a1.x, a1.y, b0.x, b0.y);
+            } else {                    // i (conj(a1) b0 - conj(a0) b1)
+                double tr = 0.0, ti = 0.0;
+                cmac(tr, ti, a1.x, a1.y, b0.x, b0.y);
+                cmac(tr, ti, -(double)a0.x, -(double)a0.y, b1.x, b1.y);
+                sr += -ti;
+                si += tr;
+            }
+        }
+    }
+    block_reduce_store(sr, si, partials + 2 * blockIdx.x);
+}
+
+__global__ void k_reduce_final(const double *partials, int nb, double *dest) {
+    double sr = 0.0, si = 0.0;
+    for (int k = threadIdx.x; k < nb; k += kBlock) { sr += partials[2 * k]; si += partials[2 * k + 1]; }
+    block_reduce_store(sr, si, dest);
+}
+
+// ------------------------------------------------------------------ Hamiltonian
+
+template <typename R>
+__global__ void k_pauli_term(const typename Cplx<R>::T *psi, typename Cplx<R>::T *out, int n, uint64_t flip,
+                             uint64_t zy, double fr, double fi, int first) {
+    const uint64_t dim = uint64_t(1) << n;
+    const R cr = (R)fr, ci = (R)fi;
+    for (uint64_t x = blockIdx.x * (uint64_t)kBlock + threadIdx.x; x < dim; x += (uint64_t)gridDim.x * kBlock) {
+        const typename Cplx<R>::T v = psi[x ^ flip];
+        const R sgn = (__popcll(x & zy) & 1) ? (R)-1 : (R)1;
+        typename Cplx<R>::T o;
+        o.x = sgn * (cr * v.x - ci * v.y);
+        o.y = sgn * (cr * v.y + ci * v.x);
+        if (!first) { const typename Cplx<R>::T w = out[x]; o.x += w.x; o.y += w.y; }
+        out[x] = o;
+    }
+}
+
+// ------------------------------------------------------------------ unpack
+
+__global__ void k_unpack_metric(const double *Lraw, const double *Traw, const int *param_of, int P, double *G,
+                                double *Tout) {
+    const int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (idx >= (int64_t)P * P) return;
+    const int r = (int)(idx / P), s = (int)(idx % P);
+    // T_k = (i/2) <y_k|sigma_k|y_k>
+    const double trr = -0.5 * Traw[2 * r + 1], tri = 0.5 * Traw[2 * r];
+    const double tsr = -0.5 * Traw[2 * s + 1], tsi = 0.5 * Traw[2 * s];
+    double lr, li;
+    if (r < s)      { lr = 0.25 * Lraw[2 * ((int64_t)r * P + s)]; li = 0.25 * Lraw[2 * ((int64_t)r * P + s) + 1]; }
+    else if (r > s) { lr = 0.25 * Lraw[2 * ((int64_t)s * P + r)]; li = -0.25 * Lraw[2 * ((int64_t)s * P + r) + 1]; }
+    else            { lr = 0.25; li = 0.0; }
+    // G = L - conj(T_r) T_s
+    const double pr = trr * tsr + tri * tsi, pi = trr * tsi - tri * tsr;
+    const int64_t o = (int64_t)param_of[r] * P + param_of[s];
+    G[2 * o] = lr - pr;
+    G[2 * o + 1] = li - pi;
+    if (Tout && r == s) { Tout[2 * param_of[r]] = trr; Tout[2 * param_of[r] + 1] = tri; }
+}
+
+__global__ void k_grad_from_raw(const double *graw, const int *param_of, int P, double *grad) {
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r < P) grad[param_of[r]] = -graw[2 * r + 1];
+}
+
+}  // namespace
+
+// ====================================================================== launchers
+
+int reduce_blocks(int n) {
+    const int64_t work = (int64_t(1) << n) / (kBlock * 8);
+    if (work < 1) return 1;
+    return work > kReduceBlocksMax ? kReduceBlocksMax : (int)work;
+}
+
+template <typename R> void launch_init_state(void *dst, int n, const void *src, hipStream_t st) {
+    const uint64_t dim = uint64_t(1) << n;
+    hipLaunchKernelGGL(k_init_state<R>, dim3(grid_for(dim)), dim3(kBlock), 0, st,
+                       (typename Cplx<R>::T *)dst, dim, (const double2 *)src);
+    check_launch();
+}
+
+template <typename R> void launch_to_c128(const void *src, void *dst, int n, hipStream_t st) {
+    const uint64_t dim = uint64_t(1) << n;
+    hipLaunchKernelGGL(k_to_c128<R>, dim3(grid_for(dim)), dim3(kBlock), 0, st,
+                       (const typename Cplx<R>::T *)src, (double2 *)dst, dim);
+    check_launch();
+}
+
+template <typename R> void launch_copy(const void *src, void *dst, int n, hipStream_t st) {
+    const uint64_t dim = uint64_t(1) << n;
+    hipLaunchKernelGGL(k_copy<R>, dim3(grid_for(dim)), dim3(kBlock), 0, st,
+                       (const typename Cplx<R>::T *)src, (typename Cplx<R>::T *)dst, dim);
+    check_launch();
+}
+
+template <typename R> void launch_apply_1q(void *s0, void *s1, int n, int q, const DevMat2 &m, hipStream_t st) {
+    hipLaunchKernelGGL(k_apply_1q<R>, dim3(grid_for(uint64_t(1) << (n - 1))), dim3(kBlock), 0, st,
+                       (typename Cplx<R>::T *)s0, (typename Cplx<R>::T *)s1, n, q, m);
+    check_launch();
+}
+
+template <typename R> void launch_cnot(void *s0, void *s1, int n, int c, int t, hipStream_t st) {
+    hipLaunchKernelGGL(k_cnot<R>, dim3(grid_for(uint64_t(1) << (n - 2))), dim3(kBlock), 0, st,
+                       (typename Cplx<R>::T *)s0, (typename Cplx<R>::T *)s1, n, c, t);
+    check_launch();
+}
+
+template <typename R> void launch_cz(void *s0, void *s1, int n, int a, int b, hipStream_t st) {
+    hipLaunchKernelGGL(k_cz<R>, dim3(grid_for(uint64_t(1) << (n - 2))), dim3(kBlock), 0, st,
+                       (typename Cplx<R>::T *)s0, (typename Cplx<R>::T *)s1, n, a, b);
+    check_launch();
+}
+
+template <typename R> void launch_seed(const void *y, void *lam, void *phi, int n, int q, int axis, hipStream_t st) {
+    hipLaunchKernelGGL(k_seed<R>, dim3(grid_for(uint64_t(1) << (n - 1))), dim3(kBlock), 0, st,
+                       (const typename Cplx<R>::T *)y, (typename Cplx<R>::T *)lam, (typename Cplx<R>::T *)phi, n, q,
+                       axis);
+    check_launch();
+}
+
+template <typename R>
+void launch_pauli_prod(const void *a, const void *b, int n, int q, int axis, double *partials, double *dest,
+                       hipStream_t st) {
+    const int nb = reduce_blocks(n);
+    hipLaunchKernelGGL(k_pauli_prod_partial<R>, dim3(nb), dim3(kBlock), 0, st, (const typename Cplx<R>::T *)a,
+                       (const typename Cplx<R>::T *)b, n, q, axis, partials);
+    check_launch();
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, st, (const double *)partials, nb, dest);
+    check_launch();
+}
+
+template <typename R>
+void launch_pauli_term(const void *psi, void *out, int n, uint64_t flip, uint64_t zy, int n_y, double coeff, int first,
+                       hipStream_t st) {
+    // coeff * (-i)^{n_y}
+    double fr = coeff, fi = 0.0;
+    for (int k = 0; k < (n_y & 3); ++k) { const double t = fr; fr = fi; fi = -t; }
+    const uint64_t dim = uint64_t(1) << n;
+    hipLaunchKernelGGL(k_pauli_term<R>, dim3(grid_for(dim)), dim3(kBlock), 0, st, (const typename Cplx<R>::T *)psi,
+                       (typename Cplx<R>::T *)out, n, flip, zy, fr, fi, first);
+    check_launch();
+}
+
+void launch_unpack_metric(const double *Lraw, const double *Traw, const int *param_of, int P, double *G_out,
+                          double *T_out, hipStream_t st) {
+    const int64_t work = (int64_t)P * P;
+    if (work == 0) return;
+    hipLaunchKernelGGL(k_unpack_metric, dim3((unsigned)((work + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, Lraw,
+                       Traw, param_of, P, G_out, T_out);
+    check_launch();
+}
+
+void launch_grad_from_raw(const double *graw, const int *param_of, int P, double *grad, hipStream_t st) {
+    if (P <= 0) return;
+    hipLaunchKernelGGL(k_grad_from_raw, dim3((P + kBlock - 1) / kBlock), dim3(kBlock), 0, st, graw, param_of, P, grad);
+    check_launch();
+}
+
+#define QNG_INSTANTIATE(R)                                                                                        \
+    template void launch_init_state<R>(void *, int, const void *, hipStream_t);                                  \
+    template void launch_to_c128<R>(const void *, void *, int, hipStream_t);                                      \
+    template void launch_copy<R>(const void *, void *, int, hipStream_t);                                         \
+    template void launch_apply_1q<R>(void *, void *, int, int, const DevMat2 &, hipStream_t);                     \
+    template void launch_cnot<R>(void *, void *, int, int, int, hipStream_t);                                     \
+    template void launch_cz<R>(void *, void *, int, int, int, hipStream_t);                                       \
+    template void launch_seed<R>(const void *, void *, void *, int, int, int, hipStream_t);                      \
+    template void launch_pauli_prod<R>(const void *, const void *, int, int, int, double *, double *, hipStream_t); \
+    template void launch_pauli_term<R>(const void *, void *, int, uint64_t, uint64_t, int, double, int, hipStream_t);
+
+QNG_INSTANTIATE(double)
+QNG_INSTANTIATE(float)
+
+}  // namespace qng

@@ -1,0 +1,58 @@
+// kernels.hpp -- host-side launchers of the per-primitive HIP kernels.
+//
+// The paper builds everything from three primitives on 2^n-amplitude state
+// vectors: clone a state, apply a gate, take an inner product (abstract;
+// appendix introduction).  These launchers are those primitives (plus the
+// Pauli-sum Hamiltonian) as one kernel each, on interleaved complex states of
+// element type R (double: complex128, float: complex64).  Inner products are
+// always accumulated in FP64 through a deterministic two-stage reduction.
+//
+// All pointers are device pointers; every launch is asynchronous on `st`.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+namespace qng {
+
+struct DevMat2 {   // 2x2 complex matrix, FP64, row-major
+    double ar, ai, br, bi, cr, ci, dr, di;
+};
+
+// Number of first-stage blocks used by the reductions for a register of n qubits.
+int reduce_blocks(int n);
+
+template <typename R> void launch_init_state(void *dst, int n, const void *src_c128, hipStream_t st);
+template <typename R> void launch_to_c128(const void *src, void *dst, int n, hipStream_t st);
+template <typename R> void launch_copy(const void *src, void *dst, int n, hipStream_t st);
+
+// Apply a 2x2 matrix on qubit q to one register (s1 == nullptr) or to two.
+template <typename R> void launch_apply_1q(void *s0, void *s1, int n, int q, const DevMat2 &m, hipStream_t st);
+template <typename R> void launch_cnot(void *s0, void *s1, int n, int control, int target, hipStream_t st);
+template <typename R> void launch_cz(void *s0, void *s1, int n, int a, int b, hipStream_t st);
+
+// lam = y; phi = sigma_q y  (axis 0/1/2 = X/Y/Z).
+template <typename R> void launch_seed(const void *y, void *lam, void *phi, int n, int q, int axis, hipStream_t st);
+
+// dest (one complex128) = <a| sigma_q |b>; axis -1 means the identity (plain inner product).
+// partials: reduce_blocks(n) complex128 scratch.
+template <typename R>
+void launch_pauli_prod(const void *a, const void *b, int n, int q, int axis, double *partials, double *dest,
+                       hipStream_t st);
+
+// out (+)= coeff * (-i)^{n_y} (-1)^{popcount(x & zy)} psi[x ^ flip]; first != 0 overwrites.
+template <typename R>
+void launch_pauli_term(const void *psi, void *out, int n, uint64_t flip, uint64_t zy, int n_y, double coeff,
+                       int first, hipStream_t st);
+
+// Device-side unpack of G = L - T^* T into parameter order (Alg. 1 unpack):
+// Lraw[r*P+s] (r<s, rotation order) holds <lam|sigma_r|phi>, Traw[s] holds <y_s|sigma_s|y_s>;
+// param_of[r] maps rotation r to its parameter index.  G_out: P*P complex, T_out: P complex (nullable).
+void launch_unpack_metric(const double *Lraw, const double *Traw, const int *param_of, int P, double *G_out,
+                          double *T_out, hipStream_t st);
+
+// grad[param_of[r]] = -Im graw[r]   (d_r E = 2 Re[(i/2) <lambda|sigma_r|phi>]).
+void launch_grad_from_raw(const double *graw, const int *param_of, int P, double *grad, hipStream_t st);
+
+}  // namespace qng

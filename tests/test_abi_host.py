@@ -1,0 +1,123 @@
+"""CPU-only checks of the C ABI library: it loads, exports every symbol the
+header declares, and its host-only logic (validation, error codes, solve) is
+correct.  No compute entry point is called without a GPU."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qng.h")
+
+
+@pytest.fixture(scope="module")
+def qng():
+    import paper_2011_02991_amd as q
+    return q
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:qng_status|void|const char \*)\s*(qng_\w+)\s*\(", text, re.M)))
+
+
+def test_header_symbols_exported(qng):
+    syms = declared_symbols()
+    assert len(syms) >= 15
+    for s in syms:
+        assert hasattr(qng.lib(), s), s
+    assert sorted(qng.EXPORTED) == syms
+
+
+def _circ(qng, pr):
+    return qng.Circuit.from_problem(pr)
+
+
+def test_validate_accepts_workloads(qng):
+    for cfg in (W.config1, W.config2, W.config3, W.config5):
+        pr = cfg()
+        qng.validate(_circ(qng, pr), pr.theta)
+    for pr in W.config4()[:5]:
+        qng.validate(_circ(qng, pr), pr.theta)
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (lambda g: g.__setitem__((0, 1), 99), "QNG_E_BAD_CIRCUIT"),          # qubit out of range
+    (lambda g: g.__setitem__((0, 0), 7), "QNG_E_BAD_CIRCUIT"),           # unknown kind
+    (lambda g: g.__setitem__((1, 3), 0), "QNG_E_BAD_PARAMS"),            # shared parameter
+    (lambda g: g.__setitem__((0, 2), 3), "QNG_E_BAD_CIRCUIT"),           # rotation with q1 != -1
+])
+def test_validate_rejects_bad_circuits(qng, mutate, status):
+    pr = W.scaled(W.config1, 4, 1)
+    g = pr.gates.copy()
+    mutate(g)
+    with pytest.raises(qng.QNGError) as e:
+        qng.validate(qng.Circuit(4, g, pr.n_params, pr.pauli, pr.coeff), pr.theta)
+    assert e.value.name == status
+
+
+def test_validate_two_qubit_gate_same_qubit(qng):
+    g = np.array([[W.RY, 0, -1, 0], [W.CNOT, 1, 1, -1]], dtype=np.int32)
+    with pytest.raises(qng.QNGError) as e:
+        qng.validate(qng.Circuit(2, g, 1), [0.1], with_hamiltonian=False)
+    assert e.value.name == "QNG_E_BAD_CIRCUIT"
+
+
+def test_validate_missing_parameter(qng):
+    g = np.array([[W.RY, 0, -1, 0], [W.RZ, 1, -1, 2]], dtype=np.int32)
+    with pytest.raises(qng.QNGError) as e:
+        qng.validate(qng.Circuit(2, g, 2), [0.1, 0.2], with_hamiltonian=False)
+    assert e.value.name == "QNG_E_BAD_PARAMS"
+
+
+def test_validate_nonfinite(qng):
+    pr = W.scaled(W.config1, 3, 1)
+    th = pr.theta.copy()
+    th[2] = np.nan
+    with pytest.raises(qng.QNGError) as e:
+        qng.validate(_circ(qng, pr), th)
+    assert e.value.name == "QNG_E_NONFINITE"
+    c = qng.Circuit(3, pr.gates, pr.n_params, pr.pauli, np.where(np.arange(pr.n_terms) == 1, np.inf, pr.coeff))
+    with pytest.raises(qng.QNGError) as e:
+        qng.validate(c, pr.theta)
+    assert e.value.name == "QNG_E_NONFINITE"
+
+
+def test_validate_bad_pauli_letter(qng):
+    pr = W.scaled(W.config1, 3, 1)
+    p = pr.pauli.copy()
+    p[0, 0] = 4
+    with pytest.raises(qng.QNGError) as e:
+        qng.validate(qng.Circuit(3, pr.gates, pr.n_params, p, pr.coeff), pr.theta)
+    assert e.value.name == "QNG_E_INVALID_ARG"
+
+
+def test_solve_shifted_matches_numpy(qng):
+    rng = np.random.default_rng(1)
+    P = 37
+    A = rng.standard_normal((P, P)) + 1j * rng.standard_normal((P, P))
+    G = A @ A.conj().T / P
+    b = rng.standard_normal(P)
+    x = qng.solve_shifted(G, 1e-4, b)
+    want = np.linalg.solve(G.real + 1e-4 * np.eye(P), b)
+    np.testing.assert_allclose(x, want, rtol=1e-10, atol=1e-12)
+
+
+def test_solve_shifted_not_spd(qng):
+    G = np.zeros((3, 3), dtype=np.complex128)
+    G[0, 0] = 1.0
+    with pytest.raises(qng.QNGError) as e:
+        qng.solve_shifted(G, 0.0, np.ones(3))
+    assert e.value.name == "QNG_E_NOT_SPD"
+
+
+def test_create_without_gpu_fails_cleanly(qng):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(qng.QNGError) as e:
+        qng.Context(0)
+    assert e.value.name == "QNG_E_DEVICE"

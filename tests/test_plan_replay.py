@@ -1,0 +1,144 @@
+"""CPU check of the fused-sweep planner.
+
+The planner reorders each column's backward sweep (commuting operations only)
+and cuts it into passes whose operations act on the pass's tile qubits.  Tiles
+of a register are independent, so executing a pass tile by tile is the same as
+applying its operations, in order, to the whole register.  These tests replay
+the exported plan that way with the oracle's own gate and Pauli routines and
+compare the resulting G and T with the oracle's definition-based values; they
+also check that every operation is executable in its pass's tile.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+OP_ROT, OP_PRODROT, OP_PROD, OP_CNOT, OP_CZ, OP_ZSUM = range(6)
+LETTER = {0: 1, 1: 2, 2: 3}   # axis -> Pauli letter
+
+
+@pytest.fixture(scope="module")
+def qng():
+    import paper_2011_02991_amd as q
+    return q
+
+
+def replay(qng, pr, tile_qubits, prec="c128"):
+    circ = qng.Circuit.from_problem(pr)
+    rows = qng.plan_export(circ, tile_qubits, prec)
+    n, P = pr.n_qubits, pr.n_params
+    gates = pr.gates
+    rot_pos = [k for k in range(len(gates)) if gates[k, 3] >= 0]
+    rot_of_pos = {k: r for r, k in enumerate(rot_pos)}
+    neg = -pr.theta    # R(theta)^dagger = R(-theta) for exp(i theta sigma/2)
+
+    def unapply(state, pos):
+        return oracle.apply_gate(n, gates[pos], neg, state)
+
+    def prod(a, b, q, axis):
+        return np.vdot(a, oracle.apply_pauli_letter(n, q, LETTER[axis], b))
+
+    # states just before each rotation
+    ys = []
+    psi = np.zeros(2 ** n, dtype=np.complex128)
+    psi[0] = 1
+    if pr.in_state is not None:
+        psi = pr.in_state.copy()
+    pos = 0
+    for k in rot_pos:
+        while pos < k:
+            psi = oracle.apply_gate(n, gates[pos], pr.theta, psi)
+            pos += 1
+        ys.append(psi.copy())
+    Lraw = np.zeros((P, P), dtype=np.complex128)
+    seen = np.zeros((P, P), dtype=bool)
+    max_tile = 0
+    cols = {}
+    for r in rows:
+        cols.setdefault(int(r[0]), []).append(r)
+    for s, ops in cols.items():
+        q_s = int(gates[rot_pos[s], 1])
+        ax_s = int(gates[rot_pos[s], 0])
+        lam = ys[s].copy()
+        phi = oracle.apply_pauli_letter(n, q_s, LETTER[ax_s], ys[s])
+        for r in ops:
+            typ, q0, q1, g, dest, axis = (int(v) for v in r[2:8])
+            mask = int(r[8]) | (int(r[9]) << 31)
+            max_tile = max(max_tile, bin(mask).count("1"))
+            inside = lambda q: (mask >> q) & 1
+            if typ in (OP_PROD, OP_PRODROT, OP_ZSUM):
+                if typ == OP_ZSUM:
+                    assert axis == 2 and not inside(q0)
+                else:
+                    assert inside(q0)
+                rr, ss = divmod(dest, P)
+                assert ss == s and rr < s and not seen[rr, ss]
+                seen[rr, ss] = True
+                Lraw[rr, ss] = prod(lam, phi, q0, axis)
+                if typ == OP_PRODROT:
+                    assert rot_of_pos[g] == rr
+                    lam, phi = unapply(lam, g), unapply(phi, g)
+            elif typ == OP_ROT:
+                assert inside(q0) and int(gates[g, 1]) == q0
+                lam, phi = unapply(lam, g), unapply(phi, g)
+            elif typ == OP_CNOT:
+                assert inside(q1)
+                lam, phi = unapply(lam, g), unapply(phi, g)
+            elif typ == OP_CZ:
+                assert inside(q0) or inside(q1)
+                lam, phi = unapply(lam, g), unapply(phi, g)
+            else:
+                raise AssertionError(typ)
+    # every element r < s evaluated exactly once
+    assert seen.sum() == P * (P - 1) // 2
+    assert np.all(np.triu(seen, 1) == seen)
+    # assemble G from the recurrence (L_rs = <lam|sigma_r|phi>/4, T_s = (i/2)<y_s|sigma_s|y_s>)
+    T = np.array([0.5j * prod(ys[s], ys[s], int(gates[rot_pos[s], 1]), int(gates[rot_pos[s], 0])) for s in range(P)])
+    Lb = 0.25 * Lraw
+    L = np.triu(Lb, 1) + np.triu(Lb, 1).conj().T + 0.25 * np.eye(P)
+    Gb = L - np.outer(T.conj(), T)
+    perm = gates[rot_pos, 3]
+    G = np.empty_like(Gb)
+    G[np.ix_(perm, perm)] = Gb
+    Tp = np.empty_like(T)
+    Tp[perm] = T
+    return G, Tp, max_tile, rows
+
+
+@pytest.mark.parametrize("cfg,n,layers,tile", [
+    (W.config3, 9, 3, 6), (W.config3, 10, 4, 7), (W.config2, 9, 3, 6), (W.config5, 8, 3, 5),
+    (W.config1, 10, 3, 10), (W.config3, 11, 2, 8), (W.config2, 12, 2, 9), (W.config3, 8, 2, 0),
+])
+def test_plan_replay_matches_oracle(qng, cfg, n, layers, tile):
+    pr = W.scaled(cfg, n, layers)
+    G, T, max_tile, rows = replay(qng, pr, tile)
+    Gw, Tw = oracle.metric(pr)
+    np.testing.assert_allclose(G, Gw, atol=1e-13)
+    np.testing.assert_allclose(T, Tw, atol=1e-13)
+    if tile:
+        assert max_tile == min(tile, n)
+    assert all(bin(int(r[8]) | (int(r[9]) << 31)).count("1") == max_tile for r in rows)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_plan_replay_random_circuits(qng, seed):
+    pr = W.random_circuit(7, 45, seed=seed, fixed_fraction=0.4)
+    if seed % 2:
+        pr.in_state = W.random_state(7, seed)
+    if seed % 3 == 0:
+        pr = W.permute_params(pr, seed)
+    G, T, max_tile, _ = replay(qng, pr, 5)
+    Gw, Tw = oracle.metric(pr)
+    np.testing.assert_allclose(G, Gw, atol=1e-13)
+    np.testing.assert_allclose(T, Tw, atol=1e-13)
+    assert max_tile == 5
+
+
+def test_plan_sizes_of_workloads(qng):
+    """The plan covers every element once and fuses many elements per pass."""
+    for cfg, prec in ((W.config3, "c64"), (W.config2, "c128"), (W.config5, "c128")):
+        pr = cfg()
+        info = qng.plan(qng.Circuit.from_problem(pr), 1, 12 if prec == "c64" else 11)
+        assert info["elements"] == pr.n_params * (pr.n_params - 1) // 2
+        assert info["elements"] / info["passes"] > 20
