@@ -102,7 +102,8 @@ typedef enum {
     QNG_OPT_TILE_QUBITS = 1,     /* qubits per on-chip tile of a fused pass (0 = automatic) */
     QNG_OPT_COLUMN_STREAMS = 2,  /* columns swept concurrently, each with its own 2 states (0 = automatic) */
     QNG_OPT_PROFILE = 3,         /* 1: time every sweep-pass launch with HIP events (see qng_stats) */
-    QNG_OPT_SMALL_N_KERNEL = 4   /* 1 (default): whole-column on-chip kernel for small registers */
+    QNG_OPT_SMALL_N_KERNEL = 4,  /* 1 (default): whole-column on-chip kernel for small registers */
+    QNG_OPT_F64_REGISTERS = 5    /* complex64 storage: 1 = sweep tiles computed in FP64 registers, 0 = FP32 */
 } qng_option;
 
 /* Counters of the last metric/energy/step call on a context. */
@@ -123,7 +124,7 @@ typedef struct {
     int64_t passes;              /* fused sweep passes over all columns */
     int64_t elements;            /* P(P-1)/2 */
     int64_t ops;                 /* gate applications + inner products inside those passes */
-    int64_t load_maps;           /* passes that start with a permuted (CNOT) gather */
+    int64_t transposes;          /* LDS exchanges between register phases inside those passes */
     int32_t tile_qubits;         /* qubits per tile used by the plan */
     int32_t small_n;             /* 1 if the whole-column on-chip kernel is used */
 } qng_plan_info;
@@ -160,13 +161,14 @@ qng_status qng_validate(const qng_circuit *circ, const double *theta, const qng_
  * (0 = automatic) and report its size.  Host only. */
 qng_status qng_plan(const qng_circuit *circ, int fusion, int tile_qubits, qng_plan_info *out);
 /* Export the fused sweep plan (host only): one row of 10 int32 per operation,
- * in execution order: {column s, pass index within the column, op type
- * (0 rotation adjoint, 1 inner product then rotation adjoint, 2 inner product,
- * 3 CNOT adjoint, 4 CZ, 5 Z inner product outside the tile), qubit q0, qubit q1
- * (CNOT target / CZ second qubit, else -1), gate position (or -1), destination
- * r*P + s of an inner product (or -1), Pauli axis (0 X, 1 Y, 2 Z; or -1),
- * tile-qubit mask bits 0..30, tile-qubit mask bits 31..61}.  amp_bytes: 16 for
- * complex128 plans, 8 for complex64.  With rows = NULL only *n_rows is set. */
+ * in execution order (in-register exchanges omitted): {column s, pass index
+ * within the column, kind (0 gate adjoint, 1 inner product then the adjoint of
+ * its rotation, 2 inner product), qubit q0 (CNOT: control), qubit q1 (CNOT
+ * target / CZ second qubit, else -1), gate position of the adjoint (or -1),
+ * destination r*P + s of an inner product (or -1), Pauli axis of the inner
+ * product (0 X, 1 Y, 2 Z; or -1), tile-qubit mask bits 0..30, bits 31..61}.
+ * amp_bytes: 16 for complex128 plans, 8 for complex64.  With rows = NULL only
+ * *n_rows is set. */
 qng_status qng_plan_export(const qng_circuit *circ, int tile_qubits, int amp_bytes, int32_t *rows, int64_t cap,
                            int64_t *n_rows);
 /* Solve (Re G + eps I) x = b in FP64 by Cholesky (host).  G: 2*P*P doubles

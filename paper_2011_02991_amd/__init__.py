@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libqng.so")
 C128, C64 = 0, 1
 PRECISIONS = {"c128": C128, "complex128": C128, C128: C128, "c64": C64, "complex64": C64, C64: C64}
 
-OPT_FUSION, OPT_TILE_QUBITS, OPT_COLUMN_STREAMS, OPT_PROFILE, OPT_SMALL_N_KERNEL = 0, 1, 2, 3, 4
+OPT_FUSION, OPT_TILE_QUBITS, OPT_COLUMN_STREAMS, OPT_PROFILE, OPT_SMALL_N_KERNEL, OPT_F64_REGISTERS = 0, 1, 2, 3, 4, 5
 
 STATUS = {
     0: "QNG_OK", -1: "QNG_E_INVALID_ARG", -2: "QNG_E_BAD_CIRCUIT", -3: "QNG_E_BAD_PARAMS",
@@ -65,7 +65,7 @@ class Stats(ctypes.Structure):
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [("passes", ctypes.c_int64), ("elements", ctypes.c_int64), ("ops", ctypes.c_int64),
-                ("load_maps", ctypes.c_int64), ("tile_qubits", ctypes.c_int32), ("small_n", ctypes.c_int32)]
+                ("transposes", ctypes.c_int64), ("tile_qubits", ctypes.c_int32), ("small_n", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -20,8 +20,11 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function"]
+# -simplifycfg-sink-common=false: the sweep kernel dispatches on a register
+# position with a switch whose cases differ only in which registers they touch;
+# sinking them into one block turns register arrays into stack memory.
 DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-fno-gpu-rdc"]
+          "-fno-gpu-rdc", "-mllvm", "-simplifycfg-sink-common=false"]
 HOST = ["-D__HIP_PLATFORM_AMD__"]
 
 

@@ -49,7 +49,7 @@ struct qng_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     size_t mem_limit = 0;
-    int opt_fusion = 1, opt_tile = 0, opt_streams = 0, opt_profile = 0, opt_small = 1;
+    int opt_fusion = 1, opt_tile = 0, opt_streams = 0, opt_profile = 0, opt_small = 1, opt_f64_regs = 0;
     std::string last_error;
     qng_stats stats{};
     void *ws = nullptr;
@@ -332,7 +332,8 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
     size_t scratch = 0;
     int n_states = 4;
     if (fused) {
-        plan = &ctx->sweep_cache.get(c, ctx->opt_tile, (int)amp, ctx->opt_small);
+        const bool f64_regs = amp == 16 || ctx->opt_f64_regs;
+        plan = &ctx->sweep_cache.get(c, ctx->opt_tile, (int)amp, ctx->opt_small, f64_regs);
         size_t free_b = 0, total_b = 0;
         HIPCHECK(hipMemGetInfo(&free_b, &total_b));
         fr = fused_config(*plan, ctx->opt_streams, V, free_b + ctx->ws_bytes);
@@ -368,7 +369,8 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
             fb.traw = e.traw();
             fb.lraw = e.lraw();
             fb.reduce_partials = e.partials();
-            pos = run_fused_metric<R>(*plan, fr, c, pb.fwd, pb.adj, fb, st, &ctx->stats, ctx->opt_profile != 0);
+            pos = run_fused_metric<R>(*plan, fr, c, pb.fwd, pb.adj, fb, st, &ctx->stats, ctx->opt_profile != 0,
+                                      amp == 16 || ctx->opt_f64_regs);
         } else {
             pos = e.metric_unfused();
         }
@@ -501,6 +503,7 @@ qng_status qng_set_option(qng_ctx *ctx, int option, int value) {
             break;
         case QNG_OPT_PROFILE: ctx->opt_profile = value ? 1 : 0; break;
         case QNG_OPT_SMALL_N_KERNEL: ctx->opt_small = value ? 1 : 0; break;
+        case QNG_OPT_F64_REGISTERS: ctx->opt_f64_regs = value ? 1 : 0; break;
         default: fail(QNG_E_INVALID_ARG, "unknown option " + std::to_string(option));
         }
     });
@@ -544,7 +547,7 @@ qng_status qng_plan(const qng_circuit *circ, int fusion, int tile_qubits, qng_pl
             out->passes = 0;
             return;
         }
-        SweepPlan plan = build_sweep_plan(c, tile_qubits, 16, 1);
+        SweepPlan plan = build_sweep_plan(c, tile_qubits, 16, 1, true);
         plan.fill_info(out);
     });
 }
@@ -556,7 +559,7 @@ qng_status qng_plan_export(const qng_circuit *circ, int tile_qubits, int amp_byt
         if (amp_bytes != 8 && amp_bytes != 16) fail(QNG_E_INVALID_ARG, "amp_bytes must be 8 or 16");
         validate_circuit(circ, kMaxQubitsC64);
         Circuit c = compile_circuit(circ);
-        SweepPlan plan = build_sweep_plan(c, tile_qubits, amp_bytes, 1);
+        SweepPlan plan = build_sweep_plan(c, tile_qubits, amp_bytes, 1, amp_bytes == 16);
         int64_t k = 0;
         for (const ColumnPlan &cp : plan.cols) {
             for (size_t pi = 0; pi < cp.passes.size(); ++pi) {
@@ -564,18 +567,21 @@ qng_status qng_plan_export(const qng_circuit *circ, int tile_qubits, int amp_byt
                 uint64_t mask = 0;
                 for (uint8_t q : hp.tile) mask |= uint64_t(1) << q;
                 for (const DevOp &op : hp.ops) {
+                    if (op.type == OP_XPOSE) continue;
                     if (rows && k < cap) {
                         int32_t *r = rows + 10 * k;
-                        const bool is_prod = op.type == OP_PRODROT || op.type == OP_PROD || op.type == OP_ZSUM;
+                        const bool prod = op.type == OP_PRODROT || op.type == OP_PROD || op.type == OP_ZSUM ||
+                                          op.type == OP_PRODZ || op.type == OP_PRODDIAG;
+                        const bool adj = op.type == OP_ROT || op.type == OP_PRODROT || op.type == OP_CNOT ||
+                                         op.type == OP_CZ || op.type == OP_DIAG || op.type == OP_PRODDIAG;
                         r[0] = cp.s;
                         r[1] = (int32_t)pi;
-                        r[2] = op.type;
+                        r[2] = prod ? (adj ? 1 : 2) : 0;
                         r[3] = op.q0;
-                        r[4] = (op.type == OP_CNOT) ? (int32_t)hp.tile[op.b1] : (op.type == OP_CZ ? op.q1 : -1);
-                        if (op.type == OP_ROT || op.type == OP_PRODROT) r[3] = hp.tile[op.b0];
-                        r[5] = op.gate;
-                        r[6] = is_prod ? hp.slot_dest[op.slot] : -1;
-                        r[7] = is_prod ? op.axis : -1;
+                        r[4] = (op.type == OP_CNOT || op.type == OP_CZ) ? op.q1 : -1;
+                        r[5] = adj ? op.gate : -1;
+                        r[6] = prod ? hp.slot_dest[op.slot] : -1;
+                        r[7] = prod ? op.axis : -1;
                         r[8] = (int32_t)(mask & 0x7fffffffu);
                         r[9] = (int32_t)((mask >> 31) & 0x7fffffffu);
                     }

@@ -38,6 +38,7 @@ size_t fused_scratch_bytes(const SweepPlan &plan, const FusedRun &fr, int M) {
     b += align256((size_t)M * 64 + 64);                                  // matrix table
     b += align256(plan.dev_passes.size() * sizeof(DevPass) + 64);       // passes
     b += align256(plan.dev_ops.size() * sizeof(DevOp) + 64);            // ops
+    b += align256(plan.dev_maps.size() * sizeof(DevMap) + 64);          // thread mappings
     b += align256(plan.dev_passes.size() * sizeof(LaunchItem) + 64);    // one item per pass
     b += align256((size_t)plan.P * plan.P * sizeof(ReduceTask) / 2 + 64);  // one task per element
     b += align256(fr.partial_elems * 16);
@@ -47,7 +48,7 @@ size_t fused_scratch_bytes(const SweepPlan &plan, const FusedRun &fr, int M) {
 template <typename R>
 int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c, const std::vector<Mat2> &fwd,
                      const std::vector<Mat2> &adj, const FusedBuffers &buf, hipStream_t st, qng_stats *stats,
-                     bool profile) {
+                     bool profile, bool f64_regs) {
     const int n = c.n;
     const size_t V = buf.state_bytes;
     const uint32_t tiles = 1u << (n - plan.m);
@@ -115,6 +116,7 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
     double *d_mats = (double *)take(mats.size() * 8);
     DevPass *d_passes = (DevPass *)take(plan.dev_passes.size() * sizeof(DevPass));
     DevOp *d_ops = (DevOp *)take(plan.dev_ops.size() * sizeof(DevOp));
+    DevMap *d_maps = (DevMap *)take(plan.dev_maps.size() * sizeof(DevMap));
     LaunchItem *d_items = (LaunchItem *)take(items.size() * sizeof(LaunchItem));
     ReduceTask *d_tasks = (ReduceTask *)take(tasks.size() * sizeof(ReduceTask));
     double *d_partials = (double *)p;
@@ -127,6 +129,9 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
     if (!plan.dev_ops.empty())
         FCHECK(hipMemcpyAsync(d_ops, plan.dev_ops.data(), plan.dev_ops.size() * sizeof(DevOp), hipMemcpyHostToDevice,
                               st));
+    if (!plan.dev_maps.empty())
+        FCHECK(hipMemcpyAsync(d_maps, plan.dev_maps.data(), plan.dev_maps.size() * sizeof(DevMap),
+                              hipMemcpyHostToDevice, st));
     if (!items.empty())
         FCHECK(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(LaunchItem), hipMemcpyHostToDevice, st));
     if (!tasks.empty())
@@ -168,8 +173,8 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
         for (size_t li = G.launch_begin; li < G.launch_end; ++li) {
             const Launch &L = launches[li];
             if (profile) FCHECK(hipEventRecord(ev[2 * li], st));
-            launch_sweep_pass<R>(d_items + L.item_begin, (int)L.n_items, L.total_tiles, d_passes, d_ops, d_mats,
-                                 d_partials, plan.m, st);
+            launch_sweep_pass<R>(d_items + L.item_begin, (int)L.n_items, L.total_tiles, d_passes, d_ops, d_maps,
+                                 d_mats, d_partials, plan.m, plan.rb, f64_regs, st);
             if (profile) FCHECK(hipEventRecord(ev[2 * li + 1], st));
             launch_reduce_tasks(d_tasks + L.task_begin, (int)L.n_tasks, d_partials, buf.lraw, st);
             ++stats->sweep_launches;
@@ -194,8 +199,8 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
 }
 
 template int run_fused_metric<double>(const SweepPlan &, const FusedRun &, const Circuit &, const std::vector<Mat2> &,
-                                      const std::vector<Mat2> &, const FusedBuffers &, hipStream_t, qng_stats *, bool);
+                                      const std::vector<Mat2> &, const FusedBuffers &, hipStream_t, qng_stats *, bool, bool);
 template int run_fused_metric<float>(const SweepPlan &, const FusedRun &, const Circuit &, const std::vector<Mat2> &,
-                                     const std::vector<Mat2> &, const FusedBuffers &, hipStream_t, qng_stats *, bool);
+                                     const std::vector<Mat2> &, const FusedBuffers &, hipStream_t, qng_stats *, bool, bool);
 
 }  // namespace qng

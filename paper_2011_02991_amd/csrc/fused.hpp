@@ -29,6 +29,6 @@ size_t fused_scratch_bytes(const SweepPlan &plan, const FusedRun &fr, int M);
 template <typename R>
 int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c, const std::vector<Mat2> &fwd,
                      const std::vector<Mat2> &adj, const FusedBuffers &buf, hipStream_t st, qng_stats *stats,
-                     bool profile);
+                     bool profile, bool f64_regs);
 
 }  // namespace qng

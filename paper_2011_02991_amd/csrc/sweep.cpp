@@ -181,81 +181,239 @@ int choose_and_emit(const std::vector<Event> &ev, std::vector<uint8_t> &done, st
     return k;
 }
 
-HostPass make_pass(const Circuit &c, int s, const std::vector<Event> &ev, const std::vector<int> &emitted,
-                   const std::vector<uint8_t> &tile) {
-    HostPass hp;
-    hp.tile = tile;
-    std::vector<int> local(c.n, -1);
-    for (size_t b = 0; b < tile.size(); ++b) local[tile[b]] = (int)b;
-    for (size_t k = 0; k < emitted.size(); ++k) {
-        const Event &e = ev[emitted[k]];
-        DevOp op{};
-        op.b0 = op.b1 = kNoBit;
-        op.gate = -1;
-        if (e.kind == EV_PROD) {
-            const int q = e.q[0];
-            const uint16_t slot = (uint16_t)hp.slot_dest.size();
-            hp.slot_dest.push_back((int32_t)(e.rot * c.P + s));
-            op.slot = slot;
-            op.axis = e.type[0];
-            op.q0 = (uint8_t)q;
-            if (local[q] < 0) {
-                op.type = OP_ZSUM;
-            } else {
-                op.b0 = (uint8_t)local[q];
-                // fuse with the adjoint of the same rotation when it follows immediately
-                if (k + 1 < emitted.size()) {
-                    const Event &f = ev[emitted[k + 1]];
-                    if (f.kind == EV_UNAPPLY && f.pos == e.pos) {
-                        op.type = OP_PRODROT;
-                        op.gate = f.pos;
-                        hp.ops.push_back(op);
-                        ++k;
-                        continue;
-                    }
-                }
-                op.type = OP_PROD;
+// Local bit that an event needs in a register (X/Y rotations and inner
+// products, CNOT targets), or -1 for diagonal events that run on any bit.
+int needs_register(const Event &e, const std::vector<int> &local) {
+    if (e.kind == EV_PROD) return e.type[0] == TY_Z ? -1 : local[e.q[0]];
+    switch (e.gkind) {
+    case QNG_RX:
+    case QNG_RY: return local[e.q[0]];
+    case QNG_CNOT: return local[e.q[1]];
+    default: return -1;
+    }
+}
+
+// In-order scan of the pass's events with a register set (bit mask over local
+// bits): emit every ready event whose register need is met.
+int scan_phase(const std::vector<Event> &ev, const std::vector<int> &pending, std::vector<uint8_t> &done,
+               uint32_t regset, const std::vector<int> &local, int n, std::vector<int> *out) {
+    std::vector<int> cnt((size_t)n * 3, 0);
+    int emitted = 0;
+    for (int idx : pending) {
+        if (done[idx]) continue;
+        const Event &e = ev[idx];
+        bool ready = true;
+        for (int j = 0; j < e.nq && ready; ++j) {
+            const int *cq = &cnt[(size_t)e.q[j] * 3];
+            for (int t = 0; t < 3; ++t)
+                if (t != e.type[j] && cq[t]) { ready = false; break; }
+        }
+        const int need = needs_register(e, local);
+        const bool ok = ready && (need < 0 || ((regset >> need) & 1u));
+        if (ok) {
+            ++emitted;
+            if (out) {
+                out->push_back(idx);
+                done[idx] = 1;
             }
         } else {
-            const qng_gate &g = c.gates[e.pos];
-            op.gate = e.pos;
-            if (g.kind == QNG_CNOT) {
-                op.type = OP_CNOT;
-                op.q0 = (uint8_t)g.q0;
-                op.b0 = local[g.q0] < 0 ? kNoBit : (uint8_t)local[g.q0];
-                op.b1 = (uint8_t)local[g.q1];
-            } else if (g.kind == QNG_CZ) {
-                op.type = OP_CZ;
-                op.q0 = (uint8_t)g.q0;
-                op.q1 = (uint8_t)g.q1;
-                op.b0 = local[g.q0] < 0 ? kNoBit : (uint8_t)local[g.q0];
-                op.b1 = local[g.q1] < 0 ? kNoBit : (uint8_t)local[g.q1];
-            } else {
-                op.type = OP_ROT;
-                op.b0 = (uint8_t)local[g.q0];
-                op.q0 = (uint8_t)g.q0;
-            }
+            for (int j = 0; j < e.nq; ++j) ++cnt[(size_t)e.q[j] * 3 + e.type[j]];
         }
-        hp.ops.push_back(op);
     }
+    return emitted;
+}
+
+DevMap mapping_for(uint32_t regset, int m, int rb, int carriers) {
+    DevMap mp{};
+    int p = 0;
+    for (int b = 0; b < m; ++b)
+        if ((regset >> b) & 1u) mp.pos[p++] = (uint8_t)b;
+    for (int b = 0; b < carriers; ++b)
+        if (!((regset >> b) & 1u)) mp.pos[p++] = (uint8_t)b;
+    for (int b = carriers; b < m; ++b)
+        if (!((regset >> b) & 1u)) mp.pos[p++] = (uint8_t)b;
+    (void)rb;
+    return mp;
+}
+
+uint8_t location(const DevMap &mp, int rb, int m, int localbit) {
+    for (int p = 0; p < m; ++p)
+        if (mp.pos[p] == localbit) return p < rb ? (uint8_t)p : (uint8_t)(kLocThread | (p - rb));
+    return kLocBase;
+}
+
+HostPass make_pass(const Circuit &c, int s, const std::vector<Event> &ev, const std::vector<int> &emitted,
+                   const std::vector<uint8_t> &tile, int rb, int carriers) {
+    HostPass hp;
+    hp.tile = tile;
+    hp.rb = rb;
+    const int m = (int)tile.size();
+    std::vector<int> local(c.n, -1);
+    for (size_t b = 0; b < tile.size(); ++b) local[tile[b]] = (int)b;
+    const uint32_t carrier_mask = (1u << carriers) - 1u;
+
+    // ---- phases: greedy choice of the register set, then emission in scan order
+    std::vector<uint8_t> done(ev.size(), 0);
+    std::vector<int> pending = emitted;
+    std::vector<std::pair<uint32_t, std::vector<int>>> phases;
+    uint32_t current = 0;
+    bool have_current = false;
+    while (!pending.empty()) {
+        std::vector<uint32_t> cands;
+        if (have_current) cands.push_back(current);
+        {   // registers for the first ready events that need one
+            uint32_t rs = 0;
+            int added = 0;
+            std::vector<int> cnt((size_t)c.n * 3, 0);
+            for (int idx : pending) {
+                if (added >= rb) break;
+                const Event &e = ev[idx];
+                bool ready = true;
+                for (int j = 0; j < e.nq && ready; ++j)
+                    for (int t = 0; t < 3; ++t)
+                        if (t != e.type[j] && cnt[(size_t)e.q[j] * 3 + t]) { ready = false; break; }
+                const int need = needs_register(e, local);
+                if (ready && need >= 0 && !((rs >> need) & 1u)) { rs |= 1u << need; ++added; }
+                for (int j = 0; j < e.nq; ++j) ++cnt[(size_t)e.q[j] * 3 + e.type[j]];
+            }
+            for (int b = m - 1; b >= 0 && added < rb; --b)
+                if (!((rs >> b) & 1u)) { rs |= 1u << b; ++added; }
+            cands.push_back(rs);
+        }
+        for (int a = 0; a + rb <= m; ++a) cands.push_back(((1u << rb) - 1u) << a);
+        int best = -1000000;
+        uint32_t best_rs = cands[0];
+        for (uint32_t rs : cands) {
+            const int k = scan_phase(ev, pending, done, rs, local, c.n, nullptr);
+            const int score = 4 * k - ((have_current && rs != current) ? 3 : 0);
+            if (k > 0 && score > best) { best = score; best_rs = rs; }
+        }
+        std::vector<int> out;
+        scan_phase(ev, pending, done, best_rs, local, c.n, &out);
+        if (out.empty()) fail(QNG_E_DEVICE, "sweep planner: phase made no progress (internal error)");
+        std::vector<int> keep;
+        for (int idx : pending)
+            if (!done[idx]) keep.push_back(idx);
+        pending.swap(keep);
+        if (have_current && best_rs == current) {
+            phases.back().second.insert(phases.back().second.end(), out.begin(), out.end());
+        } else {
+            phases.push_back({best_rs, out});
+            current = best_rs;
+            have_current = true;
+        }
+    }
+
+    // ---- thread mappings: load with the carriers on the lanes
+    auto add_map = [&](const DevMap &mp) { hp.maps.push_back(mp); return (int)hp.maps.size() - 1; };
+    uint32_t load_rs = phases[0].first;
+    bool load_xpose = false;
+    if (load_rs & carrier_mask) {
+        load_rs = ((1u << rb) - 1u) << (m - rb);
+        load_xpose = true;
+    }
+    hp.map_load = add_map(mapping_for(load_rs, m, rb, carriers));
+    int cur_map = hp.map_load;
+    auto xpose_to = [&](uint32_t rs) {
+        const int k = add_map(mapping_for(rs, m, rb, carriers));
+        DevOp op{};
+        op.type = OP_XPOSE;
+        op.b0 = op.b1 = kLocBase;
+        op.gate = -1;
+        op.aux = k;
+        hp.ops.push_back(op);
+        cur_map = k;
+        ++hp.transposes;
+    };
+
+    for (size_t ph = 0; ph < phases.size(); ++ph) {
+        if (ph > 0 || load_xpose) xpose_to(phases[ph].first);
+        const DevMap &mp = hp.maps[cur_map];
+        const std::vector<int> &order = phases[ph].second;
+        auto loc_of_qubit = [&](int q) -> uint8_t { return local[q] < 0 ? kLocBase : location(mp, rb, m, local[q]); };
+        for (size_t k = 0; k < order.size(); ++k) {
+            const Event &e = ev[order[k]];
+            DevOp op{};
+            op.b0 = op.b1 = kLocBase;
+            op.gate = -1;
+            if (e.kind == EV_PROD) {
+                const int q = e.q[0];
+                op.slot = (uint16_t)hp.slot_dest.size();
+                hp.slot_dest.push_back((int32_t)(e.rot * c.P + s));
+                op.axis = e.type[0];
+                op.q0 = (uint8_t)q;
+                const bool fuse = k + 1 < order.size() && ev[order[k + 1]].kind == EV_UNAPPLY &&
+                                  ev[order[k + 1]].pos == e.pos;
+                if (local[q] < 0) {
+                    op.type = OP_ZSUM;
+                } else if (e.type[0] == TY_Z) {
+                    op.b0 = loc_of_qubit(q);
+                    op.type = fuse ? OP_PRODDIAG : OP_PRODZ;
+                } else {
+                    op.b0 = loc_of_qubit(q);
+                    op.type = fuse ? OP_PRODROT : OP_PROD;
+                }
+                if (fuse && op.type != OP_ZSUM) {
+                    op.gate = ev[order[k + 1]].pos;
+                    ++k;
+                }
+            } else {
+                const qng_gate &g = c.gates[e.pos];
+                op.gate = e.pos;
+                op.q0 = (uint8_t)g.q0;
+                if (g.kind == QNG_CNOT) {
+                    op.type = OP_CNOT;
+                    op.q1 = (uint8_t)g.q1;
+                    op.b0 = loc_of_qubit(g.q1);       // a register position
+                    op.b1 = loc_of_qubit(g.q0);
+                } else if (g.kind == QNG_CZ) {
+                    op.type = OP_CZ;
+                    op.q1 = (uint8_t)g.q1;
+                    op.b0 = loc_of_qubit(g.q0);
+                    op.b1 = loc_of_qubit(g.q1);
+                } else if (g.kind == QNG_RZ) {
+                    op.type = OP_DIAG;
+                    op.b0 = loc_of_qubit(g.q0);
+                } else {
+                    op.type = OP_ROT;
+                    op.axis = g.kind == QNG_RX ? TY_X : TY_Y;
+                    op.b0 = loc_of_qubit(g.q0);
+                }
+            }
+            hp.ops.push_back(op);
+        }
+    }
+    // store with the carriers on the lanes
+    if (current & carrier_mask) xpose_to(((1u << rb) - 1u) << (m - rb));
     return hp;
 }
 
 }  // namespace
 
-int default_tile_qubits(int n, int amp_bytes) {
-    const int m = amp_bytes >= 16 ? 11 : 12;
+int default_tile_qubits(int n, int amp_bytes, bool reg_f64) {
+    // FP64 registers: 11 tile qubits, 8 amplitudes of each register per thread
+    // (64 VGPRs of state); FP32 registers (complex64 only): 12 tile qubits,
+    // 16 amplitudes per thread (also 64 VGPRs)
+    const int m = (amp_bytes == 8 && !reg_f64) ? 12 : 11;
     return n < m ? n : m;
 }
 
-SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int /*small*/) {
+int register_bits(int m, int /*amp_bytes*/) {
+    int rb = m - 8;
+    if (rb < 2) rb = std::min(m, 2);
+    return rb > 4 ? 4 : rb;
+}
+
+SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int /*small*/, bool reg_f64) {
     SweepPlan plan;
     plan.n = c.n;
     plan.P = c.P;
-    int m = tile_qubits > 0 ? tile_qubits : default_tile_qubits(c.n, amp_bytes);
-    if (m > kMaxTileQubits) m = kMaxTileQubits;
+    int m = tile_qubits > 0 ? tile_qubits : default_tile_qubits(c.n, amp_bytes, reg_f64);
+    if (m > (reg_f64 ? 11 : 12)) m = reg_f64 ? 11 : 12;
     if (m > c.n) m = c.n;
+    if (c.n - m > kMaxRest) fail(QNG_E_INVALID_ARG, "tile too small for this register (at most 24 qubits outside a tile)");
     plan.m = m;
+    plan.rb = register_bits(m, amp_bytes);
     plan.carriers = c.n > m ? std::min(amp_bytes >= 16 ? 3 : 4, m - 1) : 0;
     if (c.n > m && m - plan.carriers < 2) fail(QNG_E_INVALID_ARG, "tile too small for the carrier qubits");
     for (int s = 1; s < c.P; ++s) {
@@ -269,7 +427,7 @@ SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int
         std::vector<int> emitted;
         while (!pending.empty()) {
             choose_and_emit(ev, done, pending, c.n, m, plan.carriers, tile, emitted);
-            cp.passes.push_back(make_pass(c, s, ev, emitted, tile));
+            cp.passes.push_back(make_pass(c, s, ev, emitted, tile, plan.rb, plan.carriers));
         }
         plan.cols.push_back(std::move(cp));
     }
@@ -278,11 +436,14 @@ SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int
         plan.col_pass_begin.push_back((int64_t)plan.dev_passes.size());
         for (const HostPass &hp : cp.passes) {
             DevPass dp{};
+            const uint32_t map_base = (uint32_t)plan.dev_maps.size();
             dp.op_begin = (uint32_t)plan.dev_ops.size();
             dp.n_ops = (uint32_t)hp.ops.size();
             dp.n_slots = (uint16_t)hp.slot_dest.size();
             dp.m = (uint8_t)hp.tile.size();
             dp.n = (uint8_t)c.n;
+            dp.rb = (uint8_t)hp.rb;
+            dp.map_load = map_base + (uint32_t)hp.map_load;
             for (size_t b = 0; b < hp.tile.size(); ++b) dp.tile_q[b] = hp.tile[b];
             std::vector<uint8_t> in(c.n, 0);
             for (uint8_t q : hp.tile) in[q] = 1;
@@ -290,14 +451,18 @@ SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int
             for (int q = 0; q < c.n; ++q)
                 if (!in[q]) dp.rest_q[k++] = (uint8_t)q;
             dp.nrest = (uint8_t)k;
-            for (const DevOp &op : hp.ops) {
+            bool has_cnot = false;
+            for (DevOp op : hp.ops) {
                 if (op.type == OP_ZSUM) dp.has_zsum = 1;
+                if (op.type == OP_CNOT) has_cnot = true;
+                if (op.type == OP_XPOSE) op.aux += (int32_t)map_base;
                 plan.dev_ops.push_back(op);
             }
+            for (const DevMap &mp : hp.maps) plan.dev_maps.push_back(mp);
             plan.dev_passes.push_back(dp);
             plan.max_slots = std::max<int64_t>(plan.max_slots, dp.n_slots);
-            for (const DevOp &op : hp.ops)
-                if (op.type == OP_CNOT) { ++plan.load_maps; break; }
+            plan.transposes += hp.transposes;
+            if (has_cnot) ++plan.load_maps;
         }
     }
     plan.total_passes = (int64_t)plan.dev_passes.size();
@@ -306,20 +471,20 @@ SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int
 }
 
 size_t SweepPlan::device_bytes() const {
-    return dev_passes.size() * sizeof(DevPass) + dev_ops.size() * sizeof(DevOp);
+    return dev_passes.size() * sizeof(DevPass) + dev_ops.size() * sizeof(DevOp) + dev_maps.size() * sizeof(DevMap);
 }
 
 void SweepPlan::fill_info(qng_plan_info *out) const {
     out->passes = total_passes;
     out->elements = (int64_t)P * (P - 1) / 2;
     out->ops = total_ops;
-    out->load_maps = load_maps;
+    out->transposes = transposes;
     out->tile_qubits = m;
     out->small_n = n <= m ? 1 : 0;
 }
 
-const SweepPlan &SweepCache::get(const Circuit &c, int tile_qubits, int amp_bytes, int small) {
-    std::vector<int32_t> key = {c.n, c.M, c.P, tile_qubits, amp_bytes, small};
+const SweepPlan &SweepCache::get(const Circuit &c, int tile_qubits, int amp_bytes, int small, bool reg_f64) {
+    std::vector<int32_t> key = {c.n, c.M, c.P, tile_qubits, amp_bytes, small, reg_f64 ? 1 : 0};
     for (const qng_gate &g : c.gates) {
         key.push_back(g.kind);
         key.push_back(g.q0);
@@ -329,7 +494,7 @@ const SweepPlan &SweepCache::get(const Circuit &c, int tile_qubits, int amp_byte
     auto it = plans.find(key);
     if (it != plans.end()) return *it->second;
     if (plans.size() > 16) plans.clear();
-    auto p = std::make_shared<SweepPlan>(build_sweep_plan(c, tile_qubits, amp_bytes, small));
+    auto p = std::make_shared<SweepPlan>(build_sweep_plan(c, tile_qubits, amp_bytes, small, reg_f64));
     plans[key] = p;
     return *p;
 }

@@ -44,40 +44,63 @@
 namespace qng {
 
 enum : uint8_t {
-    OP_ROT = 0,      // apply the gate's stored matrix on local bit b0 to both registers
-    OP_PRODROT = 1,  // inner product on local bit b0 (axis), then the rotation (same qubit)
-    OP_PROD = 2,     // inner product <A|sigma_b0|B> on local bit b0
-    OP_CNOT = 3,     // control: local bit b0, or qubit q0 read from the tile base when b0 = 0xFF; target: local b1
-    OP_CZ = 4,       // sign (-1)^{x_a x_b}; a: local b0 or base bit q0; b: local b1 or base bit q1
-    OP_ZSUM = 5      // Z inner product on qubit q0 outside the tile: +-<A|B>_tile
+    OP_ROT = 0,       // X/Y rotation adjoint (stored matrix) on register position b0
+    OP_PRODROT = 1,   // X/Y inner product on register position b0, then the rotation adjoint
+    OP_PROD = 2,      // X/Y inner product <A|sigma|B> on register position b0
+    OP_CNOT = 3,      // CNOT adjoint: target register position b0, control location b1 (qubit q0)
+    OP_CZ = 4,        // sign (-1)^{x_a x_b}: locations b0 (qubit q0), b1 (qubit q1)
+    OP_ZSUM = 5,      // Z inner product on qubit q0 outside the tile: +-<A|B>_tile
+    OP_DIAG = 6,      // RZ adjoint diag(m00, m11) on location b0
+    OP_PRODZ = 7,     // Z inner product on location b0
+    OP_PRODDIAG = 8,  // Z inner product on location b0, then the RZ adjoint there
+    OP_XPOSE = 9      // exchange through LDS to the thread mapping `aux`
 };
 
-constexpr uint8_t kNoBit = 0xFF;
+// Location of a local bit in the current thread mapping: a register position
+// (< kLocThread), a thread position (kLocThread | t), or a bit of the tile base
+// (kLocBase: qubit given separately).
+constexpr uint8_t kLocThread = 0x10;
+constexpr uint8_t kLocBase = 0xFF;
 constexpr int kMaxSlots = 128;      // inner products per pass
 constexpr int kMaxTileQubits = 13;
+constexpr int kMaxRest = 24;        // qubits outside a tile
 
 struct DevOp {  // 16 bytes
     uint8_t type, b0, b1, axis;
     uint16_t slot;
-    uint8_t q0, q1;
-    int32_t gate;   // gate position: row of the matrix table
-    int32_t aux;
+    uint8_t q0, q1;   // qubits (global) the operation acts on
+    int32_t gate;     // gate position: row of the matrix table
+    int32_t aux;      // OP_XPOSE: mapping index
 };
 
-struct DevPass {  // 64 bytes, read with scalar loads
+struct DevPass {  // 64 bytes, read through a pointer with scalar loads
     uint32_t op_begin, n_ops;
     uint16_t n_slots;
-    uint8_t m, n, nrest, has_zsum, pad0, pad1;
-    uint8_t tile_q[16];
-    uint8_t rest_q[32];
+    uint8_t m, n;
+    uint8_t nrest, has_zsum, rb, pad0;
+    uint32_t map_load;   // thread mapping used to load the tile
+    uint32_t pad1;
+    uint8_t tile_q[16];  // local bit -> qubit
+    uint8_t rest_q[kMaxRest];
+};
+
+// Thread mapping of a tile: position p < rb is register bit p of every thread;
+// position rb + t is bit t of the thread index; pos[p] = local bit held there.
+struct DevMap {
+    uint8_t pos[16];
 };
 static_assert(sizeof(DevPass) == 64, "DevPass layout");
 static_assert(sizeof(DevOp) == 16, "DevOp layout");
+static_assert(sizeof(DevMap) == 16, "DevMap layout");
 
 struct HostPass {
     std::vector<uint8_t> tile;          // local bit -> qubit
-    std::vector<DevOp> ops;
+    std::vector<DevOp> ops;             // includes OP_XPOSE (aux = index into maps)
     std::vector<int32_t> slot_dest;     // per slot: (rotation r) * P + column s
+    std::vector<DevMap> maps;           // thread mappings of this pass
+    int map_load = 0;                   // index into maps
+    int rb = 0;                         // register bits per thread
+    int transposes = 0;
 };
 
 struct ColumnPlan {
@@ -91,6 +114,9 @@ struct SweepPlan {
     // flattened device images
     std::vector<DevPass> dev_passes;
     std::vector<DevOp> dev_ops;
+    std::vector<DevMap> dev_maps;
+    int rb = 0;                         // register bits per thread (all passes)
+    int64_t transposes = 0;
     std::vector<int64_t> col_pass_begin;   // per column: index of its first pass in dev_passes
     int64_t total_passes = 0, total_ops = 0, max_slots = 0, load_maps = 0;
 
@@ -98,14 +124,18 @@ struct SweepPlan {
     void fill_info(qng_plan_info *out) const;
 };
 
+// Register bits per thread for a tile of m qubits (256 threads per tile).
+int register_bits(int m, int amp_bytes);
+
 // Build the plan of all columns.  tile_qubits = 0 picks the default for amp_bytes
 // (complex64: 12, complex128: 11).
-SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int small);
-int default_tile_qubits(int n, int amp_bytes);
+// reg_f64: tiles are computed in FP64 registers (always for complex128).
+SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int small, bool reg_f64);
+int default_tile_qubits(int n, int amp_bytes, bool reg_f64);
 
 struct SweepCache {
     std::map<std::vector<int32_t>, std::shared_ptr<SweepPlan>> plans;
-    const SweepPlan &get(const Circuit &c, int tile_qubits, int amp_bytes, int small);
+    const SweepPlan &get(const Circuit &c, int tile_qubits, int amp_bytes, int small, bool reg_f64);
 };
 
 // Device-side launch item: one pass of one column over all its tiles.
@@ -137,7 +167,8 @@ FusedRun fused_config(const SweepPlan &plan, int requested_streams, size_t state
 // Kernel launchers (sweep_kernels.hip).
 template <typename R>
 void launch_sweep_pass(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
-                       const DevOp *ops, const double *mats, double *partials, int max_m, hipStream_t st);
+                       const DevOp *ops, const DevMap *maps, const double *mats, double *partials, int m, int rb,
+                       bool f64_registers, hipStream_t st);
 void launch_reduce_tasks(const ReduceTask *tasks, int n_tasks, const double *partials, double *results,
                          hipStream_t st);
 

@@ -1,17 +1,28 @@
 // sweep_kernels.hip -- the fused sweep-pass kernel for gfx950 (see sweep.hpp).
 //
-// One work-group (256 threads = 4 wave64) owns one tile: the 2^m amplitudes of
-// lambda (A) and phi (B) whose indices agree outside the pass's m tile qubits.
-// Load: local index l (bit b <-> qubit tile_q[b], tile qubits ascending, so the
-// lowest local bits are the lowest qubits and consecutive threads read
-// contiguous runs) -> LDS.  Execute: the pass's operations on LDS, one barrier
-// after each; every pair/amplitude is owned by exactly one thread within an
-// operation.  Inner products accumulate per thread in FP64, are summed across
-// each wave with shuffles and stored per (slot, wave) in LDS.  Store: LDS ->
-// the same global addresses (in place: the tile is read and written only by
-// this work-group).  Finally one FP64 partial sum per (slot, tile) goes to
-// global memory; k_reduce_tasks adds the partials of each slot over all tiles
-// in a fixed order, so results are bitwise reproducible.
+// One work-group of 256 threads (4 wave64) owns one tile: the 2^m amplitudes
+// of lambda (A) and phi (B) whose indices agree outside the pass's m tile
+// qubits.  The tile lives in registers: every thread holds T = 2^RB amplitudes
+// of each register, in FP64 whatever the storage precision (complex64 states
+// are widened at the load and rounded once at the store of each pass).  A thread mapping says which local bits are "register
+// bits" (the thread's own T amplitudes differ in them) and which are "thread
+// bits" (bits of the thread index).
+//
+//  * Load: amplitudes go from HBM straight into registers under the pass's
+//    load mapping, whose lowest thread bits are the lowest qubits, so the 64
+//    lanes of a wave read contiguous runs.
+//  * X/Y rotations, X/Y inner products and CNOT targets act on register bits:
+//    the pair (i, i ^ 2^j) of one thread, no communication, no barrier.
+//  * Diagonal operations (RZ, CZ, Z inner products) act on any bit: its value
+//    comes from the register index, the thread index or the tile base.
+//  * Between phases the tile is exchanged through LDS (one register at a time)
+//    to the next mapping, the only place where barriers are needed.
+//  * Inner products accumulate per thread in FP64, are summed across each wave
+//    with shuffles and kept per (slot, wave) in LDS; at the end one FP64
+//    partial per (slot, tile) is written, and k_reduce_tasks adds the partials
+//    of a slot over the tiles in a fixed order (bitwise reproducible).
+//  * Store: registers -> HBM under the final mapping (lanes on the lowest
+//    qubits again), in place: the tile is touched by this work-group only.
 #include <hip/hip_runtime.h>
 
 #include "sweep.hpp"
@@ -27,10 +38,6 @@ template <typename R> struct Amp;
 template <> struct Amp<double> { using T = double2; };
 template <> struct Amp<float>  { using T = float2; };
 
-__device__ __forceinline__ uint32_t insert0(uint32_t p, int b) {
-    return ((p >> b) << (b + 1)) | (p & ((1u << b) - 1u));
-}
-
 __device__ __forceinline__ void wave_sum(double &a, double &b) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -39,59 +46,229 @@ __device__ __forceinline__ void wave_sum(double &a, double &b) {
     }
 }
 
+// The tile is kept as four scalar arrays per thread: real and imaginary parts
+// of lambda (A) and phi (B), T values each (scalar arrays stay in VGPRs).
+template <typename CT, int T>
+struct Regs {
+    CT ar[T], ai[T], br[T], bi[T];
+};
+
 // conj(x) * y accumulated in FP64
-template <typename C>
-__device__ __forceinline__ void cmac(double &sr, double &si, const C &x, const C &y) {
-    const double xr = x.x, xi = x.y, yr = y.x, yi = y.y;
+template <typename R>
+__device__ __forceinline__ void cmac(double &sr, double &si, R xr_, R xi_, R yr_, R yi_) {
+    const double xr = xr_, xi = xi_, yr = yr_, yi = yi_;
     sr += xr * yr + xi * yi;
     si += xr * yi - xi * yr;
 }
 
-// <a|sigma|b> over the pair (i0, i1) of one qubit: Z: a0*b0 - a1*b1;
-// X: a0*b1 + a1*b0; Y: i (a1*b0 - a0*b1)   (a* meaning conj(a))
-template <typename C>
-__device__ __forceinline__ void pair_prod(int axis, const C &a0, const C &a1, const C &b0, const C &b1, double &sr,
-                                          double &si) {
-    if (axis == 2) {
-        cmac(sr, si, a0, b0);
-        double tr = 0.0, ti = 0.0;
-        cmac(tr, ti, a1, b1);
-        sr -= tr;
-        si -= ti;
-    } else if (axis == 0) {
-        cmac(sr, si, a0, b1);
-        cmac(sr, si, a1, b0);
-    } else {
-        double tr = 0.0, ti = 0.0;
-        cmac(tr, ti, a1, b0);
-        double ur = 0.0, ui = 0.0;
-        cmac(ur, ui, a0, b1);
-        tr -= ur;
-        ti -= ui;
-        sr -= ti;
-        si += tr;
-    }
+// 2x2 complex matrix [[a, b], [c, d]] as scalars
+template <typename R>
+struct M2 {
+    R ar, ai, br, bi, cr, ci, dr, di;
+};
+
+template <typename R>
+__device__ __forceinline__ M2<R> load_m2(const double *p) {
+    return M2<R>{(R)p[0], (R)p[1], (R)p[2], (R)p[3], (R)p[4], (R)p[5], (R)p[6], (R)p[7]};
 }
 
-template <typename R, typename C>
-__device__ __forceinline__ void mat_apply(const R *m, C &x0, C &x1) {
-    const C u = x0, v = x1;
-    x0.x = m[0] * u.x - m[1] * u.y + m[2] * v.x - m[3] * v.y;
-    x0.y = m[0] * u.y + m[1] * u.x + m[2] * v.y + m[3] * v.x;
-    x1.x = m[4] * u.x - m[5] * u.y + m[6] * v.x - m[7] * v.y;
-    x1.y = m[4] * u.y + m[5] * u.x + m[6] * v.y + m[7] * v.x;
+// 2x2 complex matrix on the pair (x0, x1)
+template <typename R>
+__device__ __forceinline__ void mat_apply(const M2<R> m, R &x0r, R &x0i, R &x1r, R &x1i) {
+    const R ur = x0r, ui = x0i, vr = x1r, vi = x1i;
+    x0r = m.ar * ur - m.ai * ui + m.br * vr - m.bi * vi;
+    x0i = m.ar * ui + m.ai * ur + m.br * vi + m.bi * vr;
+    x1r = m.cr * ur - m.ci * ui + m.dr * vr - m.di * vi;
+    x1i = m.cr * ui + m.ci * ur + m.dr * vi + m.di * vr;
+}
+
+// value select (by-value operands keep the choice on registers, not on addresses)
+template <typename R>
+__device__ __forceinline__ R sel(bool c, R a, R b) {
+    return c ? a : b;
 }
 
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_sweep_pass(const LaunchItem *__restrict__ items, int n_items,
-                                                         const DevPass *__restrict__ passes,
-                                                         const DevOp *__restrict__ ops,
-                                                         const double *__restrict__ mats,
-                                                         double2 *__restrict__ partials) {
+__device__ __forceinline__ void cmul(R &xr, R &xi, R fr, R fi) {
+    const R ur = xr, ui = xi;
+    xr = fr * ur - fi * ui;
+    xi = fr * ui + fi * ur;
+}
+
+// ---------------------------------------------------------- register-bit ops
+
+// <A|sigma|B> over the pairs of register bit J (a* meaning conj(a)):
+//   X: a0*b1 + a1*b0;   Y: i (a1*b0 - a0*b1).
+// The pair loop accumulates S1 = sum a0*b1 and S2 = sum a1*b0 for either axis
+// (no branch on the axis inside the loop); the axis picks the combination.
+template <int J, int T, typename CT>
+__device__ __forceinline__ void prod_bit(int axis, const Regs<CT, T> &x, double &pr, double &pi) {
+    double s1r = 0.0, s1i = 0.0, s2r = 0.0, s2i = 0.0;
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        if (i & (1 << J)) continue;
+        const int k = i | (1 << J);
+        cmac(s1r, s1i, x.ar[i], x.ai[i], x.br[k], x.bi[k]);
+        cmac(s2r, s2i, x.ar[k], x.ai[k], x.br[i], x.bi[i]);
+    }
+    const bool ax = axis == 0;
+    pr += sel(ax, s1r + s2r, s1i - s2i);
+    pi += sel(ax, s1i + s2i, s2r - s1r);
+}
+
+// Adjoint rotation on the pairs of register bit J.  The matrices of RX and RY
+// adjoints have exact zeros (RX: real diagonal, imaginary off-diagonal; RY:
+// real), so each output is two products instead of four.
+template <int J, int T, typename CT>
+__device__ __forceinline__ void rot_bit(int axis, Regs<CT, T> &x, const M2<CT> m) {
+    if (axis == 0) {
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            if (i & (1 << J)) continue;
+            const int k = i | (1 << J);
+            CT ur = x.ar[i], ui = x.ai[i], vr = x.ar[k], vi = x.ai[k];
+            x.ar[i] = m.ar * ur - m.bi * vi;
+            x.ai[i] = m.ar * ui + m.bi * vr;
+            x.ar[k] = m.dr * vr - m.ci * ui;
+            x.ai[k] = m.dr * vi + m.ci * ur;
+            ur = x.br[i]; ui = x.bi[i]; vr = x.br[k]; vi = x.bi[k];
+            x.br[i] = m.ar * ur - m.bi * vi;
+            x.bi[i] = m.ar * ui + m.bi * vr;
+            x.br[k] = m.dr * vr - m.ci * ui;
+            x.bi[k] = m.dr * vi + m.ci * ur;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            if (i & (1 << J)) continue;
+            const int k = i | (1 << J);
+            CT ur = x.ar[i], ui = x.ai[i], vr = x.ar[k], vi = x.ai[k];
+            x.ar[i] = m.ar * ur + m.br * vr;
+            x.ai[i] = m.ar * ui + m.br * vi;
+            x.ar[k] = m.cr * ur + m.dr * vr;
+            x.ai[k] = m.cr * ui + m.dr * vi;
+            ur = x.br[i]; ui = x.bi[i]; vr = x.br[k]; vi = x.bi[k];
+            x.br[i] = m.ar * ur + m.br * vr;
+            x.bi[i] = m.ar * ui + m.br * vi;
+            x.br[k] = m.cr * ur + m.dr * vr;
+            x.bi[k] = m.cr * ui + m.dr * vi;
+        }
+    }
+}
+
+// swap the pair of register bit J where the control holds; ctrl has bit i set
+// when register i's control value is 1
+template <int J, int T, typename CT>
+__device__ __forceinline__ void cnot_bit(Regs<CT, T> &x, uint32_t ctrl) {
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        if (i & (1 << J)) continue;
+        const int k = i | (1 << J);
+        const bool c = (ctrl >> i) & 1u;
+        const CT a0r = x.ar[i], a0i = x.ai[i], a1r = x.ar[k], a1i = x.ai[k];
+        const CT b0r = x.br[i], b0i = x.bi[i], b1r = x.br[k], b1i = x.bi[k];
+        x.ar[i] = sel(c, a1r, a0r); x.ar[k] = sel(c, a0r, a1r);
+        x.ai[i] = sel(c, a1i, a0i); x.ai[k] = sel(c, a0i, a1i);
+        x.br[i] = sel(c, b1r, b0r); x.br[k] = sel(c, b0r, b1r);
+        x.bi[i] = sel(c, b1i, b0i); x.bi[k] = sel(c, b0i, b1i);
+    }
+}
+
+template <int J, int T, typename CT>
+__device__ __forceinline__ void rot_prod_bit(int type, int axis, Regs<CT, T> &x, const M2<CT> mm, double &pr,
+                                             double &pi) {
+    if (type != OP_ROT) prod_bit<J, T, CT>(axis, x, pr, pi);
+    if (type != OP_PROD) rot_bit<J, T, CT>(axis, x, mm);
+}
+
+// Dispatch a runtime register position j to its template instance.
+template <int RB, int T, typename CT>
+__device__ __forceinline__ void rot_prod_at(int j, int type, int axis, Regs<CT, T> &x, const M2<CT> mm, double &pr,
+                                            double &pi) {
+    switch (j) {
+    case 0: rot_prod_bit<0, T, CT>(type, axis, x, mm, pr, pi); break;
+    case 1: if constexpr (RB > 1) rot_prod_bit<1, T, CT>(type, axis, x, mm, pr, pi); break;
+    case 2: if constexpr (RB > 2) rot_prod_bit<2, T, CT>(type, axis, x, mm, pr, pi); break;
+    case 3: if constexpr (RB > 3) rot_prod_bit<3, T, CT>(type, axis, x, mm, pr, pi); break;
+    default: break;
+    }
+}
+
+template <int RB, int T, typename CT>
+__device__ __forceinline__ void cnot_at(int j, Regs<CT, T> &x, uint32_t ctrl) {
+    switch (j) {
+    case 0: cnot_bit<0, T, CT>(x, ctrl); break;
+    case 1: if constexpr (RB > 1) cnot_bit<1, T, CT>(x, ctrl); break;
+    case 2: if constexpr (RB > 2) cnot_bit<2, T, CT>(x, ctrl); break;
+    case 3: if constexpr (RB > 3) cnot_bit<3, T, CT>(x, ctrl); break;
+    default: break;
+    }
+}
+
+// Global (element) offset of each of a thread's registers under a mapping.
+template <int RB, int T>
+__device__ __forceinline__ void global_offsets(const DevPass *pp, const DevMap *mp, int tbits, int tid, uint64_t base,
+                                               uint64_t (&off)[T]) {
+    uint64_t dth = base;
+    for (int t = 0; t < tbits; ++t) dth |= (uint64_t)((tid >> t) & 1) << pp->tile_q[mp->pos[RB + t]];
+    uint64_t u[RB];
+#pragma unroll
+    for (int j = 0; j < RB; ++j) u[j] = (uint64_t)1 << pp->tile_q[mp->pos[j]];
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        uint64_t d = dth;
+#pragma unroll
+        for (int j = 0; j < RB; ++j)
+            if ((i >> j) & 1) d |= u[j];
+        off[i] = d;
+    }
+}
+
+// Local (in-tile) index of each of a thread's registers under a mapping.
+template <int RB, int T>
+__device__ __forceinline__ void local_offsets(const DevMap *mp, int tbits, int tid, uint32_t (&off)[T]) {
+    uint32_t lth = 0;
+    for (int t = 0; t < tbits; ++t) lth |= (uint32_t)((tid >> t) & 1) << mp->pos[RB + t];
+    uint32_t u[RB];
+#pragma unroll
+    for (int j = 0; j < RB; ++j) u[j] = 1u << mp->pos[j];
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        uint32_t l = lth;
+#pragma unroll
+        for (int j = 0; j < RB; ++j)
+            if ((i >> j) & 1) l |= u[j];
+        off[i] = l;
+    }
+}
+
+// Mask over registers (bit i for register i) of the value of a location: a
+// register position, a thread position or a bit of the tile base.
+template <int T>
+__device__ __forceinline__ uint32_t loc_mask(uint8_t loc, uint8_t q, int tid, uint64_t base) {
+    constexpr uint32_t all = (T >= 32) ? 0xffffffffu : ((1u << T) - 1u);
+    if (loc < kLocThread) {
+        uint32_t mask = 0;
+#pragma unroll
+        for (int i = 0; i < T; ++i) mask |= (uint32_t)((i >> loc) & 1) << i;
+        return mask;
+    }
+    const uint32_t v = (loc == kLocBase) ? (uint32_t)((base >> q) & 1u) : (uint32_t)((tid >> (loc & 15)) & 1);
+    return v ? all : 0u;
+}
+
+template <typename R, typename CT, int RB>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 4 ? 1 : 3, 8))) void k_sweep_reg(const LaunchItem *__restrict__ items, int n_items,
+                                                        const DevPass *__restrict__ passes,
+                                                        const DevOp *__restrict__ ops,
+                                                        const DevMap *__restrict__ maps,
+                                                        const double *__restrict__ mats,
+                                                        double2 *__restrict__ partials) {
+    constexpr int T = 1 << RB;
     using C = typename Amp<R>::T;
     extern __shared__ __align__(16) unsigned char smem[];
 
-    // which item (pass of one column) this work-group belongs to
+    // ---- which item (one pass of one column) this work-group serves
     const uint32_t wg = blockIdx.x;
     int lo = 0, hi = n_items - 1;
     while (lo < hi) {
@@ -100,161 +277,199 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(const LaunchItem *__res
         else hi = mid - 1;
     }
     const LaunchItem it = items[lo];
-    const DevPass *pp = passes + it.pass;      // uniform: read with scalar loads, never copied
+    const DevPass *pp = passes + it.pass;
     const uint32_t tile = wg - it.tile_begin;
     const int m = pp->m;
     const uint32_t dimT = 1u << m;
-    C *A = (C *)smem;
-    C *B = A + dimT;
-    double2 *red = (double2 *)(B + dimT);          // [kMaxSlots][kWaves]
-    double2 *zs = red + kMaxSlots * kWaves;        // [kWaves]
-    uint64_t *dep_hi_tab = (uint64_t *)(zs + kWaves);   // [2^(m-8)]
+    const int tbits = m - RB;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nrest = pp->nrest;
-    const int n_ops = (int)pp->n_ops, op_begin = (int)pp->op_begin, n_slots = pp->n_slots;
-    const bool has_zsum = pp->has_zsum != 0;
+    const bool active = (tid >> tbits) == 0;
+
+    using CX = typename Amp<CT>::T;
+    CX *xbuf = (CX *)smem;                                // [2^m] exchange buffer
+    double2 *red = (double2 *)(xbuf + dimT);              // [kMaxSlots][kWaves]
+    double2 *zs = red + kMaxSlots * kWaves;               // [kWaves]
 
     uint64_t base = 0;
-    for (int k = 0; k < nrest; ++k) base |= (uint64_t)((tile >> k) & 1u) << pp->rest_q[k];
-    uint64_t dep_lo = 0;
-    const int mlo = m < 8 ? m : 8;
-    for (int k = 0; k < mlo; ++k) dep_lo |= (uint64_t)((tid >> k) & 1) << pp->tile_q[k];
-    const int nhi = m > 8 ? (1 << (m - 8)) : 1;
-    if (tid < nhi) {
-        uint64_t d = 0;
-        for (int k = 8; k < m; ++k) d |= (uint64_t)((tid >> (k - 8)) & 1) << pp->tile_q[k];
-        dep_hi_tab[tid] = d;
-    }
-    __syncthreads();
+    for (int k = 0; k < pp->nrest; ++k) base |= (uint64_t)((tile >> k) & 1u) << pp->rest_q[k];
 
     C *gA = (C *)it.regA;
     C *gB = (C *)it.regB;
+    Regs<CT, T> x;
 
-    // ---- load (and the plain tile sum <A|B>_tile if a Z product outside the tile needs it)
-    double sr = 0.0, si = 0.0;
-    for (uint32_t l = tid; l < dimT; l += kThreads) {
-        const uint64_t g = base | dep_lo | dep_hi_tab[l >> 8];
-        const C a = gA[g], b = gB[g];
-        A[l] = a;
-        B[l] = b;
-        if (has_zsum) cmac(sr, si, a, b);
+    // ---- load
+    const DevMap *cur = maps + pp->map_load;
+    {
+        uint64_t off[T];
+        global_offsets<RB, T>(pp, cur, tbits, tid, base, off);
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < T; ++i) {
+                const C v = gA[off[i]];
+                x.ar[i] = v.x;
+                x.ai[i] = v.y;
+            }
+#pragma unroll
+            for (int i = 0; i < T; ++i) {
+                const C v = gB[off[i]];
+                x.br[i] = v.x;
+                x.bi[i] = v.y;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < T; ++i) x.ar[i] = x.ai[i] = x.br[i] = x.bi[i] = (CT)0;
+        }
     }
+    // plain tile sum <A|B>_tile for Z inner products on qubits outside the tile
     double Sr = 0.0, Si = 0.0;
-    if (has_zsum) {
+    if (pp->has_zsum) {
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int i = 0; i < T; ++i) cmac(sr, si, x.ar[i], x.ai[i], x.br[i], x.bi[i]);
         wave_sum(sr, si);
         if (lane == 0) zs[wave] = make_double2(sr, si);
-    }
-    __syncthreads();
-    if (has_zsum) {
-        for (int w = 0; w < kWaves; ++w) { Sr += zs[w].x; Si += zs[w].y; }
+        __syncthreads();
+        for (int w = 0; w < kWaves; ++w) {
+            Sr += zs[w].x;
+            Si += zs[w].y;
+        }
     }
 
     // ---- operations
-    const uint32_t npairs = dimT >> 1;
+    const int n_ops = (int)pp->n_ops;
+    const DevOp *op_ptr = ops + pp->op_begin;
     for (int oi = 0; oi < n_ops; ++oi) {
-        const DevOp op = ops[op_begin + oi];
-        switch (op.type) {
-        case OP_ROT:
-        case OP_PRODROT:
-        case OP_PROD: {
-            const int b = op.b0;
-            R mm[8];
-            if (op.type != OP_PROD) {
-#pragma unroll
-                for (int k = 0; k < 8; ++k) mm[k] = (R)mats[(size_t)op.gate * 8 + k];
-            }
+        const DevOp op = op_ptr[oi];
+        const int type = op.type;
+        if (type == OP_ROT || type == OP_PRODROT || type == OP_PROD) {
+            const M2<CT> mm = type != OP_PROD ? load_m2<CT>(mats + (size_t)op.gate * 8) : M2<CT>{};
             double pr = 0.0, pi = 0.0;
-            // pairs owned by this thread, processed in batches of kBatch so that the
-            // LDS loads of a batch are all in flight before the first is used
-            constexpr int kBatch = 4;
-            for (uint32_t p0 = tid; p0 < npairs; p0 += kThreads * kBatch) {
-                uint32_t i0[kBatch];
-                C a0[kBatch], a1[kBatch], b0[kBatch], b1[kBatch];
-#pragma unroll
-                for (int j = 0; j < kBatch; ++j) {
-                    const uint32_t p = p0 + j * kThreads;
-                    i0[j] = insert0(p < npairs ? p : 0u, b);
-                    a0[j] = A[i0[j]]; a1[j] = A[i0[j] | (1u << b)];
-                    b0[j] = B[i0[j]]; b1[j] = B[i0[j] | (1u << b)];
-                }
-#pragma unroll
-                for (int j = 0; j < kBatch; ++j) {
-                    if (p0 + j * kThreads >= npairs) continue;
-                    if (op.type != OP_ROT) pair_prod(op.axis, a0[j], a1[j], b0[j], b1[j], pr, pi);
-                    if (op.type != OP_PROD) {
-                        mat_apply<R, C>(mm, a0[j], a1[j]);
-                        mat_apply<R, C>(mm, b0[j], b1[j]);
-                        A[i0[j]] = a0[j]; A[i0[j] | (1u << b)] = a1[j];
-                        B[i0[j]] = b0[j]; B[i0[j] | (1u << b)] = b1[j];
-                    }
-                }
-            }
-            if (op.type != OP_ROT) {
+            rot_prod_at<RB, T, CT>(op.b0, type, op.axis, x, mm, pr, pi);
+            if (type != OP_ROT) {
                 wave_sum(pr, pi);
                 if (lane == 0) red[op.slot * kWaves + wave] = make_double2(pr, pi);
             }
-            break;
-        }
-        case OP_CNOT: {
-            const int bt = op.b1;
-            if (op.b0 == kNoBit) {
-                if (!((base >> op.q0) & 1u)) break;   // control fixed to 0 on this tile
-                for (uint32_t p = tid; p < npairs; p += kThreads) {
-                    const uint32_t i0 = insert0(p, bt), i1 = i0 | (1u << bt);
-                    const C a0 = A[i0], b0 = B[i0];
-                    A[i0] = A[i1]; A[i1] = a0;
-                    B[i0] = B[i1]; B[i1] = b0;
+        } else if (type == OP_DIAG || type == OP_PRODZ || type == OP_PRODDIAG) {
+            const uint32_t ones = loc_mask<T>(op.b0, op.q0, tid, base);
+            if (type != OP_DIAG) {
+                double pr = 0.0, pi = 0.0;
+#pragma unroll
+                for (int i = 0; i < T; ++i) {
+                    double tr = 0.0, ti = 0.0;
+                    cmac(tr, ti, x.ar[i], x.ai[i], x.br[i], x.bi[i]);
+                    const double sg = ((ones >> i) & 1u) ? -1.0 : 1.0;
+                    pr += sg * tr;
+                    pi += sg * ti;
                 }
-            } else {
-                const uint32_t cb = 1u << op.b0;
-                for (uint32_t p = tid; p < npairs; p += kThreads) {
-                    const uint32_t i0 = insert0(p, bt), i1 = i0 | (1u << bt);
-                    if (!(i0 & cb)) continue;
-                    const C a0 = A[i0], b0 = B[i0];
-                    A[i0] = A[i1]; A[i1] = a0;
-                    B[i0] = B[i1]; B[i1] = b0;
+                wave_sum(pr, pi);
+                if (lane == 0) red[op.slot * kWaves + wave] = make_double2(pr, pi);
+            }
+            if (type != OP_PRODZ) {
+                const CT d0r = (CT)mats[(size_t)op.gate * 8 + 0], d0i = (CT)mats[(size_t)op.gate * 8 + 1];
+                const CT d1r = (CT)mats[(size_t)op.gate * 8 + 6], d1i = (CT)mats[(size_t)op.gate * 8 + 7];
+#pragma unroll
+                for (int i = 0; i < T; ++i) {
+                    const bool one = (ones >> i) & 1u;
+                    const CT fr = sel(one, d1r, d0r), fi = sel(one, d1i, d0i);
+                    cmul<CT>(x.ar[i], x.ai[i], fr, fi);
+                    cmul<CT>(x.br[i], x.bi[i], fr, fi);
                 }
             }
-            break;
-        }
-        case OP_CZ: {
-            const bool la = op.b0 != kNoBit, lb = op.b1 != kNoBit;
-            const uint32_t fa = la ? 0u : (uint32_t)((base >> op.q0) & 1u);
-            const uint32_t fb = lb ? 0u : (uint32_t)((base >> op.q1) & 1u);
-            for (uint32_t l = tid; l < dimT; l += kThreads) {
-                const uint32_t xa = la ? (l >> op.b0) & 1u : fa;
-                const uint32_t xb = lb ? (l >> op.b1) & 1u : fb;
-                if (xa & xb) {
-                    C a = A[l], b = B[l];
-                    a.x = -a.x; a.y = -a.y; b.x = -b.x; b.y = -b.y;
-                    A[l] = a; B[l] = b;
-                }
+        } else if (type == OP_CNOT) {
+            const uint32_t ctrl = loc_mask<T>(op.b1, op.q0, tid, base);
+            if (ctrl) cnot_at<RB, T, CT>(op.b0, x, ctrl);
+        } else if (type == OP_CZ) {
+            const uint32_t neg = loc_mask<T>(op.b0, op.q0, tid, base) & loc_mask<T>(op.b1, op.q1, tid, base);
+#pragma unroll
+            for (int i = 0; i < T; ++i) {
+                const CT sg = sel<CT>((neg >> i) & 1u, (CT)-1, (CT)1);
+                x.ar[i] *= sg;
+                x.ai[i] *= sg;
+                x.br[i] *= sg;
+                x.bi[i] *= sg;
             }
-            break;
-        }
-        case OP_ZSUM: {
+        } else if (type == OP_ZSUM) {
             if (tid == 0) {
                 const double sg = ((base >> op.q0) & 1u) ? -1.0 : 1.0;
                 red[op.slot * kWaves] = make_double2(sg * Sr, sg * Si);
                 for (int w = 1; w < kWaves; ++w) red[op.slot * kWaves + w] = make_double2(0.0, 0.0);
             }
-            break;
+        } else if (type == OP_XPOSE) {
+            const DevMap *next = maps + op.aux;
+            uint32_t lo_old[T], lo_new[T];
+            local_offsets<RB, T>(cur, tbits, tid, lo_old);
+            local_offsets<RB, T>(next, tbits, tid, lo_new);
+            if (active) {
+#pragma unroll
+                for (int i = 0; i < T; ++i) {
+                    CX v;
+                    v.x = x.ar[i];
+                    v.y = x.ai[i];
+                    xbuf[lo_old[i]] = v;
+                }
+            }
+            __syncthreads();
+            if (active) {
+#pragma unroll
+                for (int i = 0; i < T; ++i) {
+                    const CX v = xbuf[lo_new[i]];
+                    x.ar[i] = v.x;
+                    x.ai[i] = v.y;
+                }
+            }
+            __syncthreads();
+            if (active) {
+#pragma unroll
+                for (int i = 0; i < T; ++i) {
+                    CX v;
+                    v.x = x.br[i];
+                    v.y = x.bi[i];
+                    xbuf[lo_old[i]] = v;
+                }
+            }
+            __syncthreads();
+            if (active) {
+#pragma unroll
+                for (int i = 0; i < T; ++i) {
+                    const CX v = xbuf[lo_new[i]];
+                    x.br[i] = v.x;
+                    x.bi[i] = v.y;
+                }
+            }
+            __syncthreads();
+            cur = next;
         }
-        default: break;
-        }
-        __syncthreads();
     }
 
     // ---- store
-    for (uint32_t l = tid; l < dimT; l += kThreads) {
-        const uint64_t g = base | dep_lo | dep_hi_tab[l >> 8];
-        gA[g] = A[l];
-        gB[g] = B[l];
+    {
+        uint64_t off[T];
+        global_offsets<RB, T>(pp, cur, tbits, tid, base, off);
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < T; ++i) {
+                C v;
+                v.x = (R)x.ar[i];
+                v.y = (R)x.ai[i];
+                gA[off[i]] = v;
+            }
+#pragma unroll
+            for (int i = 0; i < T; ++i) {
+                C v;
+                v.x = (R)x.br[i];
+                v.y = (R)x.bi[i];
+                gB[off[i]] = v;
+            }
+        }
     }
     // ---- per-tile partial sums
-    for (int k = tid; k < n_slots; k += kThreads) {
+    __syncthreads();
+    for (int k = tid; k < pp->n_slots; k += kThreads) {
         double xr = 0.0, xi = 0.0;
-        for (int w = 0; w < kWaves; ++w) { xr += red[k * kWaves + w].x; xi += red[k * kWaves + w].y; }
+        for (int w = 0; w < kWaves; ++w) {
+            xr += red[k * kWaves + w].x;
+            xi += red[k * kWaves + w].y;
+        }
         partials[it.partial_off + (uint64_t)k * it.ntiles + tile] = make_double2(xr, xi);
     }
 }
@@ -283,27 +498,53 @@ __global__ __launch_bounds__(kThreads) void k_reduce_tasks(const ReduceTask *__r
     if (threadIdx.x == 0) results[t.dest] = make_double2(sr[0], si[0]);
 }
 
-template <typename R> size_t smem_bytes(int m) {
-    return 2 * ((size_t)1 << m) * sizeof(typename Amp<R>::T) + (size_t)(kMaxSlots + 1) * kWaves * sizeof(double2) +
-           32 * sizeof(uint64_t);
+template <typename CT> size_t smem_bytes(int m) {
+    return ((size_t)1 << m) * sizeof(typename Amp<CT>::T) + (size_t)(kMaxSlots + 1) * kWaves * sizeof(double2);
+}
+
+template <typename R, typename CT, int RB>
+void launch_rb(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes, const DevOp *ops,
+               const DevMap *maps, const double *mats, double *partials, int m, hipStream_t st) {
+    const size_t smem = smem_bytes<CT>(m);
+    static size_t attr_set = 0;
+    if (smem > attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_sweep_reg<R, CT, RB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)smem);
+        (void)hipGetLastError();
+        attr_set = smem;
+    }
+    hipLaunchKernelGGL((k_sweep_reg<R, CT, RB>), dim3(total_tiles), dim3(kThreads), smem, st, items, n_items, passes,
+                       ops, maps, mats, (double2 *)partials);
+}
+
+template <typename R, typename CT>
+void launch_ct(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes, const DevOp *ops,
+               const DevMap *maps, const double *mats, double *partials, int m, int rb, hipStream_t st) {
+    switch (rb) {
+    case 1: launch_rb<R, CT, 1>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st); break;
+    case 2: launch_rb<R, CT, 2>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st); break;
+    case 3: launch_rb<R, CT, 3>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st); break;
+    case 4:
+        if constexpr (sizeof(CT) == 4) {
+            launch_rb<R, CT, 4>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st);
+            break;
+        }
+        [[fallthrough]];
+    default: throw hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
 template <typename R>
 void launch_sweep_pass(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
-                       const DevOp *ops, const double *mats, double *partials, int max_m, hipStream_t st) {
+                       const DevOp *ops, const DevMap *maps, const double *mats, double *partials, int m, int rb,
+                       bool f64_registers, hipStream_t st) {
     if (n_items <= 0 || total_tiles == 0) return;
-    const size_t smem = smem_bytes<R>(max_m);
-    static size_t attr_set = 0;
-    if (smem > attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_sweep_pass<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)smem);
-        (void)hipGetLastError();
-        attr_set = smem;
-    }
-    hipLaunchKernelGGL(k_sweep_pass<R>, dim3(total_tiles), dim3(kThreads), smem, st, items, n_items, passes, ops, mats,
-                       (double2 *)partials);
+    if (sizeof(R) == 8 || f64_registers)
+        launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, rb, st);
+    else
+        launch_ct<R, float>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, rb, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) throw e;
 }
@@ -318,8 +559,8 @@ void launch_reduce_tasks(const ReduceTask *tasks, int n_tasks, const double *par
 }
 
 template void launch_sweep_pass<double>(const LaunchItem *, int, uint32_t, const DevPass *, const DevOp *,
-                                        const double *, double *, int, hipStream_t);
+                                        const DevMap *, const double *, double *, int, int, bool, hipStream_t);
 template void launch_sweep_pass<float>(const LaunchItem *, int, uint32_t, const DevPass *, const DevOp *,
-                                       const double *, double *, int, hipStream_t);
+                                       const DevMap *, const double *, double *, int, int, bool, hipStream_t);
 
 }  // namespace qng

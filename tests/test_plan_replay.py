@@ -14,7 +14,7 @@ import pytest
 import oracle
 import workloads as W
 
-OP_ROT, OP_PRODROT, OP_PROD, OP_CNOT, OP_CZ, OP_ZSUM = range(6)
+KIND_ADJ, KIND_PROD_ADJ, KIND_PROD = range(3)
 LETTER = {0: 1, 1: 2, 2: 3}   # axis -> Pauli letter
 
 
@@ -63,33 +63,30 @@ def replay(qng, pr, tile_qubits, prec="c128"):
         lam = ys[s].copy()
         phi = oracle.apply_pauli_letter(n, q_s, LETTER[ax_s], ys[s])
         for r in ops:
-            typ, q0, q1, g, dest, axis = (int(v) for v in r[2:8])
+            kind, q0, q1, g, dest, axis = (int(v) for v in r[2:8])
             mask = int(r[8]) | (int(r[9]) << 31)
             max_tile = max(max_tile, bin(mask).count("1"))
             inside = lambda q: (mask >> q) & 1
-            if typ in (OP_PROD, OP_PRODROT, OP_ZSUM):
-                if typ == OP_ZSUM:
-                    assert axis == 2 and not inside(q0)
-                else:
-                    assert inside(q0)
+            if kind in (KIND_PROD, KIND_PROD_ADJ):
+                # X/Y inner products need their qubit in the tile; Z ones may lie outside
+                assert axis == 2 or inside(q0)
                 rr, ss = divmod(dest, P)
                 assert ss == s and rr < s and not seen[rr, ss]
                 seen[rr, ss] = True
                 Lraw[rr, ss] = prod(lam, phi, q0, axis)
-                if typ == OP_PRODROT:
-                    assert rot_of_pos[g] == rr
+                if kind == KIND_PROD_ADJ:
+                    assert rot_of_pos[g] == rr and inside(q0)
                     lam, phi = unapply(lam, g), unapply(phi, g)
-            elif typ == OP_ROT:
-                assert inside(q0) and int(gates[g, 1]) == q0
-                lam, phi = unapply(lam, g), unapply(phi, g)
-            elif typ == OP_CNOT:
-                assert inside(q1)
-                lam, phi = unapply(lam, g), unapply(phi, g)
-            elif typ == OP_CZ:
-                assert inside(q0) or inside(q1)
-                lam, phi = unapply(lam, g), unapply(phi, g)
             else:
-                raise AssertionError(typ)
+                assert kind == KIND_ADJ
+                gk = int(gates[g, 0])
+                if gk == W.CNOT:
+                    assert inside(q1) and int(gates[g, 2]) == q1
+                elif gk == W.CZ:
+                    assert inside(q0) or inside(q1)
+                else:
+                    assert inside(q0) and int(gates[g, 1]) == q0
+                lam, phi = unapply(lam, g), unapply(phi, g)
     # every element r < s evaluated exactly once
     assert seen.sum() == P * (P - 1) // 2
     assert np.all(np.triu(seen, 1) == seen)
