@@ -17,10 +17,10 @@
 //    comes from the register index, the thread index or the tile base.
 //  * Between phases the tile is exchanged through LDS (one register at a time)
 //    to the next mapping, the only place where barriers are needed.
-//  * Inner products accumulate per thread in FP64, are summed across each wave
-//    with shuffles and kept per (slot, wave) in LDS; at the end one FP64
-//    partial per (slot, tile) is written, and k_reduce_tasks adds the partials
-//    of a slot over the tiles in a fixed order (bitwise reproducible).
+//  * Inner products accumulate per thread in FP64, are summed within each
+//    16-lane row with DPP shifts and kept per (slot, row) in LDS; at the end
+//    one FP64 partial per (slot, tile) is written, and k_reduce_tasks adds the
+//    partials of a slot over the tiles in a fixed order (bitwise reproducible).
 //  * Store: registers -> HBM under the final mapping (lanes on the lowest
 //    qubits again), in place: the tile is touched by this work-group only.
 #include <hip/hip_runtime.h>
@@ -38,12 +38,32 @@ template <typename R> struct Amp;
 template <> struct Amp<double> { using T = double2; };
 template <> struct Amp<float>  { using T = float2; };
 
-__device__ __forceinline__ void wave_sum(double &a, double &b) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        a += __shfl_xor(a, off);
-        b += __shfl_xor(b, off);
-    }
+constexpr int kRows = kThreads / 16;   // DPP rows of 16 lanes per work-group
+
+// Row reduction with DPP: after row_shr by 1, 2, 4 and 8 (zero shifted in at
+// the start of each 16-lane row), lane 15 of every row holds the row's sum.
+template <int CTRL>
+__device__ __forceinline__ double dpp_shifted(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ void row_sum(double &a, double &b) {
+    a += dpp_shifted<0x111>(a);
+    b += dpp_shifted<0x111>(b);
+    a += dpp_shifted<0x112>(a);
+    b += dpp_shifted<0x112>(b);
+    a += dpp_shifted<0x114>(a);
+    b += dpp_shifted<0x114>(b);
+    a += dpp_shifted<0x118>(a);
+    b += dpp_shifted<0x118>(b);
+}
+
+// Store a per-lane partial of slot `slot`: one value per 16-lane row.
+__device__ __forceinline__ void row_store(double2 *red, int slot, int tid, double a, double b) {
+    row_sum(a, b);
+    if ((tid & 15) == 15) red[slot * kRows + (tid >> 4)] = make_double2(a, b);
 }
 
 // The tile is kept as four scalar arrays per thread: real and imaginary parts
@@ -282,13 +302,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
     const int m = pp->m;
     const uint32_t dimT = 1u << m;
     const int tbits = m - RB;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
     const bool active = (tid >> tbits) == 0;
 
     using CX = typename Amp<CT>::T;
     CX *xbuf = (CX *)smem;                                // [2^m] exchange buffer
-    double2 *red = (double2 *)(xbuf + dimT);              // [kMaxSlots][kWaves]
-    double2 *zs = red + kMaxSlots * kWaves;               // [kWaves]
+    double2 *red = (double2 *)(xbuf + dimT);              // [kMaxSlots][kRows]
+    double2 *zs = red + kMaxSlots * kRows;                // [kRows]
 
     uint64_t base = 0;
     for (int k = 0; k < pp->nrest; ++k) base |= (uint64_t)((tile >> k) & 1u) << pp->rest_q[k];
@@ -326,10 +346,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
         double sr = 0.0, si = 0.0;
 #pragma unroll
         for (int i = 0; i < T; ++i) cmac(sr, si, x.ar[i], x.ai[i], x.br[i], x.bi[i]);
-        wave_sum(sr, si);
-        if (lane == 0) zs[wave] = make_double2(sr, si);
+        row_store(zs, 0, tid, sr, si);
         __syncthreads();
-        for (int w = 0; w < kWaves; ++w) {
+        for (int w = 0; w < kRows; ++w) {
             Sr += zs[w].x;
             Si += zs[w].y;
         }
@@ -345,10 +364,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
             const M2<CT> mm = type != OP_PROD ? load_m2<CT>(mats + (size_t)op.gate * 8) : M2<CT>{};
             double pr = 0.0, pi = 0.0;
             rot_prod_at<RB, T, CT>(op.b0, type, op.axis, x, mm, pr, pi);
-            if (type != OP_ROT) {
-                wave_sum(pr, pi);
-                if (lane == 0) red[op.slot * kWaves + wave] = make_double2(pr, pi);
-            }
+            if (type != OP_ROT) row_store(red, op.slot, tid, pr, pi);
         } else if (type == OP_DIAG || type == OP_PRODZ || type == OP_PRODDIAG) {
             const uint32_t ones = loc_mask<T>(op.b0, op.q0, tid, base);
             if (type != OP_DIAG) {
@@ -361,8 +377,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
                     pr += sg * tr;
                     pi += sg * ti;
                 }
-                wave_sum(pr, pi);
-                if (lane == 0) red[op.slot * kWaves + wave] = make_double2(pr, pi);
+                row_store(red, op.slot, tid, pr, pi);
             }
             if (type != OP_PRODZ) {
                 const CT d0r = (CT)mats[(size_t)op.gate * 8 + 0], d0i = (CT)mats[(size_t)op.gate * 8 + 1];
@@ -391,8 +406,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
         } else if (type == OP_ZSUM) {
             if (tid == 0) {
                 const double sg = ((base >> op.q0) & 1u) ? -1.0 : 1.0;
-                red[op.slot * kWaves] = make_double2(sg * Sr, sg * Si);
-                for (int w = 1; w < kWaves; ++w) red[op.slot * kWaves + w] = make_double2(0.0, 0.0);
+                red[op.slot * kRows] = make_double2(sg * Sr, sg * Si);
+                for (int w = 1; w < kRows; ++w) red[op.slot * kRows + w] = make_double2(0.0, 0.0);
             }
         } else if (type == OP_XPOSE) {
             const DevMap *next = maps + op.aux;
@@ -466,9 +481,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
     __syncthreads();
     for (int k = tid; k < pp->n_slots; k += kThreads) {
         double xr = 0.0, xi = 0.0;
-        for (int w = 0; w < kWaves; ++w) {
-            xr += red[k * kWaves + w].x;
-            xi += red[k * kWaves + w].y;
+        for (int w = 0; w < kRows; ++w) {
+            xr += red[k * kRows + w].x;
+            xi += red[k * kRows + w].y;
         }
         partials[it.partial_off + (uint64_t)k * it.ntiles + tile] = make_double2(xr, xi);
     }
@@ -499,7 +514,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce_tasks(const ReduceTask *__r
 }
 
 template <typename CT> size_t smem_bytes(int m) {
-    return ((size_t)1 << m) * sizeof(typename Amp<CT>::T) + (size_t)(kMaxSlots + 1) * kWaves * sizeof(double2);
+    return ((size_t)1 << m) * sizeof(typename Amp<CT>::T) + (size_t)(kMaxSlots + 1) * kRows * sizeof(double2);
 }
 
 template <typename R, typename CT, int RB>
@@ -541,10 +556,15 @@ void launch_sweep_pass(const LaunchItem *items, int n_items, uint32_t total_tile
                        const DevOp *ops, const DevMap *maps, const double *mats, double *partials, int m, int rb,
                        bool f64_registers, hipStream_t st) {
     if (n_items <= 0 || total_tiles == 0) return;
-    if (sizeof(R) == 8 || f64_registers)
+    if constexpr (sizeof(R) == 8) {
+        (void)f64_registers;
         launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, rb, st);
-    else
-        launch_ct<R, float>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, rb, st);
+    } else {
+        if (f64_registers)
+            launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, rb, st);
+        else
+            launch_ct<R, float>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, rb, st);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) throw e;
 }
