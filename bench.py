@@ -20,6 +20,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU peak of MI355X for FP64 and for non-packed FP32 (both 16 FMA lanes per
+# SIMD per clock): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+KERNEL_SRC = os.path.join(ROOT, "paper_2011_02991_amd", "csrc", "sweep_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_pass_cfg3_traffic.json")
 
 
 def log(*a):
@@ -42,18 +47,27 @@ def parse():
     return ap.parse_args()
 
 
-def time_steps(ctx, circ, pr, prec, steps, warmup):
+def time_steps(ctx, circ, pr, prec, steps, warmup, profile=False):
+    """Time `steps` full steps; with profile, HIP events bracket every sweep-pass
+    launch on the library's stream during the timed steps themselves."""
     import torch
+    import paper_2011_02991_amd as qng
+    ctx.set_option(qng.OPT_PROFILE, 0)
     for _ in range(warmup):
         ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, prec=prec, want_G=False)
     torch.cuda.synchronize()
+    ctx.set_option(qng.OPT_PROFILE, 1 if profile else 0)
+    acc = {}
     t0 = time.perf_counter()
     res = None
     for _ in range(steps):
         res = ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, prec=prec, want_G=False)
+        for k, v in ctx.stats().items():
+            acc[k] = acc.get(k, 0) + v
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
-    return dt, res, ctx.stats()
+    ctx.set_option(qng.OPT_PROFILE, 0)
+    return dt, res, acc
 
 
 def gate_apply_bandwidth(qng, ctx, n, prec):
@@ -101,46 +115,48 @@ def gate_apply_bandwidth(qng, ctx, n, prec):
 
 
 def cpu_baseline(pr):
-    """The oracle, as it stands, on a bounded sample of the workload: one
-    derivative state built gate by gate (the dominant cost of the oracle's
-    step), extrapolated to the full step by its primitive counts."""
+    """The oracle, as it stands, on a bounded sample of the workload: its
+    forward state (every gate of the circuit applied gate by gate) and a few of
+    its inner products, timed, then extrapolated to the oracle's full step
+    (P derivative states built from a rolling prefix, the P x P Gram matrix,
+    H psi and the gradient) by its primitive counts."""
     import numpy as np
     import oracle
     cores = len(os.sched_getaffinity(0))
     n, M, P = pr.n_qubits, pr.n_gates, pr.n_params
     rot_pos = [k for k in range(M) if pr.gates[k, 3] >= 0]
-    # sample: the derivative state of the parameter whose gate is at position
-    # M - K (K gates after it), timed end to end
-    K = 24
-    sel_pos = rot_pos[-1]
-    for k in reversed(rot_pos):
-        if M - k >= K:
-            sel_pos = k
-            break
-    p = int(pr.gates[sel_pos, 3])
-    dim = 2 ** n
     t0 = time.perf_counter()
-    psi = np.empty(dim, dtype=np.complex128)
-    # the oracle's forward pass over the first gates: time per gate apply
-    sub = type(pr)(**{**pr.__dict__, "gates": pr.gates[:K]})
-    oracle.forward(sub)                      # first touch of the oracle's buffers
-    t_fwd0 = time.perf_counter()
-    a = oracle.forward(sub)
-    t_apply = (time.perf_counter() - t_fwd0) / K
-    t_ip0 = time.perf_counter()
-    for _ in range(3):
-        oracle.inner(a, a)
-    t_inner = (time.perf_counter() - t_ip0) / 3
+    psi = oracle.forward(pr)
+    t_apply = (time.perf_counter() - t0) / M
+    t1 = time.perf_counter()
+    reps = 4
+    for _ in range(reps):
+        oracle.inner(psi, psi)
+    t_inner = (time.perf_counter() - t1) / reps
     elapsed = time.perf_counter() - t0
-    # full oracle step = P derivative states (sum over p of the gates after it,
-    # plus its prefix walked once) + P^2 inner products + H psi + solve
-    applies = M + sum(M - k for k in rot_pos)
-    inner = P * P + P
+    applies = M + sum(M - k for k in rot_pos)      # prefix walk + suffix of every derivative state
+    inner = P * P + 2 * P                          # Gram matrix, T, gradient
     est = applies * t_apply + inner * t_inner
-    del psi, a, p
+    del psi
     return {"value": est, "unit": "s/step", "cores": cores, "kind": "oracle",
-            "sample": f"{K} gate applies and 3 inner products of the oracle at n={n} (complex128, "
-                      f"{elapsed:.1f} s), extrapolated to its {applies} applies and {inner} inner products per step"}
+            "sample": f"oracle forward state of all {M} gates plus {reps} inner products at n={n} (complex128, "
+                      f"{elapsed:.1f} s measured: {t_apply * 1e3:.1f} ms/gate apply, {t_inner * 1e3:.1f} ms/inner "
+                      f"product), extrapolated to its {applies} gate applies and {inner} inner products per step"}
+
+
+def traffic_per_launch():
+    """HBM bytes per sweep launch from the committed FETCH_SIZE/WRITE_SIZE counter
+    summary, if it was taken on the current kernel source (else None)."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        h = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        if t.get("kernel_sha256") != h:
+            return None
+        return t["bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        return None
 
 
 def main():
@@ -160,15 +176,8 @@ def main():
     ctx.set_option(qng.OPT_FUSION, args.fusion)
     ctx.set_option(qng.OPT_TILE_QUBITS, args.tile)
     ctx.set_option(qng.OPT_F64_REGISTERS, args.f64_regs)
-    ctx.set_option(qng.OPT_PROFILE, 0)
-    t_chosen, res, st = time_steps(ctx, circ, pr, args.prec, args.steps, args.warmup)
+    t_chosen, res, st = time_steps(ctx, circ, pr, args.prec, args.steps, args.warmup, profile=True)
     log(f"{args.prec}: {t_chosen:.3f} s/step  stats={st}")
-    # hot-kernel timing: one more step with HIP events around every sweep launch
-    ctx.set_option(qng.OPT_PROFILE, 1)
-    ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, prec=args.prec, want_G=False)
-    torch.cuda.synchronize()
-    prof = ctx.stats()
-    ctx.set_option(qng.OPT_PROFILE, 0)
     plain = None
     if not args.no_plain:
         other = "c128" if args.prec == "c64" else "c64"
@@ -180,15 +189,19 @@ def main():
         gate = gate_apply_bandwidth(qng, ctx, min(args.gate_qubits, pr.n_qubits), args.prec)
         log(f"gate apply: {gate}")
     cpu = None if args.no_cpu else cpu_baseline(pr)
-    if prof["sweep_launches"] > 0 and prof["sweep_ms"] > 0:
-        avg_ms = prof["sweep_ms"] / prof["sweep_launches"]
-        per_launch_bytes = prof["sweep_bytes"] / prof["sweep_launches"]
-        achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "sweep_pass",
-                "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": per_launch_bytes}
-    else:
-        roof = None
+    roof = None
+    if st.get("sweep_launches", 0) > 0 and st.get("sweep_ms", 0) > 0:
+        nl = st["sweep_launches"]
+        avg_ms = st["sweep_ms"] / nl
+        flops = st["sweep_flops"] / nl
+        bytes_ = st["sweep_bytes"] / nl
+        achieved = flops / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / VALU_PEAK_TFLOPS, "traffic": traffic_per_launch(), "kernel": "k_sweep_reg",
+                "avg_launch_ms": avg_ms, "launches": nl, "algorithmic_flops_per_launch": flops,
+                "algorithmic_bytes_per_launch": bytes_,
+                "hbm_achieved_GBps": bytes_ / (avg_ms * 1e-3) / 1e9,
+                "hbm_frac": bytes_ / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     line = {
         "metric": "QNG step time (s) + gate-apply HBM GB/s at n=26,P=400; chosen vs plain FP64",
         "value": t_chosen, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -199,7 +212,7 @@ def main():
                    "hamiltonian_terms": pr.n_terms, "precision": args.prec, "fusion": args.fusion,
                    "tile_qubits": args.tile or None, "f64_registers": bool(args.f64_regs)},
         "plain_fp64": plain, "gate_apply": gate, "roofline": roof, "cpu_baseline": cpu,
-        "breakdown_ms": {"metric": st["metric_ms"], "grad": st["grad_ms"], "solve": st["solve_ms"]},
+        "breakdown_ms": {k: st[k] / args.steps for k in ("metric_ms", "grad_ms", "solve_ms")},
     }
     print(json.dumps(line), flush=True)
     ctx.close()

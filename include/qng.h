@@ -112,6 +112,8 @@ typedef struct {
     int64_t sweep_tiles;         /* tiles processed by those launches */
     double  sweep_ms;            /* summed HIP-event duration of those launches (QNG_OPT_PROFILE) */
     double  sweep_bytes;         /* algorithmic HBM bytes of those launches: read+write of 2 states per pass */
+    double  sweep_flops;         /* algorithmic FLOPs of those launches: 20 per amplitude per element
+                                    (8 for <lambda|sigma|phi>, 12 for the rotation adjoint on both states) */
     int64_t elements;            /* L_ij (i<j) elements evaluated */
     int64_t other_launches;      /* every other kernel launch */
     double  metric_ms;           /* wall-clock of the metric part (G) */

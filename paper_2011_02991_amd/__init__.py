@@ -56,7 +56,7 @@ class _PauliSum(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("sweep_launches", ctypes.c_int64), ("sweep_tiles", ctypes.c_int64), ("sweep_ms", ctypes.c_double),
-                ("sweep_bytes", ctypes.c_double), ("elements", ctypes.c_int64), ("other_launches", ctypes.c_int64),
+                ("sweep_bytes", ctypes.c_double), ("sweep_flops", ctypes.c_double), ("elements", ctypes.c_int64), ("other_launches", ctypes.c_int64),
                 ("metric_ms", ctypes.c_double), ("grad_ms", ctypes.c_double), ("solve_ms", ctypes.c_double)]
 
     def as_dict(self):

@@ -181,6 +181,7 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
             ++stats->other_launches;
             stats->sweep_tiles += L.total_tiles;
             stats->sweep_bytes += (double)L.n_items * 4.0 * (double)V;
+            stats->sweep_flops += 20.0 * (double)L.n_tasks * (double)((uint64_t)1 << n);
         }
     }
     stats->elements += (int64_t)c.P * (c.P - 1) / 2;

@@ -1,0 +1,146 @@
+"""Profiling helper for the fused sweep-pass kernel (k_sweep_reg).
+
+Two modes:
+
+  python profile_sweep.py run [--config 3] [--prec c64]
+      One metric evaluation of a workload, preceded by one plain device copy of
+      512 MiB (the calibration kernel for FETCH_SIZE / WRITE_SIZE).  Meant to run
+      under rocprofv3 --pmc, one counter group per run.
+
+  python profile_sweep.py summarize --kind {stats,traffic,counters} --out FILE DB...
+      Summarise rocprofv3 databases into short text under profiles/:
+      * stats:    per-kernel call counts and durations (kernel trace);
+      * traffic:  FETCH_SIZE and WRITE_SIZE of the sweep kernel per launch,
+                  scaled by what the same counters read for the 512 MiB copy,
+                  tagged with the SHA-256 of the kernel source;
+      * counters: any other counters of the sweep kernel, per wave.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import glob
+import hashlib
+import json
+import os
+import sqlite3
+import sys
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+KERNEL_SRC = os.path.join(ROOT, "paper_2011_02991_amd", "csrc", "sweep_kernels.hip")
+COPY_BYTES = 512 * 2 ** 20
+
+
+def run(args):
+    import torch
+    import paper_2011_02991_amd as qng
+    import workloads as W
+    dst = torch.empty(COPY_BYTES // 8, dtype=torch.complex64, device="cuda")
+    src = torch.empty_like(dst)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del dst, src
+    pr = W.CONFIGS[args.config]() if args.layers <= 0 else W.scaled(W.CONFIGS[args.config], 26, args.layers)
+    print(f"profiling metric of {pr.name} ({args.prec})", flush=True)
+    ctx = qng.Context(0)
+    ctx.set_option(qng.OPT_TILE_QUBITS, args.tile)
+    ctx.set_option(qng.OPT_F64_REGISTERS, args.f64_regs)
+    ctx.metric(qng.Circuit.from_problem(pr), pr.theta, prec=args.prec)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": pr.name, "prec": args.prec, **ctx.stats()}), flush=True)
+
+
+def _short(name: str) -> str:
+    import re
+    m = re.search(r"(k_\w+(?:<[^>]*>)?)", name)
+    return m.group(1) if m else name[:60]
+
+
+def _family(name: str) -> str:
+    if "k_sweep_reg" in name:
+        return "sweep"
+    if "copy" in name.lower():
+        return "copy"
+    return _short(name)
+
+
+def _pmc(dbs):
+    agg = collections.defaultdict(lambda: collections.defaultdict(float))
+    disp = collections.defaultdict(set)
+    for db in dbs:
+        con = sqlite3.connect(db)
+        for name, cn, v, d in con.execute("select name, counter_name, counter_value, dispatch_id from pmc_events"):
+            f = _family(name)
+            agg[f][cn] += v
+            disp[f].add(d)
+    return agg, {k: len(v) for k, v in disp.items()}
+
+
+def summarize(args):
+    dbs = []
+    for d in args.dbs:
+        dbs += glob.glob(os.path.join(d, "**", "*.db"), recursive=True) if os.path.isdir(d) else [d]
+    cmd = args.command or ""
+    if args.kind == "stats":
+        rows = collections.defaultdict(lambda: [0, 0.0])
+        for db in dbs:
+            con = sqlite3.connect(db)
+            for name, dur in con.execute("select name, duration from kernels"):
+                r = rows[_short(name)]
+                r[0] += 1
+                r[1] += dur
+        total = sum(r[1] for r in rows.values()) or 1.0
+        lines = [f"# Kernel trace summary: {args.title}", "", f"Command: `{cmd}`", "",
+                 "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
+        for name, (c, d) in sorted(rows.items(), key=lambda kv: -kv[1][1])[:15]:
+            lines.append(f"| `{name[:80]}` | {c} | {d / 1e6:.1f} | {d / c / 1e3:.1f} | {100 * d / total:.1f} |")
+        open(args.out, "w").write("\n".join(lines) + "\n")
+    elif args.kind == "traffic":
+        agg, nd = _pmc(dbs)
+        sw, cp = agg["sweep"], agg["copy"]
+        f_fetch = COPY_BYTES / (cp["FETCH_SIZE"] * 1024) if cp.get("FETCH_SIZE") else None
+        f_write = COPY_BYTES / (cp["WRITE_SIZE"] * 1024) if cp.get("WRITE_SIZE") else None
+        n = nd.get("sweep", 1)
+        fetch = sw.get("FETCH_SIZE", 0) * 1024 * (f_fetch or 1) / n
+        write = sw.get("WRITE_SIZE", 0) * 1024 * (f_write or 1) / n
+        out = {"kernel": "k_sweep_reg", "title": args.title, "command": cmd, "launches": n,
+               "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+               "bytes_per_launch": fetch + write, "copy_scale_fetch": f_fetch, "copy_scale_write": f_write,
+               "kernel_sha256": hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()}
+        json.dump(out, open(args.out, "w"), indent=1)
+    else:
+        agg, nd = _pmc(dbs)
+        sw = agg["sweep"]
+        waves = sw.get("SQ_WAVES", 0) or 1
+        lines = [f"# Sweep-kernel counters: {args.title}", "", f"Command: `{cmd}`", "",
+                 f"Launches: {nd.get('sweep', 0)}; values per wave (SQ_WAVES = {waves:.0f})", "",
+                 "| counter | per wave |", "|---|---|"]
+        for k, v in sorted(sw.items()):
+            lines.append(f"| {k} | {v / waves:.1f} |")
+        with open(args.out, "a") as f:
+            f.write("\n".join(lines) + "\n\n")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="mode", required=True)
+    r = sub.add_parser("run")
+    r.add_argument("--config", type=int, default=3)
+    r.add_argument("--prec", default="c64")
+    r.add_argument("--tile", type=int, default=0)
+    r.add_argument("--f64-regs", type=int, default=0)
+    r.add_argument("--layers", type=int, default=0, help="layers of a 26-qubit instance (0 = the full workload)")
+    s = sub.add_parser("summarize")
+    s.add_argument("--kind", choices=["stats", "traffic", "counters"], required=True)
+    s.add_argument("--out", required=True)
+    s.add_argument("--title", default="")
+    s.add_argument("--command", default="")
+    s.add_argument("dbs", nargs="+")
+    a = ap.parse_args()
+    run(a) if a.mode == "run" else summarize(a)
+
+
+if __name__ == "__main__":
+    main()
