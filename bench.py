@@ -61,7 +61,7 @@ def time_steps(ctx, circ, pr, prec, steps, warmup, profile=False):
     t0 = time.perf_counter()
     res = None
     for _ in range(steps):
-        res = ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, prec=prec, want_G=False)
+        res = ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, prec=prec, want_G=True)
         for k, v in ctx.stats().items():
             acc[k] = acc.get(k, 0) + v
     torch.cuda.synchronize()
@@ -112,6 +112,23 @@ def gate_apply_bandwidth(qng, ctx, n, prec):
     return {"rotation_median_GBps": rot[len(rot) // 2], "rotation_worst_GBps": rot[0],
             "rotation_best_GBps": rot[-1], "fixed_median_GBps": fixed[len(fixed) // 2] if fixed else None,
             "n": n, "gates_measured": len(results), "frac_of_8TBps": rot[len(rot) // 2] / HBM_PEAK_GBS}
+
+
+def precision_report(pr, res, ref, prec, ref_prec):
+    """Normwise differences of one precision's step against the other's (the
+    complex128 path is the FP64 reference at this size; it is pinned to the
+    oracle on sampled parameters by the full-size parity tests)."""
+    import numpy as np
+
+    def rel(a, b):
+        return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+    g = ref["G"].real + pr.tikhonov * np.eye(pr.n_params)
+    return {"prec": prec, "reference": ref_prec, "max_abs_dG": float(np.abs(res["G"] - ref["G"]).max()),
+            "rel_dG": rel(res["G"], ref["G"]), "max_abs_dgrad": float(np.abs(res["grad"] - ref["grad"]).max()),
+            "rel_dgrad": rel(res["grad"], ref["grad"]), "abs_dE": abs(res["E"] - ref["E"]),
+            "max_abs_ddtheta": float(np.abs(res["dtheta"] - ref["dtheta"]).max()),
+            "rel_ddtheta": rel(res["dtheta"], ref["dtheta"]), "kappa_shifted_metric": float(np.linalg.cond(g))}
 
 
 def cpu_baseline(pr):
@@ -178,12 +195,17 @@ def main():
     ctx.set_option(qng.OPT_F64_REGISTERS, args.f64_regs)
     t_chosen, res, st = time_steps(ctx, circ, pr, args.prec, args.steps, args.warmup, profile=True)
     log(f"{args.prec}: {t_chosen:.3f} s/step  stats={st}")
-    plain = None
+    plain = precision = None
     if not args.no_plain:
         other = "c128" if args.prec == "c64" else "c64"
-        t_plain, _, st2 = time_steps(ctx, circ, pr, other, max(1, args.steps - 1), 1)
+        t_plain, res_other, st2 = time_steps(ctx, circ, pr, other, max(1, args.steps - 1), 1)
         plain = {"prec": other, "s_per_step": t_plain}
         log(f"{other}: {t_plain:.3f} s/step")
+        if args.prec == "c64":
+            precision = precision_report(pr, res, res_other, "c64", "c128")
+        else:
+            precision = precision_report(pr, res_other, res, "c64", "c128")
+        log(f"precision: {precision}")
     gate = None
     if args.gate_qubits > 0:
         gate = gate_apply_bandwidth(qng, ctx, min(args.gate_qubits, pr.n_qubits), args.prec)
@@ -211,7 +233,7 @@ def main():
         "config": {"workload": pr.name, "n_qubits": pr.n_qubits, "P": pr.n_params, "gates": pr.n_gates,
                    "hamiltonian_terms": pr.n_terms, "precision": args.prec, "fusion": args.fusion,
                    "tile_qubits": args.tile or None, "f64_registers": bool(args.f64_regs)},
-        "plain_fp64": plain, "gate_apply": gate, "roofline": roof, "cpu_baseline": cpu,
+        "plain_fp64": plain, "precision_errors": precision, "gate_apply": gate, "roofline": roof, "cpu_baseline": cpu,
         "breakdown_ms": {k: st[k] / args.steps for k in ("metric_ms", "grad_ms", "solve_ms")},
     }
     print(json.dumps(line), flush=True)

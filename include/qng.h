@@ -103,7 +103,12 @@ typedef enum {
     QNG_OPT_COLUMN_STREAMS = 2,  /* columns swept concurrently, each with its own 2 states (0 = automatic) */
     QNG_OPT_PROFILE = 3,         /* 1: time every sweep-pass launch with HIP events (see qng_stats) */
     QNG_OPT_SMALL_N_KERNEL = 4,  /* 1 (default): whole-column on-chip kernel for small registers */
-    QNG_OPT_F64_REGISTERS = 5    /* complex64 storage: 1 = sweep tiles computed in FP64 registers, 0 = FP32 */
+    QNG_OPT_F64_REGISTERS = 5,   /* complex64 storage: 1 = sweep tiles computed in FP64 registers, 0 = FP32 */
+    QNG_OPT_GRAPH = 6,           /* qng_step_batched: 1 (default) = capture the metric phase of a batch into a
+                                    hipGraph on first use and replay it (needs a non-null stream) */
+    QNG_OPT_AUTOTUNE = 7,        /* qng_step_batched: 1 = time candidate tile widths and launch sizes on the
+                                    first call for a batch structure and keep the fastest; 0 (default) = fixed */
+    QNG_OPT_BATCH_TILES = 8      /* qng_step_batched: work-groups per sweep launch to aim for (0 = 4096) */
 } qng_option;
 
 /* Counters of the last metric/energy/step call on a context. */
@@ -119,6 +124,10 @@ typedef struct {
     double  metric_ms;           /* wall-clock of the metric part (G) */
     double  grad_ms;             /* wall-clock of energy + gradient */
     double  solve_ms;            /* wall-clock of the FP64 solve */
+    int32_t tile_qubits;         /* qng_step_batched: tile width used (0 = library default) */
+    int32_t target_tiles;        /* qng_step_batched: work-groups per launch aimed for */
+    double  tune_ms;             /* qng_step_batched: wall-clock spent autotuning in this call */
+    int64_t graph_replays;       /* qng_step_batched: register classes run as a replay of a captured graph */
 } qng_stats;
 
 /* Plan of a circuit under the current options (host only, no device work). */

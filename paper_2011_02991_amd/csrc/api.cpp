@@ -29,13 +29,15 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
 
+#include "batch.hpp"
 #include "circuit.hpp"
-#include "kernels.hpp"
 #include "fused.hpp"
+#include "kernels.hpp"
 #include "sweep.hpp"
 
 namespace qng {
@@ -44,17 +46,32 @@ void solve_shifted(int P, const double *G, double eps, const double *b, double *
 
 using namespace qng;
 
+// One register class of a batch: its schedule and, once captured, the hipGraph
+// of its metric phase (valid for the workspace address it was captured with).
+struct BatchClass {
+    std::shared_ptr<BatchSchedule> sched;
+    hipGraphExec_t graph = nullptr;
+    const void *graph_ws = nullptr;
+    std::vector<uint64_t> graph_ptrs;    // device addresses baked into the graph
+    ~BatchClass() {
+        if (graph) (void)hipGraphExecDestroy(graph);
+    }
+};
+
 struct qng_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     size_t mem_limit = 0;
     int opt_fusion = 1, opt_tile = 0, opt_streams = 0, opt_profile = 0, opt_small = 1, opt_f64_regs = 0;
+    int opt_graph = 1, opt_autotune = 0, opt_batch_tiles = 0;
     std::string last_error;
     qng_stats stats{};
     void *ws = nullptr;
     size_t ws_bytes = 0;
     SweepCache sweep_cache;
+    std::map<std::vector<int32_t>, std::shared_ptr<BatchClass>> batch_classes;
+    std::map<std::vector<int32_t>, BatchTuning> tuned;
 };
 
 namespace {
@@ -208,17 +225,23 @@ Problem make_problem(const qng_circuit *c, const double *theta, const qng_pauli_
 template <typename R> struct Engine {
     qng_ctx *ctx;
     const Problem &pb;
-    char *base;
-    Layout L;
     hipStream_t st;
     int n;
+    void *regs[3];            // psi, lambda, phi
+    size_t state_bytes;
+    double *partials_, *lraw_, *traw_, *graw_, *eraw_;
 
-    void *state(int k) const { return base + L.states + (size_t)k * L.state_bytes; }
-    double *partials() const { return (double *)(base + L.partials); }
-    double *lraw() const { return (double *)(base + L.lraw); }
-    double *traw() const { return (double *)(base + L.traw); }
-    double *graw() const { return (double *)(base + L.graw); }
-    double *eraw() const { return (double *)(base + L.eraw); }
+    Engine(qng_ctx *c, const Problem &p, hipStream_t s, void *psi, void *lam, void *phi, size_t sb, double *part,
+           double *lraw, double *traw, double *graw, double *eraw)
+        : ctx(c), pb(p), st(s), n(p.circ.n), regs{psi, lam, phi}, state_bytes(sb), partials_(part), lraw_(lraw),
+          traw_(traw), graw_(graw), eraw_(eraw) {}
+
+    void *state(int k) const { return regs[k]; }
+    double *partials() const { return partials_; }
+    double *lraw() const { return lraw_; }
+    double *traw() const { return traw_; }
+    double *graw() const { return graw_; }
+    double *eraw() const { return eraw_; }
 
     void apply(int pos, bool adjoint_gate, void *s0, void *s1) {
         const qng_gate &g = pb.circ.gates[pos];
@@ -294,7 +317,7 @@ template <typename R> struct Engine {
 
     void hamiltonian(const void *psi, void *out) {
         if (pb.ham.empty()) {
-            HIPCHECK(hipMemsetAsync(out, 0, L.state_bytes, st));
+            HIPCHECK(hipMemsetAsync(out, 0, state_bytes, st));
             return;
         }
         for (size_t t = 0; t < pb.ham.size(); ++t) {
@@ -343,7 +366,10 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
     Layout L = plan_layout(n, c.P, amp, n_states, spec.in_host != nullptr, scratch);
     char *base = ensure_workspace(ctx, L.total);
     hipStream_t st = ctx->stream;
-    Engine<R> e{ctx, pb, base, L, st, n};
+    char *sb = base + L.states;
+    Engine<R> e(ctx, pb, st, sb, sb + L.state_bytes, sb + 2 * L.state_bytes, L.state_bytes,
+                (double *)(base + L.partials), (double *)(base + L.lraw), (double *)(base + L.traw),
+                (double *)(base + L.graw), (double *)(base + L.eraw));
 
     const void *in_c128 = spec.in_dev;
     if (spec.in_host) {
@@ -426,6 +452,297 @@ void host_unpack_grad(const std::vector<double> &graw, const Problem &pb, double
     for (size_t r = 0; r < pb.param_of.size(); ++r) grad[pb.param_of[r]] = -graw[2 * r + 1];
 }
 
+// ------------------------------------------------------------ batched metric
+
+// Tile width a member's plan ends up with (build_sweep_plan's clamping).
+int member_tile(const Circuit &c, int opt_tile, int amp, bool f64) {
+    int m = opt_tile > 0 ? opt_tile : default_tile_qubits(c.n, amp, f64);
+    if (m > (f64 ? 11 : 12)) m = f64 ? 11 : 12;
+    return m > c.n ? c.n : m;
+}
+
+struct BatchLayout {
+    std::vector<size_t> psi, traw, graw, gout, tout, param_of, lraw_class;
+    size_t lam = 0, staging = 0, partials = 0, eraw = 0;
+    size_t scratch = 0, images = 0, arena = 0, spart = 0, fwd = 0, adj = 0, adj32 = 0;
+    size_t total = 0;
+};
+
+struct BatchRun {
+    std::vector<std::vector<int>> classes;                 // member indices per class
+    std::vector<std::shared_ptr<BatchClass>> cls;
+    BatchLayout L;
+    char *base = nullptr;
+    int64_t launches = 0;
+};
+
+template <typename R>
+BatchRun batch_metric(qng_ctx *ctx, const std::vector<Problem> &pbs, const double *const *in_states,
+                      const BatchTuning &tun, bool allow_graph, bool profile) {
+    const int B = (int)pbs.size();
+    const int amp = 2 * (int)sizeof(R);
+    const bool f64 = amp == 16 || ctx->opt_f64_regs;
+    hipStream_t st = ctx->stream;
+    BatchRun run;
+
+    // register classes: members whose plans share the tile width
+    std::map<int, std::vector<int>> by_m;
+    for (int b = 0; b < B; ++b) by_m[member_tile(pbs[b].circ, tun.tile_qubits, amp, f64)].push_back(b);
+    size_t free_b = 0, total_b = 0;
+    HIPCHECK(hipMemGetInfo(&free_b, &total_b));
+    const uint64_t arena_cap = (uint64_t)(free_b + ctx->ws_bytes) / 4;
+    for (auto &kv : by_m) {
+        std::vector<int32_t> key = {kv.first, amp, f64 ? 1 : 0, tun.tile_qubits, tun.target_tiles};
+        for (int b : kv.second) append_structure_key(pbs[b].circ, key);
+        auto it = ctx->batch_classes.find(key);
+        std::shared_ptr<BatchClass> bc;
+        if (it != ctx->batch_classes.end()) {
+            bc = it->second;
+        } else {
+            std::vector<const Circuit *> mem;
+            std::vector<std::shared_ptr<const SweepPlan>> plans;
+            for (int b : kv.second) {
+                mem.push_back(&pbs[b].circ);
+                plans.push_back(ctx->sweep_cache.get_shared(pbs[b].circ, tun.tile_qubits, amp, 1, f64));
+            }
+            bc = std::make_shared<BatchClass>();
+            bc->sched = std::make_shared<BatchSchedule>(build_batch_schedule(mem, plans, amp, tun, arena_cap));
+            if (ctx->batch_classes.size() >= 64) ctx->batch_classes.clear();
+            ctx->batch_classes[key] = bc;
+        }
+        run.classes.push_back(kv.second);
+        run.cls.push_back(bc);
+    }
+
+    // workspace
+    BatchLayout &L = run.L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes + 16); return o; };
+    size_t vmax = 0, stage = 0;
+    int nmax = 1;
+    for (int b = 0; b < B; ++b) {
+        const Circuit &c = pbs[b].circ;
+        const size_t V = (size_t(1) << c.n) * amp;
+        vmax = std::max(vmax, V);
+        nmax = std::max(nmax, c.n);
+        if (in_states && in_states[b]) stage = std::max(stage, (size_t(1) << c.n) * 16);
+        L.psi.push_back(take(V));
+        L.traw.push_back(take((size_t)c.P * 16));
+        L.graw.push_back(take((size_t)c.P * 16));
+        L.gout.push_back(take((size_t)c.P * c.P * 16));
+        L.tout.push_back(take((size_t)c.P * 16));
+        L.param_of.push_back(take((size_t)c.P * 4));
+    }
+    L.lam = take(vmax);
+    L.staging = stage ? take(stage) : 0;
+    L.partials = take((size_t)reduce_blocks(nmax) * 16);
+    L.eraw = take((size_t)B * 16);
+    size_t img = 0, arena = 0, spart = 0, mats = 0;
+    for (size_t k = 0; k < run.cls.size(); ++k) {
+        const BatchSchedule &S = *run.cls[k]->sched;
+        L.lraw_class.push_back(take((size_t)S.lraw_elems * 16));
+        img = std::max(img, batch_image_bytes(S));
+        arena = std::max(arena, (size_t)S.arena_bytes);
+        spart = std::max(spart, (size_t)S.partial_elems * 16);
+        mats = std::max(mats, (size_t)S.mat_rows * 64);
+    }
+    L.images = take(img);
+    L.arena = take(arena);
+    L.spart = take(spart);
+    L.fwd = take(mats);
+    L.adj = take(mats);
+    L.adj32 = take(mats / 2);
+    L.total = off;
+    char *base = ensure_workspace(ctx, L.total);
+    run.base = base;
+
+    // inputs: forward registers, parameter maps
+    for (int b = 0; b < B; ++b) {
+        const Circuit &c = pbs[b].circ;
+        const void *src = nullptr;
+        if (in_states && in_states[b]) {
+            HIPCHECK(hipMemcpyAsync(base + L.staging, in_states[b], (size_t(1) << c.n) * 16, hipMemcpyHostToDevice,
+                                    st));
+            src = base + L.staging;
+        }
+        launch_init_state<R>(base + L.psi[b], c.n, src, st);
+        if (c.P)
+            HIPCHECK(hipMemcpyAsync(base + L.param_of[b], pbs[b].param_of.data(), (size_t)c.P * 4,
+                                    hipMemcpyHostToDevice, st));
+        ++ctx->stats.other_launches;
+    }
+
+    // metric phase, one register class at a time
+    for (size_t k = 0; k < run.cls.size(); ++k) {
+        BatchClass &bc = *run.cls[k];
+        const BatchSchedule &S = *bc.sched;
+        const std::vector<int> &mem = run.classes[k];
+        std::vector<const Circuit *> circs;
+        BatchDevice d;
+        d.images = base + L.images;
+        d.arena = base + L.arena;
+        d.fwd_mats = (double *)(base + L.fwd);
+        d.adj_mats = (double *)(base + L.adj);
+        d.adj_mats32 = (float *)(base + L.adj32);
+        d.partials = (double *)(base + L.spart);
+        d.lraw = (double *)(base + L.lraw_class[k]);
+        d.reduce_partials = (double *)(base + L.partials);
+        std::vector<double> fm((size_t)S.mat_rows * 8 + 8, 0.0), am((size_t)S.mat_rows * 8 + 8, 0.0);
+        for (size_t i = 0; i < mem.size(); ++i) {
+            const Problem &pb = pbs[mem[i]];
+            circs.push_back(&pb.circ);
+            d.psi.push_back(base + L.psi[mem[i]]);
+            d.traw.push_back((double *)(base + L.traw[mem[i]]));
+            for (const Rot &r : pb.circ.rots) {
+                const Mat2 *src[2] = {&pb.fwd[r.pos], &pb.adj[r.pos]};
+                double *dst[2] = {&fm[(size_t)(S.gate_base[i] + r.pos) * 8], &am[(size_t)(S.gate_base[i] + r.pos) * 8]};
+                for (int w = 0; w < 2; ++w) {
+                    const Mat2 &m = *src[w];
+                    double *o = dst[w];
+                    o[0] = m.a.real(); o[1] = m.a.imag(); o[2] = m.b.real(); o[3] = m.b.imag();
+                    o[4] = m.c.real(); o[5] = m.c.imag(); o[6] = m.d.real(); o[7] = m.d.imag();
+                }
+            }
+        }
+        std::vector<float> am32(am.begin(), am.end());
+        if (S.mat_rows) {
+            HIPCHECK(hipMemcpyAsync(d.fwd_mats, fm.data(), (size_t)S.mat_rows * 64, hipMemcpyHostToDevice, st));
+            HIPCHECK(hipMemcpyAsync(d.adj_mats, am.data(), (size_t)S.mat_rows * 64, hipMemcpyHostToDevice, st));
+            HIPCHECK(hipMemcpyAsync(d.adj_mats32, am32.data(), (size_t)S.mat_rows * 32, hipMemcpyHostToDevice, st));
+        }
+        upload_batch_images(S, d, st);   // synchronises: fm, am and the images are on the device
+        // stats from the schedule
+        for (const BatchLaunch &bl : S.launches) {
+            ++ctx->stats.sweep_launches;
+            ctx->stats.sweep_tiles += bl.total_tiles;
+            for (uint32_t j = 0; j < bl.n_items; ++j) {
+                const LaunchItem &it = S.items[bl.item_begin + j];
+                const uint64_t amps = (uint64_t)it.ntiles << S.m;
+                ctx->stats.sweep_bytes += 4.0 * (double)amps * amp;
+            }
+            for (uint32_t j = 0; j < bl.n_tasks; ++j) ctx->stats.sweep_flops += 20.0 * (double)S.tasks[bl.task_begin + j].count * (double)(1u << S.m);
+        }
+        ctx->stats.elements += S.elements;
+        run.launches += (int64_t)S.launches.size();
+        const bool graph = allow_graph && !profile && st != nullptr;
+        std::vector<uint64_t> ptrs = {(uint64_t)(uintptr_t)base, (uint64_t)L.total};
+        if (graph) {
+            if (!bc.graph || bc.graph_ptrs != ptrs) {
+                if (bc.graph) {
+                    HIPCHECK(hipGraphExecDestroy(bc.graph));
+                    bc.graph = nullptr;
+                }
+                hipGraph_t g = nullptr;
+                HIPCHECK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+                try {
+                    enqueue_batch_metric<R>(S, circs, d, f64, st, nullptr);
+                } catch (...) {
+                    hipGraph_t junk = nullptr;
+                    (void)hipStreamEndCapture(st, &junk);
+                    if (junk) (void)hipGraphDestroy(junk);
+                    throw;
+                }
+                HIPCHECK(hipStreamEndCapture(st, &g));
+                hipGraphExec_t ge = nullptr;
+                const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess) fail(QNG_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+                bc.graph = ge;
+                bc.graph_ptrs = ptrs;
+            } else {
+                ++ctx->stats.graph_replays;
+            }
+            HIPCHECK(hipGraphLaunch(bc.graph, st));
+        } else {
+            std::vector<hipEvent_t> ev;
+            if (profile) {
+                ev.resize(2 * S.launches.size());
+                for (auto &e : ev) HIPCHECK(hipEventCreate(&e));
+            }
+            enqueue_batch_metric<R>(S, circs, d, f64, st, profile ? &ev : nullptr);
+            if (profile) {
+                HIPCHECK(hipStreamSynchronize(st));
+                for (size_t li = 0; li < S.launches.size(); ++li) {
+                    float ms = 0.f;
+                    HIPCHECK(hipEventElapsedTime(&ms, ev[2 * li], ev[2 * li + 1]));
+                    ctx->stats.sweep_ms += ms;
+                }
+                for (auto &e : ev) (void)hipEventDestroy(e);
+            }
+        }
+        for (size_t i = 0; i < mem.size(); ++i) {
+            const Problem &pb = pbs[mem[i]];
+            launch_unpack_metric(d.lraw + 2 * S.lraw_base[i], d.traw[i], (const int *)(base + L.param_of[mem[i]]),
+                                 pb.circ.P, (double *)(base + L.gout[mem[i]]), (double *)(base + L.tout[mem[i]]), st);
+            ++ctx->stats.other_launches;
+        }
+    }
+    return run;
+}
+
+// Autotuner of the batched metric: coordinate search over the tile width
+// (fusion width) and the work-groups per launch, timing the whole metric phase
+// of this batch; the winner is cached per batch structure.
+template <typename R>
+BatchTuning batch_tuning(qng_ctx *ctx, const std::vector<Problem> &pbs, const double *const *in_states) {
+    const int amp = 2 * (int)sizeof(R);
+    const bool f64 = amp == 16 || ctx->opt_f64_regs;
+    BatchTuning fixed;
+    fixed.tile_qubits = ctx->opt_tile;
+    fixed.target_tiles = ctx->opt_batch_tiles > 0 ? ctx->opt_batch_tiles : 4096;
+    if (!ctx->opt_autotune) return fixed;
+    std::vector<int32_t> key = {amp, f64 ? 1 : 0, ctx->opt_tile, ctx->opt_batch_tiles};
+    for (const Problem &pb : pbs) append_structure_key(pb.circ, key);
+    auto it = ctx->tuned.find(key);
+    if (it != ctx->tuned.end()) return it->second;
+    auto t0 = Clock::now();
+    hipStream_t st = ctx->stream;
+    auto time_of = [&](const BatchTuning &t) {
+        hipEvent_t e0, e1;
+        HIPCHECK(hipEventCreate(&e0));
+        HIPCHECK(hipEventCreate(&e1));
+        const qng_stats saved = ctx->stats;
+        // a first run uploads and warms; the second is timed
+        batch_metric<R>(ctx, pbs, in_states, t, false, false);
+        HIPCHECK(hipEventRecord(e0, st));
+        batch_metric<R>(ctx, pbs, in_states, t, false, false);
+        HIPCHECK(hipEventRecord(e1, st));
+        HIPCHECK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        ctx->stats = saved;
+        return (double)ms;
+    };
+    std::vector<int> tiles;
+    if (ctx->opt_tile > 0) tiles = {ctx->opt_tile};
+    else if (f64) tiles = {10, 11};
+    else tiles = {10, 11, 12};
+    std::vector<int> targets;
+    if (ctx->opt_batch_tiles > 0) targets = {ctx->opt_batch_tiles};
+    else targets = {4096, 2048, 8192};
+    BatchTuning best = fixed;
+    double best_ms = 1e300;
+    for (int m : tiles) {
+        BatchTuning t;
+        t.tile_qubits = m;
+        t.target_tiles = targets[0];
+        const double ms = time_of(t);
+        if (ms < best_ms) { best_ms = ms; best = t; }
+    }
+    for (size_t k = 1; k < targets.size(); ++k) {
+        BatchTuning t = best;
+        t.target_tiles = targets[k];
+        const double ms = time_of(t);
+        if (ms < best_ms) { best_ms = ms; best = t; }
+    }
+    if (ctx->tuned.size() >= 64) ctx->tuned.clear();
+    ctx->tuned[key] = best;
+    ctx->stats.tune_ms += ms_since(t0);
+    return best;
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -504,6 +821,12 @@ qng_status qng_set_option(qng_ctx *ctx, int option, int value) {
         case QNG_OPT_PROFILE: ctx->opt_profile = value ? 1 : 0; break;
         case QNG_OPT_SMALL_N_KERNEL: ctx->opt_small = value ? 1 : 0; break;
         case QNG_OPT_F64_REGISTERS: ctx->opt_f64_regs = value ? 1 : 0; break;
+        case QNG_OPT_GRAPH: ctx->opt_graph = value ? 1 : 0; break;
+        case QNG_OPT_AUTOTUNE: ctx->opt_autotune = value ? 1 : 0; break;
+        case QNG_OPT_BATCH_TILES:
+            if (value < 0) fail(QNG_E_INVALID_ARG, "batch tiles < 0");
+            ctx->opt_batch_tiles = value;
+            break;
         default: fail(QNG_E_INVALID_ARG, "unknown option " + std::to_string(option));
         }
     });
@@ -713,14 +1036,85 @@ qng_status qng_step_batched(qng_ctx *ctx, int32_t B, const qng_circuit *circs, c
                             double *const *grad_out, double *E_out) {
     return guarded(ctx, [&] {
         require_ctx(ctx);
+        check_prec(prec);
         if (B < 0 || (B > 0 && (!circs || !hams || !thetas || !dtheta_out)))
             fail(QNG_E_INVALID_ARG, "bad batch arguments");
+        validate_scalar(dt, "dt");
+        validate_scalar(tikhonov, "tikhonov");
+        if (tikhonov < 0) fail(QNG_E_INVALID_ARG, "tikhonov < 0");
         for (int b = 0; b < B; ++b) {
-            const qng_status s = qng_step(ctx, &circs[b], in_states ? in_states[b] : nullptr, &hams[b], thetas[b], dt,
-                                          tikhonov, prec, dtheta_out[b], G_out ? G_out[b] : nullptr,
-                                          grad_out ? grad_out[b] : nullptr, E_out ? &E_out[b] : nullptr);
-            if (s != QNG_OK) fail(s, "ansatz " + std::to_string(b) + ": " + ctx->last_error);
+            try {
+                validate_circuit(&circs[b], max_qubits(prec));
+                validate_theta(&circs[b], thetas[b]);
+                validate_hamiltonian(&circs[b], &hams[b]);
+                if (circs[b].n_params > 0 && !dtheta_out[b]) fail(QNG_E_INVALID_ARG, "dtheta_out is NULL");
+                check_in_state_host(circs[b].n_qubits, in_states ? in_states[b] : nullptr);
+            } catch (const Error &e) {
+                fail(e.status, "ansatz " + std::to_string(b) + ": " + e.msg);
+            }
         }
+        reset_stats(ctx);
+        if (B == 0) return;
+        std::vector<Problem> pbs;
+        pbs.reserve(B);
+        for (int b = 0; b < B; ++b) pbs.push_back(make_problem(&circs[b], thetas[b], &hams[b]));
+        std::vector<std::vector<double>> G(B), graw(B);
+        std::vector<double> E(2 * (size_t)B);
+        dispatch(prec, [&](auto tag) {
+            using R = decltype(tag);
+            const BatchTuning tun = batch_tuning<R>(ctx, pbs, in_states);
+            ctx->stats.tile_qubits = tun.tile_qubits;
+            ctx->stats.target_tiles = tun.target_tiles;
+            auto t0 = Clock::now();
+            BatchRun run = batch_metric<R>(ctx, pbs, in_states, tun, ctx->opt_graph != 0, ctx->opt_profile != 0);
+            HIPCHECK(hipStreamSynchronize(ctx->stream));
+            ctx->stats.metric_ms = ms_since(t0);
+            t0 = Clock::now();
+            const BatchLayout &L = run.L;
+            char *base = run.base;
+            const size_t amp = 2 * sizeof(R);
+            for (int b = 0; b < B; ++b) {
+                const Problem &pb = pbs[b];
+                Engine<R> e(ctx, pb, ctx->stream, base + L.psi[b], base + L.lam, nullptr,
+                            (size_t(1) << pb.circ.n) * amp, (double *)(base + L.partials), nullptr,
+                            (double *)(base + L.traw[b]), (double *)(base + L.graw[b]),
+                            (double *)(base + L.eraw) + 2 * b);
+                e.energy_grad_unfused(batch_final_pos(pb.circ), true, nullptr);
+            }
+            for (int b = 0; b < B; ++b) {
+                const int P = pbs[b].circ.P;
+                G[b].assign(2 * (size_t)P * P + 2, 0.0);
+                graw[b].assign(2 * (size_t)P + 2, 0.0);
+                if (P) {
+                    HIPCHECK(hipMemcpyAsync(G[b].data(), base + L.gout[b], (size_t)P * P * 16, hipMemcpyDeviceToHost,
+                                            ctx->stream));
+                    HIPCHECK(hipMemcpyAsync(graw[b].data(), base + L.graw[b], (size_t)P * 16, hipMemcpyDeviceToHost,
+                                            ctx->stream));
+                }
+            }
+            HIPCHECK(hipMemcpyAsync(E.data(), base + L.eraw, (size_t)B * 16, hipMemcpyDeviceToHost, ctx->stream));
+            HIPCHECK(hipStreamSynchronize(ctx->stream));
+            ctx->stats.grad_ms = ms_since(t0);
+        });
+        auto t0 = Clock::now();
+        for (int b = 0; b < B; ++b) {
+            const int P = pbs[b].circ.P;
+            std::vector<double> grad(P + 1), rhs(P + 1), x(P + 1);
+            host_unpack_grad(graw[b], pbs[b], grad.data());
+            for (int i = 0; i < P; ++i) rhs[i] = -dt * grad[i];
+            if (P) {
+                try {
+                    qng::solve_shifted(P, G[b].data(), tikhonov, rhs.data(), x.data());
+                } catch (const Error &e) {
+                    fail(e.status, "ansatz " + std::to_string(b) + ": " + e.msg);
+                }
+                std::memcpy(dtheta_out[b], x.data(), (size_t)P * 8);
+                if (G_out && G_out[b]) std::memcpy(G_out[b], G[b].data(), (size_t)P * P * 16);
+                if (grad_out && grad_out[b]) std::memcpy(grad_out[b], grad.data(), (size_t)P * 8);
+            }
+            if (E_out) E_out[b] = E[2 * b];
+        }
+        ctx->stats.solve_ms = ms_since(t0);
     });
 }
 

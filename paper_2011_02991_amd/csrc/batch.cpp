@@ -1,0 +1,259 @@
+// batch.cpp -- schedule and executor of the batched metric (see batch.hpp).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <numeric>
+#include <string>
+
+#include "batch.hpp"
+#include "kernels.hpp"
+
+namespace qng {
+
+namespace {
+
+#define BCHECK(call)                                                                                  \
+    do {                                                                                              \
+        hipError_t _e = (call);                                                                       \
+        if (_e != hipSuccess) fail(QNG_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct ImageLayout {
+    size_t passes, ops, maps, items, tasks, total;
+};
+
+ImageLayout image_layout(const BatchSchedule &s) {
+    ImageLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes + 64); return o; };
+    L.passes = take(s.passes.size() * sizeof(DevPass));
+    L.ops = take(s.ops.size() * sizeof(DevOp));
+    L.maps = take(s.maps.size() * sizeof(DevMap));
+    L.items = take(s.items.size() * sizeof(LaunchItem));
+    L.tasks = take(s.tasks.size() * sizeof(ReduceTask));
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+BatchSchedule build_batch_schedule(const std::vector<const Circuit *> &members,
+                                   const std::vector<std::shared_ptr<const SweepPlan>> &plans, int amp,
+                                   const BatchTuning &tun, uint64_t arena_cap) {
+    BatchSchedule S;
+    const int nb = (int)members.size();
+    S.amp = amp;
+    S.plans = plans;
+    S.gate_base.resize(nb);
+    S.lraw_base.resize(nb);
+    std::vector<int64_t> pass_base(nb);
+    for (int b = 0; b < nb; ++b) {
+        const Circuit &c = *members[b];
+        const SweepPlan &p = *plans[b];
+        if (b == 0) {
+            S.m = p.m;
+            S.rb = p.rb;
+        } else if (p.m != S.m || p.rb != S.rb) {
+            fail(QNG_E_DEVICE, "batch schedule: members of one class differ in tile width (internal)");
+        }
+        pass_base[b] = (int64_t)S.passes.size();
+        const uint32_t op_base = (uint32_t)S.ops.size(), map_base = (uint32_t)S.maps.size();
+        S.gate_base[b] = S.mat_rows;
+        S.mat_rows += c.M;
+        S.lraw_base[b] = S.lraw_elems;
+        S.lraw_elems += (int64_t)c.P * c.P;
+        for (DevPass dp : p.dev_passes) {
+            dp.op_begin += op_base;
+            dp.map_load += map_base;
+            S.passes.push_back(dp);
+        }
+        for (DevOp op : p.dev_ops) {
+            if (op.type == OPC_XPOSE) op.aux += (int32_t)map_base;
+            if (op.gate >= 0) op.gate += (int32_t)S.gate_base[b];
+            S.ops.push_back(op);
+        }
+        S.maps.insert(S.maps.end(), p.dev_maps.begin(), p.dev_maps.end());
+        if (c.P == 1) S.singles.push_back(b);
+        S.elements += (int64_t)c.P * (c.P - 1) / 2;
+    }
+    if (S.lraw_elems > INT32_MAX) fail(QNG_E_INVALID_ARG, "batch too large: more than 2^31 metric entries");
+
+    // queue: members in increasing register size, then depth; columns in increasing s
+    std::vector<int> order(nb);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (members[a]->n != members[b]->n) return members[a]->n < members[b]->n;
+        return members[a]->P < members[b]->P;
+    });
+    std::vector<std::pair<int, int>> queue;
+    for (int b : order)
+        for (int col = 0; col < (int)plans[b]->cols.size(); ++col) queue.emplace_back(b, col);
+
+    struct Active {
+        int b, col;
+        size_t t;
+        uint64_t reg;
+    };
+    std::map<int, std::vector<uint64_t>> free_pairs;   // by register size (qubits)
+    uint64_t bump = 0, act_tiles = 0;
+    std::vector<Active> act;
+    size_t qi = 0;
+    const uint64_t target = (uint64_t)std::max(1, tun.target_tiles);
+    for (;;) {
+        BatchLaunch L{};
+        L.prep_begin = (uint32_t)S.preps.size();
+        while (qi < queue.size()) {
+            const int b = queue[qi].first, col = queue[qi].second;
+            const int n = members[b]->n;
+            const uint64_t tiles = uint64_t(1) << (n - S.m);
+            const uint64_t pair = 2 * ((uint64_t(1) << n) * (uint64_t)amp);
+            if (!act.empty() && act_tiles + tiles > target) break;
+            uint64_t reg;
+            std::vector<uint64_t> &fl = free_pairs[n];
+            if (!fl.empty()) {
+                reg = fl.back();
+                fl.pop_back();
+            } else if (act.empty() || bump + pair <= arena_cap) {
+                reg = bump;
+                bump += pair;
+            } else {
+                break;
+            }
+            S.preps.push_back(BatchPrep{b, col, reg});
+            act.push_back(Active{b, col, 0, reg});
+            act_tiles += tiles;
+            ++qi;
+        }
+        if (act.empty()) break;
+        L.n_preps = (uint32_t)S.preps.size() - L.prep_begin;
+        L.item_begin = (uint32_t)S.items.size();
+        L.task_begin = (uint32_t)S.tasks.size();
+        uint64_t poff = 0;
+        for (const Active &a : act) {
+            const SweepPlan &p = *plans[a.b];
+            const HostPass &hp = p.cols[a.col].passes[a.t];
+            const int n = members[a.b]->n;
+            const uint32_t tiles = 1u << (n - S.m);
+            LaunchItem it{};
+            it.tile_begin = L.total_tiles;
+            it.pass = (uint32_t)(pass_base[a.b] + p.col_pass_begin[a.col] + (int64_t)a.t);
+            it.ntiles = tiles;
+            it.partial_off = poff;
+            it.regA = (void *)(uintptr_t)a.reg;
+            it.regB = (void *)(uintptr_t)(a.reg + (uint64_t(1) << n) * (uint64_t)amp);
+            S.items.push_back(it);
+            ++L.n_items;
+            L.total_tiles += tiles;
+            for (size_t k = 0; k < hp.slot_dest.size(); ++k) {
+                S.tasks.push_back(ReduceTask{poff + (uint64_t)k * tiles, tiles,
+                                             (int32_t)(S.lraw_base[a.b] + hp.slot_dest[k])});
+                ++L.n_tasks;
+            }
+            poff += (uint64_t)hp.slot_dest.size() * tiles;
+        }
+        S.partial_elems = std::max(S.partial_elems, poff);
+        S.launches.push_back(L);
+        std::vector<Active> next;
+        next.reserve(act.size());
+        for (Active a : act) {
+            ++a.t;
+            if (a.t < plans[a.b]->cols[a.col].passes.size()) {
+                next.push_back(a);
+            } else {
+                const int n = members[a.b]->n;
+                free_pairs[n].push_back(a.reg);
+                act_tiles -= uint64_t(1) << (n - S.m);
+            }
+        }
+        act.swap(next);
+    }
+    S.arena_bytes = bump;
+    S.partial_elems += 16;
+    return S;
+}
+
+size_t batch_image_bytes(const BatchSchedule &s) { return image_layout(s).total; }
+
+void upload_batch_images(const BatchSchedule &s, const BatchDevice &d, hipStream_t st) {
+    const ImageLayout L = image_layout(s);
+    std::vector<LaunchItem> items = s.items;
+    for (LaunchItem &it : items) {
+        it.regA = d.arena + (uintptr_t)it.regA;
+        it.regB = d.arena + (uintptr_t)it.regB;
+    }
+    auto put = [&](size_t off, const void *src, size_t bytes) {
+        if (bytes) BCHECK(hipMemcpyAsync(d.images + off, src, bytes, hipMemcpyHostToDevice, st));
+    };
+    put(L.passes, s.passes.data(), s.passes.size() * sizeof(DevPass));
+    put(L.ops, s.ops.data(), s.ops.size() * sizeof(DevOp));
+    put(L.maps, s.maps.data(), s.maps.size() * sizeof(DevMap));
+    put(L.items, items.data(), items.size() * sizeof(LaunchItem));
+    put(L.tasks, s.tasks.data(), s.tasks.size() * sizeof(ReduceTask));
+    BCHECK(hipStreamSynchronize(st));   // `items` is released at return
+}
+
+int batch_final_pos(const Circuit &c) { return c.P ? c.rots[c.P - 1].pos : 0; }
+
+template <typename R>
+void enqueue_batch_metric(const BatchSchedule &s, const std::vector<const Circuit *> &members, const BatchDevice &d,
+                          bool f64_regs, hipStream_t st, std::vector<hipEvent_t> *events) {
+    const ImageLayout IL = image_layout(s);
+    const DevPass *passes = (const DevPass *)(d.images + IL.passes);
+    const DevOp *ops = (const DevOp *)(d.images + IL.ops);
+    const DevMap *maps = (const DevMap *)(d.images + IL.maps);
+    const LaunchItem *items = (const LaunchItem *)(d.images + IL.items);
+    const ReduceTask *tasks = (const ReduceTask *)(d.images + IL.tasks);
+    const int nb = (int)members.size();
+    std::vector<int> pos(nb, 0);
+    std::vector<char> started(nb, 0);
+
+    auto forward_to = [&](int b, int target) {
+        const Circuit &c = *members[b];
+        for (; pos[b] < target; ++pos[b]) {
+            const qng_gate &g = c.gates[pos[b]];
+            if (g.kind == QNG_CNOT) launch_cnot<R>(d.psi[b], nullptr, c.n, g.q0, g.q1, st);
+            else if (g.kind == QNG_CZ) launch_cz<R>(d.psi[b], nullptr, c.n, g.q0, g.q1, st);
+            else launch_apply_1q_tab<R>(d.psi[b], nullptr, c.n, g.q0, d.fwd_mats + (s.gate_base[b] + pos[b]) * 8, st);
+        }
+    };
+    auto start = [&](int b) {
+        if (started[b]) return;
+        started[b] = 1;
+        const Circuit &c = *members[b];
+        forward_to(b, c.rots[0].pos);
+        launch_pauli_prod<R>(d.psi[b], d.psi[b], c.n, c.rots[0].qubit, c.rots[0].axis, d.reduce_partials, d.traw[b],
+                             st);
+    };
+    for (int b : s.singles) start(b);
+    for (size_t li = 0; li < s.launches.size(); ++li) {
+        const BatchLaunch &L = s.launches[li];
+        for (uint32_t k = 0; k < L.n_preps; ++k) {
+            const BatchPrep &pr = s.preps[L.prep_begin + k];
+            const Circuit &c = *members[pr.member];
+            const int sidx = s.plans[pr.member]->cols[pr.col].s;
+            const Rot &rs = c.rots[sidx];
+            start(pr.member);
+            forward_to(pr.member, rs.pos);
+            launch_pauli_prod<R>(d.psi[pr.member], d.psi[pr.member], c.n, rs.qubit, rs.axis, d.reduce_partials,
+                                 d.traw[pr.member] + 2 * sidx, st);
+            char *lam = d.arena + pr.reg_off;
+            char *phi = lam + (size_t(1) << c.n) * (size_t)s.amp;
+            launch_seed<R>(d.psi[pr.member], lam, phi, c.n, rs.qubit, rs.axis, st);
+        }
+        if (events) BCHECK(hipEventRecord((*events)[2 * li], st));
+        launch_sweep_pass<R>(items + L.item_begin, (int)L.n_items, L.total_tiles, passes, ops, maps, d.adj_mats,
+                             d.adj_mats32, d.partials, s.m, s.rb, f64_regs, st);
+        if (events) BCHECK(hipEventRecord((*events)[2 * li + 1], st));
+        launch_reduce_tasks(tasks + L.task_begin, (int)L.n_tasks, d.partials, d.lraw, st);
+    }
+}
+
+template void enqueue_batch_metric<double>(const BatchSchedule &, const std::vector<const Circuit *> &,
+                                           const BatchDevice &, bool, hipStream_t, std::vector<hipEvent_t> *);
+template void enqueue_batch_metric<float>(const BatchSchedule &, const std::vector<const Circuit *> &,
+                                          const BatchDevice &, bool, hipStream_t, std::vector<hipEvent_t> *);
+
+}  // namespace qng

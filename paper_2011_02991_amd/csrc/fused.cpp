@@ -35,7 +35,8 @@ struct Group {
 
 size_t fused_scratch_bytes(const SweepPlan &plan, const FusedRun &fr, int M) {
     size_t b = 0;
-    b += align256((size_t)M * 64 + 64);                                  // matrix table
+    b += align256((size_t)M * 64 + 64);                                  // matrix table (FP64)
+    b += align256((size_t)M * 32 + 64);                                  // matrix table (FP32)
     b += align256(plan.dev_passes.size() * sizeof(DevPass) + 64);       // passes
     b += align256(plan.dev_ops.size() * sizeof(DevOp) + 64);            // ops
     b += align256(plan.dev_maps.size() * sizeof(DevMap) + 64);          // thread mappings
@@ -111,9 +112,11 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
         d[0] = m.a.real(); d[1] = m.a.imag(); d[2] = m.b.real(); d[3] = m.b.imag();
         d[4] = m.c.real(); d[5] = m.c.imag(); d[6] = m.d.real(); d[7] = m.d.imag();
     }
+    std::vector<float> mats32(mats.begin(), mats.end());
     char *p = buf.scratch;
     auto take = [&](size_t bytes) { char *o = p; p += align256(bytes + 64); return o; };
     double *d_mats = (double *)take(mats.size() * 8);
+    float *d_mats32 = (float *)take(mats32.size() * 4);
     DevPass *d_passes = (DevPass *)take(plan.dev_passes.size() * sizeof(DevPass));
     DevOp *d_ops = (DevOp *)take(plan.dev_ops.size() * sizeof(DevOp));
     DevMap *d_maps = (DevMap *)take(plan.dev_maps.size() * sizeof(DevMap));
@@ -122,7 +125,10 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
     double *d_partials = (double *)p;
     if ((size_t)(p - buf.scratch) + fr.partial_elems * 16 > buf.scratch_bytes)
         fail(QNG_E_DEVICE, "fused sweep: scratch too small (internal)");
-    if (!mats.empty()) FCHECK(hipMemcpyAsync(d_mats, mats.data(), mats.size() * 8, hipMemcpyHostToDevice, st));
+    if (!mats.empty()) {
+        FCHECK(hipMemcpyAsync(d_mats, mats.data(), mats.size() * 8, hipMemcpyHostToDevice, st));
+        FCHECK(hipMemcpyAsync(d_mats32, mats32.data(), mats32.size() * 4, hipMemcpyHostToDevice, st));
+    }
     if (!plan.dev_passes.empty())
         FCHECK(hipMemcpyAsync(d_passes, plan.dev_passes.data(), plan.dev_passes.size() * sizeof(DevPass),
                               hipMemcpyHostToDevice, st));
@@ -174,7 +180,7 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
             const Launch &L = launches[li];
             if (profile) FCHECK(hipEventRecord(ev[2 * li], st));
             launch_sweep_pass<R>(d_items + L.item_begin, (int)L.n_items, L.total_tiles, d_passes, d_ops, d_maps,
-                                 d_mats, d_partials, plan.m, plan.rb, f64_regs, st);
+                                 d_mats, d_mats32, d_partials, plan.m, plan.rb, f64_regs, st);
             if (profile) FCHECK(hipEventRecord(ev[2 * li + 1], st));
             launch_reduce_tasks(d_tasks + L.task_begin, (int)L.n_tasks, d_partials, buf.lraw, st);
             ++stats->sweep_launches;

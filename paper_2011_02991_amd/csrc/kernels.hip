@@ -96,6 +96,22 @@ __global__ void k_apply_1q(typename Cplx<R>::T *s0, typename Cplx<R>::T *s1, int
     }
 }
 
+// Same, with the matrix read from device memory (8 doubles, row-major re/im):
+// launches whose arguments do not depend on the angles can be captured once
+// and replayed with new matrices.
+template <typename R>
+__global__ void k_apply_1q_tab(typename Cplx<R>::T *s0, typename Cplx<R>::T *s1, int n, int q,
+                               const double *__restrict__ mt) {
+    const uint64_t npairs = uint64_t(1) << (n - 1);
+    const R ar = (R)mt[0], ai = (R)mt[1], br = (R)mt[2], bi = (R)mt[3];
+    const R cr = (R)mt[4], ci = (R)mt[5], dr = (R)mt[6], di = (R)mt[7];
+    for (uint64_t p = blockIdx.x * (uint64_t)kBlock + threadIdx.x; p < npairs; p += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t i0 = insert_zero(p, q), i1 = i0 | (uint64_t(1) << q);
+        mat_pair<R>(s0, i0, i1, ar, ai, br, bi, cr, ci, dr, di);
+        if (s1) mat_pair<R>(s1, i0, i1, ar, ai, br, bi, cr, ci, dr, di);
+    }
+}
+
 // CNOT(control c, target t): swap amplitudes (x, x ^ 2^t) for x with bit c set and bit t clear.
 template <typename R>
 __global__ void k_cnot(typename Cplx<R>::T *s0, typename Cplx<R>::T *s1, int n, int c, int t) {
@@ -287,6 +303,12 @@ template <typename R> void launch_apply_1q(void *s0, void *s1, int n, int q, con
     check_launch();
 }
 
+template <typename R> void launch_apply_1q_tab(void *s0, void *s1, int n, int q, const double *m_dev, hipStream_t st) {
+    hipLaunchKernelGGL(k_apply_1q_tab<R>, dim3(grid_for(uint64_t(1) << (n - 1))), dim3(kBlock), 0, st,
+                       (typename Cplx<R>::T *)s0, (typename Cplx<R>::T *)s1, n, q, m_dev);
+    check_launch();
+}
+
 template <typename R> void launch_cnot(void *s0, void *s1, int n, int c, int t, hipStream_t st) {
     hipLaunchKernelGGL(k_cnot<R>, dim3(grid_for(uint64_t(1) << (n - 2))), dim3(kBlock), 0, st,
                        (typename Cplx<R>::T *)s0, (typename Cplx<R>::T *)s1, n, c, t);
@@ -349,6 +371,7 @@ void launch_grad_from_raw(const double *graw, const int *param_of, int P, double
     template void launch_to_c128<R>(const void *, void *, int, hipStream_t);                                      \
     template void launch_copy<R>(const void *, void *, int, hipStream_t);                                         \
     template void launch_apply_1q<R>(void *, void *, int, int, const DevMat2 &, hipStream_t);                     \
+    template void launch_apply_1q_tab<R>(void *, void *, int, int, const double *, hipStream_t);                  \
     template void launch_cnot<R>(void *, void *, int, int, int, hipStream_t);                                     \
     template void launch_cz<R>(void *, void *, int, int, int, hipStream_t);                                       \
     template void launch_seed<R>(const void *, void *, void *, int, int, int, hipStream_t);                      \

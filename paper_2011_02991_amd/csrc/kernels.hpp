@@ -29,6 +29,8 @@ template <typename R> void launch_copy(const void *src, void *dst, int n, hipStr
 
 // Apply a 2x2 matrix on qubit q to one register (s1 == nullptr) or to two.
 template <typename R> void launch_apply_1q(void *s0, void *s1, int n, int q, const DevMat2 &m, hipStream_t st);
+// As launch_apply_1q, the matrix read from device memory (8 doubles: a, b, c, d as re, im).
+template <typename R> void launch_apply_1q_tab(void *s0, void *s1, int n, int q, const double *m_dev, hipStream_t st);
 template <typename R> void launch_cnot(void *s0, void *s1, int n, int control, int target, hipStream_t st);
 template <typename R> void launch_cz(void *s0, void *s1, int n, int a, int b, hipStream_t st);
 

@@ -457,6 +457,7 @@ SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int
                 if (op.type == OP_ZSUM) dp.has_zsum = 1;
                 if (op.type == OP_CNOT) has_cnot = true;
                 if (op.type == OP_XPOSE) op.aux += (int32_t)map_base;
+                op.type = device_opcode(op);
                 plan.dev_ops.push_back(op);
             }
             for (const DevMap &mp : hp.maps) plan.dev_maps.push_back(mp);
@@ -484,20 +485,60 @@ void SweepPlan::fill_info(qng_plan_info *out) const {
     out->small_n = n <= m ? 1 : 0;
 }
 
-const SweepPlan &SweepCache::get(const Circuit &c, int tile_qubits, int amp_bytes, int small, bool reg_f64) {
-    std::vector<int32_t> key = {c.n, c.M, c.P, tile_qubits, amp_bytes, small, reg_f64 ? 1 : 0};
+uint8_t device_opcode(const DevOp &op) {
+    const bool reg0 = op.b0 < kLocThread;
+    const bool thr0 = op.b0 != kLocBase && !reg0;
+    const int j = reg0 ? op.b0 : 0;
+    if (reg0 && j > 3) fail(QNG_E_DEVICE, "device op: register position out of range (internal)");
+    switch (op.type) {
+    case OP_ROT:
+    case OP_PRODROT:
+    case OP_PROD: {
+        if (!reg0) fail(QNG_E_DEVICE, "device op: X/Y operation off the registers (internal)");
+        const int base = op.type == OP_ROT ? OPC_ROT_X : op.type == OP_PRODROT ? OPC_PRODROT_X : OPC_PROD_X;
+        return (uint8_t)(base + (op.axis == 0 ? 0 : 4) + j);
+    }
+    case OP_PRODZ: return (uint8_t)(reg0 ? OPC_PRODZ_REG + j : thr0 ? OPC_PRODZ_THR : OPC_PRODZ_BASE);
+    case OP_DIAG: return (uint8_t)(reg0 ? OPC_DIAG_REG + j : thr0 ? OPC_DIAG_THR : OPC_DIAG_BASE);
+    case OP_PRODDIAG: return (uint8_t)(reg0 ? OPC_PRODDIAG_REG + j : thr0 ? OPC_PRODDIAG_THR : OPC_PRODDIAG_BASE);
+    case OP_CNOT: {
+        if (!reg0) fail(QNG_E_DEVICE, "device op: CNOT target off the registers (internal)");
+        if (op.b1 < kLocThread) {
+            if (op.b1 == op.b0 || op.b1 > 3) fail(QNG_E_DEVICE, "device op: bad CNOT control (internal)");
+            return (uint8_t)(OPC_CNOT_REG + 4 * j + op.b1);
+        }
+        return (uint8_t)((op.b1 == kLocBase ? OPC_CNOT_BASE : OPC_CNOT_THR) + j);
+    }
+    case OP_CZ: return OPC_CZ;
+    case OP_ZSUM: return OPC_ZSUM;
+    case OP_XPOSE: return OPC_XPOSE;
+    default: fail(QNG_E_DEVICE, "device op: unknown kind (internal)");
+    }
+    return 0;
+}
+
+void append_structure_key(const Circuit &c, std::vector<int32_t> &key) {
+    key.push_back(c.n);
+    key.push_back(c.M);
+    key.push_back(c.P);
     for (const qng_gate &g : c.gates) {
         key.push_back(g.kind);
         key.push_back(g.q0);
         key.push_back(g.q1);
         key.push_back(g.param >= 0 ? 1 : 0);
     }
+}
+
+std::shared_ptr<const SweepPlan> SweepCache::get_shared(const Circuit &c, int tile_qubits, int amp_bytes, int small,
+                                                        bool reg_f64) {
+    std::vector<int32_t> key = {tile_qubits, amp_bytes, small, reg_f64 ? 1 : 0};
+    append_structure_key(c, key);
     auto it = plans.find(key);
-    if (it != plans.end()) return *it->second;
-    if (plans.size() > 16) plans.clear();
+    if (it != plans.end()) return it->second;
+    if (plans.size() >= 256) plans.clear();
     auto p = std::make_shared<SweepPlan>(build_sweep_plan(c, tile_qubits, amp_bytes, small, reg_f64));
     plans[key] = p;
-    return *p;
+    return p;
 }
 
 FusedRun fused_config(const SweepPlan &plan, int requested_streams, size_t state_bytes, size_t free_bytes) {

@@ -56,6 +56,35 @@ enum : uint8_t {
     OP_XPOSE = 9      // exchange through LDS to the thread mapping `aux`
 };
 
+// Device op codes.  In the flattened device images (SweepPlan::dev_ops and
+// the batch images) DevOp::type holds one of these codes instead of the OP_*
+// kind: the register position, the Pauli axis and where a control or a Z bit
+// lives are resolved on the host, so the kernel runs one straight-line path
+// per code.  "+ j" is the register position (< 4).
+enum : uint8_t {
+    OPC_ROT_X = 0,            // + j
+    OPC_ROT_Y = 4,            // + j
+    OPC_PRODROT_X = 8,        // + j
+    OPC_PRODROT_Y = 12,       // + j
+    OPC_PROD_X = 16,          // + j
+    OPC_PROD_Y = 20,          // + j
+    OPC_PRODZ_REG = 24,       // + j
+    OPC_PRODZ_THR = 28,       // Z bit on thread position b0 & 15
+    OPC_PRODZ_BASE = 29,      // Z bit of the tile base (qubit q0)
+    OPC_DIAG_REG = 32,        // + j
+    OPC_DIAG_THR = 36,
+    OPC_DIAG_BASE = 37,
+    OPC_PRODDIAG_REG = 40,    // + j
+    OPC_PRODDIAG_THR = 44,
+    OPC_PRODDIAG_BASE = 45,
+    OPC_CNOT_REG = 48,        // + 4 j + k: target register position j, control register position k
+    OPC_CNOT_THR = 64,        // + j: control on thread position b1 & 15
+    OPC_CNOT_BASE = 68,       // + j: control = bit q0 of the tile base
+    OPC_CZ = 72,
+    OPC_ZSUM = 73,
+    OPC_XPOSE = 74
+};
+
 // Location of a local bit in the current thread mapping: a register position
 // (< kLocThread), a thread position (kLocThread | t), or a bit of the tile base
 // (kLocBase: qubit given separately).
@@ -90,6 +119,9 @@ struct DevMap {
     uint8_t pos[16];
 };
 static_assert(sizeof(DevPass) == 64, "DevPass layout");
+
+// Device op code of a planned operation (OPC_* above).
+uint8_t device_opcode(const DevOp &op);
 static_assert(sizeof(DevOp) == 16, "DevOp layout");
 static_assert(sizeof(DevMap) == 16, "DevMap layout");
 
@@ -135,8 +167,17 @@ int default_tile_qubits(int n, int amp_bytes, bool reg_f64);
 
 struct SweepCache {
     std::map<std::vector<int32_t>, std::shared_ptr<SweepPlan>> plans;
-    const SweepPlan &get(const Circuit &c, int tile_qubits, int amp_bytes, int small, bool reg_f64);
+    const SweepPlan &get(const Circuit &c, int tile_qubits, int amp_bytes, int small, bool reg_f64) {
+        return *get_shared(c, tile_qubits, amp_bytes, small, reg_f64);
+    }
+    // The plan stays alive while the caller holds the pointer, even if the
+    // cache evicts it.
+    std::shared_ptr<const SweepPlan> get_shared(const Circuit &c, int tile_qubits, int amp_bytes, int small,
+                                                bool reg_f64);
 };
+
+// Structure key of a circuit (gate kinds, qubits, which gates are rotations).
+void append_structure_key(const Circuit &c, std::vector<int32_t> &key);
 
 // Device-side launch item: one pass of one column over all its tiles.
 struct LaunchItem {  // 48 bytes
@@ -165,10 +206,12 @@ struct FusedRun {
 FusedRun fused_config(const SweepPlan &plan, int requested_streams, size_t state_bytes, size_t free_bytes);
 
 // Kernel launchers (sweep_kernels.hip).
+// mats64 / mats32: the adjoint gate matrices (8 values per gate position) in
+// FP64 and FP32; the kernel reads the table of its register precision.
 template <typename R>
 void launch_sweep_pass(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
-                       const DevOp *ops, const DevMap *maps, const double *mats, double *partials, int m, int rb,
-                       bool f64_registers, hipStream_t st);
+                       const DevOp *ops, const DevMap *maps, const double *mats64, const float *mats32,
+                       double *partials, int m, int rb, bool f64_registers, hipStream_t st);
 void launch_reduce_tasks(const ReduceTask *tasks, int n_tasks, const double *partials, double *results,
                          hipStream_t st);
 

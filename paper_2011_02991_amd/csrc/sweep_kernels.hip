@@ -3,10 +3,15 @@
 // One work-group of 256 threads (4 wave64) owns one tile: the 2^m amplitudes
 // of lambda (A) and phi (B) whose indices agree outside the pass's m tile
 // qubits.  The tile lives in registers: every thread holds T = 2^RB amplitudes
-// of each register, in FP64 whatever the storage precision (complex64 states
-// are widened at the load and rounded once at the store of each pass).  A thread mapping says which local bits are "register
-// bits" (the thread's own T amplitudes differ in them) and which are "thread
-// bits" (bits of the thread index).
+// of each register, in the register precision CT (FP64 for complex128
+// storage; FP32 or FP64 for complex64 storage).  A thread mapping says which
+// local bits are "register bits" (the thread's own T amplitudes differ in
+// them) and which are "thread bits" (bits of the thread index).
+//
+// The operations of a pass are interpreted from a list of device op codes
+// (sweep.hpp): the register position, the Pauli axis and where a control or a
+// Z bit lives are resolved on the host, so every code runs one straight-line
+// path with its register indices fixed at compile time.
 //
 //  * Load: amplitudes go from HBM straight into registers under the pass's
 //    load mapping, whose lowest thread bits are the lowest qubits, so the 64
@@ -66,40 +71,176 @@ __device__ __forceinline__ void row_store(double2 *red, int slot, int tid, doubl
     if ((tid & 15) == 15) red[slot * kRows + (tid >> 4)] = make_double2(a, b);
 }
 
-// The tile is kept as four scalar arrays per thread: real and imaginary parts
-// of lambda (A) and phi (B), T values each (scalar arrays stay in VGPRs).
+// The tile is kept as four short vectors per thread: real and imaginary parts
+// of lambda (A) and phi (B), T values each, indexed only by compile-time
+// constants.  One vector per part (rather than T scalars) lets the register
+// allocator carry the tile through the op loop without copies at every branch
+// of the dispatch.
 template <typename CT, int T>
 struct Regs {
-    CT ar[T], ai[T], br[T], bi[T];
+    typedef CT V __attribute__((ext_vector_type(T)));
+    V ar, ai, br, bi;
 };
 
-// conj(x) * y accumulated in FP64
-template <typename R>
-__device__ __forceinline__ void cmac(double &sr, double &si, R xr_, R xi_, R yr_, R yi_) {
-    const double xr = xr_, xi = xi_, yr = yr_, yi = yi_;
-    sr += xr * yr + xi * yi;
-    si += xr * yi - xi * yr;
+// 2x2 complex matrix entries of the gate table in the register precision
+// (row-major: a, b / c, d as re, im).
+template <typename CT>
+__device__ __forceinline__ CT mat_entry(const CT *__restrict__ mt, int gate, int k) {
+    return mt[(size_t)gate * 8 + k];
 }
 
-// 2x2 complex matrix [[a, b], [c, d]] as scalars
-template <typename R>
-struct M2 {
-    R ar, ai, br, bi, cr, ci, dr, di;
-};
+// ------------------------------------------------------- inner products
+//
+// Every product is taken in FP64 from the register values (exact for FP32
+// registers) and accumulated in FP64 with explicit fused multiply-adds; the
+// first term of a chain is a plain product, so no chain starts from zero.
 
-template <typename R>
-__device__ __forceinline__ M2<R> load_m2(const double *p) {
-    return M2<R>{(R)p[0], (R)p[1], (R)p[2], (R)p[3], (R)p[4], (R)p[5], (R)p[6], (R)p[7]};
+// acc = (first ? 0 : acc) + conj(a) b, with signs sa on the whole term
+template <bool FIRST, bool NEG>
+__device__ __forceinline__ void cfma(double &r, double &i, double ar, double ai, double br, double bi) {
+    const double s = NEG ? -1.0 : 1.0;
+    if (FIRST) {
+        r = (s * ar) * br;
+        i = (s * ar) * bi;
+    } else {
+        r = __fma_rn(s * ar, br, r);
+        i = __fma_rn(s * ar, bi, i);
+    }
+    r = __fma_rn(s * ai, bi, r);
+    i = __fma_rn(-s * ai, br, i);
 }
 
-// 2x2 complex matrix on the pair (x0, x1)
-template <typename R>
-__device__ __forceinline__ void mat_apply(const M2<R> m, R &x0r, R &x0i, R &x1r, R &x1i) {
-    const R ur = x0r, ui = x0i, vr = x1r, vi = x1i;
-    x0r = m.ar * ur - m.ai * ui + m.br * vr - m.bi * vi;
-    x0i = m.ar * ui + m.ai * ur + m.br * vi + m.bi * vr;
-    x1r = m.cr * ur - m.ci * ui + m.dr * vr - m.di * vi;
-    x1i = m.cr * ui + m.ci * ur + m.dr * vi + m.di * vr;
+// X: sum over pairs of conj(a0) b1 + conj(a1) b0.
+// Y: i * sum over pairs of (conj(a1) b0 - conj(a0) b1).
+// (<A|X|B> and <A|Y|B> on register bit J; Y = [[0, -i], [i, 0]].)
+template <int J, int AX, int T, typename CT>
+__device__ __forceinline__ void prod_xy(const Regs<CT, T> &x, double &pr, double &pi) {
+    double r0 = 0.0, i0 = 0.0, r1 = 0.0, i1 = 0.0;
+    int pair = 0;
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        if (i & (1 << J)) continue;
+        const int k = i | (1 << J);
+        const double a0r = x.ar[i], a0i = x.ai[i], a1r = x.ar[k], a1i = x.ai[k];
+        const double b0r = x.br[i], b0i = x.bi[i], b1r = x.br[k], b1i = x.bi[k];
+        double &r = (pair & 1) ? r1 : r0;
+        double &m = (pair & 1) ? i1 : i0;
+        if (pair < 2) cfma<true, AX == 1>(r, m, a0r, a0i, b1r, b1i);
+        else cfma<false, AX == 1>(r, m, a0r, a0i, b1r, b1i);
+        cfma<false, false>(r, m, a1r, a1i, b0r, b0i);
+        ++pair;
+    }
+    const double sr = (T >= 4) ? r0 + r1 : r0, si = (T >= 4) ? i0 + i1 : i0;
+    if (AX == 0) {
+        pr = sr;
+        pi = si;
+    } else {
+        pr = -si;
+        pi = sr;
+    }
+}
+
+// Z on register bit J: sum_i (-1)^{bit J of i} conj(a_i) b_i
+template <int J, int T, typename CT>
+__device__ __forceinline__ void prod_z_reg(const Regs<CT, T> &x, double &pr, double &pi) {
+    double r0 = 0.0, i0 = 0.0, r1 = 0.0, i1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        double &r = (i & 1) ? r1 : r0;
+        double &m = (i & 1) ? i1 : i0;
+        const bool neg = (i >> J) & 1;
+        if (i < 2) {
+            if (neg) cfma<true, true>(r, m, x.ar[i], x.ai[i], x.br[i], x.bi[i]);
+            else cfma<true, false>(r, m, x.ar[i], x.ai[i], x.br[i], x.bi[i]);
+        } else {
+            if (neg) cfma<false, true>(r, m, x.ar[i], x.ai[i], x.br[i], x.bi[i]);
+            else cfma<false, false>(r, m, x.ar[i], x.ai[i], x.br[i], x.bi[i]);
+        }
+    }
+    pr = (T >= 2) ? r0 + r1 : r0;
+    pi = (T >= 2) ? i0 + i1 : i0;
+}
+
+// sum_i conj(a_i) b_i (the caller applies a sign common to all registers)
+template <int T, typename CT>
+__device__ __forceinline__ void prod_plain(const Regs<CT, T> &x, double &pr, double &pi) {
+    double r0 = 0.0, i0 = 0.0, r1 = 0.0, i1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        double &r = (i & 1) ? r1 : r0;
+        double &m = (i & 1) ? i1 : i0;
+        if (i < 2) cfma<true, false>(r, m, x.ar[i], x.ai[i], x.br[i], x.bi[i]);
+        else cfma<false, false>(r, m, x.ar[i], x.ai[i], x.br[i], x.bi[i]);
+    }
+    pr = (T >= 2) ? r0 + r1 : r0;
+    pi = (T >= 2) ? i0 + i1 : i0;
+}
+
+// ------------------------------------------------------- gates on registers
+
+// Adjoint X/Y rotation on the pairs of register bit J.  RX adjoint
+// [[c, -is], [-is, c]] and RY adjoint [[c, -s], [s, c]] have exact zeros, so
+// each output is two products; the table entries used are (a_re, b_im, c_im,
+// d_re) for X and (a_re, b_re, c_re, d_re) for Y.
+template <int J, int AX, int T, typename CT>
+__device__ __forceinline__ void rot_xy(Regs<CT, T> &x, CT m0, CT m1, CT m2, CT m3) {
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        if (i & (1 << J)) continue;
+        const int k = i | (1 << J);
+        if (AX == 0) {
+            CT ur = x.ar[i], ui = x.ai[i], vr = x.ar[k], vi = x.ai[k];
+            x.ar[i] = m0 * ur - m1 * vi;
+            x.ai[i] = m0 * ui + m1 * vr;
+            x.ar[k] = m3 * vr - m2 * ui;
+            x.ai[k] = m3 * vi + m2 * ur;
+            ur = x.br[i]; ui = x.bi[i]; vr = x.br[k]; vi = x.bi[k];
+            x.br[i] = m0 * ur - m1 * vi;
+            x.bi[i] = m0 * ui + m1 * vr;
+            x.br[k] = m3 * vr - m2 * ui;
+            x.bi[k] = m3 * vi + m2 * ur;
+        } else {
+            CT ur = x.ar[i], ui = x.ai[i], vr = x.ar[k], vi = x.ai[k];
+            x.ar[i] = m0 * ur + m1 * vr;
+            x.ai[i] = m0 * ui + m1 * vi;
+            x.ar[k] = m2 * ur + m3 * vr;
+            x.ai[k] = m2 * ui + m3 * vi;
+            ur = x.br[i]; ui = x.bi[i]; vr = x.br[k]; vi = x.bi[k];
+            x.br[i] = m0 * ur + m1 * vr;
+            x.bi[i] = m0 * ui + m1 * vi;
+            x.br[k] = m2 * ur + m3 * vr;
+            x.bi[k] = m2 * ui + m3 * vi;
+        }
+    }
+}
+
+// x <- f x for amplitude i of both registers (complex product)
+template <int T, typename CT>
+__device__ __forceinline__ void cmul_at(Regs<CT, T> &x, int i, CT fr, CT fi) {
+    CT ur = x.ar[i], ui = x.ai[i];
+    x.ar[i] = fr * ur - fi * ui;
+    x.ai[i] = fr * ui + fi * ur;
+    ur = x.br[i];
+    ui = x.bi[i];
+    x.br[i] = fr * ur - fi * ui;
+    x.bi[i] = fr * ui + fi * ur;
+}
+
+// RZ adjoint diag(d0, d1) on register bit J
+template <int J, int T, typename CT>
+__device__ __forceinline__ void diag_reg(Regs<CT, T> &x, CT d0r, CT d0i, CT d1r, CT d1i) {
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        const bool one = (i >> J) & 1;
+        cmul_at<T, CT>(x, i, one ? d1r : d0r, one ? d1i : d0i);
+    }
+}
+
+// one factor for every register (bit held by the thread index or the tile base)
+template <int T, typename CT>
+__device__ __forceinline__ void diag_all(Regs<CT, T> &x, CT fr, CT fi) {
+#pragma unroll
+    for (int i = 0; i < T; ++i) cmul_at<T, CT>(x, i, fr, fi);
 }
 
 // value select (by-value operands keep the choice on registers, not on addresses)
@@ -108,120 +249,36 @@ __device__ __forceinline__ R sel(bool c, R a, R b) {
     return c ? a : b;
 }
 
-template <typename R>
-__device__ __forceinline__ void cmul(R &xr, R &xi, R fr, R fi) {
-    const R ur = xr, ui = xi;
-    xr = fr * ur - fi * ui;
-    xi = fr * ui + fi * ur;
+// CNOT adjoint (itself) with target register bit J and control register bit K:
+// a fixed permutation of the registers.
+template <int J, int K, int T, typename CT>
+__device__ __forceinline__ void cnot_reg(Regs<CT, T> &x) {
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        if ((i & (1 << J)) || !(i & (1 << K))) continue;
+        const int k = i | (1 << J);
+        CT t;
+        t = x.ar[i]; x.ar[i] = x.ar[k]; x.ar[k] = t;
+        t = x.ai[i]; x.ai[i] = x.ai[k]; x.ai[k] = t;
+        t = x.br[i]; x.br[i] = x.br[k]; x.br[k] = t;
+        t = x.bi[i]; x.bi[i] = x.bi[k]; x.bi[k] = t;
+    }
 }
 
-// ---------------------------------------------------------- register-bit ops
-
-// <A|sigma|B> over the pairs of register bit J (a* meaning conj(a)):
-//   X: a0*b1 + a1*b0;   Y: i (a1*b0 - a0*b1).
-// The pair loop accumulates S1 = sum a0*b1 and S2 = sum a1*b0 for either axis
-// (no branch on the axis inside the loop); the axis picks the combination.
+// CNOT with target register bit J and a control common to all registers of
+// the thread (thread bit or tile base): conditional swap of every pair.
 template <int J, int T, typename CT>
-__device__ __forceinline__ void prod_bit(int axis, const Regs<CT, T> &x, double &pr, double &pi) {
-    double s1r = 0.0, s1i = 0.0, s2r = 0.0, s2i = 0.0;
+__device__ __forceinline__ void cnot_cond(Regs<CT, T> &x, bool c) {
 #pragma unroll
     for (int i = 0; i < T; ++i) {
         if (i & (1 << J)) continue;
         const int k = i | (1 << J);
-        cmac(s1r, s1i, x.ar[i], x.ai[i], x.br[k], x.bi[k]);
-        cmac(s2r, s2i, x.ar[k], x.ai[k], x.br[i], x.bi[i]);
-    }
-    const bool ax = axis == 0;
-    pr += sel(ax, s1r + s2r, s1i - s2i);
-    pi += sel(ax, s1i + s2i, s2r - s1r);
-}
-
-// Adjoint rotation on the pairs of register bit J.  The matrices of RX and RY
-// adjoints have exact zeros (RX: real diagonal, imaginary off-diagonal; RY:
-// real), so each output is two products instead of four.
-template <int J, int T, typename CT>
-__device__ __forceinline__ void rot_bit(int axis, Regs<CT, T> &x, const M2<CT> m) {
-    if (axis == 0) {
-#pragma unroll
-        for (int i = 0; i < T; ++i) {
-            if (i & (1 << J)) continue;
-            const int k = i | (1 << J);
-            CT ur = x.ar[i], ui = x.ai[i], vr = x.ar[k], vi = x.ai[k];
-            x.ar[i] = m.ar * ur - m.bi * vi;
-            x.ai[i] = m.ar * ui + m.bi * vr;
-            x.ar[k] = m.dr * vr - m.ci * ui;
-            x.ai[k] = m.dr * vi + m.ci * ur;
-            ur = x.br[i]; ui = x.bi[i]; vr = x.br[k]; vi = x.bi[k];
-            x.br[i] = m.ar * ur - m.bi * vi;
-            x.bi[i] = m.ar * ui + m.bi * vr;
-            x.br[k] = m.dr * vr - m.ci * ui;
-            x.bi[k] = m.dr * vi + m.ci * ur;
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < T; ++i) {
-            if (i & (1 << J)) continue;
-            const int k = i | (1 << J);
-            CT ur = x.ar[i], ui = x.ai[i], vr = x.ar[k], vi = x.ai[k];
-            x.ar[i] = m.ar * ur + m.br * vr;
-            x.ai[i] = m.ar * ui + m.br * vi;
-            x.ar[k] = m.cr * ur + m.dr * vr;
-            x.ai[k] = m.cr * ui + m.dr * vi;
-            ur = x.br[i]; ui = x.bi[i]; vr = x.br[k]; vi = x.bi[k];
-            x.br[i] = m.ar * ur + m.br * vr;
-            x.bi[i] = m.ar * ui + m.br * vi;
-            x.br[k] = m.cr * ur + m.dr * vr;
-            x.bi[k] = m.cr * ui + m.dr * vi;
-        }
-    }
-}
-
-// swap the pair of register bit J where the control holds; ctrl has bit i set
-// when register i's control value is 1
-template <int J, int T, typename CT>
-__device__ __forceinline__ void cnot_bit(Regs<CT, T> &x, uint32_t ctrl) {
-#pragma unroll
-    for (int i = 0; i < T; ++i) {
-        if (i & (1 << J)) continue;
-        const int k = i | (1 << J);
-        const bool c = (ctrl >> i) & 1u;
         const CT a0r = x.ar[i], a0i = x.ai[i], a1r = x.ar[k], a1i = x.ai[k];
         const CT b0r = x.br[i], b0i = x.bi[i], b1r = x.br[k], b1i = x.bi[k];
         x.ar[i] = sel(c, a1r, a0r); x.ar[k] = sel(c, a0r, a1r);
         x.ai[i] = sel(c, a1i, a0i); x.ai[k] = sel(c, a0i, a1i);
         x.br[i] = sel(c, b1r, b0r); x.br[k] = sel(c, b0r, b1r);
         x.bi[i] = sel(c, b1i, b0i); x.bi[k] = sel(c, b0i, b1i);
-    }
-}
-
-template <int J, int T, typename CT>
-__device__ __forceinline__ void rot_prod_bit(int type, int axis, Regs<CT, T> &x, const M2<CT> mm, double &pr,
-                                             double &pi) {
-    if (type != OP_ROT) prod_bit<J, T, CT>(axis, x, pr, pi);
-    if (type != OP_PROD) rot_bit<J, T, CT>(axis, x, mm);
-}
-
-// Dispatch a runtime register position j to its template instance.
-template <int RB, int T, typename CT>
-__device__ __forceinline__ void rot_prod_at(int j, int type, int axis, Regs<CT, T> &x, const M2<CT> mm, double &pr,
-                                            double &pi) {
-    switch (j) {
-    case 0: rot_prod_bit<0, T, CT>(type, axis, x, mm, pr, pi); break;
-    case 1: if constexpr (RB > 1) rot_prod_bit<1, T, CT>(type, axis, x, mm, pr, pi); break;
-    case 2: if constexpr (RB > 2) rot_prod_bit<2, T, CT>(type, axis, x, mm, pr, pi); break;
-    case 3: if constexpr (RB > 3) rot_prod_bit<3, T, CT>(type, axis, x, mm, pr, pi); break;
-    default: break;
-    }
-}
-
-template <int RB, int T, typename CT>
-__device__ __forceinline__ void cnot_at(int j, Regs<CT, T> &x, uint32_t ctrl) {
-    switch (j) {
-    case 0: cnot_bit<0, T, CT>(x, ctrl); break;
-    case 1: if constexpr (RB > 1) cnot_bit<1, T, CT>(x, ctrl); break;
-    case 2: if constexpr (RB > 2) cnot_bit<2, T, CT>(x, ctrl); break;
-    case 3: if constexpr (RB > 3) cnot_bit<3, T, CT>(x, ctrl); break;
-    default: break;
     }
 }
 
@@ -282,7 +339,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
                                                         const DevPass *__restrict__ passes,
                                                         const DevOp *__restrict__ ops,
                                                         const DevMap *__restrict__ maps,
-                                                        const double *__restrict__ mats,
+                                                        const void *__restrict__ mats,
                                                         double2 *__restrict__ partials) {
     constexpr int T = 1 << RB;
     using C = typename Amp<R>::T;
@@ -343,9 +400,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
     // plain tile sum <A|B>_tile for Z inner products on qubits outside the tile
     double Sr = 0.0, Si = 0.0;
     if (pp->has_zsum) {
-        double sr = 0.0, si = 0.0;
-#pragma unroll
-        for (int i = 0; i < T; ++i) cmac(sr, si, x.ar[i], x.ai[i], x.br[i], x.bi[i]);
+        double sr, si;
+        prod_plain<T, CT>(x, sr, si);
         row_store(zs, 0, tid, sr, si);
         __syncthreads();
         for (int w = 0; w < kRows; ++w) {
@@ -354,46 +410,122 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
         }
     }
 
-    // ---- operations
+    // ---- operations: one straight-line path per device op code
+    const CT *__restrict__ mt = (const CT *)mats;
     const int n_ops = (int)pp->n_ops;
     const DevOp *op_ptr = ops + pp->op_begin;
     for (int oi = 0; oi < n_ops; ++oi) {
         const DevOp op = op_ptr[oi];
-        const int type = op.type;
-        if (type == OP_ROT || type == OP_PRODROT || type == OP_PROD) {
-            const M2<CT> mm = type != OP_PROD ? load_m2<CT>(mats + (size_t)op.gate * 8) : M2<CT>{};
-            double pr = 0.0, pi = 0.0;
-            rot_prod_at<RB, T, CT>(op.b0, type, op.axis, x, mm, pr, pi);
-            if (type != OP_ROT) row_store(red, op.slot, tid, pr, pi);
-        } else if (type == OP_DIAG || type == OP_PRODZ || type == OP_PRODDIAG) {
-            const uint32_t ones = loc_mask<T>(op.b0, op.q0, tid, base);
-            if (type != OP_DIAG) {
-                double pr = 0.0, pi = 0.0;
-#pragma unroll
-                for (int i = 0; i < T; ++i) {
-                    double tr = 0.0, ti = 0.0;
-                    cmac(tr, ti, x.ar[i], x.ai[i], x.br[i], x.bi[i]);
-                    const double sg = ((ones >> i) & 1u) ? -1.0 : 1.0;
-                    pr += sg * tr;
-                    pi += sg * ti;
-                }
-                row_store(red, op.slot, tid, pr, pi);
+        switch (op.type) {
+#define QNG_REG_CASES(J)                                                                                     \
+        case OPC_ROT_X + J:                                                                                  \
+            if constexpr (J < RB)                                                                            \
+                rot_xy<J, 0, T, CT>(x, mat_entry(mt, op.gate, 0), mat_entry(mt, op.gate, 3),                \
+                                    mat_entry(mt, op.gate, 5), mat_entry(mt, op.gate, 6));                   \
+            break;                                                                                           \
+        case OPC_ROT_Y + J:                                                                                  \
+            if constexpr (J < RB)                                                                            \
+                rot_xy<J, 1, T, CT>(x, mat_entry(mt, op.gate, 0), mat_entry(mt, op.gate, 2),                \
+                                    mat_entry(mt, op.gate, 4), mat_entry(mt, op.gate, 6));                   \
+            break;                                                                                           \
+        case OPC_PRODROT_X + J:                                                                              \
+            if constexpr (J < RB) {                                                                          \
+                double pr, pi;                                                                               \
+                prod_xy<J, 0, T, CT>(x, pr, pi);                                                             \
+                rot_xy<J, 0, T, CT>(x, mat_entry(mt, op.gate, 0), mat_entry(mt, op.gate, 3),                \
+                                    mat_entry(mt, op.gate, 5), mat_entry(mt, op.gate, 6));                   \
+                row_store(red, op.slot, tid, pr, pi);                                                        \
+            }                                                                                                \
+            break;                                                                                           \
+        case OPC_PRODROT_Y + J:                                                                              \
+            if constexpr (J < RB) {                                                                          \
+                double pr, pi;                                                                               \
+                prod_xy<J, 1, T, CT>(x, pr, pi);                                                             \
+                rot_xy<J, 1, T, CT>(x, mat_entry(mt, op.gate, 0), mat_entry(mt, op.gate, 2),                \
+                                    mat_entry(mt, op.gate, 4), mat_entry(mt, op.gate, 6));                   \
+                row_store(red, op.slot, tid, pr, pi);                                                        \
+            }                                                                                                \
+            break;                                                                                           \
+        case OPC_PROD_X + J:                                                                                 \
+            if constexpr (J < RB) {                                                                          \
+                double pr, pi;                                                                               \
+                prod_xy<J, 0, T, CT>(x, pr, pi);                                                             \
+                row_store(red, op.slot, tid, pr, pi);                                                        \
+            }                                                                                                \
+            break;                                                                                           \
+        case OPC_PROD_Y + J:                                                                                 \
+            if constexpr (J < RB) {                                                                          \
+                double pr, pi;                                                                               \
+                prod_xy<J, 1, T, CT>(x, pr, pi);                                                             \
+                row_store(red, op.slot, tid, pr, pi);                                                        \
+            }                                                                                                \
+            break;                                                                                           \
+        case OPC_PRODZ_REG + J:                                                                              \
+            if constexpr (J < RB) {                                                                          \
+                double pr, pi;                                                                               \
+                prod_z_reg<J, T, CT>(x, pr, pi);                                                             \
+                row_store(red, op.slot, tid, pr, pi);                                                        \
+            }                                                                                                \
+            break;                                                                                           \
+        case OPC_DIAG_REG + J:                                                                               \
+            if constexpr (J < RB)                                                                            \
+                diag_reg<J, T, CT>(x, mat_entry(mt, op.gate, 0), mat_entry(mt, op.gate, 1),                 \
+                                   mat_entry(mt, op.gate, 6), mat_entry(mt, op.gate, 7));                    \
+            break;                                                                                           \
+        case OPC_PRODDIAG_REG + J:                                                                           \
+            if constexpr (J < RB) {                                                                          \
+                double pr, pi;                                                                               \
+                prod_z_reg<J, T, CT>(x, pr, pi);                                                             \
+                diag_reg<J, T, CT>(x, mat_entry(mt, op.gate, 0), mat_entry(mt, op.gate, 1),                 \
+                                   mat_entry(mt, op.gate, 6), mat_entry(mt, op.gate, 7));                    \
+                row_store(red, op.slot, tid, pr, pi);                                                        \
+            }                                                                                                \
+            break;                                                                                           \
+        case OPC_CNOT_THR + J:                                                                               \
+            if constexpr (J < RB) cnot_cond<J, T, CT>(x, (tid >> (op.b1 & 15)) & 1);                        \
+            break;                                                                                           \
+        case OPC_CNOT_BASE + J:                                                                              \
+            if constexpr (J < RB) {                                                                          \
+                if ((base >> op.q0) & 1u) cnot_cond<J, T, CT>(x, true);                                     \
+            }                                                                                                \
+            break;
+#define QNG_CNOT_REG_CASE(J, K)                                                                              \
+        case OPC_CNOT_REG + 4 * J + K:                                                                       \
+            if constexpr (J < RB && K < RB && J != K) cnot_reg<J, K, T, CT>(x);                             \
+            break;
+        QNG_REG_CASES(0)
+        QNG_REG_CASES(1)
+        QNG_REG_CASES(2)
+        QNG_REG_CASES(3)
+        QNG_CNOT_REG_CASE(0, 1) QNG_CNOT_REG_CASE(0, 2) QNG_CNOT_REG_CASE(0, 3)
+        QNG_CNOT_REG_CASE(1, 0) QNG_CNOT_REG_CASE(1, 2) QNG_CNOT_REG_CASE(1, 3)
+        QNG_CNOT_REG_CASE(2, 0) QNG_CNOT_REG_CASE(2, 1) QNG_CNOT_REG_CASE(2, 3)
+        QNG_CNOT_REG_CASE(3, 0) QNG_CNOT_REG_CASE(3, 1) QNG_CNOT_REG_CASE(3, 2)
+#undef QNG_REG_CASES
+#undef QNG_CNOT_REG_CASE
+        case OPC_PRODZ_THR:
+        case OPC_PRODZ_BASE:
+        case OPC_PRODDIAG_THR:
+        case OPC_PRODDIAG_BASE:
+        case OPC_DIAG_THR:
+        case OPC_DIAG_BASE: {
+            // the Z bit is common to all registers of the thread
+            const bool thr = op.type == OPC_PRODZ_THR || op.type == OPC_PRODDIAG_THR || op.type == OPC_DIAG_THR;
+            const bool one = thr ? ((tid >> (op.b0 & 15)) & 1) : ((base >> op.q0) & 1u);
+            if (op.type != OPC_DIAG_THR && op.type != OPC_DIAG_BASE) {
+                double pr, pi;
+                prod_plain<T, CT>(x, pr, pi);
+                const double sg = one ? -1.0 : 1.0;
+                row_store(red, op.slot, tid, sg * pr, sg * pi);
             }
-            if (type != OP_PRODZ) {
-                const CT d0r = (CT)mats[(size_t)op.gate * 8 + 0], d0i = (CT)mats[(size_t)op.gate * 8 + 1];
-                const CT d1r = (CT)mats[(size_t)op.gate * 8 + 6], d1i = (CT)mats[(size_t)op.gate * 8 + 7];
-#pragma unroll
-                for (int i = 0; i < T; ++i) {
-                    const bool one = (ones >> i) & 1u;
-                    const CT fr = sel(one, d1r, d0r), fi = sel(one, d1i, d0i);
-                    cmul<CT>(x.ar[i], x.ai[i], fr, fi);
-                    cmul<CT>(x.br[i], x.bi[i], fr, fi);
-                }
+            if (op.type != OPC_PRODZ_THR && op.type != OPC_PRODZ_BASE) {
+                const CT fr = one ? mat_entry(mt, op.gate, 6) : mat_entry(mt, op.gate, 0);
+                const CT fi = one ? mat_entry(mt, op.gate, 7) : mat_entry(mt, op.gate, 1);
+                diag_all<T, CT>(x, fr, fi);
             }
-        } else if (type == OP_CNOT) {
-            const uint32_t ctrl = loc_mask<T>(op.b1, op.q0, tid, base);
-            if (ctrl) cnot_at<RB, T, CT>(op.b0, x, ctrl);
-        } else if (type == OP_CZ) {
+            break;
+        }
+        case OPC_CZ: {
             const uint32_t neg = loc_mask<T>(op.b0, op.q0, tid, base) & loc_mask<T>(op.b1, op.q1, tid, base);
 #pragma unroll
             for (int i = 0; i < T; ++i) {
@@ -403,13 +535,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
                 x.br[i] *= sg;
                 x.bi[i] *= sg;
             }
-        } else if (type == OP_ZSUM) {
+            break;
+        }
+        case OPC_ZSUM:
             if (tid == 0) {
                 const double sg = ((base >> op.q0) & 1u) ? -1.0 : 1.0;
                 red[op.slot * kRows] = make_double2(sg * Sr, sg * Si);
                 for (int w = 1; w < kRows; ++w) red[op.slot * kRows + w] = make_double2(0.0, 0.0);
             }
-        } else if (type == OP_XPOSE) {
+            break;
+        case OPC_XPOSE: {
             const DevMap *next = maps + op.aux;
             uint32_t lo_old[T], lo_new[T];
             local_offsets<RB, T>(cur, tbits, tid, lo_old);
@@ -453,6 +588,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
             }
             __syncthreads();
             cur = next;
+            break;
+        }
+        default:
+            break;
         }
     }
 
@@ -519,7 +658,7 @@ template <typename CT> size_t smem_bytes(int m) {
 
 template <typename R, typename CT, int RB>
 void launch_rb(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes, const DevOp *ops,
-               const DevMap *maps, const double *mats, double *partials, int m, hipStream_t st) {
+               const DevMap *maps, const CT *mats, double *partials, int m, hipStream_t st) {
     const size_t smem = smem_bytes<CT>(m);
     static size_t attr_set = 0;
     if (smem > attr_set) {
@@ -529,12 +668,12 @@ void launch_rb(const LaunchItem *items, int n_items, uint32_t total_tiles, const
         attr_set = smem;
     }
     hipLaunchKernelGGL((k_sweep_reg<R, CT, RB>), dim3(total_tiles), dim3(kThreads), smem, st, items, n_items, passes,
-                       ops, maps, mats, (double2 *)partials);
+                       ops, maps, (const void *)mats, (double2 *)partials);
 }
 
 template <typename R, typename CT>
 void launch_ct(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes, const DevOp *ops,
-               const DevMap *maps, const double *mats, double *partials, int m, int rb, hipStream_t st) {
+               const DevMap *maps, const CT *mats, double *partials, int m, int rb, hipStream_t st) {
     switch (rb) {
     case 1: launch_rb<R, CT, 1>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st); break;
     case 2: launch_rb<R, CT, 2>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st); break;
@@ -553,17 +692,17 @@ void launch_ct(const LaunchItem *items, int n_items, uint32_t total_tiles, const
 
 template <typename R>
 void launch_sweep_pass(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
-                       const DevOp *ops, const DevMap *maps, const double *mats, double *partials, int m, int rb,
-                       bool f64_registers, hipStream_t st) {
+                       const DevOp *ops, const DevMap *maps, const double *mats64, const float *mats32,
+                       double *partials, int m, int rb, bool f64_registers, hipStream_t st) {
     if (n_items <= 0 || total_tiles == 0) return;
     if constexpr (sizeof(R) == 8) {
         (void)f64_registers;
-        launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, rb, st);
+        launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, partials, m, rb, st);
     } else {
         if (f64_registers)
-            launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, rb, st);
+            launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, partials, m, rb, st);
         else
-            launch_ct<R, float>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, rb, st);
+            launch_ct<R, float>(items, n_items, total_tiles, passes, ops, maps, mats32, partials, m, rb, st);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) throw e;
@@ -579,8 +718,10 @@ void launch_reduce_tasks(const ReduceTask *tasks, int n_tasks, const double *par
 }
 
 template void launch_sweep_pass<double>(const LaunchItem *, int, uint32_t, const DevPass *, const DevOp *,
-                                        const DevMap *, const double *, double *, int, int, bool, hipStream_t);
+                                        const DevMap *, const double *, const float *, double *, int, int, bool,
+                                        hipStream_t);
 template void launch_sweep_pass<float>(const LaunchItem *, int, uint32_t, const DevPass *, const DevOp *,
-                                       const DevMap *, const double *, double *, int, int, bool, hipStream_t);
+                                       const DevMap *, const double *, const float *, double *, int, int, bool,
+                                       hipStream_t);
 
 }  // namespace qng

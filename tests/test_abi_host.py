@@ -121,3 +121,20 @@ def test_create_without_gpu_fails_cleanly(qng):
     with pytest.raises(qng.QNGError) as e:
         qng.Context(0)
     assert e.value.name == "QNG_E_DEVICE"
+
+
+def test_header_constants_match_binding(qng):
+    """Option codes, status codes and the stats struct of the header agree with
+    the Python binding's marshalling."""
+    text = open(HEADER).read()
+    opts = dict((k, int(v)) for k, v in re.findall(r"QNG_OPT_(\w+)\s*=\s*(\d+)", text))
+    for name, val in opts.items():
+        assert getattr(qng, "OPT_" + name) == val, name
+    status = dict((k, int(v)) for k, v in re.findall(r"(QNG_(?:OK|E_\w+))\s*=\s*(-?\d+)", text))
+    for name, val in status.items():
+        assert qng.STATUS[val] == name
+    end = text.index("} qng_stats;")
+    body = text[text.rindex("typedef struct {", 0, end):end]
+    fields = re.findall(r"^\s*(int64_t|int32_t|double)\s+(\w+);", body, re.M)
+    ct = {"int64_t": "c_long", "int32_t": "c_int", "double": "c_double"}
+    assert [(n, ct[t]) for t, n in fields] == [(n, t.__name__) for n, t in qng.Stats._fields_]

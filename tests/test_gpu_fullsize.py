@@ -1,0 +1,170 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark
+times (fused passes, library-default tile), through the C ABI.
+
+* n=20, P=400 (10 layers of RX, RY + CZ ring): the oracle builds all P
+  derivative states, so G, T, grad E and dtheta are compared in full.
+* n=26, P=416 (8 layers of RY, RZ + CNOT chain) and n=24, P=432 (6 layers of
+  RX, RY, RZ + CZ ring): P explicit derivative states do not fit in host memory
+  (416 GiB and 108 GiB), so the oracle builds a seeded sample of them (the first
+  and last parameter and two runs of three consecutive ones) and the GPU's G is
+  compared on the sampled rows and columns, T and grad E on the sampled entries,
+  E in full; properties that hold at any size (Re T = 0, |T| <= 1/2, G positive
+  semidefinite, the shifted solve's residual) are checked on the whole output.
+
+complex128 bound: as in the small-size tests, normwise 1e-10.  complex64 bound
+(n=26): states and gate matrices are rounded to FP32 and each sweep register
+passes through at most M gates, each adding a relative error of at most a few
+FP32 unit roundoffs (u = 2^-24), so the normwise error of G, T and grad E is
+bounded by 4 M u (= 1.5e-4 at M = 616); the inner products themselves are exact
+FP64 products of the stored values, accumulated in FP64.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+U32 = 2.0 ** -24
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def qng():
+    import torch  # noqa: F401
+    import paper_2011_02991_amd as q
+    return q
+
+
+@pytest.fixture(scope="module")
+def ctx(qng):
+    c = qng.Context(0)
+    yield c
+    c.close()
+
+
+def rel_err(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    scale = max(np.abs(b).max(initial=0.0), 1e-300)
+    return float(np.abs(a - b).max(initial=0.0) / scale)
+
+
+def sample_params(P: int, seed: int) -> np.ndarray:
+    """First, last and two runs of three consecutive parameter indices."""
+    rng = np.random.default_rng(seed)
+    a, b = rng.choice(np.arange(1, P - 3), size=2, replace=False)
+    return np.array(sorted({0, P - 1, a, a + 1, a + 2, b, b + 1, b + 2}), dtype=np.int64)
+
+
+def check_properties(res, T, pr, label, tol=1e-12):
+    """Facts that hold at any size (Sec. 2: <psi|psi> = 1 makes T imaginary;
+    G is a Gram matrix minus a rank-one term, hence positive semidefinite)."""
+    G, P = res["G"], pr.n_params
+    assert np.abs(T.real).max() <= tol and np.abs(T).max() <= 0.5 + tol, (np.abs(T.real).max(), np.abs(T).max())
+    d = np.diag(G).real   # G_ii = 1/4 - |T_i|^2
+    assert np.all(d <= 0.25 + 1e-12) and np.all(d >= -1e-12), (d.min(), d.max())
+    assert np.abs(G - G.conj().T).max() <= 1e-12
+    w = np.linalg.eigvalsh(G)
+    say(f"{label}: min eig G = {w.min():.2e}, max = {w.max():.2e}")
+    assert w.min() >= -max(1e-10, tol) * max(1.0, w.max())
+    # backward error of the shifted solve (Sec. 1 step)
+    g = G.real + pr.tikhonov * np.eye(P)
+    r = g @ res["dtheta"] + pr.dt * res["grad"]
+    scale = np.linalg.norm(g, 2) * np.linalg.norm(res["dtheta"]) + np.linalg.norm(pr.dt * res["grad"])
+    assert np.linalg.norm(r) <= 1e-12 * scale, (np.linalg.norm(r), scale)
+
+
+_ORACLE = {}
+
+
+def oracle_sample(pr, sel, label):
+    key = (pr.name, tuple(int(i) for i in sel))
+    if key in _ORACLE:
+        return _ORACLE[key]
+    say(f"{label}: oracle derivative states for parameters {list(sel)}")
+    D, psi = oracle.derivative_states(pr, sel)
+    G, T, _ = oracle.metric_from_states(D, psi)
+    say(f"{label}: oracle energy and gradient")
+    E, grad = oracle.energy_grad(pr, sel, D=D, psi=psi)
+    del D, psi
+    _ORACLE[key] = (G, T, E, grad)
+    return _ORACLE[key]
+
+
+def compare_sample(res, T_gpu, want, sel, tol, label):
+    G, T, E, grad = want
+    eG = rel_err(res["G"][np.ix_(sel, sel)], G)
+    eT = rel_err(T_gpu[sel], T)
+    eg = rel_err(res["grad"][sel], grad)
+    eE = abs(res["E"] - E) / max(1.0, abs(E))
+    say(f"{label}: |dG|={eG:.2e} |dT|={eT:.2e} |dgrad|={eg:.2e} |dE|={eE:.2e} (bound {tol:.1e})")
+    assert eG <= tol and eT <= tol and eg <= tol and eE <= tol, (eG, eT, eg, eE)
+
+
+def gpu_step(ctx, qng, pr, prec):
+    circ = qng.Circuit.from_problem(pr)
+    res = ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, prec=prec)
+    _, T = ctx.metric(circ, pr.theta, prec=prec)
+    return res, T
+
+
+@pytest.mark.timeout(900)
+def test_n20_full_oracle(ctx, qng):
+    pr = W.config2()
+    say(f"case: {pr.name} c128 full oracle")
+    res, T = gpu_step(ctx, qng, pr, "c128")
+    check_properties(res, T, pr, pr.name)
+    say(f"{pr.name}: oracle step (all {pr.n_params} derivative states)")
+    D, psi = oracle.derivative_states(pr)
+    Go, To, _ = oracle.metric_from_states(D, psi)
+    Eo, go = oracle.energy_grad(pr, None, D=D, psi=psi)
+    del D, psi
+    dth = oracle.solve_step(Go, go, pr.dt, pr.tikhonov)
+    eG, eT, eg = rel_err(res["G"], Go), rel_err(T, To), rel_err(res["grad"], go)
+    eE = abs(res["E"] - Eo) / max(1.0, abs(Eo))
+    kappa = np.linalg.cond(Go.real + pr.tikhonov * np.eye(pr.n_params))
+    ed = rel_err(res["dtheta"], dth)
+    say(f"{pr.name}: |dG|={eG:.2e} |dT|={eT:.2e} |dgrad|={eg:.2e} |dE|={eE:.2e} |ddtheta|={ed:.2e} "
+        f"kappa={kappa:.1e}")
+    assert max(eG, eT, eg, eE) <= TOL
+    assert ed <= max(TOL, kappa * 1e-14)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("cfg", [3, 5])
+def test_sampled_c128(ctx, qng, cfg):
+    pr = W.CONFIGS[cfg]()
+    sel = sample_params(pr.n_params, 500 + cfg)
+    say(f"case: {pr.name} c128 sampled {list(sel)}")
+    res, T = gpu_step(ctx, qng, pr, "c128")
+    check_properties(res, T, pr, pr.name)
+    compare_sample(res, T, oracle_sample(pr, sel, pr.name), sel, TOL, pr.name + " c128")
+
+
+@pytest.mark.timeout(900)
+def test_n26_c64_sampled_and_vs_c128(ctx, qng):
+    """The benchmark's own configuration: complex64 storage, FP64 accumulation."""
+    pr = W.config3()
+    sel = sample_params(pr.n_params, 503)
+    bound = 4 * pr.n_gates * U32
+    say(f"case: {pr.name} c64 sampled {list(sel)}, bound {bound:.2e}")
+    res64, T64 = gpu_step(ctx, qng, pr, "c64")
+    res128, T128 = gpu_step(ctx, qng, pr, "c128")
+    check_properties(res64, T64, pr, pr.name + " c64", bound)
+    eG, eT, eg = rel_err(res64["G"], res128["G"]), rel_err(T64, T128), rel_err(res64["grad"], res128["grad"])
+    eE = abs(res64["E"] - res128["E"]) / max(1.0, abs(res128["E"]))
+    kappa = np.linalg.cond(res128["G"].real + pr.tikhonov * np.eye(pr.n_params))
+    ed = rel_err(res64["dtheta"], res128["dtheta"])
+    say(f"{pr.name} c64 vs c128 (all entries): |dG|={eG:.2e} |dT|={eT:.2e} |dgrad|={eg:.2e} |dE|={eE:.2e} "
+        f"|ddtheta|={ed:.2e} kappa={kappa:.1e}")
+    assert max(eG, eT, eg, eE) <= bound
+    assert ed <= max(bound, kappa * bound)
+    compare_sample(res64, T64, oracle_sample(pr, sel, pr.name), sel, bound, pr.name + " c64")
