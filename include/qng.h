@@ -171,17 +171,20 @@ qng_status qng_validate(const qng_circuit *circ, const double *theta, const qng_
 /* Compile the sweep plan of a circuit for the given fusion mode and tile width
  * (0 = automatic) and report its size.  Host only. */
 qng_status qng_plan(const qng_circuit *circ, int fusion, int tile_qubits, qng_plan_info *out);
-/* Export the fused sweep plan (host only): one row of 10 int32 per operation,
+/* Export a fused sweep plan (host only): one row of 10 int32 per operation,
  * in execution order (in-register exchanges omitted): {column s, pass index
  * within the column, kind (0 gate adjoint, 1 inner product then the adjoint of
  * its rotation, 2 inner product), qubit q0 (CNOT: control), qubit q1 (CNOT
  * target / CZ second qubit, else -1), gate position of the adjoint (or -1),
- * destination r*P + s of an inner product (or -1), Pauli axis of the inner
- * product (0 X, 1 Y, 2 Z; or -1), tile-qubit mask bits 0..30, bits 31..61}.
+ * destination of an inner product (or -1), Pauli axis of the inner product
+ * (0 X, 1 Y, 2 Z; or -1), tile-qubit mask bits 0..30, bits 31..61}.
+ * sweep = 0: the metric's columns s = 1..P-1 (Sec. 3, Alg. 1 inner loops),
+ * destination r*P + s of <lambda|sigma_r|phi>; sweep = 1: the reverse sweep of
+ * the energy gradient from the last gate (one column, s = P), destination r.
  * amp_bytes: 16 for complex128 plans, 8 for complex64.  With rows = NULL only
  * *n_rows is set. */
-qng_status qng_plan_export(const qng_circuit *circ, int tile_qubits, int amp_bytes, int32_t *rows, int64_t cap,
-                           int64_t *n_rows);
+qng_status qng_plan_export(const qng_circuit *circ, int tile_qubits, int amp_bytes, int32_t sweep, int32_t *rows,
+                           int64_t cap, int64_t *n_rows);
 /* Solve (Re G + eps I) x = b in FP64 by Cholesky (host).  G: 2*P*P doubles
  * (complex, row-major), b, x: P doubles.  QNG_E_NOT_SPD if not positive definite. */
 qng_status qng_solve_shifted(int32_t P, const double *G, double eps, const double *b, double *x);

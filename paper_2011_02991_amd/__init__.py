@@ -100,7 +100,7 @@ def _load():
         "qng_energy_dev": [vp, vp, vp, vp, vp, ctypes.c_int, vp, vp],
         "qng_energy_grad_from_state_dev": [vp, vp, vp, vp, ctypes.c_int, vp, vp],
         "qng_apply_circuit_dev": [vp, vp, vp, ctypes.c_int, vp],
-        "qng_plan_export": [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int64, vp],
+        "qng_plan_export": [vp, ctypes.c_int, ctypes.c_int, i32, vp, ctypes.c_int64, vp],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -200,13 +200,15 @@ def plan(circ: Circuit, fusion: int = 1, tile_qubits: int = 0) -> dict:
     return info.as_dict()
 
 
-def plan_export(circ: Circuit, tile_qubits: int = 0, prec="c128") -> np.ndarray:
-    """Host-only: the fused sweep plan as rows of 10 int32 (see qng_plan_export)."""
+def plan_export(circ: Circuit, tile_qubits: int = 0, prec="c128", gradient: bool = False) -> np.ndarray:
+    """Host-only: a fused sweep plan as rows of 10 int32 (see qng_plan_export);
+    the metric's columns, or the gradient's reverse sweep."""
     amp = 16 if _prec(prec) == C128 else 8
+    sw = 1 if gradient else 0
     n = ctypes.c_int64()
-    _check(_lib.qng_plan_export(circ.cref, tile_qubits, amp, None, 0, ctypes.byref(n)))
+    _check(_lib.qng_plan_export(circ.cref, tile_qubits, amp, sw, None, 0, ctypes.byref(n)))
     rows = np.zeros((n.value, 10), dtype=np.int32)
-    _check(_lib.qng_plan_export(circ.cref, tile_qubits, amp, _ptr(rows), n.value, ctypes.byref(n)))
+    _check(_lib.qng_plan_export(circ.cref, tile_qubits, amp, sw, _ptr(rows), n.value, ctypes.byref(n)))
     return rows
 
 

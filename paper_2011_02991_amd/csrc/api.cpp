@@ -236,6 +236,12 @@ template <typename R> struct Engine {
         : ctx(c), pb(p), st(s), n(p.circ.n), regs{psi, lam, phi}, state_bytes(sb), partials_(part), lraw_(lraw),
           traw_(traw), graw_(graw), eraw_(eraw) {}
 
+    // fused reverse sweep of the gradient (nullptr: one kernel per primitive)
+    const SweepPlan *gplan = nullptr;
+    char *gscratch = nullptr;
+    size_t gscratch_bytes = 0;
+    bool f64_regs = false;
+
     void *state(int k) const { return regs[k]; }
     double *partials() const { return partials_; }
     double *lraw() const { return lraw_; }
@@ -302,6 +308,11 @@ template <typename R> struct Engine {
         hamiltonian(psi, lam);
         prod(psi, lam, 0, -1, eraw());
         if (!want_grad || c.P == 0) return;
+        if (gplan) {
+            run_fused_gradient<R>(*gplan, c, pb.adj, lam, psi, graw(), gscratch, gscratch_bytes, st, &ctx->stats,
+                                  ctx->opt_profile != 0, f64_regs);
+            return;
+        }
         const int p0 = c.rots[0].pos;
         for (int k = c.M - 1; k >= p0; --k) {
             const int r = c.rot_at[k];
@@ -363,6 +374,12 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
         scratch = fused_scratch_bytes(*plan, fr, c.M);
         n_states = std::max(4, 1 + 2 * fr.B);
     }
+    std::shared_ptr<const SweepPlan> gplan;
+    const bool f64_regs = amp == 16 || ctx->opt_f64_regs;
+    if (ctx->opt_fusion != 0 && spec.grad && c.P > 0) {
+        gplan = ctx->sweep_cache.get_gradient(c, ctx->opt_tile, (int)amp, f64_regs);
+        scratch = std::max(scratch, fused_gradient_scratch_bytes(*gplan, c.M));
+    }
     Layout L = plan_layout(n, c.P, amp, n_states, spec.in_host != nullptr, scratch);
     char *base = ensure_workspace(ctx, L.total);
     hipStream_t st = ctx->stream;
@@ -370,6 +387,12 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
     Engine<R> e(ctx, pb, st, sb, sb + L.state_bytes, sb + 2 * L.state_bytes, L.state_bytes,
                 (double *)(base + L.partials), (double *)(base + L.lraw), (double *)(base + L.traw),
                 (double *)(base + L.graw), (double *)(base + L.eraw));
+    if (gplan) {
+        e.gplan = gplan.get();
+        e.gscratch = base + L.sweep;
+        e.gscratch_bytes = L.sweep_bytes;
+        e.f64_regs = f64_regs;
+    }
 
     const void *in_c128 = spec.in_dev;
     if (spec.in_host) {
@@ -463,7 +486,7 @@ int member_tile(const Circuit &c, int opt_tile, int amp, bool f64) {
 
 struct BatchLayout {
     std::vector<size_t> psi, traw, graw, gout, tout, param_of, lraw_class;
-    size_t lam = 0, staging = 0, partials = 0, eraw = 0;
+    size_t lam = 0, staging = 0, partials = 0, eraw = 0, gscratch = 0, gscratch_bytes = 0;
     size_t scratch = 0, images = 0, arena = 0, spart = 0, fwd = 0, adj = 0, adj32 = 0;
     size_t total = 0;
 };
@@ -534,6 +557,14 @@ BatchRun batch_metric(qng_ctx *ctx, const std::vector<Problem> &pbs, const doubl
         L.param_of.push_back(take((size_t)c.P * 4));
     }
     L.lam = take(vmax);
+    size_t gsc = 0;
+    if (ctx->opt_fusion)
+        for (int b = 0; b < B; ++b)
+            if (pbs[b].circ.P > 0)
+                gsc = std::max(gsc, fused_gradient_scratch_bytes(
+                                        *ctx->sweep_cache.get_gradient(pbs[b].circ, tun.tile_qubits, amp, f64), pbs[b].circ.M));
+    L.gscratch = take(gsc);
+    L.gscratch_bytes = gsc;
     L.staging = stage ? take(stage) : 0;
     L.partials = take((size_t)reduce_blocks(nmax) * 16);
     L.eraw = take((size_t)B * 16);
@@ -875,14 +906,16 @@ qng_status qng_plan(const qng_circuit *circ, int fusion, int tile_qubits, qng_pl
     });
 }
 
-qng_status qng_plan_export(const qng_circuit *circ, int tile_qubits, int amp_bytes, int32_t *rows, int64_t cap,
-                           int64_t *n_rows) {
+qng_status qng_plan_export(const qng_circuit *circ, int tile_qubits, int amp_bytes, int32_t sweep, int32_t *rows,
+                           int64_t cap, int64_t *n_rows) {
     return guarded(nullptr, [&] {
         if (!n_rows) fail(QNG_E_INVALID_ARG, "n_rows is NULL");
         if (amp_bytes != 8 && amp_bytes != 16) fail(QNG_E_INVALID_ARG, "amp_bytes must be 8 or 16");
+        if (sweep != 0 && sweep != 1) fail(QNG_E_INVALID_ARG, "sweep must be 0 (metric) or 1 (gradient)");
         validate_circuit(circ, kMaxQubitsC64);
         Circuit c = compile_circuit(circ);
-        SweepPlan plan = build_sweep_plan(c, tile_qubits, amp_bytes, 1, amp_bytes == 16);
+        SweepPlan plan = sweep == 0 ? build_sweep_plan(c, tile_qubits, amp_bytes, 1, amp_bytes == 16)
+                                    : build_gradient_plan(c, tile_qubits, amp_bytes, amp_bytes == 16);
         int64_t k = 0;
         for (const ColumnPlan &cp : plan.cols) {
             for (size_t pi = 0; pi < cp.passes.size(); ++pi) {
@@ -1079,6 +1112,14 @@ qng_status qng_step_batched(qng_ctx *ctx, int32_t B, const qng_circuit *circs, c
                             (size_t(1) << pb.circ.n) * amp, (double *)(base + L.partials), nullptr,
                             (double *)(base + L.traw[b]), (double *)(base + L.graw[b]),
                             (double *)(base + L.eraw) + 2 * b);
+                std::shared_ptr<const SweepPlan> gp;
+                if (ctx->opt_fusion && pb.circ.P > 0) {
+                    gp = ctx->sweep_cache.get_gradient(pb.circ, tun.tile_qubits, (int)amp, amp == 16 || ctx->opt_f64_regs);
+                    e.gplan = gp.get();
+                    e.gscratch = base + L.gscratch;
+                    e.gscratch_bytes = L.gscratch_bytes;
+                    e.f64_regs = amp == 16 || ctx->opt_f64_regs;
+                }
                 e.energy_grad_unfused(batch_final_pos(pb.circ), true, nullptr);
             }
             for (int b = 0; b < B; ++b) {

@@ -205,6 +205,109 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
     return pos;
 }
 
+size_t fused_gradient_scratch_bytes(const SweepPlan &g, int M) {
+    size_t b = 0;
+    b += align256((size_t)M * 64 + 64);
+    b += align256((size_t)M * 32 + 64);
+    b += align256(g.dev_passes.size() * sizeof(DevPass) + 64);
+    b += align256(g.dev_ops.size() * sizeof(DevOp) + 64);
+    b += align256(g.dev_maps.size() * sizeof(DevMap) + 64);
+    b += align256(g.dev_passes.size() * sizeof(LaunchItem) + 64);
+    b += align256((size_t)(g.P + 1) * sizeof(ReduceTask) + 64);
+    b += align256((size_t)g.max_slots * ((size_t)1 << (g.n - g.m)) * 16 + 64);
+    return b;
+}
+
+template <typename R>
+void run_fused_gradient(const SweepPlan &g, const Circuit &c, const std::vector<Mat2> &adj, void *lam, void *psi,
+                        double *graw, char *scratch, size_t scratch_bytes, hipStream_t st, qng_stats *stats,
+                        bool profile, bool f64_regs) {
+    if (g.cols.empty()) return;
+    const ColumnPlan &cp = g.cols[0];
+    const uint32_t tiles = 1u << (c.n - g.m);
+    std::vector<LaunchItem> items;
+    std::vector<ReduceTask> tasks;
+    std::vector<uint32_t> task_begin;
+    for (size_t t = 0; t < cp.passes.size(); ++t) {
+        LaunchItem it{};
+        it.tile_begin = 0;
+        it.pass = (uint32_t)t;
+        it.ntiles = tiles;
+        it.partial_off = 0;
+        it.regA = lam;
+        it.regB = psi;
+        items.push_back(it);
+        task_begin.push_back((uint32_t)tasks.size());
+        for (size_t k = 0; k < cp.passes[t].slot_dest.size(); ++k)
+            tasks.push_back(ReduceTask{(uint64_t)k * tiles, tiles, cp.passes[t].slot_dest[k]});
+    }
+    task_begin.push_back((uint32_t)tasks.size());
+    std::vector<double> mats((size_t)c.M * 8, 0.0);
+    for (const Rot &r : c.rots) {
+        const Mat2 &m = adj[r.pos];
+        double *d = &mats[(size_t)r.pos * 8];
+        d[0] = m.a.real(); d[1] = m.a.imag(); d[2] = m.b.real(); d[3] = m.b.imag();
+        d[4] = m.c.real(); d[5] = m.c.imag(); d[6] = m.d.real(); d[7] = m.d.imag();
+    }
+    std::vector<float> mats32(mats.begin(), mats.end());
+    char *p = scratch;
+    auto take = [&](size_t bytes) { char *o = p; p += align256(bytes + 64); return o; };
+    double *d_mats = (double *)take(mats.size() * 8);
+    float *d_mats32 = (float *)take(mats32.size() * 4);
+    DevPass *d_passes = (DevPass *)take(g.dev_passes.size() * sizeof(DevPass));
+    DevOp *d_ops = (DevOp *)take(g.dev_ops.size() * sizeof(DevOp));
+    DevMap *d_maps = (DevMap *)take(g.dev_maps.size() * sizeof(DevMap));
+    LaunchItem *d_items = (LaunchItem *)take(items.size() * sizeof(LaunchItem));
+    ReduceTask *d_tasks = (ReduceTask *)take(tasks.size() * sizeof(ReduceTask));
+    double *d_partials = (double *)p;
+    if ((size_t)(p - scratch) + (size_t)g.max_slots * tiles * 16 > scratch_bytes)
+        fail(QNG_E_DEVICE, "fused gradient: scratch too small (internal)");
+    auto put = [&](void *dst, const void *src, size_t bytes) {
+        if (bytes) FCHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+    };
+    put(d_mats, mats.data(), mats.size() * 8);
+    put(d_mats32, mats32.data(), mats32.size() * 4);
+    put(d_passes, g.dev_passes.data(), g.dev_passes.size() * sizeof(DevPass));
+    put(d_ops, g.dev_ops.data(), g.dev_ops.size() * sizeof(DevOp));
+    put(d_maps, g.dev_maps.data(), g.dev_maps.size() * sizeof(DevMap));
+    put(d_items, items.data(), items.size() * sizeof(LaunchItem));
+    put(d_tasks, tasks.data(), tasks.size() * sizeof(ReduceTask));
+    FCHECK(hipStreamSynchronize(st));   // host vectors are released at return
+    std::vector<hipEvent_t> ev;
+    if (profile) {
+        ev.resize(2 * items.size());
+        for (auto &e : ev) FCHECK(hipEventCreate(&e));
+    }
+    const size_t V = ((size_t)1 << c.n) * 2 * sizeof(R);
+    for (size_t t = 0; t < items.size(); ++t) {
+        if (profile) FCHECK(hipEventRecord(ev[2 * t], st));
+        launch_sweep_pass<R>(d_items + t, 1, tiles, d_passes, d_ops, d_maps, d_mats, d_mats32, d_partials, g.m, g.rb,
+                             f64_regs, st);
+        if (profile) FCHECK(hipEventRecord(ev[2 * t + 1], st));
+        const uint32_t nt = task_begin[t + 1] - task_begin[t];
+        launch_reduce_tasks(d_tasks + task_begin[t], (int)nt, d_partials, graw, st);
+        ++stats->sweep_launches;
+        ++stats->other_launches;
+        stats->sweep_tiles += tiles;
+        stats->sweep_bytes += 4.0 * (double)V;
+        stats->sweep_flops += 20.0 * (double)nt * (double)((uint64_t)1 << c.n);
+    }
+    if (profile) {
+        FCHECK(hipStreamSynchronize(st));
+        for (size_t t = 0; t < items.size(); ++t) {
+            float ms = 0.f;
+            FCHECK(hipEventElapsedTime(&ms, ev[2 * t], ev[2 * t + 1]));
+            stats->sweep_ms += ms;
+        }
+        for (auto &e : ev) (void)hipEventDestroy(e);
+    }
+}
+
+template void run_fused_gradient<double>(const SweepPlan &, const Circuit &, const std::vector<Mat2> &, void *, void *,
+                                         double *, char *, size_t, hipStream_t, qng_stats *, bool, bool);
+template void run_fused_gradient<float>(const SweepPlan &, const Circuit &, const std::vector<Mat2> &, void *, void *,
+                                        double *, char *, size_t, hipStream_t, qng_stats *, bool, bool);
+
 template int run_fused_metric<double>(const SweepPlan &, const FusedRun &, const Circuit &, const std::vector<Mat2> &,
                                       const std::vector<Mat2> &, const FusedBuffers &, hipStream_t, qng_stats *, bool, bool);
 template int run_fused_metric<float>(const SweepPlan &, const FusedRun &, const Circuit &, const std::vector<Mat2> &,

@@ -31,4 +31,15 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
                      const std::vector<Mat2> &adj, const FusedBuffers &buf, hipStream_t st, qng_stats *stats,
                      bool profile, bool f64_regs);
 
+size_t fused_gradient_scratch_bytes(const SweepPlan &g, int M);
+
+// Reverse sweep of the energy gradient through the fused passes of the
+// gradient plan g (build_gradient_plan): lam holds H psi and psi the final
+// state on entry (both are swept back in place); <lam|sigma_r|psi> of every
+// rotation r is written to graw[r] (complex).
+template <typename R>
+void run_fused_gradient(const SweepPlan &g, const Circuit &c, const std::vector<Mat2> &adj, void *lam, void *psi,
+                        double *graw, char *scratch, size_t scratch_bytes, hipStream_t st, qng_stats *stats,
+                        bool profile, bool f64_regs);
+
 }  // namespace qng

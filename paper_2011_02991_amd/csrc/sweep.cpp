@@ -73,6 +73,24 @@ std::vector<Event> column_events(const Circuit &c, int s) {
     return ev;
 }
 
+// Reverse sweep of the energy gradient: positions M-1 down to rots[0].pos,
+// the inner product of every rotation r just before its adjoint (again never
+// needed for the first rotation).
+std::vector<Event> gradient_events(const Circuit &c) {
+    std::vector<Event> ev;
+    const int p0 = c.rots[0].pos;
+    for (int k = c.M - 1; k >= p0; --k) {
+        const int r = c.rot_at[k];
+        if (r >= 0) {
+            ev.push_back(prod_event(c, r));
+            if (k > p0) ev.push_back(unapply_event(c, k));
+        } else {
+            ev.push_back(unapply_event(c, k));
+        }
+    }
+    return ev;
+}
+
 bool executable(const Event &e, const std::vector<uint8_t> &in_tile) {
     if (e.kind == EV_PROD) return e.type[0] == TY_Z || in_tile[e.q[0]];
     switch (e.gkind) {
@@ -242,7 +260,10 @@ uint8_t location(const DevMap &mp, int rb, int m, int localbit) {
     return kLocBase;
 }
 
-HostPass make_pass(const Circuit &c, int s, const std::vector<Event> &ev, const std::vector<int> &emitted,
+// dest_stride, dest_offset: destination of the inner product of rotation r is
+// r * dest_stride + dest_offset (metric column s: r * P + s; gradient: r).
+HostPass make_pass(const Circuit &c, int dest_stride, int dest_offset, const std::vector<Event> &ev,
+                   const std::vector<int> &emitted,
                    const std::vector<uint8_t> &tile, int rb, int carriers) {
     HostPass hp;
     hp.tile = tile;
@@ -339,7 +360,7 @@ HostPass make_pass(const Circuit &c, int s, const std::vector<Event> &ev, const 
             if (e.kind == EV_PROD) {
                 const int q = e.q[0];
                 op.slot = (uint16_t)hp.slot_dest.size();
-                hp.slot_dest.push_back((int32_t)(e.rot * c.P + s));
+                hp.slot_dest.push_back((int32_t)(e.rot * dest_stride + dest_offset));
                 op.axis = e.type[0];
                 op.q0 = (uint8_t)q;
                 const bool fuse = k + 1 < order.size() && ev[order[k + 1]].kind == EV_UNAPPLY &&
@@ -390,12 +411,13 @@ HostPass make_pass(const Circuit &c, int s, const std::vector<Event> &ev, const 
 
 }  // namespace
 
-int default_tile_qubits(int n, int /*amp_bytes*/, bool /*reg_f64*/) {
-    // 11 tile qubits: 8 amplitudes of each register per thread.  The pass is
-    // bound by VALU work per element, which does not depend on the tile width;
-    // 11 qubits keeps register pressure low enough for 3-4 waves per SIMD
-    // (measured faster than 12 qubits at n = 26 in both precisions).
-    const int m = 11;
+int default_tile_qubits(int n, int amp_bytes, bool reg_f64) {
+    // FP32 registers: 12 tile qubits (16 amplitudes of each register per
+    // thread); FP64 registers: 11 (8 per thread), the most that fits the
+    // register file without spills.  Wider tiles fuse more of each column
+    // into one pass (measured at n = 26: 2363 passes at 12 qubits against 2718
+    // at 11, at the same time per pass).
+    const int m = (amp_bytes == 8 && !reg_f64) ? 12 : 11;
     return n < m ? n : m;
 }
 
@@ -405,8 +427,10 @@ int register_bits(int m, int /*amp_bytes*/) {
     return rb > 4 ? 4 : rb;
 }
 
-SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int /*small*/, bool reg_f64) {
-    SweepPlan plan;
+namespace {
+
+// Tile width, register bits and carriers of a plan for a register of c.n qubits.
+void plan_shape(SweepPlan &plan, const Circuit &c, int tile_qubits, int amp_bytes, bool reg_f64) {
     plan.n = c.n;
     plan.P = c.P;
     int m = tile_qubits > 0 ? tile_qubits : default_tile_qubits(c.n, amp_bytes, reg_f64);
@@ -417,22 +441,26 @@ SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int
     plan.rb = register_bits(m, amp_bytes);
     plan.carriers = c.n > m ? std::min(amp_bytes >= 16 ? 3 : 4, m - 1) : 0;
     if (c.n > m && m - plan.carriers < 2) fail(QNG_E_INVALID_ARG, "tile too small for the carrier qubits");
-    for (int s = 1; s < c.P; ++s) {
-        ColumnPlan cp;
-        cp.s = s;
-        std::vector<Event> ev = column_events(c, s);
-        std::vector<uint8_t> done(ev.size(), 0);
-        std::vector<int> pending(ev.size());
-        for (size_t i = 0; i < ev.size(); ++i) pending[i] = (int)i;
-        std::vector<uint8_t> tile;
-        std::vector<int> emitted;
-        while (!pending.empty()) {
-            choose_and_emit(ev, done, pending, c.n, m, plan.carriers, tile, emitted);
-            cp.passes.push_back(make_pass(c, s, ev, emitted, tile, plan.rb, plan.carriers));
-        }
-        plan.cols.push_back(std::move(cp));
+}
+
+ColumnPlan plan_column(const Circuit &c, const SweepPlan &plan, int s, const std::vector<Event> &ev, int dest_stride,
+                       int dest_offset) {
+    ColumnPlan cp;
+    cp.s = s;
+    std::vector<uint8_t> done(ev.size(), 0);
+    std::vector<int> pending(ev.size());
+    for (size_t i = 0; i < ev.size(); ++i) pending[i] = (int)i;
+    std::vector<uint8_t> tile;
+    std::vector<int> emitted;
+    while (!pending.empty()) {
+        choose_and_emit(ev, done, pending, c.n, plan.m, plan.carriers, tile, emitted);
+        cp.passes.push_back(make_pass(c, dest_stride, dest_offset, ev, emitted, tile, plan.rb, plan.carriers));
     }
-    // flatten
+    return cp;
+}
+
+// Device images of all columns of a plan.
+void flatten(SweepPlan &plan, const Circuit &c) {
     for (const ColumnPlan &cp : plan.cols) {
         plan.col_pass_begin.push_back((int64_t)plan.dev_passes.size());
         for (const HostPass &hp : cp.passes) {
@@ -469,6 +497,23 @@ SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int
     }
     plan.total_passes = (int64_t)plan.dev_passes.size();
     plan.total_ops = (int64_t)plan.dev_ops.size();
+}
+
+}  // namespace
+
+SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int /*small*/, bool reg_f64) {
+    SweepPlan plan;
+    plan_shape(plan, c, tile_qubits, amp_bytes, reg_f64);
+    for (int s = 1; s < c.P; ++s) plan.cols.push_back(plan_column(c, plan, s, column_events(c, s), c.P, s));
+    flatten(plan, c);
+    return plan;
+}
+
+SweepPlan build_gradient_plan(const Circuit &c, int tile_qubits, int amp_bytes, bool reg_f64) {
+    SweepPlan plan;
+    plan_shape(plan, c, tile_qubits, amp_bytes, reg_f64);
+    if (c.P > 0) plan.cols.push_back(plan_column(c, plan, c.P, gradient_events(c), 1, 0));
+    flatten(plan, c);
     return plan;
 }
 
@@ -537,6 +582,18 @@ std::shared_ptr<const SweepPlan> SweepCache::get_shared(const Circuit &c, int ti
     if (it != plans.end()) return it->second;
     if (plans.size() >= 256) plans.clear();
     auto p = std::make_shared<SweepPlan>(build_sweep_plan(c, tile_qubits, amp_bytes, small, reg_f64));
+    plans[key] = p;
+    return p;
+}
+
+std::shared_ptr<const SweepPlan> SweepCache::get_gradient(const Circuit &c, int tile_qubits, int amp_bytes,
+                                                          bool reg_f64) {
+    std::vector<int32_t> key = {-1, tile_qubits, amp_bytes, reg_f64 ? 1 : 0};
+    append_structure_key(c, key);
+    auto it = plans.find(key);
+    if (it != plans.end()) return it->second;
+    if (plans.size() >= 256) plans.clear();
+    auto p = std::make_shared<SweepPlan>(build_gradient_plan(c, tile_qubits, amp_bytes, reg_f64));
     plans[key] = p;
     return p;
 }

@@ -159,11 +159,16 @@ struct SweepPlan {
 // Register bits per thread for a tile of m qubits (256 threads per tile).
 int register_bits(int m, int amp_bytes);
 
-// Build the plan of all columns.  tile_qubits = 0 picks the default for amp_bytes
-// (complex64: 12, complex128: 11).
+// Build the plan of all columns.  tile_qubits = 0 picks the default: 12 for
+// FP32 registers, 11 for FP64 registers (at most n).
 // reg_f64: tiles are computed in FP64 registers (always for complex128).
 SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int small, bool reg_f64);
 int default_tile_qubits(int n, int amp_bytes, bool reg_f64);
+
+// Plan of the energy gradient's reverse sweep (one column, s = P): registers
+// lambda = H psi and phi = psi swept back from the last gate; the inner product
+// <lambda|sigma_r|phi> of rotation r goes to destination r.
+SweepPlan build_gradient_plan(const Circuit &c, int tile_qubits, int amp_bytes, bool reg_f64);
 
 struct SweepCache {
     std::map<std::vector<int32_t>, std::shared_ptr<SweepPlan>> plans;
@@ -174,6 +179,7 @@ struct SweepCache {
     // cache evicts it.
     std::shared_ptr<const SweepPlan> get_shared(const Circuit &c, int tile_qubits, int amp_bytes, int small,
                                                 bool reg_f64);
+    std::shared_ptr<const SweepPlan> get_gradient(const Circuit &c, int tile_qubits, int amp_bytes, bool reg_f64);
 };
 
 // Structure key of a circuit (gate kinds, qubits, which gates are rotations).

@@ -282,15 +282,71 @@ __device__ __forceinline__ void cnot_cond(Regs<CT, T> &x, bool c) {
     }
 }
 
+// A DevOp read as four dwords (scalar loads need dword granularity) and its
+// fields extracted with shifts.
+struct OpD {
+    uint32_t w0, w1;
+    int32_t gate, aux;
+    __device__ __forceinline__ int type() const { return (int)(w0 & 0xffu); }
+    __device__ __forceinline__ uint8_t b0() const { return (uint8_t)((w0 >> 8) & 0xffu); }
+    __device__ __forceinline__ uint8_t b1() const { return (uint8_t)((w0 >> 16) & 0xffu); }
+    __device__ __forceinline__ int slot() const { return (int)(w1 & 0xffffu); }
+    __device__ __forceinline__ uint8_t q0() const { return (uint8_t)((w1 >> 16) & 0xffu); }
+    __device__ __forceinline__ uint8_t q1() const { return (uint8_t)(w1 >> 24); }
+};
+
+__device__ __forceinline__ OpD load_op(const DevOp *p) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(p);
+    return OpD{v.x, v.y, (int32_t)v.z, (int32_t)v.w};
+}
+
+// The byte tables of a pass (tile qubits, qubits outside the tile) and of a
+// thread mapping (local bit per position), read as dwords and kept as wide
+// integers, so that a byte with a uniform index is a shift (no indexed array,
+// which the compiler would place in scratch memory).
+typedef unsigned __int128 u128;
+
+__device__ __forceinline__ uint32_t byte_at(u128 v, int k) { return (uint32_t)(v >> (8 * k)) & 0xffu; }
+
+__device__ __forceinline__ u128 wide(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+    return (u128)a | ((u128)b << 32) | ((u128)c << 64) | ((u128)d << 96);
+}
+
+struct PassBytes {
+    u128 tq;          // DevPass::tile_q[0..15]
+    u128 rq0;         // DevPass::rest_q[0..15]
+    uint64_t rq1;     // DevPass::rest_q[16..23]
+    __device__ __forceinline__ uint32_t rest(int k) const {
+        return k < 16 ? byte_at(rq0, k) : (uint32_t)(rq1 >> (8 * (k - 16))) & 0xffu;
+    }
+};
+__device__ __forceinline__ PassBytes load_pass_bytes(const DevPass *pp) {
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(pp);
+    PassBytes b;
+    b.tq = wide(w[6], w[7], w[8], w[9]);
+    b.rq0 = wide(w[10], w[11], w[12], w[13]);
+    b.rq1 = (uint64_t)w[14] | ((uint64_t)w[15] << 32);
+    return b;
+}
+struct MapBytes {
+    u128 pos;         // DevMap::pos
+};
+__device__ __forceinline__ MapBytes load_map(const DevMap *mp) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(mp);
+    return MapBytes{wide(v.x, v.y, v.z, v.w)};
+}
+
 // Global (element) offset of each of a thread's registers under a mapping.
 template <int RB, int T>
-__device__ __forceinline__ void global_offsets(const DevPass *pp, const DevMap *mp, int tbits, int tid, uint64_t base,
-                                               uint64_t (&off)[T]) {
+__device__ __forceinline__ void global_offsets(const PassBytes &pb, const MapBytes &mp, int tbits, int tid,
+                                               uint64_t base, uint64_t (&off)[T]) {
     uint64_t dth = base;
-    for (int t = 0; t < tbits; ++t) dth |= (uint64_t)((tid >> t) & 1) << pp->tile_q[mp->pos[RB + t]];
+#pragma unroll
+    for (int t = 0; t < kMaxTileQubits; ++t)
+        if (t < tbits) dth |= (uint64_t)((tid >> t) & 1) << byte_at(pb.tq, (int)byte_at(mp.pos, RB + t));
     uint64_t u[RB];
 #pragma unroll
-    for (int j = 0; j < RB; ++j) u[j] = (uint64_t)1 << pp->tile_q[mp->pos[j]];
+    for (int j = 0; j < RB; ++j) u[j] = (uint64_t)1 << byte_at(pb.tq, (int)byte_at(mp.pos, j));
 #pragma unroll
     for (int i = 0; i < T; ++i) {
         uint64_t d = dth;
@@ -303,12 +359,14 @@ __device__ __forceinline__ void global_offsets(const DevPass *pp, const DevMap *
 
 // Local (in-tile) index of each of a thread's registers under a mapping.
 template <int RB, int T>
-__device__ __forceinline__ void local_offsets(const DevMap *mp, int tbits, int tid, uint32_t (&off)[T]) {
+__device__ __forceinline__ void local_offsets(const MapBytes &mp, int tbits, int tid, uint32_t (&off)[T]) {
     uint32_t lth = 0;
-    for (int t = 0; t < tbits; ++t) lth |= (uint32_t)((tid >> t) & 1) << mp->pos[RB + t];
+#pragma unroll
+    for (int t = 0; t < kMaxTileQubits; ++t)
+        if (t < tbits) lth |= (uint32_t)((tid >> t) & 1) << byte_at(mp.pos, RB + t);
     uint32_t u[RB];
 #pragma unroll
-    for (int j = 0; j < RB; ++j) u[j] = 1u << mp->pos[j];
+    for (int j = 0; j < RB; ++j) u[j] = 1u << byte_at(mp.pos, j);
 #pragma unroll
     for (int i = 0; i < T; ++i) {
         uint32_t l = lth;
@@ -356,7 +414,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
     const LaunchItem it = items[lo];
     const DevPass *pp = passes + it.pass;
     const uint32_t tile = wg - it.tile_begin;
-    const int m = pp->m;
+    const uint4 ph0 = *reinterpret_cast<const uint4 *>(pp);          // op_begin, n_ops, slots|m|n, nrest|zsum|rb
+    const uint4 ph1 = *(reinterpret_cast<const uint4 *>(pp) + 1);    // map_load, pad, tile_q[0..7]
+    const int m = (int)((ph0.z >> 16) & 0xffu);
+    const int pass_nrest = (int)(ph0.w & 0xffu);
+    const bool pass_zsum = ((ph0.w >> 8) & 0xffu) != 0;
+    const int pass_slots = (int)(ph0.z & 0xffffu);
     const uint32_t dimT = 1u << m;
     const int tbits = m - RB;
     const int tid = threadIdx.x;
@@ -368,17 +431,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
     double2 *zs = red + kMaxSlots * kRows;                // [kRows]
 
     uint64_t base = 0;
-    for (int k = 0; k < pp->nrest; ++k) base |= (uint64_t)((tile >> k) & 1u) << pp->rest_q[k];
+    const PassBytes pbytes = load_pass_bytes(pp);
+#pragma unroll
+    for (int k = 0; k < kMaxRest; ++k)
+        if (k < pass_nrest) base |= (uint64_t)((tile >> k) & 1u) << pbytes.rest(k);
 
     C *gA = (C *)it.regA;
     C *gB = (C *)it.regB;
     Regs<CT, T> x;
 
     // ---- load
-    const DevMap *cur = maps + pp->map_load;
+    MapBytes cur = load_map(maps + ph1.x);
     {
         uint64_t off[T];
-        global_offsets<RB, T>(pp, cur, tbits, tid, base, off);
+        global_offsets<RB, T>(pbytes, cur, tbits, tid, base, off);
         if (active) {
 #pragma unroll
             for (int i = 0; i < T; ++i) {
@@ -399,7 +465,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
     }
     // plain tile sum <A|B>_tile for Z inner products on qubits outside the tile
     double Sr = 0.0, Si = 0.0;
-    if (pp->has_zsum) {
+    if (pass_zsum) {
         double sr, si;
         prod_plain<T, CT>(x, sr, si);
         row_store(zs, 0, tid, sr, si);
@@ -412,81 +478,90 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
 
     // ---- operations: one straight-line path per device op code
     const CT *__restrict__ mt = (const CT *)mats;
-    const int n_ops = (int)pp->n_ops;
-    const DevOp *op_ptr = ops + pp->op_begin;
+    const int n_ops = (int)ph0.y;
+    const DevOp *op_ptr = ops + ph0.x;
+    // The descriptor of the next op is fetched while the current one runs, and
+    // the current op's matrix row (unused entries for ops without a gate) is
+    // fetched before the dispatch, so scalar-load latency overlaps the work.
+    OpD nxt = load_op(op_ptr);
     for (int oi = 0; oi < n_ops; ++oi) {
-        const DevOp op = op_ptr[oi];
-        switch (op.type) {
+        const OpD op = nxt;
+        nxt = load_op(op_ptr + (oi + 1 < n_ops ? oi + 1 : oi));
+        const CT *mrow = mt + (size_t)(op.gate > 0 ? op.gate : 0) * 8;
+        CT mv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) mv[k] = mrow[k];
+        switch (op.type()) {
 #define QNG_REG_CASES(J)                                                                                     \
         case OPC_ROT_X + J:                                                                                  \
             if constexpr (J < RB)                                                                            \
-                rot_xy<J, 0, T, CT>(x, mat_entry(mt, op.gate, 0), mat_entry(mt, op.gate, 3),                \
-                                    mat_entry(mt, op.gate, 5), mat_entry(mt, op.gate, 6));                   \
+                rot_xy<J, 0, T, CT>(x, mv[0], mv[3],                \
+                                    mv[5], mv[6]);                   \
             break;                                                                                           \
         case OPC_ROT_Y + J:                                                                                  \
             if constexpr (J < RB)                                                                            \
-                rot_xy<J, 1, T, CT>(x, mat_entry(mt, op.gate, 0), mat_entry(mt, op.gate, 2),                \
-                                    mat_entry(mt, op.gate, 4), mat_entry(mt, op.gate, 6));                   \
+                rot_xy<J, 1, T, CT>(x, mv[0], mv[2],                \
+                                    mv[4], mv[6]);                   \
             break;                                                                                           \
         case OPC_PRODROT_X + J:                                                                              \
             if constexpr (J < RB) {                                                                          \
                 double pr, pi;                                                                               \
                 prod_xy<J, 0, T, CT>(x, pr, pi);                                                             \
-                rot_xy<J, 0, T, CT>(x, mat_entry(mt, op.gate, 0), mat_entry(mt, op.gate, 3),                \
-                                    mat_entry(mt, op.gate, 5), mat_entry(mt, op.gate, 6));                   \
-                row_store(red, op.slot, tid, pr, pi);                                                        \
+                rot_xy<J, 0, T, CT>(x, mv[0], mv[3],                \
+                                    mv[5], mv[6]);                   \
+                row_store(red, op.slot(), tid, pr, pi);                                                        \
             }                                                                                                \
             break;                                                                                           \
         case OPC_PRODROT_Y + J:                                                                              \
             if constexpr (J < RB) {                                                                          \
                 double pr, pi;                                                                               \
                 prod_xy<J, 1, T, CT>(x, pr, pi);                                                             \
-                rot_xy<J, 1, T, CT>(x, mat_entry(mt, op.gate, 0), mat_entry(mt, op.gate, 2),                \
-                                    mat_entry(mt, op.gate, 4), mat_entry(mt, op.gate, 6));                   \
-                row_store(red, op.slot, tid, pr, pi);                                                        \
+                rot_xy<J, 1, T, CT>(x, mv[0], mv[2],                \
+                                    mv[4], mv[6]);                   \
+                row_store(red, op.slot(), tid, pr, pi);                                                        \
             }                                                                                                \
             break;                                                                                           \
         case OPC_PROD_X + J:                                                                                 \
             if constexpr (J < RB) {                                                                          \
                 double pr, pi;                                                                               \
                 prod_xy<J, 0, T, CT>(x, pr, pi);                                                             \
-                row_store(red, op.slot, tid, pr, pi);                                                        \
+                row_store(red, op.slot(), tid, pr, pi);                                                        \
             }                                                                                                \
             break;                                                                                           \
         case OPC_PROD_Y + J:                                                                                 \
             if constexpr (J < RB) {                                                                          \
                 double pr, pi;                                                                               \
                 prod_xy<J, 1, T, CT>(x, pr, pi);                                                             \
-                row_store(red, op.slot, tid, pr, pi);                                                        \
+                row_store(red, op.slot(), tid, pr, pi);                                                        \
             }                                                                                                \
             break;                                                                                           \
         case OPC_PRODZ_REG + J:                                                                              \
             if constexpr (J < RB) {                                                                          \
                 double pr, pi;                                                                               \
                 prod_z_reg<J, T, CT>(x, pr, pi);                                                             \
-                row_store(red, op.slot, tid, pr, pi);                                                        \
+                row_store(red, op.slot(), tid, pr, pi);                                                        \
             }                                                                                                \
             break;                                                                                           \
         case OPC_DIAG_REG + J:                                                                               \
             if constexpr (J < RB)                                                                            \
-                diag_reg<J, T, CT>(x, mat_entry(mt, op.gate, 0), mat_entry(mt, op.gate, 1),                 \
-                                   mat_entry(mt, op.gate, 6), mat_entry(mt, op.gate, 7));                    \
+                diag_reg<J, T, CT>(x, mv[0], mv[1],                 \
+                                   mv[6], mv[7]);                    \
             break;                                                                                           \
         case OPC_PRODDIAG_REG + J:                                                                           \
             if constexpr (J < RB) {                                                                          \
                 double pr, pi;                                                                               \
                 prod_z_reg<J, T, CT>(x, pr, pi);                                                             \
-                diag_reg<J, T, CT>(x, mat_entry(mt, op.gate, 0), mat_entry(mt, op.gate, 1),                 \
-                                   mat_entry(mt, op.gate, 6), mat_entry(mt, op.gate, 7));                    \
-                row_store(red, op.slot, tid, pr, pi);                                                        \
+                diag_reg<J, T, CT>(x, mv[0], mv[1],                 \
+                                   mv[6], mv[7]);                    \
+                row_store(red, op.slot(), tid, pr, pi);                                                        \
             }                                                                                                \
             break;                                                                                           \
         case OPC_CNOT_THR + J:                                                                               \
-            if constexpr (J < RB) cnot_cond<J, T, CT>(x, (tid >> (op.b1 & 15)) & 1);                        \
+            if constexpr (J < RB) cnot_cond<J, T, CT>(x, (tid >> (op.b1() & 15)) & 1);                        \
             break;                                                                                           \
         case OPC_CNOT_BASE + J:                                                                              \
             if constexpr (J < RB) {                                                                          \
-                if ((base >> op.q0) & 1u) cnot_cond<J, T, CT>(x, true);                                     \
+                if ((base >> op.q0()) & 1u) cnot_cond<J, T, CT>(x, true);                                     \
             }                                                                                                \
             break;
 #define QNG_CNOT_REG_CASE(J, K)                                                                              \
@@ -510,23 +585,23 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
         case OPC_DIAG_THR:
         case OPC_DIAG_BASE: {
             // the Z bit is common to all registers of the thread
-            const bool thr = op.type == OPC_PRODZ_THR || op.type == OPC_PRODDIAG_THR || op.type == OPC_DIAG_THR;
-            const bool one = thr ? ((tid >> (op.b0 & 15)) & 1) : ((base >> op.q0) & 1u);
-            if (op.type != OPC_DIAG_THR && op.type != OPC_DIAG_BASE) {
+            const bool thr = op.type() == OPC_PRODZ_THR || op.type() == OPC_PRODDIAG_THR || op.type() == OPC_DIAG_THR;
+            const bool one = thr ? ((tid >> (op.b0() & 15)) & 1) : ((base >> op.q0()) & 1u);
+            if (op.type() != OPC_DIAG_THR && op.type() != OPC_DIAG_BASE) {
                 double pr, pi;
                 prod_plain<T, CT>(x, pr, pi);
                 const double sg = one ? -1.0 : 1.0;
-                row_store(red, op.slot, tid, sg * pr, sg * pi);
+                row_store(red, op.slot(), tid, sg * pr, sg * pi);
             }
-            if (op.type != OPC_PRODZ_THR && op.type != OPC_PRODZ_BASE) {
-                const CT fr = one ? mat_entry(mt, op.gate, 6) : mat_entry(mt, op.gate, 0);
-                const CT fi = one ? mat_entry(mt, op.gate, 7) : mat_entry(mt, op.gate, 1);
+            if (op.type() != OPC_PRODZ_THR && op.type() != OPC_PRODZ_BASE) {
+                const CT fr = one ? mv[6] : mv[0];
+                const CT fi = one ? mv[7] : mv[1];
                 diag_all<T, CT>(x, fr, fi);
             }
             break;
         }
         case OPC_CZ: {
-            const uint32_t neg = loc_mask<T>(op.b0, op.q0, tid, base) & loc_mask<T>(op.b1, op.q1, tid, base);
+            const uint32_t neg = loc_mask<T>(op.b0(), op.q0(), tid, base) & loc_mask<T>(op.b1(), op.q1(), tid, base);
 #pragma unroll
             for (int i = 0; i < T; ++i) {
                 const CT sg = sel<CT>((neg >> i) & 1u, (CT)-1, (CT)1);
@@ -539,13 +614,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
         }
         case OPC_ZSUM:
             if (tid == 0) {
-                const double sg = ((base >> op.q0) & 1u) ? -1.0 : 1.0;
-                red[op.slot * kRows] = make_double2(sg * Sr, sg * Si);
-                for (int w = 1; w < kRows; ++w) red[op.slot * kRows + w] = make_double2(0.0, 0.0);
+                const double sg = ((base >> op.q0()) & 1u) ? -1.0 : 1.0;
+                red[op.slot() * kRows] = make_double2(sg * Sr, sg * Si);
+                for (int w = 1; w < kRows; ++w) red[op.slot() * kRows + w] = make_double2(0.0, 0.0);
             }
             break;
         case OPC_XPOSE: {
-            const DevMap *next = maps + op.aux;
+            const MapBytes next = load_map(maps + op.aux);
             uint32_t lo_old[T], lo_new[T];
             local_offsets<RB, T>(cur, tbits, tid, lo_old);
             local_offsets<RB, T>(next, tbits, tid, lo_new);
@@ -598,7 +673,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
     // ---- store
     {
         uint64_t off[T];
-        global_offsets<RB, T>(pp, cur, tbits, tid, base, off);
+        global_offsets<RB, T>(pbytes, cur, tbits, tid, base, off);
         if (active) {
 #pragma unroll
             for (int i = 0; i < T; ++i) {
@@ -618,7 +693,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
     }
     // ---- per-tile partial sums
     __syncthreads();
-    for (int k = tid; k < pp->n_slots; k += kThreads) {
+    for (int k = tid; k < pass_slots; k += kThreads) {
         double xr = 0.0, xi = 0.0;
         for (int w = 0; w < kRows; ++w) {
             xr += red[k * kRows + w].x;

@@ -139,3 +139,63 @@ def test_plan_sizes_of_workloads(qng):
         info = qng.plan(qng.Circuit.from_problem(pr), 1, 12 if prec == "c64" else 11)
         assert info["elements"] == pr.n_params * (pr.n_params - 1) // 2
         assert info["elements"] / info["passes"] > 20
+
+
+def replay_gradient(qng, pr, tile_qubits, prec="c128"):
+    """Replay the gradient plan: lambda = H psi and phi = psi swept back from the
+    last gate; dE/dtheta_r = -Im <lambda|sigma_r|phi> (2 Re <H psi|d_r psi>
+    with d_r psi carrying (i/2) sigma_r)."""
+    circ = qng.Circuit.from_problem(pr)
+    rows = qng.plan_export(circ, tile_qubits, prec, gradient=True)
+    n, P = pr.n_qubits, pr.n_params
+    gates = pr.gates
+    rot_pos = [k for k in range(len(gates)) if gates[k, 3] >= 0]
+    rot_of_pos = {k: r for r, k in enumerate(rot_pos)}
+    neg = -pr.theta
+    psi = oracle.forward(pr)
+    lam = oracle.apply_hamiltonian(pr, psi)
+    phi = psi.copy()
+    graw = np.zeros(P, dtype=np.complex128)
+    seen = np.zeros(P, dtype=bool)
+    for r in rows:
+        s, _, kind, q0, q1, g, dest, axis = (int(v) for v in r[:8])
+        assert s == P
+        mask = int(r[8]) | (int(r[9]) << 31)
+        assert bin(mask).count("1") == min(tile_qubits or 11, n)
+        inside = lambda q: (mask >> q) & 1
+        if kind in (KIND_PROD, KIND_PROD_ADJ):
+            assert axis == 2 or inside(q0)
+            assert not seen[dest]
+            seen[dest] = True
+            graw[dest] = np.vdot(lam, oracle.apply_pauli_letter(n, q0, LETTER[axis], phi))
+            if kind == KIND_PROD_ADJ:
+                assert rot_of_pos[g] == dest
+                lam, phi = oracle.apply_gate(n, gates[g], neg, lam), oracle.apply_gate(n, gates[g], neg, phi)
+        else:
+            lam, phi = oracle.apply_gate(n, gates[g], neg, lam), oracle.apply_gate(n, gates[g], neg, phi)
+    assert seen.all()
+    grad = np.empty(P)
+    grad[gates[rot_pos, 3]] = -graw.imag
+    return grad
+
+
+@pytest.mark.parametrize("cfg,n,layers,tile", [
+    (W.config3, 9, 3, 6), (W.config5, 8, 3, 5), (W.config2, 10, 2, 7), (W.config1, 10, 3, 10),
+])
+def test_gradient_plan_replay_matches_oracle(qng, cfg, n, layers, tile):
+    pr = W.scaled(cfg, n, layers)
+    grad = replay_gradient(qng, pr, tile)
+    _, want = oracle.energy_grad(pr)
+    np.testing.assert_allclose(grad, want, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_gradient_plan_replay_random_circuits(qng, seed):
+    pr = W.random_circuit(7, 45, seed=100 + seed, fixed_fraction=0.4, n_terms=5)
+    if seed % 2:
+        pr.in_state = W.random_state(7, seed)
+    if seed % 3 == 0:
+        pr = W.permute_params(pr, seed)
+    grad = replay_gradient(qng, pr, 5)
+    _, want = oracle.energy_grad(pr)
+    np.testing.assert_allclose(grad, want, atol=1e-12)
