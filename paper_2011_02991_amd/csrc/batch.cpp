@@ -235,13 +235,21 @@ void enqueue_batch_metric(const BatchSchedule &s, const std::vector<const Circui
             const Circuit &c = *members[pr.member];
             const int sidx = s.plans[pr.member]->cols[pr.col].s;
             const Rot &rs = c.rots[sidx];
+            const Rot &rp = c.rots[sidx - 1];
             start(pr.member);
-            forward_to(pr.member, rs.pos);
-            launch_pauli_prod<R>(d.psi[pr.member], d.psi[pr.member], c.n, rs.qubit, rs.axis, d.reduce_partials,
-                                 d.traw[pr.member] + 2 * sidx, st);
+            int qr = -1;
+            const double *mrow = d.fwd_mats;
+            if (pos[pr.member] == rp.pos && rs.pos == rp.pos + 1) {
+                qr = rp.qubit;
+                mrow = d.fwd_mats + (s.gate_base[pr.member] + rp.pos) * 8;
+                pos[pr.member] = rs.pos;
+            } else {
+                forward_to(pr.member, rs.pos);
+            }
             char *lam = d.arena + pr.reg_off;
             char *phi = lam + (size_t(1) << c.n) * (size_t)s.amp;
-            launch_seed<R>(d.psi[pr.member], lam, phi, c.n, rs.qubit, rs.axis, st);
+            launch_advance_seed<R>(d.psi[pr.member], lam, phi, c.n, qr, mrow, rs.qubit, rs.axis, d.reduce_partials,
+                                   d.traw[pr.member] + 2 * sidx, st);
         }
         if (events) BCHECK(hipEventRecord((*events)[2 * li], st));
         launch_sweep_pass<R>(items + L.item_begin, (int)L.n_items, L.total_tiles, passes, ops, maps, d.adj_mats,

@@ -37,6 +37,7 @@ size_t fused_scratch_bytes(const SweepPlan &plan, const FusedRun &fr, int M) {
     size_t b = 0;
     b += align256((size_t)M * 64 + 64);                                  // matrix table (FP64)
     b += align256((size_t)M * 32 + 64);                                  // matrix table (FP32)
+    b += align256((size_t)M * 64 + 64);                                  // forward matrices (FP64)
     b += align256(plan.dev_passes.size() * sizeof(DevPass) + 64);       // passes
     b += align256(plan.dev_ops.size() * sizeof(DevOp) + 64);            // ops
     b += align256(plan.dev_maps.size() * sizeof(DevMap) + 64);          // thread mappings
@@ -105,18 +106,23 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
     }
 
     // ---- device images
-    std::vector<double> mats((size_t)c.M * 8, 0.0);
+    std::vector<double> mats((size_t)c.M * 8, 0.0), fmats((size_t)c.M * 8, 0.0);
     for (const Rot &r : c.rots) {
-        const Mat2 &m = adj[r.pos];
-        double *d = &mats[(size_t)r.pos * 8];
-        d[0] = m.a.real(); d[1] = m.a.imag(); d[2] = m.b.real(); d[3] = m.b.imag();
-        d[4] = m.c.real(); d[5] = m.c.imag(); d[6] = m.d.real(); d[7] = m.d.imag();
+        const Mat2 *src[2] = {&adj[r.pos], &fwd[r.pos]};
+        double *dst[2] = {&mats[(size_t)r.pos * 8], &fmats[(size_t)r.pos * 8]};
+        for (int w = 0; w < 2; ++w) {
+            const Mat2 &m = *src[w];
+            double *d = dst[w];
+            d[0] = m.a.real(); d[1] = m.a.imag(); d[2] = m.b.real(); d[3] = m.b.imag();
+            d[4] = m.c.real(); d[5] = m.c.imag(); d[6] = m.d.real(); d[7] = m.d.imag();
+        }
     }
     std::vector<float> mats32(mats.begin(), mats.end());
     char *p = buf.scratch;
     auto take = [&](size_t bytes) { char *o = p; p += align256(bytes + 64); return o; };
     double *d_mats = (double *)take(mats.size() * 8);
     float *d_mats32 = (float *)take(mats32.size() * 4);
+    double *d_fmats = (double *)take(fmats.size() * 8);
     DevPass *d_passes = (DevPass *)take(plan.dev_passes.size() * sizeof(DevPass));
     DevOp *d_ops = (DevOp *)take(plan.dev_ops.size() * sizeof(DevOp));
     DevMap *d_maps = (DevMap *)take(plan.dev_maps.size() * sizeof(DevMap));
@@ -128,6 +134,7 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
     if (!mats.empty()) {
         FCHECK(hipMemcpyAsync(d_mats, mats.data(), mats.size() * 8, hipMemcpyHostToDevice, st));
         FCHECK(hipMemcpyAsync(d_mats32, mats32.data(), mats32.size() * 4, hipMemcpyHostToDevice, st));
+        FCHECK(hipMemcpyAsync(d_fmats, fmats.data(), fmats.size() * 8, hipMemcpyHostToDevice, st));
     }
     if (!plan.dev_passes.empty())
         FCHECK(hipMemcpyAsync(d_passes, plan.dev_passes.data(), plan.dev_passes.size() * sizeof(DevPass),
@@ -170,11 +177,22 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
         for (int col = G.col_begin; col < G.col_end; ++col) {
             const int s = plan.cols[col].s;
             const Rot &rs = c.rots[s];
+            const Rot &rp = c.rots[s - 1];
             const int b = col - G.col_begin;
-            forward_to(rs.pos);
-            launch_pauli_prod<R>(psi, psi, n, rs.qubit, rs.axis, buf.reduce_partials, buf.traw + 2 * s, st);
-            launch_seed<R>(psi, state(1 + 2 * b), state(2 + 2 * b), n, rs.qubit, rs.axis, st);
-            stats->other_launches += 3;
+            // y_s = R_{s-1} y_{s-1} when rotation s-1 is the only gate in between:
+            // one pass advances psi, seeds the column and takes T_s
+            int qr = -1;
+            const double *mrow = d_fmats;
+            if (pos == rp.pos && rs.pos == rp.pos + 1) {
+                qr = rp.qubit;
+                mrow = d_fmats + (size_t)rp.pos * 8;
+                pos = rs.pos;
+            } else {
+                forward_to(rs.pos);
+            }
+            launch_advance_seed<R>(psi, state(1 + 2 * b), state(2 + 2 * b), n, qr, mrow, rs.qubit, rs.axis,
+                                   buf.reduce_partials, buf.traw + 2 * s, st);
+            stats->other_launches += 2;
         }
         for (size_t li = G.launch_begin; li < G.launch_end; ++li) {
             const Launch &L = launches[li];

@@ -221,6 +221,80 @@ __global__ void k_reduce_final(const double *partials, int nb, double *dest) {
     block_reduce_store(sr, si, dest);
 }
 
+// ------------------------------------------------------------------ column start
+
+// sigma (axis 0/1/2 = X/Y/Z) on the pair (u, v): (o0, o1)
+template <typename C>
+__device__ __forceinline__ void pauli_pair(int axis, const C &u, const C &v, C &o0, C &o1) {
+    if (axis == 0) { o0 = v; o1 = u; }
+    else if (axis == 1) { o0.x = v.y; o0.y = -v.x; o1.x = -u.y; o1.y = u.x; }
+    else { o0 = u; o1.x = -v.x; o1.y = -v.y; }
+}
+
+// One pass over the forward register for the start of a column s:
+//   psi <- R psi (the rotation just before y_s, matrix mt; qr < 0: none),
+//   lam = psi, phi = sigma_s psi, and the block partials of <psi|sigma_s|psi>.
+// (Replaces apply + inner product + seed, which read psi three times.)
+template <typename R>
+__global__ void k_advance_seed(typename Cplx<R>::T *psi, typename Cplx<R>::T *lam, typename Cplx<R>::T *phi, int n,
+                               int qr, const double *__restrict__ mt, int qs, int axis, double *partials) {
+    using C = typename Cplx<R>::T;
+    R ar = 0, ai = 0, br = 0, bi = 0, cr = 0, ci = 0, dr = 0, di = 0;
+    if (qr >= 0) {
+        ar = (R)mt[0]; ai = (R)mt[1]; br = (R)mt[2]; bi = (R)mt[3];
+        cr = (R)mt[4]; ci = (R)mt[5]; dr = (R)mt[6]; di = (R)mt[7];
+    }
+    auto rot = [&](C &u, C &v) {
+        const C a = u, b = v;
+        u.x = ar * a.x - ai * a.y + br * b.x - bi * b.y;
+        u.y = ar * a.y + ai * a.x + br * b.y + bi * b.x;
+        v.x = cr * a.x - ci * a.y + dr * b.x - di * b.y;
+        v.y = cr * a.y + ci * a.x + dr * b.y + di * b.x;
+    };
+    double sr = 0.0, si = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    const uint64_t ms = uint64_t(1) << qs;
+    if (qr < 0 || qr == qs) {
+        const uint64_t npairs = uint64_t(1) << (n - 1);
+        for (uint64_t p = blockIdx.x * (uint64_t)kBlock + threadIdx.x; p < npairs; p += stride) {
+            const uint64_t i0 = insert_zero(p, qs), i1 = i0 | ms;
+            C u = psi[i0], v = psi[i1];
+            if (qr >= 0) {
+                rot(u, v);
+                psi[i0] = u;
+                psi[i1] = v;
+            }
+            C o0, o1;
+            pauli_pair(axis, u, v, o0, o1);
+            lam[i0] = u; lam[i1] = v;
+            phi[i0] = o0; phi[i1] = o1;
+            cmac(sr, si, u.x, u.y, o0.x, o0.y);
+            cmac(sr, si, v.x, v.y, o1.x, o1.y);
+        }
+    } else {
+        const uint64_t mr = uint64_t(1) << qr;
+        const int lo = qr < qs ? qr : qs, hi = qr < qs ? qs : qr;
+        const uint64_t nq = uint64_t(1) << (n - 2);
+        for (uint64_t p = blockIdx.x * (uint64_t)kBlock + threadIdx.x; p < nq; p += stride) {
+            const uint64_t b = insert_two_zeros(p, lo, hi);
+            C y00 = psi[b], y10 = psi[b | mr], y01 = psi[b | ms], y11 = psi[b | mr | ms];
+            rot(y00, y10);
+            rot(y01, y11);
+            psi[b] = y00; psi[b | mr] = y10; psi[b | ms] = y01; psi[b | mr | ms] = y11;
+            lam[b] = y00; lam[b | mr] = y10; lam[b | ms] = y01; lam[b | mr | ms] = y11;
+            C o00, o01, o10, o11;
+            pauli_pair(axis, y00, y01, o00, o01);
+            pauli_pair(axis, y10, y11, o10, o11);
+            phi[b] = o00; phi[b | ms] = o01; phi[b | mr] = o10; phi[b | mr | ms] = o11;
+            cmac(sr, si, y00.x, y00.y, o00.x, o00.y);
+            cmac(sr, si, y01.x, y01.y, o01.x, o01.y);
+            cmac(sr, si, y10.x, y10.y, o10.x, o10.y);
+            cmac(sr, si, y11.x, y11.y, o11.x, o11.y);
+        }
+    }
+    block_reduce_store(sr, si, partials + 2 * blockIdx.x);
+}
+
 // ------------------------------------------------------------------ Hamiltonian
 
 template <typename R>
@@ -340,6 +414,17 @@ void launch_pauli_prod(const void *a, const void *b, int n, int q, int axis, dou
 }
 
 template <typename R>
+void launch_advance_seed(void *psi, void *lam, void *phi, int n, int qr, const double *m_dev, int qs, int axis,
+                         double *partials, double *dest, hipStream_t st) {
+    const int nb = reduce_blocks(n);
+    hipLaunchKernelGGL(k_advance_seed<R>, dim3(nb), dim3(kBlock), 0, st, (typename Cplx<R>::T *)psi,
+                       (typename Cplx<R>::T *)lam, (typename Cplx<R>::T *)phi, n, qr, m_dev, qs, axis, partials);
+    check_launch();
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, st, (const double *)partials, nb, dest);
+    check_launch();
+}
+
+template <typename R>
 void launch_pauli_term(const void *psi, void *out, int n, uint64_t flip, uint64_t zy, int n_y, double coeff, int first,
                        hipStream_t st) {
     // coeff * (-i)^{n_y}
@@ -376,6 +461,8 @@ void launch_grad_from_raw(const double *graw, const int *param_of, int P, double
     template void launch_cz<R>(void *, void *, int, int, int, hipStream_t);                                       \
     template void launch_seed<R>(const void *, void *, void *, int, int, int, hipStream_t);                      \
     template void launch_pauli_prod<R>(const void *, const void *, int, int, int, double *, double *, hipStream_t); \
+    template void launch_advance_seed<R>(void *, void *, void *, int, int, const double *, int, int, double *,       \
+                                         double *, hipStream_t);                                                  \
     template void launch_pauli_term<R>(const void *, void *, int, uint64_t, uint64_t, int, double, int, hipStream_t);
 
 QNG_INSTANTIATE(double)

@@ -37,6 +37,14 @@ template <typename R> void launch_cz(void *s0, void *s1, int n, int a, int b, hi
 // lam = y; phi = sigma_q y  (axis 0/1/2 = X/Y/Z).
 template <typename R> void launch_seed(const void *y, void *lam, void *phi, int n, int q, int axis, hipStream_t st);
 
+// Start of a metric column in one pass over the forward register:
+// psi <- R psi (R: the rotation on qubit qr whose matrix is m_dev, 8 doubles;
+// qr < 0: no gate), lam = psi, phi = sigma_qs psi (axis 0/1/2 = X/Y/Z) and
+// dest (one complex128) = <psi| sigma_qs |psi>.  partials: reduce_blocks(n) complex128.
+template <typename R>
+void launch_advance_seed(void *psi, void *lam, void *phi, int n, int qr, const double *m_dev, int qs, int axis,
+                         double *partials, double *dest, hipStream_t st);
+
 // dest (one complex128) = <a| sigma_q |b>; axis -1 means the identity (plain inner product).
 // partials: reduce_blocks(n) complex128 scratch.
 template <typename R>

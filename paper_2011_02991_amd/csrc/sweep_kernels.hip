@@ -703,21 +703,36 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_reduce_tasks(const ReduceTask *__restrict__ tasks,
-                                                           const double2 *__restrict__ partials,
-                                                           double2 *__restrict__ results) {
-    __shared__ double sr[kThreads], si[kThreads];
+// One work-group per task sums the task's per-tile partials in a fixed order
+// (bitwise reproducible): 1024 threads, four independent loads in flight per
+// thread, then a tree over the threads.
+constexpr int kReduceThreads = 1024;
+
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_tasks(const ReduceTask *__restrict__ tasks,
+                                                                 const double2 *__restrict__ partials,
+                                                                 double2 *__restrict__ results) {
+    __shared__ double sr[kReduceThreads], si[kReduceThreads];
     const ReduceTask t = tasks[blockIdx.x];
-    double a = 0.0, b = 0.0;
-    for (uint32_t k = threadIdx.x; k < t.count; k += kThreads) {
-        const double2 v = partials[t.off + k];
-        a += v.x;
-        b += v.y;
+    const double2 *p = partials + t.off;
+    double a0 = 0.0, b0 = 0.0, a1 = 0.0, b1 = 0.0, a2 = 0.0, b2 = 0.0, a3 = 0.0, b3 = 0.0;
+    uint32_t k = threadIdx.x;
+    for (; k + 3 * kReduceThreads < t.count; k += 4 * kReduceThreads) {
+        const double2 v0 = p[k], v1 = p[k + kReduceThreads], v2 = p[k + 2 * kReduceThreads],
+                      v3 = p[k + 3 * kReduceThreads];
+        a0 += v0.x; b0 += v0.y;
+        a1 += v1.x; b1 += v1.y;
+        a2 += v2.x; b2 += v2.y;
+        a3 += v3.x; b3 += v3.y;
     }
-    sr[threadIdx.x] = a;
-    si[threadIdx.x] = b;
+    for (; k < t.count; k += kReduceThreads) {
+        const double2 v = p[k];
+        a0 += v.x;
+        b0 += v.y;
+    }
+    sr[threadIdx.x] = (a0 + a1) + (a2 + a3);
+    si[threadIdx.x] = (b0 + b1) + (b2 + b3);
     __syncthreads();
-    for (int w = kThreads / 2; w > 0; w >>= 1) {
+    for (int w = kReduceThreads / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) {
             sr[threadIdx.x] += sr[threadIdx.x + w];
             si[threadIdx.x] += si[threadIdx.x + w];
@@ -786,8 +801,8 @@ void launch_sweep_pass(const LaunchItem *items, int n_items, uint32_t total_tile
 void launch_reduce_tasks(const ReduceTask *tasks, int n_tasks, const double *partials, double *results,
                          hipStream_t st) {
     if (n_tasks <= 0) return;
-    hipLaunchKernelGGL(k_reduce_tasks, dim3(n_tasks), dim3(kThreads), 0, st, tasks, (const double2 *)partials,
-                       (double2 *)results);
+    hipLaunchKernelGGL(k_reduce_tasks, dim3(n_tasks), dim3(kReduceThreads), 0, st, tasks,
+                       (const double2 *)partials, (double2 *)results);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) throw e;
 }
