@@ -625,14 +625,13 @@ BatchRun batch_metric(qng_ctx *ctx, const std::vector<Problem> &pbs, const doubl
             d.psi.push_back(base + L.psi[mem[i]]);
             d.traw.push_back((double *)(base + L.traw[mem[i]]));
             for (const Rot &r : pb.circ.rots) {
-                const Mat2 *src[2] = {&pb.fwd[r.pos], &pb.adj[r.pos]};
-                double *dst[2] = {&fm[(size_t)(S.gate_base[i] + r.pos) * 8], &am[(size_t)(S.gate_base[i] + r.pos) * 8]};
-                for (int w = 0; w < 2; ++w) {
-                    const Mat2 &m = *src[w];
-                    double *o = dst[w];
-                    o[0] = m.a.real(); o[1] = m.a.imag(); o[2] = m.b.real(); o[3] = m.b.imag();
-                    o[4] = m.c.real(); o[5] = m.c.imag(); o[6] = m.d.real(); o[7] = m.d.imag();
-                }
+                const Mat2 &m = pb.fwd[r.pos];
+                double *o = &fm[(size_t)(S.gate_base[i] + r.pos) * 8];
+                o[0] = m.a.real(); o[1] = m.a.imag(); o[2] = m.b.real(); o[3] = m.b.imag();
+                o[4] = m.c.real(); o[5] = m.c.imag(); o[6] = m.d.real(); o[7] = m.d.imag();
+                const Shear sh = adjoint_shear(r.axis, pb.adj[r.pos]);
+                am[(size_t)(S.gate_base[i] + r.pos) * 8 + 0] = sh.u;
+                am[(size_t)(S.gate_base[i] + r.pos) * 8 + 1] = sh.w;
             }
         }
         std::vector<float> am32(am.begin(), am.end());

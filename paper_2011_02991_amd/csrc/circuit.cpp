@@ -100,6 +100,20 @@ Mat2 rotation(int axis, double theta) {
 
 Mat2 adjoint(const Mat2 &m) { return Mat2{std::conj(m.a), std::conj(m.c), std::conj(m.b), std::conj(m.d)}; }
 
+Shear adjoint_shear(int axis, const Mat2 &adj) {
+    double c = adj.a.real(), s;
+    switch (axis) {
+    case AX_X: s = -adj.b.imag(); break;   // adjoint b = -i sin
+    case AX_Y: s = adj.b.real(); break;    // adjoint b = -sin
+    default: s = -adj.a.imag(); break;     // adjoint a = cos - i sin
+    }
+    if (c < 0) {
+        c = -c;
+        s = -s;
+    }
+    return Shear{s / (1.0 + c), -s};
+}
+
 std::vector<PauliTerm> compile_hamiltonian(const qng_circuit *c, const qng_pauli_sum *h) {
     std::vector<PauliTerm> out(h->n_terms);
     for (int t = 0; t < h->n_terms; ++t) {

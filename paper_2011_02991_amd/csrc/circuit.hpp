@@ -60,6 +60,18 @@ Circuit compile_circuit(const qng_circuit *c);
 Mat2 rotation(int axis, double theta);
 Mat2 adjoint(const Mat2 &m);
 
+// On pairs of real numbers, every adjoint rotation is the plane rotation
+// [[c, s], [-s, c]]: RX on (re x0, im x1) and (re x1, im x0), RY on (re x0,
+// re x1) and (im x0, im x1), RZ on (re x, im x) of the |0> amplitude and with s
+// negated for the |1> amplitude.  The sweep applies it in place as three shears
+//   a += u b;  b += w a;  a += u b,   u = s / (1 + c), w = -s.
+// A rotation with c < 0 is applied as its negative (the same sign on both
+// registers of a sweep cancels in every <lambda|sigma|phi>), so |u| <= 1.
+struct Shear {
+    double u, w;
+};
+Shear adjoint_shear(int axis, const Mat2 &adj);
+
 // Pauli string in bit-mask form: (sigma psi)[x] = (-i)^{nY} (-1)^{popcount(x & zy)} psi[x ^ flip],
 // with flip = positions of X and Y letters, zy = positions of Z and Y letters
 // (Y = -i (-1)^{x_q} on the flipped bit: Y|0> = i|1>, Y|1> = -i|0>).

@@ -108,14 +108,13 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
     // ---- device images
     std::vector<double> mats((size_t)c.M * 8, 0.0), fmats((size_t)c.M * 8, 0.0);
     for (const Rot &r : c.rots) {
-        const Mat2 *src[2] = {&adj[r.pos], &fwd[r.pos]};
-        double *dst[2] = {&mats[(size_t)r.pos * 8], &fmats[(size_t)r.pos * 8]};
-        for (int w = 0; w < 2; ++w) {
-            const Mat2 &m = *src[w];
-            double *d = dst[w];
-            d[0] = m.a.real(); d[1] = m.a.imag(); d[2] = m.b.real(); d[3] = m.b.imag();
-            d[4] = m.c.real(); d[5] = m.c.imag(); d[6] = m.d.real(); d[7] = m.d.imag();
-        }
+        const Mat2 &m = fwd[r.pos];
+        double *d = &fmats[(size_t)r.pos * 8];
+        d[0] = m.a.real(); d[1] = m.a.imag(); d[2] = m.b.real(); d[3] = m.b.imag();
+        d[4] = m.c.real(); d[5] = m.c.imag(); d[6] = m.d.real(); d[7] = m.d.imag();
+        const Shear sh = adjoint_shear(r.axis, adj[r.pos]);
+        mats[(size_t)r.pos * 8 + 0] = sh.u;
+        mats[(size_t)r.pos * 8 + 1] = sh.w;
     }
     std::vector<float> mats32(mats.begin(), mats.end());
     char *p = buf.scratch;
@@ -262,10 +261,9 @@ void run_fused_gradient(const SweepPlan &g, const Circuit &c, const std::vector<
     task_begin.push_back((uint32_t)tasks.size());
     std::vector<double> mats((size_t)c.M * 8, 0.0);
     for (const Rot &r : c.rots) {
-        const Mat2 &m = adj[r.pos];
-        double *d = &mats[(size_t)r.pos * 8];
-        d[0] = m.a.real(); d[1] = m.a.imag(); d[2] = m.b.real(); d[3] = m.b.imag();
-        d[4] = m.c.real(); d[5] = m.c.imag(); d[6] = m.d.real(); d[7] = m.d.imag();
+        const Shear sh = adjoint_shear(r.axis, adj[r.pos]);
+        mats[(size_t)r.pos * 8 + 0] = sh.u;
+        mats[(size_t)r.pos * 8 + 1] = sh.w;
     }
     std::vector<float> mats32(mats.begin(), mats.end());
     char *p = scratch;

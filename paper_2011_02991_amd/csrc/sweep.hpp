@@ -212,8 +212,9 @@ struct FusedRun {
 FusedRun fused_config(const SweepPlan &plan, int requested_streams, size_t state_bytes, size_t free_bytes);
 
 // Kernel launchers (sweep_kernels.hip).
-// mats64 / mats32: the adjoint gate matrices (8 values per gate position) in
-// FP64 and FP32; the kernel reads the table of its register precision.
+// mats64 / mats32: per gate position 8 values, of which the first two are the
+// shear parameters (u, w) of the gate's adjoint (circuit.hpp, adjoint_shear),
+// in FP64 and FP32; the kernel reads the table of its register precision.
 template <typename R>
 void launch_sweep_pass(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
                        const DevOp *ops, const DevMap *maps, const double *mats64, const float *mats32,

@@ -65,10 +65,14 @@ __device__ __forceinline__ void row_sum(double &a, double &b) {
     b += dpp_shifted<0x118>(b);
 }
 
-// Store a per-lane partial of slot `slot`: one value per 16-lane row.
+// Store a per-lane partial of slot `slot`: one value per 16-lane row.  Every
+// lane stores (lane 15 of a row to the slot, the others to a sink entry of their
+// own), so the op loop has no divergent branch.
 __device__ __forceinline__ void row_store(double2 *red, int slot, int tid, double a, double b) {
     row_sum(a, b);
-    if ((tid & 15) == 15) red[slot * kRows + (tid >> 4)] = make_double2(a, b);
+    double2 *sink = red + (kMaxSlots + 1) * kRows;
+    double2 *dst = ((tid & 15) == 15) ? red + slot * kRows + (tid >> 4) : sink + tid;
+    *dst = make_double2(a, b);
 }
 
 // The tile is kept as four short vectors per thread: real and imaginary parts
@@ -178,69 +182,74 @@ __device__ __forceinline__ void prod_plain(const Regs<CT, T> &x, double &pr, dou
 
 // ------------------------------------------------------- gates on registers
 
-// Adjoint X/Y rotation on the pairs of register bit J.  RX adjoint
-// [[c, -is], [-is, c]] and RY adjoint [[c, -s], [s, c]] have exact zeros, so
-// each output is two products; the table entries used are (a_re, b_im, c_im,
-// d_re) for X and (a_re, b_re, c_re, d_re) for Y.
+// Every adjoint rotation is, on pairs of reals, the plane rotation
+// [[c, s], [-s, c]] applied in place as three shears (u = s / (1 + c), w = -s;
+// rotations with c < 0 arrive negated, a sign both registers share):
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename CT>
+struct Pair {
+    CT a, b;
+};
+template <typename CT>
+__device__ __forceinline__ Pair<CT> shear3(CT a, CT b, CT u, CT w) {
+    a = fmadd(u, b, a);
+    b = fmadd(w, a, b);
+    a = fmadd(u, b, a);
+    return Pair<CT>{a, b};
+}
+// (A, B) <- shears of (A, B); A and B are register-vector elements
+#define QNG_SHEAR(A, B, U, W)                   \
+    do {                                        \
+        const Pair<CT> r_ = shear3(A, B, U, W); \
+        A = r_.a;                               \
+        B = r_.b;                               \
+    } while (0)
+
+// Adjoint X/Y rotation on the pairs of register bit J: RX on (re x0, im x1)
+// and (re x1, im x0), RY on (re x0, re x1) and (im x0, im x1).
 template <int J, int AX, int T, typename CT>
-__device__ __forceinline__ void rot_xy(Regs<CT, T> &x, CT m0, CT m1, CT m2, CT m3) {
+__device__ __forceinline__ void rot_xy(Regs<CT, T> &x, CT u, CT w) {
 #pragma unroll
     for (int i = 0; i < T; ++i) {
         if (i & (1 << J)) continue;
         const int k = i | (1 << J);
         if (AX == 0) {
-            CT ur = x.ar[i], ui = x.ai[i], vr = x.ar[k], vi = x.ai[k];
-            x.ar[i] = m0 * ur - m1 * vi;
-            x.ai[i] = m0 * ui + m1 * vr;
-            x.ar[k] = m3 * vr - m2 * ui;
-            x.ai[k] = m3 * vi + m2 * ur;
-            ur = x.br[i]; ui = x.bi[i]; vr = x.br[k]; vi = x.bi[k];
-            x.br[i] = m0 * ur - m1 * vi;
-            x.bi[i] = m0 * ui + m1 * vr;
-            x.br[k] = m3 * vr - m2 * ui;
-            x.bi[k] = m3 * vi + m2 * ur;
+            QNG_SHEAR(x.ar[i], x.ai[k], u, w);
+            QNG_SHEAR(x.ar[k], x.ai[i], u, w);
+            QNG_SHEAR(x.br[i], x.bi[k], u, w);
+            QNG_SHEAR(x.br[k], x.bi[i], u, w);
         } else {
-            CT ur = x.ar[i], ui = x.ai[i], vr = x.ar[k], vi = x.ai[k];
-            x.ar[i] = m0 * ur + m1 * vr;
-            x.ai[i] = m0 * ui + m1 * vi;
-            x.ar[k] = m2 * ur + m3 * vr;
-            x.ai[k] = m2 * ui + m3 * vi;
-            ur = x.br[i]; ui = x.bi[i]; vr = x.br[k]; vi = x.bi[k];
-            x.br[i] = m0 * ur + m1 * vr;
-            x.bi[i] = m0 * ui + m1 * vi;
-            x.br[k] = m2 * ur + m3 * vr;
-            x.bi[k] = m2 * ui + m3 * vi;
+            QNG_SHEAR(x.ar[i], x.ar[k], u, w);
+            QNG_SHEAR(x.ai[i], x.ai[k], u, w);
+            QNG_SHEAR(x.br[i], x.br[k], u, w);
+            QNG_SHEAR(x.bi[i], x.bi[k], u, w);
         }
     }
 }
 
-// x <- f x for amplitude i of both registers (complex product)
-template <int T, typename CT>
-__device__ __forceinline__ void cmul_at(Regs<CT, T> &x, int i, CT fr, CT fi) {
-    CT ur = x.ar[i], ui = x.ai[i];
-    x.ar[i] = fr * ur - fi * ui;
-    x.ai[i] = fr * ui + fi * ur;
-    ur = x.br[i];
-    ui = x.bi[i];
-    x.br[i] = fr * ur - fi * ui;
-    x.bi[i] = fr * ui + fi * ur;
-}
-
-// RZ adjoint diag(d0, d1) on register bit J
+// RZ adjoint on register bit J: (re, im) of the |0> amplitude rotated by
+// (u, w), of the |1> amplitude by (-u, -w)
 template <int J, int T, typename CT>
-__device__ __forceinline__ void diag_reg(Regs<CT, T> &x, CT d0r, CT d0i, CT d1r, CT d1i) {
+__device__ __forceinline__ void diag_reg(Regs<CT, T> &x, CT u, CT w) {
 #pragma unroll
     for (int i = 0; i < T; ++i) {
         const bool one = (i >> J) & 1;
-        cmul_at<T, CT>(x, i, one ? d1r : d0r, one ? d1i : d0i);
+        const CT ui = one ? -u : u, wi = one ? -w : w;
+        QNG_SHEAR(x.ar[i], x.ai[i], ui, wi);
+        QNG_SHEAR(x.br[i], x.bi[i], ui, wi);
     }
 }
 
-// one factor for every register (bit held by the thread index or the tile base)
+// one rotation for every register (bit held by the thread index or the tile base)
 template <int T, typename CT>
-__device__ __forceinline__ void diag_all(Regs<CT, T> &x, CT fr, CT fi) {
+__device__ __forceinline__ void diag_all(Regs<CT, T> &x, CT u, CT w) {
 #pragma unroll
-    for (int i = 0; i < T; ++i) cmul_at<T, CT>(x, i, fr, fi);
+    for (int i = 0; i < T; ++i) {
+        QNG_SHEAR(x.ar[i], x.ai[i], u, w);
+        QNG_SHEAR(x.br[i], x.bi[i], u, w);
+    }
 }
 
 // value select (by-value operands keep the choice on registers, not on addresses)
@@ -392,7 +401,7 @@ __device__ __forceinline__ uint32_t loc_mask(uint8_t loc, uint8_t q, int tid, ui
     return v ? all : 0u;
 }
 
-template <typename R, typename CT, int RB>
+template <typename R, typename CT, int RB, bool FULL>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 4 ? 1 : 3, 8))) void k_sweep_reg(const LaunchItem *__restrict__ items, int n_items,
                                                         const DevPass *__restrict__ passes,
                                                         const DevOp *__restrict__ ops,
@@ -423,7 +432,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
     const uint32_t dimT = 1u << m;
     const int tbits = m - RB;
     const int tid = threadIdx.x;
-    const bool active = (tid >> tbits) == 0;
+    // FULL: the tile has exactly kThreads * T amplitudes, every thread holds a
+    // part of it (no divergent branches around the exchanges)
+    const bool active = FULL || (tid >> tbits) == 0;
 
     using CX = typename Amp<CT>::T;
     CX *xbuf = (CX *)smem;                                // [2^m] exchange buffer
@@ -488,27 +499,24 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
         const OpD op = nxt;
         nxt = load_op(op_ptr + (oi + 1 < n_ops ? oi + 1 : oi));
         const CT *mrow = mt + (size_t)(op.gate > 0 ? op.gate : 0) * 8;
-        CT mv[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) mv[k] = mrow[k];
+        CT mv[2];
+        mv[0] = mrow[0];
+        mv[1] = mrow[1];
         switch (op.type()) {
 #define QNG_REG_CASES(J)                                                                                     \
         case OPC_ROT_X + J:                                                                                  \
             if constexpr (J < RB)                                                                            \
-                rot_xy<J, 0, T, CT>(x, mv[0], mv[3],                \
-                                    mv[5], mv[6]);                   \
+                rot_xy<J, 0, T, CT>(x, mv[0], mv[1]);                   \
             break;                                                                                           \
         case OPC_ROT_Y + J:                                                                                  \
             if constexpr (J < RB)                                                                            \
-                rot_xy<J, 1, T, CT>(x, mv[0], mv[2],                \
-                                    mv[4], mv[6]);                   \
+                rot_xy<J, 1, T, CT>(x, mv[0], mv[1]);                   \
             break;                                                                                           \
         case OPC_PRODROT_X + J:                                                                              \
             if constexpr (J < RB) {                                                                          \
                 double pr, pi;                                                                               \
                 prod_xy<J, 0, T, CT>(x, pr, pi);                                                             \
-                rot_xy<J, 0, T, CT>(x, mv[0], mv[3],                \
-                                    mv[5], mv[6]);                   \
+                rot_xy<J, 0, T, CT>(x, mv[0], mv[1]);                   \
                 row_store(red, op.slot(), tid, pr, pi);                                                        \
             }                                                                                                \
             break;                                                                                           \
@@ -516,8 +524,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
             if constexpr (J < RB) {                                                                          \
                 double pr, pi;                                                                               \
                 prod_xy<J, 1, T, CT>(x, pr, pi);                                                             \
-                rot_xy<J, 1, T, CT>(x, mv[0], mv[2],                \
-                                    mv[4], mv[6]);                   \
+                rot_xy<J, 1, T, CT>(x, mv[0], mv[1]);                   \
                 row_store(red, op.slot(), tid, pr, pi);                                                        \
             }                                                                                                \
             break;                                                                                           \
@@ -544,15 +551,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
             break;                                                                                           \
         case OPC_DIAG_REG + J:                                                                               \
             if constexpr (J < RB)                                                                            \
-                diag_reg<J, T, CT>(x, mv[0], mv[1],                 \
-                                   mv[6], mv[7]);                    \
+                diag_reg<J, T, CT>(x, mv[0], mv[1]);                    \
             break;                                                                                           \
         case OPC_PRODDIAG_REG + J:                                                                           \
             if constexpr (J < RB) {                                                                          \
                 double pr, pi;                                                                               \
                 prod_z_reg<J, T, CT>(x, pr, pi);                                                             \
-                diag_reg<J, T, CT>(x, mv[0], mv[1],                 \
-                                   mv[6], mv[7]);                    \
+                diag_reg<J, T, CT>(x, mv[0], mv[1]);                    \
                 row_store(red, op.slot(), tid, pr, pi);                                                        \
             }                                                                                                \
             break;                                                                                           \
@@ -593,11 +598,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
                 const double sg = one ? -1.0 : 1.0;
                 row_store(red, op.slot(), tid, sg * pr, sg * pi);
             }
-            if (op.type() != OPC_PRODZ_THR && op.type() != OPC_PRODZ_BASE) {
-                const CT fr = one ? mv[6] : mv[0];
-                const CT fi = one ? mv[7] : mv[1];
-                diag_all<T, CT>(x, fr, fi);
-            }
+            if (op.type() != OPC_PRODZ_THR && op.type() != OPC_PRODZ_BASE)
+                diag_all<T, CT>(x, one ? -mv[0] : mv[0], one ? -mv[1] : mv[1]);
             break;
         }
         case OPC_CZ: {
@@ -743,22 +745,35 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_tasks(const ReduceTas
 }
 
 template <typename CT> size_t smem_bytes(int m) {
-    return ((size_t)1 << m) * sizeof(typename Amp<CT>::T) + (size_t)(kMaxSlots + 1) * kRows * sizeof(double2);
+    return ((size_t)1 << m) * sizeof(typename Amp<CT>::T) + (size_t)(kMaxSlots + 1) * kRows * sizeof(double2) +
+           (size_t)kThreads * sizeof(double2);
 }
 
-template <typename R, typename CT, int RB>
-void launch_rb(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes, const DevOp *ops,
-               const DevMap *maps, const CT *mats, double *partials, int m, hipStream_t st) {
+template <typename R, typename CT, int RB, bool FULL>
+void launch_full(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes, const DevOp *ops,
+                 const DevMap *maps, const CT *mats, double *partials, int m, hipStream_t st) {
     const size_t smem = smem_bytes<CT>(m);
     static size_t attr_set = 0;
     if (smem > attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_sweep_reg<R, CT, RB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)smem);
+        (void)hipFuncSetAttribute((const void *)k_sweep_reg<R, CT, RB, FULL>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         (void)hipGetLastError();
         attr_set = smem;
     }
-    hipLaunchKernelGGL((k_sweep_reg<R, CT, RB>), dim3(total_tiles), dim3(kThreads), smem, st, items, n_items, passes,
-                       ops, maps, (const void *)mats, (double2 *)partials);
+    hipLaunchKernelGGL((k_sweep_reg<R, CT, RB, FULL>), dim3(total_tiles), dim3(kThreads), smem, st, items, n_items,
+                       passes, ops, maps, (const void *)mats, (double2 *)partials);
+}
+
+// Every pass of a launch has the launch's tile width m (one plan, or one
+// register class of a batch), so "every thread holds part of the tile" is a
+// property of the launch.
+template <typename R, typename CT, int RB>
+void launch_rb(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes, const DevOp *ops,
+               const DevMap *maps, const CT *mats, double *partials, int m, hipStream_t st) {
+    if (m - RB == 8)
+        launch_full<R, CT, RB, true>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st);
+    else
+        launch_full<R, CT, RB, false>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st);
 }
 
 template <typename R, typename CT>
