@@ -258,36 +258,56 @@ __device__ __forceinline__ R sel(bool c, R a, R b) {
     return c ? a : b;
 }
 
+// Conditional swap of two register values by three in-place XORs: where the
+// mask is all ones A and B trade places, where it is zero they stay.  Every
+// tile update of the op loop is then an in-place rewrite of each register
+// (rotations and phases are shears, swaps are XORs), so the register
+// allocator keeps one set of registers for the tile across the whole loop
+// instead of copying it at every dispatch.  The all-ones mask of an
+// unconditional swap comes from the launch item, so the compiler cannot fold
+// the XORs back into a two-register exchange.
+template <typename CT> struct UInt;
+template <> struct UInt<float> { using T = uint32_t; };
+template <> struct UInt<double> { using T = uint64_t; };
+
+#define QNG_CSWAP(A, B, M)                                      \
+    do {                                                        \
+        using U_ = typename UInt<CT>::T;                        \
+        const U_ a_ = __builtin_bit_cast(U_, (CT)(A));          \
+        const U_ b_ = __builtin_bit_cast(U_, (CT)(B));          \
+        const U_ d_ = (a_ ^ b_) & (M);                          \
+        A = __builtin_bit_cast(CT, (U_)(a_ ^ d_));              \
+        B = __builtin_bit_cast(CT, (U_)(b_ ^ d_));              \
+    } while (0)
+
 // CNOT adjoint (itself) with target register bit J and control register bit K:
-// a fixed permutation of the registers.
+// the pairs of bit J whose bit K is set trade places.
 template <int J, int K, int T, typename CT>
-__device__ __forceinline__ void cnot_reg(Regs<CT, T> &x) {
+__device__ __forceinline__ void cnot_reg(Regs<CT, T> &x, typename UInt<CT>::T ones) {
 #pragma unroll
     for (int i = 0; i < T; ++i) {
         if ((i & (1 << J)) || !(i & (1 << K))) continue;
         const int k = i | (1 << J);
-        CT t;
-        t = x.ar[i]; x.ar[i] = x.ar[k]; x.ar[k] = t;
-        t = x.ai[i]; x.ai[i] = x.ai[k]; x.ai[k] = t;
-        t = x.br[i]; x.br[i] = x.br[k]; x.br[k] = t;
-        t = x.bi[i]; x.bi[i] = x.bi[k]; x.bi[k] = t;
+        QNG_CSWAP(x.ar[i], x.ar[k], ones);
+        QNG_CSWAP(x.ai[i], x.ai[k], ones);
+        QNG_CSWAP(x.br[i], x.br[k], ones);
+        QNG_CSWAP(x.bi[i], x.bi[k], ones);
     }
 }
 
 // CNOT with target register bit J and a control common to all registers of
-// the thread (thread bit or tile base): conditional swap of every pair.
+// the thread (thread bit or tile base): every pair of bit J trades places
+// where the mask is all ones.
 template <int J, int T, typename CT>
-__device__ __forceinline__ void cnot_cond(Regs<CT, T> &x, bool c) {
+__device__ __forceinline__ void cnot_cond(Regs<CT, T> &x, typename UInt<CT>::T mask) {
 #pragma unroll
     for (int i = 0; i < T; ++i) {
         if (i & (1 << J)) continue;
         const int k = i | (1 << J);
-        const CT a0r = x.ar[i], a0i = x.ai[i], a1r = x.ar[k], a1i = x.ai[k];
-        const CT b0r = x.br[i], b0i = x.bi[i], b1r = x.br[k], b1i = x.bi[k];
-        x.ar[i] = sel(c, a1r, a0r); x.ar[k] = sel(c, a0r, a1r);
-        x.ai[i] = sel(c, a1i, a0i); x.ai[k] = sel(c, a0i, a1i);
-        x.br[i] = sel(c, b1r, b0r); x.br[k] = sel(c, b0r, b1r);
-        x.bi[i] = sel(c, b1i, b0i); x.bi[k] = sel(c, b0i, b1i);
+        QNG_CSWAP(x.ar[i], x.ar[k], mask);
+        QNG_CSWAP(x.ai[i], x.ai[k], mask);
+        QNG_CSWAP(x.br[i], x.br[k], mask);
+        QNG_CSWAP(x.bi[i], x.bi[k], mask);
     }
 }
 
@@ -489,6 +509,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
 
     // ---- operations: one straight-line path per device op code
     const CT *__restrict__ mt = (const CT *)mats;
+    using U = typename UInt<CT>::T;
+    const U ones = ~(U)it.pad;   // all ones (the host sets pad to zero), opaque to the compiler
     const int n_ops = (int)ph0.y;
     const DevOp *op_ptr = ops + ph0.x;
     // The descriptor of the next op is fetched while the current one runs, and
@@ -562,16 +584,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
             }                                                                                                \
             break;                                                                                           \
         case OPC_CNOT_THR + J:                                                                               \
-            if constexpr (J < RB) cnot_cond<J, T, CT>(x, (tid >> (op.b1() & 15)) & 1);                        \
+            if constexpr (J < RB) cnot_cond<J, T, CT>(x, ((tid >> (op.b1() & 15)) & 1) ? ones : (U)0);                        \
             break;                                                                                           \
         case OPC_CNOT_BASE + J:                                                                              \
-            if constexpr (J < RB) {                                                                          \
-                if ((base >> op.q0()) & 1u) cnot_cond<J, T, CT>(x, true);                                     \
-            }                                                                                                \
+            if constexpr (J < RB) cnot_cond<J, T, CT>(x, ((base >> op.q0()) & 1u) ? ones : (U)0);               \
             break;
 #define QNG_CNOT_REG_CASE(J, K)                                                                              \
         case OPC_CNOT_REG + 4 * J + K:                                                                       \
-            if constexpr (J < RB && K < RB && J != K) cnot_reg<J, K, T, CT>(x);                             \
+            if constexpr (J < RB && K < RB && J != K) cnot_reg<J, K, T, CT>(x, ones);                             \
             break;
         QNG_REG_CASES(0)
         QNG_REG_CASES(1)
