@@ -486,6 +486,9 @@ void flatten(SweepPlan &plan, const Circuit &c) {
                 if (op.type == OP_CNOT) has_cnot = true;
                 if (op.type == OP_XPOSE) op.aux += (int32_t)map_base;
                 op.type = device_opcode(op);
+                const uint64_t hb = uint64_t(1) << device_handler(op.type);
+                op.hlo = (uint32_t)hb;
+                op.hhi = (uint32_t)(hb >> 32);
                 plan.dev_ops.push_back(op);
             }
             for (const DevMap &mp : hp.maps) plan.dev_maps.push_back(mp);
@@ -559,6 +562,33 @@ uint8_t device_opcode(const DevOp &op) {
     case OP_XPOSE: return OPC_XPOSE;
     default: fail(QNG_E_DEVICE, "device op: unknown kind (internal)");
     }
+    return 0;
+}
+
+int device_handler(uint8_t c) {
+    if (c < OPC_ROT_Y) return HB_ROT_X + c;
+    if (c < OPC_PRODROT_X) return HB_ROT_Y + (c - OPC_ROT_Y);
+    if (c < OPC_PRODROT_Y) return HB_PRODROT_X + (c - OPC_PRODROT_X);
+    if (c < OPC_PROD_X) return HB_PRODROT_Y + (c - OPC_PRODROT_Y);
+    if (c < OPC_PROD_Y) return HB_PROD_X + (c - OPC_PROD_X);
+    if (c < OPC_PRODZ_REG) return HB_PROD_Y + (c - OPC_PROD_Y);
+    if (c < OPC_PRODZ_THR) return HB_PRODZ_REG + (c - OPC_PRODZ_REG);
+    if (c <= OPC_PRODZ_BASE) return HB_PRODZ_UNI;
+    if (c >= OPC_DIAG_REG && c < OPC_DIAG_THR) return HB_DIAG_REG + (c - OPC_DIAG_REG);
+    if (c == OPC_DIAG_THR || c == OPC_DIAG_BASE) return HB_DIAG_UNI;
+    if (c >= OPC_PRODDIAG_REG && c < OPC_PRODDIAG_THR) return HB_PRODDIAG_REG + (c - OPC_PRODDIAG_REG);
+    if (c == OPC_PRODDIAG_THR || c == OPC_PRODDIAG_BASE) return HB_PRODDIAG_UNI;
+    if (c >= OPC_CNOT_REG && c < OPC_CNOT_THR) {
+        const int j = (c - OPC_CNOT_REG) / 4, k = (c - OPC_CNOT_REG) % 4;
+        if (j == k) fail(QNG_E_DEVICE, "device handler: CNOT control on its target (internal)");
+        return HB_CNOT_REG + 3 * j + (k < j ? k : k - 1);
+    }
+    if (c >= OPC_CNOT_THR && c < OPC_CNOT_BASE) return HB_CNOT_THR + (c - OPC_CNOT_THR);
+    if (c >= OPC_CNOT_BASE && c < OPC_CZ) return HB_CNOT_BASE + (c - OPC_CNOT_BASE);
+    if (c == OPC_CZ) return HB_CZ;
+    if (c == OPC_ZSUM) return HB_ZSUM;
+    if (c == OPC_XPOSE) return HB_XPOSE;
+    fail(QNG_E_DEVICE, "device handler: unknown op code (internal)");
     return 0;
 }
 

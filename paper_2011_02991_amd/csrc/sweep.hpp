@@ -94,12 +94,14 @@ constexpr int kMaxSlots = 64;       // inner products per pass
 constexpr int kMaxTileQubits = 13;
 constexpr int kMaxRest = 24;        // qubits outside a tile
 
-struct DevOp {  // 16 bytes
+struct DevOp {  // 32 bytes
     uint8_t type, b0, b1, axis;
     uint16_t slot;
     uint8_t q0, q1;   // qubits (global) the operation acts on
     int32_t gate;     // gate position: row of the matrix table
     int32_t aux;      // OP_XPOSE: mapping index
+    uint32_t hlo, hhi;   // device images: one-hot handler bit (HB_* below), low and high word
+    uint32_t pad0, pad1;
 };
 
 struct DevPass {  // 64 bytes, read through a pointer with scalar loads
@@ -122,7 +124,35 @@ static_assert(sizeof(DevPass) == 64, "DevPass layout");
 
 // Device op code of a planned operation (OPC_* above).
 uint8_t device_opcode(const DevOp &op);
-static_assert(sizeof(DevOp) == 16, "DevOp layout");
+
+// Handler bits of the kernel's op loop.  Every op carries exactly one bit
+// (one-hot, read from memory), and the kernel runs each handler under its own
+// test of that word: a chain of independent tests, rather than one multi-way
+// branch, lets the compiler keep the register tile in place through the loop
+// (at a multi-way merge it assigns the tile new registers and copies it every
+// iteration).  Groups of bits are tested first.
+enum : int {
+    HB_ROT_X = 0,            // + j
+    HB_ROT_Y = 4,            // + j
+    HB_PRODROT_X = 8,        // + j
+    HB_PRODROT_Y = 12,       // + j
+    HB_PROD_X = 16,          // + j
+    HB_PROD_Y = 20,          // + j
+    HB_PRODZ_REG = 24,       // + j
+    HB_PRODZ_UNI = 28,       // Z bit held by the thread index or the tile base
+    HB_XPOSE = 29,
+    HB_CZ = 30,
+    HB_ZSUM = 31,
+    HB_DIAG_REG = 32,        // + j
+    HB_DIAG_UNI = 36,
+    HB_PRODDIAG_REG = 37,    // + j
+    HB_PRODDIAG_UNI = 41,
+    HB_CNOT_REG = 42,        // + index of (j, k), k != j: 3 j + (k < j ? k : k - 1)
+    HB_CNOT_THR = 54,        // + j
+    HB_CNOT_BASE = 58        // + j
+};
+int device_handler(uint8_t opcode);
+static_assert(sizeof(DevOp) == 32, "DevOp layout");
 static_assert(sizeof(DevMap) == 16, "DevMap layout");
 
 struct HostPass {

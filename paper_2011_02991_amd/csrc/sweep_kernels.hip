@@ -270,14 +270,29 @@ template <typename CT> struct UInt;
 template <> struct UInt<float> { using T = uint32_t; };
 template <> struct UInt<double> { using T = uint64_t; };
 
+// x ^= d in the register that holds x (an opaque in-place XOR: the compiler
+// cannot fuse the two halves of a swap into one three-input operation that
+// needs both old values at once)
+__device__ __forceinline__ void xor_in_place(uint32_t &x, uint32_t d) {
+    asm("v_xor_b32 %0, %0, %1" : "+v"(x) : "v"(d));
+}
+__device__ __forceinline__ void xor_in_place(uint64_t &x, uint64_t d) {
+    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    xor_in_place(lo, (uint32_t)d);
+    xor_in_place(hi, (uint32_t)(d >> 32));
+    x = (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
 #define QNG_CSWAP(A, B, M)                                      \
     do {                                                        \
         using U_ = typename UInt<CT>::T;                        \
-        const U_ a_ = __builtin_bit_cast(U_, (CT)(A));          \
-        const U_ b_ = __builtin_bit_cast(U_, (CT)(B));          \
+        U_ a_ = __builtin_bit_cast(U_, (CT)(A));                \
+        U_ b_ = __builtin_bit_cast(U_, (CT)(B));                \
         const U_ d_ = (a_ ^ b_) & (M);                          \
-        A = __builtin_bit_cast(CT, (U_)(a_ ^ d_));              \
-        B = __builtin_bit_cast(CT, (U_)(b_ ^ d_));              \
+        xor_in_place(a_, d_);                                   \
+        xor_in_place(b_, d_);                                   \
+        A = __builtin_bit_cast(CT, a_);                         \
+        B = __builtin_bit_cast(CT, b_);                         \
     } while (0)
 
 // CNOT adjoint (itself) with target register bit J and control register bit K:
@@ -316,6 +331,7 @@ __device__ __forceinline__ void cnot_cond(Regs<CT, T> &x, typename UInt<CT>::T m
 struct OpD {
     uint32_t w0, w1;
     int32_t gate, aux;
+    uint64_t hf;   // one-hot handler bit (sweep.hpp, HB_*)
     __device__ __forceinline__ int type() const { return (int)(w0 & 0xffu); }
     __device__ __forceinline__ uint8_t b0() const { return (uint8_t)((w0 >> 8) & 0xffu); }
     __device__ __forceinline__ uint8_t b1() const { return (uint8_t)((w0 >> 16) & 0xffu); }
@@ -326,8 +342,12 @@ struct OpD {
 
 __device__ __forceinline__ OpD load_op(const DevOp *p) {
     const uint4 v = *reinterpret_cast<const uint4 *>(p);
-    return OpD{v.x, v.y, (int32_t)v.z, (int32_t)v.w};
+    const uint4 h = *(reinterpret_cast<const uint4 *>(p) + 1);
+    return OpD{v.x, v.y, (int32_t)v.z, (int32_t)v.w, (uint64_t)h.x | ((uint64_t)h.y << 32)};
 }
+
+constexpr uint64_t hbit(int b) { return uint64_t(1) << b; }
+constexpr uint64_t hbits(int b, int count) { return ((uint64_t(1) << count) - 1) << b; }
 
 // The byte tables of a pass (tile qubits, qubits outside the tile) and of a
 // thread mapping (local bit per position), read as dwords and kept as wide
@@ -507,188 +527,198 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
         }
     }
 
-    // ---- operations: one straight-line path per device op code
+    // ---- operations.  Each op carries a one-hot handler bit; the handlers run
+    // under independent tests of that word (groups first), each one a
+    // straight-line update of the register tile in place.
     const CT *__restrict__ mt = (const CT *)mats;
     using U = typename UInt<CT>::T;
     const U ones = ~(U)it.pad;   // all ones (the host sets pad to zero), opaque to the compiler
     const int n_ops = (int)ph0.y;
     const DevOp *op_ptr = ops + ph0.x;
     // The descriptor of the next op is fetched while the current one runs, and
-    // the current op's matrix row (unused entries for ops without a gate) is
-    // fetched before the dispatch, so scalar-load latency overlaps the work.
+    // the current op's shear parameters (unused by ops without a gate) before
+    // the handlers, so scalar-load latency overlaps the work.
     OpD nxt = load_op(op_ptr);
     for (int oi = 0; oi < n_ops; ++oi) {
         const OpD op = nxt;
         nxt = load_op(op_ptr + (oi + 1 < n_ops ? oi + 1 : oi));
         const CT *mrow = mt + (size_t)(op.gate > 0 ? op.gate : 0) * 8;
-        CT mv[2];
-        mv[0] = mrow[0];
-        mv[1] = mrow[1];
-        switch (op.type()) {
-#define QNG_REG_CASES(J)                                                                                     \
-        case OPC_ROT_X + J:                                                                                  \
-            if constexpr (J < RB)                                                                            \
-                rot_xy<J, 0, T, CT>(x, mv[0], mv[1]);                   \
-            break;                                                                                           \
-        case OPC_ROT_Y + J:                                                                                  \
-            if constexpr (J < RB)                                                                            \
-                rot_xy<J, 1, T, CT>(x, mv[0], mv[1]);                   \
-            break;                                                                                           \
-        case OPC_PRODROT_X + J:                                                                              \
+        const CT u = mrow[0], w = mrow[1];
+        const uint64_t hf = op.hf;
+        // X/Y rotations, alone or after their inner product
+        if (hf & (hbits(HB_ROT_X, 16))) {
+#define QNG_ROT_HANDLERS(J)                                                                                  \
             if constexpr (J < RB) {                                                                          \
-                double pr, pi;                                                                               \
-                prod_xy<J, 0, T, CT>(x, pr, pi);                                                             \
-                rot_xy<J, 0, T, CT>(x, mv[0], mv[1]);                   \
-                row_store(red, op.slot(), tid, pr, pi);                                                        \
-            }                                                                                                \
-            break;                                                                                           \
-        case OPC_PRODROT_Y + J:                                                                              \
-            if constexpr (J < RB) {                                                                          \
-                double pr, pi;                                                                               \
-                prod_xy<J, 1, T, CT>(x, pr, pi);                                                             \
-                rot_xy<J, 1, T, CT>(x, mv[0], mv[1]);                   \
-                row_store(red, op.slot(), tid, pr, pi);                                                        \
-            }                                                                                                \
-            break;                                                                                           \
-        case OPC_PROD_X + J:                                                                                 \
-            if constexpr (J < RB) {                                                                          \
-                double pr, pi;                                                                               \
-                prod_xy<J, 0, T, CT>(x, pr, pi);                                                             \
-                row_store(red, op.slot(), tid, pr, pi);                                                        \
-            }                                                                                                \
-            break;                                                                                           \
-        case OPC_PROD_Y + J:                                                                                 \
-            if constexpr (J < RB) {                                                                          \
-                double pr, pi;                                                                               \
-                prod_xy<J, 1, T, CT>(x, pr, pi);                                                             \
-                row_store(red, op.slot(), tid, pr, pi);                                                        \
-            }                                                                                                \
-            break;                                                                                           \
-        case OPC_PRODZ_REG + J:                                                                              \
-            if constexpr (J < RB) {                                                                          \
-                double pr, pi;                                                                               \
-                prod_z_reg<J, T, CT>(x, pr, pi);                                                             \
-                row_store(red, op.slot(), tid, pr, pi);                                                        \
-            }                                                                                                \
-            break;                                                                                           \
-        case OPC_DIAG_REG + J:                                                                               \
-            if constexpr (J < RB)                                                                            \
-                diag_reg<J, T, CT>(x, mv[0], mv[1]);                    \
-            break;                                                                                           \
-        case OPC_PRODDIAG_REG + J:                                                                           \
-            if constexpr (J < RB) {                                                                          \
-                double pr, pi;                                                                               \
-                prod_z_reg<J, T, CT>(x, pr, pi);                                                             \
-                diag_reg<J, T, CT>(x, mv[0], mv[1]);                    \
-                row_store(red, op.slot(), tid, pr, pi);                                                        \
-            }                                                                                                \
-            break;                                                                                           \
-        case OPC_CNOT_THR + J:                                                                               \
-            if constexpr (J < RB) cnot_cond<J, T, CT>(x, ((tid >> (op.b1() & 15)) & 1) ? ones : (U)0);                        \
-            break;                                                                                           \
-        case OPC_CNOT_BASE + J:                                                                              \
-            if constexpr (J < RB) cnot_cond<J, T, CT>(x, ((base >> op.q0()) & 1u) ? ones : (U)0);               \
-            break;
-#define QNG_CNOT_REG_CASE(J, K)                                                                              \
-        case OPC_CNOT_REG + 4 * J + K:                                                                       \
-            if constexpr (J < RB && K < RB && J != K) cnot_reg<J, K, T, CT>(x, ones);                             \
-            break;
-        QNG_REG_CASES(0)
-        QNG_REG_CASES(1)
-        QNG_REG_CASES(2)
-        QNG_REG_CASES(3)
-        QNG_CNOT_REG_CASE(0, 1) QNG_CNOT_REG_CASE(0, 2) QNG_CNOT_REG_CASE(0, 3)
-        QNG_CNOT_REG_CASE(1, 0) QNG_CNOT_REG_CASE(1, 2) QNG_CNOT_REG_CASE(1, 3)
-        QNG_CNOT_REG_CASE(2, 0) QNG_CNOT_REG_CASE(2, 1) QNG_CNOT_REG_CASE(2, 3)
-        QNG_CNOT_REG_CASE(3, 0) QNG_CNOT_REG_CASE(3, 1) QNG_CNOT_REG_CASE(3, 2)
-#undef QNG_REG_CASES
-#undef QNG_CNOT_REG_CASE
-        case OPC_PRODZ_THR:
-        case OPC_PRODZ_BASE:
-        case OPC_PRODDIAG_THR:
-        case OPC_PRODDIAG_BASE:
-        case OPC_DIAG_THR:
-        case OPC_DIAG_BASE: {
-            // the Z bit is common to all registers of the thread
-            const bool thr = op.type() == OPC_PRODZ_THR || op.type() == OPC_PRODDIAG_THR || op.type() == OPC_DIAG_THR;
-            const bool one = thr ? ((tid >> (op.b0() & 15)) & 1) : ((base >> op.q0()) & 1u);
-            if (op.type() != OPC_DIAG_THR && op.type() != OPC_DIAG_BASE) {
-                double pr, pi;
+                if (hf & hbit(HB_ROT_X + J)) rot_xy<J, 0, T, CT>(x, u, w);                                   \
+                if (hf & hbit(HB_ROT_Y + J)) rot_xy<J, 1, T, CT>(x, u, w);                                   \
+                if (hf & hbit(HB_PRODROT_X + J)) {                                                           \
+                    double pr, pi;                                                                           \
+                    prod_xy<J, 0, T, CT>(x, pr, pi);                                                         \
+                    rot_xy<J, 0, T, CT>(x, u, w);                                                            \
+                    row_store(red, op.slot(), tid, pr, pi);                                                  \
+                }                                                                                            \
+                if (hf & hbit(HB_PRODROT_Y + J)) {                                                           \
+                    double pr, pi;                                                                           \
+                    prod_xy<J, 1, T, CT>(x, pr, pi);                                                         \
+                    rot_xy<J, 1, T, CT>(x, u, w);                                                            \
+                    row_store(red, op.slot(), tid, pr, pi);                                                  \
+                }                                                                                            \
+            }
+            QNG_ROT_HANDLERS(0)
+            QNG_ROT_HANDLERS(1)
+            QNG_ROT_HANDLERS(2)
+            QNG_ROT_HANDLERS(3)
+#undef QNG_ROT_HANDLERS
+        }
+        // inner products without an adjoint after them: they only read the
+        // tile, so one multi-way branch serves them (no tile update to merge)
+        if (hf & hbits(HB_PROD_X, 13)) {
+            double pr = 0.0, pi = 0.0;
+            switch (op.type()) {
+#define QNG_PROD_CASES(J)                                                                                    \
+            case OPC_PROD_X + J:                                                                             \
+                if constexpr (J < RB) prod_xy<J, 0, T, CT>(x, pr, pi);                                      \
+                break;                                                                                       \
+            case OPC_PROD_Y + J:                                                                             \
+                if constexpr (J < RB) prod_xy<J, 1, T, CT>(x, pr, pi);                                      \
+                break;                                                                                       \
+            case OPC_PRODZ_REG + J:                                                                          \
+                if constexpr (J < RB) prod_z_reg<J, T, CT>(x, pr, pi);                                      \
+                break;
+                QNG_PROD_CASES(0)
+                QNG_PROD_CASES(1)
+                QNG_PROD_CASES(2)
+                QNG_PROD_CASES(3)
+#undef QNG_PROD_CASES
+            default: {   // Z bit held by the thread index or the tile base
+                const bool one =
+                    (op.b0() == kLocBase) ? ((base >> op.q0()) & 1u) : ((tid >> (op.b0() & 15)) & 1);
                 prod_plain<T, CT>(x, pr, pi);
-                const double sg = one ? -1.0 : 1.0;
-                row_store(red, op.slot(), tid, sg * pr, sg * pi);
+                if (one) {
+                    pr = -pr;
+                    pi = -pi;
+                }
+                break;
             }
-            if (op.type() != OPC_PRODZ_THR && op.type() != OPC_PRODZ_BASE)
-                diag_all<T, CT>(x, one ? -mv[0] : mv[0], one ? -mv[1] : mv[1]);
-            break;
+            }
+            row_store(red, op.slot(), tid, pr, pi);
         }
-        case OPC_CZ: {
-            const uint32_t neg = loc_mask<T>(op.b0(), op.q0(), tid, base) & loc_mask<T>(op.b1(), op.q1(), tid, base);
-#pragma unroll
-            for (int i = 0; i < T; ++i) {
-                const CT sg = sel<CT>((neg >> i) & 1u, (CT)-1, (CT)1);
-                x.ar[i] *= sg;
-                x.ai[i] *= sg;
-                x.br[i] *= sg;
-                x.bi[i] *= sg;
+        // RZ adjoints, alone or after their Z inner product
+        if (hf & hbits(HB_DIAG_REG, 10)) {
+#define QNG_DIAG_HANDLERS(J)                                                                                 \
+            if constexpr (J < RB) {                                                                          \
+                if (hf & hbit(HB_DIAG_REG + J)) diag_reg<J, T, CT>(x, u, w);                                 \
+                if (hf & hbit(HB_PRODDIAG_REG + J)) {                                                        \
+                    double pr, pi;                                                                           \
+                    prod_z_reg<J, T, CT>(x, pr, pi);                                                         \
+                    diag_reg<J, T, CT>(x, u, w);                                                             \
+                    row_store(red, op.slot(), tid, pr, pi);                                                  \
+                }                                                                                            \
             }
-            break;
+            QNG_DIAG_HANDLERS(0)
+            QNG_DIAG_HANDLERS(1)
+            QNG_DIAG_HANDLERS(2)
+            QNG_DIAG_HANDLERS(3)
+#undef QNG_DIAG_HANDLERS
+            if (hf & (hbit(HB_DIAG_UNI) | hbit(HB_PRODDIAG_UNI))) {
+                // the Z bit is common to all registers of the thread
+                const bool one = (op.b0() == kLocBase) ? ((base >> op.q0()) & 1u) : ((tid >> (op.b0() & 15)) & 1);
+                if (hf & hbit(HB_PRODDIAG_UNI)) {
+                    double pr, pi;
+                    prod_plain<T, CT>(x, pr, pi);
+                    const double sg = one ? -1.0 : 1.0;
+                    row_store(red, op.slot(), tid, sg * pr, sg * pi);
+                }
+                diag_all<T, CT>(x, one ? -u : u, one ? -w : w);
+            }
         }
-        case OPC_ZSUM:
-            if (tid == 0) {
-                const double sg = ((base >> op.q0()) & 1u) ? -1.0 : 1.0;
-                red[op.slot() * kRows] = make_double2(sg * Sr, sg * Si);
-                for (int w = 1; w < kRows; ++w) red[op.slot() * kRows + w] = make_double2(0.0, 0.0);
+        // CNOT adjoints (register target)
+        if (hf & hbits(HB_CNOT_REG, 20)) {
+#define QNG_CNOT_REG_HANDLER(J, K)                                                                           \
+            if constexpr (J < RB && K < RB && J != K) {                                                      \
+                if (hf & hbit(HB_CNOT_REG + 3 * J + (K < J ? K : K - 1))) cnot_reg<J, K, T, CT>(x, ones);    \
             }
-            break;
-        case OPC_XPOSE: {
-            const MapBytes next = load_map(maps + op.aux);
-            uint32_t lo_old[T], lo_new[T];
-            local_offsets<RB, T>(cur, tbits, tid, lo_old);
-            local_offsets<RB, T>(next, tbits, tid, lo_new);
-            if (active) {
-#pragma unroll
-                for (int i = 0; i < T; ++i) {
-                    CX v;
-                    v.x = x.ar[i];
-                    v.y = x.ai[i];
-                    xbuf[lo_old[i]] = v;
-                }
+            QNG_CNOT_REG_HANDLER(0, 1) QNG_CNOT_REG_HANDLER(0, 2) QNG_CNOT_REG_HANDLER(0, 3)
+            QNG_CNOT_REG_HANDLER(1, 0) QNG_CNOT_REG_HANDLER(1, 2) QNG_CNOT_REG_HANDLER(1, 3)
+            QNG_CNOT_REG_HANDLER(2, 0) QNG_CNOT_REG_HANDLER(2, 1) QNG_CNOT_REG_HANDLER(2, 3)
+            QNG_CNOT_REG_HANDLER(3, 0) QNG_CNOT_REG_HANDLER(3, 1) QNG_CNOT_REG_HANDLER(3, 2)
+#undef QNG_CNOT_REG_HANDLER
+#define QNG_CNOT_UNI_HANDLERS(J)                                                                             \
+            if constexpr (J < RB) {                                                                          \
+                if (hf & hbit(HB_CNOT_THR + J))                                                              \
+                    cnot_cond<J, T, CT>(x, ((tid >> (op.b1() & 15)) & 1) ? ones : (U)0);                     \
+                if (hf & hbit(HB_CNOT_BASE + J)) cnot_cond<J, T, CT>(x, ((base >> op.q0()) & 1u) ? ones : (U)0); \
             }
-            __syncthreads();
-            if (active) {
-#pragma unroll
-                for (int i = 0; i < T; ++i) {
-                    const CX v = xbuf[lo_new[i]];
-                    x.ar[i] = v.x;
-                    x.ai[i] = v.y;
-                }
-            }
-            __syncthreads();
-            if (active) {
-#pragma unroll
-                for (int i = 0; i < T; ++i) {
-                    CX v;
-                    v.x = x.br[i];
-                    v.y = x.bi[i];
-                    xbuf[lo_old[i]] = v;
-                }
-            }
-            __syncthreads();
-            if (active) {
-#pragma unroll
-                for (int i = 0; i < T; ++i) {
-                    const CX v = xbuf[lo_new[i]];
-                    x.br[i] = v.x;
-                    x.bi[i] = v.y;
-                }
-            }
-            __syncthreads();
-            cur = next;
-            break;
+            QNG_CNOT_UNI_HANDLERS(0)
+            QNG_CNOT_UNI_HANDLERS(1)
+            QNG_CNOT_UNI_HANDLERS(2)
+            QNG_CNOT_UNI_HANDLERS(3)
+#undef QNG_CNOT_UNI_HANDLERS
         }
-        default:
-            break;
+        if (hf & (hbit(HB_XPOSE) | hbit(HB_CZ) | hbit(HB_ZSUM))) {
+            if (hf & hbit(HB_CZ)) {
+                const uint32_t neg = loc_mask<T>(op.b0(), op.q0(), tid, base) & loc_mask<T>(op.b1(), op.q1(), tid, base);
+#pragma unroll
+                for (int i = 0; i < T; ++i) {
+                    const CT sg = sel<CT>((neg >> i) & 1u, (CT)-1, (CT)1);
+                    x.ar[i] *= sg;
+                    x.ai[i] *= sg;
+                    x.br[i] *= sg;
+                    x.bi[i] *= sg;
+                }
+            }
+            if (hf & hbit(HB_ZSUM)) {
+                if (tid == 0) {
+                    const double sg = ((base >> op.q0()) & 1u) ? -1.0 : 1.0;
+                    red[op.slot() * kRows] = make_double2(sg * Sr, sg * Si);
+                    for (int k = 1; k < kRows; ++k) red[op.slot() * kRows + k] = make_double2(0.0, 0.0);
+                }
+            }
+            if (hf & hbit(HB_XPOSE)) {
+                const MapBytes next = load_map(maps + op.aux);
+                uint32_t lo_old[T], lo_new[T];
+                local_offsets<RB, T>(cur, tbits, tid, lo_old);
+                local_offsets<RB, T>(next, tbits, tid, lo_new);
+                if (active) {
+#pragma unroll
+                    for (int i = 0; i < T; ++i) {
+                        CX v;
+                        v.x = x.ar[i];
+                        v.y = x.ai[i];
+                        xbuf[lo_old[i]] = v;
+                    }
+                }
+                __syncthreads();
+                if (active) {
+#pragma unroll
+                    for (int i = 0; i < T; ++i) {
+                        const CX v = xbuf[lo_new[i]];
+                        x.ar[i] = v.x;
+                        x.ai[i] = v.y;
+                    }
+                }
+                __syncthreads();
+                if (active) {
+#pragma unroll
+                    for (int i = 0; i < T; ++i) {
+                        CX v;
+                        v.x = x.br[i];
+                        v.y = x.bi[i];
+                        xbuf[lo_old[i]] = v;
+                    }
+                }
+                __syncthreads();
+                if (active) {
+#pragma unroll
+                    for (int i = 0; i < T; ++i) {
+                        const CX v = xbuf[lo_new[i]];
+                        x.br[i] = v.x;
+                        x.bi[i] = v.y;
+                    }
+                }
+                __syncthreads();
+                cur = next;
+            }
         }
     }
 
