@@ -75,15 +75,15 @@ __device__ __forceinline__ void row_store(double2 *red, int slot, int tid, doubl
     *dst = make_double2(a, b);
 }
 
-// The tile is kept as four short vectors per thread: real and imaginary parts
-// of lambda (A) and phi (B), T values each, indexed only by compile-time
-// constants.  One vector per part (rather than T scalars) lets the register
-// allocator carry the tile through the op loop without copies at every branch
-// of the dispatch.
+// The tile is kept as four arrays of T scalars per thread: real and imaginary
+// parts of lambda (A) and phi (B), indexed only by compile-time constants, so
+// every element is a register of its own.  With the one-hot handler dispatch
+// each element stays in one register through the whole op loop; as short
+// vectors, the CNOT handlers of the T=16 tile rebuilt whole vectors (a copy of
+// the tile per op).
 template <typename CT, int T>
 struct Regs {
-    typedef CT V __attribute__((ext_vector_type(T)));
-    V ar, ai, br, bi;
+    CT ar[T], ai[T], br[T], bi[T];
 };
 
 // 2x2 complex matrix entries of the gate table in the register precision
