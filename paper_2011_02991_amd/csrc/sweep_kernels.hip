@@ -258,71 +258,55 @@ __device__ __forceinline__ R sel(bool c, R a, R b) {
     return c ? a : b;
 }
 
-// Conditional swap of two register values by three in-place XORs: where the
-// mask is all ones A and B trade places, where it is zero they stay.  Every
+// Swap of two register values in place (v_swap_b32 on each dword).  Every
 // tile update of the op loop is then an in-place rewrite of each register
-// (rotations and phases are shears, swaps are XORs), so the register
-// allocator keeps one set of registers for the tile across the whole loop
-// instead of copying it at every dispatch.  The all-ones mask of an
-// unconditional swap comes from the launch item, so the compiler cannot fold
-// the XORs back into a two-register exchange.
-template <typename CT> struct UInt;
-template <> struct UInt<float> { using T = uint32_t; };
-template <> struct UInt<double> { using T = uint64_t; };
-
-// x ^= d in the register that holds x (an opaque in-place XOR: the compiler
-// cannot fuse the two halves of a swap into one three-input operation that
-// needs both old values at once)
-__device__ __forceinline__ void xor_in_place(uint32_t &x, uint32_t d) {
-    asm("v_xor_b32 %0, %0, %1" : "+v"(x) : "v"(d));
+// (rotations and phases are shears, swaps exchange register contents), so the
+// register allocator keeps one set of registers for the tile across the whole
+// loop instead of copying it at every dispatch.  A conditional swap (CNOT with
+// a control held by the thread index or the tile base) runs under a branch:
+// lanes whose control is clear are masked off, so they keep their values.
+__device__ __forceinline__ void swap_in_place(float &a, float &b) {
+    asm("v_swap_b32 %0, %1" : "+v"(a), "+v"(b));
 }
-__device__ __forceinline__ void xor_in_place(uint64_t &x, uint64_t d) {
-    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
-    xor_in_place(lo, (uint32_t)d);
-    xor_in_place(hi, (uint32_t)(d >> 32));
-    x = (uint64_t)lo | ((uint64_t)hi << 32);
+__device__ __forceinline__ void swap_in_place(double &a, double &b) {
+    uint32_t alo = (uint32_t)__builtin_bit_cast(uint64_t, a), ahi = (uint32_t)(__builtin_bit_cast(uint64_t, a) >> 32);
+    uint32_t blo = (uint32_t)__builtin_bit_cast(uint64_t, b), bhi = (uint32_t)(__builtin_bit_cast(uint64_t, b) >> 32);
+    asm("v_swap_b32 %0, %1" : "+v"(alo), "+v"(blo));
+    asm("v_swap_b32 %0, %1" : "+v"(ahi), "+v"(bhi));
+    a = __builtin_bit_cast(double, (uint64_t)alo | ((uint64_t)ahi << 32));
+    b = __builtin_bit_cast(double, (uint64_t)blo | ((uint64_t)bhi << 32));
 }
-
-#define QNG_CSWAP(A, B, M)                                      \
-    do {                                                        \
-        using U_ = typename UInt<CT>::T;                        \
-        U_ a_ = __builtin_bit_cast(U_, (CT)(A));                \
-        U_ b_ = __builtin_bit_cast(U_, (CT)(B));                \
-        const U_ d_ = (a_ ^ b_) & (M);                          \
-        xor_in_place(a_, d_);                                   \
-        xor_in_place(b_, d_);                                   \
-        A = __builtin_bit_cast(CT, a_);                         \
-        B = __builtin_bit_cast(CT, b_);                         \
-    } while (0)
 
 // CNOT adjoint (itself) with target register bit J and control register bit K:
 // the pairs of bit J whose bit K is set trade places.
 template <int J, int K, int T, typename CT>
-__device__ __forceinline__ void cnot_reg(Regs<CT, T> &x, typename UInt<CT>::T ones) {
+__device__ __forceinline__ void cnot_reg(Regs<CT, T> &x) {
 #pragma unroll
     for (int i = 0; i < T; ++i) {
         if ((i & (1 << J)) || !(i & (1 << K))) continue;
         const int k = i | (1 << J);
-        QNG_CSWAP(x.ar[i], x.ar[k], ones);
-        QNG_CSWAP(x.ai[i], x.ai[k], ones);
-        QNG_CSWAP(x.br[i], x.br[k], ones);
-        QNG_CSWAP(x.bi[i], x.bi[k], ones);
+        swap_in_place(x.ar[i], x.ar[k]);
+        swap_in_place(x.ai[i], x.ai[k]);
+        swap_in_place(x.br[i], x.br[k]);
+        swap_in_place(x.bi[i], x.bi[k]);
     }
 }
 
 // CNOT with target register bit J and a control common to all registers of
 // the thread (thread bit or tile base): every pair of bit J trades places
-// where the mask is all ones.
+// where the control is set.
 template <int J, int T, typename CT>
-__device__ __forceinline__ void cnot_cond(Regs<CT, T> &x, typename UInt<CT>::T mask) {
+__device__ __forceinline__ void cnot_cond(Regs<CT, T> &x, bool control) {
+    if (control) {
 #pragma unroll
-    for (int i = 0; i < T; ++i) {
-        if (i & (1 << J)) continue;
-        const int k = i | (1 << J);
-        QNG_CSWAP(x.ar[i], x.ar[k], mask);
-        QNG_CSWAP(x.ai[i], x.ai[k], mask);
-        QNG_CSWAP(x.br[i], x.br[k], mask);
-        QNG_CSWAP(x.bi[i], x.bi[k], mask);
+        for (int i = 0; i < T; ++i) {
+            if (i & (1 << J)) continue;
+            const int k = i | (1 << J);
+            swap_in_place(x.ar[i], x.ar[k]);
+            swap_in_place(x.ai[i], x.ai[k]);
+            swap_in_place(x.br[i], x.br[k]);
+            swap_in_place(x.bi[i], x.bi[k]);
+        }
     }
 }
 
@@ -406,22 +390,43 @@ __device__ __forceinline__ void global_offsets(const PassBytes &pb, const MapByt
     }
 }
 
-// Local (in-tile) index of each of a thread's registers under a mapping.
+// Exchange-buffer slot of an in-tile index: the index with its higher bit
+// fields folded onto the low kSwizzleBits by XOR.  The map is linear over
+// GF(2) and leaves the high bits alone, so it is a bijection of the tile, and
+// a set of lanes whose tile positions fall in distinct classes modulo
+// kSwizzleBits lands in distinct banks whichever positions the mapping gives
+// them (without it, lanes on high tile positions all hit one bank).
+#ifndef QNG_SWIZZLE_BITS
+#define QNG_SWIZZLE_BITS 4
+#endif
+constexpr int kSwizzleBits = QNG_SWIZZLE_BITS;
+__device__ __forceinline__ uint32_t swizzle(uint32_t l) {
+    constexpr uint32_t mask = (1u << kSwizzleBits) - 1u;
+    uint32_t f = l;
+#pragma unroll
+    for (int k = kSwizzleBits; k < kMaxTileQubits; k += kSwizzleBits) f ^= (l >> k) & mask;
+    return f;
+}
+
+// Exchange-buffer slot of each of a thread's registers under a mapping: the
+// swizzled local (in-tile) index.  The swizzle is linear and the register and
+// thread bits are disjoint, so the slot is the XOR of the swizzled parts.
 template <int RB, int T>
 __device__ __forceinline__ void local_offsets(const MapBytes &mp, int tbits, int tid, uint32_t (&off)[T]) {
     uint32_t lth = 0;
 #pragma unroll
     for (int t = 0; t < kMaxTileQubits; ++t)
         if (t < tbits) lth |= (uint32_t)((tid >> t) & 1) << byte_at(mp.pos, RB + t);
+    lth = swizzle(lth);
     uint32_t u[RB];
 #pragma unroll
-    for (int j = 0; j < RB; ++j) u[j] = 1u << byte_at(mp.pos, j);
+    for (int j = 0; j < RB; ++j) u[j] = swizzle(1u << byte_at(mp.pos, j));
 #pragma unroll
     for (int i = 0; i < T; ++i) {
         uint32_t l = lth;
 #pragma unroll
         for (int j = 0; j < RB; ++j)
-            if ((i >> j) & 1) l |= u[j];
+            if ((i >> j) & 1) l ^= u[j];
         off[i] = l;
     }
 }
@@ -439,6 +444,76 @@ __device__ __forceinline__ uint32_t loc_mask(uint8_t loc, uint8_t q, int tid, ui
     }
     const uint32_t v = (loc == kLocBase) ? (uint32_t)((base >> q) & 1u) : (uint32_t)((tid >> (loc & 15)) & 1);
     return v ? all : 0u;
+}
+
+// ------------------------------------------------------- op handlers
+//
+// Each op carries one handler bit; the op loop tests it group by group, then
+// register bit by register bit, then kind by kind (independent tests, nested),
+// so an op costs about a dozen scalar tests and every handler is a
+// straight-line update of the tile in place.
+
+constexpr uint64_t rot_bits(int j) {
+    return hbit(HB_ROT_X + j) | hbit(HB_ROT_Y + j) | hbit(HB_PRODROT_X + j) | hbit(HB_PRODROT_Y + j);
+}
+constexpr uint64_t diag_bits(int j) { return hbit(HB_DIAG_REG + j) | hbit(HB_PRODDIAG_REG + j); }
+constexpr uint64_t cnot_uni_bits(int j) { return hbit(HB_CNOT_THR + j) | hbit(HB_CNOT_BASE + j); }
+constexpr uint64_t cnot_reg_bits(int j) { return hbits(HB_CNOT_REG + 3 * j, 3); }   // target register bit j
+
+// X/Y rotation adjoints on register bit J, alone or after their inner product
+template <int J, int RB, int T, typename CT>
+__device__ __forceinline__ void rot_handlers(Regs<CT, T> &x, uint64_t hf, CT u, CT w, double2 *red, int slot,
+                                             int tid) {
+    if constexpr (J < RB) {
+        if (hf & hbit(HB_PRODROT_Y + J)) {
+            double pr, pi;
+            prod_xy<J, 1, T, CT>(x, pr, pi);
+            rot_xy<J, 1, T, CT>(x, u, w);
+            row_store(red, slot, tid, pr, pi);
+        }
+        if (hf & hbit(HB_PRODROT_X + J)) {
+            double pr, pi;
+            prod_xy<J, 0, T, CT>(x, pr, pi);
+            rot_xy<J, 0, T, CT>(x, u, w);
+            row_store(red, slot, tid, pr, pi);
+        }
+        if (hf & hbit(HB_ROT_Y + J)) rot_xy<J, 1, T, CT>(x, u, w);
+        if (hf & hbit(HB_ROT_X + J)) rot_xy<J, 0, T, CT>(x, u, w);
+    }
+}
+
+// RZ adjoints on register bit J, alone or after their Z inner product
+template <int J, int RB, int T, typename CT>
+__device__ __forceinline__ void diag_handlers(Regs<CT, T> &x, uint64_t hf, CT u, CT w, double2 *red, int slot,
+                                              int tid) {
+    if constexpr (J < RB) {
+        if (hf & hbit(HB_PRODDIAG_REG + J)) {
+            double pr, pi;
+            prod_z_reg<J, T, CT>(x, pr, pi);
+            diag_reg<J, T, CT>(x, u, w);
+            row_store(red, slot, tid, pr, pi);
+        }
+        if (hf & hbit(HB_DIAG_REG + J)) diag_reg<J, T, CT>(x, u, w);
+    }
+}
+
+template <int J, int RB, int T, typename CT>
+__device__ __forceinline__ void cnot_uni(Regs<CT, T> &x, bool control) {
+    if constexpr (J < RB) cnot_cond<J, T, CT>(x, control);
+}
+
+// CNOT adjoints with target register bit J and a register control
+template <int J, int RB, int T, typename CT>
+__device__ __forceinline__ void cnot_reg_handlers(Regs<CT, T> &x, uint64_t hf) {
+    if constexpr (J < RB) {
+        constexpr int K0 = J == 0 ? 1 : 0, K1 = J <= 1 ? 2 : 1, K2 = J <= 2 ? 3 : 2;   // controls != J
+        if constexpr (K0 < RB)
+            if (hf & hbit(HB_CNOT_REG + 3 * J + 0)) cnot_reg<J, K0, T, CT>(x);
+        if constexpr (K1 < RB)
+            if (hf & hbit(HB_CNOT_REG + 3 * J + 1)) cnot_reg<J, K1, T, CT>(x);
+        if constexpr (K2 < RB)
+            if (hf & hbit(HB_CNOT_REG + 3 * J + 2)) cnot_reg<J, K2, T, CT>(x);
+    }
 }
 
 template <typename R, typename CT, int RB, bool FULL>
@@ -528,11 +603,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
     }
 
     // ---- operations.  Each op carries a one-hot handler bit; the handlers run
-    // under independent tests of that word (groups first), each one a
-    // straight-line update of the register tile in place.
+    // under independent tests of that word (by group, register bit, kind),
+    // each one a straight-line update of the register tile in place.
     const CT *__restrict__ mt = (const CT *)mats;
-    using U = typename UInt<CT>::T;
-    const U ones = ~(U)it.pad;   // all ones (the host sets pad to zero), opaque to the compiler
     const int n_ops = (int)ph0.y;
     const DevOp *op_ptr = ops + ph0.x;
     // The descriptor of the next op is fetched while the current one runs, and
@@ -545,34 +618,54 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
         const CT *mrow = mt + (size_t)(op.gate > 0 ? op.gate : 0) * 8;
         const CT u = mrow[0], w = mrow[1];
         const uint64_t hf = op.hf;
-        // X/Y rotations, alone or after their inner product
-        if (hf & (hbits(HB_ROT_X, 16))) {
-#define QNG_ROT_HANDLERS(J)                                                                                  \
-            if constexpr (J < RB) {                                                                          \
-                if (hf & hbit(HB_ROT_X + J)) rot_xy<J, 0, T, CT>(x, u, w);                                   \
-                if (hf & hbit(HB_ROT_Y + J)) rot_xy<J, 1, T, CT>(x, u, w);                                   \
-                if (hf & hbit(HB_PRODROT_X + J)) {                                                           \
-                    double pr, pi;                                                                           \
-                    prod_xy<J, 0, T, CT>(x, pr, pi);                                                         \
-                    rot_xy<J, 0, T, CT>(x, u, w);                                                            \
-                    row_store(red, op.slot(), tid, pr, pi);                                                  \
-                }                                                                                            \
-                if (hf & hbit(HB_PRODROT_Y + J)) {                                                           \
-                    double pr, pi;                                                                           \
-                    prod_xy<J, 1, T, CT>(x, pr, pi);                                                         \
-                    rot_xy<J, 1, T, CT>(x, u, w);                                                            \
-                    row_store(red, op.slot(), tid, pr, pi);                                                  \
-                }                                                                                            \
-            }
-            QNG_ROT_HANDLERS(0)
-            QNG_ROT_HANDLERS(1)
-            QNG_ROT_HANDLERS(2)
-            QNG_ROT_HANDLERS(3)
-#undef QNG_ROT_HANDLERS
+        // Handlers under independent tests of the handler word, nested by
+        // group and register bit (an if / else-if chain would merge several
+        // tile updates at one point, and the compiler then gives the tile a
+        // second register set and copies it at every op).
+        if (hf & hbits(HB_ROT_X, 16)) {
+            // X/Y rotations, alone or after their inner product
+            if (hf & rot_bits(0)) rot_handlers<0, RB, T, CT>(x, hf, u, w, red, op.slot(), tid);
+            if (hf & rot_bits(1)) rot_handlers<1, RB, T, CT>(x, hf, u, w, red, op.slot(), tid);
+            if (hf & rot_bits(2)) rot_handlers<2, RB, T, CT>(x, hf, u, w, red, op.slot(), tid);
+            if (hf & rot_bits(3)) rot_handlers<3, RB, T, CT>(x, hf, u, w, red, op.slot(), tid);
         }
-        // inner products without an adjoint after them: they only read the
-        // tile, so one multi-way branch serves them (no tile update to merge)
+        if (hf & hbits(HB_DIAG_REG, 10)) {
+            // RZ adjoints, alone or after their Z inner product
+            if (hf & (hbit(HB_DIAG_UNI) | hbit(HB_PRODDIAG_UNI))) {
+                // the Z bit is common to all registers of the thread
+                const bool one = (op.b0() == kLocBase) ? ((base >> op.q0()) & 1u) : ((tid >> (op.b0() & 15)) & 1);
+                if (hf & hbit(HB_PRODDIAG_UNI)) {
+                    double pr, pi;
+                    prod_plain<T, CT>(x, pr, pi);
+                    const double sg = one ? -1.0 : 1.0;
+                    row_store(red, op.slot(), tid, sg * pr, sg * pi);
+                }
+                diag_all<T, CT>(x, one ? -u : u, one ? -w : w);
+            }
+            if (hf & diag_bits(0)) diag_handlers<0, RB, T, CT>(x, hf, u, w, red, op.slot(), tid);
+            if (hf & diag_bits(1)) diag_handlers<1, RB, T, CT>(x, hf, u, w, red, op.slot(), tid);
+            if (hf & diag_bits(2)) diag_handlers<2, RB, T, CT>(x, hf, u, w, red, op.slot(), tid);
+            if (hf & diag_bits(3)) diag_handlers<3, RB, T, CT>(x, hf, u, w, red, op.slot(), tid);
+        }
+        if (hf & hbits(HB_CNOT_REG, 20)) {
+            // CNOT adjoints (register target)
+            if (hf & hbits(HB_CNOT_THR, 8)) {
+                // control held by the thread index or the tile base
+                const bool control = (hf & hbits(HB_CNOT_THR, 4)) ? ((tid >> (op.b1() & 15)) & 1) != 0
+                                                                   : ((base >> op.q0()) & 1u) != 0;
+                if (hf & cnot_uni_bits(0)) cnot_cond<0, T, CT>(x, control);
+                if (hf & cnot_uni_bits(1)) cnot_uni<1, RB, T, CT>(x, control);
+                if (hf & cnot_uni_bits(2)) cnot_uni<2, RB, T, CT>(x, control);
+                if (hf & cnot_uni_bits(3)) cnot_uni<3, RB, T, CT>(x, control);
+            }
+            if (hf & cnot_reg_bits(0)) cnot_reg_handlers<0, RB, T, CT>(x, hf);
+            if (hf & cnot_reg_bits(1)) cnot_reg_handlers<1, RB, T, CT>(x, hf);
+            if (hf & cnot_reg_bits(2)) cnot_reg_handlers<2, RB, T, CT>(x, hf);
+            if (hf & cnot_reg_bits(3)) cnot_reg_handlers<3, RB, T, CT>(x, hf);
+        }
         if (hf & hbits(HB_PROD_X, 13)) {
+            // inner products without an adjoint after them: they only read the
+            // tile, so one multi-way branch serves them (no tile update to merge)
             double pr = 0.0, pi = 0.0;
             switch (op.type()) {
 #define QNG_PROD_CASES(J)                                                                                    \
@@ -602,58 +695,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
             }
             }
             row_store(red, op.slot(), tid, pr, pi);
-        }
-        // RZ adjoints, alone or after their Z inner product
-        if (hf & hbits(HB_DIAG_REG, 10)) {
-#define QNG_DIAG_HANDLERS(J)                                                                                 \
-            if constexpr (J < RB) {                                                                          \
-                if (hf & hbit(HB_DIAG_REG + J)) diag_reg<J, T, CT>(x, u, w);                                 \
-                if (hf & hbit(HB_PRODDIAG_REG + J)) {                                                        \
-                    double pr, pi;                                                                           \
-                    prod_z_reg<J, T, CT>(x, pr, pi);                                                         \
-                    diag_reg<J, T, CT>(x, u, w);                                                             \
-                    row_store(red, op.slot(), tid, pr, pi);                                                  \
-                }                                                                                            \
-            }
-            QNG_DIAG_HANDLERS(0)
-            QNG_DIAG_HANDLERS(1)
-            QNG_DIAG_HANDLERS(2)
-            QNG_DIAG_HANDLERS(3)
-#undef QNG_DIAG_HANDLERS
-            if (hf & (hbit(HB_DIAG_UNI) | hbit(HB_PRODDIAG_UNI))) {
-                // the Z bit is common to all registers of the thread
-                const bool one = (op.b0() == kLocBase) ? ((base >> op.q0()) & 1u) : ((tid >> (op.b0() & 15)) & 1);
-                if (hf & hbit(HB_PRODDIAG_UNI)) {
-                    double pr, pi;
-                    prod_plain<T, CT>(x, pr, pi);
-                    const double sg = one ? -1.0 : 1.0;
-                    row_store(red, op.slot(), tid, sg * pr, sg * pi);
-                }
-                diag_all<T, CT>(x, one ? -u : u, one ? -w : w);
-            }
-        }
-        // CNOT adjoints (register target)
-        if (hf & hbits(HB_CNOT_REG, 20)) {
-#define QNG_CNOT_REG_HANDLER(J, K)                                                                           \
-            if constexpr (J < RB && K < RB && J != K) {                                                      \
-                if (hf & hbit(HB_CNOT_REG + 3 * J + (K < J ? K : K - 1))) cnot_reg<J, K, T, CT>(x, ones);    \
-            }
-            QNG_CNOT_REG_HANDLER(0, 1) QNG_CNOT_REG_HANDLER(0, 2) QNG_CNOT_REG_HANDLER(0, 3)
-            QNG_CNOT_REG_HANDLER(1, 0) QNG_CNOT_REG_HANDLER(1, 2) QNG_CNOT_REG_HANDLER(1, 3)
-            QNG_CNOT_REG_HANDLER(2, 0) QNG_CNOT_REG_HANDLER(2, 1) QNG_CNOT_REG_HANDLER(2, 3)
-            QNG_CNOT_REG_HANDLER(3, 0) QNG_CNOT_REG_HANDLER(3, 1) QNG_CNOT_REG_HANDLER(3, 2)
-#undef QNG_CNOT_REG_HANDLER
-#define QNG_CNOT_UNI_HANDLERS(J)                                                                             \
-            if constexpr (J < RB) {                                                                          \
-                if (hf & hbit(HB_CNOT_THR + J))                                                              \
-                    cnot_cond<J, T, CT>(x, ((tid >> (op.b1() & 15)) & 1) ? ones : (U)0);                     \
-                if (hf & hbit(HB_CNOT_BASE + J)) cnot_cond<J, T, CT>(x, ((base >> op.q0()) & 1u) ? ones : (U)0); \
-            }
-            QNG_CNOT_UNI_HANDLERS(0)
-            QNG_CNOT_UNI_HANDLERS(1)
-            QNG_CNOT_UNI_HANDLERS(2)
-            QNG_CNOT_UNI_HANDLERS(3)
-#undef QNG_CNOT_UNI_HANDLERS
         }
         if (hf & (hbit(HB_XPOSE) | hbit(HB_CZ) | hbit(HB_ZSUM))) {
             if (hf & hbit(HB_CZ)) {
@@ -834,6 +875,9 @@ void launch_ct(const LaunchItem *items, int n_items, uint32_t total_tiles, const
     case 2: launch_rb<R, CT, 2>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st); break;
     case 3: launch_rb<R, CT, 3>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st); break;
     case 4:
+        // FP64 registers stop at 8 amplitudes per thread: at 16 the kernel
+        // needs 178-226 VGPRs (two waves per SIMD) and measured 1.8-2.2x slower
+        // per pass at n = 26
         if constexpr (sizeof(CT) == 4) {
             launch_rb<R, CT, 4>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st);
             break;
