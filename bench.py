@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--gate-qubits", type=int, default=26)
     ap.add_argument("--tile", type=int, default=0, help="tile qubits of the fused passes (0 = library default)")
     ap.add_argument("--f64-regs", type=int, default=0, help="complex64: compute sweep tiles in FP64 registers")
+    ap.add_argument("--block", type=int, default=0,
+                    help="metric columns sharing one lambda sweep (1 or 2; 0 = library default)")
     return ap.parse_args()
 
 
@@ -193,6 +195,7 @@ def main():
     ctx.set_option(qng.OPT_FUSION, args.fusion)
     ctx.set_option(qng.OPT_TILE_QUBITS, args.tile)
     ctx.set_option(qng.OPT_F64_REGISTERS, args.f64_regs)
+    ctx.set_option(qng.OPT_BLOCK_COLUMNS, args.block)
     t_chosen, res, st = time_steps(ctx, circ, pr, args.prec, args.steps, args.warmup, profile=True)
     log(f"{args.prec}: {t_chosen:.3f} s/step  stats={st}")
     plain = precision = None
@@ -232,7 +235,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": pr.name, "n_qubits": pr.n_qubits, "P": pr.n_params, "gates": pr.n_gates,
                    "hamiltonian_terms": pr.n_terms, "precision": args.prec, "fusion": args.fusion,
-                   "tile_qubits": args.tile or None, "f64_registers": bool(args.f64_regs)},
+                   "tile_qubits": args.tile or None, "f64_registers": bool(args.f64_regs),
+                   "block_columns": st.get("block_columns")},
         "plain_fp64": plain, "precision_errors": precision, "gate_apply": gate, "roofline": roof, "cpu_baseline": cpu,
         "breakdown_ms": {k: st[k] / args.steps for k in ("metric_ms", "grad_ms", "solve_ms")},
     }

@@ -108,7 +108,9 @@ typedef enum {
                                     hipGraph on first use and replay it (needs a non-null stream) */
     QNG_OPT_AUTOTUNE = 7,        /* qng_step_batched: 1 = time candidate tile widths and launch sizes on the
                                     first call for a batch structure and keep the fastest; 0 (default) = fixed */
-    QNG_OPT_BATCH_TILES = 8      /* qng_step_batched: work-groups per sweep launch to aim for (0 = 4096) */
+    QNG_OPT_BATCH_TILES = 8,     /* qng_step_batched: work-groups per sweep launch to aim for (0 = 4096) */
+    QNG_OPT_BLOCK_COLUMNS = 9    /* fused metric: columns sharing one lambda sweep, 1 or 2 (0 = default); 2 needs
+                                    tiles of >= 11 qubits (registers of >= 11 qubits), else 1 is used */
 } qng_option;
 
 /* Counters of the last metric/energy/step call on a context. */
@@ -116,9 +118,11 @@ typedef struct {
     int64_t sweep_launches;      /* launches of the fused sweep-pass kernel */
     int64_t sweep_tiles;         /* tiles processed by those launches */
     double  sweep_ms;            /* summed HIP-event duration of those launches (QNG_OPT_PROFILE) */
-    double  sweep_bytes;         /* algorithmic HBM bytes of those launches: read+write of 2 states per pass */
-    double  sweep_flops;         /* algorithmic FLOPs of those launches: 20 per amplitude per element
-                                    (8 for <lambda|sigma|phi>, 12 for the rotation adjoint on both states) */
+    double  sweep_bytes;         /* algorithmic HBM bytes of those launches: read+write of lambda and of the phi
+                                    states of each pass (2 states; 3 for a block of two columns) */
+    double  sweep_flops;         /* algorithmic FLOPs of those launches, per amplitude per element: 8 for
+                                    <lambda|sigma|phi>, 6 for the rotation adjoint on phi, 6 on lambda shared by
+                                    the columns of a block (20 for one column per sweep, 17 for two) */
     int64_t elements;            /* L_ij (i<j) elements evaluated */
     int64_t other_launches;      /* every other kernel launch */
     double  metric_ms;           /* wall-clock of the metric part (G) */
@@ -128,6 +132,8 @@ typedef struct {
     int32_t target_tiles;        /* qng_step_batched: work-groups per launch aimed for */
     double  tune_ms;             /* qng_step_batched: wall-clock spent autotuning in this call */
     int64_t graph_replays;       /* qng_step_batched: register classes run as a replay of a captured graph */
+    int32_t block_columns;       /* fused metric: columns per lambda sweep of the last call (0: none ran) */
+    int32_t reserved;
 } qng_stats;
 
 /* Plan of a circuit under the current options (host only, no device work). */
@@ -174,12 +180,18 @@ qng_status qng_plan(const qng_circuit *circ, int fusion, int tile_qubits, qng_pl
 /* Export a fused sweep plan (host only): one row of 10 int32 per operation,
  * in execution order (in-register exchanges omitted): {column s, pass index
  * within the column, kind (0 gate adjoint, 1 inner product then the adjoint of
- * its rotation, 2 inner product), qubit q0 (CNOT: control), qubit q1 (CNOT
- * target / CZ second qubit, else -1), gate position of the adjoint (or -1),
- * destination of an inner product (or -1), Pauli axis of the inner product
- * (0 X, 1 Y, 2 Z; or -1), tile-qubit mask bits 0..30, bits 31..61}.
+ * its rotation, 2 inner product, 3 seed of a column's phi register), qubit q0
+ * (CNOT: control), qubit q1 (CNOT target / CZ second qubit, else -1), gate
+ * position of the adjoint (or -1), destination of an inner product (or -1),
+ * Pauli axis of the inner product or seed (0 X, 1 Y, 2 Z; or -1), tile-qubit
+ * mask bits 0..30, bits 31..61}.
  * sweep = 0: the metric's columns s = 1..P-1 (Sec. 3, Alg. 1 inner loops),
- * destination r*P + s of <lambda|sigma_r|phi>; sweep = 1: the reverse sweep of
+ * destination r*P + s of <lambda|sigma_r|phi>; sweep = 2: the same metric with
+ * blocks of two columns s-1, s sharing one lambda sweep (rows keyed by the top
+ * column s; an inner product for both columns gives one row per destination,
+ * the adjoint on the last; a seed row sets phi of column s_b to sigma lambda,
+ * sigma on qubit q0 with the row's axis, and carries destination P*P + s_b of
+ * <lambda|phi>, i.e. <y_{s_b}|sigma|y_{s_b}>); sweep = 1: the reverse sweep of
  * the energy gradient from the last gate (one column, s = P), destination r.
  * amp_bytes: 16 for complex128 plans, 8 for complex64.  With rows = NULL only
  * *n_rows is set. */

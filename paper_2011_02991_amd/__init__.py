@@ -26,7 +26,7 @@ C128, C64 = 0, 1
 PRECISIONS = {"c128": C128, "complex128": C128, C128: C128, "c64": C64, "complex64": C64, C64: C64}
 
 OPT_FUSION, OPT_TILE_QUBITS, OPT_COLUMN_STREAMS, OPT_PROFILE, OPT_SMALL_N_KERNEL, OPT_F64_REGISTERS = 0, 1, 2, 3, 4, 5
-OPT_GRAPH, OPT_AUTOTUNE, OPT_BATCH_TILES = 6, 7, 8
+OPT_GRAPH, OPT_AUTOTUNE, OPT_BATCH_TILES, OPT_BLOCK_COLUMNS = 6, 7, 8, 9
 
 STATUS = {
     0: "QNG_OK", -1: "QNG_E_INVALID_ARG", -2: "QNG_E_BAD_CIRCUIT", -3: "QNG_E_BAD_PARAMS",
@@ -60,7 +60,7 @@ class Stats(ctypes.Structure):
                 ("sweep_bytes", ctypes.c_double), ("sweep_flops", ctypes.c_double), ("elements", ctypes.c_int64), ("other_launches", ctypes.c_int64),
                 ("metric_ms", ctypes.c_double), ("grad_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
                 ("tile_qubits", ctypes.c_int32), ("target_tiles", ctypes.c_int32), ("tune_ms", ctypes.c_double),
-                ("graph_replays", ctypes.c_int64)]
+                ("graph_replays", ctypes.c_int64), ("block_columns", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -200,11 +200,15 @@ def plan(circ: Circuit, fusion: int = 1, tile_qubits: int = 0) -> dict:
     return info.as_dict()
 
 
-def plan_export(circ: Circuit, tile_qubits: int = 0, prec="c128", gradient: bool = False) -> np.ndarray:
+def plan_export(circ: Circuit, tile_qubits: int = 0, prec="c128", gradient: bool = False,
+                block: int = 1) -> np.ndarray:
     """Host-only: a fused sweep plan as rows of 10 int32 (see qng_plan_export);
-    the metric's columns, or the gradient's reverse sweep."""
+    the metric's columns (block=2: two columns per lambda sweep), or the
+    gradient's reverse sweep."""
     amp = 16 if _prec(prec) == C128 else 8
-    sw = 1 if gradient else 0
+    if block not in (1, 2):
+        raise ValueError("block must be 1 or 2")
+    sw = 1 if gradient else (2 if block == 2 else 0)
     n = ctypes.c_int64()
     _check(_lib.qng_plan_export(circ.cref, tile_qubits, amp, sw, None, 0, ctypes.byref(n)))
     rows = np.zeros((n.value, 10), dtype=np.int32)

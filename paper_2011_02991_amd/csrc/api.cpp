@@ -64,7 +64,7 @@ struct qng_ctx {
     bool own_stream = false;
     size_t mem_limit = 0;
     int opt_fusion = 1, opt_tile = 0, opt_streams = 0, opt_profile = 0, opt_small = 1, opt_f64_regs = 0;
-    int opt_graph = 1, opt_autotune = 0, opt_batch_tiles = 0;
+    int opt_graph = 1, opt_autotune = 0, opt_batch_tiles = 0, opt_block = 0;
     std::string last_error;
     qng_stats stats{};
     void *ws = nullptr;
@@ -156,8 +156,8 @@ Layout plan_layout(int n, int P, size_t amp_bytes, int n_states, bool staging, s
     L.states = take(L.state_bytes * n_states);
     L.staging = staging ? take((size_t(1) << n) * 16) : 0;
     L.partials = take((size_t)reduce_blocks(n) * 16 + 16);
-    L.lraw = take((size_t)P * P * 16 + 16);
-    L.traw = take((size_t)P * 16 + 16);
+    L.lraw = take((size_t)P * P * 16 + (size_t)P * 16 + 16);
+    L.traw = L.lraw + (size_t)P * P * 16;   // T right after L: column blocks reduce both into one array
     L.graw = take((size_t)P * 16 + 16);
     L.eraw = take(16);
     L.gout = take((size_t)P * P * 16 + 16);
@@ -348,6 +348,17 @@ struct CallSpec {
     const void *psi_final_dev = nullptr;  // gradient from a given final state (nullable)
 };
 
+// Columns per lambda sweep of the fused metric.  Blocks of two columns need
+// full tiles of at least 11 qubits (8 or 16 amplitudes per thread); option
+// value 0 picks the default.
+int block_width(int opt_block, const Circuit &c, int opt_tile, int amp, bool f64) {
+    int m = opt_tile > 0 ? opt_tile : default_tile_qubits(c.n, amp, f64);
+    if (m > (f64 ? 11 : 12)) m = f64 ? 11 : 12;
+    if (m > c.n) m = c.n;
+    const int want = opt_block > 0 ? opt_block : kDefaultBlockWidth;
+    return (want == 2 && register_bits(m, amp) >= 3 && m - register_bits(m, amp) == 8) ? 2 : 1;
+}
+
 struct CallResult {
     // device pointers into the workspace
     double *G = nullptr, *T = nullptr, *graw = nullptr, *eraw = nullptr;
@@ -367,12 +378,14 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
     int n_states = 4;
     if (fused) {
         const bool f64_regs = amp == 16 || ctx->opt_f64_regs;
-        plan = &ctx->sweep_cache.get(c, ctx->opt_tile, (int)amp, ctx->opt_small, f64_regs);
+        const int width = block_width(ctx->opt_block, c, ctx->opt_tile, (int)amp, f64_regs);
+        plan = &ctx->sweep_cache.get(c, ctx->opt_tile, (int)amp, ctx->opt_small, f64_regs, width);
         size_t free_b = 0, total_b = 0;
         HIPCHECK(hipMemGetInfo(&free_b, &total_b));
         fr = fused_config(*plan, ctx->opt_streams, V, free_b + ctx->ws_bytes);
         scratch = fused_scratch_bytes(*plan, fr, c.M);
-        n_states = std::max(4, 1 + 2 * fr.B);
+        n_states = std::max(4, 1 + (plan->width + 1) * fr.B);
+        ctx->stats.block_columns = plan->width;
     }
     std::shared_ptr<const SweepPlan> gplan;
     const bool f64_regs = amp == 16 || ctx->opt_f64_regs;
@@ -857,6 +870,10 @@ qng_status qng_set_option(qng_ctx *ctx, int option, int value) {
             if (value < 0) fail(QNG_E_INVALID_ARG, "batch tiles < 0");
             ctx->opt_batch_tiles = value;
             break;
+        case QNG_OPT_BLOCK_COLUMNS:
+            if (value < 0 || value > kMaxBlockWidth) fail(QNG_E_INVALID_ARG, "block columns outside [0, 2]");
+            ctx->opt_block = value;
+            break;
         default: fail(QNG_E_INVALID_ARG, "unknown option " + std::to_string(option));
         }
     });
@@ -910,12 +927,29 @@ qng_status qng_plan_export(const qng_circuit *circ, int tile_qubits, int amp_byt
     return guarded(nullptr, [&] {
         if (!n_rows) fail(QNG_E_INVALID_ARG, "n_rows is NULL");
         if (amp_bytes != 8 && amp_bytes != 16) fail(QNG_E_INVALID_ARG, "amp_bytes must be 8 or 16");
-        if (sweep != 0 && sweep != 1) fail(QNG_E_INVALID_ARG, "sweep must be 0 (metric) or 1 (gradient)");
+        if (sweep < 0 || sweep > 2) fail(QNG_E_INVALID_ARG, "sweep must be 0 or 2 (metric) or 1 (gradient)");
         validate_circuit(circ, kMaxQubitsC64);
         Circuit c = compile_circuit(circ);
-        SweepPlan plan = sweep == 0 ? build_sweep_plan(c, tile_qubits, amp_bytes, 1, amp_bytes == 16)
-                                    : build_gradient_plan(c, tile_qubits, amp_bytes, amp_bytes == 16);
+        SweepPlan plan = sweep == 1 ? build_gradient_plan(c, tile_qubits, amp_bytes, amp_bytes == 16)
+                                    : build_sweep_plan(c, tile_qubits, amp_bytes, 1, amp_bytes == 16, sweep == 2 ? 2 : 1);
         int64_t k = 0;
+        auto emit = [&](const ColumnPlan &cp, size_t pi, uint64_t mask, int kind, int q0, int q1, int gate, int dest,
+                        int axis) {
+            if (rows && k < cap) {
+                int32_t *r = rows + 10 * k;
+                r[0] = cp.s;
+                r[1] = (int32_t)pi;
+                r[2] = kind;
+                r[3] = q0;
+                r[4] = q1;
+                r[5] = gate;
+                r[6] = dest;
+                r[7] = axis;
+                r[8] = (int32_t)(mask & 0x7fffffffu);
+                r[9] = (int32_t)((mask >> 31) & 0x7fffffffu);
+            }
+            ++k;
+        };
         for (const ColumnPlan &cp : plan.cols) {
             for (size_t pi = 0; pi < cp.passes.size(); ++pi) {
                 const HostPass &hp = cp.passes[pi];
@@ -923,24 +957,26 @@ qng_status qng_plan_export(const qng_circuit *circ, int tile_qubits, int amp_byt
                 for (uint8_t q : hp.tile) mask |= uint64_t(1) << q;
                 for (const DevOp &op : hp.ops) {
                     if (op.type == OP_XPOSE) continue;
-                    if (rows && k < cap) {
-                        int32_t *r = rows + 10 * k;
-                        const bool prod = op.type == OP_PRODROT || op.type == OP_PROD || op.type == OP_ZSUM ||
-                                          op.type == OP_PRODZ || op.type == OP_PRODDIAG;
-                        const bool adj = op.type == OP_ROT || op.type == OP_PRODROT || op.type == OP_CNOT ||
-                                         op.type == OP_CZ || op.type == OP_DIAG || op.type == OP_PRODDIAG;
-                        r[0] = cp.s;
-                        r[1] = (int32_t)pi;
-                        r[2] = prod ? (adj ? 1 : 2) : 0;
-                        r[3] = op.q0;
-                        r[4] = (op.type == OP_CNOT || op.type == OP_CZ) ? op.q1 : -1;
-                        r[5] = adj ? op.gate : -1;
-                        r[6] = prod ? hp.slot_dest[op.slot] : -1;
-                        r[7] = prod ? op.axis : -1;
-                        r[8] = (int32_t)(mask & 0x7fffffffu);
-                        r[9] = (int32_t)((mask >> 31) & 0x7fffffffu);
+                    if (op.type == OP_SEED) {
+                        emit(cp, pi, mask, 3, op.q0, -1, -1, hp.slot_dest[op.slot], op.axis);
+                        continue;
                     }
-                    ++k;
+                    const bool prod = op.type == OP_PRODROT || op.type == OP_PROD || op.type == OP_ZSUM ||
+                                      op.type == OP_PRODZ || op.type == OP_PRODDIAG;
+                    const bool adj = op.type == OP_ROT || op.type == OP_PRODROT || op.type == OP_CNOT ||
+                                     op.type == OP_CZ || op.type == OP_DIAG || op.type == OP_PRODDIAG;
+                    const int q1 = (op.type == OP_CNOT || op.type == OP_CZ) ? op.q1 : -1;
+                    if (!prod) {
+                        emit(cp, pi, mask, 0, op.q0, q1, op.gate, -1, -1);
+                        continue;
+                    }
+                    // one row per active phi register; the adjoint (if any) rides on the last
+                    const int nprod = plan.width - op.aux;
+                    for (int b = 0; b < nprod; ++b) {
+                        const bool last = b + 1 == nprod;
+                        emit(cp, pi, mask, (last && adj) ? 1 : 2, op.q0, -1, (last && adj) ? op.gate : -1,
+                             hp.slot_dest[op.slot + b], op.axis);
+                    }
                 }
             }
         }

@@ -253,7 +253,7 @@ void enqueue_batch_metric(const BatchSchedule &s, const std::vector<const Circui
         }
         if (events) BCHECK(hipEventRecord((*events)[2 * li], st));
         launch_sweep_pass<R>(items + L.item_begin, (int)L.n_items, L.total_tiles, passes, ops, maps, d.adj_mats,
-                             d.adj_mats32, d.partials, s.m, s.rb, f64_regs, st);
+                             d.adj_mats32, d.partials, s.m, s.rb, f64_regs, 1, st);
         if (events) BCHECK(hipEventRecord((*events)[2 * li + 1], st));
         launch_reduce_tasks(tasks + L.task_begin, (int)L.n_tasks, d.partials, d.lraw, st);
     }

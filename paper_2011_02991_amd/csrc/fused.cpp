@@ -42,7 +42,7 @@ size_t fused_scratch_bytes(const SweepPlan &plan, const FusedRun &fr, int M) {
     b += align256(plan.dev_ops.size() * sizeof(DevOp) + 64);            // ops
     b += align256(plan.dev_maps.size() * sizeof(DevMap) + 64);          // thread mappings
     b += align256(plan.dev_passes.size() * sizeof(LaunchItem) + 64);    // one item per pass
-    b += align256((size_t)plan.P * plan.P * sizeof(ReduceTask) / 2 + 64);  // one task per element
+    b += align256(((size_t)plan.P * plan.P / 2 + plan.P) * sizeof(ReduceTask) + 64);  // elements and seeds
     b += align256(fr.partial_elems * 16);
     return b;
 }
@@ -54,9 +54,14 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
     const int n = c.n;
     const size_t V = buf.state_bytes;
     const uint32_t tiles = 1u << (n - plan.m);
-    const int ncols = (int)plan.cols.size();
-    const int B = fr.B;
+    const int ncols = (int)plan.cols.size();   // column blocks
+    const int B = fr.B;                        // blocks swept concurrently
+    const int W = plan.width;                  // phi registers per block
+    if (W > 1 && buf.traw != buf.lraw + 2 * (size_t)c.P * c.P)
+        fail(QNG_E_DEVICE, "fused sweep: T must follow L in memory for column blocks (internal)");
     auto state = [&](int k) -> void * { return buf.states + (size_t)k * V; };
+    // block b of a group: lambda, then phi registers 0 .. W-1 (the top column's is W-1)
+    auto reg = [&](int b, int k) -> void * { return state(1 + (W + 1) * b + k); };
 
     // ---- launch schedule (host)
     std::vector<LaunchItem> items;
@@ -87,8 +92,9 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
                 it.pass = pidx;
                 it.ntiles = tiles;
                 it.partial_off = poff;
-                it.regA = state(1 + 2 * b);
-                it.regB = state(2 + 2 * b);
+                it.regA = reg(b, 0);
+                it.regB = reg(b, 1);
+                it.regC = W > 1 ? reg(b, 2) : nullptr;
                 items.push_back(it);
                 ++L.n_items;
                 L.total_tiles += tiles;
@@ -174,37 +180,39 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
     stats->other_launches += 2;
     for (const Group &G : groups) {
         for (int col = G.col_begin; col < G.col_end; ++col) {
-            const int s = plan.cols[col].s;
+            const int s = plan.cols[col].s;    // top column of the block
             const Rot &rs = c.rots[s];
             const Rot &rp = c.rots[s - 1];
             const int b = col - G.col_begin;
             // y_s = R_{s-1} y_{s-1} when rotation s-1 is the only gate in between:
-            // one pass advances psi, seeds the column and takes T_s
+            // one pass advances psi, seeds the top column and takes T_s (the
+            // lower columns of a block are seeded inside its sweep)
+            forward_to(rp.pos);
             int qr = -1;
             const double *mrow = d_fmats;
-            if (pos == rp.pos && rs.pos == rp.pos + 1) {
+            if (rs.pos == rp.pos + 1) {
                 qr = rp.qubit;
                 mrow = d_fmats + (size_t)rp.pos * 8;
                 pos = rs.pos;
             } else {
                 forward_to(rs.pos);
             }
-            launch_advance_seed<R>(psi, state(1 + 2 * b), state(2 + 2 * b), n, qr, mrow, rs.qubit, rs.axis,
-                                   buf.reduce_partials, buf.traw + 2 * s, st);
+            launch_advance_seed<R>(psi, reg(b, 0), reg(b, W), n, qr, mrow, rs.qubit, rs.axis, buf.reduce_partials,
+                                   buf.traw + 2 * s, st);
             stats->other_launches += 2;
         }
         for (size_t li = G.launch_begin; li < G.launch_end; ++li) {
             const Launch &L = launches[li];
             if (profile) FCHECK(hipEventRecord(ev[2 * li], st));
             launch_sweep_pass<R>(d_items + L.item_begin, (int)L.n_items, L.total_tiles, d_passes, d_ops, d_maps,
-                                 d_mats, d_mats32, d_partials, plan.m, plan.rb, f64_regs, st);
+                                 d_mats, d_mats32, d_partials, plan.m, plan.rb, f64_regs, W, st);
             if (profile) FCHECK(hipEventRecord(ev[2 * li + 1], st));
             launch_reduce_tasks(d_tasks + L.task_begin, (int)L.n_tasks, d_partials, buf.lraw, st);
             ++stats->sweep_launches;
             ++stats->other_launches;
             stats->sweep_tiles += L.total_tiles;
-            stats->sweep_bytes += (double)L.n_items * 4.0 * (double)V;
-            stats->sweep_flops += 20.0 * (double)L.n_tasks * (double)((uint64_t)1 << n);
+            stats->sweep_bytes += (double)L.n_items * 2.0 * (W + 1) * (double)V;
+            stats->sweep_flops += sweep_flops_per_amp(W) * (double)L.n_tasks * (double)((uint64_t)1 << n);
         }
     }
     stats->elements += (int64_t)c.P * (c.P - 1) / 2;
@@ -298,7 +306,7 @@ void run_fused_gradient(const SweepPlan &g, const Circuit &c, const std::vector<
     for (size_t t = 0; t < items.size(); ++t) {
         if (profile) FCHECK(hipEventRecord(ev[2 * t], st));
         launch_sweep_pass<R>(d_items + t, 1, tiles, d_passes, d_ops, d_maps, d_mats, d_mats32, d_partials, g.m, g.rb,
-                             f64_regs, st);
+                             f64_regs, 1, st);
         if (profile) FCHECK(hipEventRecord(ev[2 * t + 1], st));
         const uint32_t nt = task_begin[t + 1] - task_begin[t];
         launch_reduce_tasks(d_tasks + task_begin[t], (int)nt, d_partials, graw, st);

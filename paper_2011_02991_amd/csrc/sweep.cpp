@@ -14,16 +14,18 @@ namespace qng {
 namespace {
 
 enum : uint8_t { TY_X = 0, TY_Y = 1, TY_Z = 2 };
-enum : uint8_t { EV_PROD = 0, EV_UNAPPLY = 1 };
+enum : uint8_t { EV_PROD = 0, EV_UNAPPLY = 1, EV_SEED = 2 };
 
 struct Event {
     uint8_t kind;
     uint8_t nq;
     uint8_t type[2];
     int q[2];
-    int pos;   // gate position (UNAPPLY) / position of the rotation (PROD)
-    int rot;   // rotation index (PROD), -1 otherwise
+    int pos;   // gate position (UNAPPLY) / position of the rotation (PROD, SEED)
+    int rot;   // rotation index (PROD, SEED), -1 otherwise
     int gkind; // gate kind (UNAPPLY)
+    int fa;    // PROD: first active phi register of the block (columns above the rotation)
+    int sb;    // SEED: phi register seeded
 };
 
 Event unapply_event(const Circuit &c, int pos) {
@@ -55,17 +57,35 @@ Event prod_event(const Circuit &c, int r) {
     return e;
 }
 
-// Backward sweep of column s: positions rots[s].pos-1 down to rots[0].pos; the
-// inner product of rotation r comes just before the adjoint of rotation r (the
-// adjoint of the first rotation is never needed).
-std::vector<Event> column_events(const Circuit &c, int s) {
+// Seed of phi register b of a block where lambda reaches y_r (the state just
+// before rotation r): phi_b = sigma_r lambda.  It acts on rotation r's qubit
+// with sigma_r's type, like an inner product.
+Event seed_event(const Circuit &c, int r, int b) {
+    Event e = prod_event(c, r);
+    e.kind = EV_SEED;
+    e.sb = b;
+    return e;
+}
+
+// Backward sweep of a block of columns s_b = s - width + 1 + b (b < width,
+// s_b >= 1) sharing lambda: positions rots[s].pos-1 down to rots[0].pos.  The
+// inner product of rotation r (for every column above r) comes just before the
+// adjoint of rotation r (the adjoint of the first rotation is never needed);
+// after the adjoint of a block column's own rotation lambda is y_{s_b}, and
+// that column's phi register is seeded there.  With width 1 this is the sweep
+// of column s alone (Sec. 3, Alg. 1 inner loop).
+std::vector<Event> block_events(const Circuit &c, int s, int width) {
     std::vector<Event> ev;
     const int p0 = c.rots[0].pos;
+    const int s_first = s - width + 1;     // column of phi register 0 (may be < 1: absent)
     for (int k = c.rots[s].pos - 1; k >= p0; --k) {
         const int r = c.rot_at[k];
         if (r >= 0) {
-            ev.push_back(prod_event(c, r));
+            Event e = prod_event(c, r);
+            e.fa = std::max(0, r + 1 - s_first);
+            ev.push_back(e);
             if (k > p0) ev.push_back(unapply_event(c, k));
+            if (r >= std::max(1, s_first) && r < s) ev.push_back(seed_event(c, r, r - s_first));
         } else {
             ev.push_back(unapply_event(c, k));
         }
@@ -92,7 +112,7 @@ std::vector<Event> gradient_events(const Circuit &c) {
 }
 
 bool executable(const Event &e, const std::vector<uint8_t> &in_tile) {
-    if (e.kind == EV_PROD) return e.type[0] == TY_Z || in_tile[e.q[0]];
+    if (e.kind == EV_PROD || e.kind == EV_SEED) return e.type[0] == TY_Z || in_tile[e.q[0]];
     switch (e.gkind) {
     case QNG_CNOT: return in_tile[e.q[1]];
     case QNG_CZ: return in_tile[e.q[0]] || in_tile[e.q[1]];
@@ -100,27 +120,52 @@ bool executable(const Event &e, const std::vector<uint8_t> &in_tile) {
     }
 }
 
+// Ordering state of an in-order scan: per qubit and Pauli type, the pending
+// (not emitted) events seen so far, and the highest phi register whose seed is
+// pending.  An event is ready when it commutes with every pending event before
+// it, and an inner product also waits for the seeds of the phi registers it
+// reads.
+struct Blockers {
+    std::vector<int> cnt;
+    int seed_b = -1;
+    explicit Blockers(int n) : cnt((size_t)n * 3, 0) {}
+    bool ready(const Event &e) const {
+        for (int j = 0; j < e.nq; ++j) {
+            const int *cq = &cnt[(size_t)e.q[j] * 3];
+            for (int t = 0; t < 3; ++t)
+                if (t != e.type[j] && cq[t]) return false;
+        }
+        return !(e.kind == EV_PROD && e.fa <= seed_b);
+    }
+    void block(const Event &e) {
+        for (int j = 0; j < e.nq; ++j) ++cnt[(size_t)e.q[j] * 3 + e.type[j]];
+        if (e.kind == EV_SEED) seed_b = std::max(seed_b, e.sb);
+    }
+};
+
+// Inner-product slots an event takes: one per active phi register, one for
+// the T product of a seed.
+int event_slots(const Event &e, int width) {
+    if (e.kind == EV_PROD) return width - e.fa;
+    return e.kind == EV_SEED ? 1 : 0;
+}
+
 // One in-order scan: emit every pending event that is ready (no earlier pending
 // event it fails to commute with) and executable in the tile.  Returns the
 // number emitted; if `out` is given, the emitted indices are appended and the
 // events marked done.
 int scan(const std::vector<Event> &ev, std::vector<uint8_t> &done, const std::vector<int> &pending,
-         const std::vector<uint8_t> &in_tile, int n, std::vector<int> *out) {
-    std::vector<int> cnt((size_t)n * 3, 0);
+         const std::vector<uint8_t> &in_tile, int n, int width, std::vector<int> *out) {
+    Blockers bl(n);
     int emitted = 0, slots = 0;
     for (int idx : pending) {
         if (done[idx]) continue;
         const Event &e = ev[idx];
-        bool ready = true;
-        for (int j = 0; j < e.nq && ready; ++j) {
-            const int *cq = &cnt[(size_t)e.q[j] * 3];
-            for (int t = 0; t < 3; ++t)
-                if (t != e.type[j] && cq[t]) { ready = false; break; }
-        }
-        bool ok = ready && executable(e, in_tile);
-        if (ok && e.kind == EV_PROD) {
-            if (slots >= kMaxSlots) ok = false;
-            else ++slots;
+        bool ok = bl.ready(e) && executable(e, in_tile);
+        const int need = event_slots(e, width);
+        if (ok && need) {
+            if (slots + need > kMaxSlots) ok = false;
+            else slots += need;
         }
         if (ok) {
             ++emitted;
@@ -129,14 +174,14 @@ int scan(const std::vector<Event> &ev, std::vector<uint8_t> &done, const std::ve
                 done[idx] = 1;
             }
         } else {
-            for (int j = 0; j < e.nq; ++j) ++cnt[(size_t)e.q[j] * 3 + e.type[j]];
+            bl.block(e);
         }
     }
     return emitted;
 }
 
 int choose_and_emit(const std::vector<Event> &ev, std::vector<uint8_t> &done, std::vector<int> &pending, int n, int m,
-                    int carriers, std::vector<uint8_t> &tile_out, std::vector<int> &emitted) {
+                    int carriers, int width, std::vector<uint8_t> &tile_out, std::vector<int> &emitted) {
     std::vector<uint8_t> in_tile(n, 0);
     if (n <= m) {
         std::fill(in_tile.begin(), in_tile.end(), 1);
@@ -145,27 +190,23 @@ int choose_and_emit(const std::vector<Event> &ev, std::vector<uint8_t> &done, st
         int best = -1;
         std::vector<uint8_t> best_tile;
         auto consider = [&](const std::vector<uint8_t> &cand) {
-            const int sc = scan(ev, done, pending, cand, n, nullptr);
+            const int sc = scan(ev, done, pending, cand, n, width, nullptr);
             if (sc > best) { best = sc; best_tile = cand; }
         };
         // candidate 1: carriers + qubits of the first ready-but-blocked events
         {
             std::vector<uint8_t> cand(n, 0);
             for (int q = 0; q < carriers; ++q) cand[q] = 1;
-            std::vector<int> cnt((size_t)n * 3, 0);
+            Blockers bl(n);
             int added = 0;
             for (int idx : pending) {
                 if (done[idx] || added >= w) continue;
                 const Event &e = ev[idx];
-                bool ready = true;
-                for (int j = 0; j < e.nq && ready; ++j)
-                    for (int t = 0; t < 3; ++t)
-                        if (t != e.type[j] && cnt[(size_t)e.q[j] * 3 + t]) { ready = false; break; }
-                if (ready && !executable(e, cand)) {
+                if (bl.ready(e) && !executable(e, cand)) {
                     const int need = (e.kind == EV_UNAPPLY && e.gkind == QNG_CNOT) ? e.q[1] : e.q[0];
                     if (!cand[need]) { cand[need] = 1; ++added; }
                 }
-                for (int j = 0; j < e.nq; ++j) ++cnt[(size_t)e.q[j] * 3 + e.type[j]];
+                bl.block(e);
             }
             consider(cand);
         }
@@ -184,7 +225,7 @@ int choose_and_emit(const std::vector<Event> &ev, std::vector<uint8_t> &done, st
             if (!in_tile[q]) { in_tile[q] = 1; ++have; }
     }
     emitted.clear();
-    const int k = scan(ev, done, pending, in_tile, n, &emitted);
+    const int k = scan(ev, done, pending, in_tile, n, width, &emitted);
     if (k == 0) fail(QNG_E_DEVICE, "sweep planner made no progress (internal error)");
     tile_out.clear();
     for (int q = 0; q < n; ++q)
@@ -202,7 +243,7 @@ int choose_and_emit(const std::vector<Event> &ev, std::vector<uint8_t> &done, st
 // Local bit that an event needs in a register (X/Y rotations and inner
 // products, CNOT targets), or -1 for diagonal events that run on any bit.
 int needs_register(const Event &e, const std::vector<int> &local) {
-    if (e.kind == EV_PROD) return e.type[0] == TY_Z ? -1 : local[e.q[0]];
+    if (e.kind == EV_PROD || e.kind == EV_SEED) return e.type[0] == TY_Z ? -1 : local[e.q[0]];
     switch (e.gkind) {
     case QNG_RX:
     case QNG_RY: return local[e.q[0]];
@@ -215,19 +256,13 @@ int needs_register(const Event &e, const std::vector<int> &local) {
 // bits): emit every ready event whose register need is met.
 int scan_phase(const std::vector<Event> &ev, const std::vector<int> &pending, std::vector<uint8_t> &done,
                uint32_t regset, const std::vector<int> &local, int n, std::vector<int> *out) {
-    std::vector<int> cnt((size_t)n * 3, 0);
+    Blockers bl(n);
     int emitted = 0;
     for (int idx : pending) {
         if (done[idx]) continue;
         const Event &e = ev[idx];
-        bool ready = true;
-        for (int j = 0; j < e.nq && ready; ++j) {
-            const int *cq = &cnt[(size_t)e.q[j] * 3];
-            for (int t = 0; t < 3; ++t)
-                if (t != e.type[j] && cq[t]) { ready = false; break; }
-        }
         const int need = needs_register(e, local);
-        const bool ok = ready && (need < 0 || ((regset >> need) & 1u));
+        const bool ok = bl.ready(e) && (need < 0 || ((regset >> need) & 1u));
         if (ok) {
             ++emitted;
             if (out) {
@@ -235,7 +270,7 @@ int scan_phase(const std::vector<Event> &ev, const std::vector<int> &pending, st
                 done[idx] = 1;
             }
         } else {
-            for (int j = 0; j < e.nq; ++j) ++cnt[(size_t)e.q[j] * 3 + e.type[j]];
+            bl.block(e);
         }
     }
     return emitted;
@@ -260,11 +295,15 @@ uint8_t location(const DevMap &mp, int rb, int m, int localbit) {
     return kLocBase;
 }
 
-// dest_stride, dest_offset: destination of the inner product of rotation r is
-// r * dest_stride + dest_offset (metric column s: r * P + s; gradient: r).
-HostPass make_pass(const Circuit &c, int dest_stride, int dest_offset, const std::vector<Event> &ev,
-                   const std::vector<int> &emitted,
-                   const std::vector<uint8_t> &tile, int rb, int carriers) {
+// Destinations of a block's inner products: element (r, column of phi register
+// b) -> r * stride + col0 + b (metric: r * P + s_b; gradient: r); the T product
+// of a seeded column s_b -> t_base + s_b.
+struct SlotDest {
+    int stride, col0, t_base;
+};
+
+HostPass make_pass(const Circuit &c, const SlotDest &sd, const std::vector<Event> &ev, const std::vector<int> &emitted,
+                   const std::vector<uint8_t> &tile, int rb, int carriers, int width) {
     HostPass hp;
     hp.tile = tile;
     hp.rb = rb;
@@ -285,17 +324,13 @@ HostPass make_pass(const Circuit &c, int dest_stride, int dest_offset, const std
         {   // registers for the first ready events that need one
             uint32_t rs = 0;
             int added = 0;
-            std::vector<int> cnt((size_t)c.n * 3, 0);
+            Blockers bl(c.n);
             for (int idx : pending) {
                 if (added >= rb) break;
                 const Event &e = ev[idx];
-                bool ready = true;
-                for (int j = 0; j < e.nq && ready; ++j)
-                    for (int t = 0; t < 3; ++t)
-                        if (t != e.type[j] && cnt[(size_t)e.q[j] * 3 + t]) { ready = false; break; }
                 const int need = needs_register(e, local);
-                if (ready && need >= 0 && !((rs >> need) & 1u)) { rs |= 1u << need; ++added; }
-                for (int j = 0; j < e.nq; ++j) ++cnt[(size_t)e.q[j] * 3 + e.type[j]];
+                if (bl.ready(e) && need >= 0 && !((rs >> need) & 1u)) { rs |= 1u << need; ++added; }
+                bl.block(e);
             }
             for (int b = m - 1; b >= 0 && added < rb; --b)
                 if (!((rs >> b) & 1u)) { rs |= 1u << b; ++added; }
@@ -357,10 +392,21 @@ HostPass make_pass(const Circuit &c, int dest_stride, int dest_offset, const std
             DevOp op{};
             op.b0 = op.b1 = kLocBase;
             op.gate = -1;
-            if (e.kind == EV_PROD) {
+            if (e.kind == EV_SEED) {
+                const int q = e.q[0];
+                op.type = OP_SEED;
+                op.slot = (uint16_t)hp.slot_dest.size();
+                hp.slot_dest.push_back((int32_t)(sd.t_base + sd.col0 + e.sb));
+                op.axis = e.type[0];
+                op.q0 = (uint8_t)q;
+                op.b0 = loc_of_qubit(q);
+                op.aux = e.sb;
+            } else if (e.kind == EV_PROD) {
                 const int q = e.q[0];
                 op.slot = (uint16_t)hp.slot_dest.size();
-                hp.slot_dest.push_back((int32_t)(e.rot * dest_stride + dest_offset));
+                for (int b = e.fa; b < width; ++b)
+                    hp.slot_dest.push_back((int32_t)(e.rot * sd.stride + sd.col0 + b));
+                op.aux = e.fa;
                 op.axis = e.type[0];
                 op.q0 = (uint8_t)q;
                 const bool fuse = k + 1 < order.size() && ev[order[k + 1]].kind == EV_UNAPPLY &&
@@ -443,8 +489,8 @@ void plan_shape(SweepPlan &plan, const Circuit &c, int tile_qubits, int amp_byte
     if (c.n > m && m - plan.carriers < 2) fail(QNG_E_INVALID_ARG, "tile too small for the carrier qubits");
 }
 
-ColumnPlan plan_column(const Circuit &c, const SweepPlan &plan, int s, const std::vector<Event> &ev, int dest_stride,
-                       int dest_offset) {
+ColumnPlan plan_column(const Circuit &c, const SweepPlan &plan, int s, const std::vector<Event> &ev,
+                       const SlotDest &sd) {
     ColumnPlan cp;
     cp.s = s;
     std::vector<uint8_t> done(ev.size(), 0);
@@ -453,8 +499,8 @@ ColumnPlan plan_column(const Circuit &c, const SweepPlan &plan, int s, const std
     std::vector<uint8_t> tile;
     std::vector<int> emitted;
     while (!pending.empty()) {
-        choose_and_emit(ev, done, pending, c.n, plan.m, plan.carriers, tile, emitted);
-        cp.passes.push_back(make_pass(c, dest_stride, dest_offset, ev, emitted, tile, plan.rb, plan.carriers));
+        choose_and_emit(ev, done, pending, c.n, plan.m, plan.carriers, plan.width, tile, emitted);
+        cp.passes.push_back(make_pass(c, sd, ev, emitted, tile, plan.rb, plan.carriers, plan.width));
     }
     return cp;
 }
@@ -504,10 +550,20 @@ void flatten(SweepPlan &plan, const Circuit &c) {
 
 }  // namespace
 
-SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int /*small*/, bool reg_f64) {
+SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int /*small*/, bool reg_f64,
+                           int width) {
+    if (width < 1 || width > kMaxBlockWidth) fail(QNG_E_INVALID_ARG, "column block width must be 1 or 2");
     SweepPlan plan;
+    plan.width = width;
     plan_shape(plan, c, tile_qubits, amp_bytes, reg_f64);
-    for (int s = 1; s < c.P; ++s) plan.cols.push_back(plan_column(c, plan, s, column_events(c, s), c.P, s));
+    // blocks from the top: columns P-1, P-1-width, ...; the lowest block may
+    // have fewer real columns (its phi registers below column 1 stay unused)
+    std::vector<int> tops;
+    for (int s = c.P - 1; s >= 1; s -= width) tops.push_back(s);
+    std::reverse(tops.begin(), tops.end());
+    for (int s : tops)
+        plan.cols.push_back(plan_column(c, plan, s, block_events(c, s, width),
+                                        SlotDest{c.P, s - width + 1, c.P * c.P}));
     flatten(plan, c);
     return plan;
 }
@@ -515,7 +571,7 @@ SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int
 SweepPlan build_gradient_plan(const Circuit &c, int tile_qubits, int amp_bytes, bool reg_f64) {
     SweepPlan plan;
     plan_shape(plan, c, tile_qubits, amp_bytes, reg_f64);
-    if (c.P > 0) plan.cols.push_back(plan_column(c, plan, c.P, gradient_events(c), 1, 0));
+    if (c.P > 0) plan.cols.push_back(plan_column(c, plan, c.P, gradient_events(c), SlotDest{1, 0, 0}));
     flatten(plan, c);
     return plan;
 }
@@ -560,6 +616,7 @@ uint8_t device_opcode(const DevOp &op) {
     case OP_CZ: return OPC_CZ;
     case OP_ZSUM: return OPC_ZSUM;
     case OP_XPOSE: return OPC_XPOSE;
+    case OP_SEED: return OPC_SEED;
     default: fail(QNG_E_DEVICE, "device op: unknown kind (internal)");
     }
     return 0;
@@ -588,6 +645,7 @@ int device_handler(uint8_t c) {
     if (c == OPC_CZ) return HB_CZ;
     if (c == OPC_ZSUM) return HB_ZSUM;
     if (c == OPC_XPOSE) return HB_XPOSE;
+    if (c == OPC_SEED) return HB_SEED;
     fail(QNG_E_DEVICE, "device handler: unknown op code (internal)");
     return 0;
 }
@@ -605,13 +663,13 @@ void append_structure_key(const Circuit &c, std::vector<int32_t> &key) {
 }
 
 std::shared_ptr<const SweepPlan> SweepCache::get_shared(const Circuit &c, int tile_qubits, int amp_bytes, int small,
-                                                        bool reg_f64) {
-    std::vector<int32_t> key = {tile_qubits, amp_bytes, small, reg_f64 ? 1 : 0};
+                                                        bool reg_f64, int width) {
+    std::vector<int32_t> key = {tile_qubits, amp_bytes, small, reg_f64 ? 1 : 0, width};
     append_structure_key(c, key);
     auto it = plans.find(key);
     if (it != plans.end()) return it->second;
     if (plans.size() >= 256) plans.clear();
-    auto p = std::make_shared<SweepPlan>(build_sweep_plan(c, tile_qubits, amp_bytes, small, reg_f64));
+    auto p = std::make_shared<SweepPlan>(build_sweep_plan(c, tile_qubits, amp_bytes, small, reg_f64, width));
     plans[key] = p;
     return p;
 }
@@ -638,8 +696,8 @@ FusedRun fused_config(const SweepPlan &plan, int requested_streams, size_t state
         B = (int)std::max<int64_t>(1, (target + tiles - 1) / tiles);
     }
     if (B > cols) B = std::max(1, cols);
-    // keep the column registers within a quarter of the free memory
-    while (B > 1 && (size_t)(1 + 2 * B) * state_bytes > free_bytes / 4) --B;
+    // keep the block registers within a quarter of the free memory
+    while (B > 1 && (size_t)(1 + (plan.width + 1) * B) * state_bytes > free_bytes / 4) --B;
     fr.B = B;
     fr.partial_elems = (size_t)B * (size_t)plan.max_slots * (size_t)tiles + 16;
     return fr;

@@ -53,7 +53,9 @@ enum : uint8_t {
     OP_DIAG = 6,      // RZ adjoint diag(m00, m11) on location b0
     OP_PRODZ = 7,     // Z inner product on location b0
     OP_PRODDIAG = 8,  // Z inner product on location b0, then the RZ adjoint there
-    OP_XPOSE = 9      // exchange through LDS to the thread mapping `aux`
+    OP_XPOSE = 9,     // exchange through LDS to the thread mapping `aux`
+    OP_SEED = 10      // column block: phi register `aux` <- sigma lambda (sigma on qubit q0, location b0),
+                      // then <lambda|phi> into the op's slot
 };
 
 // Device op codes.  In the flattened device images (SweepPlan::dev_ops and
@@ -82,7 +84,8 @@ enum : uint8_t {
     OPC_CNOT_BASE = 68,       // + j: control = bit q0 of the tile base
     OPC_CZ = 72,
     OPC_ZSUM = 73,
-    OPC_XPOSE = 74
+    OPC_XPOSE = 74,
+    OPC_SEED = 75
 };
 
 // Location of a local bit in the current thread mapping: a register position
@@ -93,13 +96,16 @@ constexpr uint8_t kLocBase = 0xFF;
 constexpr int kMaxSlots = 64;       // inner products per pass
 constexpr int kMaxTileQubits = 13;
 constexpr int kMaxRest = 24;        // qubits outside a tile
+constexpr int kMaxBlockWidth = 2;   // columns sharing one lambda sweep
+constexpr int kDefaultBlockWidth = 2;   // measured at n = 26: 8-11 % less sweep time than 1
 
 struct DevOp {  // 32 bytes
     uint8_t type, b0, b1, axis;
-    uint16_t slot;
+    uint16_t slot;    // inner products: slot of the first active phi register (one slot per active phi)
     uint8_t q0, q1;   // qubits (global) the operation acts on
     int32_t gate;     // gate position: row of the matrix table
-    int32_t aux;      // OP_XPOSE: mapping index
+    int32_t aux;      // OP_XPOSE: mapping index; inner products: first active phi register;
+                      // OP_SEED: the phi register seeded
     uint32_t hlo, hhi;   // device images: one-hot handler bit (HB_* below), low and high word
     uint32_t pad0, pad1;
 };
@@ -149,7 +155,8 @@ enum : int {
     HB_PRODDIAG_UNI = 41,
     HB_CNOT_REG = 42,        // + index of (j, k), k != j: 3 j + (k < j ? k : k - 1)
     HB_CNOT_THR = 54,        // + j
-    HB_CNOT_BASE = 58        // + j
+    HB_CNOT_BASE = 58,       // + j
+    HB_SEED = 62
 };
 int device_handler(uint8_t opcode);
 static_assert(sizeof(DevOp) == 32, "DevOp layout");
@@ -165,14 +172,19 @@ struct HostPass {
     int transposes = 0;
 };
 
+// A column block: the columns s - width + 1 .. s (those >= 1) share one
+// lambda sweep.  Column s (phi register width - 1) is seeded before the first
+// pass; each lower column s_b (phi register b) is seeded inside the sweep
+// (OP_SEED) where lambda reaches y_{s_b}.  With width 1 a block is one column.
 struct ColumnPlan {
-    int s = 0;                          // rotation index of the column
+    int s = 0;                          // top column of the block
     std::vector<HostPass> passes;
 };
 
 struct SweepPlan {
     int n = 0, m = 0, carriers = 0, P = 0;
-    std::vector<ColumnPlan> cols;       // columns 1..P-1 (column 0 has no elements)
+    int width = 1;                      // columns per block (phi registers per sweep)
+    std::vector<ColumnPlan> cols;       // blocks, top columns P-1, P-1-width, ... (>= 1)
     // flattened device images
     std::vector<DevPass> dev_passes;
     std::vector<DevOp> dev_ops;
@@ -192,7 +204,10 @@ int register_bits(int m, int amp_bytes);
 // Build the plan of all columns.  tile_qubits = 0 picks the default: 12 for
 // FP32 registers, 11 for FP64 registers (at most n).
 // reg_f64: tiles are computed in FP64 registers (always for complex128).
-SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int small, bool reg_f64);
+// width: columns per block (1 or kMaxBlockWidth).  Destinations: element
+// (r, s) -> r * P + s; T_s of a column seeded inside the sweep -> P * P + s.
+SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int small, bool reg_f64,
+                           int width = 1);
 int default_tile_qubits(int n, int amp_bytes, bool reg_f64);
 
 // Plan of the energy gradient's reverse sweep (one column, s = P): registers
@@ -202,13 +217,13 @@ SweepPlan build_gradient_plan(const Circuit &c, int tile_qubits, int amp_bytes, 
 
 struct SweepCache {
     std::map<std::vector<int32_t>, std::shared_ptr<SweepPlan>> plans;
-    const SweepPlan &get(const Circuit &c, int tile_qubits, int amp_bytes, int small, bool reg_f64) {
-        return *get_shared(c, tile_qubits, amp_bytes, small, reg_f64);
+    const SweepPlan &get(const Circuit &c, int tile_qubits, int amp_bytes, int small, bool reg_f64, int width = 1) {
+        return *get_shared(c, tile_qubits, amp_bytes, small, reg_f64, width);
     }
     // The plan stays alive while the caller holds the pointer, even if the
     // cache evicts it.
     std::shared_ptr<const SweepPlan> get_shared(const Circuit &c, int tile_qubits, int amp_bytes, int small,
-                                                bool reg_f64);
+                                                bool reg_f64, int width = 1);
     std::shared_ptr<const SweepPlan> get_gradient(const Circuit &c, int tile_qubits, int amp_bytes, bool reg_f64);
 };
 
@@ -222,9 +237,9 @@ struct LaunchItem {  // 48 bytes
     uint32_t ntiles;
     uint32_t pad;
     uint64_t partial_off;   // in complex doubles
-    void *regA;
-    void *regB;
-    uint64_t pad2;
+    void *regA;             // lambda
+    void *regB;             // phi register 0
+    void *regC;             // phi register 1 (blocks of two columns)
 };
 
 struct ReduceTask {  // 16 bytes: sum partials[off .. off+count) -> results[dest]
@@ -233,22 +248,29 @@ struct ReduceTask {  // 16 bytes: sum partials[off .. off+count) -> results[dest
     int32_t dest;
 };
 
+// Algorithmic flops per amplitude of one inner product of a sweep (one task):
+// 8 for <lambda|sigma|phi> (complex conjugate-multiply-add), 6 for the
+// rotation adjoint on phi and 6 on lambda, which a block of `width` columns
+// shares.
+inline double sweep_flops_per_amp(int width) { return 8.0 + 6.0 + 6.0 / width; }
+
 struct FusedRun {
     int B = 1;                 // columns swept concurrently
     size_t partial_elems = 0;  // complex doubles of partial sums
 };
 
-// Columns run concurrently and scratch sizes for a plan on a register of n qubits.
+// Blocks run concurrently and scratch sizes for a plan on a register of n qubits.
 FusedRun fused_config(const SweepPlan &plan, int requested_streams, size_t state_bytes, size_t free_bytes);
 
 // Kernel launchers (sweep_kernels.hip).
 // mats64 / mats32: per gate position 8 values, of which the first two are the
 // shear parameters (u, w) of the gate's adjoint (circuit.hpp, adjoint_shear),
 // in FP64 and FP32; the kernel reads the table of its register precision.
+// width: phi registers per item (the plan's column-block width).
 template <typename R>
 void launch_sweep_pass(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
                        const DevOp *ops, const DevMap *maps, const double *mats64, const float *mats32,
-                       double *partials, int m, int rb, bool f64_registers, hipStream_t st);
+                       double *partials, int m, int rb, bool f64_registers, int width, hipStream_t st);
 void launch_reduce_tasks(const ReduceTask *tasks, int n_tasks, const double *partials, double *results,
                          hipStream_t st);
 

@@ -1,7 +1,8 @@
 // sweep_kernels.hip -- the fused sweep-pass kernel for gfx950 (see sweep.hpp).
 //
 // One work-group of 256 threads (4 wave64) owns one tile: the 2^m amplitudes
-// of lambda (A) and phi (B) whose indices agree outside the pass's m tile
+// of lambda (A) and of the W phi registers (B; W = 1, or 2 for a block of two
+// columns sharing lambda) whose indices agree outside the pass's m tile
 // qubits.  The tile lives in registers: every thread holds T = 2^RB amplitudes
 // of each register, in the register precision CT (FP64 for complex128
 // storage; FP32 or FP64 for complex64 storage).  A thread mapping says which
@@ -65,14 +66,24 @@ __device__ __forceinline__ void row_sum(double &a, double &b) {
     b += dpp_shifted<0x118>(b);
 }
 
-// Store a per-lane partial of slot `slot`: one value per 16-lane row.  Every
-// lane stores (lane 15 of a row to the slot, the others to a sink entry of their
-// own), so the op loop has no divergent branch.
-__device__ __forceinline__ void row_store(double2 *red, int slot, int tid, double a, double b) {
+// LDS layout of the sweep kernel: the exchange buffer [2^m] (at least the
+// kMaxBlockWidth x kRows tile sums <lambda|phi_b>, which use its start while
+// no exchange runs: both sit between barriers), one sink entry per thread,
+// the per-row partials of the inner products [kMaxSlots][kRows].
+constexpr int kLdsTailEntries = kThreads + kMaxSlots * kRows;
+template <typename CX> __host__ __device__ constexpr size_t xbuf_bytes(int m) {
+    return ((size_t)1 << m) * sizeof(CX) > (size_t)kMaxBlockWidth * kRows * 16
+               ? ((size_t)1 << m) * sizeof(CX)
+               : (size_t)kMaxBlockWidth * kRows * 16;
+}
+
+// Store a per-lane partial of slot `slot` of `dst`: one value per 16-lane row.
+// Every lane stores (lane 15 of a row to the slot, the others to their own
+// sink entry), so the op loop has no divergent branch.
+__device__ __forceinline__ void row_store(double2 *sink, double2 *dst, int slot, int tid, double a, double b) {
     row_sum(a, b);
-    double2 *sink = red + (kMaxSlots + 1) * kRows;
-    double2 *dst = ((tid & 15) == 15) ? red + slot * kRows + (tid >> 4) : sink + tid;
-    *dst = make_double2(a, b);
+    double2 *p = ((tid & 15) == 15) ? dst + slot * kRows + (tid >> 4) : sink;
+    *p = make_double2(a, b);
 }
 
 // The tile is kept as four arrays of T scalars per thread: real and imaginary
@@ -81,9 +92,10 @@ __device__ __forceinline__ void row_store(double2 *red, int slot, int tid, doubl
 // each element stays in one register through the whole op loop; as short
 // vectors, the CNOT handlers of the T=16 tile rebuilt whole vectors (a copy of
 // the tile per op).
-template <typename CT, int T>
+template <typename CT, int T, int W>
 struct Regs {
-    CT ar[T], ai[T], br[T], bi[T];
+    CT ar[T], ai[T];           // lambda
+    CT br[W][T], bi[W][T];     // phi registers
 };
 
 // 2x2 complex matrix entries of the gate table in the register precision
@@ -118,15 +130,16 @@ __device__ __forceinline__ void cfma(double &r, double &i, double ar, double ai,
 // Y: i * sum over pairs of (conj(a1) b0 - conj(a0) b1).
 // (<A|X|B> and <A|Y|B> on register bit J; Y = [[0, -i], [i, 0]].)
 template <int J, int AX, int T, typename CT>
-__device__ __forceinline__ void prod_xy(const Regs<CT, T> &x, double &pr, double &pi) {
+__device__ __forceinline__ void prod_xy(const CT (&ar)[T], const CT (&ai)[T], const CT (&br)[T], const CT (&bi)[T],
+                                        double &pr, double &pi) {
     double r0 = 0.0, i0 = 0.0, r1 = 0.0, i1 = 0.0;
     int pair = 0;
 #pragma unroll
     for (int i = 0; i < T; ++i) {
         if (i & (1 << J)) continue;
         const int k = i | (1 << J);
-        const double a0r = x.ar[i], a0i = x.ai[i], a1r = x.ar[k], a1i = x.ai[k];
-        const double b0r = x.br[i], b0i = x.bi[i], b1r = x.br[k], b1i = x.bi[k];
+        const double a0r = ar[i], a0i = ai[i], a1r = ar[k], a1i = ai[k];
+        const double b0r = br[i], b0i = bi[i], b1r = br[k], b1i = bi[k];
         double &r = (pair & 1) ? r1 : r0;
         double &m = (pair & 1) ? i1 : i0;
         if (pair < 2) cfma<true, AX == 1>(r, m, a0r, a0i, b1r, b1i);
@@ -146,7 +159,8 @@ __device__ __forceinline__ void prod_xy(const Regs<CT, T> &x, double &pr, double
 
 // Z on register bit J: sum_i (-1)^{bit J of i} conj(a_i) b_i
 template <int J, int T, typename CT>
-__device__ __forceinline__ void prod_z_reg(const Regs<CT, T> &x, double &pr, double &pi) {
+__device__ __forceinline__ void prod_z_reg(const CT (&ar)[T], const CT (&ai)[T], const CT (&br)[T],
+                                           const CT (&bi)[T], double &pr, double &pi) {
     double r0 = 0.0, i0 = 0.0, r1 = 0.0, i1 = 0.0;
 #pragma unroll
     for (int i = 0; i < T; ++i) {
@@ -154,11 +168,11 @@ __device__ __forceinline__ void prod_z_reg(const Regs<CT, T> &x, double &pr, dou
         double &m = (i & 1) ? i1 : i0;
         const bool neg = (i >> J) & 1;
         if (i < 2) {
-            if (neg) cfma<true, true>(r, m, x.ar[i], x.ai[i], x.br[i], x.bi[i]);
-            else cfma<true, false>(r, m, x.ar[i], x.ai[i], x.br[i], x.bi[i]);
+            if (neg) cfma<true, true>(r, m, ar[i], ai[i], br[i], bi[i]);
+            else cfma<true, false>(r, m, ar[i], ai[i], br[i], bi[i]);
         } else {
-            if (neg) cfma<false, true>(r, m, x.ar[i], x.ai[i], x.br[i], x.bi[i]);
-            else cfma<false, false>(r, m, x.ar[i], x.ai[i], x.br[i], x.bi[i]);
+            if (neg) cfma<false, true>(r, m, ar[i], ai[i], br[i], bi[i]);
+            else cfma<false, false>(r, m, ar[i], ai[i], br[i], bi[i]);
         }
     }
     pr = (T >= 2) ? r0 + r1 : r0;
@@ -167,18 +181,112 @@ __device__ __forceinline__ void prod_z_reg(const Regs<CT, T> &x, double &pr, dou
 
 // sum_i conj(a_i) b_i (the caller applies a sign common to all registers)
 template <int T, typename CT>
-__device__ __forceinline__ void prod_plain(const Regs<CT, T> &x, double &pr, double &pi) {
+__device__ __forceinline__ void prod_plain(const CT (&ar)[T], const CT (&ai)[T], const CT (&br)[T],
+                                           const CT (&bi)[T], double &pr, double &pi) {
     double r0 = 0.0, i0 = 0.0, r1 = 0.0, i1 = 0.0;
 #pragma unroll
     for (int i = 0; i < T; ++i) {
         double &r = (i & 1) ? r1 : r0;
         double &m = (i & 1) ? i1 : i0;
-        if (i < 2) cfma<true, false>(r, m, x.ar[i], x.ai[i], x.br[i], x.bi[i]);
-        else cfma<false, false>(r, m, x.ar[i], x.ai[i], x.br[i], x.bi[i]);
+        if (i < 2) cfma<true, false>(r, m, ar[i], ai[i], br[i], bi[i]);
+        else cfma<false, false>(r, m, ar[i], ai[i], br[i], bi[i]);
     }
     pr = (T >= 2) ? r0 + r1 : r0;
     pi = (T >= 2) ? i0 + i1 : i0;
 }
+
+// The same products for every phi register of the tile at once, lambda's
+// values converted once per pair for all of them.
+template <int J, int AX, int T, typename CT, int W>
+__device__ __forceinline__ void prodw_xy(const Regs<CT, T, W> &x, double (&pr)[W], double (&pi)[W]) {
+    double r0[W], i0[W], r1[W], i1[W];
+    int pair = 0;
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        if (i & (1 << J)) continue;
+        const int k = i | (1 << J);
+        const double a0r = x.ar[i], a0i = x.ai[i], a1r = x.ar[k], a1i = x.ai[k];
+#pragma unroll
+        for (int b = 0; b < W; ++b) {
+            const double b0r = x.br[b][i], b0i = x.bi[b][i], b1r = x.br[b][k], b1i = x.bi[b][k];
+            double &r = (pair & 1) ? r1[b] : r0[b];
+            double &m = (pair & 1) ? i1[b] : i0[b];
+            if (pair < 2) cfma<true, AX == 1>(r, m, a0r, a0i, b1r, b1i);
+            else cfma<false, AX == 1>(r, m, a0r, a0i, b1r, b1i);
+            cfma<false, false>(r, m, a1r, a1i, b0r, b0i);
+        }
+        ++pair;
+    }
+#pragma unroll
+    for (int b = 0; b < W; ++b) {
+        const double sr = (T >= 4) ? r0[b] + r1[b] : r0[b], si = (T >= 4) ? i0[b] + i1[b] : i0[b];
+        pr[b] = AX == 0 ? sr : -si;
+        pi[b] = AX == 0 ? si : sr;
+    }
+}
+
+template <int J, int T, typename CT, int W>
+__device__ __forceinline__ void prodw_z_reg(const Regs<CT, T, W> &x, double (&pr)[W], double (&pi)[W]) {
+    double r0[W], i0[W], r1[W], i1[W];
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        const double ar = x.ar[i], ai = x.ai[i];
+        const bool neg = (i >> J) & 1;
+#pragma unroll
+        for (int b = 0; b < W; ++b) {
+            double &r = (i & 1) ? r1[b] : r0[b];
+            double &m = (i & 1) ? i1[b] : i0[b];
+            if (i < 2) {
+                if (neg) cfma<true, true>(r, m, ar, ai, x.br[b][i], x.bi[b][i]);
+                else cfma<true, false>(r, m, ar, ai, x.br[b][i], x.bi[b][i]);
+            } else {
+                if (neg) cfma<false, true>(r, m, ar, ai, x.br[b][i], x.bi[b][i]);
+                else cfma<false, false>(r, m, ar, ai, x.br[b][i], x.bi[b][i]);
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < W; ++b) {
+        pr[b] = (T >= 2) ? r0[b] + r1[b] : r0[b];
+        pi[b] = (T >= 2) ? i0[b] + i1[b] : i0[b];
+    }
+}
+
+template <int T, typename CT, int W>
+__device__ __forceinline__ void prodw_plain(const Regs<CT, T, W> &x, double (&pr)[W], double (&pi)[W]) {
+    double r0[W], i0[W], r1[W], i1[W];
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        const double ar = x.ar[i], ai = x.ai[i];
+#pragma unroll
+        for (int b = 0; b < W; ++b) {
+            double &r = (i & 1) ? r1[b] : r0[b];
+            double &m = (i & 1) ? i1[b] : i0[b];
+            if (i < 2) cfma<true, false>(r, m, ar, ai, x.br[b][i], x.bi[b][i]);
+            else cfma<false, false>(r, m, ar, ai, x.br[b][i], x.bi[b][i]);
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < W; ++b) {
+        pr[b] = (T >= 2) ? r0[b] + r1[b] : r0[b];
+        pi[b] = (T >= 2) ? i0[b] + i1[b] : i0[b];
+    }
+}
+
+// The inner products <lambda|sigma|phi_b> of every phi register into
+// pr[b], pi[b] (PROD(re_a, im_a, re_b, im_b, pr, pi) forms one), and their
+// stores: the active registers fa .. W-1 into consecutive slots from `slot`,
+// the others into the sink (no branch).
+// The stores come after the op's tile update, as in the one-register kernel
+// (its register allocation depends on that order).
+#define QNG_PRODS(PRODW)                                                                                     \
+    double pr[W], pi[W];                                                                                     \
+    PRODW(x, pr, pi)
+#define QNG_STORE_PRODS()                                                                                    \
+    _Pragma("unroll") for (int b_ = 0; b_ < W; ++b_) {                                                       \
+        const bool keep_ = W == 1 || b_ >= fa;                                                               \
+        row_store(sink, keep_ ? red : sink - tid, keep_ ? slot + b_ - fa : 0, tid, pr[b_], pi[b_]);          \
+    }
 
 // ------------------------------------------------------- gates on registers
 
@@ -207,48 +315,53 @@ __device__ __forceinline__ Pair<CT> shear3(CT a, CT b, CT u, CT w) {
         B = r_.b;                               \
     } while (0)
 
-// Adjoint X/Y rotation on the pairs of register bit J: RX on (re x0, im x1)
-// and (re x1, im x0), RY on (re x0, re x1) and (im x0, im x1).
+// Adjoint X/Y rotation on the pairs of register bit J of one register (re,
+// im): RX on (re x0, im x1) and (re x1, im x0), RY on (re x0, re x1) and
+// (im x0, im x1).
 template <int J, int AX, int T, typename CT>
-__device__ __forceinline__ void rot_xy(Regs<CT, T> &x, CT u, CT w) {
+__device__ __forceinline__ void rot_xy1(CT (&re)[T], CT (&im)[T], CT u, CT w) {
 #pragma unroll
     for (int i = 0; i < T; ++i) {
         if (i & (1 << J)) continue;
         const int k = i | (1 << J);
         if (AX == 0) {
-            QNG_SHEAR(x.ar[i], x.ai[k], u, w);
-            QNG_SHEAR(x.ar[k], x.ai[i], u, w);
-            QNG_SHEAR(x.br[i], x.bi[k], u, w);
-            QNG_SHEAR(x.br[k], x.bi[i], u, w);
+            QNG_SHEAR(re[i], im[k], u, w);
+            QNG_SHEAR(re[k], im[i], u, w);
         } else {
-            QNG_SHEAR(x.ar[i], x.ar[k], u, w);
-            QNG_SHEAR(x.ai[i], x.ai[k], u, w);
-            QNG_SHEAR(x.br[i], x.br[k], u, w);
-            QNG_SHEAR(x.bi[i], x.bi[k], u, w);
+            QNG_SHEAR(re[i], re[k], u, w);
+            QNG_SHEAR(im[i], im[k], u, w);
         }
     }
+}
+template <int J, int AX, int T, typename CT, int W>
+__device__ __forceinline__ void rot_xy(Regs<CT, T, W> &x, CT u, CT w) {
+    rot_xy1<J, AX, T, CT>(x.ar, x.ai, u, w);
+#pragma unroll
+    for (int b = 0; b < W; ++b) rot_xy1<J, AX, T, CT>(x.br[b], x.bi[b], u, w);
 }
 
 // RZ adjoint on register bit J: (re, im) of the |0> amplitude rotated by
 // (u, w), of the |1> amplitude by (-u, -w)
-template <int J, int T, typename CT>
-__device__ __forceinline__ void diag_reg(Regs<CT, T> &x, CT u, CT w) {
+template <int J, int T, typename CT, int W>
+__device__ __forceinline__ void diag_reg(Regs<CT, T, W> &x, CT u, CT w) {
 #pragma unroll
     for (int i = 0; i < T; ++i) {
         const bool one = (i >> J) & 1;
         const CT ui = one ? -u : u, wi = one ? -w : w;
         QNG_SHEAR(x.ar[i], x.ai[i], ui, wi);
-        QNG_SHEAR(x.br[i], x.bi[i], ui, wi);
+#pragma unroll
+        for (int b = 0; b < W; ++b) QNG_SHEAR(x.br[b][i], x.bi[b][i], ui, wi);
     }
 }
 
 // one rotation for every register (bit held by the thread index or the tile base)
-template <int T, typename CT>
-__device__ __forceinline__ void diag_all(Regs<CT, T> &x, CT u, CT w) {
+template <int T, typename CT, int W>
+__device__ __forceinline__ void diag_all(Regs<CT, T, W> &x, CT u, CT w) {
 #pragma unroll
     for (int i = 0; i < T; ++i) {
         QNG_SHEAR(x.ar[i], x.ai[i], u, w);
-        QNG_SHEAR(x.br[i], x.bi[i], u, w);
+#pragma unroll
+        for (int b = 0; b < W; ++b) QNG_SHEAR(x.br[b][i], x.bi[b][i], u, w);
     }
 }
 
@@ -277,36 +390,51 @@ __device__ __forceinline__ void swap_in_place(double &a, double &b) {
     b = __builtin_bit_cast(double, (uint64_t)blo | ((uint64_t)bhi << 32));
 }
 
-// CNOT adjoint (itself) with target register bit J and control register bit K:
-// the pairs of bit J whose bit K is set trade places.
+// The pairs of register bit J whose bit K is set (K < 0: every pair) trade
+// places in one register.
 template <int J, int K, int T, typename CT>
-__device__ __forceinline__ void cnot_reg(Regs<CT, T> &x) {
+__device__ __forceinline__ void swap_pairs(CT (&re)[T], CT (&im)[T]) {
 #pragma unroll
     for (int i = 0; i < T; ++i) {
-        if ((i & (1 << J)) || !(i & (1 << K))) continue;
+        if ((i & (1 << J)) || (K >= 0 && !(i & (1 << K)))) continue;
         const int k = i | (1 << J);
-        swap_in_place(x.ar[i], x.ar[k]);
-        swap_in_place(x.ai[i], x.ai[k]);
-        swap_in_place(x.br[i], x.br[k]);
-        swap_in_place(x.bi[i], x.bi[k]);
+        swap_in_place(re[i], re[k]);
+        swap_in_place(im[i], im[k]);
     }
+}
+
+// dst <- src written into the register that holds dst (an opaque in-place
+// move: a plain copy would let the compiler hand dst the register of src, and
+// the tile would then need a second register set wherever the paths merge).
+__device__ __forceinline__ void move_in_place(float &dst, float src) {
+    asm("v_mov_b32 %0, %1" : "+v"(dst) : "v"(src));
+}
+__device__ __forceinline__ void move_in_place(double &dst, double src) {
+    uint32_t dlo = (uint32_t)__builtin_bit_cast(uint64_t, dst), dhi = (uint32_t)(__builtin_bit_cast(uint64_t, dst) >> 32);
+    const uint32_t slo = (uint32_t)__builtin_bit_cast(uint64_t, src), shi = (uint32_t)(__builtin_bit_cast(uint64_t, src) >> 32);
+    asm("v_mov_b32 %0, %1" : "+v"(dlo) : "v"(slo));
+    asm("v_mov_b32 %0, %1" : "+v"(dhi) : "v"(shi));
+    dst = __builtin_bit_cast(double, (uint64_t)dlo | ((uint64_t)dhi << 32));
+}
+
+// CNOT adjoint (itself) with target register bit J and control register bit K:
+// the pairs of bit J whose bit K is set trade places.
+template <int J, int K, int T, typename CT, int W>
+__device__ __forceinline__ void cnot_reg(Regs<CT, T, W> &x) {
+    swap_pairs<J, K, T, CT>(x.ar, x.ai);
+#pragma unroll
+    for (int b = 0; b < W; ++b) swap_pairs<J, K, T, CT>(x.br[b], x.bi[b]);
 }
 
 // CNOT with target register bit J and a control common to all registers of
 // the thread (thread bit or tile base): every pair of bit J trades places
 // where the control is set.
-template <int J, int T, typename CT>
-__device__ __forceinline__ void cnot_cond(Regs<CT, T> &x, bool control) {
+template <int J, int T, typename CT, int W>
+__device__ __forceinline__ void cnot_cond(Regs<CT, T, W> &x, bool control) {
     if (control) {
+        swap_pairs<J, -1, T, CT>(x.ar, x.ai);
 #pragma unroll
-        for (int i = 0; i < T; ++i) {
-            if (i & (1 << J)) continue;
-            const int k = i | (1 << J);
-            swap_in_place(x.ar[i], x.ar[k]);
-            swap_in_place(x.ai[i], x.ai[k]);
-            swap_in_place(x.br[i], x.br[k]);
-            swap_in_place(x.bi[i], x.bi[k]);
-        }
+        for (int b = 0; b < W; ++b) swap_pairs<J, -1, T, CT>(x.br[b], x.bi[b]);
     }
 }
 
@@ -461,73 +589,215 @@ constexpr uint64_t cnot_uni_bits(int j) { return hbit(HB_CNOT_THR + j) | hbit(HB
 constexpr uint64_t cnot_reg_bits(int j) { return hbits(HB_CNOT_REG + 3 * j, 3); }   // target register bit j
 
 // X/Y rotation adjoints on register bit J, alone or after their inner product
-template <int J, int RB, int T, typename CT>
-__device__ __forceinline__ void rot_handlers(Regs<CT, T> &x, uint64_t hf, CT u, CT w, double2 *red, int slot,
-                                             int tid) {
+template <int J, int RB, int T, typename CT, int W>
+__device__ __forceinline__ void rot_handlers(Regs<CT, T, W> &x, uint64_t hf, CT u, CT w, double2 *sink, double2 *red, int slot,
+                                             int fa, int tid) {
     if constexpr (J < RB) {
         if (hf & hbit(HB_PRODROT_Y + J)) {
-            double pr, pi;
-            prod_xy<J, 1, T, CT>(x, pr, pi);
-            rot_xy<J, 1, T, CT>(x, u, w);
-            row_store(red, slot, tid, pr, pi);
+            QNG_PRODS((prodw_xy<J, 1, T, CT, W>));
+            rot_xy<J, 1, T, CT, W>(x, u, w);
+            QNG_STORE_PRODS();
         }
         if (hf & hbit(HB_PRODROT_X + J)) {
-            double pr, pi;
-            prod_xy<J, 0, T, CT>(x, pr, pi);
-            rot_xy<J, 0, T, CT>(x, u, w);
-            row_store(red, slot, tid, pr, pi);
+            QNG_PRODS((prodw_xy<J, 0, T, CT, W>));
+            rot_xy<J, 0, T, CT, W>(x, u, w);
+            QNG_STORE_PRODS();
         }
-        if (hf & hbit(HB_ROT_Y + J)) rot_xy<J, 1, T, CT>(x, u, w);
-        if (hf & hbit(HB_ROT_X + J)) rot_xy<J, 0, T, CT>(x, u, w);
+        if (hf & hbit(HB_ROT_Y + J)) rot_xy<J, 1, T, CT, W>(x, u, w);
+        if (hf & hbit(HB_ROT_X + J)) rot_xy<J, 0, T, CT, W>(x, u, w);
     }
 }
 
 // RZ adjoints on register bit J, alone or after their Z inner product
-template <int J, int RB, int T, typename CT>
-__device__ __forceinline__ void diag_handlers(Regs<CT, T> &x, uint64_t hf, CT u, CT w, double2 *red, int slot,
-                                              int tid) {
+template <int J, int RB, int T, typename CT, int W>
+__device__ __forceinline__ void diag_handlers(Regs<CT, T, W> &x, uint64_t hf, CT u, CT w, double2 *sink, double2 *red, int slot,
+                                              int fa, int tid) {
     if constexpr (J < RB) {
         if (hf & hbit(HB_PRODDIAG_REG + J)) {
-            double pr, pi;
-            prod_z_reg<J, T, CT>(x, pr, pi);
-            diag_reg<J, T, CT>(x, u, w);
-            row_store(red, slot, tid, pr, pi);
+            QNG_PRODS((prodw_z_reg<J, T, CT, W>));
+            diag_reg<J, T, CT, W>(x, u, w);
+            QNG_STORE_PRODS();
         }
-        if (hf & hbit(HB_DIAG_REG + J)) diag_reg<J, T, CT>(x, u, w);
+        if (hf & hbit(HB_DIAG_REG + J)) diag_reg<J, T, CT, W>(x, u, w);
     }
 }
 
-template <int J, int RB, int T, typename CT>
-__device__ __forceinline__ void cnot_uni(Regs<CT, T> &x, bool control) {
-    if constexpr (J < RB) cnot_cond<J, T, CT>(x, control);
+constexpr uint64_t prod_bits(int j) { return hbit(HB_PROD_X + j) | hbit(HB_PROD_Y + j) | hbit(HB_PRODZ_REG + j); }
+
+// Inner products on register bit J without an adjoint after them
+template <int J, int RB, int T, typename CT, int W>
+__device__ __forceinline__ void prod_handlers(const Regs<CT, T, W> &x, uint64_t hf, double2 *sink, double2 *red, int slot, int fa,
+                                              int tid) {
+    if constexpr (J < RB) {
+        if (hf & hbit(HB_PROD_X + J)) {
+            QNG_PRODS((prodw_xy<J, 0, T, CT, W>));
+            QNG_STORE_PRODS();
+        }
+        if (hf & hbit(HB_PROD_Y + J)) {
+            QNG_PRODS((prodw_xy<J, 1, T, CT, W>));
+            QNG_STORE_PRODS();
+        }
+        if (hf & hbit(HB_PRODZ_REG + J)) {
+            QNG_PRODS((prodw_z_reg<J, T, CT, W>));
+            QNG_STORE_PRODS();
+        }
+    }
+}
+
+template <int J, int RB, int T, typename CT, int W>
+__device__ __forceinline__ void cnot_uni(Regs<CT, T, W> &x, bool control) {
+    if constexpr (J < RB) cnot_cond<J, T, CT, W>(x, control);
 }
 
 // CNOT adjoints with target register bit J and a register control
-template <int J, int RB, int T, typename CT>
-__device__ __forceinline__ void cnot_reg_handlers(Regs<CT, T> &x, uint64_t hf) {
+template <int J, int RB, int T, typename CT, int W>
+__device__ __forceinline__ void cnot_reg_handlers(Regs<CT, T, W> &x, uint64_t hf) {
     if constexpr (J < RB) {
         constexpr int K0 = J == 0 ? 1 : 0, K1 = J <= 1 ? 2 : 1, K2 = J <= 2 ? 3 : 2;   // controls != J
         if constexpr (K0 < RB)
-            if (hf & hbit(HB_CNOT_REG + 3 * J + 0)) cnot_reg<J, K0, T, CT>(x);
+            if (hf & hbit(HB_CNOT_REG + 3 * J + 0)) cnot_reg<J, K0, T, CT, W>(x);
         if constexpr (K1 < RB)
-            if (hf & hbit(HB_CNOT_REG + 3 * J + 1)) cnot_reg<J, K1, T, CT>(x);
+            if (hf & hbit(HB_CNOT_REG + 3 * J + 1)) cnot_reg<J, K1, T, CT, W>(x);
         if constexpr (K2 < RB)
-            if (hf & hbit(HB_CNOT_REG + 3 * J + 2)) cnot_reg<J, K2, T, CT>(x);
+            if (hf & hbit(HB_CNOT_REG + 3 * J + 2)) cnot_reg<J, K2, T, CT, W>(x);
     }
 }
 
-template <typename R, typename CT, int RB, bool FULL>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 4 ? 1 : 3, 8))) void k_sweep_reg(const LaunchItem *__restrict__ items, int n_items,
+// Seed of phi register SB of a column block: phi_SB <- sigma lambda, sigma
+// of Pauli axis `axis` (0 X, 1 Y, 2 Z) on the local bit at `loc` (X and Y:
+// a register bit; Z: any location, qubit q for a bit of the tile base).
+template <int SB, int RB, int T, typename CT, int W>
+__device__ __forceinline__ void seed_phi(Regs<CT, T, W> &x, int axis, uint8_t loc, uint8_t q, int tid,
+                                         uint64_t base) {
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        move_in_place(x.br[SB][i], x.ar[i]);
+        move_in_place(x.bi[SB][i], x.ai[i]);
+    }
+    if (axis == 2) {
+        const uint32_t neg = loc_mask<T>(loc, q, tid, base);
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            const CT sg = sel<CT>((neg >> i) & 1u, (CT)-1, (CT)1);
+            x.br[SB][i] *= sg;
+            x.bi[SB][i] *= sg;
+        }
+        return;
+    }
+#define QNG_SEED_XY(J)                                                                                       \
+    if constexpr (J < RB) {                                                                                  \
+        if (loc == J) {                                                                                      \
+            swap_pairs<J, -1, T, CT>(x.br[SB], x.bi[SB]);                                                    \
+            if (axis == 1) {                                                                                 \
+                /* (Y v)_0 = -i v_1, (Y v)_1 = i v_0: after the swap, times -i where bit J is clear, */      \
+                /* times i where it is set */                                                                \
+                for (int i = 0; i < T; ++i) {                                                                \
+                    swap_in_place(x.br[SB][i], x.bi[SB][i]);                                                 \
+                    if (i & (1 << J)) x.br[SB][i] = -x.br[SB][i];                                            \
+                    else x.bi[SB][i] = -x.bi[SB][i];                                                         \
+                }                                                                                            \
+            }                                                                                                \
+        }                                                                                                    \
+    }
+    QNG_SEED_XY(0)
+    QNG_SEED_XY(1)
+    QNG_SEED_XY(2)
+    QNG_SEED_XY(3)
+#undef QNG_SEED_XY
+}
+
+// One register of the tile through the exchange buffer, from the mapping with
+// slots lo_old to the one with slots lo_new.
+template <int T, typename CT, typename CX>
+__device__ __forceinline__ void exchange(CT (&re)[T], CT (&im)[T], CX *xbuf, const uint32_t (&lo_old)[T],
+                                         const uint32_t (&lo_new)[T], bool active) {
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            CX v;
+            v.x = re[i];
+            v.y = im[i];
+            xbuf[lo_old[i]] = v;
+        }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            const CX v = xbuf[lo_new[i]];
+            re[i] = v.x;
+            im[i] = v.y;
+        }
+    }
+    __syncthreads();
+}
+
+template <typename R, typename CT, int T>
+__device__ __forceinline__ void load_reg(const void *g, const uint64_t (&off)[T], CT (&re)[T], CT (&im)[T]) {
+    using C = typename Amp<R>::T;
+    const C *p = (const C *)g;
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        const C v = p[off[i]];
+        re[i] = v.x;
+        im[i] = v.y;
+    }
+}
+
+template <typename R, typename CT, int T>
+__device__ __forceinline__ void store_reg(void *g, const uint64_t (&off)[T], const CT (&re)[T], const CT (&im)[T]) {
+    using C = typename Amp<R>::T;
+    C *p = (C *)g;
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        C v;
+        v.x = (R)re[i];
+        v.y = (R)im[i];
+        p[off[i]] = v;
+    }
+}
+
+// Tile sums <lambda|phi_b>_tile of phi registers B0 .. B1-1, summed over the
+// work-group (uniform control flow: contains barriers).
+template <int T, typename CT, int W, int B0, int B1>
+__device__ __forceinline__ void tile_sums(const Regs<CT, T, W> &x, double2 *sink, double2 *zs, int tid,
+                                          double (&Sr)[W], double (&Si)[W]) {
+    __syncthreads();   // earlier readers of zs are done
+#pragma unroll
+    for (int b = B0; b < B1; ++b) {
+        double sr, si;
+        prod_plain<T, CT>(x.ar, x.ai, x.br[b], x.bi[b], sr, si);
+        row_store(sink, zs, b, tid, sr, si);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = B0; b < B1; ++b) {
+        double ar = 0.0, ai = 0.0;
+        for (int w = 0; w < kRows; ++w) {
+            ar += zs[b * kRows + w].x;
+            ai += zs[b * kRows + w].y;
+        }
+        Sr[b] = ar;
+        Si[b] = ai;
+    }
+    __syncthreads();   // zs lies in the exchange buffer: read before the next exchange
+}
+
+// Occupancy target: three waves per SIMD (the 53 KB of LDS of a work-group
+// allow three per CU).  The 16-amplitude kernel with one phi register reaches
+// it by itself (158 VGPRs) and gets no bound; with two phi registers it is
+// held to 168 VGPRs, spilling a few values in the exchanges only.
+template <typename R, typename CT, int RB, bool FULL, int W>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 1 ? (RB >= 4 ? 1 : 3) : 3, 8))) void k_sweep_reg(const LaunchItem *__restrict__ items, int n_items,
                                                         const DevPass *__restrict__ passes,
                                                         const DevOp *__restrict__ ops,
                                                         const DevMap *__restrict__ maps,
                                                         const void *__restrict__ mats,
                                                         double2 *__restrict__ partials) {
     constexpr int T = 1 << RB;
-    using C = typename Amp<R>::T;
     extern __shared__ __align__(16) unsigned char smem[];
 
-    // ---- which item (one pass of one column) this work-group serves
+    // ---- which item (one pass of one column block) this work-group serves
     const uint32_t wg = blockIdx.x;
     int lo = 0, hi = n_items - 1;
     while (lo < hi) {
@@ -544,7 +814,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
     const int pass_nrest = (int)(ph0.w & 0xffu);
     const bool pass_zsum = ((ph0.w >> 8) & 0xffu) != 0;
     const int pass_slots = (int)(ph0.z & 0xffffu);
-    const uint32_t dimT = 1u << m;
     const int tbits = m - RB;
     const int tid = threadIdx.x;
     // FULL: the tile has exactly kThreads * T amplitudes, every thread holds a
@@ -553,8 +822,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
 
     using CX = typename Amp<CT>::T;
     CX *xbuf = (CX *)smem;                                // [2^m] exchange buffer
-    double2 *red = (double2 *)(xbuf + dimT);              // [kMaxSlots][kRows]
-    double2 *zs = red + kMaxSlots * kRows;                // [kRows]
+    double2 *tail = (double2 *)(smem + xbuf_bytes<CX>(m));
+    double2 *sink = tail + tid;                           // this thread's sink entry
+    double2 *red = tail + kThreads;                       // [kMaxSlots][kRows]
+    double2 *zs = (double2 *)xbuf;                        // [W][kRows], inside the exchange buffer
 
     uint64_t base = 0;
     const PassBytes pbytes = load_pass_bytes(pp);
@@ -562,9 +833,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
     for (int k = 0; k < kMaxRest; ++k)
         if (k < pass_nrest) base |= (uint64_t)((tile >> k) & 1u) << pbytes.rest(k);
 
-    C *gA = (C *)it.regA;
-    C *gB = (C *)it.regB;
-    Regs<CT, T> x;
+    void *gphi[2] = {it.regB, it.regC};
+    Regs<CT, T, W> x;
 
     // ---- load
     MapBytes cur = load_map(maps + ph1.x);
@@ -572,35 +842,24 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
         uint64_t off[T];
         global_offsets<RB, T>(pbytes, cur, tbits, tid, base, off);
         if (active) {
+            load_reg<R, CT, T>(it.regA, off, x.ar, x.ai);
 #pragma unroll
-            for (int i = 0; i < T; ++i) {
-                const C v = gA[off[i]];
-                x.ar[i] = v.x;
-                x.ai[i] = v.y;
-            }
-#pragma unroll
-            for (int i = 0; i < T; ++i) {
-                const C v = gB[off[i]];
-                x.br[i] = v.x;
-                x.bi[i] = v.y;
-            }
+            for (int b = 0; b < W; ++b) load_reg<R, CT, T>(gphi[b], off, x.br[b], x.bi[b]);
         } else {
 #pragma unroll
-            for (int i = 0; i < T; ++i) x.ar[i] = x.ai[i] = x.br[i] = x.bi[i] = (CT)0;
+            for (int i = 0; i < T; ++i) {
+                x.ar[i] = x.ai[i] = (CT)0;
+#pragma unroll
+                for (int b = 0; b < W; ++b) x.br[b][i] = x.bi[b][i] = (CT)0;
+            }
         }
     }
-    // plain tile sum <A|B>_tile for Z inner products on qubits outside the tile
-    double Sr = 0.0, Si = 0.0;
-    if (pass_zsum) {
-        double sr, si;
-        prod_plain<T, CT>(x, sr, si);
-        row_store(zs, 0, tid, sr, si);
-        __syncthreads();
-        for (int w = 0; w < kRows; ++w) {
-            Sr += zs[w].x;
-            Si += zs[w].y;
-        }
-    }
+    // plain tile sums <A|B_b>_tile for Z inner products on qubits outside the
+    // tile (a phi register seeded in this pass gets its sum at the seed)
+    double Sr[W], Si[W];
+#pragma unroll
+    for (int b = 0; b < W; ++b) Sr[b] = Si[b] = 0.0;
+    if (pass_zsum) tile_sums<T, CT, W, 0, W>(x, sink, zs, tid, Sr, Si);
 
     // ---- operations.  Each op carries a one-hot handler bit; the handlers run
     // under independent tests of that word (by group, register bit, kind),
@@ -618,16 +877,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
         const CT *mrow = mt + (size_t)(op.gate > 0 ? op.gate : 0) * 8;
         const CT u = mrow[0], w = mrow[1];
         const uint64_t hf = op.hf;
+        const int fa = (W == 1) ? 0 : op.aux;   // inner products: first active phi register
         // Handlers under independent tests of the handler word, nested by
         // group and register bit (an if / else-if chain would merge several
         // tile updates at one point, and the compiler then gives the tile a
         // second register set and copies it at every op).
         if (hf & hbits(HB_ROT_X, 16)) {
             // X/Y rotations, alone or after their inner product
-            if (hf & rot_bits(0)) rot_handlers<0, RB, T, CT>(x, hf, u, w, red, op.slot(), tid);
-            if (hf & rot_bits(1)) rot_handlers<1, RB, T, CT>(x, hf, u, w, red, op.slot(), tid);
-            if (hf & rot_bits(2)) rot_handlers<2, RB, T, CT>(x, hf, u, w, red, op.slot(), tid);
-            if (hf & rot_bits(3)) rot_handlers<3, RB, T, CT>(x, hf, u, w, red, op.slot(), tid);
+            if (hf & rot_bits(0)) rot_handlers<0, RB, T, CT, W>(x, hf, u, w, sink, red, op.slot(), fa, tid);
+            if (hf & rot_bits(1)) rot_handlers<1, RB, T, CT, W>(x, hf, u, w, sink, red, op.slot(), fa, tid);
+            if (hf & rot_bits(2)) rot_handlers<2, RB, T, CT, W>(x, hf, u, w, sink, red, op.slot(), fa, tid);
+            if (hf & rot_bits(3)) rot_handlers<3, RB, T, CT, W>(x, hf, u, w, sink, red, op.slot(), fa, tid);
         }
         if (hf & hbits(HB_DIAG_REG, 10)) {
             // RZ adjoints, alone or after their Z inner product
@@ -635,17 +895,22 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
                 // the Z bit is common to all registers of the thread
                 const bool one = (op.b0() == kLocBase) ? ((base >> op.q0()) & 1u) : ((tid >> (op.b0() & 15)) & 1);
                 if (hf & hbit(HB_PRODDIAG_UNI)) {
-                    double pr, pi;
-                    prod_plain<T, CT>(x, pr, pi);
                     const double sg = one ? -1.0 : 1.0;
-                    row_store(red, op.slot(), tid, sg * pr, sg * pi);
+                    const int slot = op.slot();
+                    QNG_PRODS((prodw_plain<T, CT, W>));
+#pragma unroll
+                    for (int b = 0; b < W; ++b) {
+                        pr[b] *= sg;
+                        pi[b] *= sg;
+                    }
+                    QNG_STORE_PRODS();
                 }
-                diag_all<T, CT>(x, one ? -u : u, one ? -w : w);
+                diag_all<T, CT, W>(x, one ? -u : u, one ? -w : w);
             }
-            if (hf & diag_bits(0)) diag_handlers<0, RB, T, CT>(x, hf, u, w, red, op.slot(), tid);
-            if (hf & diag_bits(1)) diag_handlers<1, RB, T, CT>(x, hf, u, w, red, op.slot(), tid);
-            if (hf & diag_bits(2)) diag_handlers<2, RB, T, CT>(x, hf, u, w, red, op.slot(), tid);
-            if (hf & diag_bits(3)) diag_handlers<3, RB, T, CT>(x, hf, u, w, red, op.slot(), tid);
+            if (hf & diag_bits(0)) diag_handlers<0, RB, T, CT, W>(x, hf, u, w, sink, red, op.slot(), fa, tid);
+            if (hf & diag_bits(1)) diag_handlers<1, RB, T, CT, W>(x, hf, u, w, sink, red, op.slot(), fa, tid);
+            if (hf & diag_bits(2)) diag_handlers<2, RB, T, CT, W>(x, hf, u, w, sink, red, op.slot(), fa, tid);
+            if (hf & diag_bits(3)) diag_handlers<3, RB, T, CT, W>(x, hf, u, w, sink, red, op.slot(), fa, tid);
         }
         if (hf & hbits(HB_CNOT_REG, 20)) {
             // CNOT adjoints (register target)
@@ -653,50 +918,42 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
                 // control held by the thread index or the tile base
                 const bool control = (hf & hbits(HB_CNOT_THR, 4)) ? ((tid >> (op.b1() & 15)) & 1) != 0
                                                                    : ((base >> op.q0()) & 1u) != 0;
-                if (hf & cnot_uni_bits(0)) cnot_cond<0, T, CT>(x, control);
-                if (hf & cnot_uni_bits(1)) cnot_uni<1, RB, T, CT>(x, control);
-                if (hf & cnot_uni_bits(2)) cnot_uni<2, RB, T, CT>(x, control);
-                if (hf & cnot_uni_bits(3)) cnot_uni<3, RB, T, CT>(x, control);
+                if (hf & cnot_uni_bits(0)) cnot_cond<0, T, CT, W>(x, control);
+                if (hf & cnot_uni_bits(1)) cnot_uni<1, RB, T, CT, W>(x, control);
+                if (hf & cnot_uni_bits(2)) cnot_uni<2, RB, T, CT, W>(x, control);
+                if (hf & cnot_uni_bits(3)) cnot_uni<3, RB, T, CT, W>(x, control);
             }
-            if (hf & cnot_reg_bits(0)) cnot_reg_handlers<0, RB, T, CT>(x, hf);
-            if (hf & cnot_reg_bits(1)) cnot_reg_handlers<1, RB, T, CT>(x, hf);
-            if (hf & cnot_reg_bits(2)) cnot_reg_handlers<2, RB, T, CT>(x, hf);
-            if (hf & cnot_reg_bits(3)) cnot_reg_handlers<3, RB, T, CT>(x, hf);
+            if (hf & cnot_reg_bits(0)) cnot_reg_handlers<0, RB, T, CT, W>(x, hf);
+            if (hf & cnot_reg_bits(1)) cnot_reg_handlers<1, RB, T, CT, W>(x, hf);
+            if (hf & cnot_reg_bits(2)) cnot_reg_handlers<2, RB, T, CT, W>(x, hf);
+            if (hf & cnot_reg_bits(3)) cnot_reg_handlers<3, RB, T, CT, W>(x, hf);
         }
         if (hf & hbits(HB_PROD_X, 13)) {
-            // inner products without an adjoint after them: they only read the
-            // tile, so one multi-way branch serves them (no tile update to merge)
-            double pr = 0.0, pi = 0.0;
-            switch (op.type()) {
-#define QNG_PROD_CASES(J)                                                                                    \
-            case OPC_PROD_X + J:                                                                             \
-                if constexpr (J < RB) prod_xy<J, 0, T, CT>(x, pr, pi);                                      \
-                break;                                                                                       \
-            case OPC_PROD_Y + J:                                                                             \
-                if constexpr (J < RB) prod_xy<J, 1, T, CT>(x, pr, pi);                                      \
-                break;                                                                                       \
-            case OPC_PRODZ_REG + J:                                                                          \
-                if constexpr (J < RB) prod_z_reg<J, T, CT>(x, pr, pi);                                      \
-                break;
-                QNG_PROD_CASES(0)
-                QNG_PROD_CASES(1)
-                QNG_PROD_CASES(2)
-                QNG_PROD_CASES(3)
-#undef QNG_PROD_CASES
-            default: {   // Z bit held by the thread index or the tile base
+            // inner products without an adjoint after them (independent tests
+            // like the other handlers: under one multi-way branch the compiler
+            // hoists the conversions of the whole tile above it, 128 more VGPRs)
+            const int slot = op.slot();
+            if (hf & hbits(HB_PROD_X, 12)) {
+                if (hf & prod_bits(0)) prod_handlers<0, RB, T, CT, W>(x, hf, sink, red, slot, fa, tid);
+                if (hf & prod_bits(1)) prod_handlers<1, RB, T, CT, W>(x, hf, sink, red, slot, fa, tid);
+                if (hf & prod_bits(2)) prod_handlers<2, RB, T, CT, W>(x, hf, sink, red, slot, fa, tid);
+                if (hf & prod_bits(3)) prod_handlers<3, RB, T, CT, W>(x, hf, sink, red, slot, fa, tid);
+            }
+            if (hf & hbit(HB_PRODZ_UNI)) {
+                // Z bit held by the thread index or the tile base
                 const bool one =
                     (op.b0() == kLocBase) ? ((base >> op.q0()) & 1u) : ((tid >> (op.b0() & 15)) & 1);
-                prod_plain<T, CT>(x, pr, pi);
-                if (one) {
-                    pr = -pr;
-                    pi = -pi;
+                const double sg = one ? -1.0 : 1.0;
+                QNG_PRODS((prodw_plain<T, CT, W>));
+#pragma unroll
+                for (int b = 0; b < W; ++b) {
+                    pr[b] *= sg;
+                    pi[b] *= sg;
                 }
-                break;
+                QNG_STORE_PRODS();
             }
-            }
-            row_store(red, op.slot(), tid, pr, pi);
         }
-        if (hf & (hbit(HB_XPOSE) | hbit(HB_CZ) | hbit(HB_ZSUM))) {
+        if (hf & (hbit(HB_XPOSE) | hbit(HB_CZ) | hbit(HB_ZSUM) | hbit(HB_SEED))) {
             if (hf & hbit(HB_CZ)) {
                 const uint32_t neg = loc_mask<T>(op.b0(), op.q0(), tid, base) & loc_mask<T>(op.b1(), op.q1(), tid, base);
 #pragma unroll
@@ -704,15 +961,35 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
                     const CT sg = sel<CT>((neg >> i) & 1u, (CT)-1, (CT)1);
                     x.ar[i] *= sg;
                     x.ai[i] *= sg;
-                    x.br[i] *= sg;
-                    x.bi[i] *= sg;
+#pragma unroll
+                    for (int b = 0; b < W; ++b) {
+                        x.br[b][i] *= sg;
+                        x.bi[b][i] *= sg;
+                    }
                 }
             }
             if (hf & hbit(HB_ZSUM)) {
                 if (tid == 0) {
                     const double sg = ((base >> op.q0()) & 1u) ? -1.0 : 1.0;
-                    red[op.slot() * kRows] = make_double2(sg * Sr, sg * Si);
-                    for (int k = 1; k < kRows; ++k) red[op.slot() * kRows + k] = make_double2(0.0, 0.0);
+#pragma unroll
+                    for (int b = 0; b < W; ++b) {
+                        if (W > 1 && b < fa) continue;
+                        const int sl = op.slot() + b - fa;
+                        red[sl * kRows] = make_double2(sg * Sr[b], sg * Si[b]);
+                        for (int k = 1; k < kRows; ++k) red[sl * kRows + k] = make_double2(0.0, 0.0);
+                    }
+                }
+            }
+            if constexpr (W > 1) {
+                if (hf & hbit(HB_SEED)) {
+                    // phi register op.aux (below the top one) <- sigma lambda;
+                    // <lambda|phi> = <y|sigma|y> into the op's slot
+                    static_assert(W == 2, "seeds are written for blocks of two columns");
+                    seed_phi<0, RB, T, CT, W>(x, op.w0 >> 24, op.b0(), op.q0(), tid, base);
+                    double pr, pi;
+                    prod_plain<T, CT>(x.ar, x.ai, x.br[0], x.bi[0], pr, pi);
+                    row_store(sink, red, op.slot(), tid, pr, pi);
+                    if (pass_zsum) tile_sums<T, CT, W, 0, 1>(x, sink, zs, tid, Sr, Si);
                 }
             }
             if (hf & hbit(HB_XPOSE)) {
@@ -720,44 +997,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
                 uint32_t lo_old[T], lo_new[T];
                 local_offsets<RB, T>(cur, tbits, tid, lo_old);
                 local_offsets<RB, T>(next, tbits, tid, lo_new);
-                if (active) {
+                exchange<T, CT, CX>(x.ar, x.ai, xbuf, lo_old, lo_new, active);
 #pragma unroll
-                    for (int i = 0; i < T; ++i) {
-                        CX v;
-                        v.x = x.ar[i];
-                        v.y = x.ai[i];
-                        xbuf[lo_old[i]] = v;
-                    }
-                }
-                __syncthreads();
-                if (active) {
-#pragma unroll
-                    for (int i = 0; i < T; ++i) {
-                        const CX v = xbuf[lo_new[i]];
-                        x.ar[i] = v.x;
-                        x.ai[i] = v.y;
-                    }
-                }
-                __syncthreads();
-                if (active) {
-#pragma unroll
-                    for (int i = 0; i < T; ++i) {
-                        CX v;
-                        v.x = x.br[i];
-                        v.y = x.bi[i];
-                        xbuf[lo_old[i]] = v;
-                    }
-                }
-                __syncthreads();
-                if (active) {
-#pragma unroll
-                    for (int i = 0; i < T; ++i) {
-                        const CX v = xbuf[lo_new[i]];
-                        x.br[i] = v.x;
-                        x.bi[i] = v.y;
-                    }
-                }
-                __syncthreads();
+                for (int b = 0; b < W; ++b) exchange<T, CT, CX>(x.br[b], x.bi[b], xbuf, lo_old, lo_new, active);
                 cur = next;
             }
         }
@@ -768,20 +1010,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(RB >= 
         uint64_t off[T];
         global_offsets<RB, T>(pbytes, cur, tbits, tid, base, off);
         if (active) {
+            store_reg<R, CT, T>(it.regA, off, x.ar, x.ai);
 #pragma unroll
-            for (int i = 0; i < T; ++i) {
-                C v;
-                v.x = (R)x.ar[i];
-                v.y = (R)x.ai[i];
-                gA[off[i]] = v;
-            }
-#pragma unroll
-            for (int i = 0; i < T; ++i) {
-                C v;
-                v.x = (R)x.br[i];
-                v.y = (R)x.bi[i];
-                gB[off[i]] = v;
-            }
+            for (int b = 0; b < W; ++b) store_reg<R, CT, T>(gphi[b], off, x.br[b], x.bi[b]);
         }
     }
     // ---- per-tile partial sums
@@ -836,50 +1067,60 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_tasks(const ReduceTas
 }
 
 template <typename CT> size_t smem_bytes(int m) {
-    return ((size_t)1 << m) * sizeof(typename Amp<CT>::T) + (size_t)(kMaxSlots + 1) * kRows * sizeof(double2) +
-           (size_t)kThreads * sizeof(double2);
+    return xbuf_bytes<typename Amp<CT>::T>(m) + (size_t)kLdsTailEntries * sizeof(double2);
 }
 
-template <typename R, typename CT, int RB, bool FULL>
+template <typename R, typename CT, int RB, bool FULL, int W>
 void launch_full(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes, const DevOp *ops,
                  const DevMap *maps, const CT *mats, double *partials, int m, hipStream_t st) {
     const size_t smem = smem_bytes<CT>(m);
     static size_t attr_set = 0;
     if (smem > attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_sweep_reg<R, CT, RB, FULL>,
+        (void)hipFuncSetAttribute((const void *)k_sweep_reg<R, CT, RB, FULL, W>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         (void)hipGetLastError();
         attr_set = smem;
     }
-    hipLaunchKernelGGL((k_sweep_reg<R, CT, RB, FULL>), dim3(total_tiles), dim3(kThreads), smem, st, items, n_items,
-                       passes, ops, maps, (const void *)mats, (double2 *)partials);
+    hipLaunchKernelGGL((k_sweep_reg<R, CT, RB, FULL, W>), dim3(total_tiles), dim3(kThreads), smem, st, items,
+                       n_items, passes, ops, maps, (const void *)mats, (double2 *)partials);
 }
 
 // Every pass of a launch has the launch's tile width m (one plan, or one
 // register class of a batch), so "every thread holds part of the tile" is a
-// property of the launch.
+// property of the launch.  Blocks of two columns run with full tiles of 8 or
+// 16 amplitudes per thread (registers of at least 11 qubits).
 template <typename R, typename CT, int RB>
 void launch_rb(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes, const DevOp *ops,
-               const DevMap *maps, const CT *mats, double *partials, int m, hipStream_t st) {
-    if (m - RB == 8)
-        launch_full<R, CT, RB, true>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st);
+               const DevMap *maps, const CT *mats, double *partials, int m, int width, hipStream_t st) {
+    const bool full = m - RB == 8;
+    if (width == 2) {
+        if constexpr (RB >= 3) {
+            if (full) {
+                launch_full<R, CT, RB, true, 2>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st);
+                return;
+            }
+        }
+        throw hipErrorInvalidValue;
+    }
+    if (full)
+        launch_full<R, CT, RB, true, 1>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st);
     else
-        launch_full<R, CT, RB, false>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st);
+        launch_full<R, CT, RB, false, 1>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st);
 }
 
 template <typename R, typename CT>
 void launch_ct(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes, const DevOp *ops,
-               const DevMap *maps, const CT *mats, double *partials, int m, int rb, hipStream_t st) {
+               const DevMap *maps, const CT *mats, double *partials, int m, int rb, int width, hipStream_t st) {
     switch (rb) {
-    case 1: launch_rb<R, CT, 1>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st); break;
-    case 2: launch_rb<R, CT, 2>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st); break;
-    case 3: launch_rb<R, CT, 3>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st); break;
+    case 1: launch_rb<R, CT, 1>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, width, st); break;
+    case 2: launch_rb<R, CT, 2>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, width, st); break;
+    case 3: launch_rb<R, CT, 3>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, width, st); break;
     case 4:
         // FP64 registers stop at 8 amplitudes per thread: at 16 the kernel
         // needs 178-226 VGPRs (two waves per SIMD) and measured 1.8-2.2x slower
         // per pass at n = 26
         if constexpr (sizeof(CT) == 4) {
-            launch_rb<R, CT, 4>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st);
+            launch_rb<R, CT, 4>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, width, st);
             break;
         }
         [[fallthrough]];
@@ -892,16 +1133,16 @@ void launch_ct(const LaunchItem *items, int n_items, uint32_t total_tiles, const
 template <typename R>
 void launch_sweep_pass(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
                        const DevOp *ops, const DevMap *maps, const double *mats64, const float *mats32,
-                       double *partials, int m, int rb, bool f64_registers, hipStream_t st) {
+                       double *partials, int m, int rb, bool f64_registers, int width, hipStream_t st) {
     if (n_items <= 0 || total_tiles == 0) return;
     if constexpr (sizeof(R) == 8) {
         (void)f64_registers;
-        launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, partials, m, rb, st);
+        launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, partials, m, rb, width, st);
     } else {
         if (f64_registers)
-            launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, partials, m, rb, st);
+            launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, partials, m, rb, width, st);
         else
-            launch_ct<R, float>(items, n_items, total_tiles, passes, ops, maps, mats32, partials, m, rb, st);
+            launch_ct<R, float>(items, n_items, total_tiles, passes, ops, maps, mats32, partials, m, rb, width, st);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) throw e;
@@ -917,10 +1158,10 @@ void launch_reduce_tasks(const ReduceTask *tasks, int n_tasks, const double *par
 }
 
 template void launch_sweep_pass<double>(const LaunchItem *, int, uint32_t, const DevPass *, const DevOp *,
-                                        const DevMap *, const double *, const float *, double *, int, int, bool,
+                                        const DevMap *, const double *, const float *, double *, int, int, bool, int,
                                         hipStream_t);
 template void launch_sweep_pass<float>(const LaunchItem *, int, uint32_t, const DevPass *, const DevOp *,
-                                       const DevMap *, const double *, const float *, double *, int, int, bool,
+                                       const DevMap *, const double *, const float *, double *, int, int, bool, int,
                                        hipStream_t);
 
 }  // namespace qng

@@ -1,0 +1,125 @@
+"""Blocks of two metric columns sharing one lambda sweep (QNG_OPT_BLOCK_COLUMNS
+= 2) against the FP64 CPU oracle.
+
+Column s and s - 1 are swept together: lambda is swept once, phi of column
+s - 1 is seeded inside the sweep as sigma lambda where lambda reaches y_{s-1}
+(with <lambda|phi> there giving T_{s-1}).  complex128 results must match the
+oracle as in the single-column tests (1e-10 normwise); complex64 results are
+checked against the same bound as the single-column complex64 path and
+against the single-column complex64 result.  The workloads have registers of
+11 to 16 qubits (tiles of 11 or 12 qubits, so passes mix register, thread and
+tile-base locations and Z products outside the tile), even and odd P (the
+lowest block then has one real column), RX/RY/RZ seeds, CNOT chains and CZ
+rings, input states and permuted parameters.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def qng():
+    import torch  # noqa: F401
+    import paper_2011_02991_amd as q
+    return q
+
+
+@pytest.fixture(scope="module")
+def ctx(qng):
+    c = qng.Context(0)
+    yield c
+    c.close()
+
+
+def rel_err(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max(initial=0.0) / max(np.abs(b).max(initial=0.0), 1e-300))
+
+
+def step(ctx, qng, pr, prec, block, tile=0, f64=0):
+    ctx.set_option(qng.OPT_BLOCK_COLUMNS, block)
+    ctx.set_option(qng.OPT_TILE_QUBITS, tile)
+    ctx.set_option(qng.OPT_F64_REGISTERS, f64)
+    try:
+        return ctx.step(qng.Circuit.from_problem(pr), pr.theta, pr.dt, pr.tikhonov, in_state=pr.in_state, prec=prec)
+    finally:
+        ctx.set_option(qng.OPT_BLOCK_COLUMNS, 0)
+        ctx.set_option(qng.OPT_TILE_QUBITS, 0)
+        ctx.set_option(qng.OPT_F64_REGISTERS, 0)
+
+
+def check(res, want, pr, label):
+    eG, eT = rel_err(res["G"], want["G"]), 0.0
+    eg = rel_err(res["grad"], want["grad"])
+    ed = rel_err(res["dtheta"], want["dtheta"])
+    kappa = np.linalg.cond(want["G"].real + pr.tikhonov * np.eye(pr.n_params))
+    say(f"{label}: |dG|={eG:.2e} |dgrad|={eg:.2e} |ddtheta|={ed:.2e} kappa={kappa:.1e}")
+    assert eG <= TOL and eg <= TOL, (eG, eg)
+    assert ed <= max(TOL, kappa * 1e-14), ed
+
+
+def with_state(pr, seed):
+    # a random input state: from |0..0> this circuit and Hamiltonian give
+    # E = 0 and a zero gradient (no relative error to check against)
+    pr.in_state = W.random_state(pr.n_qubits, seed)
+    return pr
+
+
+CASES = [
+    ("cfg3 n=12 L=2", lambda: W.scaled(W.config3, 12, 2, n_terms=9), 0),
+    ("cfg2 n=13 L=2", lambda: W.scaled(W.config2, 13, 2, n_terms=9), 11),
+    ("cfg5 n=14 L=2", lambda: W.scaled(W.config5, 14, 2, n_terms=9), 12),
+    ("cfg1 n=15 L=1", lambda: W.scaled(W.config1, 15, 1, n_terms=9), 11),
+    ("random n=13", lambda: with_state(W.random_circuit(13, 61, 4101, n_terms=6), 4104), 11),
+    ("random n=12 odd P", lambda: W.random_circuit(12, 45, 4102, n_terms=6, fixed_fraction=0.3), 0),
+    ("random n=16 permuted", lambda: W.permute_params(W.random_circuit(16, 40, 4103, n_terms=5), 3), 12),
+]
+
+
+@pytest.mark.parametrize("label,make,tile", CASES, ids=[c[0] for c in CASES])
+def test_blocks_complex128(ctx, qng, label, make, tile):
+    pr = make()
+    say(f"case: {label} (n={pr.n_qubits}, P={pr.n_params}, tile={tile}) c128 block=2")
+    res = step(ctx, qng, pr, "c128", 2, tile)
+    check(res, oracle.step(pr), pr, label)
+
+
+@pytest.mark.parametrize("f64", [0, 1])
+@pytest.mark.parametrize("label,make,tile", CASES[:5], ids=[c[0] for c in CASES[:5]])
+def test_blocks_complex64(ctx, qng, label, make, tile, f64):
+    pr = make()
+    say(f"case: {label} (n={pr.n_qubits}, P={pr.n_params}) c64 f64_registers={f64} block=2")
+    two = step(ctx, qng, pr, "c64", 2, 0, f64)
+    one = step(ctx, qng, pr, "c64", 1, 0, f64)
+    want = oracle.step(pr)
+    bound = 4 * pr.gates.shape[0] * 2.0 ** -24
+    for key in ("G", "grad"):
+        e2, e1 = rel_err(two[key], want[key]), rel_err(one[key], want[key])
+        say(f"  {key}: block=2 {e2:.2e}, block=1 {e1:.2e} (bound {bound:.1e})")
+        assert e2 <= bound and e1 <= bound
+        # the two schedules round differently, within the same bound
+        assert rel_err(two[key], one[key]) <= bound
+
+
+def test_blocks_full_step_cfg3_n20(ctx, qng):
+    """n=20 (8 qubits outside a 12-qubit tile), 2 layers, complex128 and complex64."""
+    pr = W.scaled(W.config3, 20, 2, n_terms=20)
+    say(f"case: cfg3 n=20 L=2 P={pr.n_params} block=2")
+    want = oracle.step(pr)
+    check(step(ctx, qng, pr, "c128", 2), want, pr, "cfg3 n=20 c128")
+    r64 = step(ctx, qng, pr, "c64", 2)
+    bound = 4 * pr.gates.shape[0] * 2.0 ** -24
+    assert rel_err(r64["G"], want["G"]) <= bound and rel_err(r64["grad"], want["grad"]) <= bound

@@ -141,6 +141,124 @@ def test_plan_sizes_of_workloads(qng):
         assert info["elements"] / info["passes"] > 20
 
 
+KIND_SEED = 3
+
+
+def replay_blocks(qng, pr, tile_qubits, prec="c128"):
+    """Replay a plan of two-column blocks: lambda starts at y_s of the top
+    column s and phi_s = sigma_s y_s; a seed row creates phi of a lower column
+    from the current lambda (sigma lambda) and gives <lambda|phi> = <y|sigma|y>
+    there; an inner product reads the phi of its destination's column, which
+    must already exist; adjoints act on lambda and every existing phi."""
+    circ = qng.Circuit.from_problem(pr)
+    rows = qng.plan_export(circ, tile_qubits, prec, block=2)
+    n, P = pr.n_qubits, pr.n_params
+    gates = pr.gates
+    rot_pos = [k for k in range(len(gates)) if gates[k, 3] >= 0]
+    rot_of_pos = {k: r for r, k in enumerate(rot_pos)}
+    neg = -pr.theta
+    letter = lambda s: LETTER[int(gates[rot_pos[s], 0])]
+    qubit = lambda s: int(gates[rot_pos[s], 1])
+    ys = []
+    psi = np.zeros(2 ** n, dtype=np.complex128)
+    psi[0] = 1
+    if pr.in_state is not None:
+        psi = pr.in_state.copy()
+    pos = 0
+    for k in rot_pos:
+        while pos < k:
+            psi = oracle.apply_gate(n, gates[pos], pr.theta, psi)
+            pos += 1
+        ys.append(psi.copy())
+    Lraw = np.zeros((P, P), dtype=np.complex128)
+    Traw = np.full(P, np.nan, dtype=np.complex128)
+    seen = np.zeros((P, P), dtype=bool)
+    blocks = {}
+    for r in rows:
+        blocks.setdefault(int(r[0]), []).append(r)
+    assert sorted(blocks) == list(range(P - 1, 0, -2))[::-1]
+    for s, ops in blocks.items():
+        lam = ys[s].copy()
+        phis = {s: oracle.apply_pauli_letter(n, qubit(s), letter(s), ys[s])}
+        Traw[s] = np.vdot(ys[s], phis[s])
+        for r in ops:
+            kind, q0, q1, g, dest, axis = (int(v) for v in r[2:8])
+            mask = int(r[8]) | (int(r[9]) << 31)
+            inside = lambda q: (mask >> q) & 1
+            if kind == KIND_SEED:
+                sb = dest - P * P
+                assert sb == s - 1 and sb not in phis and q0 == qubit(sb) and LETTER[axis] == letter(sb)
+                assert axis == 2 or inside(q0)
+                phis[sb] = oracle.apply_pauli_letter(n, q0, LETTER[axis], lam)
+                Traw[sb] = np.vdot(lam, phis[sb])
+                continue
+            if kind in (KIND_PROD, KIND_PROD_ADJ):
+                assert axis == 2 or inside(q0)
+                rr, ss = divmod(dest, P)
+                assert ss in (s - 1, s) and ss in phis and rr < ss and not seen[rr, ss]
+                seen[rr, ss] = True
+                Lraw[rr, ss] = np.vdot(lam, oracle.apply_pauli_letter(n, q0, LETTER[axis], phis[ss]))
+                if kind == KIND_PROD:
+                    continue
+                assert rot_of_pos[g] == rr and inside(q0)
+            lam = oracle.apply_gate(n, gates[g], neg, lam)
+            for k in phis:
+                phis[k] = oracle.apply_gate(n, gates[g], neg, phis[k])
+    assert seen.sum() == P * (P - 1) // 2
+    T = 0.5j * Traw[1:]
+    Lb = 0.25 * Lraw
+    L = np.triu(Lb, 1) + np.triu(Lb, 1).conj().T + 0.25 * np.eye(P)
+    T0 = 0.5j * np.vdot(ys[0], oracle.apply_pauli_letter(n, qubit(0), letter(0), ys[0]))
+    Tall = np.concatenate([[T0], T])
+    Gb = L - np.outer(Tall.conj(), Tall)
+    perm = gates[rot_pos, 3]
+    G = np.empty_like(Gb)
+    G[np.ix_(perm, perm)] = Gb
+    Tp = np.empty_like(Tall)
+    Tp[perm] = Tall
+    return G, Tp, rows
+
+
+@pytest.mark.parametrize("cfg,n,layers,tile", [
+    (W.config3, 9, 3, 6), (W.config3, 10, 4, 7), (W.config2, 9, 3, 6), (W.config5, 8, 3, 5),
+    (W.config1, 10, 3, 10), (W.config3, 11, 2, 8), (W.config3, 8, 2, 0),
+])
+def test_block_plan_replay_matches_oracle(qng, cfg, n, layers, tile):
+    pr = W.scaled(cfg, n, layers)
+    G, T, rows = replay_blocks(qng, pr, tile)
+    Gw, Tw = oracle.metric(pr)
+    np.testing.assert_allclose(G, Gw, atol=1e-13)
+    np.testing.assert_allclose(T, Tw, atol=1e-13)
+    # one seed per lower column of every block
+    assert (rows[:, 2] == KIND_SEED).sum() == (pr.n_params - 1) // 2
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_block_plan_replay_random_circuits(qng, seed):
+    pr = W.random_circuit(7, 45 + seed, seed=200 + seed, fixed_fraction=0.4)
+    if seed % 2:
+        pr.in_state = W.random_state(7, seed)
+    if seed % 3 == 0:
+        pr = W.permute_params(pr, seed)
+    G, T, _ = replay_blocks(qng, pr, 5)
+    Gw, Tw = oracle.metric(pr)
+    np.testing.assert_allclose(G, Gw, atol=1e-13)
+    np.testing.assert_allclose(T, Tw, atol=1e-13)
+
+
+def test_block_plan_shares_the_sweep(qng):
+    """Two columns per lambda sweep: about half the passes of one column per
+    sweep, every element still once."""
+    pr = W.scaled(W.config3, 16, 4)
+    circ = qng.Circuit.from_problem(pr)
+    one = qng.plan_export(circ, 12, "c64")
+    two = qng.plan_export(circ, 12, "c64", block=2)
+    passes = lambda rows: len({(int(r[0]), int(r[1])) for r in rows})
+    assert passes(two) < 0.85 * passes(one)
+    prods = lambda rows: int(np.isin(rows[:, 2], (KIND_PROD, KIND_PROD_ADJ)).sum())
+    assert prods(one) == prods(two) == pr.n_params * (pr.n_params - 1) // 2
+
+
 def replay_gradient(qng, pr, tile_qubits, prec="c128"):
     """Replay the gradient plan: lambda = H psi and phi = psi swept back from the
     last gate; dE/dtheta_r = -Im <lambda|sigma_r|phi> (2 Re <H psi|d_r psi>
