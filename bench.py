@@ -65,7 +65,8 @@ def time_steps(ctx, circ, pr, prec, steps, warmup, profile=False):
     for _ in range(steps):
         res = ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, prec=prec, want_G=True)
         for k, v in ctx.stats().items():
-            acc[k] = acc.get(k, 0) + v
+            # counters add up over the steps; settings are the last step's
+            acc[k] = v if k in ("block_columns", "tile_qubits", "target_tiles") else acc.get(k, 0) + v
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     ctx.set_option(qng.OPT_PROFILE, 0)

@@ -706,25 +706,33 @@ __device__ __forceinline__ void seed_phi(Regs<CT, T, W> &x, int axis, uint8_t lo
 #undef QNG_SEED_XY
 }
 
-// One register of the tile through the exchange buffer, from the mapping with
-// slots lo_old to the one with slots lo_new.
-template <int T, typename CT, typename CX>
-__device__ __forceinline__ void exchange(CT (&re)[T], CT (&im)[T], CX *xbuf, const uint32_t (&lo_old)[T],
-                                         const uint32_t (&lo_new)[T], bool active) {
+// One register of the tile through the exchange buffer, from mapping `from`
+// to mapping `to`.  The slots are recomputed for every register from an
+// opaque copy of the thread index: kept across the exchanges of all registers
+// they would hold 2T more VGPRs next to the tile, and spill.
+template <int RB, int T, typename CT, typename CX>
+__device__ __forceinline__ void exchange(CT (&re)[T], CT (&im)[T], CX *xbuf, const MapBytes &from,
+                                         const MapBytes &to, int tbits, int tid, bool active) {
+    int t = tid;
+    asm volatile("" : "+v"(t));
     if (active) {
+        uint32_t lo[T];
+        local_offsets<RB, T>(from, tbits, t, lo);
 #pragma unroll
         for (int i = 0; i < T; ++i) {
             CX v;
             v.x = re[i];
             v.y = im[i];
-            xbuf[lo_old[i]] = v;
+            xbuf[lo[i]] = v;
         }
     }
     __syncthreads();
     if (active) {
+        uint32_t lo[T];
+        local_offsets<RB, T>(to, tbits, t, lo);
 #pragma unroll
         for (int i = 0; i < T; ++i) {
-            const CX v = xbuf[lo_new[i]];
+            const CX v = xbuf[lo[i]];
             re[i] = v.x;
             im[i] = v.y;
         }
@@ -994,12 +1002,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 1
             }
             if (hf & hbit(HB_XPOSE)) {
                 const MapBytes next = load_map(maps + op.aux);
-                uint32_t lo_old[T], lo_new[T];
-                local_offsets<RB, T>(cur, tbits, tid, lo_old);
-                local_offsets<RB, T>(next, tbits, tid, lo_new);
-                exchange<T, CT, CX>(x.ar, x.ai, xbuf, lo_old, lo_new, active);
+                exchange<RB, T, CT, CX>(x.ar, x.ai, xbuf, cur, next, tbits, tid, active);
 #pragma unroll
-                for (int b = 0; b < W; ++b) exchange<T, CT, CX>(x.br[b], x.bi[b], xbuf, lo_old, lo_new, active);
+                for (int b = 0; b < W; ++b)
+                    exchange<RB, T, CT, CX>(x.br[b], x.bi[b], xbuf, cur, next, tbits, tid, active);
                 cur = next;
             }
         }
