@@ -86,6 +86,53 @@ __device__ __forceinline__ void row_store(double2 *sink, double2 *dst, int slot,
     *p = make_double2(a, b);
 }
 
+// The inner products pr[b], pi[b] of the W phi registers, summed over each
+// 16-lane row and stored, the active ones (b >= fa) to slot slot + b - fa, the
+// others to the sink.  The sums use halving exchanges: lanes pair up across the
+// row (DPP row_mirror: lane i with 15 - i; row_half_mirror: i with i ^ 7
+// inside each half; quad_perm: i ^ 2, then i ^ 1), and in the first steps a
+// lane keeps half of its values and sends the other half, which its partner
+// keeps, so the values to exchange halve at each step.  At the end each
+// quarter (W = 2) or half (W = 1) of the row holds one of the sums.
+template <int CTRL>
+__device__ __forceinline__ double dpp_xchg(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+constexpr int kDppRowMirror = 0x140, kDppRowHalfMirror = 0x141, kDppXor2 = 0x4E, kDppXor1 = 0xB1;
+
+template <int W>
+__device__ __forceinline__ void row_reduce_store(double2 *sink, double2 *red, int slot, int fa, int tid,
+                                                 const double (&pr)[W], const double (&pi)[W]) {
+    static_assert(W == 1 || W == 2, "one or two phi registers");
+    const int lane = tid & 15;
+    const bool h8 = lane & 8;
+    double v;
+    if constexpr (W == 1) {
+        // lanes 0-7 keep the real part, lanes 8-15 the imaginary part
+        v = (h8 ? pi[0] : pr[0]) + dpp_xchg<kDppRowMirror>(h8 ? pr[0] : pi[0]);
+    } else {
+        // lanes 0-7 keep register 0's pair, lanes 8-15 register 1's ...
+        const double a = (h8 ? pr[1] : pr[0]) + dpp_xchg<kDppRowMirror>(h8 ? pr[0] : pr[1]);
+        const double b = (h8 ? pi[1] : pi[0]) + dpp_xchg<kDppRowMirror>(h8 ? pi[0] : pi[1]);
+        // ... then the lower quarter of each half the real part
+        const bool h4 = lane & 4;
+        v = (h4 ? b : a) + dpp_xchg<kDppRowHalfMirror>(h4 ? a : b);
+    }
+    if constexpr (W == 1) v += dpp_xchg<kDppRowHalfMirror>(v);
+    v += dpp_xchg<kDppXor2>(v);
+    v += dpp_xchg<kDppXor1>(v);
+    // W = 1: lane 7 holds the real sum, lane 15 the imaginary one; W = 2: lanes
+    // 3, 7 hold register 0's, lanes 11, 15 register 1's
+    const int b = W == 1 ? 0 : lane >> 3;
+    const bool last = W == 1 ? (lane & 7) == 7 : (lane & 3) == 3;
+    const bool keep = W == 1 || b >= fa;
+    const int part = W == 1 ? lane >> 3 : (lane >> 2) & 1;
+    double *p = (last && keep) ? &red[(slot + b - fa) * kRows + (tid >> 4)].x + part : (double *)sink;
+    *p = v;
+}
+
 // The tile is kept as four arrays of T scalars per thread: real and imaginary
 // parts of lambda (A) and phi (B), indexed only by compile-time constants, so
 // every element is a register of its own.  With the one-hot handler dispatch
@@ -282,11 +329,7 @@ __device__ __forceinline__ void prodw_plain(const Regs<CT, T, W> &x, double (&pr
 #define QNG_PRODS(PRODW)                                                                                     \
     double pr[W], pi[W];                                                                                     \
     PRODW(x, pr, pi)
-#define QNG_STORE_PRODS()                                                                                    \
-    _Pragma("unroll") for (int b_ = 0; b_ < W; ++b_) {                                                       \
-        const bool keep_ = W == 1 || b_ >= fa;                                                               \
-        row_store(sink, keep_ ? red : sink - tid, keep_ ? slot + b_ - fa : 0, tid, pr[b_], pi[b_]);          \
-    }
+#define QNG_STORE_PRODS() row_reduce_store<W>(sink, red, slot, fa, tid, pr, pi)
 
 // ------------------------------------------------------- gates on registers
 
@@ -707,14 +750,16 @@ __device__ __forceinline__ void seed_phi(Regs<CT, T, W> &x, int axis, uint8_t lo
 }
 
 // One register of the tile through the exchange buffer, from mapping `from`
-// to mapping `to`.  The slots are recomputed for every register from an
-// opaque copy of the thread index: kept across the exchanges of all registers
-// they would hold 2T more VGPRs next to the tile, and spill.
-template <int RB, int T, typename CT, typename CX>
+// to mapping `to`.  With RECOMPUTE the slots are recomputed for every
+// register from an opaque copy of the thread index (the kernels with two phi
+// registers near the VGPR bound: kept across the exchanges of all three
+// registers the slots hold 2T more VGPRs next to the tile, and spill);
+// otherwise the compiler computes them once for all registers.
+template <int RB, int T, typename CT, typename CX, bool RECOMPUTE>
 __device__ __forceinline__ void exchange(CT (&re)[T], CT (&im)[T], CX *xbuf, const MapBytes &from,
                                          const MapBytes &to, int tbits, int tid, bool active) {
     int t = tid;
-    asm volatile("" : "+v"(t));
+    if constexpr (RECOMPUTE) asm volatile("" : "+v"(t));
     if (active) {
         uint32_t lo[T];
         local_offsets<RB, T>(from, tbits, t, lo);
@@ -1002,10 +1047,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 1
             }
             if (hf & hbit(HB_XPOSE)) {
                 const MapBytes next = load_map(maps + op.aux);
-                exchange<RB, T, CT, CX>(x.ar, x.ai, xbuf, cur, next, tbits, tid, active);
+                constexpr bool kRecompute = W > 1 && (RB >= 4 || sizeof(R) < sizeof(CT));
+                exchange<RB, T, CT, CX, kRecompute>(x.ar, x.ai, xbuf, cur, next, tbits, tid, active);
 #pragma unroll
                 for (int b = 0; b < W; ++b)
-                    exchange<RB, T, CT, CX>(x.br[b], x.bi[b], xbuf, cur, next, tbits, tid, active);
+                    exchange<RB, T, CT, CX, kRecompute>(x.br[b], x.bi[b], xbuf, cur, next, tbits, tid, active);
                 cur = next;
             }
         }
