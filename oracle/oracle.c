@@ -153,9 +153,11 @@ int oracle_forward(int n, int n_gates, const int32_t *gates, const double *theta
 /*
  * Derivative states d psi / d theta_p for the parameters listed in sel[0..n_sel).
  * out holds n_sel states back to back (n_sel * 2^n amplitudes).  A rolling prefix
- * state is advanced gate by gate; at the gate carrying a selected parameter, the
+ * state is advanced gate by gate; at a gate carrying a selected parameter, the
  * prefix is cloned, the derivative matrix applied and the remaining gates applied
- * to the clone.  psi_out (nullable) receives the ansatz state.
+ * to the clone.  A parameter carried by several gates gets the sum of those
+ * terms (the product rule: U depends on theta_p through each of them).
+ * psi_out (nullable) receives the ansatz state.
  * Returns 0, or -1 if a selected parameter carries no gate.
  */
 int oracle_derivative_states(int n, int n_gates, const int32_t *gates, const double *theta,
@@ -164,26 +166,34 @@ int oracle_derivative_states(int n, int n_gates, const int32_t *gates, const dou
 {
     const int64_t dim = (int64_t)1 << n;
     cplx *prefix = (cplx *)malloc((size_t)dim * sizeof(cplx));
-    if (!prefix) return -2;
+    cplx *term = (cplx *)malloc((size_t)dim * sizeof(cplx));
+    char *seen = (char *)calloc((size_t)(n_sel > 0 ? n_sel : 1), 1);
+    if (!prefix || !term || !seen) { free(prefix); free(term); free(seen); return -2; }
     or_load_input(prefix, n, in_state);
-    int found = 0;
     for (int k = 0; k < n_gates; ++k) {
         const int32_t *g = gates + 4 * k;
         if (g[3] >= 0) {
             for (int a = 0; a < n_sel; ++a) {
                 if (sel[a] != g[3]) continue;
                 cplx *d = out + (int64_t)a * dim;
-                memcpy(d, prefix, (size_t)dim * sizeof(cplx));
-                or_apply_gate(d, n, g, theta, 1);
-                for (int k2 = k + 1; k2 < n_gates; ++k2) or_apply_gate(d, n, gates + 4 * k2, theta, 0);
-                ++found;
+                cplx *t = seen[a] ? term : d;
+                memcpy(t, prefix, (size_t)dim * sizeof(cplx));
+                or_apply_gate(t, n, g, theta, 1);
+                for (int k2 = k + 1; k2 < n_gates; ++k2) or_apply_gate(t, n, gates + 4 * k2, theta, 0);
+                if (seen[a])
+                    for (int64_t x = 0; x < dim; ++x) d[x] += term[x];
+                seen[a] = 1;
             }
         }
         or_apply_gate(prefix, n, g, theta, 0);
     }
     if (psi_out) memcpy(psi_out, prefix, (size_t)dim * sizeof(cplx));
+    int missing = 0;
+    for (int a = 0; a < n_sel; ++a) missing += !seen[a];
     free(prefix);
-    return found == n_sel ? 0 : -1;
+    free(term);
+    free(seen);
+    return missing ? -1 : 0;
 }
 
 /*

@@ -314,3 +314,56 @@ def test_parameter_relabelling_permutes_outputs():
     perm = rng.permutation(pr.n_params)
     np.testing.assert_allclose(Gp[np.ix_(perm, perm)], G, atol=1e-15)
     np.testing.assert_allclose(Tp[perm], T, atol=1e-15)
+
+
+# ------------------------------------------------------- shared parameters
+
+def test_shared_parameter_derivatives_match_finite_differences():
+    """A parameter carried by several gates: d psi / d theta_a (the sum of the
+    gates' terms) against central differences of the forward state, whose
+    error is h^2/6 |psi'''| <= h^2/6 (k/2)^3 for k gates carrying the angle."""
+    pr = W.share_params(W.random_circuit(5, 40, 901, n_terms=5), 6, 902)
+    D, psi = oracle.derivative_states(pr)
+    h = 1e-5
+    for a in range(pr.n_params):
+        k = int((pr.gates[:, 3] == a).sum())
+        assert k >= 1
+        tp, tm = pr.theta.copy(), pr.theta.copy()
+        tp[a] += h
+        tm[a] -= h
+        fd = (oracle.forward(W.Problem(**{**pr.__dict__, "theta": tp}))
+              - oracle.forward(W.Problem(**{**pr.__dict__, "theta": tm}))) / (2 * h)
+        assert np.abs(D[a] - fd).max() < h * h / 6 * (k / 2) ** 3 + 1e-9
+
+
+def test_shared_rx_pair_closed_form():
+    """RX(theta) twice on one qubit, one shared angle: the state is RX(2 theta)|0>,
+    so d psi/d theta is twice the single-gate derivative at 2 theta and
+    G = 4 * 1/4 = 1, T = 2 * (i/2) <psi|X|psi> = 0 (|<X>| = 0 on RX|0>)."""
+    g = np.array([[W.RX, 0, -1, 0], [W.RX, 0, -1, 0]], dtype=np.int32)
+    pr = W.Problem("rx_pair", 1, g, np.array([0.7]), np.array([[3]], np.uint8), np.array([1.0]))
+    G, T = oracle.metric(pr)
+    np.testing.assert_allclose(G, [[1.0]], atol=1e-15)
+    np.testing.assert_allclose(T, [0.0], atol=1e-15)
+    # energy <Z> = cos(2 theta): gradient -2 sin(2 theta)
+    E, grad = oracle.energy_grad(pr)
+    np.testing.assert_allclose([E, grad[0]], [math.cos(1.4), -2 * math.sin(1.4)], atol=1e-14)
+
+
+def test_shared_parameters_contract_the_unshared_metric():
+    """Relabelling merges parameters: G' = J^T G J and grad' = J^T grad, where
+    G, grad belong to the same circuit with one parameter per gate (J maps
+    each gate's parameter to the shared one).  Checks the oracle's sum of
+    derivative terms against its one-gate-per-parameter evaluation."""
+    base = W.random_circuit(5, 36, 903, n_terms=5)
+    pr = W.share_params(base, 5, 904)
+    unshared = W.Problem(**{**base.__dict__, "theta": pr.theta[pr.gates[pr.gates[:, 3] >= 0, 3]][
+        np.argsort(base.gates[base.gates[:, 3] >= 0, 3])]})
+    J = np.zeros((base.n_params, pr.n_params))
+    J[base.gates[base.gates[:, 3] >= 0, 3], pr.gates[pr.gates[:, 3] >= 0, 3]] = 1.0
+    G, _ = oracle.metric(unshared)
+    Gs, _ = oracle.metric(pr)
+    np.testing.assert_allclose(Gs, J.T @ G @ J, atol=1e-13)
+    _, g = oracle.energy_grad(unshared)
+    _, gs = oracle.energy_grad(pr)
+    np.testing.assert_allclose(gs, J.T @ g, atol=1e-13)

@@ -212,6 +212,39 @@ def permute_params(problem: Problem, seed: int) -> Problem:
     return dataclasses.replace(problem, name=problem.name + f"_perm{seed}", gates=gates, theta=theta)
 
 
+def share_params(problem: Problem, n_shared: int, seed: int) -> Problem:
+    """Same circuit with its P parameters merged into n_shared shared ones:
+    every parameterised gate is relabelled to one of 0..n_shared-1 (each used at
+    least once), with new seeded angles uniform in [0, 2 pi)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    P = problem.n_params
+    if not 1 <= n_shared <= P:
+        raise ValueError("need 1 <= n_shared <= P")
+    labels = np.concatenate([np.arange(n_shared), rng.integers(0, n_shared, P - n_shared)])
+    rng.shuffle(labels)                 # old parameter -> shared parameter
+    gates = problem.gates.copy()
+    mask = gates[:, 3] >= 0
+    gates[mask, 3] = labels[gates[mask, 3]]
+    theta = rng.uniform(0.0, 2.0 * np.pi, n_shared)
+    return dataclasses.replace(problem, name=problem.name + f"_shared{n_shared}", gates=gates, theta=theta)
+
+
+def layer_shared(n: int, layers: int, n_terms: int, seed: int) -> Problem:
+    """Layers of RX on every qubit (one angle per layer), a CNOT chain and RZ on
+    every qubit (one angle per layer): 2 parameters per layer, each carried by
+    n gates.  Seeded angles and Pauli-sum Hamiltonian as in the other workloads."""
+    base = make_problem(f"layer_shared_n{n}_L{layers}", n, layers, (RX, RZ), "cnot_chain", n_terms, seed)
+    gates = base.gates.copy()
+    rot = np.nonzero(gates[:, 3] >= 0)[0]
+    per_layer = 2 * n
+    for k, g in enumerate(rot):
+        layer, within = divmod(k, per_layer)
+        gates[g, 3] = 2 * layer + (0 if within < n else 1)
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    theta = rng.uniform(0.0, 2.0 * np.pi, 2 * layers)
+    return dataclasses.replace(base, gates=gates, theta=theta)
+
+
 def random_state(n: int, seed: int) -> np.ndarray:
     """A normalised random complex128 input state (Gaussian amplitudes)."""
     rng = np.random.Generator(np.random.PCG64(seed))
