@@ -4,7 +4,10 @@
  * The library evaluates, for a unitary ansatz U = U_P ... U_1 with one unique
  * parameter per parameterised gate acting on an input state |in>
  * (Jones, "Efficient classical calculation of the Quantum Natural Gradient",
- * Sec. 2 problem statement):
+ * Sec. 2 problem statement) -- or with parameters shared by several gates, whose
+ * results are the contractions G' = J^T G J, T' = J^T T, grad' = J^T grad of
+ * the one-parameter-per-gate results (J: gate parameter -> shared parameter;
+ * the derivative of a shared angle is the sum over its gates):
  *
  *   - the quantum geometric tensor G_ij = L_ij - T_i^* T_j (Sec. 2, assembly
  *     equation; Sec. 1 definition), with L_ij = <d_i psi, d_j psi> and
@@ -55,7 +58,7 @@ typedef enum {
     QNG_OK = 0,
     QNG_E_INVALID_ARG = -1,     /* null pointer, bad size, unknown option/precision */
     QNG_E_BAD_CIRCUIT = -2,     /* qubit out of range, q0 == q1, unknown gate kind */
-    QNG_E_BAD_PARAMS = -3,      /* parameter indices are not a permutation of 0..P-1 */
+    QNG_E_BAD_PARAMS = -3,      /* a parameter index outside 0..n_params-1, or a parameter no rotation carries */
     QNG_E_NOT_NORMALIZED = -4,  /* | <in|in> - 1 | > 1e-12 */
     QNG_E_NONFINITE = -5,       /* NaN/Inf in theta, dt, eps, coefficients or the input state */
     QNG_E_OUT_OF_MEMORY = -6,   /* workspace above the device memory or the context's limit */
@@ -76,9 +79,10 @@ typedef enum { QNG_C128 = 0, QNG_C64 = 1 } qng_precision;
  * two qubits, param = -1.  Gates act in array order: gates[0] first. */
 typedef struct { int32_t kind, q0, q1, param; } qng_gate;
 
-/* An ansatz: n_params parameterised rotations whose param fields form a
- * permutation of 0..n_params-1 (one unique parameter per gate, Sec. 2), plus
- * any number of fixed CNOT/CZ gates. */
+/* An ansatz: parameterised rotations whose param fields lie in
+ * 0..n_params-1, each parameter carried by at least one rotation (one unique
+ * parameter per gate, Sec. 2, when they form a permutation; otherwise shared
+ * parameters, see above), plus any number of fixed CNOT/CZ gates. */
 typedef struct {
     int32_t n_qubits;
     int32_t n_gates;

@@ -147,7 +147,7 @@ struct Layout {
     size_t total = 0;
 };
 
-Layout plan_layout(int n, int P, size_t amp_bytes, int n_states, bool staging, size_t sweep_bytes) {
+Layout plan_layout(int n, int P, int NP, size_t amp_bytes, int n_states, bool staging, size_t sweep_bytes) {
     Layout L;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
@@ -162,7 +162,7 @@ Layout plan_layout(int n, int P, size_t amp_bytes, int n_states, bool staging, s
     L.eraw = take(16);
     L.gout = take((size_t)P * P * 16 + 16);
     L.tout = take((size_t)P * 16 + 16);
-    L.param_of = take((size_t)P * 4 + 4);
+    L.param_of = take(((size_t)2 * P + NP + 1) * 4 + 4);
     L.sweep_bytes = sweep_bytes;
     L.sweep = take(sweep_bytes + 16);
     L.total = off;
@@ -201,9 +201,15 @@ struct Problem {
     Circuit circ;
     std::vector<Mat2> fwd, adj;       // per gate position (rotations only)
     std::vector<int> param_of;        // rotation (list order) -> parameter index
+    // device image of the parameter map: param_of [P], then the rotations of
+    // each parameter as off [NP + 1] and rot [P] (rot[off[a] .. off[a+1]) carry a)
+    std::vector<int> param_map;
     std::vector<PauliTerm> ham;
     bool has_ham = false;
 };
+
+// ints of a Problem's parameter map image
+inline size_t param_map_ints(const Circuit &c) { return (size_t)2 * c.P + c.NP + 1; }
 
 Problem make_problem(const qng_circuit *c, const double *theta, const qng_pauli_sum *h) {
     Problem p;
@@ -215,6 +221,15 @@ Problem make_problem(const qng_circuit *c, const double *theta, const qng_pauli_
         p.adj[r.pos] = adjoint(p.fwd[r.pos]);
         p.param_of.push_back(r.param);
     }
+    const int P = p.circ.P, NP = p.circ.NP;
+    p.param_map = p.param_of;
+    std::vector<int> count(NP + 1, 0);
+    for (int r = 0; r < P; ++r) ++count[p.param_of[r] + 1];
+    for (int a = 0; a < NP; ++a) count[a + 1] += count[a];
+    p.param_map.insert(p.param_map.end(), count.begin(), count.end());
+    std::vector<int> rot(P), fill(count.begin(), count.end() - 1);
+    for (int r = 0; r < P; ++r) rot[fill[p.param_of[r]]++] = r;
+    p.param_map.insert(p.param_map.end(), rot.begin(), rot.end());
     if (h) {
         p.ham = compile_hamiltonian(c, h);
         p.has_ham = true;
@@ -359,6 +374,26 @@ int block_width(int opt_block, const Circuit &c, int opt_tile, int amp, bool f64
     return (want == 2 && register_bits(m, amp) >= 3 && m - register_bits(m, amp) == 8) ? 2 : 1;
 }
 
+// G and T in parameter order from the raw L and T of the rotations: with one
+// parameter per rotation, unpacked straight into gout/tout; with shared
+// parameters, unpacked in rotation order into gout/tout and contracted
+// (J^T G J, J^T T) into `spare`, which must hold NP*NP + NP complex (the raw L
+// of P*P >= that is dead by then).  G and T are set to where the results are.
+void unpack_to_params(const Problem &pb, const double *lraw, const double *traw, const int *param_map_dev,
+                      double *gout, double *tout, double *spare, double *&G, double *&T, hipStream_t st) {
+    const Circuit &c = pb.circ;
+    if (!c.shared) {
+        launch_unpack_metric(lraw, traw, param_map_dev, c.P, gout, tout, st);
+        G = gout;
+        T = tout;
+        return;
+    }
+    launch_unpack_metric(lraw, traw, nullptr, c.P, gout, tout, st);
+    G = spare;
+    T = spare + 2 * (size_t)c.NP * c.NP;
+    launch_contract_metric(gout, tout, c.P, param_map_dev + c.P, param_map_dev + c.P + c.NP + 1, c.NP, G, T, st);
+}
+
 struct CallResult {
     // device pointers into the workspace
     double *G = nullptr, *T = nullptr, *graw = nullptr, *eraw = nullptr;
@@ -393,7 +428,7 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
         gplan = ctx->sweep_cache.get_gradient(c, ctx->opt_tile, (int)amp, f64_regs);
         scratch = std::max(scratch, fused_gradient_scratch_bytes(*gplan, c.M));
     }
-    Layout L = plan_layout(n, c.P, amp, n_states, spec.in_host != nullptr, scratch);
+    Layout L = plan_layout(n, c.P, c.NP, amp, n_states, spec.in_host != nullptr, scratch);
     char *base = ensure_workspace(ctx, L.total);
     hipStream_t st = ctx->stream;
     char *sb = base + L.states;
@@ -412,7 +447,9 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
         HIPCHECK(hipMemcpyAsync(base + L.staging, spec.in_host, (size_t(1) << n) * 16, hipMemcpyHostToDevice, st));
         in_c128 = base + L.staging;
     }
-    if (c.P) HIPCHECK(hipMemcpyAsync(base + L.param_of, pb.param_of.data(), (size_t)c.P * 4, hipMemcpyHostToDevice, st));
+    if (c.P)
+        HIPCHECK(hipMemcpyAsync(base + L.param_of, pb.param_map.data(), pb.param_map.size() * 4, hipMemcpyHostToDevice,
+                                st));
     CallResult res;
     res.graw = e.graw();
     res.param_of = (const int *)(base + L.param_of);
@@ -436,10 +473,8 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
         } else {
             pos = e.metric_unfused();
         }
-        launch_unpack_metric(e.lraw(), e.traw(), (const int *)(base + L.param_of), c.P, (double *)(base + L.gout),
-                             (double *)(base + L.tout), st);
-        res.G = (double *)(base + L.gout);
-        res.T = (double *)(base + L.tout);
+        unpack_to_params(pb, e.lraw(), e.traw(), (const int *)(base + L.param_of), (double *)(base + L.gout),
+                         (double *)(base + L.tout), e.lraw(), res.G, res.T, st);
         if (spec.host_call || ctx->opt_profile) HIPCHECK(hipStreamSynchronize(st));
         ctx->stats.metric_ms = ms_since(t0);
     }
@@ -484,8 +519,10 @@ template <typename F> void dispatch(qng_precision prec, F &&f) {
     else f((double)0);
 }
 
+// d E / d theta_a = sum over the rotations r carrying a of -Im graw[r]
 void host_unpack_grad(const std::vector<double> &graw, const Problem &pb, double *grad) {
-    for (size_t r = 0; r < pb.param_of.size(); ++r) grad[pb.param_of[r]] = -graw[2 * r + 1];
+    for (int a = 0; a < pb.circ.NP; ++a) grad[a] = 0.0;
+    for (size_t r = 0; r < pb.param_of.size(); ++r) grad[pb.param_of[r]] -= graw[2 * r + 1];
 }
 
 // ------------------------------------------------------------ batched metric
@@ -510,6 +547,7 @@ struct BatchRun {
     BatchLayout L;
     char *base = nullptr;
     int64_t launches = 0;
+    std::vector<double *> G, T;                            // per member: G, T in parameter order (device)
 };
 
 template <typename R>
@@ -520,6 +558,8 @@ BatchRun batch_metric(qng_ctx *ctx, const std::vector<Problem> &pbs, const doubl
     const bool f64 = amp == 16 || ctx->opt_f64_regs;
     hipStream_t st = ctx->stream;
     BatchRun run;
+    run.G.assign(B, nullptr);
+    run.T.assign(B, nullptr);
 
     // register classes: members whose plans share the tile width
     std::map<int, std::vector<int>> by_m;
@@ -567,7 +607,7 @@ BatchRun batch_metric(qng_ctx *ctx, const std::vector<Problem> &pbs, const doubl
         L.graw.push_back(take((size_t)c.P * 16));
         L.gout.push_back(take((size_t)c.P * c.P * 16));
         L.tout.push_back(take((size_t)c.P * 16));
-        L.param_of.push_back(take((size_t)c.P * 4));
+        L.param_of.push_back(take(param_map_ints(c) * 4));
     }
     L.lam = take(vmax);
     size_t gsc = 0;
@@ -611,7 +651,7 @@ BatchRun batch_metric(qng_ctx *ctx, const std::vector<Problem> &pbs, const doubl
         }
         launch_init_state<R>(base + L.psi[b], c.n, src, st);
         if (c.P)
-            HIPCHECK(hipMemcpyAsync(base + L.param_of[b], pbs[b].param_of.data(), (size_t)c.P * 4,
+            HIPCHECK(hipMemcpyAsync(base + L.param_of[b], pbs[b].param_map.data(), pbs[b].param_map.size() * 4,
                                     hipMemcpyHostToDevice, st));
         ++ctx->stats.other_launches;
     }
@@ -715,8 +755,10 @@ BatchRun batch_metric(qng_ctx *ctx, const std::vector<Problem> &pbs, const doubl
         }
         for (size_t i = 0; i < mem.size(); ++i) {
             const Problem &pb = pbs[mem[i]];
-            launch_unpack_metric(d.lraw + 2 * S.lraw_base[i], d.traw[i], (const int *)(base + L.param_of[mem[i]]),
-                                 pb.circ.P, (double *)(base + L.gout[mem[i]]), (double *)(base + L.tout[mem[i]]), st);
+            double *lraw_i = d.lraw + 2 * S.lraw_base[i];   // P*P complex, dead after the unpack
+            unpack_to_params(pb, lraw_i, d.traw[i], (const int *)(base + L.param_of[mem[i]]),
+                             (double *)(base + L.gout[mem[i]]), (double *)(base + L.tout[mem[i]]), lraw_i,
+                             run.G[mem[i]], run.T[mem[i]], st);
             ++ctx->stats.other_launches;
         }
     }
@@ -1004,7 +1046,7 @@ qng_status qng_metric(qng_ctx *ctx, const qng_circuit *circ, const double *in_st
         check_in_state_host(circ->n_qubits, in_state);
         reset_stats(ctx);
         Problem pb = make_problem(circ, theta, nullptr);
-        const int P = pb.circ.P;
+        const int NP = pb.circ.NP;
         dispatch(prec, [&](auto tag) {
             using R = decltype(tag);
             CallSpec spec;
@@ -1012,9 +1054,9 @@ qng_status qng_metric(qng_ctx *ctx, const qng_circuit *circ, const double *in_st
             spec.in_host = in_state;
             spec.host_call = true;
             CallResult r = run<R>(ctx, pb, spec);
-            if (P) {
-                HIPCHECK(hipMemcpyAsync(G_out, r.G, (size_t)P * P * 16, hipMemcpyDeviceToHost, ctx->stream));
-                if (T_out) HIPCHECK(hipMemcpyAsync(T_out, r.T, (size_t)P * 16, hipMemcpyDeviceToHost, ctx->stream));
+            if (NP) {
+                HIPCHECK(hipMemcpyAsync(G_out, r.G, (size_t)NP * NP * 16, hipMemcpyDeviceToHost, ctx->stream));
+                if (T_out) HIPCHECK(hipMemcpyAsync(T_out, r.T, (size_t)NP * 16, hipMemcpyDeviceToHost, ctx->stream));
             }
             HIPCHECK(hipStreamSynchronize(ctx->stream));
         });
@@ -1067,8 +1109,8 @@ qng_status qng_step(qng_ctx *ctx, const qng_circuit *circ, const double *in_stat
         check_in_state_host(circ->n_qubits, in_state);
         reset_stats(ctx);
         Problem pb = make_problem(circ, theta, ham);
-        const int P = pb.circ.P;
-        std::vector<double> G(2 * (size_t)P * P + 2), graw(2 * (size_t)P + 2), e(2), grad(P + 1);
+        const int P = pb.circ.P, NP = pb.circ.NP;
+        std::vector<double> G(2 * (size_t)NP * NP + 2), graw(2 * (size_t)P + 2), e(2), grad(NP + 1);
         dispatch(prec, [&](auto tag) {
             using R = decltype(tag);
             CallSpec spec;
@@ -1078,7 +1120,7 @@ qng_status qng_step(qng_ctx *ctx, const qng_circuit *circ, const double *in_stat
             spec.host_call = true;
             CallResult r = run<R>(ctx, pb, spec);
             if (P) {
-                HIPCHECK(hipMemcpyAsync(G.data(), r.G, (size_t)P * P * 16, hipMemcpyDeviceToHost, ctx->stream));
+                HIPCHECK(hipMemcpyAsync(G.data(), r.G, (size_t)NP * NP * 16, hipMemcpyDeviceToHost, ctx->stream));
                 HIPCHECK(hipMemcpyAsync(graw.data(), r.graw, (size_t)P * 16, hipMemcpyDeviceToHost, ctx->stream));
             }
             HIPCHECK(hipMemcpyAsync(e.data(), r.eraw, 16, hipMemcpyDeviceToHost, ctx->stream));
@@ -1086,14 +1128,14 @@ qng_status qng_step(qng_ctx *ctx, const qng_circuit *circ, const double *in_stat
         });
         host_unpack_grad(graw, pb, grad.data());
         auto t0 = Clock::now();
-        std::vector<double> b(P + 1);
-        for (int i = 0; i < P; ++i) b[i] = -dt * grad[i];
-        std::vector<double> x(P + 1);
-        if (P) qng::solve_shifted(P, G.data(), tikhonov, b.data(), x.data());
+        std::vector<double> b(NP + 1);
+        for (int i = 0; i < NP; ++i) b[i] = -dt * grad[i];
+        std::vector<double> x(NP + 1);
+        if (NP) qng::solve_shifted(NP, G.data(), tikhonov, b.data(), x.data());
         ctx->stats.solve_ms = ms_since(t0);
-        if (P) std::memcpy(dtheta_out, x.data(), (size_t)P * 8);
-        if (G_out && P) std::memcpy(G_out, G.data(), (size_t)P * P * 16);
-        if (grad_out && P) std::memcpy(grad_out, grad.data(), (size_t)P * 8);
+        if (NP) std::memcpy(dtheta_out, x.data(), (size_t)NP * 8);
+        if (G_out && NP) std::memcpy(G_out, G.data(), (size_t)NP * NP * 16);
+        if (grad_out && NP) std::memcpy(grad_out, grad.data(), (size_t)NP * 8);
         if (E_out) *E_out = e[0];
     });
 }
@@ -1158,11 +1200,11 @@ qng_status qng_step_batched(qng_ctx *ctx, int32_t B, const qng_circuit *circs, c
                 e.energy_grad_unfused(batch_final_pos(pb.circ), true, nullptr);
             }
             for (int b = 0; b < B; ++b) {
-                const int P = pbs[b].circ.P;
-                G[b].assign(2 * (size_t)P * P + 2, 0.0);
+                const int P = pbs[b].circ.P, NP = pbs[b].circ.NP;
+                G[b].assign(2 * (size_t)NP * NP + 2, 0.0);
                 graw[b].assign(2 * (size_t)P + 2, 0.0);
                 if (P) {
-                    HIPCHECK(hipMemcpyAsync(G[b].data(), base + L.gout[b], (size_t)P * P * 16, hipMemcpyDeviceToHost,
+                    HIPCHECK(hipMemcpyAsync(G[b].data(), run.G[b], (size_t)NP * NP * 16, hipMemcpyDeviceToHost,
                                             ctx->stream));
                     HIPCHECK(hipMemcpyAsync(graw[b].data(), base + L.graw[b], (size_t)P * 16, hipMemcpyDeviceToHost,
                                             ctx->stream));
@@ -1174,19 +1216,19 @@ qng_status qng_step_batched(qng_ctx *ctx, int32_t B, const qng_circuit *circs, c
         });
         auto t0 = Clock::now();
         for (int b = 0; b < B; ++b) {
-            const int P = pbs[b].circ.P;
-            std::vector<double> grad(P + 1), rhs(P + 1), x(P + 1);
+            const int NP = pbs[b].circ.NP;
+            std::vector<double> grad(NP + 1), rhs(NP + 1), x(NP + 1);
             host_unpack_grad(graw[b], pbs[b], grad.data());
-            for (int i = 0; i < P; ++i) rhs[i] = -dt * grad[i];
-            if (P) {
+            for (int i = 0; i < NP; ++i) rhs[i] = -dt * grad[i];
+            if (NP) {
                 try {
-                    qng::solve_shifted(P, G[b].data(), tikhonov, rhs.data(), x.data());
+                    qng::solve_shifted(NP, G[b].data(), tikhonov, rhs.data(), x.data());
                 } catch (const Error &e) {
                     fail(e.status, "ansatz " + std::to_string(b) + ": " + e.msg);
                 }
-                std::memcpy(dtheta_out[b], x.data(), (size_t)P * 8);
-                if (G_out && G_out[b]) std::memcpy(G_out[b], G[b].data(), (size_t)P * P * 16);
-                if (grad_out && grad_out[b]) std::memcpy(grad_out[b], grad.data(), (size_t)P * 8);
+                std::memcpy(dtheta_out[b], x.data(), (size_t)NP * 8);
+                if (G_out && G_out[b]) std::memcpy(G_out[b], G[b].data(), (size_t)NP * NP * 16);
+                if (grad_out && grad_out[b]) std::memcpy(grad_out[b], grad.data(), (size_t)NP * 8);
             }
             if (E_out) E_out[b] = E[2 * b];
         }
@@ -1204,16 +1246,16 @@ qng_status qng_metric_dev(qng_ctx *ctx, const qng_circuit *circ, const void *in_
         if (circ->n_params > 0 && !G_dev) fail(QNG_E_INVALID_ARG, "G_dev is NULL");
         reset_stats(ctx);
         Problem pb = make_problem(circ, theta, nullptr);
-        const int P = pb.circ.P;
+        const int NP = pb.circ.NP;
         dispatch(prec, [&](auto tag) {
             using R = decltype(tag);
             CallSpec spec;
             spec.metric = true;
             spec.in_dev = in_state_dev;
             CallResult r = run<R>(ctx, pb, spec);
-            if (P) {
-                HIPCHECK(hipMemcpyAsync(G_dev, r.G, (size_t)P * P * 16, hipMemcpyDeviceToDevice, ctx->stream));
-                if (T_dev) HIPCHECK(hipMemcpyAsync(T_dev, r.T, (size_t)P * 16, hipMemcpyDeviceToDevice, ctx->stream));
+            if (NP) {
+                HIPCHECK(hipMemcpyAsync(G_dev, r.G, (size_t)NP * NP * 16, hipMemcpyDeviceToDevice, ctx->stream));
+                if (T_dev) HIPCHECK(hipMemcpyAsync(T_dev, r.T, (size_t)NP * 16, hipMemcpyDeviceToDevice, ctx->stream));
             }
         });
     });
@@ -1260,7 +1302,10 @@ qng_status qng_energy_grad_from_state_dev(qng_ctx *ctx, const qng_circuit *circ,
             spec.grad = true;
             spec.psi_final_dev = psi_dev;
             CallResult r = run<R>(ctx, pb, spec);
-            if (P) launch_grad_from_raw(r.graw, r.param_of, P, (double *)grad_dev, ctx->stream);
+            if (P && !pb.circ.shared) launch_grad_from_raw(r.graw, r.param_of, P, (double *)grad_dev, ctx->stream);
+            if (P && pb.circ.shared)
+                launch_grad_contract(r.graw, r.param_of + P, r.param_of + P + pb.circ.NP + 1, pb.circ.NP,
+                                     (double *)grad_dev, ctx->stream);
         });
     });
 }

@@ -32,8 +32,7 @@ void validate_circuit(const qng_circuit *c, int max_qubits) {
             if (g.q1 != -1) fail(QNG_E_BAD_CIRCUIT, where + "rotation must have q1 = -1");
             if (g.param < 0) fail(QNG_E_BAD_PARAMS, where + "rotation needs a parameter index >= 0");
             if (g.param >= c->n_params) fail(QNG_E_BAD_PARAMS, where + "parameter index >= n_params");
-            if (seen[g.param]++) fail(QNG_E_BAD_PARAMS, where + "parameter " + std::to_string(g.param) +
-                                                             " is shared (one unique parameter per gate is required)");
+            ++seen[g.param];
             ++n_rot;
             break;
         case QNG_CNOT:
@@ -47,9 +46,12 @@ void validate_circuit(const qng_circuit *c, int max_qubits) {
             fail(QNG_E_BAD_CIRCUIT, where + "unknown gate kind " + std::to_string(g.kind));
         }
     }
-    if (n_rot != c->n_params)
-        fail(QNG_E_BAD_PARAMS, "n_params=" + std::to_string(c->n_params) + " but the circuit has " +
-                                   std::to_string(n_rot) + " rotations");
+    // a parameter may be carried by several rotations (its derivative is the
+    // sum of theirs), but every parameter must be carried by one
+    for (int p = 0; p < c->n_params; ++p)
+        if (!seen[p])
+            fail(QNG_E_BAD_PARAMS, "parameter " + std::to_string(p) + " is carried by no rotation (n_params=" +
+                                       std::to_string(c->n_params) + ", " + std::to_string(n_rot) + " rotations)");
 }
 
 void validate_theta(const qng_circuit *c, const double *theta) {
@@ -74,7 +76,7 @@ Circuit compile_circuit(const qng_circuit *c) {
     Circuit k;
     k.n = c->n_qubits;
     k.M = c->n_gates;
-    k.P = c->n_params;
+    k.NP = c->n_params;
     k.gates.assign(c->gates, c->gates + c->n_gates);
     k.rot_at.assign(k.M, -1);
     for (int pos = 0; pos < k.M; ++pos) {
@@ -84,6 +86,8 @@ Circuit compile_circuit(const qng_circuit *c) {
             k.rots.push_back(Rot{g.kind == QNG_RX ? AX_X : g.kind == QNG_RY ? AX_Y : AX_Z, g.q0, g.param, pos});
         }
     }
+    k.P = (int)k.rots.size();
+    k.shared = k.P != k.NP;
     return k;
 }
 

@@ -42,7 +42,9 @@ struct Rot {
 struct Circuit {
     int n = 0;              // qubits
     int M = 0;              // gates
-    int P = 0;              // parameters = rotations
+    int P = 0;              // rotations (one recurrence column each)
+    int NP = 0;             // parameters; NP < P when rotations share parameters
+    bool shared = false;    // some parameter is carried by several rotations
     std::vector<qng_gate> gates;
     std::vector<int> rot_at;   // gate position -> rotation index (list order) or -1
     std::vector<Rot> rots;     // rotations in list order

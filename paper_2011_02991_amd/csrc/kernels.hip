@@ -329,15 +329,52 @@ __global__ void k_unpack_metric(const double *Lraw, const double *Traw, const in
     else            { lr = 0.25; li = 0.0; }
     // G = L - conj(T_r) T_s
     const double pr = trr * tsr + tri * tsi, pi = trr * tsi - tri * tsr;
-    const int64_t o = (int64_t)param_of[r] * P + param_of[s];
+    const int pr_ = param_of ? param_of[r] : r, ps_ = param_of ? param_of[s] : s;
+    const int64_t o = (int64_t)pr_ * P + ps_;
     G[2 * o] = lr - pr;
     G[2 * o + 1] = li - pi;
-    if (Tout && r == s) { Tout[2 * param_of[r]] = trr; Tout[2 * param_of[r] + 1] = tri; }
+    if (Tout && r == s) { Tout[2 * pr_] = trr; Tout[2 * pr_ + 1] = tri; }
 }
 
 __global__ void k_grad_from_raw(const double *graw, const int *param_of, int P, double *grad) {
     const int r = blockIdx.x * kBlock + threadIdx.x;
     if (r < P) grad[param_of[r]] = -graw[2 * r + 1];
+}
+
+// Shared parameters: G'[a][b] = sum over rotations r of a and s of b of
+// G[r][s], T'[a] = sum over r of a of T[r] (the rotations of parameter a are
+// rot[off[a] .. off[a+1]); G, T in rotation order, P rotations).
+__global__ void k_contract_metric(const double *G, const double *T, int P, const int *off, const int *rot, int NP,
+                                  double *Gp, double *Tp) {
+    const int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (idx >= (int64_t)NP * NP) return;
+    const int a = (int)(idx / NP), b = (int)(idx % NP);
+    double gr = 0.0, gi = 0.0;
+    for (int i = off[a]; i < off[a + 1]; ++i)
+        for (int j = off[b]; j < off[b + 1]; ++j) {
+            const int64_t o = (int64_t)rot[i] * P + rot[j];
+            gr += G[2 * o];
+            gi += G[2 * o + 1];
+        }
+    Gp[2 * idx] = gr;
+    Gp[2 * idx + 1] = gi;
+    if (Tp && b == 0) {
+        double tr = 0.0, ti = 0.0;
+        for (int i = off[a]; i < off[a + 1]; ++i) {
+            tr += T[2 * rot[i]];
+            ti += T[2 * rot[i] + 1];
+        }
+        Tp[2 * a] = tr;
+        Tp[2 * a + 1] = ti;
+    }
+}
+
+__global__ void k_grad_contract(const double *graw, const int *off, const int *rot, int NP, double *grad) {
+    const int a = blockIdx.x * kBlock + threadIdx.x;
+    if (a >= NP) return;
+    double g = 0.0;
+    for (int i = off[a]; i < off[a + 1]; ++i) g -= graw[2 * rot[i] + 1];
+    grad[a] = g;
 }
 
 }  // namespace
@@ -442,6 +479,22 @@ void launch_unpack_metric(const double *Lraw, const double *Traw, const int *par
     if (work == 0) return;
     hipLaunchKernelGGL(k_unpack_metric, dim3((unsigned)((work + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, Lraw,
                        Traw, param_of, P, G_out, T_out);
+    check_launch();
+}
+
+void launch_contract_metric(const double *G, const double *T, int P, const int *off, const int *rot, int NP,
+                            double *Gp, double *Tp, hipStream_t st) {
+    const int64_t work = (int64_t)NP * NP;
+    if (work == 0) return;
+    hipLaunchKernelGGL(k_contract_metric, dim3((unsigned)((work + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, G, T,
+                       P, off, rot, NP, Gp, Tp);
+    check_launch();
+}
+
+void launch_grad_contract(const double *graw, const int *off, const int *rot, int NP, double *grad, hipStream_t st) {
+    if (NP == 0) return;
+    hipLaunchKernelGGL(k_grad_contract, dim3((unsigned)((NP + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, graw, off,
+                       rot, NP, grad);
     check_launch();
 }
 

@@ -59,10 +59,18 @@ void launch_pauli_term(const void *psi, void *out, int n, uint64_t flip, uint64_
 // Device-side unpack of G = L - T^* T into parameter order (Alg. 1 unpack):
 // Lraw[r*P+s] (r<s, rotation order) holds <lam|sigma_r|phi>, Traw[s] holds <y_s|sigma_s|y_s>;
 // param_of[r] maps rotation r to its parameter index.  G_out: P*P complex, T_out: P complex (nullable).
+// param_of = NULL: rotation order.
 void launch_unpack_metric(const double *Lraw, const double *Traw, const int *param_of, int P, double *G_out,
                           double *T_out, hipStream_t st);
 
 // grad[param_of[r]] = -Im graw[r]   (d_r E = 2 Re[(i/2) <lambda|sigma_r|phi>]).
 void launch_grad_from_raw(const double *graw, const int *param_of, int P, double *grad, hipStream_t st);
+
+// Shared parameters (rotations rot[off[a] .. off[a+1]) carry parameter a):
+// Gp = J^T G J, Tp = J^T T from G (P x P, rotation order) and T (P), and
+// grad[a] = sum over those rotations of -Im graw[r].
+void launch_contract_metric(const double *G, const double *T, int P, const int *off, const int *rot, int NP,
+                            double *Gp, double *Tp, hipStream_t st);
+void launch_grad_contract(const double *graw, const int *off, const int *rot, int NP, double *grad, hipStream_t st);
 
 }  // namespace qng

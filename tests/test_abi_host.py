@@ -47,7 +47,7 @@ def test_validate_accepts_workloads(qng):
 @pytest.mark.parametrize("mutate,status", [
     (lambda g: g.__setitem__((0, 1), 99), "QNG_E_BAD_CIRCUIT"),          # qubit out of range
     (lambda g: g.__setitem__((0, 0), 7), "QNG_E_BAD_CIRCUIT"),           # unknown kind
-    (lambda g: g.__setitem__((1, 3), 0), "QNG_E_BAD_PARAMS"),            # shared parameter
+    (lambda g: g.__setitem__((1, 3), 0), "QNG_E_BAD_PARAMS"),            # parameter 1 left on no rotation
     (lambda g: g.__setitem__((0, 2), 3), "QNG_E_BAD_CIRCUIT"),           # rotation with q1 != -1
 ])
 def test_validate_rejects_bad_circuits(qng, mutate, status):
@@ -57,6 +57,15 @@ def test_validate_rejects_bad_circuits(qng, mutate, status):
     with pytest.raises(qng.QNGError) as e:
         qng.validate(qng.Circuit(4, g, pr.n_params, pr.pauli, pr.coeff), pr.theta)
     assert e.value.name == status
+
+
+def test_validate_accepts_shared_parameters(qng):
+    """Several rotations may carry one parameter (n_params < rotations)."""
+    pr = W.layer_shared(5, 3, 6, 11)
+    assert pr.n_params == 6 and int((pr.gates[:, 3] >= 0).sum()) == 30
+    qng.validate(_circ(qng, pr), pr.theta)
+    pr2 = W.share_params(W.random_circuit(6, 30, 12), 4, 13)
+    qng.validate(_circ(qng, pr2), pr2.theta)
 
 
 def test_validate_two_qubit_gate_same_qubit(qng):
