@@ -113,8 +113,11 @@ typedef enum {
     QNG_OPT_AUTOTUNE = 7,        /* qng_step_batched: 1 = time candidate tile widths and launch sizes on the
                                     first call for a batch structure and keep the fastest; 0 (default) = fixed */
     QNG_OPT_BATCH_TILES = 8,     /* qng_step_batched: work-groups per sweep launch to aim for (0 = 4096) */
-    QNG_OPT_BLOCK_COLUMNS = 9    /* fused metric: columns sharing one lambda sweep, 1 or 2 (0 = default); 2 needs
+    QNG_OPT_BLOCK_COLUMNS = 9,   /* fused metric: columns sharing one lambda sweep, 1 or 2 (0 = default); 2 needs
                                     tiles of >= 11 qubits (registers of >= 11 qubits), else 1 is used */
+    QNG_OPT_METRIC_KIND = 10     /* 0 (default): G = L - T^* T; 1: L alone, L_ij = <d_i psi, d_j psi> (the
+                                    coefficient matrix of imaginary-time evolution when psi's global phase does
+                                    not depend on theta); T is still returned.  Metric and step entry points. */
 } qng_option;
 
 /* Counters of the last metric/energy/step call on a context. */
@@ -168,6 +171,16 @@ qng_status qng_set_stream(qng_ctx *ctx, void *hip_stream);
 qng_status qng_set_mem_limit(qng_ctx *ctx, size_t bytes);
 qng_status qng_set_option(qng_ctx *ctx, int option, int value);
 qng_status qng_get_stats(const qng_ctx *ctx, qng_stats *out);
+/* Block-diagonal approximation of the metric (a cheaper variant: only the
+ * entries between parameters of one block are formed).  block_of_param[a] is
+ * the block id of parameter a (any int32 values; equal ids = one block).  The
+ * metric and step entry points then return G (or L) with zeros between
+ * different blocks and T in full; each column's sweep stops at the lowest
+ * rotation of its block (no work for the entries left out).  The setting
+ * applies to circuits with exactly n_params parameters (others fail with
+ * QNG_E_INVALID_ARG) until n_params = 0 clears it; qng_step_batched rejects it.
+ * The array is copied. */
+qng_status qng_set_metric_blocks(qng_ctx *ctx, int32_t n_params, const int32_t *block_of_param);
 /* Synchronise the context's stream. */
 qng_status qng_synchronize(qng_ctx *ctx);
 

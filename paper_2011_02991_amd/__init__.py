@@ -26,7 +26,7 @@ C128, C64 = 0, 1
 PRECISIONS = {"c128": C128, "complex128": C128, C128: C128, "c64": C64, "complex64": C64, C64: C64}
 
 OPT_FUSION, OPT_TILE_QUBITS, OPT_COLUMN_STREAMS, OPT_PROFILE, OPT_SMALL_N_KERNEL, OPT_F64_REGISTERS = 0, 1, 2, 3, 4, 5
-OPT_GRAPH, OPT_AUTOTUNE, OPT_BATCH_TILES, OPT_BLOCK_COLUMNS = 6, 7, 8, 9
+OPT_GRAPH, OPT_AUTOTUNE, OPT_BATCH_TILES, OPT_BLOCK_COLUMNS, OPT_METRIC_KIND = 6, 7, 8, 9, 10
 
 STATUS = {
     0: "QNG_OK", -1: "QNG_E_INVALID_ARG", -2: "QNG_E_BAD_CIRCUIT", -3: "QNG_E_BAD_PARAMS",
@@ -87,6 +87,7 @@ def _load():
         "qng_set_stream": [vp, vp],
         "qng_set_mem_limit": [vp, sz],
         "qng_set_option": [vp, ctypes.c_int, ctypes.c_int],
+        "qng_set_metric_blocks": [vp, i32, vp],
         "qng_get_stats": [vp, vp],
         "qng_synchronize": [vp],
         "qng_validate": [vp, vp, vp, ctypes.c_char_p, sz],
@@ -115,6 +116,7 @@ _lib = _load()
 
 # Symbols the C header declares (checked by the CPU test suite).
 EXPORTED = ("qng_create", "qng_destroy", "qng_last_error", "qng_set_stream", "qng_set_mem_limit", "qng_set_option",
+            "qng_set_metric_blocks",
             "qng_get_stats", "qng_synchronize", "qng_validate", "qng_plan", "qng_solve_shifted", "qng_metric",
             "qng_energy_grad", "qng_step", "qng_step_batched", "qng_metric_dev", "qng_energy_dev",
             "qng_energy_grad_from_state_dev", "qng_apply_circuit_dev", "qng_plan_export")
@@ -248,6 +250,14 @@ class Context:
 
     def set_option(self, option: int, value: int):
         self._c(_lib.qng_set_option(self._h, option, int(value)))
+
+    def set_metric_blocks(self, block_of_param=None):
+        """Block-diagonal metric: block id per parameter (None clears it)."""
+        if block_of_param is None:
+            self._c(_lib.qng_set_metric_blocks(self._h, 0, None))
+            return
+        b = np.ascontiguousarray(block_of_param, dtype=np.int32)
+        self._c(_lib.qng_set_metric_blocks(self._h, int(b.shape[0]), _ptr(b)))
 
     def set_stream(self, stream: Optional[int]):
         self._c(_lib.qng_set_stream(self._h, stream))

@@ -64,7 +64,8 @@ struct qng_ctx {
     bool own_stream = false;
     size_t mem_limit = 0;
     int opt_fusion = 1, opt_tile = 0, opt_streams = 0, opt_profile = 0, opt_small = 1, opt_f64_regs = 0;
-    int opt_graph = 1, opt_autotune = 0, opt_batch_tiles = 0, opt_block = 0;
+    int opt_graph = 1, opt_autotune = 0, opt_batch_tiles = 0, opt_block = 0, opt_metric_kind = 0;
+    std::vector<int> metric_blocks;   // block id per parameter (block-diagonal metric); empty = full
     std::string last_error;
     qng_stats stats{};
     void *ws = nullptr;
@@ -147,7 +148,8 @@ struct Layout {
     size_t total = 0;
 };
 
-Layout plan_layout(int n, int P, int NP, size_t amp_bytes, int n_states, bool staging, size_t sweep_bytes) {
+Layout plan_layout(int n, int P, size_t param_map_ints, size_t amp_bytes, int n_states, bool staging,
+                   size_t sweep_bytes) {
     Layout L;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
@@ -162,7 +164,7 @@ Layout plan_layout(int n, int P, int NP, size_t amp_bytes, int n_states, bool st
     L.eraw = take(16);
     L.gout = take((size_t)P * P * 16 + 16);
     L.tout = take((size_t)P * 16 + 16);
-    L.param_of = take(((size_t)2 * P + NP + 1) * 4 + 4);
+    L.param_of = take(param_map_ints * 4 + 4);
     L.sweep_bytes = sweep_bytes;
     L.sweep = take(sweep_bytes + 16);
     L.total = off;
@@ -202,14 +204,17 @@ struct Problem {
     std::vector<Mat2> fwd, adj;       // per gate position (rotations only)
     std::vector<int> param_of;        // rotation (list order) -> parameter index
     // device image of the parameter map: param_of [P], then the rotations of
-    // each parameter as off [NP + 1] and rot [P] (rot[off[a] .. off[a+1]) carry a)
+    // each parameter as off [NP + 1] and rot [P] (rot[off[a] .. off[a+1]) carry
+    // a), then the block of each rotation [P] (block-diagonal metric)
     std::vector<int> param_map;
     std::vector<PauliTerm> ham;
     bool has_ham = false;
+    std::vector<int> rot_block;       // block id per rotation; empty = full metric
+    bool l_only = false;              // metric without the conj(T_i) T_j term
 };
 
 // ints of a Problem's parameter map image
-inline size_t param_map_ints(const Circuit &c) { return (size_t)2 * c.P + c.NP + 1; }
+inline size_t param_map_ints(const Circuit &c) { return (size_t)3 * c.P + c.NP + 1; }
 
 Problem make_problem(const qng_circuit *c, const double *theta, const qng_pauli_sum *h) {
     Problem p;
@@ -230,11 +235,28 @@ Problem make_problem(const qng_circuit *c, const double *theta, const qng_pauli_
     std::vector<int> rot(P), fill(count.begin(), count.end() - 1);
     for (int r = 0; r < P; ++r) rot[fill[p.param_of[r]]++] = r;
     p.param_map.insert(p.param_map.end(), rot.begin(), rot.end());
+    p.param_map.resize(param_map_ints(p.circ), 0);   // rotation blocks: set by apply_metric_settings
     if (h) {
         p.ham = compile_hamiltonian(c, h);
         p.has_ham = true;
     }
     return p;
+}
+
+// The context's metric settings for a problem: block-diagonal blocks (when the
+// circuit has the number of parameters they were given for) and the L-only
+// form.
+void apply_metric_settings(const qng_ctx *ctx, Problem &p) {
+    const Circuit &c = p.circ;
+    p.l_only = ctx->opt_metric_kind == 1;
+    if (!ctx->metric_blocks.empty()) {
+        if ((int)ctx->metric_blocks.size() != c.NP)
+            fail(QNG_E_INVALID_ARG, "metric blocks were set for " + std::to_string(ctx->metric_blocks.size()) +
+                                        " parameters, the circuit has " + std::to_string(c.NP));
+        p.rot_block.resize(c.P);
+        for (int r = 0; r < c.P; ++r) p.rot_block[r] = ctx->metric_blocks[p.param_of[r]];
+        std::copy(p.rot_block.begin(), p.rot_block.end(), p.param_map.begin() + 2 * c.P + c.NP + 1);
+    }
 }
 
 template <typename R> struct Engine {
@@ -296,14 +318,25 @@ template <typename R> struct Engine {
             prod(psi, psi, rs.qubit, rs.axis, traw() + 2 * s);              // <y_s|sigma_s|y_s>
             if (s == 0) continue;
             ++ctx->stats.other_launches;
+            // block-diagonal metric: the column stops at the lowest rotation of its block
+            int lo = 0;
+            if (!pb.rot_block.empty()) {
+                lo = -1;
+                for (int r = s - 1; r >= 0; --r)
+                    if (pb.rot_block[r] == pb.rot_block[s]) lo = r;
+                if (lo < 0) continue;
+            }
+            const int plo = lo ? c.rots[lo].pos : p0;
             launch_seed<R>(psi, lam, phi, n, rs.qubit, rs.axis, st);
-            for (int k = rs.pos - 1; k >= p0; --k) {
+            for (int k = rs.pos - 1; k >= plo; --k) {
                 const int r = c.rot_at[k];
                 if (r >= 0) {
                     const Rot &rr = c.rots[r];
-                    prod(lam, phi, rr.qubit, rr.axis, lraw() + 2 * ((size_t)r * c.P + s));
-                    ++ctx->stats.elements;
-                    if (k > p0) apply(k, true, lam, phi);
+                    if (pb.rot_block.empty() || pb.rot_block[r] == pb.rot_block[s]) {
+                        prod(lam, phi, rr.qubit, rr.axis, lraw() + 2 * ((size_t)r * c.P + s));
+                        ++ctx->stats.elements;
+                    }
+                    if (k > plo) apply(k, true, lam, phi);
                 } else {
                     apply(k, true, lam, phi);
                 }
@@ -382,13 +415,14 @@ int block_width(int opt_block, const Circuit &c, int opt_tile, int amp, bool f64
 void unpack_to_params(const Problem &pb, const double *lraw, const double *traw, const int *param_map_dev,
                       double *gout, double *tout, double *spare, double *&G, double *&T, hipStream_t st) {
     const Circuit &c = pb.circ;
+    const int *rot_block = pb.rot_block.empty() ? nullptr : param_map_dev + 2 * c.P + c.NP + 1;
     if (!c.shared) {
-        launch_unpack_metric(lraw, traw, param_map_dev, c.P, gout, tout, st);
+        launch_unpack_metric(lraw, traw, param_map_dev, c.P, gout, tout, rot_block, pb.l_only, st);
         G = gout;
         T = tout;
         return;
     }
-    launch_unpack_metric(lraw, traw, nullptr, c.P, gout, tout, st);
+    launch_unpack_metric(lraw, traw, nullptr, c.P, gout, tout, rot_block, pb.l_only, st);
     G = spare;
     T = spare + 2 * (size_t)c.NP * c.NP;
     launch_contract_metric(gout, tout, c.P, param_map_dev + c.P, param_map_dev + c.P + c.NP + 1, c.NP, G, T, st);
@@ -413,8 +447,10 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
     int n_states = 4;
     if (fused) {
         const bool f64_regs = amp == 16 || ctx->opt_f64_regs;
-        const int width = block_width(ctx->opt_block, c, ctx->opt_tile, (int)amp, f64_regs);
-        plan = &ctx->sweep_cache.get(c, ctx->opt_tile, (int)amp, ctx->opt_small, f64_regs, width);
+        const bool blocked = !pb.rot_block.empty();
+        const int width = blocked ? 1 : block_width(ctx->opt_block, c, ctx->opt_tile, (int)amp, f64_regs);
+        plan = &ctx->sweep_cache.get(c, ctx->opt_tile, (int)amp, ctx->opt_small, f64_regs, width,
+                                     blocked ? &pb.rot_block : nullptr);
         size_t free_b = 0, total_b = 0;
         HIPCHECK(hipMemGetInfo(&free_b, &total_b));
         fr = fused_config(*plan, ctx->opt_streams, V, free_b + ctx->ws_bytes);
@@ -428,7 +464,7 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
         gplan = ctx->sweep_cache.get_gradient(c, ctx->opt_tile, (int)amp, f64_regs);
         scratch = std::max(scratch, fused_gradient_scratch_bytes(*gplan, c.M));
     }
-    Layout L = plan_layout(n, c.P, c.NP, amp, n_states, spec.in_host != nullptr, scratch);
+    Layout L = plan_layout(n, c.P, param_map_ints(c), amp, n_states, spec.in_host != nullptr, scratch);
     char *base = ensure_workspace(ctx, L.total);
     hipStream_t st = ctx->stream;
     char *sb = base + L.states;
@@ -916,8 +952,21 @@ qng_status qng_set_option(qng_ctx *ctx, int option, int value) {
             if (value < 0 || value > kMaxBlockWidth) fail(QNG_E_INVALID_ARG, "block columns outside [0, 2]");
             ctx->opt_block = value;
             break;
+        case QNG_OPT_METRIC_KIND:
+            if (value < 0 || value > 1) fail(QNG_E_INVALID_ARG, "metric kind must be 0 (G) or 1 (L)");
+            ctx->opt_metric_kind = value;
+            break;
         default: fail(QNG_E_INVALID_ARG, "unknown option " + std::to_string(option));
         }
+    });
+}
+
+qng_status qng_set_metric_blocks(qng_ctx *ctx, int32_t n_params, const int32_t *block_of_param) {
+    return guarded(ctx, [&] {
+        if (!ctx) fail(QNG_E_INVALID_ARG, "context is NULL");
+        if (n_params < 0) fail(QNG_E_INVALID_ARG, "n_params < 0");
+        if (n_params > 0 && !block_of_param) fail(QNG_E_INVALID_ARG, "block_of_param is NULL");
+        ctx->metric_blocks.assign(block_of_param, block_of_param + (n_params > 0 ? n_params : 0));
     });
 }
 
@@ -1046,6 +1095,7 @@ qng_status qng_metric(qng_ctx *ctx, const qng_circuit *circ, const double *in_st
         check_in_state_host(circ->n_qubits, in_state);
         reset_stats(ctx);
         Problem pb = make_problem(circ, theta, nullptr);
+        apply_metric_settings(ctx, pb);
         const int NP = pb.circ.NP;
         dispatch(prec, [&](auto tag) {
             using R = decltype(tag);
@@ -1109,6 +1159,7 @@ qng_status qng_step(qng_ctx *ctx, const qng_circuit *circ, const double *in_stat
         check_in_state_host(circ->n_qubits, in_state);
         reset_stats(ctx);
         Problem pb = make_problem(circ, theta, ham);
+        apply_metric_settings(ctx, pb);
         const int P = pb.circ.P, NP = pb.circ.NP;
         std::vector<double> G(2 * (size_t)NP * NP + 2), graw(2 * (size_t)P + 2), e(2), grad(NP + 1);
         dispatch(prec, [&](auto tag) {
@@ -1167,7 +1218,12 @@ qng_status qng_step_batched(qng_ctx *ctx, int32_t B, const qng_circuit *circs, c
         if (B == 0) return;
         std::vector<Problem> pbs;
         pbs.reserve(B);
-        for (int b = 0; b < B; ++b) pbs.push_back(make_problem(&circs[b], thetas[b], &hams[b]));
+        if (!ctx->metric_blocks.empty())
+            fail(QNG_E_INVALID_ARG, "the block-diagonal metric is not available in qng_step_batched");
+        for (int b = 0; b < B; ++b) {
+            pbs.push_back(make_problem(&circs[b], thetas[b], &hams[b]));
+            apply_metric_settings(ctx, pbs.back());
+        }
         std::vector<std::vector<double>> G(B), graw(B);
         std::vector<double> E(2 * (size_t)B);
         dispatch(prec, [&](auto tag) {
@@ -1246,6 +1302,7 @@ qng_status qng_metric_dev(qng_ctx *ctx, const qng_circuit *circ, const void *in_
         if (circ->n_params > 0 && !G_dev) fail(QNG_E_INVALID_ARG, "G_dev is NULL");
         reset_stats(ctx);
         Problem pb = make_problem(circ, theta, nullptr);
+        apply_metric_settings(ctx, pb);
         const int NP = pb.circ.NP;
         dispatch(prec, [&](auto tag) {
             using R = decltype(tag);

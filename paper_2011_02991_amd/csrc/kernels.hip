@@ -316,7 +316,7 @@ __global__ void k_pauli_term(const typename Cplx<R>::T *psi, typename Cplx<R>::T
 // ------------------------------------------------------------------ unpack
 
 __global__ void k_unpack_metric(const double *Lraw, const double *Traw, const int *param_of, int P, double *G,
-                                double *Tout) {
+                                double *Tout, const int *rot_block, int l_only) {
     const int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     if (idx >= (int64_t)P * P) return;
     const int r = (int)(idx / P), s = (int)(idx % P);
@@ -327,12 +327,14 @@ __global__ void k_unpack_metric(const double *Lraw, const double *Traw, const in
     if (r < s)      { lr = 0.25 * Lraw[2 * ((int64_t)r * P + s)]; li = 0.25 * Lraw[2 * ((int64_t)r * P + s) + 1]; }
     else if (r > s) { lr = 0.25 * Lraw[2 * ((int64_t)s * P + r)]; li = -0.25 * Lraw[2 * ((int64_t)s * P + r) + 1]; }
     else            { lr = 0.25; li = 0.0; }
-    // G = L - conj(T_r) T_s
-    const double pr = trr * tsr + tri * tsi, pi = trr * tsi - tri * tsr;
+    // G = L - conj(T_r) T_s (or L alone); zero between different blocks
+    double pr = trr * tsr + tri * tsi, pi = trr * tsi - tri * tsr;
+    if (l_only) pr = pi = 0.0;
     const int pr_ = param_of ? param_of[r] : r, ps_ = param_of ? param_of[s] : s;
     const int64_t o = (int64_t)pr_ * P + ps_;
-    G[2 * o] = lr - pr;
-    G[2 * o + 1] = li - pi;
+    const bool off_block = rot_block && rot_block[r] != rot_block[s];
+    G[2 * o] = off_block ? 0.0 : lr - pr;
+    G[2 * o + 1] = off_block ? 0.0 : li - pi;
     if (Tout && r == s) { Tout[2 * pr_] = trr; Tout[2 * pr_ + 1] = tri; }
 }
 
@@ -474,11 +476,11 @@ void launch_pauli_term(const void *psi, void *out, int n, uint64_t flip, uint64_
 }
 
 void launch_unpack_metric(const double *Lraw, const double *Traw, const int *param_of, int P, double *G_out,
-                          double *T_out, hipStream_t st) {
+                          double *T_out, const int *rot_block, bool l_only, hipStream_t st) {
     const int64_t work = (int64_t)P * P;
     if (work == 0) return;
     hipLaunchKernelGGL(k_unpack_metric, dim3((unsigned)((work + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, Lraw,
-                       Traw, param_of, P, G_out, T_out);
+                       Traw, param_of, P, G_out, T_out, rot_block, l_only ? 1 : 0);
     check_launch();
 }
 

@@ -59,9 +59,11 @@ void launch_pauli_term(const void *psi, void *out, int n, uint64_t flip, uint64_
 // Device-side unpack of G = L - T^* T into parameter order (Alg. 1 unpack):
 // Lraw[r*P+s] (r<s, rotation order) holds <lam|sigma_r|phi>, Traw[s] holds <y_s|sigma_s|y_s>;
 // param_of[r] maps rotation r to its parameter index.  G_out: P*P complex, T_out: P complex (nullable).
-// param_of = NULL: rotation order.
+// param_of = NULL: rotation order.  rot_block (nullable): block id per
+// rotation; entries between rotations of different blocks are set to zero
+// (block-diagonal approximation).  l_only: G = L (the conj(T_r) T_s term left out).
 void launch_unpack_metric(const double *Lraw, const double *Traw, const int *param_of, int P, double *G_out,
-                          double *T_out, hipStream_t st);
+                          double *T_out, const int *rot_block, bool l_only, hipStream_t st);
 
 // grad[param_of[r]] = -Im graw[r]   (d_r E = 2 Re[(i/2) <lambda|sigma_r|phi>]).
 void launch_grad_from_raw(const double *graw, const int *param_of, int P, double *grad, hipStream_t st);

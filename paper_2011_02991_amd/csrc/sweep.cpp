@@ -74,16 +74,28 @@ Event seed_event(const Circuit &c, int r, int b) {
 // after the adjoint of a block column's own rotation lambda is y_{s_b}, and
 // that column's phi register is seeded there.  With width 1 this is the sweep
 // of column s alone (Sec. 3, Alg. 1 inner loop).
-std::vector<Event> block_events(const Circuit &c, int s, int width) {
+//
+// rot_block (nullable, width 1 only): block id per rotation.  The column then
+// takes the inner products of the rotations of its own block only and its
+// sweep stops at the lowest of them (block-diagonal approximation of G); a
+// column alone in its block below s has no events.
+std::vector<Event> block_events(const Circuit &c, int s, int width, const std::vector<int> *rot_block) {
     std::vector<Event> ev;
-    const int p0 = c.rots[0].pos;
+    int lo = 0;
+    if (rot_block) {
+        lo = -1;
+        for (int r = s - 1; r >= 0; --r)
+            if ((*rot_block)[r] == (*rot_block)[s]) lo = r;
+        if (lo < 0) return ev;
+    }
+    const int p0 = c.rots[lo].pos;
     const int s_first = s - width + 1;     // column of phi register 0 (may be < 1: absent)
     for (int k = c.rots[s].pos - 1; k >= p0; --k) {
         const int r = c.rot_at[k];
         if (r >= 0) {
             Event e = prod_event(c, r);
             e.fa = std::max(0, r + 1 - s_first);
-            ev.push_back(e);
+            if (!rot_block || (*rot_block)[r] == (*rot_block)[s]) ev.push_back(e);
             if (k > p0) ev.push_back(unapply_event(c, k));
             if (r >= std::max(1, s_first) && r < s) ev.push_back(seed_event(c, r, r - s_first));
         } else {
@@ -551,8 +563,9 @@ void flatten(SweepPlan &plan, const Circuit &c) {
 }  // namespace
 
 SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int /*small*/, bool reg_f64,
-                           int width) {
+                           int width, const std::vector<int> *rot_block) {
     if (width < 1 || width > kMaxBlockWidth) fail(QNG_E_INVALID_ARG, "column block width must be 1 or 2");
+    if (rot_block && width != 1) fail(QNG_E_INVALID_ARG, "a block-diagonal metric sweeps one column at a time");
     SweepPlan plan;
     plan.width = width;
     plan_shape(plan, c, tile_qubits, amp_bytes, reg_f64);
@@ -562,7 +575,7 @@ SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int
     for (int s = c.P - 1; s >= 1; s -= width) tops.push_back(s);
     std::reverse(tops.begin(), tops.end());
     for (int s : tops)
-        plan.cols.push_back(plan_column(c, plan, s, block_events(c, s, width),
+        plan.cols.push_back(plan_column(c, plan, s, block_events(c, s, width, rot_block),
                                         SlotDest{c.P, s - width + 1, c.P * c.P}));
     flatten(plan, c);
     return plan;
@@ -663,13 +676,17 @@ void append_structure_key(const Circuit &c, std::vector<int32_t> &key) {
 }
 
 std::shared_ptr<const SweepPlan> SweepCache::get_shared(const Circuit &c, int tile_qubits, int amp_bytes, int small,
-                                                        bool reg_f64, int width) {
+                                                        bool reg_f64, int width, const std::vector<int> *rot_block) {
     std::vector<int32_t> key = {tile_qubits, amp_bytes, small, reg_f64 ? 1 : 0, width};
+    if (rot_block) {
+        key.push_back(-2);
+        key.insert(key.end(), rot_block->begin(), rot_block->end());
+    }
     append_structure_key(c, key);
     auto it = plans.find(key);
     if (it != plans.end()) return it->second;
     if (plans.size() >= 256) plans.clear();
-    auto p = std::make_shared<SweepPlan>(build_sweep_plan(c, tile_qubits, amp_bytes, small, reg_f64, width));
+    auto p = std::make_shared<SweepPlan>(build_sweep_plan(c, tile_qubits, amp_bytes, small, reg_f64, width, rot_block));
     plans[key] = p;
     return p;
 }

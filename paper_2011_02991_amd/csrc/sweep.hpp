@@ -206,8 +206,10 @@ int register_bits(int m, int amp_bytes);
 // reg_f64: tiles are computed in FP64 registers (always for complex128).
 // width: columns per block (1 or kMaxBlockWidth).  Destinations: element
 // (r, s) -> r * P + s; T_s of a column seeded inside the sweep -> P * P + s.
+// rot_block (nullable, width 1): block id per rotation -- only the elements
+// inside a block are planned (block-diagonal approximation).
 SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int small, bool reg_f64,
-                           int width = 1);
+                           int width = 1, const std::vector<int> *rot_block = nullptr);
 int default_tile_qubits(int n, int amp_bytes, bool reg_f64);
 
 // Plan of the energy gradient's reverse sweep (one column, s = P): registers
@@ -217,13 +219,15 @@ SweepPlan build_gradient_plan(const Circuit &c, int tile_qubits, int amp_bytes, 
 
 struct SweepCache {
     std::map<std::vector<int32_t>, std::shared_ptr<SweepPlan>> plans;
-    const SweepPlan &get(const Circuit &c, int tile_qubits, int amp_bytes, int small, bool reg_f64, int width = 1) {
-        return *get_shared(c, tile_qubits, amp_bytes, small, reg_f64, width);
+    const SweepPlan &get(const Circuit &c, int tile_qubits, int amp_bytes, int small, bool reg_f64, int width = 1,
+                         const std::vector<int> *rot_block = nullptr) {
+        return *get_shared(c, tile_qubits, amp_bytes, small, reg_f64, width, rot_block);
     }
     // The plan stays alive while the caller holds the pointer, even if the
     // cache evicts it.
     std::shared_ptr<const SweepPlan> get_shared(const Circuit &c, int tile_qubits, int amp_bytes, int small,
-                                                bool reg_f64, int width = 1);
+                                                bool reg_f64, int width = 1,
+                                                const std::vector<int> *rot_block = nullptr);
     std::shared_ptr<const SweepPlan> get_gradient(const Circuit &c, int tile_qubits, int amp_bytes, bool reg_f64);
 };
 
