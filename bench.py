@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--gate-qubits", type=int, default=26)
     ap.add_argument("--tile", type=int, default=0, help="tile qubits of the fused passes (0 = library default)")
     ap.add_argument("--f64-regs", type=int, default=0, help="complex64: compute sweep tiles in FP64 registers")
+    ap.add_argument("--variants", action="store_true",
+                    help="also time the cheaper metric variants (block-diagonal per layer, L only) on the workload")
     ap.add_argument("--block", type=int, default=0,
                     help="metric columns sharing one lambda sweep (1 or 2; 0 = library default)")
     return ap.parse_args()
@@ -164,6 +166,41 @@ def cpu_baseline(pr):
                       f"product), extrapolated to its {applies} gate applies and {inner} inner products per step"}
 
 
+def metric_variants(qng, ctx, circ, pr, prec, reps=2):
+    """Metric time (s) of the full G and of the cheaper variants on the same
+    workload: block-diagonal with one block per layer (parameters of a layer in
+    gate order) and the L-only matrix."""
+    import numpy as np
+    import torch
+    layers = max(1, int(round(pr.n_params / (2 * pr.n_qubits))))
+    blocks = np.repeat(np.arange(layers), -(-pr.n_params // layers))[:pr.n_params].astype(np.int32)
+
+    def timed():
+        ctx.metric(circ, pr.theta, prec=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.metric(circ, pr.theta, prec=prec)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    out = {"full_s": timed()}
+    ctx.set_metric_blocks(blocks)
+    try:
+        out["block_diagonal_s"] = timed()
+        out["block_diagonal_elements"] = ctx.stats()["elements"]
+    finally:
+        ctx.set_metric_blocks(None)
+    ctx.set_option(qng.OPT_METRIC_KIND, 1)
+    try:
+        out["l_only_s"] = timed()
+    finally:
+        ctx.set_option(qng.OPT_METRIC_KIND, 0)
+    out["blocks"] = f"{layers} blocks of {pr.n_params // layers} parameters (one per layer)"
+    log(f"metric variants: {out}")
+    return out
+
+
 def traffic_per_launch():
     """HBM bytes per sweep launch from the committed FETCH_SIZE/WRITE_SIZE counter
     summary, if it was taken on the current kernel source (else None)."""
@@ -214,6 +251,7 @@ def main():
     if args.gate_qubits > 0:
         gate = gate_apply_bandwidth(qng, ctx, min(args.gate_qubits, pr.n_qubits), args.prec)
         log(f"gate apply: {gate}")
+    variants = metric_variants(qng, ctx, circ, pr, args.prec) if args.variants else None
     cpu = None if args.no_cpu else cpu_baseline(pr)
     roof = None
     if st.get("sweep_launches", 0) > 0 and st.get("sweep_ms", 0) > 0:
@@ -239,6 +277,7 @@ def main():
                    "tile_qubits": args.tile or None, "f64_registers": bool(args.f64_regs),
                    "block_columns": st.get("block_columns")},
         "plain_fp64": plain, "precision_errors": precision, "gate_apply": gate, "roofline": roof, "cpu_baseline": cpu,
+        "metric_variants": variants,
         "breakdown_ms": {k: st[k] / args.steps for k in ("metric_ms", "grad_ms", "solve_ms")},
     }
     print(json.dumps(line), flush=True)

@@ -68,6 +68,7 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
     std::vector<ReduceTask> tasks;
     std::vector<Launch> launches;
     std::vector<Group> groups;
+    int64_t elements = 0;
     items.reserve(plan.dev_passes.size());
     for (int g0 = 0; g0 < ncols; g0 += B) {
         Group G;
@@ -101,6 +102,7 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
                 for (size_t k = 0; k < hp.slot_dest.size(); ++k) {
                     tasks.push_back(ReduceTask{poff + (uint64_t)k * tiles, tiles, hp.slot_dest[k]});
                     ++L.n_tasks;
+                    if (hp.slot_dest[k] < c.P * c.P) ++elements;   // (the rest: T of in-sweep seeds)
                 }
                 poff += (uint64_t)hp.slot_dest.size() * tiles;
             }
@@ -215,7 +217,7 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
             stats->sweep_flops += sweep_flops_per_amp(W) * (double)L.n_tasks * (double)((uint64_t)1 << n);
         }
     }
-    stats->elements += (int64_t)c.P * (c.P - 1) / 2;
+    stats->elements += elements;
     if (profile) {
         FCHECK(hipStreamSynchronize(st));
         double tot = 0.0;
