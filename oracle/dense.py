@@ -10,6 +10,8 @@ real sizes, which makes it a good independent check at n <= 4.
 * its derivative: (i/2) sigma R(theta) (Sec. 2, Pauli-generator form);
 * CNOT and CZ: permutation / diagonal matrices written from their action on
   basis states;
+* controlled rotations (kinds 5/6/7, control q0, target q1): |0><0| (x) I +
+  |1><1| (x) R on (control, target); derivative |1><1| (x) (i/2) sigma R;
 * G, T from the definition (Sec. 1), E = <psi|H|psi>, grad E by its
   definition as a vector of partial derivatives of <E> (Sec. 1).
 """
@@ -24,7 +26,9 @@ _PAULI = {
     2: np.array([[0, -1j], [1j, 0]], dtype=np.complex128),
     3: np.array([[1, 0], [0, -1]], dtype=np.complex128),
 }
-_KIND_TO_LETTER = {0: 1, 1: 2, 2: 3}
+_KIND_TO_LETTER = {0: 1, 1: 2, 2: 3, 5: 1, 6: 2, 7: 3}
+_P0 = np.array([[1, 0], [0, 0]], dtype=np.complex128)
+_P1 = np.array([[0, 0], [0, 1]], dtype=np.complex128)
 
 
 def embed_1q(n: int, q: int, m: np.ndarray) -> np.ndarray:
@@ -50,6 +54,9 @@ def gate_unitary(n: int, gate, theta, derivative: bool = False) -> np.ndarray:
     r = scipy.linalg.expm(0.5j * float(theta[p]) * sigma)
     if derivative:
         r = 0.5j * sigma @ r
+    if kind >= 5:   # controlled rotation: control q0, target q1
+        on = embed_1q(n, q0, _P1) @ embed_1q(n, q1, r)
+        return on if derivative else embed_1q(n, q0, _P0) + on
     return embed_1q(n, q0, r)
 
 

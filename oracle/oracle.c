@@ -32,7 +32,10 @@
  *
  * Conventions: qubit q is bit q of the amplitude index; amplitudes are C99
  * double complex, contiguous.  Gate rows are (kind, q0, q1, param) with
- * kind 0/1/2 = RX/RY/RZ on q0, 3 = CNOT (control q0, target q1), 4 = CZ.
+ * kind 0/1/2 = RX/RY/RZ on q0, 3 = CNOT (control q0, target q1), 4 = CZ,
+ * 5/6/7 = controlled RX/RY/RZ (control q0, target q1): the rotation acts on the
+ * target where the control is 1, the identity where it is 0, so its derivative
+ * is the rotation's derivative where the control is 1 and zero where it is 0.
  *
  * Loops over amplitudes may run on several OpenMP threads; every amplitude is
  * written by exactly one iteration, so the result does not depend on the
@@ -47,7 +50,8 @@
 
 typedef double complex cplx;
 
-enum { OR_KIND_RX = 0, OR_KIND_RY = 1, OR_KIND_RZ = 2, OR_KIND_CNOT = 3, OR_KIND_CZ = 4 };
+enum { OR_KIND_RX = 0, OR_KIND_RY = 1, OR_KIND_RZ = 2, OR_KIND_CNOT = 3, OR_KIND_CZ = 4,
+       OR_KIND_CRX = 5, OR_KIND_CRY = 6, OR_KIND_CRZ = 7 };
 
 /* Pauli matrix of a rotation kind, row-major [[s0, s1], [s2, s3]]. */
 static void or_pauli_of_kind(int kind, cplx s[4])
@@ -97,6 +101,25 @@ static void or_apply_1q(cplx *psi, int n, int q, const cplx m[4])
     }
 }
 
+/* (m on qubit t) where qubit c is 1; where c is 0 the amplitudes are kept, or
+ * set to zero if zero_off (the derivative of a controlled rotation). */
+static void or_apply_controlled_1q(cplx *psi, int n, int c, int t, const cplx m[4], int zero_off)
+{
+    const int64_t dim = (int64_t)1 << n, cb = (int64_t)1 << c, tb = (int64_t)1 << t;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < dim; ++i) {
+        if (i & tb) continue;
+        const int64_t j = i | tb;
+        if (!(i & cb)) {
+            if (zero_off) { psi[i] = 0; psi[j] = 0; }
+            continue;
+        }
+        const cplx a = psi[i], b = psi[j];
+        psi[i] = m[0] * a + m[1] * b;
+        psi[j] = m[2] * a + m[3] * b;
+    }
+}
+
 /* CNOT: |c t> -> |c, t xor c> */
 static void or_apply_cnot(cplx *psi, int n, int control, int target)
 {
@@ -126,10 +149,13 @@ static void or_apply_gate(cplx *psi, int n, const int32_t *g, const double *thet
     const int kind = g[0];
     if (kind == OR_KIND_CNOT) { or_apply_cnot(psi, n, g[1], g[2]); return; }
     if (kind == OR_KIND_CZ)   { or_apply_cz(psi, n, g[1], g[2]); return; }
+    const int controlled = kind >= OR_KIND_CRX;
+    const int axis = controlled ? kind - OR_KIND_CRX : kind;
     cplx m[4];
-    if (derivative) or_rotation_derivative(kind, theta[g[3]], m);
-    else            or_rotation(kind, theta[g[3]], m);
-    or_apply_1q(psi, n, g[1], m);
+    if (derivative) or_rotation_derivative(axis, theta[g[3]], m);
+    else            or_rotation(axis, theta[g[3]], m);
+    if (controlled) or_apply_controlled_1q(psi, n, g[1], g[2], m, derivative);
+    else            or_apply_1q(psi, n, g[1], m);
 }
 
 static void or_load_input(cplx *psi, int n, const cplx *in_state)

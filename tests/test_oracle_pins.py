@@ -367,3 +367,118 @@ def test_shared_parameters_contract_the_unshared_metric():
     _, g = oracle.energy_grad(unshared)
     _, gs = oracle.energy_grad(pr)
     np.testing.assert_allclose(gs, J.T @ g, atol=1e-13)
+
+
+# ------------------------------------------------------ controlled rotations
+
+def test_controlled_rotation_on_basis_states():
+    """A controlled rotation leaves every basis state whose control bit is 0
+    untouched and rotates the target of the others (the gate of Sec. 3's
+    controlled-rotation example); its derivative vanishes where the control
+    is 0.  Checked against the plain rotation applied to a 1-qubit target."""
+    rng = np.random.default_rng(41)
+    for kind, plain in ((W.CRX, W.RX), (W.CRY, W.RY), (W.CRZ, W.RZ)):
+        th = rng.uniform(0, 2 * np.pi, size=1)
+        for deriv in (False, True):
+            r = np.stack([oracle.apply_gate(1, (plain, 0, -1, 0), th, e, derivative=deriv)
+                          for e in np.eye(2, dtype=np.complex128)], axis=1)
+            for x in range(8):
+                e = np.zeros(8, dtype=np.complex128)
+                e[x] = 1
+                got = oracle.apply_gate(3, (kind, 2, 0, 0), th, e, derivative=deriv)
+                want = np.zeros(8, dtype=np.complex128)
+                if x & 4:
+                    t = x & 1
+                    want[x & ~1] = r[0, t]
+                    want[x | 1] = r[1, t]
+                elif not deriv:
+                    want[x] = 1
+                np.testing.assert_allclose(got, want, atol=1e-15)
+                u = dense.gate_unitary(3, (kind, 2, 0, 0), th, derivative=deriv)
+                np.testing.assert_allclose(got, u[:, x], atol=1e-15)
+
+
+def test_controlled_closed_forms():
+    """Control prepared as cos(a)|0> + sin(a)|1> (p = sin^2 a), target |0>.
+    CRY(theta): psi = cos a |00> + sin a |1> RY|0>, and RY(theta)|0> is real, so
+    <Y> = 0 there: T = 0 and G = p/4.  CRZ(theta): RZ|0> is an eigenvector of
+    Z with eigenvalue 1, so <psi|d psi> = i p/2 and G = p/4 - p^2/4."""
+    for a in (0.3, math.pi / 4, 1.2):
+        p = math.sin(a) ** 2
+        ins = np.zeros(4, dtype=np.complex128)
+        ins[0], ins[1] = math.cos(a), math.sin(a)           # qubit 0 = control, qubit 1 = target
+        for kind, G_want, T_want in ((W.CRY, p / 4, 0.0), (W.CRZ, p / 4 - p * p / 4, 0.5j * p)):
+            pr = _problem(2, [[kind, 0, 1, 0]], [0.9], in_state=ins)
+            G, T = oracle.metric(pr)
+            np.testing.assert_allclose(G, [[G_want]], atol=1e-15)
+            np.testing.assert_allclose(T, [T_want], atol=1e-15)
+
+
+def test_controlled_diagonal_is_quarter_control_probability():
+    """Sec. 3: for a controlled rotation L_ii = 1/4 <psi_{i-1}| (|1><1| on the
+    control) |psi_{i-1}>, with psi_{i-1} the state just before gate i; for a
+    plain rotation L_ii = 1/4."""
+    pr = W.controlled_circuit(5, 40, 411, n_terms=4)
+    pr.in_state = W.random_state(5, 412)
+    D, psi = oracle.derivative_states(pr)
+    L = np.einsum("ix,ix->i", D.conj(), D).real
+    state = pr.in_state.copy()
+    for g in pr.gates:
+        kind, q0, _, p = (int(v) for v in g)
+        if p >= 0:
+            if kind >= W.CRX:
+                idx = np.arange(1 << pr.n_qubits)
+                prob = float(np.sum(np.abs(state[(idx >> q0) & 1 == 1]) ** 2))
+                assert abs(L[p] - prob / 4) < 1e-14
+            else:
+                assert abs(L[p] - 0.25) < 1e-14
+        state = oracle.apply_gate(pr.n_qubits, g, pr.theta, state)
+
+
+@pytest.mark.parametrize("n,ngates,seed", [(2, 12, 421), (3, 20, 422), (4, 30, 423), (5, 26, 424)])
+def test_controlled_oracle_matches_dense_brute_force(n, ngates, seed):
+    pr = W.controlled_circuit(n, ngates, seed, n_terms=6)
+    if seed % 2 == 0:
+        pr.in_state = W.random_state(n, seed + 100)
+    bf = dense.brute_force(pr)
+    st = oracle.step(pr)
+    np.testing.assert_allclose(st["psi"], bf["psi"], atol=1e-13)
+    np.testing.assert_allclose(st["G"], bf["G"], atol=1e-13)
+    np.testing.assert_allclose(st["T"], bf["T"], atol=1e-13)
+    assert abs(st["E"] - bf["E"]) < 1e-12
+    np.testing.assert_allclose(st["grad"], bf["grad"], atol=1e-12)
+
+
+def test_controlled_derivatives_match_finite_differences():
+    """d psi / d theta of controlled rotations (alone and with a shared angle)
+    against central differences of the forward state; error <= h^2/6 (k/2)^3."""
+    base = W.controlled_circuit(4, 30, 431, n_terms=4)
+    for pr in (base, W.share_params(base, 5, 432)):
+        D, _ = oracle.derivative_states(pr)
+        h = 1e-5
+        for a in range(pr.n_params):
+            k = int((pr.gates[:, 3] == a).sum())
+            tp, tm = pr.theta.copy(), pr.theta.copy()
+            tp[a] += h
+            tm[a] -= h
+            fd = (oracle.forward(W.Problem(**{**pr.__dict__, "theta": tp}))
+                  - oracle.forward(W.Problem(**{**pr.__dict__, "theta": tm}))) / (2 * h)
+            assert np.abs(D[a] - fd).max() < h * h / 6 * (k / 2) ** 3 + 1e-9
+
+
+def test_controlled_gradient_four_term_shift():
+    """A controlled rotation's generator |1><1| (x) sigma/2 has eigenvalues
+    0, +-1/2, so E(theta) is a trigonometric polynomial of frequencies 1/2 and
+    1; the four-term shift rule with shifts pi/2 and 3pi/2 (coefficients
+    (sqrt2 + 1)/(4 sqrt2) and (sqrt2 - 1)/(4 sqrt2)) gives the exact derivative."""
+    pr = W.controlled_layers(3, 2, 7, 441)
+    E, grad = oracle.energy_grad(pr)
+    c1 = (math.sqrt(2) + 1) / (4 * math.sqrt(2))
+    c2 = (math.sqrt(2) - 1) / (4 * math.sqrt(2))
+    for p in range(pr.n_params):
+        def e(shift):
+            th = pr.theta.copy()
+            th[p] += shift
+            return oracle.energy(W.Problem(**{**pr.__dict__, "theta": th}))
+        d = c1 * (e(math.pi / 2) - e(-math.pi / 2)) - c2 * (e(3 * math.pi / 2) - e(-3 * math.pi / 2))
+        assert abs(d - grad[p]) < 1e-12, (p, d, grad[p])

@@ -18,7 +18,9 @@ Gate encoding (one row per gate, int32): ``(kind, q0, q1, param)``
 * kind 0/1/2 = RX/RY/RZ on qubit q0 (q1 = -1), rotation exp(+i theta sigma/2)
   as written in Sec. 2 of the paper;
 * kind 3 = CNOT with control q0 and target q1;
-* kind 4 = CZ on qubits q0, q1.
+* kind 4 = CZ on qubits q0, q1;
+* kind 5/6/7 = controlled RX/RY/RZ with control q0 and target q1 (the rotation
+  acts on the target where the control is 1; Sec. 3, controlled rotations).
 
 Qubit q is bit q of the amplitude index (qubit 0 is the least significant bit).
 Pauli letters are 0=I, 1=X, 2=Y, 3=Z, stored row-major as ``pauli[t, q]``.
@@ -36,7 +38,8 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 RX, RY, RZ, CNOT, CZ = 0, 1, 2, 3, 4
-KIND_NAMES = {RX: "RX", RY: "RY", RZ: "RZ", CNOT: "CNOT", CZ: "CZ"}
+CRX, CRY, CRZ = 5, 6, 7                 # controlled rotations: control q0, target q1
+KIND_NAMES = {RX: "RX", RY: "RY", RZ: "RZ", CNOT: "CNOT", CZ: "CZ", CRX: "CRX", CRY: "CRY", CRZ: "CRZ"}
 ROTATION_KINDS = (RX, RY, RZ)
 
 
@@ -243,6 +246,63 @@ def layer_shared(n: int, layers: int, n_terms: int, seed: int) -> Problem:
     rng = np.random.Generator(np.random.PCG64(seed + 1))
     theta = rng.uniform(0.0, 2.0 * np.pi, 2 * layers)
     return dataclasses.replace(base, gates=gates, theta=theta)
+
+
+def controlled_circuit(n: int, n_gates: int, seed: int, controlled_fraction: float = 0.35,
+                       fixed_fraction: float = 0.2, n_terms: int = 6) -> Problem:
+    """A random gate list with controlled rotations among the other kinds.
+
+    Each gate is, in this order of draws from a second stream (seed + 1): a
+    fixed two-qubit gate (CNOT/CZ) with probability ``fixed_fraction``, else a
+    controlled rotation (CRX/CRY/CRZ on a random distinct control/target pair)
+    with probability ``controlled_fraction``, else a plain rotation.  Every
+    parameterised gate gets the next parameter index; angles and Hamiltonian
+    follow the documented draw order from ``seed``.
+    """
+    assert n >= 2
+    srng = np.random.Generator(np.random.PCG64(seed + 1))
+    rows = []
+    p = 0
+    for _ in range(n_gates):
+        u = srng.uniform()
+        if u < fixed_fraction:
+            kind = int(srng.integers(CNOT, CZ + 1))
+            a, b = srng.choice(n, size=2, replace=False)
+            rows.append([kind, int(a), int(b), -1])
+        elif u < fixed_fraction + controlled_fraction:
+            kind = int(srng.integers(CRX, CRZ + 1))
+            a, b = srng.choice(n, size=2, replace=False)
+            rows.append([kind, int(a), int(b), p])
+            p += 1
+        else:
+            rows.append([int(srng.integers(RX, RZ + 1)), int(srng.integers(0, n)), -1, p])
+            p += 1
+    gates = np.asarray(rows, dtype=np.int32).reshape(-1, 4)
+    theta, pauli, coeff = draw_problem_data(seed, p, n, n_terms)
+    return Problem(name=f"controlled_n{n}_g{n_gates}_s{seed}", n_qubits=n, gates=gates,
+                   theta=theta, pauli=pauli, coeff=coeff, seed=seed)
+
+
+def controlled_layers(n: int, layers: int, n_terms: int, seed: int, dt: float = 0.1,
+                      tikhonov: float = 1e-4) -> Problem:
+    """Layers of [RY on every qubit, then CRZ(q -> q+1) for q = 0..n-2, then
+    CRX(n-1 -> 0)]: a ring of controlled rotations, each with its own angle
+    (P = layers * 2n).  Angles and Hamiltonian in the documented draw order."""
+    rows: List[List[int]] = []
+    p = 0
+    for _ in range(layers):
+        for q in range(n):
+            rows.append([RY, q, -1, p])
+            p += 1
+        for q in range(n - 1):
+            rows.append([CRZ, q, q + 1, p])
+            p += 1
+        rows.append([CRX, n - 1, 0, p])
+        p += 1
+    gates = np.asarray(rows, dtype=np.int32).reshape(-1, 4)
+    theta, pauli, coeff = draw_problem_data(seed, p, n, n_terms)
+    return Problem(name=f"controlled_layers_n{n}_L{layers}", n_qubits=n, gates=gates, theta=theta,
+                   pauli=pauli, coeff=coeff, dt=dt, tikhonov=tikhonov, seed=seed)
 
 
 def random_state(n: int, seed: int) -> np.ndarray:
