@@ -7,7 +7,8 @@ library is missing, importing the binding raises: there is no fallback.
 
 Problems are described the way the library's C ABI describes them: a gate
 list of rows (kind, q0, q1, param) with kind 0/1/2 = RX/RY/RZ (rotation
-exp(+i theta sigma/2)), 3 = CNOT (control q0, target q1), 4 = CZ; a vector of
+exp(+i theta sigma/2)), 3 = CNOT (control q0, target q1), 4 = CZ, 5/6/7 =
+controlled RX/RY/RZ (control q0, target q1); a vector of
 angles indexed by parameter; a Pauli-sum Hamiltonian (letters 0..3 = I, X, Y, Z
 per qubit, real coefficients); an optional complex128 input state.
 """

@@ -205,7 +205,8 @@ struct Problem {
     std::vector<int> param_of;        // rotation (list order) -> parameter index
     // device image of the parameter map: param_of [P], then the rotations of
     // each parameter as off [NP + 1] and rot [P] (rot[off[a] .. off[a+1]) carry
-    // a), then the block of each rotation [P] (block-diagonal metric)
+    // a), then the block of each rotation [P] (block-diagonal metric), then
+    // the control qubit of each rotation [P] (-1: plain rotation)
     std::vector<int> param_map;
     std::vector<PauliTerm> ham;
     bool has_ham = false;
@@ -214,7 +215,8 @@ struct Problem {
 };
 
 // ints of a Problem's parameter map image
-inline size_t param_map_ints(const Circuit &c) { return (size_t)3 * c.P + c.NP + 1; }
+inline size_t param_map_ints(const Circuit &c) { return (size_t)4 * c.P + c.NP + 1; }
+inline size_t rot_ctrl_offset(const Circuit &c) { return (size_t)3 * c.P + c.NP + 1; }
 
 Problem make_problem(const qng_circuit *c, const double *theta, const qng_pauli_sum *h) {
     Problem p;
@@ -235,7 +237,8 @@ Problem make_problem(const qng_circuit *c, const double *theta, const qng_pauli_
     std::vector<int> rot(P), fill(count.begin(), count.end() - 1);
     for (int r = 0; r < P; ++r) rot[fill[p.param_of[r]]++] = r;
     p.param_map.insert(p.param_map.end(), rot.begin(), rot.end());
-    p.param_map.resize(param_map_ints(p.circ), 0);   // rotation blocks: set by apply_metric_settings
+    p.param_map.resize(rot_ctrl_offset(p.circ), 0);   // rotation blocks: set by apply_metric_settings
+    for (const Rot &r : p.circ.rots) p.param_map.push_back(r.ctrl);
     if (h) {
         p.ham = compile_hamiltonian(c, h);
         p.has_ham = true;
@@ -289,14 +292,17 @@ template <typename R> struct Engine {
     void apply(int pos, bool adjoint_gate, void *s0, void *s1) {
         const qng_gate &g = pb.circ.gates[pos];
         ++ctx->stats.other_launches;
+        const DevMat2 m = dev(adjoint_gate ? pb.adj[pos] : pb.fwd[pos]);
         if (g.kind == QNG_CNOT) launch_cnot<R>(s0, s1, n, g.q0, g.q1, st);
         else if (g.kind == QNG_CZ) launch_cz<R>(s0, s1, n, g.q0, g.q1, st);
-        else launch_apply_1q<R>(s0, s1, n, g.q0, dev(adjoint_gate ? pb.adj[pos] : pb.fwd[pos]), st);
+        else if (g.kind >= QNG_CRX) launch_apply_c1q<R>(s0, s1, n, g.q0, g.q1, m, st);
+        else launch_apply_1q<R>(s0, s1, n, g.q0, m, st);
     }
 
-    void prod(const void *a, const void *b, int q, int axis, double *dest) {
+    // <a| K |b> with K = sigma_q, or |1><1|_ctrl (x) sigma_q for ctrl >= 0
+    void prod(const void *a, const void *b, int q, int axis, double *dest, int ctrl = -1) {
         ctx->stats.other_launches += 2;
-        launch_pauli_prod<R>(a, b, n, q, axis, partials(), dest, st);
+        launch_pauli_prod<R>(a, b, n, q, axis, partials(), dest, st, ctrl);
     }
 
     // psi (state 0) <- |in>.  in_c128: device complex128 or nullptr.
@@ -315,7 +321,9 @@ template <typename R> struct Engine {
         for (int s = 0; s < c.P; ++s) {
             const Rot &rs = c.rots[s];
             for (; pos < rs.pos; ++pos) apply(pos, false, psi, nullptr);   // psi <- gates up to rotation s
-            prod(psi, psi, rs.qubit, rs.axis, traw() + 2 * s);              // <y_s|sigma_s|y_s>
+            prod(psi, psi, rs.qubit, rs.axis, traw() + 2 * s, rs.ctrl);     // <y_s|K_s|y_s>
+            // controlled rotation: <y_s|K_s^2|y_s> = Prob(control = 1) on the diagonal (Sec. 3)
+            if (rs.ctrl >= 0) prod(psi, psi, rs.ctrl, -1, lraw() + 2 * ((size_t)s * c.P + s), rs.ctrl);
             if (s == 0) continue;
             ++ctx->stats.other_launches;
             // block-diagonal metric: the column stops at the lowest rotation of its block
@@ -327,13 +335,13 @@ template <typename R> struct Engine {
                 if (lo < 0) continue;
             }
             const int plo = lo ? c.rots[lo].pos : p0;
-            launch_seed<R>(psi, lam, phi, n, rs.qubit, rs.axis, st);
+            launch_seed<R>(psi, lam, phi, n, rs.qubit, rs.axis, st, rs.ctrl);
             for (int k = rs.pos - 1; k >= plo; --k) {
                 const int r = c.rot_at[k];
                 if (r >= 0) {
                     const Rot &rr = c.rots[r];
                     if (pb.rot_block.empty() || pb.rot_block[r] == pb.rot_block[s]) {
-                        prod(lam, phi, rr.qubit, rr.axis, lraw() + 2 * ((size_t)r * c.P + s));
+                        prod(lam, phi, rr.qubit, rr.axis, lraw() + 2 * ((size_t)r * c.P + s), rr.ctrl);
                         ++ctx->stats.elements;
                     }
                     if (k > plo) apply(k, true, lam, phi);
@@ -366,7 +374,7 @@ template <typename R> struct Engine {
             const int r = c.rot_at[k];
             if (r >= 0) {
                 const Rot &rr = c.rots[r];
-                prod(lam, psi, rr.qubit, rr.axis, graw() + 2 * r);
+                prod(lam, psi, rr.qubit, rr.axis, graw() + 2 * r, rr.ctrl);
                 if (k > p0) apply(k, true, lam, psi);
             } else {
                 apply(k, true, lam, psi);
@@ -416,13 +424,14 @@ void unpack_to_params(const Problem &pb, const double *lraw, const double *traw,
                       double *gout, double *tout, double *spare, double *&G, double *&T, hipStream_t st) {
     const Circuit &c = pb.circ;
     const int *rot_block = pb.rot_block.empty() ? nullptr : param_map_dev + 2 * c.P + c.NP + 1;
+    const int *rot_ctrl = c.controlled ? param_map_dev + rot_ctrl_offset(c) : nullptr;
     if (!c.shared) {
-        launch_unpack_metric(lraw, traw, param_map_dev, c.P, gout, tout, rot_block, pb.l_only, st);
+        launch_unpack_metric(lraw, traw, param_map_dev, c.P, gout, tout, rot_block, rot_ctrl, pb.l_only, st);
         G = gout;
         T = tout;
         return;
     }
-    launch_unpack_metric(lraw, traw, nullptr, c.P, gout, tout, rot_block, pb.l_only, st);
+    launch_unpack_metric(lraw, traw, nullptr, c.P, gout, tout, rot_block, rot_ctrl, pb.l_only, st);
     G = spare;
     T = spare + 2 * (size_t)c.NP * c.NP;
     launch_contract_metric(gout, tout, c.P, param_map_dev + c.P, param_map_dev + c.P + c.NP + 1, c.NP, G, T, st);
@@ -440,7 +449,9 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
     const int n = c.n;
     const size_t amp = 2 * sizeof(R);
     const size_t V = (size_t(1) << n) * amp;
-    const bool fused = ctx->opt_fusion != 0 && spec.metric && c.P > 1;
+    // controlled rotations: per-primitive kernels only (the fused passes
+    // implement plain rotations, CNOT and CZ)
+    const bool fused = ctx->opt_fusion != 0 && spec.metric && c.P > 1 && !c.controlled;
     const SweepPlan *plan = nullptr;
     FusedRun fr;
     size_t scratch = 0;
@@ -460,7 +471,7 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
     }
     std::shared_ptr<const SweepPlan> gplan;
     const bool f64_regs = amp == 16 || ctx->opt_f64_regs;
-    if (ctx->opt_fusion != 0 && spec.grad && c.P > 0) {
+    if (ctx->opt_fusion != 0 && spec.grad && c.P > 0 && !c.controlled) {
         gplan = ctx->sweep_cache.get_gradient(c, ctx->opt_tile, (int)amp, f64_regs);
         scratch = std::max(scratch, fused_gradient_scratch_bytes(*gplan, c.M));
     }
@@ -1003,6 +1014,8 @@ qng_status qng_plan(const qng_circuit *circ, int fusion, int tile_qubits, qng_pl
         Circuit c = compile_circuit(circ);
         *out = qng_plan_info{};
         out->elements = (int64_t)c.P * (c.P - 1) / 2;
+        if (fusion && c.controlled)
+            fail(QNG_E_UNSUPPORTED, "fused sweep passes do not take controlled rotations");
         if (!fusion) {
             for (int s = 1; s < c.P; ++s) out->ops += c.rots[s].pos - c.rots[0].pos + (s);
             out->passes = 0;
@@ -1021,6 +1034,7 @@ qng_status qng_plan_export(const qng_circuit *circ, int tile_qubits, int amp_byt
         if (sweep < 0 || sweep > 2) fail(QNG_E_INVALID_ARG, "sweep must be 0 or 2 (metric) or 1 (gradient)");
         validate_circuit(circ, kMaxQubitsC64);
         Circuit c = compile_circuit(circ);
+        if (c.controlled) fail(QNG_E_UNSUPPORTED, "fused sweep passes do not take controlled rotations");
         SweepPlan plan = sweep == 1 ? build_gradient_plan(c, tile_qubits, amp_bytes, amp_bytes == 16)
                                     : build_sweep_plan(c, tile_qubits, amp_bytes, 1, amp_bytes == 16, sweep == 2 ? 2 : 1);
         int64_t k = 0;
@@ -1206,6 +1220,9 @@ qng_status qng_step_batched(qng_ctx *ctx, int32_t B, const qng_circuit *circs, c
         for (int b = 0; b < B; ++b) {
             try {
                 validate_circuit(&circs[b], max_qubits(prec));
+                for (int k = 0; k < circs[b].n_gates; ++k)
+                    if (circs[b].gates[k].kind >= QNG_CRX)
+                        fail(QNG_E_UNSUPPORTED, "controlled rotations are not available in qng_step_batched");
                 validate_theta(&circs[b], thetas[b]);
                 validate_hamiltonian(&circs[b], &hams[b]);
                 if (circs[b].n_params > 0 && !dtheta_out[b]) fail(QNG_E_INVALID_ARG, "dtheta_out is NULL");
@@ -1383,6 +1400,8 @@ qng_status qng_apply_circuit_dev(qng_ctx *ctx, const qng_circuit *circ, const do
                 const qng_gate &g = pb.circ.gates[pos];
                 if (g.kind == QNG_CNOT) launch_cnot<R>(state_dev, nullptr, n, g.q0, g.q1, ctx->stream);
                 else if (g.kind == QNG_CZ) launch_cz<R>(state_dev, nullptr, n, g.q0, g.q1, ctx->stream);
+                else if (g.kind >= QNG_CRX)
+                    launch_apply_c1q<R>(state_dev, nullptr, n, g.q0, g.q1, dev(pb.fwd[pos]), ctx->stream);
                 else launch_apply_1q<R>(state_dev, nullptr, n, g.q0, dev(pb.fwd[pos]), ctx->stream);
             }
         });

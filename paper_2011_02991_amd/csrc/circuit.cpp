@@ -35,6 +35,17 @@ void validate_circuit(const qng_circuit *c, int max_qubits) {
             ++seen[g.param];
             ++n_rot;
             break;
+        case QNG_CRX:
+        case QNG_CRY:
+        case QNG_CRZ:
+            if (g.q0 < 0 || g.q0 >= n || g.q1 < 0 || g.q1 >= n)
+                fail(QNG_E_BAD_CIRCUIT, where + "qubit out of range");
+            if (g.q0 == g.q1) fail(QNG_E_BAD_CIRCUIT, where + "control and target are the same qubit");
+            if (g.param < 0) fail(QNG_E_BAD_PARAMS, where + "rotation needs a parameter index >= 0");
+            if (g.param >= c->n_params) fail(QNG_E_BAD_PARAMS, where + "parameter index >= n_params");
+            ++seen[g.param];
+            ++n_rot;
+            break;
         case QNG_CNOT:
         case QNG_CZ:
             if (g.q0 < 0 || g.q0 >= n || g.q1 < 0 || g.q1 >= n)
@@ -84,6 +95,10 @@ Circuit compile_circuit(const qng_circuit *c) {
         if (g.kind <= QNG_RZ) {
             k.rot_at[pos] = (int)k.rots.size();
             k.rots.push_back(Rot{g.kind == QNG_RX ? AX_X : g.kind == QNG_RY ? AX_Y : AX_Z, g.q0, g.param, pos});
+        } else if (g.kind >= QNG_CRX && g.kind <= QNG_CRZ) {
+            k.rot_at[pos] = (int)k.rots.size();
+            k.rots.push_back(Rot{g.kind - QNG_CRX, g.q1, g.param, pos, g.q0});
+            k.controlled = true;
         }
     }
     k.P = (int)k.rots.size();

@@ -31,12 +31,15 @@ struct Mat2 {  // row-major 2x2 complex, [[a, b], [c, d]]
     cd a, b, c, d;
 };
 
-// One rotation of the ansatz, in gate-list order.
+// One rotation of the ansatz, in gate-list order.  A controlled rotation
+// (ctrl >= 0) rotates `qubit` where qubit `ctrl` is 1; its generator is
+// |1><1|_ctrl (x) sigma, which replaces sigma in every product of its column.
 struct Rot {
     int axis;    // generator sigma: X, Y or Z
     int qubit;
     int param;   // parameter index (row/column of G)
     int pos;     // position in the gate list
+    int ctrl = -1;
 };
 
 struct Circuit {
@@ -45,6 +48,7 @@ struct Circuit {
     int P = 0;              // rotations (one recurrence column each)
     int NP = 0;             // parameters; NP < P when rotations share parameters
     bool shared = false;    // some parameter is carried by several rotations
+    bool controlled = false;  // some rotation is a controlled rotation
     std::vector<qng_gate> gates;
     std::vector<int> rot_at;   // gate position -> rotation index (list order) or -1
     std::vector<Rot> rots;     // rotations in list order

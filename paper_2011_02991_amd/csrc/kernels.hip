@@ -112,6 +112,22 @@ __global__ void k_apply_1q_tab(typename Cplx<R>::T *s0, typename Cplx<R>::T *s1,
     }
 }
 
+// Controlled single-qubit gate: the matrix acts on the pairs (x, x | 2^q) whose
+// control bit c is 1 (a quarter index p enumerates the pairs with bit c set and
+// bit q clear); the other amplitudes keep their values.
+template <typename R>
+__global__ void k_apply_c1q(typename Cplx<R>::T *s0, typename Cplx<R>::T *s1, int n, int c, int q, DevMat2 m) {
+    const uint64_t nq = uint64_t(1) << (n - 2);
+    const int lo = c < q ? c : q, hi = c < q ? q : c;
+    const R ar = (R)m.ar, ai = (R)m.ai, br = (R)m.br, bi = (R)m.bi;
+    const R cr = (R)m.cr, ci = (R)m.ci, dr = (R)m.dr, di = (R)m.di;
+    for (uint64_t p = blockIdx.x * (uint64_t)kBlock + threadIdx.x; p < nq; p += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t i0 = insert_two_zeros(p, lo, hi) | (uint64_t(1) << c), i1 = i0 | (uint64_t(1) << q);
+        mat_pair<R>(s0, i0, i1, ar, ai, br, bi, cr, ci, dr, di);
+        if (s1) mat_pair<R>(s1, i0, i1, ar, ai, br, bi, cr, ci, dr, di);
+    }
+}
+
 // CNOT(control c, target t): swap amplitudes (x, x ^ 2^t) for x with bit c set and bit t clear.
 template <typename R>
 __global__ void k_cnot(typename Cplx<R>::T *s0, typename Cplx<R>::T *s1, int n, int c, int t) {
@@ -140,9 +156,11 @@ __global__ void k_cz(typename Cplx<R>::T *s0, typename Cplx<R>::T *s1, int n, in
 }
 
 // lam = y; phi = sigma_q y.   (X: swap; Y: phi0 = -i y1, phi1 = i y0; Z: phi1 = -y1)
+// With a control qubit c >= 0 the generator is |1><1|_c (x) sigma_q: phi is
+// zero on the amplitudes whose bit c is 0 (c != q).
 template <typename R>
 __global__ void k_seed(const typename Cplx<R>::T *y, typename Cplx<R>::T *lam, typename Cplx<R>::T *phi, int n, int q,
-                       int axis) {
+                       int axis, int c) {
     const uint64_t npairs = uint64_t(1) << (n - 1);
     for (uint64_t p = blockIdx.x * (uint64_t)kBlock + threadIdx.x; p < npairs; p += (uint64_t)gridDim.x * kBlock) {
         const uint64_t i0 = insert_zero(p, q), i1 = i0 | (uint64_t(1) << q);
@@ -153,6 +171,7 @@ __global__ void k_seed(const typename Cplx<R>::T *y, typename Cplx<R>::T *lam, t
         if (axis == 0) { o0 = v; o1 = u; }
         else if (axis == 1) { o0.x = v.y; o0.y = -v.x; o1.x = -u.y; o1.y = u.x; }
         else { o0 = u; o1.x = -v.x; o1.y = -v.y; }
+        if (c >= 0 && !((i0 >> c) & 1)) { o0.x = o0.y = o1.x = o1.y = (R)0; }
         phi[i0] = o0;
         phi[i1] = o1;
     }
@@ -181,21 +200,27 @@ __device__ __forceinline__ void cmac(double &sr, double &si, double ar, double a
     si += ar * bi - ai * br;
 }
 
+// Block partials of <a| sigma_q |b> (axis 0/1/2; axis < 0: the identity).
+// With a control qubit c >= 0 the operator is |1><1|_c (x) sigma_q: only the
+// amplitudes whose bit c is 1 contribute (c != q; for axis < 0, q is ignored).
 template <typename R>
 __global__ void k_pauli_prod_partial(const typename Cplx<R>::T *a, const typename Cplx<R>::T *b, int n, int q,
-                                     int axis, double *partials) {
+                                     int axis, int c, double *partials) {
     double sr = 0.0, si = 0.0;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     if (axis < 0) {
-        const uint64_t dim = uint64_t(1) << n;
-        for (uint64_t x = blockIdx.x * (uint64_t)kBlock + threadIdx.x; x < dim; x += stride) {
+        const uint64_t dim = uint64_t(1) << (c >= 0 ? n - 1 : n);
+        for (uint64_t p = blockIdx.x * (uint64_t)kBlock + threadIdx.x; p < dim; p += stride) {
+            const uint64_t x = c >= 0 ? insert_zero(p, c) | (uint64_t(1) << c) : p;
             const typename Cplx<R>::T u = a[x], v = b[x];
             cmac(sr, si, u.x, u.y, v.x, v.y);
         }
     } else {
-        const uint64_t npairs = uint64_t(1) << (n - 1);
+        const uint64_t npairs = uint64_t(1) << (c >= 0 ? n - 2 : n - 1);
+        const int lo = c < q ? c : q, hi = c < q ? q : c;
         for (uint64_t p = blockIdx.x * (uint64_t)kBlock + threadIdx.x; p < npairs; p += stride) {
-            const uint64_t i0 = insert_zero(p, q), i1 = i0 | (uint64_t(1) << q);
+            const uint64_t i0 = c >= 0 ? insert_two_zeros(p, lo, hi) | (uint64_t(1) << c) : insert_zero(p, q);
+            const uint64_t i1 = i0 | (uint64_t(1) << q);
             const typename Cplx<R>::T a0 = a[i0], a1 = a[i1], b0 = b[i0], b1 = b[i1];
             if (axis == 2) {            // conj(a0) b0 - conj(a1) b1
                 cmac(sr, si, a0.x, a0.y, b0.x, b0.y);
@@ -316,7 +341,7 @@ __global__ void k_pauli_term(const typename Cplx<R>::T *psi, typename Cplx<R>::T
 // ------------------------------------------------------------------ unpack
 
 __global__ void k_unpack_metric(const double *Lraw, const double *Traw, const int *param_of, int P, double *G,
-                                double *Tout, const int *rot_block, int l_only) {
+                                double *Tout, const int *rot_block, const int *rot_ctrl, int l_only) {
     const int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     if (idx >= (int64_t)P * P) return;
     const int r = (int)(idx / P), s = (int)(idx % P);
@@ -326,7 +351,7 @@ __global__ void k_unpack_metric(const double *Lraw, const double *Traw, const in
     double lr, li;
     if (r < s)      { lr = 0.25 * Lraw[2 * ((int64_t)r * P + s)]; li = 0.25 * Lraw[2 * ((int64_t)r * P + s) + 1]; }
     else if (r > s) { lr = 0.25 * Lraw[2 * ((int64_t)s * P + r)]; li = -0.25 * Lraw[2 * ((int64_t)s * P + r) + 1]; }
-    else            { lr = 0.25; li = 0.0; }
+    else            { lr = (rot_ctrl && rot_ctrl[s] >= 0) ? 0.25 * Lraw[2 * ((int64_t)s * P + s)] : 0.25; li = 0.0; }
     // G = L - conj(T_r) T_s (or L alone); zero between different blocks
     double pr = trr * tsr + tri * tsi, pi = trr * tsi - tri * tsr;
     if (l_only) pr = pi = 0.0;
@@ -422,6 +447,13 @@ template <typename R> void launch_apply_1q_tab(void *s0, void *s1, int n, int q,
     check_launch();
 }
 
+template <typename R>
+void launch_apply_c1q(void *s0, void *s1, int n, int c, int q, const DevMat2 &m, hipStream_t st) {
+    hipLaunchKernelGGL(k_apply_c1q<R>, dim3(grid_for(uint64_t(1) << (n - 2))), dim3(kBlock), 0, st,
+                       (typename Cplx<R>::T *)s0, (typename Cplx<R>::T *)s1, n, c, q, m);
+    check_launch();
+}
+
 template <typename R> void launch_cnot(void *s0, void *s1, int n, int c, int t, hipStream_t st) {
     hipLaunchKernelGGL(k_cnot<R>, dim3(grid_for(uint64_t(1) << (n - 2))), dim3(kBlock), 0, st,
                        (typename Cplx<R>::T *)s0, (typename Cplx<R>::T *)s1, n, c, t);
@@ -434,19 +466,20 @@ template <typename R> void launch_cz(void *s0, void *s1, int n, int a, int b, hi
     check_launch();
 }
 
-template <typename R> void launch_seed(const void *y, void *lam, void *phi, int n, int q, int axis, hipStream_t st) {
+template <typename R>
+void launch_seed(const void *y, void *lam, void *phi, int n, int q, int axis, hipStream_t st, int ctrl) {
     hipLaunchKernelGGL(k_seed<R>, dim3(grid_for(uint64_t(1) << (n - 1))), dim3(kBlock), 0, st,
                        (const typename Cplx<R>::T *)y, (typename Cplx<R>::T *)lam, (typename Cplx<R>::T *)phi, n, q,
-                       axis);
+                       axis, ctrl);
     check_launch();
 }
 
 template <typename R>
 void launch_pauli_prod(const void *a, const void *b, int n, int q, int axis, double *partials, double *dest,
-                       hipStream_t st) {
+                       hipStream_t st, int ctrl) {
     const int nb = reduce_blocks(n);
     hipLaunchKernelGGL(k_pauli_prod_partial<R>, dim3(nb), dim3(kBlock), 0, st, (const typename Cplx<R>::T *)a,
-                       (const typename Cplx<R>::T *)b, n, q, axis, partials);
+                       (const typename Cplx<R>::T *)b, n, q, axis, ctrl, partials);
     check_launch();
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, st, (const double *)partials, nb, dest);
     check_launch();
@@ -476,11 +509,11 @@ void launch_pauli_term(const void *psi, void *out, int n, uint64_t flip, uint64_
 }
 
 void launch_unpack_metric(const double *Lraw, const double *Traw, const int *param_of, int P, double *G_out,
-                          double *T_out, const int *rot_block, bool l_only, hipStream_t st) {
+                          double *T_out, const int *rot_block, const int *rot_ctrl, bool l_only, hipStream_t st) {
     const int64_t work = (int64_t)P * P;
     if (work == 0) return;
     hipLaunchKernelGGL(k_unpack_metric, dim3((unsigned)((work + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, Lraw,
-                       Traw, param_of, P, G_out, T_out, rot_block, l_only ? 1 : 0);
+                       Traw, param_of, P, G_out, T_out, rot_block, rot_ctrl, l_only ? 1 : 0);
     check_launch();
 }
 
@@ -512,10 +545,12 @@ void launch_grad_from_raw(const double *graw, const int *param_of, int P, double
     template void launch_copy<R>(const void *, void *, int, hipStream_t);                                         \
     template void launch_apply_1q<R>(void *, void *, int, int, const DevMat2 &, hipStream_t);                     \
     template void launch_apply_1q_tab<R>(void *, void *, int, int, const double *, hipStream_t);                  \
+    template void launch_apply_c1q<R>(void *, void *, int, int, int, const DevMat2 &, hipStream_t);               \
     template void launch_cnot<R>(void *, void *, int, int, int, hipStream_t);                                     \
     template void launch_cz<R>(void *, void *, int, int, int, hipStream_t);                                       \
-    template void launch_seed<R>(const void *, void *, void *, int, int, int, hipStream_t);                      \
-    template void launch_pauli_prod<R>(const void *, const void *, int, int, int, double *, double *, hipStream_t); \
+    template void launch_seed<R>(const void *, void *, void *, int, int, int, hipStream_t, int);                 \
+    template void launch_pauli_prod<R>(const void *, const void *, int, int, int, double *, double *, hipStream_t, \
+                                       int);                                                                      \
     template void launch_advance_seed<R>(void *, void *, void *, int, int, const double *, int, int, double *,       \
                                          double *, hipStream_t);                                                  \
     template void launch_pauli_term<R>(const void *, void *, int, uint64_t, uint64_t, int, double, int, hipStream_t);

@@ -31,11 +31,16 @@ template <typename R> void launch_copy(const void *src, void *dst, int n, hipStr
 template <typename R> void launch_apply_1q(void *s0, void *s1, int n, int q, const DevMat2 &m, hipStream_t st);
 // As launch_apply_1q, the matrix read from device memory (8 doubles: a, b, c, d as re, im).
 template <typename R> void launch_apply_1q_tab(void *s0, void *s1, int n, int q, const double *m_dev, hipStream_t st);
+// Controlled: the matrix acts on qubit q where qubit c (!= q) is 1.
+template <typename R>
+void launch_apply_c1q(void *s0, void *s1, int n, int c, int q, const DevMat2 &m, hipStream_t st);
 template <typename R> void launch_cnot(void *s0, void *s1, int n, int control, int target, hipStream_t st);
 template <typename R> void launch_cz(void *s0, void *s1, int n, int a, int b, hipStream_t st);
 
-// lam = y; phi = sigma_q y  (axis 0/1/2 = X/Y/Z).
-template <typename R> void launch_seed(const void *y, void *lam, void *phi, int n, int q, int axis, hipStream_t st);
+// lam = y; phi = sigma_q y  (axis 0/1/2 = X/Y/Z).  ctrl >= 0: phi = (|1><1|_ctrl (x) sigma_q) y,
+// the generator of a controlled rotation.
+template <typename R>
+void launch_seed(const void *y, void *lam, void *phi, int n, int q, int axis, hipStream_t st, int ctrl = -1);
 
 // Start of a metric column in one pass over the forward register:
 // psi <- R psi (R: the rotation on qubit qr whose matrix is m_dev, 8 doubles;
@@ -46,10 +51,11 @@ void launch_advance_seed(void *psi, void *lam, void *phi, int n, int qr, const d
                          double *partials, double *dest, hipStream_t st);
 
 // dest (one complex128) = <a| sigma_q |b>; axis -1 means the identity (plain inner product).
+// ctrl >= 0: <a| |1><1|_ctrl (x) sigma_q |b> (only amplitudes with bit ctrl = 1).
 // partials: reduce_blocks(n) complex128 scratch.
 template <typename R>
 void launch_pauli_prod(const void *a, const void *b, int n, int q, int axis, double *partials, double *dest,
-                       hipStream_t st);
+                       hipStream_t st, int ctrl = -1);
 
 // out (+)= coeff * (-i)^{n_y} (-1)^{popcount(x & zy)} psi[x ^ flip]; first != 0 overwrites.
 template <typename R>
@@ -61,9 +67,12 @@ void launch_pauli_term(const void *psi, void *out, int n, uint64_t flip, uint64_
 // param_of[r] maps rotation r to its parameter index.  G_out: P*P complex, T_out: P complex (nullable).
 // param_of = NULL: rotation order.  rot_block (nullable): block id per
 // rotation; entries between rotations of different blocks are set to zero
-// (block-diagonal approximation).  l_only: G = L (the conj(T_r) T_s term left out).
+// (block-diagonal approximation).  rot_ctrl (nullable): control qubit per
+// rotation (-1: plain); a controlled rotation s takes L_ss = Lraw[s*P+s] / 4,
+// where the caller stored <y_s|(|1><1| on the control)|y_s> (Sec. 3); plain
+// rotations take 1/4.  l_only: G = L (the conj(T_r) T_s term left out).
 void launch_unpack_metric(const double *Lraw, const double *Traw, const int *param_of, int P, double *G_out,
-                          double *T_out, const int *rot_block, bool l_only, hipStream_t st);
+                          double *T_out, const int *rot_block, const int *rot_ctrl, bool l_only, hipStream_t st);
 
 // grad[param_of[r]] = -Im graw[r]   (d_r E = 2 Re[(i/2) <lambda|sigma_r|phi>]).
 void launch_grad_from_raw(const double *graw, const int *param_of, int P, double *grad, hipStream_t st);

@@ -46,7 +46,7 @@ def test_validate_accepts_workloads(qng):
 
 @pytest.mark.parametrize("mutate,status", [
     (lambda g: g.__setitem__((0, 1), 99), "QNG_E_BAD_CIRCUIT"),          # qubit out of range
-    (lambda g: g.__setitem__((0, 0), 7), "QNG_E_BAD_CIRCUIT"),           # unknown kind
+    (lambda g: g.__setitem__((0, 0), 11), "QNG_E_BAD_CIRCUIT"),          # unknown kind
     (lambda g: g.__setitem__((1, 3), 0), "QNG_E_BAD_PARAMS"),            # parameter 1 left on no rotation
     (lambda g: g.__setitem__((0, 2), 3), "QNG_E_BAD_CIRCUIT"),           # rotation with q1 != -1
 ])
@@ -66,6 +66,36 @@ def test_validate_accepts_shared_parameters(qng):
     qng.validate(_circ(qng, pr), pr.theta)
     pr2 = W.share_params(W.random_circuit(6, 30, 12), 4, 13)
     qng.validate(_circ(qng, pr2), pr2.theta)
+
+
+def test_validate_controlled_rotations(qng):
+    """CRX/CRY/CRZ (kinds 5/6/7): control q0, target q1, a parameter index."""
+    for pr in (W.controlled_circuit(6, 40, 21), W.controlled_layers(5, 2, 4, 22)):
+        assert (pr.gates[:, 0] >= W.CRX).any()
+        qng.validate(_circ(qng, pr), pr.theta)
+    bad = [([W.CRY, 1, 1, 0], "QNG_E_BAD_CIRCUIT"),     # control == target
+           ([W.CRX, 0, 5, 0], "QNG_E_BAD_CIRCUIT"),     # target out of range
+           ([W.CRZ, -1, 1, 0], "QNG_E_BAD_CIRCUIT"),    # control out of range
+           ([W.CRZ, 0, 1, -1], "QNG_E_BAD_PARAMS"),     # no parameter
+           ([W.CRZ, 0, 1, 2], "QNG_E_BAD_PARAMS")]      # parameter >= n_params
+    for row, status in bad:
+        g = np.array([[W.RY, 0, -1, 0], row], dtype=np.int32)
+        with pytest.raises(qng.QNGError) as e:
+            qng.validate(qng.Circuit(2, g, 1), [0.1], with_hamiltonian=False)
+        assert e.value.name == status, (row, e.value.name)
+
+
+def test_controlled_rotations_not_planned_for_fused_passes(qng):
+    """The per-primitive plan counts them; the fused-pass planner and its export
+    reject them (QNG_E_UNSUPPORTED)."""
+    pr = W.controlled_layers(6, 2, 4, 23)
+    c = _circ(qng, pr)
+    info = qng.plan(c, fusion=0)
+    assert info["elements"] == pr.n_params * (pr.n_params - 1) // 2
+    for call in (lambda: qng.plan(c, fusion=1), lambda: qng.plan_export(c)):
+        with pytest.raises(qng.QNGError) as e:
+            call()
+        assert e.value.name == "QNG_E_UNSUPPORTED"
 
 
 def test_validate_two_qubit_gate_same_qubit(qng):
