@@ -69,7 +69,7 @@ typedef enum {
 
 typedef enum {
     QNG_RX = 0, QNG_RY = 1, QNG_RZ = 2, QNG_CNOT = 3, QNG_CZ = 4,
-    QNG_CRX = 5, QNG_CRY = 6, QNG_CRZ = 7   /* controlled rotations (Sec. 3, the controlled-rotation diagonal) */
+    QNG_CRX = 5, QNG_CRY = 6, QNG_CRZ = 7   /* controlled rotations (Sec. 2, the controlled-rotation diagonal) */
 } qng_gate_kind;
 
 /* Storage precision of the state vectors.  QNG_C64 keeps states and gate
@@ -82,7 +82,7 @@ typedef enum { QNG_C128 = 0, QNG_C64 = 1 } qng_precision;
  * two qubits, param = -1.  Controlled rotations (CRX/CRY/CRZ): q0 = control,
  * q1 = target (q0 != q1), param >= 0; the gate is |0><0| (x) 1 + |1><1| (x)
  * exp(i theta sigma/2), so its column of G has the generator |1><1| (x) sigma
- * and the diagonal L_ii = 1/4 Prob(control = 1) instead of 1/4 (Sec. 3).
+ * and the diagonal L_ii = 1/4 Prob(control = 1) instead of 1/4 (Sec. 2).
  * Circuits with controlled rotations run on the per-primitive kernels whatever
  * QNG_OPT_FUSION says; qng_plan with fusion, qng_plan_export and
  * qng_step_batched reject them with QNG_E_UNSUPPORTED.

@@ -322,7 +322,7 @@ template <typename R> struct Engine {
             const Rot &rs = c.rots[s];
             for (; pos < rs.pos; ++pos) apply(pos, false, psi, nullptr);   // psi <- gates up to rotation s
             prod(psi, psi, rs.qubit, rs.axis, traw() + 2 * s, rs.ctrl);     // <y_s|K_s|y_s>
-            // controlled rotation: <y_s|K_s^2|y_s> = Prob(control = 1) on the diagonal (Sec. 3)
+            // controlled rotation: <y_s|K_s^2|y_s> = Prob(control = 1) on the diagonal (Sec. 2)
             if (rs.ctrl >= 0) prod(psi, psi, rs.ctrl, -1, lraw() + 2 * ((size_t)s * c.P + s), rs.ctrl);
             if (s == 0) continue;
             ++ctx->stats.other_launches;

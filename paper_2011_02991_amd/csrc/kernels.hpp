@@ -69,7 +69,7 @@ void launch_pauli_term(const void *psi, void *out, int n, uint64_t flip, uint64_
 // rotation; entries between rotations of different blocks are set to zero
 // (block-diagonal approximation).  rot_ctrl (nullable): control qubit per
 // rotation (-1: plain); a controlled rotation s takes L_ss = Lraw[s*P+s] / 4,
-// where the caller stored <y_s|(|1><1| on the control)|y_s> (Sec. 3); plain
+// where the caller stored <y_s|(|1><1| on the control)|y_s> (Sec. 2); plain
 // rotations take 1/4.  l_only: G = L (the conj(T_r) T_s term left out).
 void launch_unpack_metric(const double *Lraw, const double *Traw, const int *param_of, int P, double *G_out,
                           double *T_out, const int *rot_block, const int *rot_ctrl, bool l_only, hipStream_t st);

@@ -2,7 +2,7 @@
 
 A controlled rotation's column uses the generator |1><1|_c (x) sigma_t in
 every product and seed, and its diagonal L_ii is 1/4 Prob(control = 1) of the
-state before the gate (Sec. 3) rather than 1/4.  These circuits run on the
+state before the gate (Sec. 2) rather than 1/4.  These circuits run on the
 per-primitive kernels whatever the fusion option says (no fused sweep launch
 may appear in the stats).  complex128 results must match the oracle to 1e-10
 normwise (Delta theta: kappa(Re G + eps I) * 1e-14 when larger); complex64 to
@@ -81,7 +81,7 @@ def test_random_controlled_circuits(env, n, ngates, seed):
 
 
 def test_diagonal_is_quarter_control_probability(env):
-    """L_ii = 1/4 Prob(control = 1) (Sec. 3): the L-only metric's diagonal
+    """L_ii = 1/4 Prob(control = 1) (Sec. 2): the L-only metric's diagonal
     against the probabilities of the oracle's states before each gate."""
     torch, q, ctx = env
     pr = W.controlled_layers(6, 2, 5, 5207)

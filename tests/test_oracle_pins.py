@@ -373,7 +373,7 @@ def test_shared_parameters_contract_the_unshared_metric():
 
 def test_controlled_rotation_on_basis_states():
     """A controlled rotation leaves every basis state whose control bit is 0
-    untouched and rotates the target of the others (the gate of Sec. 3's
+    untouched and rotates the target of the others (the gate of Sec. 2's
     controlled-rotation example); its derivative vanishes where the control
     is 0.  Checked against the plain rotation applied to a 1-qubit target."""
     rng = np.random.default_rng(41)
@@ -415,7 +415,7 @@ def test_controlled_closed_forms():
 
 
 def test_controlled_diagonal_is_quarter_control_probability():
-    """Sec. 3: for a controlled rotation L_ii = 1/4 <psi_{i-1}| (|1><1| on the
+    """Sec. 2: for a controlled rotation L_ii = 1/4 <psi_{i-1}| (|1><1| on the
     control) |psi_{i-1}>, with psi_{i-1} the state just before gate i; for a
     plain rotation L_ii = 1/4."""
     pr = W.controlled_circuit(5, 40, 411, n_terms=4)
@@ -482,3 +482,35 @@ def test_controlled_gradient_four_term_shift():
             return oracle.energy(W.Problem(**{**pr.__dict__, "theta": th}))
         d = c1 * (e(math.pi / 2) - e(-math.pi / 2)) - c2 * (e(3 * math.pi / 2) - e(-3 * math.pi / 2))
         assert abs(d - grad[p]) < 1e-12, (p, d, grad[p])
+
+
+# ------------------------------------------------ the element-by-element route
+
+@pytest.mark.parametrize("make", [lambda: W.random_circuit(3, 11, 451, n_terms=3),
+                                  lambda: W.controlled_circuit(3, 9, 452, n_terms=3)])
+def test_each_element_prepared_independently(make):
+    """Alg. 2 of the appendix (each element from two states, each prepared from
+    |in> on its own, P <= 8), with dense gate matrices: every
+    L_ij = <phi_A|phi_B>, where phi_A is the ansatz with gate i replaced by its
+    derivative and phi_B the same for j; T_i = <psi|phi_A>; G = L - T^* T."""
+    pr = make()
+    pr.in_state = W.random_state(pr.n_qubits, 453)
+    P, n = pr.n_params, pr.n_qubits
+    assert 2 <= P <= 8
+
+    def prepare(deriv):
+        v = pr.in_state.copy()
+        for g in pr.gates:
+            v = dense.gate_unitary(n, g, pr.theta, derivative=int(g[3]) == deriv and deriv >= 0) @ v
+        return v
+
+    psi = prepare(-1)
+    L = np.empty((P, P), dtype=np.complex128)
+    T = np.empty(P, dtype=np.complex128)
+    for i in range(P):
+        for j in range(P):
+            L[i, j] = np.vdot(prepare(i), prepare(j))
+        T[i] = np.vdot(psi, prepare(i))
+    G, To = oracle.metric(pr)
+    np.testing.assert_allclose(To, T, atol=1e-14)
+    np.testing.assert_allclose(G, L - np.outer(T.conj(), T), atol=1e-14)

@@ -20,7 +20,7 @@ Gate encoding (one row per gate, int32): ``(kind, q0, q1, param)``
 * kind 3 = CNOT with control q0 and target q1;
 * kind 4 = CZ on qubits q0, q1;
 * kind 5/6/7 = controlled RX/RY/RZ with control q0 and target q1 (the rotation
-  acts on the target where the control is 1; Sec. 3, controlled rotations).
+  acts on the target where the control is 1; Sec. 2, controlled rotations).
 
 Qubit q is bit q of the amplitude index (qubit 0 is the least significant bit).
 Pauli letters are 0=I, 1=X, 2=Y, 3=Z, stored row-major as ``pauli[t, q]``.
