@@ -54,11 +54,11 @@ def _load():
         build(force=True)
     lib = ctypes.CDLL(_LIB)
     c_int, c_p = ctypes.c_int, ctypes.c_void_p
-    lib.oracle_forward.argtypes = [c_int, c_int, c_p, c_p, c_p, c_p]
-    lib.oracle_derivative_states.argtypes = [c_int, c_int, c_p, c_p, c_p, c_int, c_p, c_p, c_p]
+    lib.oracle_forward.argtypes = [c_int, c_int, c_p, c_p, c_p, c_p, c_p]
+    lib.oracle_derivative_states.argtypes = [c_int, c_int, c_p, c_p, c_p, c_int, c_p, c_p, c_p, c_p]
     lib.oracle_apply_pauli_sum.argtypes = [c_int, c_int, c_p, c_p, c_p, c_p]
     lib.oracle_apply_pauli_letter.argtypes = [c_int, c_int, c_int, c_p]
-    lib.oracle_apply_gate.argtypes = [c_int, c_p, c_p, c_int, c_p]
+    lib.oracle_apply_gate.argtypes = [c_int, c_p, c_p, c_int, c_p, c_p]
     lib.oracle_inner.argtypes = [c_int, c_p, c_p, c_p]
     lib.oracle_inner.restype = None
     _lib = lib
@@ -69,26 +69,34 @@ def _ptr(a: Optional[np.ndarray]):
     return None if a is None else ctypes.c_void_p(a.ctypes.data)
 
 
+def _strings(strings, n):
+    """The Pauli-string table of kind-8 gates as contiguous uint8 (n letters per string)."""
+    if strings is None:
+        return None
+    return np.ascontiguousarray(np.asarray(strings, dtype=np.uint8).reshape(-1, n))
+
+
 def _prep(problem):
     gates = np.ascontiguousarray(problem.gates, dtype=np.int32)
     theta = np.ascontiguousarray(problem.theta, dtype=np.float64)
     ins = None if problem.in_state is None else np.ascontiguousarray(problem.in_state, dtype=np.complex128)
-    return gates, theta, ins
+    return gates, theta, ins, _strings(getattr(problem, "strings", None), problem.n_qubits)
 
 
 def forward(problem) -> np.ndarray:
     """psi = U|in>, every gate in list order."""
     lib = _load()
-    gates, theta, ins = _prep(problem)
+    gates, theta, ins, strings = _prep(problem)
     out = np.empty(2 ** problem.n_qubits, dtype=np.complex128)
-    lib.oracle_forward(problem.n_qubits, gates.shape[0], _ptr(gates), _ptr(theta), _ptr(ins), _ptr(out))
+    lib.oracle_forward(problem.n_qubits, gates.shape[0], _ptr(gates), _ptr(theta), _ptr(ins), _ptr(out),
+                       _ptr(strings))
     return out
 
 
 def derivative_states(problem, sel: Optional[Sequence[int]] = None):
     """(D, psi): D[a] = d psi / d theta_{sel[a]} (rolling-prefix derivative states)."""
     lib = _load()
-    gates, theta, ins = _prep(problem)
+    gates, theta, ins, strings = _prep(problem)
     if sel is None:
         sel = range(problem.n_params)
     sel = np.ascontiguousarray(np.asarray(list(sel), dtype=np.int32))
@@ -96,7 +104,7 @@ def derivative_states(problem, sel: Optional[Sequence[int]] = None):
     D = np.empty((sel.shape[0], dim), dtype=np.complex128)
     psi = np.empty(dim, dtype=np.complex128)
     rc = lib.oracle_derivative_states(problem.n_qubits, gates.shape[0], _ptr(gates), _ptr(theta), _ptr(ins),
-                                      sel.shape[0], _ptr(sel), _ptr(D), _ptr(psi))
+                                      sel.shape[0], _ptr(sel), _ptr(D), _ptr(psi), _ptr(strings))
     if rc != 0:
         raise ValueError(f"oracle_derivative_states failed ({rc})")
     return D, psi
@@ -157,13 +165,14 @@ def step(problem):
     return {"G": G, "T": T, "E": E, "grad": grad, "dtheta": dtheta, "psi": psi}
 
 
-def apply_gate(n: int, gate, theta, psi: np.ndarray, derivative: bool = False) -> np.ndarray:
+def apply_gate(n: int, gate, theta, psi: np.ndarray, derivative: bool = False, strings=None) -> np.ndarray:
     """One gate row applied to a copy of psi (used by convention tests)."""
     lib = _load()
     g = np.ascontiguousarray(np.asarray(gate, dtype=np.int32))
     th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
     out = np.ascontiguousarray(psi, dtype=np.complex128).copy()
-    lib.oracle_apply_gate(n, _ptr(g), _ptr(th), int(derivative), _ptr(out))
+    st = _strings(strings, n)
+    lib.oracle_apply_gate(n, _ptr(g), _ptr(th), int(derivative), _ptr(out), _ptr(st))
     return out
 
 

@@ -12,6 +12,9 @@ real sizes, which makes it a good independent check at n <= 4.
   basis states;
 * controlled rotations (kinds 5/6/7, control q0, target q1): |0><0| (x) I +
   |1><1| (x) R on (control, target); derivative |1><1| (x) (i/2) sigma R;
+* Pauli-string rotations (kind 8, string q0 of the problem's table): scipy's
+  matrix exponential of +i theta S / 2 for the dense string S; derivative
+  (i/2) S R;
 * G, T from the definition (Sec. 1), E = <psi|H|psi>, grad E by its
   definition as a vector of partial derivatives of <E> (Sec. 1).
 """
@@ -39,9 +42,13 @@ def embed_1q(n: int, q: int, m: np.ndarray) -> np.ndarray:
     return out
 
 
-def gate_unitary(n: int, gate, theta, derivative: bool = False) -> np.ndarray:
+def gate_unitary(n: int, gate, theta, derivative: bool = False, strings=None) -> np.ndarray:
     kind, q0, q1, p = (int(v) for v in gate)
     dim = 2 ** n
+    if kind == 8:   # Pauli-string rotation
+        s = pauli_string(n, np.asarray(strings).reshape(-1, n)[q0])
+        r = scipy.linalg.expm(0.5j * float(theta[p]) * s)
+        return 0.5j * s @ r if derivative else r
     if kind == 3:   # CNOT control q0 target q1
         m = np.zeros((dim, dim), dtype=np.complex128)
         for x in range(dim):
@@ -88,7 +95,8 @@ def unitary(problem, deriv_param: int = -1) -> np.ndarray:
     n = problem.n_qubits
     u = np.eye(2 ** n, dtype=np.complex128)
     for g in problem.gates:
-        u = gate_unitary(n, g, problem.theta, derivative=(int(g[3]) == deriv_param and deriv_param >= 0)) @ u
+        u = gate_unitary(n, g, problem.theta, derivative=(int(g[3]) == deriv_param and deriv_param >= 0),
+                         strings=getattr(problem, "strings", None)) @ u
     return u
 
 

@@ -35,7 +35,11 @@
  * kind 0/1/2 = RX/RY/RZ on q0, 3 = CNOT (control q0, target q1), 4 = CZ,
  * 5/6/7 = controlled RX/RY/RZ (control q0, target q1): the rotation acts on the
  * target where the control is 1, the identity where it is 0, so its derivative
- * is the rotation's derivative where the control is 1 and zero where it is 0.
+ * is the rotation's derivative where the control is 1 and zero where it is 0,
+ * 8 = Pauli-string rotation exp(i theta S/2) with S the tensor product of the
+ * letters strings[q0*n + q] (0..3 = I, X, Y, Z on qubit q), q1 = -1; since
+ * S^2 = 1 it equals cos(theta/2) + i sin(theta/2) S and its derivative is
+ * (i/2) S exp(i theta S/2) (Sec. 2, Pauli-string generators).
  *
  * Loops over amplitudes may run on several OpenMP threads; every amplitude is
  * written by exactly one iteration, so the result does not depend on the
@@ -51,7 +55,7 @@
 typedef double complex cplx;
 
 enum { OR_KIND_RX = 0, OR_KIND_RY = 1, OR_KIND_RZ = 2, OR_KIND_CNOT = 3, OR_KIND_CZ = 4,
-       OR_KIND_CRX = 5, OR_KIND_CRY = 6, OR_KIND_CRZ = 7 };
+       OR_KIND_CRX = 5, OR_KIND_CRY = 6, OR_KIND_CRZ = 7, OR_KIND_RPAULI = 8 };
 
 /* Pauli matrix of a rotation kind, row-major [[s0, s1], [s2, s3]]. */
 static void or_pauli_of_kind(int kind, cplx s[4])
@@ -143,10 +147,61 @@ static void or_apply_cz(cplx *psi, int n, int a, int b)
         if ((i & ab) && (i & bb)) psi[i] = -psi[i];
 }
 
-/* Apply gate row g; if derivative != 0 the rotation is replaced by dR/dtheta. */
-static void or_apply_gate(cplx *psi, int n, const int32_t *g, const double *theta, int derivative)
+/*
+ * out (+)= factor * S psi for the Pauli string S with letters p[0..n) (p[q]
+ * acts on qubit q, 0..3 = I, X, Y, Z).  A Pauli string has one nonzero entry
+ * per row: row y picks column x (X and Y flip bit q, I and Z keep it) with a
+ * factor that is the product over qubits of the letter's matrix entry
+ * <y_q|letter|x_q>: X gives 1, Y gives -i for y_q = 0 and +i for y_q = 1
+ * (Y|0> = i|1>, Y|1> = -i|0>), Z gives (-1)^{y_q}.
+ */
+static void or_add_string(int n, const uint8_t *p, cplx factor0, const cplx *psi, cplx *out)
+{
+    const int64_t dim = (int64_t)1 << n;
+#pragma omp parallel for schedule(static)
+    for (int64_t y = 0; y < dim; ++y) {
+        int64_t x = y;
+        cplx factor = factor0;
+        for (int q = 0; q < n; ++q) {
+            const int64_t bit = (int64_t)1 << q;
+            switch (p[q]) {
+            case 1: x ^= bit; break;                              /* X|b> = |1-b> */
+            case 2: x ^= bit; factor *= (x & bit) ? -I : I; break; /* Y|0>=i|1>, Y|1>=-i|0> */
+            case 3: if (y & bit) factor = -factor; break;         /* Z|1> = -|1> */
+            default: break;
+            }
+        }
+        out[y] += factor * psi[x];
+    }
+}
+
+/* Pauli-string rotation: psi <- cos(t/2) psi + i sin(t/2) S psi; derivative:
+ * then psi <- (i/2) S psi. */
+static void or_apply_string_rotation(cplx *psi, int n, const uint8_t *p, double t, int derivative)
+{
+    const int64_t dim = (int64_t)1 << n;
+    cplx *tmp = (cplx *)malloc((size_t)dim * sizeof(cplx));
+    memcpy(tmp, psi, (size_t)dim * sizeof(cplx));
+    for (int64_t x = 0; x < dim; ++x) psi[x] *= cos(0.5 * t);
+    or_add_string(n, p, I * sin(0.5 * t), tmp, psi);
+    if (derivative) {
+        memset(tmp, 0, (size_t)dim * sizeof(cplx));
+        or_add_string(n, p, 0.5 * I, psi, tmp);
+        memcpy(psi, tmp, (size_t)dim * sizeof(cplx));
+    }
+    free(tmp);
+}
+
+/* Apply gate row g; if derivative != 0 the rotation is replaced by dR/dtheta.
+ * strings: the Pauli-string table of kind-8 gates (n letters per string). */
+static void or_apply_gate(cplx *psi, int n, const int32_t *g, const double *theta, int derivative,
+                          const uint8_t *strings)
 {
     const int kind = g[0];
+    if (kind == OR_KIND_RPAULI) {
+        or_apply_string_rotation(psi, n, strings + (int64_t)g[1] * n, theta[g[3]], derivative);
+        return;
+    }
     if (kind == OR_KIND_CNOT) { or_apply_cnot(psi, n, g[1], g[2]); return; }
     if (kind == OR_KIND_CZ)   { or_apply_cz(psi, n, g[1], g[2]); return; }
     const int controlled = kind >= OR_KIND_CRX;
@@ -169,10 +224,10 @@ static void or_load_input(cplx *psi, int n, const cplx *in_state)
 
 /* Ansatz state: every gate applied to |in> in list order.  Returns 0. */
 int oracle_forward(int n, int n_gates, const int32_t *gates, const double *theta,
-                   const cplx *in_state, cplx *out)
+                   const cplx *in_state, cplx *out, const uint8_t *strings)
 {
     or_load_input(out, n, in_state);
-    for (int k = 0; k < n_gates; ++k) or_apply_gate(out, n, gates + 4 * k, theta, 0);
+    for (int k = 0; k < n_gates; ++k) or_apply_gate(out, n, gates + 4 * k, theta, 0, strings);
     return 0;
 }
 
@@ -188,7 +243,7 @@ int oracle_forward(int n, int n_gates, const int32_t *gates, const double *theta
  */
 int oracle_derivative_states(int n, int n_gates, const int32_t *gates, const double *theta,
                              const cplx *in_state, int n_sel, const int32_t *sel,
-                             cplx *out, cplx *psi_out)
+                             cplx *out, cplx *psi_out, const uint8_t *strings)
 {
     const int64_t dim = (int64_t)1 << n;
     cplx *prefix = (cplx *)malloc((size_t)dim * sizeof(cplx));
@@ -204,14 +259,14 @@ int oracle_derivative_states(int n, int n_gates, const int32_t *gates, const dou
                 cplx *d = out + (int64_t)a * dim;
                 cplx *t = seen[a] ? term : d;
                 memcpy(t, prefix, (size_t)dim * sizeof(cplx));
-                or_apply_gate(t, n, g, theta, 1);
-                for (int k2 = k + 1; k2 < n_gates; ++k2) or_apply_gate(t, n, gates + 4 * k2, theta, 0);
+                or_apply_gate(t, n, g, theta, 1, strings);
+                for (int k2 = k + 1; k2 < n_gates; ++k2) or_apply_gate(t, n, gates + 4 * k2, theta, 0, strings);
                 if (seen[a])
                     for (int64_t x = 0; x < dim; ++x) d[x] += term[x];
                 seen[a] = 1;
             }
         }
-        or_apply_gate(prefix, n, g, theta, 0);
+        or_apply_gate(prefix, n, g, theta, 0, strings);
     }
     if (psi_out) memcpy(psi_out, prefix, (size_t)dim * sizeof(cplx));
     int missing = 0;
@@ -224,36 +279,14 @@ int oracle_derivative_states(int n, int n_gates, const int32_t *gates, const dou
 
 /*
  * out = H psi with H = sum_t coeff[t] * (Pauli string t); pauli[t*n + q] in
- * {0=I, 1=X, 2=Y, 3=Z} acts on qubit q.  A Pauli string has one nonzero entry
- * per row: row y of the string picks column x (X and Y flip bit q, I and Z keep
- * it) with a factor that is the product over qubits of the letter's matrix
- * entry <y_q|letter|x_q>: X gives 1, Y gives -i for y_q = 0 and +i for y_q = 1
- * (Y|0> = i|1>, Y|1> = -i|0>), Z gives (-1)^{y_q}.
+ * {0=I, 1=X, 2=Y, 3=Z} acts on qubit q.
  */
 int oracle_apply_pauli_sum(int n, int n_terms, const uint8_t *pauli, const double *coeff,
                            const cplx *psi, cplx *out)
 {
     const int64_t dim = (int64_t)1 << n;
     memset(out, 0, (size_t)dim * sizeof(cplx));
-    for (int t = 0; t < n_terms; ++t) {
-        const uint8_t *p = pauli + (int64_t)t * n;
-#pragma omp parallel for schedule(static)
-        for (int64_t y = 0; y < dim; ++y) {
-            /* find the basis state x that this string maps onto y, and the factor */
-            int64_t x = y;
-            cplx factor = coeff[t];
-            for (int q = 0; q < n; ++q) {
-                const int64_t bit = (int64_t)1 << q;
-                switch (p[q]) {
-                case 1: x ^= bit; break;                              /* X|b> = |1-b> */
-                case 2: x ^= bit; factor *= (x & bit) ? -I : I; break; /* Y|0>=i|1>, Y|1>=-i|0> */
-                case 3: if (y & bit) factor = -factor; break;         /* Z|1> = -|1> */
-                default: break;
-                }
-            }
-            out[y] += factor * psi[x];
-        }
-    }
+    for (int t = 0; t < n_terms; ++t) or_add_string(n, pauli + (int64_t)t * n, coeff[t], psi, out);
     return 0;
 }
 
@@ -268,9 +301,10 @@ int oracle_apply_pauli_letter(int n, int q, int letter, cplx *psi)
 }
 
 /* Apply one gate row (rotation, or its derivative if derivative != 0). */
-int oracle_apply_gate(int n, const int32_t *gate, const double *theta, int derivative, cplx *psi)
+int oracle_apply_gate(int n, const int32_t *gate, const double *theta, int derivative, cplx *psi,
+                      const uint8_t *strings)
 {
-    or_apply_gate(psi, n, gate, theta, derivative);
+    or_apply_gate(psi, n, gate, theta, derivative, strings);
     return 0;
 }
 

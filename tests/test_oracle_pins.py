@@ -514,3 +514,94 @@ def test_each_element_prepared_independently(make):
     G, To = oracle.metric(pr)
     np.testing.assert_allclose(To, T, atol=1e-14)
     np.testing.assert_allclose(G, L - np.outer(T.conj(), T), atol=1e-14)
+
+
+# ------------------------------------------------------ Pauli-string rotations
+
+def test_string_rotation_on_basis_states():
+    """exp(i t S/2) for multi-qubit strings (identity letters included) against
+    scipy's matrix exponential of the dense string, and its derivative
+    (i/2) S exp(i t S/2), on every basis state."""
+    rng = np.random.default_rng(61)
+    table = np.array([[1, 0, 3], [2, 2, 0], [3, 1, 2], [0, 0, 0], [3, 3, 3]], dtype=np.uint8)
+    for k in range(table.shape[0]):
+        th = rng.uniform(0, 2 * np.pi, size=1)
+        for deriv in (False, True):
+            u = dense.gate_unitary(3, (W.RPAULI, k, -1, 0), th, derivative=deriv, strings=table)
+            for x in range(8):
+                e = np.zeros(8, dtype=np.complex128)
+                e[x] = 1
+                got = oracle.apply_gate(3, (W.RPAULI, k, -1, 0), th, e, derivative=deriv, strings=table)
+                np.testing.assert_allclose(got, u[:, x], atol=1e-15)
+
+
+def test_single_letter_string_is_the_plain_rotation():
+    rng = np.random.default_rng(62)
+    psi = W.random_state(3, 63)
+    for letter, kind in ((1, W.RX), (2, W.RY), (3, W.RZ)):
+        for q in range(3):
+            table = np.zeros((1, 3), dtype=np.uint8)
+            table[0, q] = letter
+            th = rng.uniform(0, 2 * np.pi, size=1)
+            for deriv in (False, True):
+                a = oracle.apply_gate(3, (W.RPAULI, 0, -1, 0), th, psi, derivative=deriv, strings=table)
+                b = oracle.apply_gate(3, (kind, q, -1, 0), th, psi, derivative=deriv)
+                np.testing.assert_allclose(a, b, atol=1e-15)
+
+
+def test_string_closed_forms():
+    """ZZ rotation on cos a|x=0> + sin a|x=2> (ZZ eigenvalues +1, -1): <S> =
+    cos 2a, so T = (i/2) cos 2a and G = (1 - cos^2 2a)/4; the X^{(x)3} rotation
+    on |000>: psi = cos(t/2)|000> + i sin(t/2)|111>, so with H = Z_0,
+    E = cos t and dE/dt = -sin t."""
+    table = np.array([[3, 3]], dtype=np.uint8)
+    for a in (0.2, 0.7, 1.3):
+        ins = np.zeros(4, dtype=np.complex128)
+        ins[0], ins[2] = math.cos(a), math.sin(a)
+        pr = _problem(2, [[W.RPAULI, 0, -1, 0]], [1.1], in_state=ins)
+        pr.strings = table
+        G, T = oracle.metric(pr)
+        np.testing.assert_allclose(G, [[(1 - math.cos(2 * a) ** 2) / 4]], atol=1e-15)
+        np.testing.assert_allclose(T, [0.5j * math.cos(2 * a)], atol=1e-15)
+    for t in (0.4, 2.5):
+        pr = _problem(3, [[W.RPAULI, 0, -1, 0]], [t], pauli=[[3, 0, 0]], coeff=[1.0])
+        pr.strings = np.array([[1, 1, 1]], dtype=np.uint8)
+        E, g = oracle.energy_grad(pr)
+        np.testing.assert_allclose([E, g[0]], [math.cos(t), -math.sin(t)], atol=1e-14)
+
+
+@pytest.mark.parametrize("n,ngates,seed", [(2, 10, 461), (3, 18, 462), (4, 26, 463), (4, 16, 464)])
+def test_string_oracle_matches_dense_brute_force(n, ngates, seed):
+    pr = W.string_circuit(n, ngates, seed, n_terms=6)
+    if seed % 2 == 0:
+        pr.in_state = W.random_state(n, seed + 100)
+    bf = dense.brute_force(pr)
+    st = oracle.step(pr)
+    np.testing.assert_allclose(st["psi"], bf["psi"], atol=1e-13)
+    np.testing.assert_allclose(st["G"], bf["G"], atol=1e-13)
+    np.testing.assert_allclose(st["T"], bf["T"], atol=1e-13)
+    assert abs(st["E"] - bf["E"]) < 1e-12
+    np.testing.assert_allclose(st["grad"], bf["grad"], atol=1e-12)
+
+
+def test_string_gradient_two_term_shift_and_derivatives():
+    """A Pauli string has eigenvalues +-1, so the two-term shift rule is exact
+    for its angle; derivative states against central differences."""
+    pr = W.string_layers(4, 2, 7, 471)
+    E, grad = oracle.energy_grad(pr)
+    for p in range(pr.n_params):
+        vals = []
+        for s_ in (+1, -1):
+            th = pr.theta.copy()
+            th[p] += s_ * np.pi / 2
+            vals.append(oracle.energy(W.Problem(**{**pr.__dict__, "theta": th})))
+        assert abs(0.5 * (vals[0] - vals[1]) - grad[p]) < 1e-12
+    D, _ = oracle.derivative_states(pr)
+    h = 1e-5
+    for a in range(pr.n_params):
+        tp, tm = pr.theta.copy(), pr.theta.copy()
+        tp[a] += h
+        tm[a] -= h
+        fd = (oracle.forward(W.Problem(**{**pr.__dict__, "theta": tp}))
+              - oracle.forward(W.Problem(**{**pr.__dict__, "theta": tm}))) / (2 * h)
+        assert np.abs(D[a] - fd).max() < h * h / 6 / 8 + 1e-9

@@ -20,7 +20,9 @@ Gate encoding (one row per gate, int32): ``(kind, q0, q1, param)``
 * kind 3 = CNOT with control q0 and target q1;
 * kind 4 = CZ on qubits q0, q1;
 * kind 5/6/7 = controlled RX/RY/RZ with control q0 and target q1 (the rotation
-  acts on the target where the control is 1; Sec. 2, controlled rotations).
+  acts on the target where the control is 1; Sec. 2, controlled rotations);
+* kind 8 = Pauli-string rotation exp(+i theta S/2), S = the tensor product of
+  the letters ``strings[q0]`` (one letter per qubit, 0..3 = I, X, Y, Z), q1 = -1.
 
 Qubit q is bit q of the amplitude index (qubit 0 is the least significant bit).
 Pauli letters are 0=I, 1=X, 2=Y, 3=Z, stored row-major as ``pauli[t, q]``.
@@ -39,7 +41,9 @@ import numpy as np
 
 RX, RY, RZ, CNOT, CZ = 0, 1, 2, 3, 4
 CRX, CRY, CRZ = 5, 6, 7                 # controlled rotations: control q0, target q1
-KIND_NAMES = {RX: "RX", RY: "RY", RZ: "RZ", CNOT: "CNOT", CZ: "CZ", CRX: "CRX", CRY: "CRY", CRZ: "CRZ"}
+RPAULI = 8                              # Pauli-string rotation: q0 = row of Problem.strings
+KIND_NAMES = {RX: "RX", RY: "RY", RZ: "RZ", CNOT: "CNOT", CZ: "CZ", CRX: "CRX", CRY: "CRY", CRZ: "CRZ",
+              RPAULI: "RPAULI"}
 ROTATION_KINDS = (RX, RY, RZ)
 
 
@@ -57,6 +61,7 @@ class Problem:
     dt: float = 0.1
     tikhonov: float = 1e-4
     seed: int = 0
+    strings: Optional[np.ndarray] = None    # (k, n) uint8: letters of the kind-8 gates' Pauli strings
 
     @property
     def n_params(self) -> int:
@@ -303,6 +308,71 @@ def controlled_layers(n: int, layers: int, n_terms: int, seed: int, dt: float = 
     theta, pauli, coeff = draw_problem_data(seed, p, n, n_terms)
     return Problem(name=f"controlled_layers_n{n}_L{layers}", n_qubits=n, gates=gates, theta=theta,
                    pauli=pauli, coeff=coeff, dt=dt, tikhonov=tikhonov, seed=seed)
+
+
+def string_circuit(n: int, n_gates: int, seed: int, string_fraction: float = 0.4,
+                   fixed_fraction: float = 0.2, max_support: int = 4, n_terms: int = 6) -> Problem:
+    """A random gate list with Pauli-string rotations among the other kinds.
+
+    Each gate is, in this order of draws from a second stream (seed + 1): a
+    fixed gate (CNOT/CZ) with probability ``fixed_fraction``, else a
+    Pauli-string rotation with probability ``string_fraction`` -- its support
+    is a random set of 1..min(n, max_support) qubits, each carrying a letter
+    drawn from {X, Y, Z}, and it adds a row to ``strings`` -- else a plain
+    rotation.  Angles and Hamiltonian follow the documented draw order.
+    """
+    srng = np.random.Generator(np.random.PCG64(seed + 1))
+    rows, strings = [], []
+    p = 0
+    for _ in range(n_gates):
+        u = srng.uniform()
+        if n >= 2 and u < fixed_fraction:
+            kind = int(srng.integers(CNOT, CZ + 1))
+            a, b = srng.choice(n, size=2, replace=False)
+            rows.append([kind, int(a), int(b), -1])
+        elif u < fixed_fraction + string_fraction:
+            k = int(srng.integers(1, min(n, max_support) + 1))
+            support = srng.choice(n, size=k, replace=False)
+            letters = np.zeros(n, dtype=np.uint8)
+            letters[support] = srng.integers(1, 4, size=k)
+            rows.append([RPAULI, len(strings), -1, p])
+            strings.append(letters)
+            p += 1
+        else:
+            rows.append([int(srng.integers(RX, RZ + 1)), int(srng.integers(0, n)), -1, p])
+            p += 1
+    gates = np.asarray(rows, dtype=np.int32).reshape(-1, 4)
+    theta, pauli, coeff = draw_problem_data(seed, p, n, n_terms)
+    table = np.asarray(strings, dtype=np.uint8).reshape(-1, n)
+    return Problem(name=f"strings_n{n}_g{n_gates}_s{seed}", n_qubits=n, gates=gates, theta=theta, pauli=pauli,
+                   coeff=coeff, seed=seed, strings=table)
+
+
+def string_layers(n: int, layers: int, n_terms: int, seed: int, dt: float = 0.1, tikhonov: float = 1e-4) -> Problem:
+    """Layers of [RX on every qubit, then ZZ rotations exp(i t Z_q Z_{q+1}/2) for
+    q = 0..n-2, then one rotation about X Y ... Y X on every qubit (X at both
+    ends)]: P = layers * 2n.  Angles and Hamiltonian in the documented draw order."""
+    strings = []
+    for q in range(n - 1):
+        s_ = np.zeros(n, dtype=np.uint8)
+        s_[q] = s_[q + 1] = 3
+        strings.append(s_)
+    ladder = np.full(n, 2, dtype=np.uint8)
+    ladder[0] = ladder[n - 1] = 1
+    strings.append(ladder)
+    rows: List[List[int]] = []
+    p = 0
+    for _ in range(layers):
+        for q in range(n):
+            rows.append([RX, q, -1, p])
+            p += 1
+        for k in range(n):
+            rows.append([RPAULI, k, -1, p])
+            p += 1
+    gates = np.asarray(rows, dtype=np.int32).reshape(-1, 4)
+    theta, pauli, coeff = draw_problem_data(seed, p, n, n_terms)
+    return Problem(name=f"string_layers_n{n}_L{layers}", n_qubits=n, gates=gates, theta=theta, pauli=pauli,
+                   coeff=coeff, dt=dt, tikhonov=tikhonov, seed=seed, strings=np.asarray(strings, dtype=np.uint8))
 
 
 def random_state(n: int, seed: int) -> np.ndarray:
