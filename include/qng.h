@@ -69,7 +69,8 @@ typedef enum {
 
 typedef enum {
     QNG_RX = 0, QNG_RY = 1, QNG_RZ = 2, QNG_CNOT = 3, QNG_CZ = 4,
-    QNG_CRX = 5, QNG_CRY = 6, QNG_CRZ = 7   /* controlled rotations (Sec. 2, the controlled-rotation diagonal) */
+    QNG_CRX = 5, QNG_CRY = 6, QNG_CRZ = 7,  /* controlled rotations (Sec. 2, the controlled-rotation diagonal) */
+    QNG_RPAULI = 8                          /* Pauli-string rotation (Sec. 2, single-Pauli-string gates) */
 } qng_gate_kind;
 
 /* Storage precision of the state vectors.  QNG_C64 keeps states and gate
@@ -83,21 +84,31 @@ typedef enum { QNG_C128 = 0, QNG_C64 = 1 } qng_precision;
  * q1 = target (q0 != q1), param >= 0; the gate is |0><0| (x) 1 + |1><1| (x)
  * exp(i theta sigma/2), so its column of G has the generator |1><1| (x) sigma
  * and the diagonal L_ii = 1/4 Prob(control = 1) instead of 1/4 (Sec. 2).
- * Circuits with controlled rotations run on the per-primitive kernels whatever
- * QNG_OPT_FUSION says; qng_plan with fusion, qng_plan_export and
- * qng_step_batched reject them with QNG_E_UNSUPPORTED.
+ * Pauli-string rotations (RPAULI): q0 = index of the string in the circuit's
+ * table (0 <= q0 < n_strings), q1 = -1, param >= 0; the gate is
+ * exp(i theta S/2) = cos(theta/2) + i sin(theta/2) S for the tensor product S
+ * of the string's letters, so its column has the generator S and, as S^2 = 1,
+ * the diagonal L_ii = 1/4.
+ * Circuits with controlled or Pauli-string rotations run on the per-primitive
+ * kernels whatever QNG_OPT_FUSION says; qng_plan with fusion, qng_plan_export
+ * and qng_step_batched reject them with QNG_E_UNSUPPORTED.
  * Gates act in array order: gates[0] first. */
 typedef struct { int32_t kind, q0, q1, param; } qng_gate;
 
 /* An ansatz: parameterised rotations whose param fields lie in
  * 0..n_params-1, each parameter carried by at least one rotation (one unique
  * parameter per gate, Sec. 2, when they form a permutation; otherwise shared
- * parameters, see above), plus any number of fixed CNOT/CZ gates. */
+ * parameters, see above), plus any number of fixed CNOT/CZ gates.
+ * strings: n_strings Pauli strings for RPAULI gates, n_qubits letters each,
+ * strings[k*n_qubits + q] in {0=I, 1=X, 2=Y, 3=Z} acting on qubit q (host
+ * pointer; may be NULL when n_strings = 0, which zero-initialised structs give). */
 typedef struct {
     int32_t n_qubits;
     int32_t n_gates;
     int32_t n_params;
     const qng_gate *gates;
+    int32_t n_strings;
+    const uint8_t *strings;
 } qng_circuit;
 
 /* H = sum_t coeff[t] * (Pauli string t); pauli[t*n_qubits + q] in

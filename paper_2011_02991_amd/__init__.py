@@ -8,7 +8,8 @@ library is missing, importing the binding raises: there is no fallback.
 Problems are described the way the library's C ABI describes them: a gate
 list of rows (kind, q0, q1, param) with kind 0/1/2 = RX/RY/RZ (rotation
 exp(+i theta sigma/2)), 3 = CNOT (control q0, target q1), 4 = CZ, 5/6/7 =
-controlled RX/RY/RZ (control q0, target q1); a vector of
+controlled RX/RY/RZ (control q0, target q1), 8 = Pauli-string rotation (q0 =
+row of a table of letters per qubit); a vector of
 angles indexed by parameter; a Pauli-sum Hamiltonian (letters 0..3 = I, X, Y, Z
 per qubit, real coefficients); an optional complex128 input state.
 """
@@ -49,7 +50,7 @@ class _Gate(ctypes.Structure):
 
 class _Circuit(ctypes.Structure):
     _fields_ = [("n_qubits", ctypes.c_int32), ("n_gates", ctypes.c_int32), ("n_params", ctypes.c_int32),
-                ("gates", ctypes.c_void_p)]
+                ("gates", ctypes.c_void_p), ("n_strings", ctypes.c_int32), ("strings", ctypes.c_void_p)]
 
 
 class _PauliSum(ctypes.Structure):
@@ -148,12 +149,17 @@ def _prec(p) -> int:
 class Circuit:
     """Marshalled circuit (+ optional Hamiltonian) kept alive for the C calls."""
 
-    def __init__(self, n_qubits: int, gates, n_params: Optional[int] = None, pauli=None, coeff=None):
+    def __init__(self, n_qubits: int, gates, n_params: Optional[int] = None, pauli=None, coeff=None,
+                 strings=None):
         self.gates = np.ascontiguousarray(np.asarray(gates, dtype=np.int32).reshape(-1, 4))
         self.n_qubits = int(n_qubits)
         self.n_params = int((self.gates[:, 3] >= 0).sum()) if n_params is None else int(n_params)
+        # letters of the Pauli-string rotations (kind 8): one row of n_qubits per string
+        self.strings = (np.zeros((0, self.n_qubits), dtype=np.uint8) if strings is None else
+                        np.ascontiguousarray(np.asarray(strings, dtype=np.uint8).reshape(-1, self.n_qubits)))
         self.c = _Circuit(self.n_qubits, self.gates.shape[0], self.n_params,
-                          self.gates.ctypes.data if self.gates.size else None)
+                          self.gates.ctypes.data if self.gates.size else None, self.strings.shape[0],
+                          self.strings.ctypes.data if self.strings.size else None)
         self.h = None
         if pauli is not None:
             self.pauli = np.ascontiguousarray(np.asarray(pauli, dtype=np.uint8).reshape(-1, self.n_qubits))
@@ -163,7 +169,7 @@ class Circuit:
 
     @classmethod
     def from_problem(cls, pr) -> "Circuit":
-        return cls(pr.n_qubits, pr.gates, pr.n_params, pr.pauli, pr.coeff)
+        return cls(pr.n_qubits, pr.gates, pr.n_params, pr.pauli, pr.coeff, getattr(pr, "strings", None))
 
     @property
     def cref(self):

@@ -262,6 +262,23 @@ void apply_metric_settings(const qng_ctx *ctx, Problem &p) {
     }
 }
 
+// Gate `pos` of a problem (or its adjoint) on one register or two.  A
+// Pauli-string rotation's fwd/adj hold cos(theta/2) on the diagonal and
+// +-i sin(theta/2) off it (the RX matrix of its angle), i.e. c + (i s) S.
+template <typename R>
+void apply_gate(const Problem &pb, int pos, bool adjoint_gate, void *s0, void *s1, hipStream_t st) {
+    const qng_gate &g = pb.circ.gates[pos];
+    const int n = pb.circ.n;
+    const Mat2 &mm = adjoint_gate ? pb.adj[pos] : pb.fwd[pos];
+    if (g.kind == QNG_CNOT) launch_cnot<R>(s0, s1, n, g.q0, g.q1, st);
+    else if (g.kind == QNG_CZ) launch_cz<R>(s0, s1, n, g.q0, g.q1, st);
+    else if (g.kind == QNG_RPAULI) {
+        const Rot &r = pb.circ.rots[pb.circ.rot_at[pos]];
+        launch_apply_string<R>(s0, s1, n, r.flip, r.zy, r.n_y, mm.a.real(), mm.b.real(), mm.b.imag(), st);
+    } else if (g.kind >= QNG_CRX) launch_apply_c1q<R>(s0, s1, n, g.q0, g.q1, dev(mm), st);
+    else launch_apply_1q<R>(s0, s1, n, g.q0, dev(mm), st);
+}
+
 template <typename R> struct Engine {
     qng_ctx *ctx;
     const Problem &pb;
@@ -290,19 +307,28 @@ template <typename R> struct Engine {
     double *eraw() const { return eraw_; }
 
     void apply(int pos, bool adjoint_gate, void *s0, void *s1) {
-        const qng_gate &g = pb.circ.gates[pos];
         ++ctx->stats.other_launches;
-        const DevMat2 m = dev(adjoint_gate ? pb.adj[pos] : pb.fwd[pos]);
-        if (g.kind == QNG_CNOT) launch_cnot<R>(s0, s1, n, g.q0, g.q1, st);
-        else if (g.kind == QNG_CZ) launch_cz<R>(s0, s1, n, g.q0, g.q1, st);
-        else if (g.kind >= QNG_CRX) launch_apply_c1q<R>(s0, s1, n, g.q0, g.q1, m, st);
-        else launch_apply_1q<R>(s0, s1, n, g.q0, m, st);
+        apply_gate<R>(pb, pos, adjoint_gate, s0, s1, st);
     }
 
     // <a| K |b> with K = sigma_q, or |1><1|_ctrl (x) sigma_q for ctrl >= 0
     void prod(const void *a, const void *b, int q, int axis, double *dest, int ctrl = -1) {
         ctx->stats.other_launches += 2;
         launch_pauli_prod<R>(a, b, n, q, axis, partials(), dest, st, ctrl);
+    }
+
+    // <a| K_r |b> for the generator K_r of rotation r
+    void rprod(const void *a, const void *b, const Rot &r, double *dest) {
+        if (r.string < 0) return prod(a, b, r.qubit, r.axis, dest, r.ctrl);
+        ctx->stats.other_launches += 2;
+        launch_string_prod<R>(a, b, n, r.flip, r.zy, r.n_y, partials(), dest, st);
+    }
+
+    // lam = y, phi = K_r y
+    void rseed(const void *y, void *lam, void *phi, const Rot &r) {
+        ++ctx->stats.other_launches;
+        if (r.string < 0) launch_seed<R>(y, lam, phi, n, r.qubit, r.axis, st, r.ctrl);
+        else launch_seed_string<R>(y, lam, phi, n, r.flip, r.zy, r.n_y, st);
     }
 
     // psi (state 0) <- |in>.  in_c128: device complex128 or nullptr.
@@ -321,11 +347,10 @@ template <typename R> struct Engine {
         for (int s = 0; s < c.P; ++s) {
             const Rot &rs = c.rots[s];
             for (; pos < rs.pos; ++pos) apply(pos, false, psi, nullptr);   // psi <- gates up to rotation s
-            prod(psi, psi, rs.qubit, rs.axis, traw() + 2 * s, rs.ctrl);     // <y_s|K_s|y_s>
+            rprod(psi, psi, rs, traw() + 2 * s);                             // <y_s|K_s|y_s>
             // controlled rotation: <y_s|K_s^2|y_s> = Prob(control = 1) on the diagonal (Sec. 2)
             if (rs.ctrl >= 0) prod(psi, psi, rs.ctrl, -1, lraw() + 2 * ((size_t)s * c.P + s), rs.ctrl);
             if (s == 0) continue;
-            ++ctx->stats.other_launches;
             // block-diagonal metric: the column stops at the lowest rotation of its block
             int lo = 0;
             if (!pb.rot_block.empty()) {
@@ -335,13 +360,13 @@ template <typename R> struct Engine {
                 if (lo < 0) continue;
             }
             const int plo = lo ? c.rots[lo].pos : p0;
-            launch_seed<R>(psi, lam, phi, n, rs.qubit, rs.axis, st, rs.ctrl);
+            rseed(psi, lam, phi, rs);
             for (int k = rs.pos - 1; k >= plo; --k) {
                 const int r = c.rot_at[k];
                 if (r >= 0) {
                     const Rot &rr = c.rots[r];
                     if (pb.rot_block.empty() || pb.rot_block[r] == pb.rot_block[s]) {
-                        prod(lam, phi, rr.qubit, rr.axis, lraw() + 2 * ((size_t)r * c.P + s), rr.ctrl);
+                        rprod(lam, phi, rr, lraw() + 2 * ((size_t)r * c.P + s));
                         ++ctx->stats.elements;
                     }
                     if (k > plo) apply(k, true, lam, phi);
@@ -374,7 +399,7 @@ template <typename R> struct Engine {
             const int r = c.rot_at[k];
             if (r >= 0) {
                 const Rot &rr = c.rots[r];
-                prod(lam, psi, rr.qubit, rr.axis, graw() + 2 * r, rr.ctrl);
+                rprod(lam, psi, rr, graw() + 2 * r);
                 if (k > p0) apply(k, true, lam, psi);
             } else {
                 apply(k, true, lam, psi);
@@ -449,9 +474,9 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
     const int n = c.n;
     const size_t amp = 2 * sizeof(R);
     const size_t V = (size_t(1) << n) * amp;
-    // controlled rotations: per-primitive kernels only (the fused passes
-    // implement plain rotations, CNOT and CZ)
-    const bool fused = ctx->opt_fusion != 0 && spec.metric && c.P > 1 && !c.controlled;
+    // controlled and Pauli-string rotations: per-primitive kernels only (the
+    // fused passes implement single-qubit rotations, CNOT and CZ)
+    const bool fused = ctx->opt_fusion != 0 && spec.metric && c.P > 1 && !c.extended();
     const SweepPlan *plan = nullptr;
     FusedRun fr;
     size_t scratch = 0;
@@ -471,7 +496,7 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
     }
     std::shared_ptr<const SweepPlan> gplan;
     const bool f64_regs = amp == 16 || ctx->opt_f64_regs;
-    if (ctx->opt_fusion != 0 && spec.grad && c.P > 0 && !c.controlled) {
+    if (ctx->opt_fusion != 0 && spec.grad && c.P > 0 && !c.extended()) {
         gplan = ctx->sweep_cache.get_gradient(c, ctx->opt_tile, (int)amp, f64_regs);
         scratch = std::max(scratch, fused_gradient_scratch_bytes(*gplan, c.M));
     }
@@ -1014,8 +1039,8 @@ qng_status qng_plan(const qng_circuit *circ, int fusion, int tile_qubits, qng_pl
         Circuit c = compile_circuit(circ);
         *out = qng_plan_info{};
         out->elements = (int64_t)c.P * (c.P - 1) / 2;
-        if (fusion && c.controlled)
-            fail(QNG_E_UNSUPPORTED, "fused sweep passes do not take controlled rotations");
+        if (fusion && c.extended())
+            fail(QNG_E_UNSUPPORTED, "fused sweep passes do not take controlled or Pauli-string rotations");
         if (!fusion) {
             for (int s = 1; s < c.P; ++s) out->ops += c.rots[s].pos - c.rots[0].pos + (s);
             out->passes = 0;
@@ -1034,7 +1059,8 @@ qng_status qng_plan_export(const qng_circuit *circ, int tile_qubits, int amp_byt
         if (sweep < 0 || sweep > 2) fail(QNG_E_INVALID_ARG, "sweep must be 0 or 2 (metric) or 1 (gradient)");
         validate_circuit(circ, kMaxQubitsC64);
         Circuit c = compile_circuit(circ);
-        if (c.controlled) fail(QNG_E_UNSUPPORTED, "fused sweep passes do not take controlled rotations");
+        if (c.extended())
+            fail(QNG_E_UNSUPPORTED, "fused sweep passes do not take controlled or Pauli-string rotations");
         SweepPlan plan = sweep == 1 ? build_gradient_plan(c, tile_qubits, amp_bytes, amp_bytes == 16)
                                     : build_sweep_plan(c, tile_qubits, amp_bytes, 1, amp_bytes == 16, sweep == 2 ? 2 : 1);
         int64_t k = 0;
@@ -1222,7 +1248,8 @@ qng_status qng_step_batched(qng_ctx *ctx, int32_t B, const qng_circuit *circs, c
                 validate_circuit(&circs[b], max_qubits(prec));
                 for (int k = 0; k < circs[b].n_gates; ++k)
                     if (circs[b].gates[k].kind >= QNG_CRX)
-                        fail(QNG_E_UNSUPPORTED, "controlled rotations are not available in qng_step_batched");
+                        fail(QNG_E_UNSUPPORTED,
+                             "controlled and Pauli-string rotations are not available in qng_step_batched");
                 validate_theta(&circs[b], thetas[b]);
                 validate_hamiltonian(&circs[b], &hams[b]);
                 if (circs[b].n_params > 0 && !dtheta_out[b]) fail(QNG_E_INVALID_ARG, "dtheta_out is NULL");
@@ -1393,17 +1420,9 @@ qng_status qng_apply_circuit_dev(qng_ctx *ctx, const qng_circuit *circ, const do
         validate_theta(circ, theta);
         if (!state_dev) fail(QNG_E_INVALID_ARG, "state_dev is NULL");
         Problem pb = make_problem(circ, theta, nullptr);
-        const int n = pb.circ.n;
         dispatch(prec, [&](auto tag) {
             using R = decltype(tag);
-            for (int pos = 0; pos < pb.circ.M; ++pos) {
-                const qng_gate &g = pb.circ.gates[pos];
-                if (g.kind == QNG_CNOT) launch_cnot<R>(state_dev, nullptr, n, g.q0, g.q1, ctx->stream);
-                else if (g.kind == QNG_CZ) launch_cz<R>(state_dev, nullptr, n, g.q0, g.q1, ctx->stream);
-                else if (g.kind >= QNG_CRX)
-                    launch_apply_c1q<R>(state_dev, nullptr, n, g.q0, g.q1, dev(pb.fwd[pos]), ctx->stream);
-                else launch_apply_1q<R>(state_dev, nullptr, n, g.q0, dev(pb.fwd[pos]), ctx->stream);
-            }
+            for (int pos = 0; pos < pb.circ.M; ++pos) apply_gate<R>(pb, pos, false, state_dev, nullptr, ctx->stream);
         });
     });
 }

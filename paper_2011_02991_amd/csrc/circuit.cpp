@@ -18,7 +18,12 @@ void validate_circuit(const qng_circuit *c, int max_qubits) {
     if (c->n_gates < 0) fail(QNG_E_BAD_CIRCUIT, "n_gates < 0");
     if (c->n_params < 0) fail(QNG_E_BAD_PARAMS, "n_params < 0");
     if (c->n_gates > 0 && !c->gates) fail(QNG_E_INVALID_ARG, "gates is NULL");
+    if (c->n_strings < 0) fail(QNG_E_BAD_CIRCUIT, "n_strings < 0");
+    if (c->n_strings > 0 && !c->strings) fail(QNG_E_INVALID_ARG, "strings is NULL");
     const int n = c->n_qubits;
+    for (int64_t k = 0; k < (int64_t)c->n_strings * n; ++k)
+        if (c->strings[k] > 3)
+            fail(QNG_E_BAD_CIRCUIT, "Pauli letter outside {0,1,2,3} in string " + std::to_string(k / n));
     std::vector<int> seen(c->n_params, 0);
     int n_rot = 0;
     for (int k = 0; k < c->n_gates; ++k) {
@@ -41,6 +46,14 @@ void validate_circuit(const qng_circuit *c, int max_qubits) {
             if (g.q0 < 0 || g.q0 >= n || g.q1 < 0 || g.q1 >= n)
                 fail(QNG_E_BAD_CIRCUIT, where + "qubit out of range");
             if (g.q0 == g.q1) fail(QNG_E_BAD_CIRCUIT, where + "control and target are the same qubit");
+            if (g.param < 0) fail(QNG_E_BAD_PARAMS, where + "rotation needs a parameter index >= 0");
+            if (g.param >= c->n_params) fail(QNG_E_BAD_PARAMS, where + "parameter index >= n_params");
+            ++seen[g.param];
+            ++n_rot;
+            break;
+        case QNG_RPAULI:
+            if (g.q0 < 0 || g.q0 >= c->n_strings) fail(QNG_E_BAD_CIRCUIT, where + "string index out of range");
+            if (g.q1 != -1) fail(QNG_E_BAD_CIRCUIT, where + "Pauli-string rotation must have q1 = -1");
             if (g.param < 0) fail(QNG_E_BAD_PARAMS, where + "rotation needs a parameter index >= 0");
             if (g.param >= c->n_params) fail(QNG_E_BAD_PARAMS, where + "parameter index >= n_params");
             ++seen[g.param];
@@ -99,6 +112,18 @@ Circuit compile_circuit(const qng_circuit *c) {
             k.rot_at[pos] = (int)k.rots.size();
             k.rots.push_back(Rot{g.kind - QNG_CRX, g.q1, g.param, pos, g.q0});
             k.controlled = true;
+        } else if (g.kind == QNG_RPAULI) {
+            Rot r{AX_X, 0, g.param, pos};
+            r.string = g.q0;
+            for (int q = 0; q < k.n; ++q) {
+                const uint8_t l = c->strings[(int64_t)g.q0 * k.n + q];
+                if (l == 1 || l == 2) r.flip |= uint64_t(1) << q;
+                if (l == 2 || l == 3) r.zy |= uint64_t(1) << q;
+                r.n_y += l == 2;
+            }
+            k.rot_at[pos] = (int)k.rots.size();
+            k.rots.push_back(r);
+            k.has_strings = true;
         }
     }
     k.P = (int)k.rots.size();

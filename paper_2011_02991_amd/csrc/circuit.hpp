@@ -34,12 +34,18 @@ struct Mat2 {  // row-major 2x2 complex, [[a, b], [c, d]]
 // One rotation of the ansatz, in gate-list order.  A controlled rotation
 // (ctrl >= 0) rotates `qubit` where qubit `ctrl` is 1; its generator is
 // |1><1|_ctrl (x) sigma, which replaces sigma in every product of its column.
+// A Pauli-string rotation (string >= 0) has the generator S given by its masks
+// (S psi)[x] = (-i)^{n_y} (-1)^{popcount(x & zy)} psi[x ^ flip]; axis and qubit
+// are unused for it.
 struct Rot {
     int axis;    // generator sigma: X, Y or Z
     int qubit;
     int param;   // parameter index (row/column of G)
     int pos;     // position in the gate list
     int ctrl = -1;
+    int string = -1;
+    uint64_t flip = 0, zy = 0;
+    int n_y = 0;
 };
 
 struct Circuit {
@@ -49,6 +55,9 @@ struct Circuit {
     int NP = 0;             // parameters; NP < P when rotations share parameters
     bool shared = false;    // some parameter is carried by several rotations
     bool controlled = false;  // some rotation is a controlled rotation
+    bool has_strings = false; // some rotation is a Pauli-string rotation
+    // rotations other than single-qubit ones: only the per-primitive kernels take them
+    bool extended() const { return controlled || has_strings; }
     std::vector<qng_gate> gates;
     std::vector<int> rot_at;   // gate position -> rotation index (list order) or -1
     std::vector<Rot> rots;     // rotations in list order

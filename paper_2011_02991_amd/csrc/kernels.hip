@@ -128,6 +128,75 @@ __global__ void k_apply_c1q(typename Cplx<R>::T *s0, typename Cplx<R>::T *s1, in
     }
 }
 
+// Pauli string S in mask form: (S psi)[x] = w (-1)^{popcount(x & zy)} psi[x ^ flip],
+// w = (-i)^{n_y}.  A rotation c + kappa S' with S' the string without w (the
+// host folds w and i sin into kappa): out[x] = c psi[x] + kappa sgn(x) psi[x ^ flip].
+// flip != 0: pairs (x0, x0 ^ flip) with the highest bit hb of flip clear in x0;
+// flip == 0: a diagonal phase.
+__device__ __forceinline__ double string_sign(uint64_t x, uint64_t zy) { return (__popcll(x & zy) & 1) ? -1.0 : 1.0; }
+
+template <typename R>
+__device__ __forceinline__ void string_pair(typename Cplx<R>::T *s, uint64_t x0, uint64_t x1, R c, R kr, R ki, R g0,
+                                            R g1) {
+    const typename Cplx<R>::T u = s[x0], v = s[x1];
+    typename Cplx<R>::T o0, o1;
+    o0.x = c * u.x + g0 * (kr * v.x - ki * v.y);
+    o0.y = c * u.y + g0 * (kr * v.y + ki * v.x);
+    o1.x = c * v.x + g1 * (kr * u.x - ki * u.y);
+    o1.y = c * v.y + g1 * (kr * u.y + ki * u.x);
+    s[x0] = o0;
+    s[x1] = o1;
+}
+
+template <typename R>
+__global__ void k_apply_string(typename Cplx<R>::T *s0, typename Cplx<R>::T *s1, int n, uint64_t flip, uint64_t zy,
+                               double c, double kr, double ki) {
+    const R cc = (R)c, kkr = (R)kr, kki = (R)ki;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    if (flip) {
+        const int hb = 63 - __clzll(flip);
+        const uint64_t npairs = uint64_t(1) << (n - 1);
+        for (uint64_t p = blockIdx.x * (uint64_t)kBlock + threadIdx.x; p < npairs; p += stride) {
+            const uint64_t x0 = insert_zero(p, hb), x1 = x0 ^ flip;
+            const R g0 = (R)string_sign(x0, zy), g1 = (R)string_sign(x1, zy);
+            string_pair<R>(s0, x0, x1, cc, kkr, kki, g0, g1);
+            if (s1) string_pair<R>(s1, x0, x1, cc, kkr, kki, g0, g1);
+        }
+    } else {
+        const uint64_t dim = uint64_t(1) << n;
+        for (uint64_t x = blockIdx.x * (uint64_t)kBlock + threadIdx.x; x < dim; x += stride) {
+            const R g = (R)string_sign(x, zy);
+            const R fr = cc + g * kkr, fi = g * kki;
+            typename Cplx<R>::T *regs[2] = {s0, s1};
+            for (int k = 0; k < 2; ++k) {
+                if (!regs[k]) continue;
+                const typename Cplx<R>::T u = regs[k][x];
+                typename Cplx<R>::T o;
+                o.x = fr * u.x - fi * u.y;
+                o.y = fr * u.y + fi * u.x;
+                regs[k][x] = o;
+            }
+        }
+    }
+}
+
+// lam = y; phi = S y with S = w S' (w = wr + i wi, a power of -i).
+template <typename R>
+__global__ void k_seed_string(const typename Cplx<R>::T *y, typename Cplx<R>::T *lam, typename Cplx<R>::T *phi, int n,
+                              uint64_t flip, uint64_t zy, double wr, double wi) {
+    const uint64_t dim = uint64_t(1) << n;
+    const R ar = (R)wr, ai = (R)wi;
+    for (uint64_t x = blockIdx.x * (uint64_t)kBlock + threadIdx.x; x < dim; x += (uint64_t)gridDim.x * kBlock) {
+        lam[x] = y[x];
+        const typename Cplx<R>::T v = y[x ^ flip];
+        const R g = (R)string_sign(x, zy);
+        typename Cplx<R>::T o;
+        o.x = g * (ar * v.x - ai * v.y);
+        o.y = g * (ar * v.y + ai * v.x);
+        phi[x] = o;
+    }
+}
+
 // CNOT(control c, target t): swap amplitudes (x, x ^ 2^t) for x with bit c set and bit t clear.
 template <typename R>
 __global__ void k_cnot(typename Cplx<R>::T *s0, typename Cplx<R>::T *s1, int n, int c, int t) {
@@ -238,6 +307,20 @@ __global__ void k_pauli_prod_partial(const typename Cplx<R>::T *a, const typenam
         }
     }
     block_reduce_store(sr, si, partials + 2 * blockIdx.x);
+}
+
+// Block partials of <a| S |b> = w sum_x conj(a[x]) sgn(x) b[x ^ flip] (w = wr + i wi).
+template <typename R>
+__global__ void k_string_prod_partial(const typename Cplx<R>::T *a, const typename Cplx<R>::T *b, int n,
+                                      uint64_t flip, uint64_t zy, double wr, double wi, double *partials) {
+    double sr = 0.0, si = 0.0;
+    const uint64_t dim = uint64_t(1) << n;
+    for (uint64_t x = blockIdx.x * (uint64_t)kBlock + threadIdx.x; x < dim; x += (uint64_t)gridDim.x * kBlock) {
+        const typename Cplx<R>::T u = a[x], v = b[x ^ flip];
+        const double g = string_sign(x, zy);
+        cmac(sr, si, g * (double)u.x, g * (double)u.y, v.x, v.y);
+    }
+    block_reduce_store(sr * wr - si * wi, sr * wi + si * wr, partials + 2 * blockIdx.x);
 }
 
 __global__ void k_reduce_final(const double *partials, int nb, double *dest) {
@@ -454,6 +537,50 @@ void launch_apply_c1q(void *s0, void *s1, int n, int c, int q, const DevMat2 &m,
     check_launch();
 }
 
+// w = (-i)^{n_y}
+inline void string_phase(int n_y, double &wr, double &wi) {
+    wr = 1.0;
+    wi = 0.0;
+    for (int k = 0; k < (n_y & 3); ++k) { const double t = wr; wr = wi; wi = -t; }
+}
+
+template <typename R>
+void launch_apply_string(void *s0, void *s1, int n, uint64_t flip, uint64_t zy, int n_y, double c, double sr,
+                         double si, hipStream_t st) {
+    // kappa = (sr + i si) w
+    double wr, wi;
+    string_phase(n_y, wr, wi);
+    const double kr = sr * wr - si * wi, ki = sr * wi + si * wr;
+    const uint64_t work = flip ? uint64_t(1) << (n - 1) : uint64_t(1) << n;
+    hipLaunchKernelGGL(k_apply_string<R>, dim3(grid_for(work)), dim3(kBlock), 0, st, (typename Cplx<R>::T *)s0,
+                       (typename Cplx<R>::T *)s1, n, flip, zy, c, kr, ki);
+    check_launch();
+}
+
+template <typename R>
+void launch_seed_string(const void *y, void *lam, void *phi, int n, uint64_t flip, uint64_t zy, int n_y,
+                        hipStream_t st) {
+    double wr, wi;
+    string_phase(n_y, wr, wi);
+    hipLaunchKernelGGL(k_seed_string<R>, dim3(grid_for(uint64_t(1) << n)), dim3(kBlock), 0, st,
+                       (const typename Cplx<R>::T *)y, (typename Cplx<R>::T *)lam, (typename Cplx<R>::T *)phi, n, flip,
+                       zy, wr, wi);
+    check_launch();
+}
+
+template <typename R>
+void launch_string_prod(const void *a, const void *b, int n, uint64_t flip, uint64_t zy, int n_y, double *partials,
+                        double *dest, hipStream_t st) {
+    double wr, wi;
+    string_phase(n_y, wr, wi);
+    const int nb = reduce_blocks(n);
+    hipLaunchKernelGGL(k_string_prod_partial<R>, dim3(nb), dim3(kBlock), 0, st, (const typename Cplx<R>::T *)a,
+                       (const typename Cplx<R>::T *)b, n, flip, zy, wr, wi, partials);
+    check_launch();
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, st, (const double *)partials, nb, dest);
+    check_launch();
+}
+
 template <typename R> void launch_cnot(void *s0, void *s1, int n, int c, int t, hipStream_t st) {
     hipLaunchKernelGGL(k_cnot<R>, dim3(grid_for(uint64_t(1) << (n - 2))), dim3(kBlock), 0, st,
                        (typename Cplx<R>::T *)s0, (typename Cplx<R>::T *)s1, n, c, t);
@@ -546,6 +673,11 @@ void launch_grad_from_raw(const double *graw, const int *param_of, int P, double
     template void launch_apply_1q<R>(void *, void *, int, int, const DevMat2 &, hipStream_t);                     \
     template void launch_apply_1q_tab<R>(void *, void *, int, int, const double *, hipStream_t);                  \
     template void launch_apply_c1q<R>(void *, void *, int, int, int, const DevMat2 &, hipStream_t);               \
+    template void launch_apply_string<R>(void *, void *, int, uint64_t, uint64_t, int, double, double, double,      \
+                                         hipStream_t);                                                            \
+    template void launch_seed_string<R>(const void *, void *, void *, int, uint64_t, uint64_t, int, hipStream_t);  \
+    template void launch_string_prod<R>(const void *, const void *, int, uint64_t, uint64_t, int, double *,        \
+                                        double *, hipStream_t);                                                   \
     template void launch_cnot<R>(void *, void *, int, int, int, hipStream_t);                                     \
     template void launch_cz<R>(void *, void *, int, int, int, hipStream_t);                                       \
     template void launch_seed<R>(const void *, void *, void *, int, int, int, hipStream_t, int);                 \

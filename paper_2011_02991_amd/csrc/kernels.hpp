@@ -35,6 +35,19 @@ template <typename R> void launch_apply_1q_tab(void *s0, void *s1, int n, int q,
 template <typename R>
 void launch_apply_c1q(void *s0, void *s1, int n, int c, int q, const DevMat2 &m, hipStream_t st);
 template <typename R> void launch_cnot(void *s0, void *s1, int n, int control, int target, hipStream_t st);
+
+// Pauli-string gates, S in mask form (S psi)[x] = (-i)^{n_y} (-1)^{popcount(x & zy)} psi[x ^ flip]:
+// apply c + (sr + i si) S to one register (s1 == nullptr) or two; lam = y, phi = S y;
+// dest (one complex128) = <a| S |b> (partials: reduce_blocks(n) complex128).
+template <typename R>
+void launch_apply_string(void *s0, void *s1, int n, uint64_t flip, uint64_t zy, int n_y, double c, double sr,
+                         double si, hipStream_t st);
+template <typename R>
+void launch_seed_string(const void *y, void *lam, void *phi, int n, uint64_t flip, uint64_t zy, int n_y,
+                        hipStream_t st);
+template <typename R>
+void launch_string_prod(const void *a, const void *b, int n, uint64_t flip, uint64_t zy, int n_y, double *partials,
+                        double *dest, hipStream_t st);
 template <typename R> void launch_cz(void *s0, void *s1, int n, int a, int b, hipStream_t st);
 
 // lam = y; phi = sigma_q y  (axis 0/1/2 = X/Y/Z).  ctrl >= 0: phi = (|1><1|_ctrl (x) sigma_q) y,

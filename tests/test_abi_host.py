@@ -85,17 +85,40 @@ def test_validate_controlled_rotations(qng):
         assert e.value.name == status, (row, e.value.name)
 
 
-def test_controlled_rotations_not_planned_for_fused_passes(qng):
-    """The per-primitive plan counts them; the fused-pass planner and its export
-    reject them (QNG_E_UNSUPPORTED)."""
-    pr = W.controlled_layers(6, 2, 4, 23)
-    c = _circ(qng, pr)
-    info = qng.plan(c, fusion=0)
-    assert info["elements"] == pr.n_params * (pr.n_params - 1) // 2
-    for call in (lambda: qng.plan(c, fusion=1), lambda: qng.plan_export(c)):
+def test_validate_pauli_string_rotations(qng):
+    """RPAULI (kind 8): q0 indexes the circuit's string table, q1 = -1."""
+    for pr in (W.string_circuit(6, 40, 31), W.string_layers(5, 2, 4, 32)):
+        assert (pr.gates[:, 0] == W.RPAULI).any()
+        qng.validate(_circ(qng, pr), pr.theta)
+    table = np.array([[1, 3], [0, 2]], dtype=np.uint8)
+    bad = [([W.RPAULI, 2, -1, 0], table, "QNG_E_BAD_CIRCUIT"),     # string index out of range
+           ([W.RPAULI, -1, -1, 0], table, "QNG_E_BAD_CIRCUIT"),
+           ([W.RPAULI, 0, 1, 0], table, "QNG_E_BAD_CIRCUIT"),      # q1 != -1
+           ([W.RPAULI, 0, -1, -1], table, "QNG_E_BAD_PARAMS"),     # no parameter
+           ([W.RPAULI, 1, -1, 0], np.array([[1, 3], [0, 4]], np.uint8), "QNG_E_BAD_CIRCUIT")]   # letter 4
+    for row, tab, status in bad:
+        g = np.array([[W.RY, 0, -1, 0], row], dtype=np.int32)
         with pytest.raises(qng.QNGError) as e:
-            call()
-        assert e.value.name == "QNG_E_UNSUPPORTED"
+            qng.validate(qng.Circuit(2, g, 1, strings=tab), [0.1], with_hamiltonian=False)
+        assert e.value.name == status, (row, e.value.name)
+    c = qng.Circuit(2, np.array([[W.RPAULI, 0, -1, 0]], np.int32), 1, strings=table)
+    c.c.strings = None
+    with pytest.raises(qng.QNGError) as e:
+        qng.validate(c, [0.1], with_hamiltonian=False)
+    assert e.value.name == "QNG_E_INVALID_ARG"
+
+
+def test_controlled_rotations_not_planned_for_fused_passes(qng):
+    """Controlled and Pauli-string rotations: the per-primitive plan counts
+    them; the fused-pass planner and its export reject them (QNG_E_UNSUPPORTED)."""
+    for pr in (W.controlled_layers(6, 2, 4, 23), W.string_layers(6, 2, 4, 24)):
+        c = _circ(qng, pr)
+        info = qng.plan(c, fusion=0)
+        assert info["elements"] == pr.n_params * (pr.n_params - 1) // 2
+        for call in (lambda: qng.plan(c, fusion=1), lambda: qng.plan_export(c)):
+            with pytest.raises(qng.QNGError) as e:
+                call()
+            assert e.value.name == "QNG_E_UNSUPPORTED"
 
 
 def test_validate_two_qubit_gate_same_qubit(qng):
