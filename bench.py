@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--f64-regs", type=int, default=0, help="complex64: compute sweep tiles in FP64 registers")
     ap.add_argument("--variants", action="store_true",
                     help="also time the cheaper metric variants (block-diagonal per layer, L only) on the workload")
+    ap.add_argument("--gateset", action="store_true",
+                    help="also measure controlled and Pauli-string rotations (isolated gate bandwidth at n=26 and "
+                         "the step at n=24 next to plain rotations)")
     ap.add_argument("--block", type=int, default=0,
                     help="metric columns sharing one lambda sweep (1 or 2; 0 = library default)")
     return ap.parse_args()
@@ -201,6 +204,84 @@ def metric_variants(qng, ctx, circ, pr, prec, reps=2):
     return out
 
 
+def extended_gates(qng, ctx, prec, n_gate=26, n_step=24, layers=2, reps=2):
+    """Controlled (CRX/CRY/CRZ) and Pauli-string rotations.
+
+    Isolated apply at n_gate qubits (HIP events on the library's stream):
+    a controlled rotation reads and writes the half of the amplitudes whose
+    control is 1 (V bytes); a string rotation reads and writes every amplitude
+    (2V).  Then the step at n_step qubits for the controlled ring ansatz and the
+    ZZ / X Y..Y X string ansatz (both per-primitive kernels), next to a plain
+    RY/RZ + CNOT ansatz with the same P on the per-primitive kernels and on the
+    fused passes."""
+    import numpy as np
+    import torch
+    import workloads as W
+    dev = torch.device("cuda:0")
+    dtype = torch.complex64 if prec == "c64" else torch.complex128
+    n = n_gate
+    state = torch.zeros(2 ** n, dtype=dtype, device=dev)
+    state[0] = 1
+    V = (8 if prec == "c64" else 16) * 2 ** n
+    cases = []
+    for kind in (W.CRX, W.CRY, W.CRZ):
+        for q in (0, 5, 12, n - 2):
+            cases.append((f"CR{'XYZ'[kind - W.CRX]}({q},{q + 1})", [[kind, q, q + 1, 0]], None, V))
+            cases.append((f"CR{'XYZ'[kind - W.CRX]}({q + 1},{q})", [[kind, q + 1, q, 0]], None, V))
+    for name, letters in (("ZZ(0,1)", {0: 3, 1: 3}), ("ZZ(12,13)", {12: 3, 13: 3}), ("XX(0,1)", {0: 1, 1: 1}),
+                          ("XYYX(10..13)", {10: 1, 11: 2, 12: 2, 13: 1}), ("X..X (all)", {q: 1 for q in range(n)}),
+                          ("Y(n-1)Z(0)", {n - 1: 2, 0: 3})):
+        st_ = np.zeros((1, n), dtype=np.uint8)
+        for q, l in letters.items():
+            st_[0, q] = l
+        cases.append((name, [[W.RPAULI, 0, -1, 0]], st_, 2 * V))
+    iso = []
+    s = torch.cuda.Stream()
+    ctx.set_stream(s.cuda_stream)
+    try:
+        with torch.cuda.stream(s):
+            for name, g, strings, moved in cases:
+                circ = qng.Circuit(n, np.array(g, dtype=np.int32), 1, strings=strings)
+                ctx.apply_circuit_dev(circ, [0.3], state.data_ptr(), prec=prec)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(s)
+                for _ in range(5):
+                    ctx.apply_circuit_dev(circ, [0.3], state.data_ptr(), prec=prec)
+                e1.record(s)
+                s.synchronize()
+                ms = e0.elapsed_time(e1) / 5
+                iso.append({"gate": name, "ms": ms, "GBps": moved / (ms * 1e-3) / 1e9})
+    finally:
+        torch.cuda.synchronize()
+        ctx.set_stream(None)
+    del state
+
+    def step_time(pr, fusion):
+        c = qng.Circuit.from_problem(pr)
+        ctx.set_option(qng.OPT_FUSION, fusion)
+        try:
+            ctx.step(c, pr.theta, pr.dt, pr.tikhonov, prec=prec, want_G=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ctx.step(c, pr.theta, pr.dt, pr.tikhonov, prec=prec, want_G=False)
+            torch.cuda.synchronize()
+            st = ctx.stats()
+        finally:
+            ctx.set_option(qng.OPT_FUSION, 1)
+        return {"workload": pr.name, "P": pr.n_params, "fusion": fusion, "s_per_step": (time.perf_counter() - t0) / reps,
+                "elements": st["elements"], "sweep_launches": st["sweep_launches"],
+                "other_launches": st["other_launches"]}
+
+    plain = W.make_problem(f"ry_rz_cnot_n{n_step}_L{layers}", n_step, layers, (W.RY, W.RZ), "cnot_chain", 30, 5401)
+    steps = [step_time(W.controlled_layers(n_step, layers, 30, 5402), 1),
+             step_time(W.string_layers(n_step, layers, 30, 5403), 1),
+             step_time(plain, 0), step_time(plain, 1)]
+    out = {"isolated_n": n, "isolated": iso, "steps_n": n_step, "steps": steps}
+    log(f"extended gates: {out}")
+    return out
+
+
 def traffic_per_launch():
     """HBM bytes per sweep launch from the committed FETCH_SIZE/WRITE_SIZE counter
     summary, if it was taken on the current kernel source (else None)."""
@@ -252,6 +333,7 @@ def main():
         gate = gate_apply_bandwidth(qng, ctx, min(args.gate_qubits, pr.n_qubits), args.prec)
         log(f"gate apply: {gate}")
     variants = metric_variants(qng, ctx, circ, pr, args.prec) if args.variants else None
+    gateset = extended_gates(qng, ctx, args.prec) if args.gateset else None
     cpu = None if args.no_cpu else cpu_baseline(pr)
     roof = None
     if st.get("sweep_launches", 0) > 0 and st.get("sweep_ms", 0) > 0:
@@ -277,7 +359,7 @@ def main():
                    "tile_qubits": args.tile or None, "f64_registers": bool(args.f64_regs),
                    "block_columns": st.get("block_columns")},
         "plain_fp64": plain, "precision_errors": precision, "gate_apply": gate, "roofline": roof, "cpu_baseline": cpu,
-        "metric_variants": variants,
+        "metric_variants": variants, "extended_gates": gateset,
         "breakdown_ms": {k: st[k] / args.steps for k in ("metric_ms", "grad_ms", "solve_ms")},
     }
     print(json.dumps(line), flush=True)
