@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--gate-qubits", type=int, default=26)
     ap.add_argument("--tile", type=int, default=0, help="tile qubits of the fused passes (0 = library default)")
     ap.add_argument("--f64-regs", type=int, default=0, help="complex64: compute sweep tiles in FP64 registers")
+    ap.add_argument("--exact-products", type=int, default=0,
+                    help="complex64 with FP32 registers: form every inner-product term in FP64")
+    ap.add_argument("--no-exact", action="store_true",
+                    help="skip the complex64 leg with every inner-product term in FP64")
     ap.add_argument("--variants", action="store_true",
                     help="also time the cheaper metric variants (block-diagonal per layer, L only) on the workload")
     ap.add_argument("--gateset", action="store_true",
@@ -314,6 +318,7 @@ def main():
     ctx.set_option(qng.OPT_FUSION, args.fusion)
     ctx.set_option(qng.OPT_TILE_QUBITS, args.tile)
     ctx.set_option(qng.OPT_F64_REGISTERS, args.f64_regs)
+    ctx.set_option(qng.OPT_EXACT_PRODUCTS, args.exact_products)
     ctx.set_option(qng.OPT_BLOCK_COLUMNS, args.block)
     t_chosen, res, st = time_steps(ctx, circ, pr, args.prec, args.steps, args.warmup, profile=True)
     log(f"{args.prec}: {t_chosen:.3f} s/step  stats={st}")
@@ -328,6 +333,17 @@ def main():
         else:
             precision = precision_report(pr, res_other, res, "c64", "c128")
         log(f"precision: {precision}")
+    exact = None
+    if args.prec == "c64" and not args.f64_regs and not args.exact_products and not args.no_exact:
+        # the same step with every inner-product term formed in FP64
+        ctx.set_option(qng.OPT_EXACT_PRODUCTS, 1)
+        try:
+            t_exact, res_exact, _ = time_steps(ctx, circ, pr, "c64", max(1, args.steps - 1), 1)
+        finally:
+            ctx.set_option(qng.OPT_EXACT_PRODUCTS, 0)
+        exact = {"s_per_step": t_exact,
+                 "precision_errors": precision_report(pr, res_exact, res_other, "c64", "c128") if plain else None}
+        log(f"c64 with FP64 products: {exact}")
     gate = None
     if args.gate_qubits > 0:
         gate = gate_apply_bandwidth(qng, ctx, min(args.gate_qubits, pr.n_qubits), args.prec)
@@ -352,13 +368,17 @@ def main():
         "metric": "QNG step time (s) + gate-apply HBM GB/s at n=26,P=400; chosen vs plain FP64",
         "value": t_chosen, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": t_chosen * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c64 storage, f64 accumulate" if args.prec == "c64" else "c128",
+        "dtype": ("c128" if args.prec == "c128" else
+                  "c64 storage, f64 registers" if args.f64_regs else
+                  "c64 storage, f64 products and accumulation" if args.exact_products else
+                  "c64 storage, f32 per-thread product shares, f64 accumulation"),
         "data": "synthetic",
         "config": {"workload": pr.name, "n_qubits": pr.n_qubits, "P": pr.n_params, "gates": pr.n_gates,
                    "hamiltonian_terms": pr.n_terms, "precision": args.prec, "fusion": args.fusion,
                    "tile_qubits": args.tile or None, "f64_registers": bool(args.f64_regs),
+                   "exact_products": bool(args.exact_products),
                    "block_columns": st.get("block_columns")},
-        "plain_fp64": plain, "precision_errors": precision, "gate_apply": gate, "roofline": roof, "cpu_baseline": cpu,
+        "plain_fp64": plain, "precision_errors": precision, "c64_exact_fp64_products": exact, "gate_apply": gate, "roofline": roof, "cpu_baseline": cpu,
         "metric_variants": variants, "extended_gates": gateset,
         "breakdown_ms": {k: st[k] / args.steps for k in ("metric_ms", "grad_ms", "solve_ms")},
     }

@@ -74,8 +74,11 @@ typedef enum {
 } qng_gate_kind;
 
 /* Storage precision of the state vectors.  QNG_C64 keeps states and gate
- * matrices in complex64 (rounded from FP64) while every inner product, the
- * assembly of G and the solve stay in FP64. */
+ * matrices in complex64 (rounded from FP64) while the inner products are
+ * accumulated in FP64 and the assembly of G and the solve stay in FP64.  In the
+ * fused passes each thread forms its share of an inner product (at most 16
+ * amplitudes) in the register precision before the FP64 sums; with
+ * QNG_OPT_EXACT_PRODUCTS = 1 every product is formed in FP64 as well. */
 typedef enum { QNG_C128 = 0, QNG_C64 = 1 } qng_precision;
 
 /* One gate.  Rotations (RX/RY/RZ): q0 = target, q1 = -1, param = its parameter
@@ -136,9 +139,13 @@ typedef enum {
     QNG_OPT_BATCH_TILES = 8,     /* qng_step_batched: work-groups per sweep launch to aim for (0 = 4096) */
     QNG_OPT_BLOCK_COLUMNS = 9,   /* fused metric: columns sharing one lambda sweep, 1 or 2 (0 = default); 2 needs
                                     tiles of >= 11 qubits (registers of >= 11 qubits), else 1 is used */
-    QNG_OPT_METRIC_KIND = 10     /* 0 (default): G = L - T^* T; 1: L alone, L_ij = <d_i psi, d_j psi> (the
+    QNG_OPT_METRIC_KIND = 10,    /* 0 (default): G = L - T^* T; 1: L alone, L_ij = <d_i psi, d_j psi> (the
                                     coefficient matrix of imaginary-time evolution when psi's global phase does
                                     not depend on theta); T is still returned.  Metric and step entry points. */
+    QNG_OPT_EXACT_PRODUCTS = 11  /* complex64 with FP32 registers: 0 (default) = each thread forms its share of
+                                    an inner product (16 or fewer amplitudes) in FP32 and converts it to FP64, all
+                                    further sums FP64; 1 = every product formed and accumulated in FP64 (exact
+                                    products of the stored FP32 values; slower) */
 } qng_option;
 
 /* Counters of the last metric/energy/step call on a context. */

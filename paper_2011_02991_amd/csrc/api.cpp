@@ -64,6 +64,7 @@ struct qng_ctx {
     bool own_stream = false;
     size_t mem_limit = 0;
     int opt_fusion = 1, opt_tile = 0, opt_streams = 0, opt_profile = 0, opt_small = 1, opt_f64_regs = 0;
+    int opt_exact_products = 0;
     int opt_graph = 1, opt_autotune = 0, opt_batch_tiles = 0, opt_block = 0, opt_metric_kind = 0;
     std::vector<int> metric_blocks;   // block id per parameter (block-diagonal metric); empty = full
     std::string last_error;
@@ -246,6 +247,15 @@ Problem make_problem(const qng_circuit *c, const double *theta, const qng_pauli_
     return p;
 }
 
+// Arithmetic of the fused sweep passes for a storage precision (amp bytes per
+// amplitude): FP64 for complex128 or when FP64 registers are asked for, else
+// FP32 registers with FP32 thread shares of the products or, on request,
+// every product in FP64.
+int sweep_reg_mode(const qng_ctx *ctx, size_t amp) {
+    if (amp == 16 || ctx->opt_f64_regs) return REG_F64;
+    return ctx->opt_exact_products ? REG_F32_EXACT : REG_F32;
+}
+
 // The context's metric settings for a problem: block-diagonal blocks (when the
 // circuit has the number of parameters they were given for) and the L-only
 // form.
@@ -297,7 +307,7 @@ template <typename R> struct Engine {
     const SweepPlan *gplan = nullptr;
     char *gscratch = nullptr;
     size_t gscratch_bytes = 0;
-    bool f64_regs = false;
+    int reg_mode = REG_F32;
 
     void *state(int k) const { return regs[k]; }
     double *partials() const { return partials_; }
@@ -391,7 +401,7 @@ template <typename R> struct Engine {
         if (!want_grad || c.P == 0) return;
         if (gplan) {
             run_fused_gradient<R>(*gplan, c, pb.adj, lam, psi, graw(), gscratch, gscratch_bytes, st, &ctx->stats,
-                                  ctx->opt_profile != 0, f64_regs);
+                                  ctx->opt_profile != 0, reg_mode);
             return;
         }
         const int p0 = c.rots[0].pos;
@@ -511,7 +521,7 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
         e.gplan = gplan.get();
         e.gscratch = base + L.sweep;
         e.gscratch_bytes = L.sweep_bytes;
-        e.f64_regs = f64_regs;
+        e.reg_mode = sweep_reg_mode(ctx, amp);
     }
 
     const void *in_c128 = spec.in_dev;
@@ -541,7 +551,7 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
             fb.lraw = e.lraw();
             fb.reduce_partials = e.partials();
             pos = run_fused_metric<R>(*plan, fr, c, pb.fwd, pb.adj, fb, st, &ctx->stats, ctx->opt_profile != 0,
-                                      amp == 16 || ctx->opt_f64_regs);
+                                      sweep_reg_mode(ctx, amp));
         } else {
             pos = e.metric_unfused();
         }
@@ -640,7 +650,7 @@ BatchRun batch_metric(qng_ctx *ctx, const std::vector<Problem> &pbs, const doubl
     HIPCHECK(hipMemGetInfo(&free_b, &total_b));
     const uint64_t arena_cap = (uint64_t)(free_b + ctx->ws_bytes) / 4;
     for (auto &kv : by_m) {
-        std::vector<int32_t> key = {kv.first, amp, f64 ? 1 : 0, tun.tile_qubits, tun.target_tiles};
+        std::vector<int32_t> key = {kv.first, amp, sweep_reg_mode(ctx, amp), tun.tile_qubits, tun.target_tiles};
         for (int b : kv.second) append_structure_key(pbs[b].circ, key);
         auto it = ctx->batch_classes.find(key);
         std::shared_ptr<BatchClass> bc;
@@ -790,7 +800,7 @@ BatchRun batch_metric(qng_ctx *ctx, const std::vector<Problem> &pbs, const doubl
                 hipGraph_t g = nullptr;
                 HIPCHECK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
                 try {
-                    enqueue_batch_metric<R>(S, circs, d, f64, st, nullptr);
+                    enqueue_batch_metric<R>(S, circs, d, sweep_reg_mode(ctx, amp), st, nullptr);
                 } catch (...) {
                     hipGraph_t junk = nullptr;
                     (void)hipStreamEndCapture(st, &junk);
@@ -814,7 +824,7 @@ BatchRun batch_metric(qng_ctx *ctx, const std::vector<Problem> &pbs, const doubl
                 ev.resize(2 * S.launches.size());
                 for (auto &e : ev) HIPCHECK(hipEventCreate(&e));
             }
-            enqueue_batch_metric<R>(S, circs, d, f64, st, profile ? &ev : nullptr);
+            enqueue_batch_metric<R>(S, circs, d, sweep_reg_mode(ctx, amp), st, profile ? &ev : nullptr);
             if (profile) {
                 HIPCHECK(hipStreamSynchronize(st));
                 for (size_t li = 0; li < S.launches.size(); ++li) {
@@ -848,7 +858,7 @@ BatchTuning batch_tuning(qng_ctx *ctx, const std::vector<Problem> &pbs, const do
     fixed.tile_qubits = ctx->opt_tile;
     fixed.target_tiles = ctx->opt_batch_tiles > 0 ? ctx->opt_batch_tiles : 4096;
     if (!ctx->opt_autotune) return fixed;
-    std::vector<int32_t> key = {amp, f64 ? 1 : 0, ctx->opt_tile, ctx->opt_batch_tiles};
+    std::vector<int32_t> key = {amp, sweep_reg_mode(ctx, amp), ctx->opt_tile, ctx->opt_batch_tiles};
     for (const Problem &pb : pbs) append_structure_key(pb.circ, key);
     auto it = ctx->tuned.find(key);
     if (it != ctx->tuned.end()) return it->second;
@@ -978,6 +988,7 @@ qng_status qng_set_option(qng_ctx *ctx, int option, int value) {
         case QNG_OPT_PROFILE: ctx->opt_profile = value ? 1 : 0; break;
         case QNG_OPT_SMALL_N_KERNEL: ctx->opt_small = value ? 1 : 0; break;
         case QNG_OPT_F64_REGISTERS: ctx->opt_f64_regs = value ? 1 : 0; break;
+        case QNG_OPT_EXACT_PRODUCTS: ctx->opt_exact_products = value ? 1 : 0; break;
         case QNG_OPT_GRAPH: ctx->opt_graph = value ? 1 : 0; break;
         case QNG_OPT_AUTOTUNE: ctx->opt_autotune = value ? 1 : 0; break;
         case QNG_OPT_BATCH_TILES:
@@ -1295,7 +1306,7 @@ qng_status qng_step_batched(qng_ctx *ctx, int32_t B, const qng_circuit *circs, c
                     e.gplan = gp.get();
                     e.gscratch = base + L.gscratch;
                     e.gscratch_bytes = L.gscratch_bytes;
-                    e.f64_regs = amp == 16 || ctx->opt_f64_regs;
+                    e.reg_mode = sweep_reg_mode(ctx, amp);
                 }
                 e.energy_grad_unfused(batch_final_pos(pb.circ), true, nullptr);
             }

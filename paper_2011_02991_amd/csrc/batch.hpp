@@ -91,7 +91,7 @@ void upload_batch_images(const BatchSchedule &s, const BatchDevice &d, hipStream
 // (in stream order) member b's forward register holds y_{P_b - 1}.
 template <typename R>
 void enqueue_batch_metric(const BatchSchedule &s, const std::vector<const Circuit *> &members, const BatchDevice &d,
-                          bool f64_regs, hipStream_t st, std::vector<hipEvent_t> *events);
+                          int reg_mode, hipStream_t st, std::vector<hipEvent_t> *events);
 
 // Gate position of member b's forward register after the metric phase.
 int batch_final_pos(const Circuit &c);

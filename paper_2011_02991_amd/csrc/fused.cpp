@@ -50,7 +50,7 @@ size_t fused_scratch_bytes(const SweepPlan &plan, const FusedRun &fr, int M) {
 template <typename R>
 int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c, const std::vector<Mat2> &fwd,
                      const std::vector<Mat2> &adj, const FusedBuffers &buf, hipStream_t st, qng_stats *stats,
-                     bool profile, bool f64_regs) {
+                     bool profile, int reg_mode) {
     const int n = c.n;
     const size_t V = buf.state_bytes;
     const uint32_t tiles = 1u << (n - plan.m);
@@ -207,7 +207,7 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
             const Launch &L = launches[li];
             if (profile) FCHECK(hipEventRecord(ev[2 * li], st));
             launch_sweep_pass<R>(d_items + L.item_begin, (int)L.n_items, L.total_tiles, d_passes, d_ops, d_maps,
-                                 d_mats, d_mats32, d_partials, plan.m, plan.rb, f64_regs, W, st);
+                                 d_mats, d_mats32, d_partials, plan.m, plan.rb, reg_mode, W, st);
             if (profile) FCHECK(hipEventRecord(ev[2 * li + 1], st));
             launch_reduce_tasks(d_tasks + L.task_begin, (int)L.n_tasks, d_partials, buf.lraw, st);
             ++stats->sweep_launches;
@@ -248,7 +248,7 @@ size_t fused_gradient_scratch_bytes(const SweepPlan &g, int M) {
 template <typename R>
 void run_fused_gradient(const SweepPlan &g, const Circuit &c, const std::vector<Mat2> &adj, void *lam, void *psi,
                         double *graw, char *scratch, size_t scratch_bytes, hipStream_t st, qng_stats *stats,
-                        bool profile, bool f64_regs) {
+                        bool profile, int reg_mode) {
     if (g.cols.empty()) return;
     const ColumnPlan &cp = g.cols[0];
     const uint32_t tiles = 1u << (c.n - g.m);
@@ -308,7 +308,7 @@ void run_fused_gradient(const SweepPlan &g, const Circuit &c, const std::vector<
     for (size_t t = 0; t < items.size(); ++t) {
         if (profile) FCHECK(hipEventRecord(ev[2 * t], st));
         launch_sweep_pass<R>(d_items + t, 1, tiles, d_passes, d_ops, d_maps, d_mats, d_mats32, d_partials, g.m, g.rb,
-                             f64_regs, 1, st);
+                             reg_mode, 1, st);
         if (profile) FCHECK(hipEventRecord(ev[2 * t + 1], st));
         const uint32_t nt = task_begin[t + 1] - task_begin[t];
         launch_reduce_tasks(d_tasks + task_begin[t], (int)nt, d_partials, graw, st);
@@ -330,13 +330,13 @@ void run_fused_gradient(const SweepPlan &g, const Circuit &c, const std::vector<
 }
 
 template void run_fused_gradient<double>(const SweepPlan &, const Circuit &, const std::vector<Mat2> &, void *, void *,
-                                         double *, char *, size_t, hipStream_t, qng_stats *, bool, bool);
+                                         double *, char *, size_t, hipStream_t, qng_stats *, bool, int);
 template void run_fused_gradient<float>(const SweepPlan &, const Circuit &, const std::vector<Mat2> &, void *, void *,
-                                        double *, char *, size_t, hipStream_t, qng_stats *, bool, bool);
+                                        double *, char *, size_t, hipStream_t, qng_stats *, bool, int);
 
 template int run_fused_metric<double>(const SweepPlan &, const FusedRun &, const Circuit &, const std::vector<Mat2> &,
-                                      const std::vector<Mat2> &, const FusedBuffers &, hipStream_t, qng_stats *, bool, bool);
+                                      const std::vector<Mat2> &, const FusedBuffers &, hipStream_t, qng_stats *, bool, int);
 template int run_fused_metric<float>(const SweepPlan &, const FusedRun &, const Circuit &, const std::vector<Mat2> &,
-                                     const std::vector<Mat2> &, const FusedBuffers &, hipStream_t, qng_stats *, bool, bool);
+                                     const std::vector<Mat2> &, const FusedBuffers &, hipStream_t, qng_stats *, bool, int);
 
 }  // namespace qng

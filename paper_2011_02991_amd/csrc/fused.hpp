@@ -29,7 +29,7 @@ size_t fused_scratch_bytes(const SweepPlan &plan, const FusedRun &fr, int M);
 template <typename R>
 int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c, const std::vector<Mat2> &fwd,
                      const std::vector<Mat2> &adj, const FusedBuffers &buf, hipStream_t st, qng_stats *stats,
-                     bool profile, bool f64_regs);
+                     bool profile, int reg_mode);
 
 size_t fused_gradient_scratch_bytes(const SweepPlan &g, int M);
 
@@ -40,6 +40,6 @@ size_t fused_gradient_scratch_bytes(const SweepPlan &g, int M);
 template <typename R>
 void run_fused_gradient(const SweepPlan &g, const Circuit &c, const std::vector<Mat2> &adj, void *lam, void *psi,
                         double *graw, char *scratch, size_t scratch_bytes, hipStream_t st, qng_stats *stats,
-                        bool profile, bool f64_regs);
+                        bool profile, int reg_mode);
 
 }  // namespace qng

@@ -266,6 +266,13 @@ struct FusedRun {
 // Blocks run concurrently and scratch sizes for a plan on a register of n qubits.
 FusedRun fused_config(const SweepPlan &plan, int requested_streams, size_t state_bytes, size_t free_bytes);
 
+// Arithmetic of a sweep pass over complex64 storage: tiles in FP32 registers
+// with each thread's share of an inner product formed in FP32 and summed in
+// FP64 beyond the thread (REG_F32), tiles in FP64 registers (REG_F64), or FP32
+// registers with every product formed and accumulated in FP64 (REG_F32_EXACT).
+// complex128 storage always computes in FP64.
+enum RegMode : int { REG_F32 = 0, REG_F64 = 1, REG_F32_EXACT = 2 };
+
 // Kernel launchers (sweep_kernels.hip).
 // mats64 / mats32: per gate position 8 values, of which the first two are the
 // shear parameters (u, w) of the gate's adjoint (circuit.hpp, adjoint_shear),
@@ -274,7 +281,12 @@ FusedRun fused_config(const SweepPlan &plan, int requested_streams, size_t state
 template <typename R>
 void launch_sweep_pass(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
                        const DevOp *ops, const DevMap *maps, const double *mats64, const float *mats32,
-                       double *partials, int m, int rb, bool f64_registers, int width, hipStream_t st);
+                       double *partials, int m, int rb, int reg_mode, int width, hipStream_t st);
+// The REG_F32_EXACT kernels (sweep_kernels_exact.hip: the same source built
+// with every product in FP64), complex64 storage only.
+void launch_sweep_pass_exact(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
+                             const DevOp *ops, const DevMap *maps, const float *mats32, double *partials, int m,
+                             int rb, int width, hipStream_t st);
 void launch_reduce_tasks(const ReduceTask *tasks, int n_tasks, const double *partials, double *results,
                          hipStream_t st);
 

@@ -31,6 +31,8 @@
 //    qubits again), in place: the tile is touched by this work-group only.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "sweep.hpp"
 
 namespace qng {
@@ -154,23 +156,41 @@ __device__ __forceinline__ CT mat_entry(const CT *__restrict__ mt, int gate, int
 
 // ------------------------------------------------------- inner products
 //
-// Every product is taken in FP64 from the register values (exact for FP32
-// registers) and accumulated in FP64 with explicit fused multiply-adds; the
-// first term of a chain is a plain product, so no chain starts from zero.
+// A thread's share of a product (its T amplitudes, two chains of fused
+// multiply-adds) is formed in the register precision CT and converted to FP64
+// once; every sum beyond the thread (row, work-group, tiles, launches) is
+// FP64.  Built with QNG_EXACT_PRODUCTS = 1 (sweep_kernels_exact.hip), the
+// share is formed in FP64 from the register values (each product of two FP32
+// values exact) instead.  For FP32 registers this rounds each term relative to the thread's
+// own partial, a few units of 2^-24 of a sum of T = 16 terms, which is far
+// below what storing the state in FP32 already costs (the state is rounded
+// at every gate), and it spares converting every register value to FP64 for
+// each product.  The first term of a chain is a plain product, so no chain
+// starts from zero.
 
-// acc = (first ? 0 : acc) + conj(a) b, with signs sa on the whole term
-template <bool FIRST, bool NEG>
-__device__ __forceinline__ void cfma(double &r, double &i, double ar, double ai, double br, double bi) {
-    const double s = NEG ? -1.0 : 1.0;
+#ifndef QNG_EXACT_PRODUCTS
+#define QNG_EXACT_PRODUCTS 0
+#endif
+template <typename CT> using ProdT = typename std::conditional<QNG_EXACT_PRODUCTS != 0, double, CT>::type;
+
+__device__ __forceinline__ float fma_rn(float a, float b, float c) { return __fmaf_rn(a, b, c); }
+__device__ __forceinline__ double fma_rn(double a, double b, double c) { return __fma_rn(a, b, c); }
+
+// acc = (first ? 0 : acc) + conj(a) b, with signs sa on the whole term; the
+// operands are taken in the accumulator's precision A
+template <typename T> using AccArg = typename std::common_type<T>::type;   // not deduced
+template <bool FIRST, bool NEG, typename A>
+__device__ __forceinline__ void cfma(A &r, A &i, AccArg<A> ar, AccArg<A> ai, AccArg<A> br, AccArg<A> bi) {
+    const A s = NEG ? A(-1) : A(1);
     if (FIRST) {
         r = (s * ar) * br;
         i = (s * ar) * bi;
     } else {
-        r = __fma_rn(s * ar, br, r);
-        i = __fma_rn(s * ar, bi, i);
+        r = fma_rn(s * ar, br, r);
+        i = fma_rn(s * ar, bi, i);
     }
-    r = __fma_rn(s * ai, bi, r);
-    i = __fma_rn(-s * ai, br, i);
+    r = fma_rn(s * ai, bi, r);
+    i = fma_rn(-s * ai, br, i);
 }
 
 // X: sum over pairs of conj(a0) b1 + conj(a1) b0.
@@ -179,22 +199,23 @@ __device__ __forceinline__ void cfma(double &r, double &i, double ar, double ai,
 template <int J, int AX, int T, typename CT>
 __device__ __forceinline__ void prod_xy(const CT (&ar)[T], const CT (&ai)[T], const CT (&br)[T], const CT (&bi)[T],
                                         double &pr, double &pi) {
-    double r0 = 0.0, i0 = 0.0, r1 = 0.0, i1 = 0.0;
+    ProdT<CT> r0 = 0, i0 = 0, r1 = 0, i1 = 0;
     int pair = 0;
 #pragma unroll
     for (int i = 0; i < T; ++i) {
         if (i & (1 << J)) continue;
         const int k = i | (1 << J);
-        const double a0r = ar[i], a0i = ai[i], a1r = ar[k], a1i = ai[k];
-        const double b0r = br[i], b0i = bi[i], b1r = br[k], b1i = bi[k];
-        double &r = (pair & 1) ? r1 : r0;
-        double &m = (pair & 1) ? i1 : i0;
+        const ProdT<CT> a0r = ar[i], a0i = ai[i], a1r = ar[k], a1i = ai[k];
+        const ProdT<CT> b0r = br[i], b0i = bi[i], b1r = br[k], b1i = bi[k];
+        ProdT<CT> &r = (pair & 1) ? r1 : r0;
+        ProdT<CT> &m = (pair & 1) ? i1 : i0;
         if (pair < 2) cfma<true, AX == 1>(r, m, a0r, a0i, b1r, b1i);
         else cfma<false, AX == 1>(r, m, a0r, a0i, b1r, b1i);
         cfma<false, false>(r, m, a1r, a1i, b0r, b0i);
         ++pair;
     }
-    const double sr = (T >= 4) ? r0 + r1 : r0, si = (T >= 4) ? i0 + i1 : i0;
+    const double sr = (T >= 4) ? (double)r0 + (double)r1 : (double)r0;
+    const double si = (T >= 4) ? (double)i0 + (double)i1 : (double)i0;
     if (AX == 0) {
         pr = sr;
         pi = si;
@@ -208,11 +229,11 @@ __device__ __forceinline__ void prod_xy(const CT (&ar)[T], const CT (&ai)[T], co
 template <int J, int T, typename CT>
 __device__ __forceinline__ void prod_z_reg(const CT (&ar)[T], const CT (&ai)[T], const CT (&br)[T],
                                            const CT (&bi)[T], double &pr, double &pi) {
-    double r0 = 0.0, i0 = 0.0, r1 = 0.0, i1 = 0.0;
+    ProdT<CT> r0 = 0, i0 = 0, r1 = 0, i1 = 0;
 #pragma unroll
     for (int i = 0; i < T; ++i) {
-        double &r = (i & 1) ? r1 : r0;
-        double &m = (i & 1) ? i1 : i0;
+        ProdT<CT> &r = (i & 1) ? r1 : r0;
+        ProdT<CT> &m = (i & 1) ? i1 : i0;
         const bool neg = (i >> J) & 1;
         if (i < 2) {
             if (neg) cfma<true, true>(r, m, ar[i], ai[i], br[i], bi[i]);
@@ -222,42 +243,42 @@ __device__ __forceinline__ void prod_z_reg(const CT (&ar)[T], const CT (&ai)[T],
             else cfma<false, false>(r, m, ar[i], ai[i], br[i], bi[i]);
         }
     }
-    pr = (T >= 2) ? r0 + r1 : r0;
-    pi = (T >= 2) ? i0 + i1 : i0;
+    pr = (T >= 2) ? (double)r0 + (double)r1 : (double)r0;
+    pi = (T >= 2) ? (double)i0 + (double)i1 : (double)i0;
 }
 
 // sum_i conj(a_i) b_i (the caller applies a sign common to all registers)
 template <int T, typename CT>
 __device__ __forceinline__ void prod_plain(const CT (&ar)[T], const CT (&ai)[T], const CT (&br)[T],
                                            const CT (&bi)[T], double &pr, double &pi) {
-    double r0 = 0.0, i0 = 0.0, r1 = 0.0, i1 = 0.0;
+    ProdT<CT> r0 = 0, i0 = 0, r1 = 0, i1 = 0;
 #pragma unroll
     for (int i = 0; i < T; ++i) {
-        double &r = (i & 1) ? r1 : r0;
-        double &m = (i & 1) ? i1 : i0;
+        ProdT<CT> &r = (i & 1) ? r1 : r0;
+        ProdT<CT> &m = (i & 1) ? i1 : i0;
         if (i < 2) cfma<true, false>(r, m, ar[i], ai[i], br[i], bi[i]);
         else cfma<false, false>(r, m, ar[i], ai[i], br[i], bi[i]);
     }
-    pr = (T >= 2) ? r0 + r1 : r0;
-    pi = (T >= 2) ? i0 + i1 : i0;
+    pr = (T >= 2) ? (double)r0 + (double)r1 : (double)r0;
+    pi = (T >= 2) ? (double)i0 + (double)i1 : (double)i0;
 }
 
 // The same products for every phi register of the tile at once, lambda's
 // values converted once per pair for all of them.
 template <int J, int AX, int T, typename CT, int W>
 __device__ __forceinline__ void prodw_xy(const Regs<CT, T, W> &x, double (&pr)[W], double (&pi)[W]) {
-    double r0[W], i0[W], r1[W], i1[W];
+    ProdT<CT> r0[W], i0[W], r1[W], i1[W];
     int pair = 0;
 #pragma unroll
     for (int i = 0; i < T; ++i) {
         if (i & (1 << J)) continue;
         const int k = i | (1 << J);
-        const double a0r = x.ar[i], a0i = x.ai[i], a1r = x.ar[k], a1i = x.ai[k];
+        const ProdT<CT> a0r = x.ar[i], a0i = x.ai[i], a1r = x.ar[k], a1i = x.ai[k];
 #pragma unroll
         for (int b = 0; b < W; ++b) {
-            const double b0r = x.br[b][i], b0i = x.bi[b][i], b1r = x.br[b][k], b1i = x.bi[b][k];
-            double &r = (pair & 1) ? r1[b] : r0[b];
-            double &m = (pair & 1) ? i1[b] : i0[b];
+            const ProdT<CT> b0r = x.br[b][i], b0i = x.bi[b][i], b1r = x.br[b][k], b1i = x.bi[b][k];
+            ProdT<CT> &r = (pair & 1) ? r1[b] : r0[b];
+            ProdT<CT> &m = (pair & 1) ? i1[b] : i0[b];
             if (pair < 2) cfma<true, AX == 1>(r, m, a0r, a0i, b1r, b1i);
             else cfma<false, AX == 1>(r, m, a0r, a0i, b1r, b1i);
             cfma<false, false>(r, m, a1r, a1i, b0r, b0i);
@@ -266,7 +287,8 @@ __device__ __forceinline__ void prodw_xy(const Regs<CT, T, W> &x, double (&pr)[W
     }
 #pragma unroll
     for (int b = 0; b < W; ++b) {
-        const double sr = (T >= 4) ? r0[b] + r1[b] : r0[b], si = (T >= 4) ? i0[b] + i1[b] : i0[b];
+        const double sr = (T >= 4) ? (double)r0[b] + (double)r1[b] : (double)r0[b];
+        const double si = (T >= 4) ? (double)i0[b] + (double)i1[b] : (double)i0[b];
         pr[b] = AX == 0 ? sr : -si;
         pi[b] = AX == 0 ? si : sr;
     }
@@ -274,15 +296,15 @@ __device__ __forceinline__ void prodw_xy(const Regs<CT, T, W> &x, double (&pr)[W
 
 template <int J, int T, typename CT, int W>
 __device__ __forceinline__ void prodw_z_reg(const Regs<CT, T, W> &x, double (&pr)[W], double (&pi)[W]) {
-    double r0[W], i0[W], r1[W], i1[W];
+    ProdT<CT> r0[W], i0[W], r1[W], i1[W];
 #pragma unroll
     for (int i = 0; i < T; ++i) {
-        const double ar = x.ar[i], ai = x.ai[i];
+        const ProdT<CT> ar = x.ar[i], ai = x.ai[i];
         const bool neg = (i >> J) & 1;
 #pragma unroll
         for (int b = 0; b < W; ++b) {
-            double &r = (i & 1) ? r1[b] : r0[b];
-            double &m = (i & 1) ? i1[b] : i0[b];
+            ProdT<CT> &r = (i & 1) ? r1[b] : r0[b];
+            ProdT<CT> &m = (i & 1) ? i1[b] : i0[b];
             if (i < 2) {
                 if (neg) cfma<true, true>(r, m, ar, ai, x.br[b][i], x.bi[b][i]);
                 else cfma<true, false>(r, m, ar, ai, x.br[b][i], x.bi[b][i]);
@@ -294,29 +316,29 @@ __device__ __forceinline__ void prodw_z_reg(const Regs<CT, T, W> &x, double (&pr
     }
 #pragma unroll
     for (int b = 0; b < W; ++b) {
-        pr[b] = (T >= 2) ? r0[b] + r1[b] : r0[b];
-        pi[b] = (T >= 2) ? i0[b] + i1[b] : i0[b];
+        pr[b] = (T >= 2) ? (double)r0[b] + (double)r1[b] : (double)r0[b];
+        pi[b] = (T >= 2) ? (double)i0[b] + (double)i1[b] : (double)i0[b];
     }
 }
 
 template <int T, typename CT, int W>
 __device__ __forceinline__ void prodw_plain(const Regs<CT, T, W> &x, double (&pr)[W], double (&pi)[W]) {
-    double r0[W], i0[W], r1[W], i1[W];
+    ProdT<CT> r0[W], i0[W], r1[W], i1[W];
 #pragma unroll
     for (int i = 0; i < T; ++i) {
-        const double ar = x.ar[i], ai = x.ai[i];
+        const ProdT<CT> ar = x.ar[i], ai = x.ai[i];
 #pragma unroll
         for (int b = 0; b < W; ++b) {
-            double &r = (i & 1) ? r1[b] : r0[b];
-            double &m = (i & 1) ? i1[b] : i0[b];
+            ProdT<CT> &r = (i & 1) ? r1[b] : r0[b];
+            ProdT<CT> &m = (i & 1) ? i1[b] : i0[b];
             if (i < 2) cfma<true, false>(r, m, ar, ai, x.br[b][i], x.bi[b][i]);
             else cfma<false, false>(r, m, ar, ai, x.br[b][i], x.bi[b][i]);
         }
     }
 #pragma unroll
     for (int b = 0; b < W; ++b) {
-        pr[b] = (T >= 2) ? r0[b] + r1[b] : r0[b];
-        pi[b] = (T >= 2) ? i0[b] + i1[b] : i0[b];
+        pr[b] = (T >= 2) ? (double)r0[b] + (double)r1[b] : (double)r0[b];
+        pi[b] = (T >= 2) ? (double)i0[b] + (double)i1[b] : (double)i0[b];
     }
 }
 
@@ -1182,17 +1204,21 @@ void launch_ct(const LaunchItem *items, int n_items, uint32_t total_tiles, const
 
 }  // namespace
 
+#if !QNG_EXACT_PRODUCTS
 template <typename R>
 void launch_sweep_pass(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
                        const DevOp *ops, const DevMap *maps, const double *mats64, const float *mats32,
-                       double *partials, int m, int rb, bool f64_registers, int width, hipStream_t st) {
+                       double *partials, int m, int rb, int reg_mode, int width, hipStream_t st) {
     if (n_items <= 0 || total_tiles == 0) return;
     if constexpr (sizeof(R) == 8) {
-        (void)f64_registers;
+        (void)reg_mode;
         launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, partials, m, rb, width, st);
     } else {
-        if (f64_registers)
+        if (reg_mode == REG_F64)
             launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, partials, m, rb, width, st);
+        else if (reg_mode == REG_F32_EXACT)
+            launch_sweep_pass_exact(items, n_items, total_tiles, passes, ops, maps, mats32, partials, m, rb, width,
+                                    st);
         else
             launch_ct<R, float>(items, n_items, total_tiles, passes, ops, maps, mats32, partials, m, rb, width, st);
     }
@@ -1210,10 +1236,20 @@ void launch_reduce_tasks(const ReduceTask *tasks, int n_tasks, const double *par
 }
 
 template void launch_sweep_pass<double>(const LaunchItem *, int, uint32_t, const DevPass *, const DevOp *,
-                                        const DevMap *, const double *, const float *, double *, int, int, bool, int,
+                                        const DevMap *, const double *, const float *, double *, int, int, int, int,
                                         hipStream_t);
 template void launch_sweep_pass<float>(const LaunchItem *, int, uint32_t, const DevPass *, const DevOp *,
-                                       const DevMap *, const double *, const float *, double *, int, int, bool, int,
+                                       const DevMap *, const double *, const float *, double *, int, int, int, int,
                                        hipStream_t);
+#else
+void launch_sweep_pass_exact(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
+                             const DevOp *ops, const DevMap *maps, const float *mats32, double *partials, int m,
+                             int rb, int width, hipStream_t st) {
+    if (n_items <= 0 || total_tiles == 0) return;
+    launch_ct<float, float>(items, n_items, total_tiles, passes, ops, maps, mats32, partials, m, rb, width, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw e;
+}
+#endif
 
 }  // namespace qng

@@ -49,16 +49,18 @@ def rel_err(a, b):
     return float(np.abs(a - b).max(initial=0.0) / max(np.abs(b).max(initial=0.0), 1e-300))
 
 
-def step(ctx, qng, pr, prec, block, tile=0, f64=0):
+def step(ctx, qng, pr, prec, block, tile=0, f64=0, exact=0):
     ctx.set_option(qng.OPT_BLOCK_COLUMNS, block)
     ctx.set_option(qng.OPT_TILE_QUBITS, tile)
     ctx.set_option(qng.OPT_F64_REGISTERS, f64)
+    ctx.set_option(qng.OPT_EXACT_PRODUCTS, exact)
     try:
         return ctx.step(qng.Circuit.from_problem(pr), pr.theta, pr.dt, pr.tikhonov, in_state=pr.in_state, prec=prec)
     finally:
         ctx.set_option(qng.OPT_BLOCK_COLUMNS, 0)
         ctx.set_option(qng.OPT_TILE_QUBITS, 0)
         ctx.set_option(qng.OPT_F64_REGISTERS, 0)
+        ctx.set_option(qng.OPT_EXACT_PRODUCTS, 0)
 
 
 def check(res, want, pr, label):
@@ -97,13 +99,17 @@ def test_blocks_complex128(ctx, qng, label, make, tile):
     check(res, oracle.step(pr), pr, label)
 
 
-@pytest.mark.parametrize("f64", [0, 1])
+@pytest.mark.parametrize("mode", ["fp32", "fp64_registers", "exact_products"])
 @pytest.mark.parametrize("label,make,tile", CASES[:5], ids=[c[0] for c in CASES[:5]])
-def test_blocks_complex64(ctx, qng, label, make, tile, f64):
+def test_blocks_complex64(ctx, qng, label, make, tile, mode):
+    """complex64 storage in each register mode: FP32 registers with FP32
+    thread shares of the products (default), FP64 registers, and FP32
+    registers with every product in FP64."""
     pr = make()
-    say(f"case: {label} (n={pr.n_qubits}, P={pr.n_params}) c64 f64_registers={f64} block=2")
-    two = step(ctx, qng, pr, "c64", 2, 0, f64)
-    one = step(ctx, qng, pr, "c64", 1, 0, f64)
+    f64, exact = int(mode == "fp64_registers"), int(mode == "exact_products")
+    say(f"case: {label} (n={pr.n_qubits}, P={pr.n_params}) c64 {mode} block=2")
+    two = step(ctx, qng, pr, "c64", 2, 0, f64, exact)
+    one = step(ctx, qng, pr, "c64", 1, 0, f64, exact)
     want = oracle.step(pr)
     bound = 4 * pr.gates.shape[0] * 2.0 ** -24
     for key in ("G", "grad"):
