@@ -860,8 +860,9 @@ __device__ __forceinline__ void tile_sums(const Regs<CT, T, W> &x, double2 *sink
 
 // Occupancy target: three waves per SIMD (the 53 KB of LDS of a work-group
 // allow three per CU).  The 16-amplitude kernel with one phi register reaches
-// it by itself (158 VGPRs) and gets no bound; with two phi registers it is
-// held to 168 VGPRs, spilling a few values in the exchanges only.
+// it by itself (114 VGPRs; 158 with every product in FP64) and gets no bound;
+// with two phi registers it is held to 168 VGPRs (it needs 146; with every
+// product in FP64 a few values spill in the exchanges).
 template <typename R, typename CT, int RB, bool FULL, int W>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 1 ? (RB >= 4 ? 1 : 3) : 3, 8))) void k_sweep_reg(const LaunchItem *__restrict__ items, int n_items,
                                                         const DevPass *__restrict__ passes,
