@@ -158,7 +158,7 @@ Layout plan_layout(int n, int P, size_t param_map_ints, size_t amp_bytes, int n_
     L.n_states = n_states;
     L.states = take(L.state_bytes * n_states);
     L.staging = staging ? take((size_t(1) << n) * 16) : 0;
-    L.partials = take((size_t)reduce_blocks(n) * 16 + 16);
+    L.partials = take((size_t)reduce_blocks(n) * kStepMaxPhi * 16 + 16);
     L.lraw = take((size_t)P * P * 16 + (size_t)P * 16 + 16);
     L.traw = L.lraw + (size_t)P * P * 16;   // T right after L: column blocks reduce both into one array
     L.graw = take((size_t)P * 16 + 16);
@@ -308,8 +308,11 @@ template <typename R> struct Engine {
     char *gscratch = nullptr;
     size_t gscratch_bytes = 0;
     int reg_mode = REG_F32;
+    bool stepped = false;     // one kernel per sweep step (circuits the fused passes do not take)
 
-    void *state(int k) const { return regs[k]; }
+    // registers 0..2 as given; further ones (the phi registers of a stepped
+    // block) follow psi contiguously, as run() lays them out
+    void *state(int k) const { return k < 3 ? regs[k] : (char *)regs[0] + (size_t)k * state_bytes; }
     double *partials() const { return partials_; }
     double *lraw() const { return lraw_; }
     double *traw() const { return traw_; }
@@ -325,6 +328,44 @@ template <typename R> struct Engine {
     void prod(const void *a, const void *b, int q, int axis, double *dest, int ctrl = -1) {
         ctx->stats.other_launches += 2;
         launch_pauli_prod<R>(a, b, n, q, axis, partials(), dest, st, ctrl);
+    }
+
+    // One back-sweep step of rotation r (gate position pos) over lambda and the
+    // phi registers of sr: <lambda|K_r|phi_k> into dests (if given), then the
+    // adjoint of r on all of them.
+    StepGate step_gate(const Rot &r, int pos) const {
+        StepGate g{};
+        g.n = n;
+        const Mat2 &a = pb.adj[pos];
+        if (r.string >= 0) {
+            // adjoint c - i s S = c + kappa S' with kappa = (-i s) w (a.b holds -i s)
+            g.kind = STEP_STRING;
+            g.flip = r.flip;
+            g.zy = r.zy;
+            cd w(1, 0);
+            for (int k = 0; k < (r.n_y & 3); ++k) w *= cd(0, -1);
+            g.wr = w.real();
+            g.wi = w.imag();
+            const cd kappa = a.b * w;
+            g.m[0] = a.a.real();
+            g.m[2] = kappa.real();
+            g.m[3] = kappa.imag();
+        } else {
+            g.kind = r.ctrl >= 0 ? STEP_C1Q : STEP_1Q;
+            g.q = r.qubit;
+            g.c = r.ctrl;
+            g.axis = r.axis;
+            const cd e[4] = {a.a, a.b, a.c, a.d};
+            for (int k = 0; k < 4; ++k) {
+                g.m[2 * k] = e[k].real();
+                g.m[2 * k + 1] = e[k].imag();
+            }
+        }
+        return g;
+    }
+    void step(const StepRegs &sr, int r, int pos, const StepDests *dests) {
+        ctx->stats.other_launches += dests && sr.n_phi ? 2 : 1;
+        launch_sweep_step<R>(sr, step_gate(pb.circ.rots[r], pos), partials(), dests, st);
     }
 
     // <a| K_r |b> for the generator K_r of rotation r
@@ -388,6 +429,57 @@ template <typename R> struct Engine {
         return pos;
     }
 
+    // Recurrent metric for circuits the fused passes do not take (controlled
+    // and Pauli-string rotations): columns in blocks of up to `width`
+    // consecutive rotations share one lambda sweep, as in the fused passes --
+    // lambda swept back from the top column is the forward state y_r at every
+    // rotation r, so the block's lower columns are seeded from it on the way
+    // down -- and every step is one kernel over lambda and the block's phi
+    // registers (state(2) .. state(1 + width)).  On return psi holds y_{P-1}.
+    int metric_stepped(int width) {
+        const Circuit &c = pb.circ;
+        void *psi = state(0), *lam = state(1);
+        int pos = 0;
+        const int p0 = c.P ? c.rots[0].pos : 0;
+        for (int s0 = 0; s0 < c.P; s0 += width) {
+            const int s1 = std::min(c.P, s0 + width) - 1;
+            for (int s = s0; s <= s1; ++s) {
+                const Rot &rs = c.rots[s];
+                for (; pos < rs.pos; ++pos) apply(pos, false, psi, nullptr);
+                rprod(psi, psi, rs, traw() + 2 * s);                      // <y_s|K_s|y_s>
+                if (rs.ctrl >= 0) prod(psi, psi, rs.ctrl, -1, lraw() + 2 * ((size_t)s * c.P + s), rs.ctrl);
+            }
+            if (s1 == 0) continue;
+            StepRegs sr{};
+            sr.lam = lam;
+            int col[kStepMaxPhi];
+            rseed(psi, lam, state(2), c.rots[s1]);
+            sr.phi[0] = state(2);
+            col[0] = s1;
+            sr.n_phi = 1;
+            for (int k = c.rots[s1].pos - 1; k >= p0; --k) {
+                const int r = c.rot_at[k];
+                if (r < 0) {
+                    const qng_gate &g = c.gates[k];
+                    ++ctx->stats.other_launches;
+                    launch_fixed_multi<R>(sr, n, g.kind == QNG_CNOT, g.q0, g.q1, st);
+                    continue;
+                }
+                StepDests d{};
+                d.base = lraw();
+                for (int j = 0; j < sr.n_phi; ++j) d.off[j] = (int64_t)r * c.P + col[j];
+                step(sr, r, k, &d);
+                ctx->stats.elements += sr.n_phi;
+                if (r >= s0 && r > 0) {           // lambda = y_r: column r starts here
+                    rseed(lam, lam, state(2 + sr.n_phi), c.rots[r]);
+                    sr.phi[sr.n_phi] = state(2 + sr.n_phi);
+                    col[sr.n_phi++] = r;
+                }
+            }
+        }
+        return pos;
+    }
+
     // From psi at gate position pos: finish the forward pass, lambda = H psi,
     // E = <psi|lambda>, then the reverse sweep for the gradient.  If keep_psi,
     // the final state is copied to state(3) before the sweep modifies psi.
@@ -405,6 +497,25 @@ template <typename R> struct Engine {
             return;
         }
         const int p0 = c.rots[0].pos;
+        if (stepped) {
+            // one kernel per rotation: <lambda|K_r|psi> and the adjoint on both
+            StepRegs sr{};
+            sr.lam = lam;
+            sr.phi[0] = psi;
+            sr.n_phi = 1;
+            for (int k = c.M - 1; k >= p0; --k) {
+                const int r = c.rot_at[k];
+                if (r >= 0) {
+                    StepDests d{};
+                    d.base = graw();
+                    d.off[0] = r;
+                    step(sr, r, k, &d);
+                } else {
+                    apply(k, true, lam, psi);
+                }
+            }
+            return;
+        }
         for (int k = c.M - 1; k >= p0; --k) {
             const int r = c.rot_at[k];
             if (r >= 0) {
@@ -510,6 +621,22 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
         gplan = ctx->sweep_cache.get_gradient(c, ctx->opt_tile, (int)amp, f64_regs);
         scratch = std::max(scratch, fused_gradient_scratch_bytes(*gplan, c.M));
     }
+    // circuits the fused passes do not take: one kernel per sweep step, with up
+    // to kStepMaxPhi columns per lambda sweep as memory allows (half of what is
+    // free, and the context's limit)
+    const bool stepped = ctx->opt_fusion != 0 && c.extended();
+    int step_width = 0;
+    if (stepped && spec.metric && pb.rot_block.empty() && c.P > 1) {
+        size_t free_b = 0, total_b = 0;
+        HIPCHECK(hipMemGetInfo(&free_b, &total_b));
+        size_t budget = (free_b + ctx->ws_bytes) / 2;
+        if (ctx->mem_limit) budget = std::min(budget, ctx->mem_limit);
+        const size_t fixed = (size_t)c.P * c.P * 48 + ((size_t)1 << n) * 16 + ((size_t)64 << 20);
+        const size_t fit = budget > fixed ? (budget - fixed) / V : 0;
+        step_width = (int)std::min<size_t>(kStepMaxPhi, fit > 2 ? fit - 2 : 0);
+        if (step_width < 2) step_width = 0;     // the one-column loop needs 3 registers
+        n_states = std::max(n_states, 2 + step_width);
+    }
     Layout L = plan_layout(n, c.P, param_map_ints(c), amp, n_states, spec.in_host != nullptr, scratch);
     char *base = ensure_workspace(ctx, L.total);
     hipStream_t st = ctx->stream;
@@ -523,6 +650,7 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
         e.gscratch_bytes = L.sweep_bytes;
         e.reg_mode = sweep_reg_mode(ctx, amp);
     }
+    e.stepped = stepped;
 
     const void *in_c128 = spec.in_dev;
     if (spec.in_host) {
@@ -552,6 +680,8 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
             fb.reduce_partials = e.partials();
             pos = run_fused_metric<R>(*plan, fr, c, pb.fwd, pb.adj, fb, st, &ctx->stats, ctx->opt_profile != 0,
                                       sweep_reg_mode(ctx, amp));
+        } else if (step_width > 0) {
+            pos = e.metric_stepped(step_width);
         } else {
             pos = e.metric_unfused();
         }

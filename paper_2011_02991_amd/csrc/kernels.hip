@@ -403,6 +403,202 @@ __global__ void k_advance_seed(typename Cplx<R>::T *psi, typename Cplx<R>::T *la
     block_reduce_store(sr, si, partials + 2 * blockIdx.x);
 }
 
+// ------------------------------------------------------------------ sweep steps
+//
+// One step of the recurrence's back sweep over lambda and several phi
+// registers at once (columns of one block): for the rotation r at this step,
+// <lambda|K_r|phi_k> for every phi register from the values before the step,
+// then the adjoint of r on lambda and every phi (K_r commutes with r, so the
+// product is the same before or after).  The threads walk the index groups of
+// the rotation's own structure, which is also the structure of K_r:
+//   STEP_1Q     pairs (i0, i0 | 2^q), K = sigma on the pair;
+//   STEP_C1Q    the pairs with control bit c set, K = sigma there (zero elsewhere,
+//               where the gate also acts as the identity);
+//   STEP_STRING pairs (x0, x0 ^ flip) with the highest flip bit clear in x0, or
+//               single amplitudes when flip = 0; K = S.
+
+template <typename C>
+__device__ __forceinline__ C cmul(C a, double br, double bi) {   // a * (br + i bi)
+    C o;
+    o.x = a.x * br - a.y * bi;
+    o.y = a.x * bi + a.y * br;
+    return o;
+}
+
+// 2x2 adjoint matrix (row-major a, b, c, d; re, im) on the pair (u, v)
+template <typename C, typename RR>
+__device__ __forceinline__ void mat2(const RR (&m)[8], C &u, C &v) {
+    const C a = u, b = v;
+    u.x = m[0] * a.x - m[1] * a.y + m[2] * b.x - m[3] * b.y;
+    u.y = m[0] * a.y + m[1] * a.x + m[2] * b.y + m[3] * b.x;
+    v.x = m[4] * a.x - m[5] * a.y + m[6] * b.x - m[7] * b.y;
+    v.y = m[4] * a.y + m[5] * a.x + m[6] * b.y + m[7] * b.x;
+}
+
+template <int KIND, typename R>
+__global__ void k_sweep_step(StepRegs regs, StepGate g, double *partials) {
+    using C = typename Cplx<R>::T;
+    constexpr int M = kStepMaxPhi;
+    const int nphi = regs.n_phi;
+    const int n = g.n;
+    R m[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) m[k] = (R)g.m[k];
+    double sr[M], si[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) sr[k] = si[k] = 0.0;
+    C *lam = (C *)regs.lam;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    // K on a pair of values (w0, w1) at indices (x0, x1): (o0, o1)
+    auto apply_k = [&](const C &w0, const C &w1, uint64_t x0, uint64_t x1, C &o0, C &o1) {
+        if constexpr (KIND == STEP_STRING) {
+            const double g0 = string_sign(x0, g.zy), g1 = string_sign(x1, g.zy);
+            o0 = cmul(w1, g0 * g.wr, g0 * g.wi);
+            o1 = cmul(w0, g1 * g.wr, g1 * g.wi);
+        } else {
+            pauli_pair(g.axis, w0, w1, o0, o1);
+        }
+    };
+    if (KIND == STEP_STRING && g.flip == 0) {
+        // diagonal string: K = sgn(x) (no Y letter), the adjoint is c + kappa sgn(x)
+        const uint64_t dim = uint64_t(1) << n;
+        for (uint64_t x = blockIdx.x * (uint64_t)kBlock + threadIdx.x; x < dim; x += stride) {
+            const double gx = string_sign(x, g.zy);
+            const R fr = m[0] + (R)gx * m[2], fi = (R)gx * m[3];
+            const C l = lam[x];
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                if (k >= nphi) break;
+                C *ph = (C *)regs.phi[k];
+                C f = ph[x];
+                cmac(sr[k], si[k], l.x, l.y, gx * (double)f.x, gx * (double)f.y);
+                const C t = f;
+                f.x = fr * t.x - fi * t.y;
+                f.y = fr * t.y + fi * t.x;
+                ph[x] = f;
+            }
+            C o;
+            o.x = fr * l.x - fi * l.y;
+            o.y = fr * l.y + fi * l.x;
+            lam[x] = o;
+        }
+    } else {
+        const uint64_t npairs = uint64_t(1) << (KIND == STEP_C1Q ? n - 2 : n - 1);
+        const int lo = g.c < g.q ? g.c : g.q, hi = g.c < g.q ? g.q : g.c;
+        const int hb = KIND == STEP_STRING ? 63 - __clzll(g.flip) : 0;
+        for (uint64_t p = blockIdx.x * (uint64_t)kBlock + threadIdx.x; p < npairs; p += stride) {
+            uint64_t x0, x1;
+            if constexpr (KIND == STEP_1Q) {
+                x0 = insert_zero(p, g.q);
+                x1 = x0 | (uint64_t(1) << g.q);
+            } else if constexpr (KIND == STEP_C1Q) {
+                x0 = insert_two_zeros(p, lo, hi) | (uint64_t(1) << g.c);
+                x1 = x0 | (uint64_t(1) << g.q);
+            } else {
+                x0 = insert_zero(p, hb);
+                x1 = x0 ^ g.flip;
+            }
+            C l0 = lam[x0], l1 = lam[x1];
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                if (k >= nphi) break;
+                C *ph = (C *)regs.phi[k];
+                C f0 = ph[x0], f1 = ph[x1], k0, k1;
+                apply_k(f0, f1, x0, x1, k0, k1);
+                cmac(sr[k], si[k], l0.x, l0.y, k0.x, k0.y);
+                cmac(sr[k], si[k], l1.x, l1.y, k1.x, k1.y);
+                if constexpr (KIND == STEP_STRING) {
+                    // c + kappa S' on the pair: S' maps x1 -> x0 with sgn(x0), x0 -> x1 with sgn(x1)
+                    const double g0 = string_sign(x0, g.zy), g1 = string_sign(x1, g.zy);
+                    const C a = f0, b = f1;
+                    f0.x = m[0] * a.x + (R)g0 * (m[2] * b.x - m[3] * b.y);
+                    f0.y = m[0] * a.y + (R)g0 * (m[2] * b.y + m[3] * b.x);
+                    f1.x = m[0] * b.x + (R)g1 * (m[2] * a.x - m[3] * a.y);
+                    f1.y = m[0] * b.y + (R)g1 * (m[2] * a.y + m[3] * a.x);
+                } else {
+                    mat2(m, f0, f1);
+                }
+                ph[x0] = f0;
+                ph[x1] = f1;
+            }
+            if constexpr (KIND == STEP_STRING) {
+                const double g0 = string_sign(x0, g.zy), g1 = string_sign(x1, g.zy);
+                const C a = l0, b = l1;
+                l0.x = m[0] * a.x + (R)g0 * (m[2] * b.x - m[3] * b.y);
+                l0.y = m[0] * a.y + (R)g0 * (m[2] * b.y + m[3] * b.x);
+                l1.x = m[0] * b.x + (R)g1 * (m[2] * a.x - m[3] * a.y);
+                l1.y = m[0] * b.y + (R)g1 * (m[2] * a.y + m[3] * a.x);
+            } else {
+                mat2(m, l0, l1);
+            }
+            lam[x0] = l0;
+            lam[x1] = l1;
+        }
+    }
+    if (nphi == 0) return;
+    // block sums of every product, one after the other through one LDS array
+    __shared__ double sh[2 * kBlock];
+    for (int k = 0; k < nphi; ++k) {
+        double vr = 0.0, vi = 0.0;
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+            if (j == k) { vr = sr[j]; vi = si[j]; }
+        __syncthreads();
+        sh[threadIdx.x] = vr;
+        sh[kBlock + threadIdx.x] = vi;
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) {
+                sh[threadIdx.x] += sh[threadIdx.x + w];
+                sh[kBlock + threadIdx.x] += sh[kBlock + threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            partials[2 * ((size_t)blockIdx.x * M + k)] = sh[0];
+            partials[2 * ((size_t)blockIdx.x * M + k) + 1] = sh[kBlock];
+        }
+    }
+}
+
+// dest[k] (complex128 at base + 2 * off[k]) = sum over blocks of partials[block][k]
+__global__ void k_reduce_steps(const double *partials, int nb, StepDests d) {
+    const int k = blockIdx.x;
+    double sr = 0.0, si = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) {
+        sr += partials[2 * ((size_t)b * kStepMaxPhi + k)];
+        si += partials[2 * ((size_t)b * kStepMaxPhi + k) + 1];
+    }
+    block_reduce_store(sr, si, d.base + 2 * d.off[k]);
+}
+
+// A fixed gate on lambda and every phi register: CNOT (swap the target pair
+// where the control is 1) or CZ (negate where both bits are 1).
+template <bool IS_CNOT, typename R>
+__global__ void k_fixed_multi(StepRegs regs, int n, int a, int b) {
+    using C = typename Cplx<R>::T;
+    const uint64_t nq = uint64_t(1) << (n - 2);
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    for (uint64_t p = blockIdx.x * (uint64_t)kBlock + threadIdx.x; p < nq; p += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t base = insert_two_zeros(p, lo, hi) | (uint64_t(1) << a);
+        for (int k = -1; k < regs.n_phi; ++k) {
+            C *s = (C *)(k < 0 ? regs.lam : regs.phi[k]);
+            if constexpr (IS_CNOT) {
+                const uint64_t i1 = base | (uint64_t(1) << b);
+                const C u = s[base], v = s[i1];
+                s[base] = v;
+                s[i1] = u;
+            } else {
+                const uint64_t i = base | (uint64_t(1) << b);
+                C u = s[i];
+                u.x = -u.x;
+                u.y = -u.y;
+                s[i] = u;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ Hamiltonian
 
 template <typename R>
@@ -581,6 +777,41 @@ void launch_string_prod(const void *a, const void *b, int n, uint64_t flip, uint
     check_launch();
 }
 
+template <typename R>
+void launch_sweep_step(const StepRegs &regs, const StepGate &g, double *partials, const StepDests *dests,
+                       hipStream_t st) {
+    if (regs.n_phi < 0 || regs.n_phi > kStepMaxPhi) throw hipErrorInvalidValue;
+    const int nb = reduce_blocks(g.n);
+    switch (g.kind) {
+    case STEP_1Q:
+        hipLaunchKernelGGL((k_sweep_step<STEP_1Q, R>), dim3(nb), dim3(kBlock), 0, st, regs, g, partials);
+        break;
+    case STEP_C1Q:
+        hipLaunchKernelGGL((k_sweep_step<STEP_C1Q, R>), dim3(nb), dim3(kBlock), 0, st, regs, g, partials);
+        break;
+    case STEP_STRING:
+        hipLaunchKernelGGL((k_sweep_step<STEP_STRING, R>), dim3(nb), dim3(kBlock), 0, st, regs, g, partials);
+        break;
+    default: throw hipErrorInvalidValue;
+    }
+    check_launch();
+    if (regs.n_phi > 0 && dests) {
+        hipLaunchKernelGGL(k_reduce_steps, dim3(regs.n_phi), dim3(kBlock), 0, st, (const double *)partials, nb, *dests);
+        check_launch();
+    }
+}
+
+template <typename R> void launch_fixed_multi(const StepRegs &regs, int n, bool cnot, int a, int b, hipStream_t st) {
+    if (regs.n_phi < 0 || regs.n_phi > kStepMaxPhi) throw hipErrorInvalidValue;
+    if (cnot)
+        hipLaunchKernelGGL((k_fixed_multi<true, R>), dim3(grid_for(uint64_t(1) << (n - 2))), dim3(kBlock), 0, st, regs,
+                           n, a, b);
+    else
+        hipLaunchKernelGGL((k_fixed_multi<false, R>), dim3(grid_for(uint64_t(1) << (n - 2))), dim3(kBlock), 0, st, regs,
+                           n, a, b);
+    check_launch();
+}
+
 template <typename R> void launch_cnot(void *s0, void *s1, int n, int c, int t, hipStream_t st) {
     hipLaunchKernelGGL(k_cnot<R>, dim3(grid_for(uint64_t(1) << (n - 2))), dim3(kBlock), 0, st,
                        (typename Cplx<R>::T *)s0, (typename Cplx<R>::T *)s1, n, c, t);
@@ -678,6 +909,9 @@ void launch_grad_from_raw(const double *graw, const int *param_of, int P, double
     template void launch_seed_string<R>(const void *, void *, void *, int, uint64_t, uint64_t, int, hipStream_t);  \
     template void launch_string_prod<R>(const void *, const void *, int, uint64_t, uint64_t, int, double *,        \
                                         double *, hipStream_t);                                                   \
+    template void launch_sweep_step<R>(const StepRegs &, const StepGate &, double *, const StepDests *,           \
+                                       hipStream_t);                                                              \
+    template void launch_fixed_multi<R>(const StepRegs &, int, bool, int, int, hipStream_t);                      \
     template void launch_cnot<R>(void *, void *, int, int, int, hipStream_t);                                     \
     template void launch_cz<R>(void *, void *, int, int, int, hipStream_t);                                       \
     template void launch_seed<R>(const void *, void *, void *, int, int, int, hipStream_t, int);                 \

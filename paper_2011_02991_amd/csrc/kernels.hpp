@@ -23,6 +23,36 @@ struct DevMat2 {   // 2x2 complex matrix, FP64, row-major
 // Number of first-stage blocks used by the reductions for a register of n qubits.
 int reduce_blocks(int n);
 
+// One step of the back sweep over lambda and up to kStepMaxPhi phi registers
+// (the columns of a block share lambda): launch_sweep_step takes
+// <lambda|K|phi_k> for every phi register, K the generator of the step's
+// rotation, then applies the rotation's adjoint to lambda and every phi.
+constexpr int kStepMaxPhi = 8;
+enum StepKind : int { STEP_1Q = 0, STEP_C1Q = 1, STEP_STRING = 2 };
+struct StepRegs {
+    void *lam;
+    void *phi[kStepMaxPhi];
+    int n_phi;
+};
+struct StepGate {
+    int kind, n;
+    int q, c, axis;          // STEP_1Q: target q, generator axis; STEP_C1Q: also control c
+    uint64_t flip, zy;       // STEP_STRING: the string in mask form (w = wr + i wi = (-i)^{n_y})
+    double wr, wi;
+    double m[8];             // the adjoint: 2x2 matrix (row-major, re/im), or for a string
+                             // m[0] = c and (m[2], m[3]) = kappa of c + kappa S' (S = w S')
+};
+struct StepDests {            // product k goes to the complex128 at base + 2 * off[k]
+    double *base;
+    int64_t off[kStepMaxPhi];
+};
+// partials: reduce_blocks(n) * kStepMaxPhi complex128.  dests == nullptr: no products kept.
+template <typename R>
+void launch_sweep_step(const StepRegs &regs, const StepGate &g, double *partials, const StepDests *dests,
+                       hipStream_t st);
+// CNOT (cnot = true; control a, target b) or CZ on lambda and every phi register.
+template <typename R> void launch_fixed_multi(const StepRegs &regs, int n, bool cnot, int a, int b, hipStream_t st);
+
 template <typename R> void launch_init_state(void *dst, int n, const void *src_c128, hipStream_t st);
 template <typename R> void launch_to_c128(const void *src, void *dst, int n, hipStream_t st);
 template <typename R> void launch_copy(const void *src, void *dst, int n, hipStream_t st);

@@ -222,3 +222,31 @@ def test_controlled_n22_sampled(env):
     # Re G symmetric, diagonal = 1/4 or 1/4 Prob(control) - |T|^2 >= 0
     assert np.allclose(res["G"], res["G"].conj().T, atol=1e-14)
     assert (np.diag(res["G"]).real >= -1e-14).all()
+
+
+@pytest.mark.parametrize("make", [lambda: W.controlled_layers(9, 3, 6, 5280),
+                                  lambda: W.string_circuit(10, 61, 5281, n_terms=6),
+                                  lambda: W.share_params(W.controlled_circuit(8, 45, 5282), 11, 5283)])
+def test_stepped_blocks_match_per_primitive_kernels(env, make):
+    """With fusion on, these circuits sweep up to 8 columns per lambda sweep, one
+    kernel per step (products of every column, then the adjoint); with fusion
+    off, one kernel per primitive.  P is not a multiple of 8, so the last block
+    is ragged.  Both against each other and against the oracle."""
+    torch, q, ctx = env
+    pr = make()
+    pr.in_state = W.random_state(pr.n_qubits, 5284)
+    circ = q.Circuit.from_problem(pr)
+    say(f"case: {pr.name} (P={pr.n_params}, rotations={(pr.gates[:, 3] >= 0).sum()})")
+    a = ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, in_state=pr.in_state)
+    st = ctx.stats()
+    ctx.set_option(q.OPT_FUSION, 0)
+    try:
+        b = ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, in_state=pr.in_state)
+        st0 = ctx.stats()
+    finally:
+        ctx.set_option(q.OPT_FUSION, 1)
+    say(f"launches: stepped {st['other_launches']}, per primitive {st0['other_launches']}")
+    assert st["other_launches"] < st0["other_launches"]
+    for key in ("G", "grad"):
+        assert rel_err(a[key], b[key]) <= 1e-12, key
+    check(a, oracle.step(pr), pr, TOL, pr.name + " stepped")
