@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--f64-regs", type=int, default=0, help="complex64: compute sweep tiles in FP64 registers")
     ap.add_argument("--exact-products", type=int, default=0,
                     help="complex64 with FP32 registers: form every inner-product term in FP64")
+    ap.add_argument("--no-with-g", action="store_true",
+                    help="skip timing the step that also returns the complex G")
     ap.add_argument("--no-exact", action="store_true",
                     help="skip the complex64 leg with every inner-product term in FP64")
     ap.add_argument("--variants", action="store_true",
@@ -58,9 +60,13 @@ def parse():
     return ap.parse_args()
 
 
-def time_steps(ctx, circ, pr, prec, steps, warmup, profile=False):
-    """Time `steps` full steps; with profile, HIP events bracket every sweep-pass
-    launch on the library's stream during the timed steps themselves."""
+def time_steps(ctx, circ, pr, prec, steps, warmup, profile=False, want_G=False, need_G=True):
+    """Time `steps` full steps (dtheta, grad E and E out; the metric enters the
+    solve as Re G, so without a G output the library keeps the real parts of
+    its inner products); with profile, HIP events bracket every sweep-pass
+    launch on the library's stream during the timed steps themselves.  Returns
+    the time, the last step's results (with G: one further untimed step with
+    the G output when need_G) and the counters of the timed steps."""
     import torch
     import paper_2011_02991_amd as qng
     ctx.set_option(qng.OPT_PROFILE, 0)
@@ -72,13 +78,15 @@ def time_steps(ctx, circ, pr, prec, steps, warmup, profile=False):
     t0 = time.perf_counter()
     res = None
     for _ in range(steps):
-        res = ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, prec=prec, want_G=True)
+        res = ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, prec=prec, want_G=want_G)
         for k, v in ctx.stats().items():
             # counters add up over the steps; settings are the last step's
             acc[k] = v if k in ("block_columns", "tile_qubits", "target_tiles") else acc.get(k, 0) + v
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     ctx.set_option(qng.OPT_PROFILE, 0)
+    if not want_G and need_G:
+        res = ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, prec=prec, want_G=True)
     return dt, res, acc
 
 
@@ -320,7 +328,8 @@ def main():
     ctx.set_option(qng.OPT_F64_REGISTERS, args.f64_regs)
     ctx.set_option(qng.OPT_EXACT_PRODUCTS, args.exact_products)
     ctx.set_option(qng.OPT_BLOCK_COLUMNS, args.block)
-    t_chosen, res, st = time_steps(ctx, circ, pr, args.prec, args.steps, args.warmup, profile=True)
+    t_chosen, res, st = time_steps(ctx, circ, pr, args.prec, args.steps, args.warmup, profile=True,
+                                   need_G=not args.no_plain)
     log(f"{args.prec}: {t_chosen:.3f} s/step  stats={st}")
     plain = precision = None
     if not args.no_plain:
@@ -333,6 +342,11 @@ def main():
         else:
             precision = precision_report(pr, res_other, res, "c64", "c128")
         log(f"precision: {precision}")
+    # the same step asked for the complex G as well (full inner products)
+    t_with_G = None
+    if not args.no_with_g:
+        t_with_G, _, _ = time_steps(ctx, circ, pr, args.prec, max(1, args.steps - 1), 0, want_G=True)
+        log(f"{args.prec} with the G output: {t_with_G:.3f} s/step")
     exact = None
     if args.prec == "c64" and not args.f64_regs and not args.exact_products and not args.no_exact:
         # the same step with every inner-product term formed in FP64
@@ -378,7 +392,8 @@ def main():
                    "tile_qubits": args.tile or None, "f64_registers": bool(args.f64_regs),
                    "exact_products": bool(args.exact_products),
                    "block_columns": st.get("block_columns")},
-        "plain_fp64": plain, "precision_errors": precision, "c64_exact_fp64_products": exact, "gate_apply": gate, "roofline": roof, "cpu_baseline": cpu,
+        "plain_fp64": plain, "precision_errors": precision, "c64_exact_fp64_products": exact,
+        "step_with_G_output_s": t_with_G, "gate_apply": gate, "roofline": roof, "cpu_baseline": cpu,
         "metric_variants": variants, "extended_gates": gateset,
         "breakdown_ms": {k: st[k] / args.steps for k in ("metric_ms", "grad_ms", "solve_ms")},
     }

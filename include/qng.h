@@ -156,8 +156,10 @@ typedef struct {
     double  sweep_bytes;         /* algorithmic HBM bytes of those launches: read+write of lambda and of the phi
                                     states of each pass (2 states; 3 for a block of two columns) */
     double  sweep_flops;         /* algorithmic FLOPs of those launches, per amplitude per element: 8 for
-                                    <lambda|sigma|phi>, 6 for the rotation adjoint on phi, 6 on lambda shared by
-                                    the columns of a block (20 for one column per sweep, 17 for two) */
+                                    <lambda|sigma|phi> (4 for its real part, taken when qng_step has no G
+                                    output), 6 for the rotation adjoint on phi, 6 on lambda shared by the
+                                    columns of a block (20 for one column per sweep, 17 for two; 13 for two
+                                    with real parts) */
     int64_t elements;            /* L_ij (i<j) elements evaluated */
     int64_t other_launches;      /* every other kernel launch */
     double  metric_ms;           /* wall-clock of the metric part (G) */
@@ -261,7 +263,10 @@ qng_status qng_energy_grad(qng_ctx *ctx, const qng_circuit *circ, const double *
                            double *E_out, double *grad_out);
 
 /* One natural-gradient step (Sec. 1): dtheta solving (Re G + eps I) dtheta = -dt grad E.
- * G_out (2*P*P), grad_out (P), E_out (1) are optional (NULL = not returned). */
+ * G_out (2*P*P), grad_out (P), E_out (1) are optional (NULL = not returned).
+ * The solve reads Re G only; with G_out = NULL the fused passes form only the
+ * real parts of the metric's inner products (half their multiply-adds), with
+ * G_out the full complex G is computed and returned. */
 qng_status qng_step(qng_ctx *ctx, const qng_circuit *circ, const double *in_state,
                     const qng_pauli_sum *ham, const double *theta, double dt, double tikhonov,
                     qng_precision prec, double *dtheta_out, double *G_out, double *grad_out,

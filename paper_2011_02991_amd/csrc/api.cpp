@@ -548,6 +548,7 @@ struct CallSpec {
     void *psi_out_dev = nullptr;          // complex128 device copy of the final state (nullable)
     bool host_call = false;               // synchronous host-pointer entry point: time each phase
     const void *psi_final_dev = nullptr;  // gradient from a given final state (nullable)
+    bool real_products = false;           // fused metric: real parts of L only (the caller needs Re G)
 };
 
 // Columns per lambda sweep of the fused metric.  Blocks of two columns need
@@ -679,7 +680,7 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
             fb.lraw = e.lraw();
             fb.reduce_partials = e.partials();
             pos = run_fused_metric<R>(*plan, fr, c, pb.fwd, pb.adj, fb, st, &ctx->stats, ctx->opt_profile != 0,
-                                      sweep_reg_mode(ctx, amp));
+                                      sweep_reg_mode(ctx, amp), spec.real_products);
         } else if (step_width > 0) {
             pos = e.metric_stepped(step_width);
         } else {
@@ -1350,6 +1351,9 @@ qng_status qng_step(qng_ctx *ctx, const qng_circuit *circ, const double *in_stat
             spec.grad = true;
             spec.in_host = in_state;
             spec.host_call = true;
+            // the solve reads Re G only: without a G output, the metric's
+            // inner products keep their real parts
+            spec.real_products = G_out == nullptr;
             CallResult r = run<R>(ctx, pb, spec);
             if (P) {
                 HIPCHECK(hipMemcpyAsync(G.data(), r.G, (size_t)NP * NP * 16, hipMemcpyDeviceToHost, ctx->stream));

@@ -50,7 +50,7 @@ size_t fused_scratch_bytes(const SweepPlan &plan, const FusedRun &fr, int M) {
 template <typename R>
 int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c, const std::vector<Mat2> &fwd,
                      const std::vector<Mat2> &adj, const FusedBuffers &buf, hipStream_t st, qng_stats *stats,
-                     bool profile, int reg_mode) {
+                     bool profile, int reg_mode, bool real_products) {
     const int n = c.n;
     const size_t V = buf.state_bytes;
     const uint32_t tiles = 1u << (n - plan.m);
@@ -207,14 +207,15 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
             const Launch &L = launches[li];
             if (profile) FCHECK(hipEventRecord(ev[2 * li], st));
             launch_sweep_pass<R>(d_items + L.item_begin, (int)L.n_items, L.total_tiles, d_passes, d_ops, d_maps,
-                                 d_mats, d_mats32, d_partials, plan.m, plan.rb, reg_mode, W, st);
+                                 d_mats, d_mats32, d_partials, plan.m, plan.rb, reg_mode, W, st, real_products);
             if (profile) FCHECK(hipEventRecord(ev[2 * li + 1], st));
             launch_reduce_tasks(d_tasks + L.task_begin, (int)L.n_tasks, d_partials, buf.lraw, st);
             ++stats->sweep_launches;
             ++stats->other_launches;
             stats->sweep_tiles += L.total_tiles;
             stats->sweep_bytes += (double)L.n_items * 2.0 * (W + 1) * (double)V;
-            stats->sweep_flops += sweep_flops_per_amp(W) * (double)L.n_tasks * (double)((uint64_t)1 << n);
+            stats->sweep_flops +=
+                sweep_flops_per_amp(W, real_products) * (double)L.n_tasks * (double)((uint64_t)1 << n);
         }
     }
     stats->elements += elements;
@@ -335,8 +336,10 @@ template void run_fused_gradient<float>(const SweepPlan &, const Circuit &, cons
                                         double *, char *, size_t, hipStream_t, qng_stats *, bool, int);
 
 template int run_fused_metric<double>(const SweepPlan &, const FusedRun &, const Circuit &, const std::vector<Mat2> &,
-                                      const std::vector<Mat2> &, const FusedBuffers &, hipStream_t, qng_stats *, bool, int);
+                                      const std::vector<Mat2> &, const FusedBuffers &, hipStream_t, qng_stats *, bool, int,
+                                      bool);
 template int run_fused_metric<float>(const SweepPlan &, const FusedRun &, const Circuit &, const std::vector<Mat2> &,
-                                     const std::vector<Mat2> &, const FusedBuffers &, hipStream_t, qng_stats *, bool, int);
+                                     const std::vector<Mat2> &, const FusedBuffers &, hipStream_t, qng_stats *, bool, int,
+                                     bool);
 
 }  // namespace qng

@@ -26,10 +26,12 @@ size_t fused_scratch_bytes(const SweepPlan &plan, const FusedRun &fr, int M);
 // Runs T for every rotation and L_rs for every r < s.  psi (state 0) must hold
 // |in> on entry; on return it holds y_{P-1} and the gate position of the last
 // rotation is returned.
+// real_products: the inner products of L keep their real parts only (what a
+// natural-gradient step needs); T stays complex.
 template <typename R>
 int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c, const std::vector<Mat2> &fwd,
                      const std::vector<Mat2> &adj, const FusedBuffers &buf, hipStream_t st, qng_stats *stats,
-                     bool profile, int reg_mode);
+                     bool profile, int reg_mode, bool real_products = false);
 
 size_t fused_gradient_scratch_bytes(const SweepPlan &g, int M);
 

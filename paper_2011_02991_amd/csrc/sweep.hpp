@@ -256,7 +256,12 @@ struct ReduceTask {  // 16 bytes: sum partials[off .. off+count) -> results[dest
 // 8 for <lambda|sigma|phi> (complex conjugate-multiply-add), 6 for the
 // rotation adjoint on phi and 6 on lambda, which a block of `width` columns
 // shares.
-inline double sweep_flops_per_amp(int width) { return 8.0 + 6.0 + 6.0 / width; }
+// Algorithmic flops per amplitude per element of a fused pass: the inner
+// product (8, or 4 for its real part alone), the rotation adjoint on phi (6)
+// and on lambda, shared by the block's columns (6 / width).
+inline double sweep_flops_per_amp(int width, bool real_products = false) {
+    return (real_products ? 4.0 : 8.0) + 6.0 + 6.0 / width;
+}
 
 struct FusedRun {
     int B = 1;                 // columns swept concurrently
@@ -278,10 +283,17 @@ enum RegMode : int { REG_F32 = 0, REG_F64 = 1, REG_F32_EXACT = 2 };
 // shear parameters (u, w) of the gate's adjoint (circuit.hpp, adjoint_shear),
 // in FP64 and FP32; the kernel reads the table of its register precision.
 // width: phi registers per item (the plan's column-block width).
+// real_products: keep only the real parts of the metric's inner products
+// (sweep_kernels_real.hip; the step needs Re G alone); not with REG_F32_EXACT.
 template <typename R>
 void launch_sweep_pass(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
                        const DevOp *ops, const DevMap *maps, const double *mats64, const float *mats32,
-                       double *partials, int m, int rb, int reg_mode, int width, hipStream_t st);
+                       double *partials, int m, int rb, int reg_mode, int width, hipStream_t st,
+                       bool real_products = false);
+template <typename R>
+void launch_sweep_pass_real(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
+                            const DevOp *ops, const DevMap *maps, const double *mats64, const float *mats32,
+                            double *partials, int m, int rb, int reg_mode, int width, hipStream_t st);
 // The REG_F32_EXACT kernels (sweep_kernels_exact.hip: the same source built
 // with every product in FP64), complex64 storage only.
 void launch_sweep_pass_exact(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,

@@ -104,12 +104,37 @@ __device__ __forceinline__ double dpp_xchg(double v) {
 }
 constexpr int kDppRowMirror = 0x140, kDppRowHalfMirror = 0x141, kDppXor2 = 0x4E, kDppXor1 = 0xB1;
 
+// Built with QNG_REAL_PRODUCTS = 1 (sweep_kernels_real.hip), the metric's
+// inner products keep their real parts only (the natural-gradient step needs
+// Re G alone): half the multiply-adds and half the row sums; the imaginary
+// parts are stored as zero.  The products that give T (column seeds) and the
+// Z products on qubits outside the tile stay complex.
+#ifndef QNG_REAL_PRODUCTS
+#define QNG_REAL_PRODUCTS 0
+#endif
+constexpr bool kRealProducts = QNG_REAL_PRODUCTS != 0;
+
 template <int W>
 __device__ __forceinline__ void row_reduce_store(double2 *sink, double2 *red, int slot, int fa, int tid,
                                                  const double (&pr)[W], const double (&pi)[W]) {
     static_assert(W == 1 || W == 2, "one or two phi registers");
     const int lane = tid & 15;
     const bool h8 = lane & 8;
+    if constexpr (kRealProducts) {
+        // W = 1: every lane ends with the row's sum; W = 2: lanes 0-7 with
+        // register 0's, lanes 8-15 with register 1's
+        double v = W == 1 ? pr[0] : (h8 ? pr[W - 1] : pr[0]) + dpp_xchg<kDppRowMirror>(h8 ? pr[0] : pr[W - 1]);
+        if constexpr (W == 1) v += dpp_xchg<kDppRowMirror>(v);
+        v += dpp_xchg<kDppRowHalfMirror>(v);
+        v += dpp_xchg<kDppXor2>(v);
+        v += dpp_xchg<kDppXor1>(v);
+        const int b = W == 1 ? 0 : lane >> 3;
+        const bool last = (lane & 7) == 7;
+        const bool keep = W == 1 ? lane == 15 : b >= fa;
+        double2 *p = (last && keep) ? &red[(slot + b - fa) * kRows + (tid >> 4)] : sink;
+        *p = make_double2(v, 0.0);
+        return;
+    }
     double v;
     if constexpr (W == 1) {
         // lanes 0-7 keep the real part, lanes 8-15 the imaginary part
@@ -263,10 +288,57 @@ __device__ __forceinline__ void prod_plain(const CT (&ar)[T], const CT (&ai)[T],
     pi = (T >= 2) ? (double)i0 + (double)i1 : (double)i0;
 }
 
+// Real parts only (QNG_REAL_PRODUCTS): Re(s conj(a) b) = s (a.x b.x + a.y b.y)
+// and Im(s conj(a) b) = s (a.x b.y - a.y b.x), one chain each.
+template <bool NEG, typename A>
+__device__ __forceinline__ void cfma_re(A &r, AccArg<A> ar, AccArg<A> ai, AccArg<A> br, AccArg<A> bi) {
+    r = fma_rn(NEG ? -ar : ar, br, r);
+    r = fma_rn(NEG ? -ai : ai, bi, r);
+}
+template <bool NEG, typename A>
+__device__ __forceinline__ void cfma_im(A &r, AccArg<A> ar, AccArg<A> ai, AccArg<A> br, AccArg<A> bi) {
+    r = fma_rn(NEG ? -ar : ar, bi, r);
+    r = fma_rn(NEG ? ai : -ai, br, r);
+}
+
 // The same products for every phi register of the tile at once, lambda's
 // values converted once per pair for all of them.
 template <int J, int AX, int T, typename CT, int W>
 __device__ __forceinline__ void prodw_xy(const Regs<CT, T, W> &x, double (&pr)[W], double (&pi)[W]) {
+    if constexpr (kRealProducts) {
+        // X: the real part of sum conj(a0) b1 + conj(a1) b0; Y: minus the
+        // imaginary part of sum -conj(a0) b1 + conj(a1) b0
+        ProdT<CT> c0[W], c1[W];
+#pragma unroll
+        for (int b = 0; b < W; ++b) c0[b] = c1[b] = 0;
+        int pair = 0;
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            if (i & (1 << J)) continue;
+            const int k = i | (1 << J);
+            const ProdT<CT> a0r = x.ar[i], a0i = x.ai[i], a1r = x.ar[k], a1i = x.ai[k];
+#pragma unroll
+            for (int b = 0; b < W; ++b) {
+                const ProdT<CT> b0r = x.br[b][i], b0i = x.bi[b][i], b1r = x.br[b][k], b1i = x.bi[b][k];
+                ProdT<CT> &c = (pair & 1) ? c1[b] : c0[b];
+                if (AX == 0) {
+                    cfma_re<false>(c, a0r, a0i, b1r, b1i);
+                    cfma_re<false>(c, a1r, a1i, b0r, b0i);
+                } else {
+                    cfma_im<true>(c, a0r, a0i, b1r, b1i);
+                    cfma_im<false>(c, a1r, a1i, b0r, b0i);
+                }
+            }
+            ++pair;
+        }
+#pragma unroll
+        for (int b = 0; b < W; ++b) {
+            const double v = (double)c0[b] + (double)c1[b];
+            pr[b] = AX == 0 ? v : -v;
+            pi[b] = 0.0;
+        }
+        return;
+    }
     ProdT<CT> r0[W], i0[W], r1[W], i1[W];
     int pair = 0;
 #pragma unroll
@@ -296,6 +368,27 @@ __device__ __forceinline__ void prodw_xy(const Regs<CT, T, W> &x, double (&pr)[W
 
 template <int J, int T, typename CT, int W>
 __device__ __forceinline__ void prodw_z_reg(const Regs<CT, T, W> &x, double (&pr)[W], double (&pi)[W]) {
+    if constexpr (kRealProducts) {
+        ProdT<CT> c0[W], c1[W];
+#pragma unroll
+        for (int b = 0; b < W; ++b) c0[b] = c1[b] = 0;
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            const ProdT<CT> ar = x.ar[i], ai = x.ai[i];
+#pragma unroll
+            for (int b = 0; b < W; ++b) {
+                ProdT<CT> &c = (i & 1) ? c1[b] : c0[b];
+                if ((i >> J) & 1) cfma_re<true>(c, ar, ai, x.br[b][i], x.bi[b][i]);
+                else cfma_re<false>(c, ar, ai, x.br[b][i], x.bi[b][i]);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < W; ++b) {
+            pr[b] = (double)c0[b] + (double)c1[b];
+            pi[b] = 0.0;
+        }
+        return;
+    }
     ProdT<CT> r0[W], i0[W], r1[W], i1[W];
 #pragma unroll
     for (int i = 0; i < T; ++i) {
@@ -323,6 +416,23 @@ __device__ __forceinline__ void prodw_z_reg(const Regs<CT, T, W> &x, double (&pr
 
 template <int T, typename CT, int W>
 __device__ __forceinline__ void prodw_plain(const Regs<CT, T, W> &x, double (&pr)[W], double (&pi)[W]) {
+    if constexpr (kRealProducts) {
+        ProdT<CT> c0[W], c1[W];
+#pragma unroll
+        for (int b = 0; b < W; ++b) c0[b] = c1[b] = 0;
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            const ProdT<CT> ar = x.ar[i], ai = x.ai[i];
+#pragma unroll
+            for (int b = 0; b < W; ++b) cfma_re<false>((i & 1) ? c1[b] : c0[b], ar, ai, x.br[b][i], x.bi[b][i]);
+        }
+#pragma unroll
+        for (int b = 0; b < W; ++b) {
+            pr[b] = (double)c0[b] + (double)c1[b];
+            pi[b] = 0.0;
+        }
+        return;
+    }
     ProdT<CT> r0[W], i0[W], r1[W], i1[W];
 #pragma unroll
     for (int i = 0; i < T; ++i) {
@@ -1205,12 +1315,43 @@ void launch_ct(const LaunchItem *items, int n_items, uint32_t total_tiles, const
 
 }  // namespace
 
-#if !QNG_EXACT_PRODUCTS
+#if QNG_REAL_PRODUCTS
+template <typename R>
+void launch_sweep_pass_real(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
+                            const DevOp *ops, const DevMap *maps, const double *mats64, const float *mats32,
+                            double *partials, int m, int rb, int reg_mode, int width, hipStream_t st) {
+    if (n_items <= 0 || total_tiles == 0) return;
+    if constexpr (sizeof(R) == 8) {
+        (void)reg_mode;
+        launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, partials, m, rb, width, st);
+    } else {
+        if (reg_mode == REG_F64)
+            launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, partials, m, rb, width, st);
+        else if (reg_mode == REG_F32)
+            launch_ct<R, float>(items, n_items, total_tiles, passes, ops, maps, mats32, partials, m, rb, width, st);
+        else
+            throw hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw e;
+}
+template void launch_sweep_pass_real<double>(const LaunchItem *, int, uint32_t, const DevPass *, const DevOp *,
+                                             const DevMap *, const double *, const float *, double *, int, int, int,
+                                             int, hipStream_t);
+template void launch_sweep_pass_real<float>(const LaunchItem *, int, uint32_t, const DevPass *, const DevOp *,
+                                            const DevMap *, const double *, const float *, double *, int, int, int,
+                                            int, hipStream_t);
+#elif !QNG_EXACT_PRODUCTS
 template <typename R>
 void launch_sweep_pass(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
                        const DevOp *ops, const DevMap *maps, const double *mats64, const float *mats32,
-                       double *partials, int m, int rb, int reg_mode, int width, hipStream_t st) {
+                       double *partials, int m, int rb, int reg_mode, int width, hipStream_t st, bool real_products) {
     if (n_items <= 0 || total_tiles == 0) return;
+    if (real_products && reg_mode != REG_F32_EXACT) {
+        launch_sweep_pass_real<R>(items, n_items, total_tiles, passes, ops, maps, mats64, mats32, partials, m, rb,
+                                  reg_mode, width, st);
+        return;
+    }
     if constexpr (sizeof(R) == 8) {
         (void)reg_mode;
         launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, partials, m, rb, width, st);
@@ -1238,10 +1379,10 @@ void launch_reduce_tasks(const ReduceTask *tasks, int n_tasks, const double *par
 
 template void launch_sweep_pass<double>(const LaunchItem *, int, uint32_t, const DevPass *, const DevOp *,
                                         const DevMap *, const double *, const float *, double *, int, int, int, int,
-                                        hipStream_t);
+                                        hipStream_t, bool);
 template void launch_sweep_pass<float>(const LaunchItem *, int, uint32_t, const DevPass *, const DevOp *,
                                        const DevMap *, const double *, const float *, double *, int, int, int, int,
-                                       hipStream_t);
+                                       hipStream_t, bool);
 #else
 void launch_sweep_pass_exact(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
                              const DevOp *ops, const DevMap *maps, const float *mats32, double *partials, int m,

@@ -3,9 +3,10 @@
 Two modes:
 
   python profile_sweep.py run [--config 3] [--prec c64]
-      One metric evaluation of a workload, preceded by one plain device copy of
-      512 MiB (the calibration kernel for FETCH_SIZE / WRITE_SIZE).  Meant to run
-      under rocprofv3 --pmc, one counter group per run.
+      One natural-gradient step of a workload without the G output (the passes
+      bench.py times), preceded by one plain device copy of 512 MiB (the
+      calibration kernel for FETCH_SIZE / WRITE_SIZE).  Meant to run under
+      rocprofv3 --pmc, one counter group per run.
 
   python profile_sweep.py summarize --kind {stats,traffic,counters} --out FILE DB...
       Summarise rocprofv3 databases into short text under profiles/:
@@ -43,11 +44,11 @@ def run(args):
     torch.cuda.synchronize()
     del dst, src
     pr = W.CONFIGS[args.config]() if args.layers <= 0 else W.scaled(W.CONFIGS[args.config], 26, args.layers)
-    print(f"profiling metric of {pr.name} ({args.prec})", flush=True)
+    print(f"profiling a step of {pr.name} ({args.prec})", flush=True)
     ctx = qng.Context(0)
     ctx.set_option(qng.OPT_TILE_QUBITS, args.tile)
     ctx.set_option(qng.OPT_F64_REGISTERS, args.f64_regs)
-    ctx.metric(qng.Circuit.from_problem(pr), pr.theta, prec=args.prec)
+    ctx.step(qng.Circuit.from_problem(pr), pr.theta, pr.dt, pr.tikhonov, prec=args.prec, want_G=False)
     torch.cuda.synchronize()
     print(json.dumps({"workload": pr.name, "prec": args.prec, **ctx.stats()}), flush=True)
 

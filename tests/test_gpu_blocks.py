@@ -129,3 +129,29 @@ def test_blocks_full_step_cfg3_n20(ctx, qng):
     r64 = step(ctx, qng, pr, "c64", 2)
     bound = 4 * pr.gates.shape[0] * 2.0 ** -24
     assert rel_err(r64["G"], want["G"]) <= bound and rel_err(r64["grad"], want["grad"]) <= bound
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("label,make", [("cfg3 n=14 L=2", lambda: W.scaled(W.config3, 14, 2, n_terms=9)),
+                                        ("cfg5 n=13 L=2", lambda: W.scaled(W.config5, 13, 2, n_terms=9)),
+                                        ("cfg2 n=9 L=3", lambda: W.scaled(W.config2, 9, 3, n_terms=9))])
+def test_step_without_G_output(ctx, qng, label, make, prec):
+    """Without a G output the step needs Re G only, and the fused passes keep the
+    real parts of the metric's inner products (half the multiply-adds).  The
+    real parts are formed by the same chains in the same order, so the step is
+    the same to the last bit or close to it; against the oracle as usual."""
+    pr = make()
+    pr.in_state = W.random_state(pr.n_qubits, 731)
+    circ = qng.Circuit.from_problem(pr)
+    full = ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, in_state=pr.in_state, prec=prec, want_G=True)
+    real = ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, in_state=pr.in_state, prec=prec, want_G=False)
+    st = ctx.stats()
+    assert st["sweep_launches"] > 0
+    ed = rel_err(real["dtheta"], full["dtheta"])
+    say(f"{label} {prec}: |ddtheta| real vs full {ed:.2e}")
+    assert ed <= 1e-13
+    assert np.array_equal(real["grad"], full["grad"]) and real["E"] == full["E"]
+    want = oracle.step(pr)
+    kappa = np.linalg.cond(want["G"].real + pr.tikhonov * np.eye(pr.n_params))
+    bound = TOL if prec == "c128" else 4 * pr.gates.shape[0] * 2.0 ** -24
+    assert rel_err(real["dtheta"], want["dtheta"]) <= max(bound, kappa * bound if prec == "c64" else kappa * 1e-14)
