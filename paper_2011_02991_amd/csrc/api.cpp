@@ -488,8 +488,7 @@ template <typename R> struct Engine {
         void *psi = state(0), *lam = state(1);
         for (; pos < c.M; ++pos) apply(pos, false, psi, nullptr);
         if (psi_copy_c128) { ++ctx->stats.other_launches; launch_to_c128<R>(psi, psi_copy_c128, n, st); }
-        hamiltonian(psi, lam);
-        prod(psi, lam, 0, -1, eraw());
+        energy(psi, lam);
         if (!want_grad || c.P == 0) return;
         if (gplan) {
             run_fused_gradient<R>(*gplan, c, pb.adj, lam, psi, graw(), gscratch, gscratch_bytes, st, &ctx->stats,
@@ -528,16 +527,18 @@ template <typename R> struct Engine {
         }
     }
 
-    void hamiltonian(const void *psi, void *out) {
-        if (pb.ham.empty()) {
-            HIPCHECK(hipMemsetAsync(out, 0, state_bytes, st));
-            return;
-        }
+    // out = H psi and E = <psi|out> (into eraw), one pass over the register per
+    // chunk of terms
+    void energy(const void *psi, void *out) {
+        std::vector<HamTerm> terms(pb.ham.size());
         for (size_t t = 0; t < pb.ham.size(); ++t) {
             const PauliTerm &h = pb.ham[t];
-            ++ctx->stats.other_launches;
-            launch_pauli_term<R>(psi, out, n, h.flip, h.zy, h.n_y, h.coeff, t == 0, st);
+            cd c(h.coeff, 0.0);
+            for (int k = 0; k < (h.n_y & 3); ++k) c *= cd(0, -1);
+            terms[t] = HamTerm{h.flip, h.zy, c.real(), c.imag()};
         }
+        ctx->stats.other_launches += 1 + (int64_t)(terms.size() + kHamChunk - 1) / kHamChunk;
+        launch_pauli_sum<R>(psi, out, n, terms.data(), (int)terms.size(), partials(), eraw(), st);
     }
 };
 

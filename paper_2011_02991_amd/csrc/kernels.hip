@@ -617,6 +617,42 @@ __global__ void k_pauli_term(const typename Cplx<R>::T *psi, typename Cplx<R>::T
     }
 }
 
+// All terms of a chunk in one pass: out[x] = (first ? 0 : out[x]) +
+// sum_t c_t (-1)^{popcount(x & zy_t)} psi[x ^ flip_t], summed in the storage
+// precision as the one-term kernel does; with partials, the block sums of
+// conj(psi[x]) out[x] in FP64.
+struct HamChunk {
+    HamTerm t[kHamChunk];
+    int n_terms, first;
+};
+
+template <typename R>
+__global__ void k_pauli_sum(const typename Cplx<R>::T *psi, typename Cplx<R>::T *out, int n, HamChunk h,
+                            double *partials) {
+    using C = typename Cplx<R>::T;
+    const uint64_t dim = uint64_t(1) << n;
+    double er = 0.0, ei = 0.0;
+    for (uint64_t x = blockIdx.x * (uint64_t)kBlock + threadIdx.x; x < dim; x += (uint64_t)gridDim.x * kBlock) {
+        C acc;
+        if (h.first) { acc.x = (R)0; acc.y = (R)0; }
+        else acc = out[x];
+        for (int t = 0; t < h.n_terms; ++t) {
+            const HamTerm &term = h.t[t];
+            const C v = psi[x ^ term.flip];
+            const R sgn = (__popcll(x & term.zy) & 1) ? (R)-1 : (R)1;
+            const R cr = (R)term.cr, ci = (R)term.ci;
+            acc.x += sgn * (cr * v.x - ci * v.y);
+            acc.y += sgn * (cr * v.y + ci * v.x);
+        }
+        out[x] = acc;
+        if (partials) {
+            const C p = psi[x];
+            cmac(er, ei, p.x, p.y, acc.x, acc.y);
+        }
+    }
+    if (partials) block_reduce_store(er, ei, partials + 2 * blockIdx.x);
+}
+
 // ------------------------------------------------------------------ unpack
 
 __global__ void k_unpack_metric(const double *Lraw, const double *Traw, const int *param_of, int P, double *G,
@@ -855,6 +891,27 @@ void launch_advance_seed(void *psi, void *lam, void *phi, int n, int qr, const d
 }
 
 template <typename R>
+void launch_pauli_sum(const void *psi, void *out, int n, const HamTerm *terms, int n_terms, double *partials,
+                      double *dest, hipStream_t st) {
+    const int nb = reduce_blocks(n);
+    for (int t0 = 0; t0 < n_terms || t0 == 0; t0 += kHamChunk) {
+        HamChunk h;
+        h.n_terms = n_terms - t0 < kHamChunk ? n_terms - t0 : kHamChunk;
+        h.first = t0 == 0;
+        for (int k = 0; k < h.n_terms; ++k) h.t[k] = terms[t0 + k];
+        const bool last = t0 + kHamChunk >= n_terms;
+        hipLaunchKernelGGL(k_pauli_sum<R>, dim3(nb), dim3(kBlock), 0, st, (const typename Cplx<R>::T *)psi,
+                           (typename Cplx<R>::T *)out, n, h, (last && dest) ? partials : nullptr);
+        check_launch();
+        if (n_terms == 0) break;
+    }
+    if (dest) {
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, st, (const double *)partials, nb, dest);
+        check_launch();
+    }
+}
+
+template <typename R>
 void launch_pauli_term(const void *psi, void *out, int n, uint64_t flip, uint64_t zy, int n_y, double coeff, int first,
                        hipStream_t st) {
     // coeff * (-i)^{n_y}
@@ -919,7 +976,8 @@ void launch_grad_from_raw(const double *graw, const int *param_of, int P, double
                                        int);                                                                      \
     template void launch_advance_seed<R>(void *, void *, void *, int, int, const double *, int, int, double *,       \
                                          double *, hipStream_t);                                                  \
-    template void launch_pauli_term<R>(const void *, void *, int, uint64_t, uint64_t, int, double, int, hipStream_t);
+    template void launch_pauli_term<R>(const void *, void *, int, uint64_t, uint64_t, int, double, int, hipStream_t); \
+    template void launch_pauli_sum<R>(const void *, void *, int, const HamTerm *, int, double *, double *, hipStream_t);
 
 QNG_INSTANTIATE(double)
 QNG_INSTANTIATE(float)

@@ -100,6 +100,19 @@ template <typename R>
 void launch_pauli_prod(const void *a, const void *b, int n, int q, int axis, double *partials, double *dest,
                        hipStream_t st, int ctrl = -1);
 
+// out = H psi for H = sum_t c_t S_t in one pass per chunk of kHamChunk terms
+// (each amplitude of out gathers psi[x ^ flip_t] of every term), and
+// dest (one complex128, nullable) = <psi|out> from the stored values.
+// c_t holds coeff_t (-i)^{n_y} of term t.  partials: reduce_blocks(n) complex128.
+constexpr int kHamChunk = 96;
+struct HamTerm {
+    uint64_t flip, zy;
+    double cr, ci;
+};
+template <typename R>
+void launch_pauli_sum(const void *psi, void *out, int n, const HamTerm *terms, int n_terms, double *partials,
+                      double *dest, hipStream_t st);
+
 // out (+)= coeff * (-i)^{n_y} (-1)^{popcount(x & zy)} psi[x ^ flip]; first != 0 overwrites.
 template <typename R>
 void launch_pauli_term(const void *psi, void *out, int n, uint64_t flip, uint64_t zy, int n_y, double coeff,

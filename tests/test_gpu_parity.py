@@ -184,3 +184,27 @@ def test_errors_before_device_work(ctx, qng):
     with pytest.raises(qng.QNGError) as e:
         ctx.step(qng.Circuit.from_problem(pr2), pr2.theta, 0.1, 0.0)
     assert e.value.name == "QNG_E_NOT_SPD"
+
+
+@pytest.mark.parametrize("n_terms", [0, 1, 96, 97, 250])
+def test_hamiltonian_chunks(ctx, qng, n_terms):
+    """H psi is formed in one pass per chunk of 96 terms (the first chunk
+    overwrites, later ones add): term counts at and around the chunk size, and
+    none at all (E = 0, zero gradient)."""
+    pr = W.random_circuit(9, 40, 4400 + n_terms, n_terms=max(n_terms, 1))
+    if n_terms == 0:
+        pr = W.Problem(**{**pr.__dict__, "pauli": np.zeros((0, 9), np.uint8), "coeff": np.zeros(0)})
+    pr.in_state = W.random_state(9, 4401)
+    say(f"case: {n_terms} Hamiltonian terms")
+    E, grad = ctx.energy_grad(qng.Circuit.from_problem(pr), pr.theta, in_state=pr.in_state)
+    if n_terms == 0:
+        assert E == 0.0 and not grad.any()
+        return
+    Eo, go = oracle.energy_grad(pr)
+    assert abs(E - Eo) <= TOL * max(1.0, abs(Eo)), (E, Eo)
+    assert rel_err(grad, go) <= TOL
+    E64, g64 = ctx.energy_grad(qng.Circuit.from_problem(pr), pr.theta, in_state=pr.in_state, prec="c64")
+    bound = 4 * (pr.n_gates + n_terms) * 2.0 ** -24
+    # complex64: each gate and each term rounds once in FP32 (4 M' 2^-24, M' = gates + terms),
+    # E relative to the coefficient sum that bounds |H|
+    assert abs(E64 - Eo) <= bound * max(1.0, np.abs(pr.coeff).sum()) and rel_err(g64, go) <= bound
