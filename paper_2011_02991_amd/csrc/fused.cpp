@@ -188,7 +188,19 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
             const int b = col - G.col_begin;
             // y_s = R_{s-1} y_{s-1} when rotation s-1 is the only gate in between:
             // one pass advances psi, seeds the top column and takes T_s (the
-            // lower columns of a block are seeded inside its sweep)
+            // lower columns of a block are seeded inside its sweep).  When the
+            // gate before rotation s-1 is a rotation too, on a third qubit, the
+            // same pass applies both.
+            const int ra = pos < c.M ? c.rot_at[pos] : -1;
+            if (ra >= 0 && pos + 1 == rp.pos && rs.pos == rp.pos + 1 && n >= 3 && c.rots[ra].qubit != rp.qubit &&
+                c.rots[ra].qubit != rs.qubit && rp.qubit != rs.qubit) {
+                launch_advance2_seed<R>(psi, reg(b, 0), reg(b, W), n, c.rots[ra].qubit, d_fmats + (size_t)pos * 8,
+                                        rp.qubit, d_fmats + (size_t)rp.pos * 8, rs.qubit, rs.axis,
+                                        buf.reduce_partials, buf.traw + 2 * s, st);
+                stats->other_launches += 2;
+                pos = rs.pos;
+                continue;
+            }
             forward_to(rp.pos);
             int qr = -1;
             const double *mrow = d_fmats;

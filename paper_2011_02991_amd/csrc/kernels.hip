@@ -9,6 +9,8 @@
 // 2-amplitude run).
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "kernels.hpp"
 
 namespace qng {
@@ -599,6 +601,59 @@ __global__ void k_fixed_multi(StepRegs regs, int n, int a, int b) {
     }
 }
 
+// The same with two rotations before y_s: psi <- R_b R_a psi (matrices ma on
+// qubit qa, then mb on qubit qb), lam = psi, phi = sigma_c psi and the block
+// partials of <psi|sigma_c|psi>, for three distinct qubits.  A thread takes
+// the 8 amplitudes of one (qa, qb, qc) octet; LA, LB, LC are the positions of
+// qa, qb, qc among the three in increasing order (bits of the local index), so
+// every register index is a compile-time constant.
+template <typename R, int LA, int LB, int LC>
+__global__ void k_advance2_seed(typename Cplx<R>::T *psi, typename Cplx<R>::T *lam, typename Cplx<R>::T *phi, int n,
+                                int p0, int p1, int p2, const double *__restrict__ ma, const double *__restrict__ mb,
+                                int axis, double *partials) {
+    using C = typename Cplx<R>::T;
+    R a[8], b[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) { a[k] = (R)ma[k]; b[k] = (R)mb[k]; }
+    double sr = 0.0, si = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    const uint64_t no = uint64_t(1) << (n - 3);
+    const uint64_t bit[3] = {uint64_t(1) << p0, uint64_t(1) << p1, uint64_t(1) << p2};
+    for (uint64_t p = blockIdx.x * (uint64_t)kBlock + threadIdx.x; p < no; p += stride) {
+        const uint64_t base = insert_zero(insert_zero(insert_zero(p, p0), p1), p2);
+        uint64_t off[8];
+        C v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            off[k] = base | ((k & 1) ? bit[0] : 0) | ((k & 2) ? bit[1] : 0) | ((k & 4) ? bit[2] : 0);
+            v[k] = psi[off[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (!(k & (1 << LA))) mat2(a, v[k], v[k | (1 << LA)]);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (!(k & (1 << LB))) mat2(b, v[k], v[k | (1 << LB)]);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            psi[off[k]] = v[k];
+            lam[off[k]] = v[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k & (1 << LC)) continue;
+            const int k1 = k | (1 << LC);
+            C o0, o1;
+            pauli_pair(axis, v[k], v[k1], o0, o1);
+            phi[off[k]] = o0;
+            phi[off[k1]] = o1;
+            cmac(sr, si, v[k].x, v[k].y, o0.x, o0.y);
+            cmac(sr, si, v[k1].x, v[k1].y, o1.x, o1.y);
+        }
+    }
+    block_reduce_store(sr, si, partials + 2 * blockIdx.x);
+}
+
 // ------------------------------------------------------------------ Hamiltonian
 
 template <typename R>
@@ -891,6 +946,40 @@ void launch_advance_seed(void *psi, void *lam, void *phi, int n, int qr, const d
 }
 
 template <typename R>
+void launch_advance2_seed(void *psi, void *lam, void *phi, int n, int qa, const double *ma, int qb, const double *mb,
+                          int qc, int axis, double *partials, double *dest, hipStream_t st) {
+    if (n < 3 || qa == qb || qa == qc || qb == qc) throw hipErrorInvalidValue;
+    int q[3] = {qa, qb, qc};
+    int s[3] = {qa, qb, qc};
+    if (s[0] > s[1]) std::swap(s[0], s[1]);
+    if (s[1] > s[2]) std::swap(s[1], s[2]);
+    if (s[0] > s[1]) std::swap(s[0], s[1]);
+    int l[3];
+    for (int k = 0; k < 3; ++k) l[k] = q[k] == s[0] ? 0 : q[k] == s[1] ? 1 : 2;
+    const int nb = reduce_blocks(n);
+    using C = typename Cplx<R>::T;
+    const int code = l[0] * 9 + l[1] * 3 + l[2];
+#define QNG_ADV2(LA, LB, LC)                                                                                       \
+    case LA * 9 + LB * 3 + LC:                                                                                     \
+        hipLaunchKernelGGL((k_advance2_seed<R, LA, LB, LC>), dim3(nb), dim3(kBlock), 0, st, (C *)psi, (C *)lam,     \
+                           (C *)phi, n, s[0], s[1], s[2], ma, mb, axis, partials);                                  \
+        break;
+    switch (code) {
+        QNG_ADV2(0, 1, 2)
+        QNG_ADV2(0, 2, 1)
+        QNG_ADV2(1, 0, 2)
+        QNG_ADV2(1, 2, 0)
+        QNG_ADV2(2, 0, 1)
+        QNG_ADV2(2, 1, 0)
+    default: throw hipErrorInvalidValue;
+    }
+#undef QNG_ADV2
+    check_launch();
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, st, (const double *)partials, nb, dest);
+    check_launch();
+}
+
+template <typename R>
 void launch_pauli_sum(const void *psi, void *out, int n, const HamTerm *terms, int n_terms, double *partials,
                       double *dest, hipStream_t st) {
     const int nb = reduce_blocks(n);
@@ -977,7 +1066,9 @@ void launch_grad_from_raw(const double *graw, const int *param_of, int P, double
     template void launch_advance_seed<R>(void *, void *, void *, int, int, const double *, int, int, double *,       \
                                          double *, hipStream_t);                                                  \
     template void launch_pauli_term<R>(const void *, void *, int, uint64_t, uint64_t, int, double, int, hipStream_t); \
-    template void launch_pauli_sum<R>(const void *, void *, int, const HamTerm *, int, double *, double *, hipStream_t);
+    template void launch_pauli_sum<R>(const void *, void *, int, const HamTerm *, int, double *, double *, hipStream_t); \
+    template void launch_advance2_seed<R>(void *, void *, void *, int, int, const double *, int, const double *, int, \
+                                          int, double *, double *, hipStream_t);
 
 QNG_INSTANTIATE(double)
 QNG_INSTANTIATE(float)

@@ -93,6 +93,12 @@ template <typename R>
 void launch_advance_seed(void *psi, void *lam, void *phi, int n, int qr, const double *m_dev, int qs, int axis,
                          double *partials, double *dest, hipStream_t st);
 
+// The same with two rotations before y_s (qa, ma first, then qb, mb; three
+// distinct qubits qa, qb, qc = the seeded column's qubit, n >= 3): one pass.
+template <typename R>
+void launch_advance2_seed(void *psi, void *lam, void *phi, int n, int qa, const double *ma, int qb, const double *mb,
+                          int qc, int axis, double *partials, double *dest, hipStream_t st);
+
 // dest (one complex128) = <a| sigma_q |b>; axis -1 means the identity (plain inner product).
 // ctrl >= 0: <a| |1><1|_ctrl (x) sigma_q |b> (only amplitudes with bit ctrl = 1).
 // partials: reduce_blocks(n) complex128 scratch.
