@@ -765,8 +765,10 @@ struct BatchRun {
 };
 
 template <typename R>
+// real_products: the sweeps keep the real parts of the metric's inner products
+// (the caller needs Re G only).
 BatchRun batch_metric(qng_ctx *ctx, const std::vector<Problem> &pbs, const double *const *in_states,
-                      const BatchTuning &tun, bool allow_graph, bool profile) {
+                      const BatchTuning &tun, bool allow_graph, bool profile, bool real_products = false) {
     const int B = (int)pbs.size();
     const int amp = 2 * (int)sizeof(R);
     const bool f64 = amp == 16 || ctx->opt_f64_regs;
@@ -782,7 +784,8 @@ BatchRun batch_metric(qng_ctx *ctx, const std::vector<Problem> &pbs, const doubl
     HIPCHECK(hipMemGetInfo(&free_b, &total_b));
     const uint64_t arena_cap = (uint64_t)(free_b + ctx->ws_bytes) / 4;
     for (auto &kv : by_m) {
-        std::vector<int32_t> key = {kv.first, amp, sweep_reg_mode(ctx, amp), tun.tile_qubits, tun.target_tiles};
+        std::vector<int32_t> key = {kv.first, amp, sweep_reg_mode(ctx, amp), tun.tile_qubits, tun.target_tiles,
+                                    real_products ? 1 : 0};
         for (int b : kv.second) append_structure_key(pbs[b].circ, key);
         auto it = ctx->batch_classes.find(key);
         std::shared_ptr<BatchClass> bc;
@@ -917,7 +920,9 @@ BatchRun batch_metric(qng_ctx *ctx, const std::vector<Problem> &pbs, const doubl
                 const uint64_t amps = (uint64_t)it.ntiles << S.m;
                 ctx->stats.sweep_bytes += 4.0 * (double)amps * amp;
             }
-            for (uint32_t j = 0; j < bl.n_tasks; ++j) ctx->stats.sweep_flops += 20.0 * (double)S.tasks[bl.task_begin + j].count * (double)(1u << S.m);
+            for (uint32_t j = 0; j < bl.n_tasks; ++j)
+                ctx->stats.sweep_flops += sweep_flops_per_amp(1, real_products) *
+                                          (double)S.tasks[bl.task_begin + j].count * (double)(1u << S.m);
         }
         ctx->stats.elements += S.elements;
         run.launches += (int64_t)S.launches.size();
@@ -932,7 +937,7 @@ BatchRun batch_metric(qng_ctx *ctx, const std::vector<Problem> &pbs, const doubl
                 hipGraph_t g = nullptr;
                 HIPCHECK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
                 try {
-                    enqueue_batch_metric<R>(S, circs, d, sweep_reg_mode(ctx, amp), st, nullptr);
+                    enqueue_batch_metric<R>(S, circs, d, sweep_reg_mode(ctx, amp), st, nullptr, real_products);
                 } catch (...) {
                     hipGraph_t junk = nullptr;
                     (void)hipStreamEndCapture(st, &junk);
@@ -956,7 +961,7 @@ BatchRun batch_metric(qng_ctx *ctx, const std::vector<Problem> &pbs, const doubl
                 ev.resize(2 * S.launches.size());
                 for (auto &e : ev) HIPCHECK(hipEventCreate(&e));
             }
-            enqueue_batch_metric<R>(S, circs, d, sweep_reg_mode(ctx, amp), st, profile ? &ev : nullptr);
+            enqueue_batch_metric<R>(S, circs, d, sweep_reg_mode(ctx, amp), st, profile ? &ev : nullptr, real_products);
             if (profile) {
                 HIPCHECK(hipStreamSynchronize(st));
                 for (size_t li = 0; li < S.launches.size(); ++li) {
@@ -1422,7 +1427,11 @@ qng_status qng_step_batched(qng_ctx *ctx, int32_t B, const qng_circuit *circs, c
             ctx->stats.tile_qubits = tun.tile_qubits;
             ctx->stats.target_tiles = tun.target_tiles;
             auto t0 = Clock::now();
-            BatchRun run = batch_metric<R>(ctx, pbs, in_states, tun, ctx->opt_graph != 0, ctx->opt_profile != 0);
+            // the solves read Re G only: without G outputs the sweeps keep real parts
+            bool want_G = false;
+            for (int b = 0; G_out && b < B; ++b) want_G = want_G || G_out[b] != nullptr;
+            BatchRun run = batch_metric<R>(ctx, pbs, in_states, tun, ctx->opt_graph != 0, ctx->opt_profile != 0,
+                                           !want_G);
             HIPCHECK(hipStreamSynchronize(ctx->stream));
             ctx->stats.metric_ms = ms_since(t0);
             t0 = Clock::now();

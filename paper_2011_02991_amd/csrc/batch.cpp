@@ -199,7 +199,7 @@ int batch_final_pos(const Circuit &c) { return c.P ? c.rots[c.P - 1].pos : 0; }
 
 template <typename R>
 void enqueue_batch_metric(const BatchSchedule &s, const std::vector<const Circuit *> &members, const BatchDevice &d,
-                          int reg_mode, hipStream_t st, std::vector<hipEvent_t> *events) {
+                          int reg_mode, hipStream_t st, std::vector<hipEvent_t> *events, bool real_products) {
     const ImageLayout IL = image_layout(s);
     const DevPass *passes = (const DevPass *)(d.images + IL.passes);
     const DevOp *ops = (const DevOp *)(d.images + IL.ops);
@@ -253,15 +253,15 @@ void enqueue_batch_metric(const BatchSchedule &s, const std::vector<const Circui
         }
         if (events) BCHECK(hipEventRecord((*events)[2 * li], st));
         launch_sweep_pass<R>(items + L.item_begin, (int)L.n_items, L.total_tiles, passes, ops, maps, d.adj_mats,
-                             d.adj_mats32, d.partials, s.m, s.rb, reg_mode, 1, st);
+                             d.adj_mats32, d.partials, s.m, s.rb, reg_mode, 1, st, real_products);
         if (events) BCHECK(hipEventRecord((*events)[2 * li + 1], st));
         launch_reduce_tasks(tasks + L.task_begin, (int)L.n_tasks, d.partials, d.lraw, st);
     }
 }
 
 template void enqueue_batch_metric<double>(const BatchSchedule &, const std::vector<const Circuit *> &,
-                                           const BatchDevice &, int, hipStream_t, std::vector<hipEvent_t> *);
+                                           const BatchDevice &, int, hipStream_t, std::vector<hipEvent_t> *, bool);
 template void enqueue_batch_metric<float>(const BatchSchedule &, const std::vector<const Circuit *> &,
-                                          const BatchDevice &, int, hipStream_t, std::vector<hipEvent_t> *);
+                                          const BatchDevice &, int, hipStream_t, std::vector<hipEvent_t> *, bool);
 
 }  // namespace qng

@@ -91,7 +91,8 @@ void upload_batch_images(const BatchSchedule &s, const BatchDevice &d, hipStream
 // (in stream order) member b's forward register holds y_{P_b - 1}.
 template <typename R>
 void enqueue_batch_metric(const BatchSchedule &s, const std::vector<const Circuit *> &members, const BatchDevice &d,
-                          int reg_mode, hipStream_t st, std::vector<hipEvent_t> *events);
+                          int reg_mode, hipStream_t st, std::vector<hipEvent_t> *events,
+                          bool real_products = false);
 
 // Gate position of member b's forward register after the metric phase.
 int batch_final_pos(const Circuit &c);

@@ -173,3 +173,24 @@ def test_64_ansatz_workload(env):
         assert eG <= TOL and eg <= TOL and eE <= TOL, (b, eG, eg, eE)
         if b % 8 == 0:
             say(f"member {b} (n={p.n_qubits}, P={p.n_params}): |dG|={eG:.2e} |dgrad|={eg:.2e} |dE|={eE:.2e}")
+
+
+def test_batch_without_G_outputs(env):
+    """Without G outputs the batched sweeps keep the real parts of the metric's
+    inner products (the solves read Re G only): the same dtheta, gradient and
+    energy as with the G outputs, through eager runs and graph replays."""
+    q, ctx = env
+    probs = mixed_batch()[:6]
+    circs = [q.Circuit.from_problem(p) for p in probs]
+    ths = [p.theta for p in probs]
+    ins = [p.in_state for p in probs]
+    full = ctx.step_batched(circs, ths, probs[0].dt, probs[0].tikhonov, in_states=ins, want_G=True)
+    for rep in range(2):
+        real = ctx.step_batched(circs, ths, probs[0].dt, probs[0].tikhonov, in_states=ins, want_G=False)
+        for b, p in enumerate(probs):
+            if not p.n_params:
+                continue
+            ed = rel_err(real[b]["dtheta"], full[b]["dtheta"])
+            assert ed <= 1e-13, (rep, b, ed)
+            assert np.array_equal(real[b]["grad"], full[b]["grad"]) and real[b]["E"] == full[b]["E"]
+    say(f"replays {ctx.stats()['graph_replays']}")
