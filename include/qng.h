@@ -276,7 +276,8 @@ qng_status qng_step(qng_ctx *ctx, const qng_circuit *circ, const double *in_stat
  * Hamiltonian and theta; n and P may differ).  Array-of-pointer arguments have
  * B entries; in_states[b] may be NULL (|0...0>); G_out/grad_out/E_out may be
  * NULL as a whole.  The ansaetze are swept together: every launch carries
- * tiles of several ansaetze. */
+ * tiles of several ansaetze.  Without any G output the sweeps form only the
+ * real parts of the metric's inner products, as qng_step does. */
 qng_status qng_step_batched(qng_ctx *ctx, int32_t B, const qng_circuit *circs,
                             const double *const *in_states, const qng_pauli_sum *hams,
                             const double *const *thetas, double dt, double tikhonov,
