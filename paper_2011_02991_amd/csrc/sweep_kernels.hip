@@ -48,6 +48,15 @@ template <> struct Amp<float>  { using T = float2; };
 
 constexpr int kRows = kThreads / 16;   // DPP rows of 16 lanes per work-group
 
+// Sum of a value over the four 16-lane rows of the wavefront (lane l with
+// l ^ 16, then l ^ 32): lane l of row 0 then holds the sum of lane l of every
+// row, added in the same order on every row.
+__device__ __forceinline__ double across_rows(double v) {
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    return v;
+}
+
 // Row reduction with DPP: after row_shr by 1, 2, 4 and 8 (zero shifted in at
 // the start of each 16-lane row), lane 15 of every row holds the row's sum.
 template <int CTRL>
@@ -69,22 +78,24 @@ __device__ __forceinline__ void row_sum(double &a, double &b) {
 }
 
 // LDS layout of the sweep kernel: the exchange buffer [2^m] (at least the
-// kMaxBlockWidth x kRows tile sums <lambda|phi_b>, which use its start while
+// kMaxBlockWidth x kWaves tile sums <lambda|phi_b>, which use its start while
 // no exchange runs: both sit between barriers), one sink entry per thread,
-// the per-row partials of the inner products [kMaxSlots][kRows].
-constexpr int kLdsTailEntries = kThreads + kMaxSlots * kRows;
+// the per-wavefront partials of the inner products [kMaxSlots][kWaves].
+constexpr int kLdsTailEntries = kThreads + kMaxSlots * kWaves;
 template <typename CX> __host__ __device__ constexpr size_t xbuf_bytes(int m) {
-    return ((size_t)1 << m) * sizeof(CX) > (size_t)kMaxBlockWidth * kRows * 16
+    return ((size_t)1 << m) * sizeof(CX) > (size_t)kMaxBlockWidth * kWaves * 16
                ? ((size_t)1 << m) * sizeof(CX)
-               : (size_t)kMaxBlockWidth * kRows * 16;
+               : (size_t)kMaxBlockWidth * kWaves * 16;
 }
 
-// Store a per-lane partial of slot `slot` of `dst`: one value per 16-lane row.
-// Every lane stores (lane 15 of a row to the slot, the others to their own
-// sink entry), so the op loop has no divergent branch.
+// Store a per-lane partial of slot `slot` of `dst`: one value per wavefront.
+// Every lane stores (lane 15 of the wavefront's first row to the slot, the
+// others to the sink), so the op loop has no divergent branch.
 __device__ __forceinline__ void row_store(double2 *sink, double2 *dst, int slot, int tid, double a, double b) {
     row_sum(a, b);
-    double2 *p = ((tid & 15) == 15) ? dst + slot * kRows + (tid >> 4) : sink;
+    a = across_rows(a);
+    b = across_rows(b);
+    double2 *p = ((tid & 63) == 15) ? dst + slot * kWaves + (tid >> 6) : sink;
     *p = make_double2(a, b);
 }
 
@@ -128,10 +139,11 @@ __device__ __forceinline__ void row_reduce_store(double2 *sink, double2 *red, in
         v += dpp_xchg<kDppRowHalfMirror>(v);
         v += dpp_xchg<kDppXor2>(v);
         v += dpp_xchg<kDppXor1>(v);
+        v = across_rows(v);
         const int b = W == 1 ? 0 : lane >> 3;
-        const bool last = (lane & 7) == 7;
+        const bool last = (lane & 7) == 7 && (tid & 63) < 16;
         const bool keep = W == 1 ? lane == 15 : b >= fa;
-        double2 *p = (last && keep) ? &red[(slot + b - fa) * kRows + (tid >> 4)] : sink;
+        double2 *p = (last && keep) ? &red[(slot + b - fa) * kWaves + (tid >> 6)] : sink;
         *p = make_double2(v, 0.0);
         return;
     }
@@ -150,13 +162,15 @@ __device__ __forceinline__ void row_reduce_store(double2 *sink, double2 *red, in
     if constexpr (W == 1) v += dpp_xchg<kDppRowHalfMirror>(v);
     v += dpp_xchg<kDppXor2>(v);
     v += dpp_xchg<kDppXor1>(v);
+    v = across_rows(v);
     // W = 1: lane 7 holds the real sum, lane 15 the imaginary one; W = 2: lanes
-    // 3, 7 hold register 0's, lanes 11, 15 register 1's
+    // 3, 7 hold register 0's, lanes 11, 15 register 1's (those of the
+    // wavefront's first row store the wavefront's sums)
     const int b = W == 1 ? 0 : lane >> 3;
-    const bool last = W == 1 ? (lane & 7) == 7 : (lane & 3) == 3;
+    const bool last = (W == 1 ? (lane & 7) == 7 : (lane & 3) == 3) && (tid & 63) < 16;
     const bool keep = W == 1 || b >= fa;
     const int part = W == 1 ? lane >> 3 : (lane >> 2) & 1;
-    double *p = (last && keep) ? &red[(slot + b - fa) * kRows + (tid >> 4)].x + part : (double *)sink;
+    double *p = (last && keep) ? &red[(slot + b - fa) * kWaves + (tid >> 6)].x + part : (double *)sink;
     *p = v;
 }
 
@@ -958,9 +972,9 @@ __device__ __forceinline__ void tile_sums(const Regs<CT, T, W> &x, double2 *sink
 #pragma unroll
     for (int b = B0; b < B1; ++b) {
         double ar = 0.0, ai = 0.0;
-        for (int w = 0; w < kRows; ++w) {
-            ar += zs[b * kRows + w].x;
-            ai += zs[b * kRows + w].y;
+        for (int w = 0; w < kWaves; ++w) {
+            ar += zs[b * kWaves + w].x;
+            ai += zs[b * kWaves + w].y;
         }
         Sr[b] = ar;
         Si[b] = ai;
@@ -1010,8 +1024,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 1
     CX *xbuf = (CX *)smem;                                // [2^m] exchange buffer
     double2 *tail = (double2 *)(smem + xbuf_bytes<CX>(m));
     double2 *sink = tail + tid;                           // this thread's sink entry
-    double2 *red = tail + kThreads;                       // [kMaxSlots][kRows]
-    double2 *zs = (double2 *)xbuf;                        // [W][kRows], inside the exchange buffer
+    double2 *red = tail + kThreads;                       // [kMaxSlots][kWaves]
+    double2 *zs = (double2 *)xbuf;                        // [W][kWaves], inside the exchange buffer
 
     uint64_t base = 0;
     const PassBytes pbytes = load_pass_bytes(pp);
@@ -1161,8 +1175,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 1
                     for (int b = 0; b < W; ++b) {
                         if (W > 1 && b < fa) continue;
                         const int sl = op.slot() + b - fa;
-                        red[sl * kRows] = make_double2(sg * Sr[b], sg * Si[b]);
-                        for (int k = 1; k < kRows; ++k) red[sl * kRows + k] = make_double2(0.0, 0.0);
+                        red[sl * kWaves] = make_double2(sg * Sr[b], sg * Si[b]);
+                        for (int k = 1; k < kWaves; ++k) red[sl * kWaves + k] = make_double2(0.0, 0.0);
                     }
                 }
             }
@@ -1204,9 +1218,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 1
     __syncthreads();
     for (int k = tid; k < pass_slots; k += kThreads) {
         double xr = 0.0, xi = 0.0;
-        for (int w = 0; w < kRows; ++w) {
-            xr += red[k * kRows + w].x;
-            xi += red[k * kRows + w].y;
+        for (int w = 0; w < kWaves; ++w) {
+            xr += red[k * kWaves + w].x;
+            xi += red[k * kWaves + w].y;
         }
         partials[it.partial_off + (uint64_t)k * it.ntiles + tile] = make_double2(xr, xi);
     }
