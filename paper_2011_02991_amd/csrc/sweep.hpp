@@ -93,7 +93,7 @@ enum : uint8_t {
 // (kLocBase: qubit given separately).
 constexpr uint8_t kLocThread = 0x10;
 constexpr uint8_t kLocBase = 0xFF;
-constexpr int kMaxSlots = 128;      // inner products per pass
+constexpr int kMaxSlots = 256;      // inner products per pass
 constexpr int kMaxTileQubits = 13;
 constexpr int kMaxRest = 24;        // qubits outside a tile
 constexpr int kMaxBlockWidth = 2;   // columns sharing one lambda sweep
