@@ -127,11 +127,23 @@ def gate_apply_bandwidth(qng, ctx, n, prec):
     finally:
         torch.cuda.synchronize()
         ctx.set_stream(None)
+    # a plain device copy of one state (read V, write V) as the attainable reference
+    other = torch.empty_like(state)
+    other.copy_(state)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        other.copy_(state)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_GBps = 2 * V / (e0.elapsed_time(e1) / 5 * 1e-3) / 1e9
     rot = sorted(r[2] for r in results if r[0] < 3)
     fixed = sorted(r[2] for r in results if r[0] >= 3)
     return {"rotation_median_GBps": rot[len(rot) // 2], "rotation_worst_GBps": rot[0],
             "rotation_best_GBps": rot[-1], "fixed_median_GBps": fixed[len(fixed) // 2] if fixed else None,
-            "n": n, "gates_measured": len(results), "frac_of_8TBps": rot[len(rot) // 2] / HBM_PEAK_GBS}
+            "n": n, "gates_measured": len(results), "frac_of_8TBps": rot[len(rot) // 2] / HBM_PEAK_GBS,
+            "copy_GBps": copy_GBps, "rotation_median_frac_of_copy": rot[len(rot) // 2] / copy_GBps}
 
 
 def precision_report(pr, res, ref, prec, ref_prec):
