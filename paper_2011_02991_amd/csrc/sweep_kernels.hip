@@ -23,10 +23,12 @@
 //    comes from the register index, the thread index or the tile base.
 //  * Between phases the tile is exchanged through LDS (one register at a time)
 //    to the next mapping, the only place where barriers are needed.
-//  * Inner products accumulate per thread in FP64, are summed within each
-//    16-lane row with DPP shifts and kept per (slot, row) in LDS; at the end
-//    one FP64 partial per (slot, tile) is written, and k_reduce_tasks adds the
-//    partials of a slot over the tiles in a fixed order (bitwise reproducible).
+//  * Inner products: each thread's share (register precision, then FP64) is
+//    summed within each 16-lane row with DPP exchanges and across the
+//    wavefront's rows with two lane exchanges, kept per (slot, wavefront) in
+//    LDS; at the end one FP64 partial per (slot, tile) is written, and
+//    k_reduce_tasks adds the partials of a slot over the tiles in a fixed
+//    order (bitwise reproducible).
 //  * Store: registers -> HBM under the final mapping (lanes on the lowest
 //    qubits again), in place: the tile is touched by this work-group only.
 #include <hip/hip_runtime.h>
@@ -100,8 +102,8 @@ __device__ __forceinline__ void row_store(double2 *sink, double2 *dst, int slot,
 }
 
 // The inner products pr[b], pi[b] of the W phi registers, summed over each
-// 16-lane row and stored, the active ones (b >= fa) to slot slot + b - fa, the
-// others to the sink.  The sums use halving exchanges: lanes pair up across the
+// wavefront (16-lane rows, then across the rows) and stored, the active ones
+// (b >= fa) to slot slot + b - fa, the others to the sink.  The sums use halving exchanges: lanes pair up across the
 // row (DPP row_mirror: lane i with 15 - i; row_half_mirror: i with i ^ 7
 // inside each half; quad_perm: i ^ 2, then i ^ 1), and in the first steps a
 // lane keeps half of its values and sends the other half, which its partner
