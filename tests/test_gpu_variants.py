@@ -162,3 +162,27 @@ def test_settings_errors(env):
         ctx.set_metric_blocks(None)
     with pytest.raises(q.QNGError):
         ctx.set_option(q.OPT_METRIC_KIND, 2)
+
+
+@pytest.mark.parametrize("variant", ["blocks", "l_only", "shared"])
+def test_step_without_G_output_in_variants(env, variant):
+    """The real-part passes of a step without a G output under the cheaper
+    variants and shared parameters: the same dtheta as the step that returns G."""
+    q, ctx = env
+    pr = W.scaled(W.config3, 13, 3, n_terms=8)
+    if variant == "shared":
+        pr = W.share_params(pr, 30, 771)
+    circ = q.Circuit.from_problem(pr)
+    if variant == "blocks":
+        ctx.set_metric_blocks(layer_blocks(pr, 3))
+    elif variant == "l_only":
+        ctx.set_option(q.OPT_METRIC_KIND, 1)
+    try:
+        full = ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, want_G=True)
+        real = ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, want_G=False)
+    finally:
+        ctx.set_metric_blocks(None)
+        ctx.set_option(q.OPT_METRIC_KIND, 0)
+    ed = rel_err(real["dtheta"], full["dtheta"])
+    say(f"{variant}: |ddtheta| real vs full {ed:.2e}")
+    assert ed <= 1e-13
