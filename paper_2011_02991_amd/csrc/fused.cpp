@@ -168,16 +168,33 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
     // ---- execute
     void *psi = state(0);
     int pos = 0;
-    auto forward_to = [&](int target) {
+    // forward gates up to `target`; a run of three or more CNOTs goes through
+    // `scratch` (a register free at this point) as one gather and one copy
+    auto forward_to = [&](int target, void *scratch) {
         for (; pos < target; ++pos) {
             const qng_gate &g = c.gates[pos];
+            if (scratch && g.kind == QNG_CNOT) {
+                int ctl[kCnotRunMax], tgt[kCnotRunMax], k = 0;
+                while (pos + k < target && k < kCnotRunMax && c.gates[pos + k].kind == QNG_CNOT) {
+                    ctl[k] = c.gates[pos + k].q0;
+                    tgt[k] = c.gates[pos + k].q1;
+                    ++k;
+                }
+                if (k >= 3) {
+                    launch_cnot_run<R>(psi, scratch, n, ctl, tgt, k, st);
+                    launch_copy<R>(scratch, psi, n, st);
+                    stats->other_launches += 2;
+                    pos += k - 1;
+                    continue;
+                }
+            }
             if (g.kind == QNG_CNOT) launch_cnot<R>(psi, nullptr, n, g.q0, g.q1, st);
             else if (g.kind == QNG_CZ) launch_cz<R>(psi, nullptr, n, g.q0, g.q1, st);
             else launch_apply_1q<R>(psi, nullptr, n, g.q0, to_dev(fwd[pos]), st);
             ++stats->other_launches;
         }
     };
-    forward_to(c.rots[0].pos);
+    forward_to(c.rots[0].pos, nullptr);
     launch_pauli_prod<R>(psi, psi, n, c.rots[0].qubit, c.rots[0].axis, buf.reduce_partials, buf.traw, st);
     stats->other_launches += 2;
     for (const Group &G : groups) {
@@ -201,7 +218,7 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
                 pos = rs.pos;
                 continue;
             }
-            forward_to(rp.pos);
+            forward_to(rp.pos, reg(b, 0));
             int qr = -1;
             const double *mrow = d_fmats;
             if (rs.pos == rp.pos + 1) {
@@ -209,7 +226,7 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
                 mrow = d_fmats + (size_t)rp.pos * 8;
                 pos = rs.pos;
             } else {
-                forward_to(rs.pos);
+                forward_to(rs.pos, reg(b, 0));
             }
             launch_advance_seed<R>(psi, reg(b, 0), reg(b, W), n, qr, mrow, rs.qubit, rs.axis, buf.reduce_partials,
                                    buf.traw + 2 * s, st);

@@ -213,6 +213,23 @@ __global__ void k_cnot(typename Cplx<R>::T *s0, typename Cplx<R>::T *s1, int n, 
     }
 }
 
+// A run of CNOTs as one gather: undoing the run on the output index y (its
+// CNOTs in reverse order, each its own inverse) gives the input index.
+struct CnotRun {
+    uint8_t c[kCnotRunMax], t[kCnotRunMax];
+    int count;
+};
+
+template <typename R>
+__global__ void k_cnot_run(const typename Cplx<R>::T *src, typename Cplx<R>::T *dst, int n, CnotRun run) {
+    const uint64_t dim = uint64_t(1) << n;
+    for (uint64_t y = blockIdx.x * (uint64_t)kBlock + threadIdx.x; y < dim; y += (uint64_t)gridDim.x * kBlock) {
+        uint64_t x = y;
+        for (int k = run.count - 1; k >= 0; --k) x ^= ((x >> run.c[k]) & 1) << run.t[k];
+        dst[y] = src[x];
+    }
+}
+
 // CZ(a, b): negate amplitudes with both bits set.
 template <typename R>
 __global__ void k_cz(typename Cplx<R>::T *s0, typename Cplx<R>::T *s1, int n, int a, int b) {
@@ -903,6 +920,23 @@ template <typename R> void launch_fixed_multi(const StepRegs &regs, int n, bool 
     check_launch();
 }
 
+template <typename R>
+void launch_cnot_run(const void *src, void *dst, int n, const int *control, const int *target, int count,
+                     hipStream_t st) {
+    if (count < 0 || count > kCnotRunMax) throw hipErrorInvalidValue;
+    CnotRun run;
+    run.count = count;
+    for (int k = 0; k < count; ++k) {
+        if (control[k] < 0 || control[k] >= n || target[k] < 0 || target[k] >= n) throw hipErrorInvalidValue;
+        run.c[k] = (uint8_t)control[k];
+        run.t[k] = (uint8_t)target[k];
+    }
+    const uint64_t dim = uint64_t(1) << n;
+    hipLaunchKernelGGL(k_cnot_run<R>, dim3(grid_for(dim)), dim3(kBlock), 0, st, (const typename Cplx<R>::T *)src,
+                       (typename Cplx<R>::T *)dst, n, run);
+    check_launch();
+}
+
 template <typename R> void launch_cnot(void *s0, void *s1, int n, int c, int t, hipStream_t st) {
     hipLaunchKernelGGL(k_cnot<R>, dim3(grid_for(uint64_t(1) << (n - 2))), dim3(kBlock), 0, st,
                        (typename Cplx<R>::T *)s0, (typename Cplx<R>::T *)s1, n, c, t);
@@ -1059,6 +1093,7 @@ void launch_grad_from_raw(const double *graw, const int *param_of, int P, double
                                        hipStream_t);                                                              \
     template void launch_fixed_multi<R>(const StepRegs &, int, bool, int, int, hipStream_t);                      \
     template void launch_cnot<R>(void *, void *, int, int, int, hipStream_t);                                     \
+    template void launch_cnot_run<R>(const void *, void *, int, const int *, const int *, int, hipStream_t);       \
     template void launch_cz<R>(void *, void *, int, int, int, hipStream_t);                                       \
     template void launch_seed<R>(const void *, void *, void *, int, int, int, hipStream_t, int);                 \
     template void launch_pauli_prod<R>(const void *, const void *, int, int, int, double *, double *, hipStream_t, \

@@ -66,6 +66,14 @@ template <typename R>
 void launch_apply_c1q(void *s0, void *s1, int n, int c, int q, const DevMat2 &m, hipStream_t st);
 template <typename R> void launch_cnot(void *s0, void *s1, int n, int control, int target, hipStream_t st);
 
+// A run of CNOTs (control[k], target[k], k = 0 .. count-1, applied in that
+// order) as one permutation of the amplitudes, out of place: dst[y] =
+// src[x] with x the index the run maps to y.  count <= kCnotRunMax.
+constexpr int kCnotRunMax = 64;
+template <typename R>
+void launch_cnot_run(const void *src, void *dst, int n, const int *control, const int *target, int count,
+                     hipStream_t st);
+
 // Pauli-string gates, S in mask form (S psi)[x] = (-i)^{n_y} (-1)^{popcount(x & zy)} psi[x ^ flip]:
 // apply c + (sr + i si) S to one register (s1 == nullptr) or two; lam = y, phi = S y;
 // dest (one complex128) = <a| S |b> (partials: reduce_blocks(n) complex128).
