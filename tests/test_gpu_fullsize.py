@@ -168,3 +168,10 @@ def test_n26_c64_sampled_and_vs_c128(ctx, qng):
     assert max(eG, eT, eg, eE) <= bound
     assert ed <= max(bound, kappa * bound)
     compare_sample(res64, T64, oracle_sample(pr, sel, pr.name), sel, bound, pr.name + " c64")
+    # the step as the benchmark times it (no G output: real-part passes) gives the
+    # same dtheta, gradient and energy as the step that returns G
+    timed = ctx.step(qng.Circuit.from_problem(pr), pr.theta, pr.dt, pr.tikhonov, prec="c64", want_G=False)
+    e_t = rel_err(timed["dtheta"], res64["dtheta"])
+    say(f"{pr.name} c64 step without G output vs with: |ddtheta|={e_t:.2e}")
+    assert e_t <= 1e-13
+    assert np.array_equal(timed["grad"], res64["grad"]) and timed["E"] == res64["E"]
