@@ -784,8 +784,10 @@ BatchRun batch_metric(qng_ctx *ctx, const std::vector<Problem> &pbs, const doubl
     HIPCHECK(hipMemGetInfo(&free_b, &total_b));
     const uint64_t arena_cap = (uint64_t)(free_b + ctx->ws_bytes) / 4;
     for (auto &kv : by_m) {
+        // columns per lambda sweep: blocks of two for full tiles, as in the single step
+        const int width = block_width(ctx->opt_block, pbs[kv.second[0]].circ, tun.tile_qubits, amp, f64);
         std::vector<int32_t> key = {kv.first, amp, sweep_reg_mode(ctx, amp), tun.tile_qubits, tun.target_tiles,
-                                    real_products ? 1 : 0};
+                                    real_products ? 1 : 0, width};
         for (int b : kv.second) append_structure_key(pbs[b].circ, key);
         auto it = ctx->batch_classes.find(key);
         std::shared_ptr<BatchClass> bc;
@@ -796,7 +798,7 @@ BatchRun batch_metric(qng_ctx *ctx, const std::vector<Problem> &pbs, const doubl
             std::vector<std::shared_ptr<const SweepPlan>> plans;
             for (int b : kv.second) {
                 mem.push_back(&pbs[b].circ);
-                plans.push_back(ctx->sweep_cache.get_shared(pbs[b].circ, tun.tile_qubits, amp, 1, f64));
+                plans.push_back(ctx->sweep_cache.get_shared(pbs[b].circ, tun.tile_qubits, amp, 1, f64, width));
             }
             bc = std::make_shared<BatchClass>();
             bc->sched = std::make_shared<BatchSchedule>(build_batch_schedule(mem, plans, amp, tun, arena_cap));
@@ -893,7 +895,8 @@ BatchRun batch_metric(qng_ctx *ctx, const std::vector<Problem> &pbs, const doubl
             const Problem &pb = pbs[mem[i]];
             circs.push_back(&pb.circ);
             d.psi.push_back(base + L.psi[mem[i]]);
-            d.traw.push_back((double *)(base + L.traw[mem[i]]));
+            // T right after the member's raw L: the blocks' in-pass seeds reduce into it
+            d.traw.push_back(d.lraw + 2 * (S.lraw_base[i] + (int64_t)pb.circ.P * pb.circ.P));
             for (const Rot &r : pb.circ.rots) {
                 const Mat2 &m = pb.fwd[r.pos];
                 double *o = &fm[(size_t)(S.gate_base[i] + r.pos) * 8];

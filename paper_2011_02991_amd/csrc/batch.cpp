@@ -56,15 +56,16 @@ BatchSchedule build_batch_schedule(const std::vector<const Circuit *> &members,
         if (b == 0) {
             S.m = p.m;
             S.rb = p.rb;
-        } else if (p.m != S.m || p.rb != S.rb) {
-            fail(QNG_E_DEVICE, "batch schedule: members of one class differ in tile width (internal)");
+            S.width = p.width;
+        } else if (p.m != S.m || p.rb != S.rb || p.width != S.width) {
+            fail(QNG_E_DEVICE, "batch schedule: members of one class differ in tile or block width (internal)");
         }
         pass_base[b] = (int64_t)S.passes.size();
         const uint32_t op_base = (uint32_t)S.ops.size(), map_base = (uint32_t)S.maps.size();
         S.gate_base[b] = S.mat_rows;
         S.mat_rows += c.M;
         S.lraw_base[b] = S.lraw_elems;
-        S.lraw_elems += (int64_t)c.P * c.P;
+        S.lraw_elems += (int64_t)c.P * c.P + c.P;
         for (DevPass dp : p.dev_passes) {
             dp.op_begin += op_base;
             dp.map_load += map_base;
@@ -109,7 +110,7 @@ BatchSchedule build_batch_schedule(const std::vector<const Circuit *> &members,
             const int b = queue[qi].first, col = queue[qi].second;
             const int n = members[b]->n;
             const uint64_t tiles = uint64_t(1) << (n - S.m);
-            const uint64_t pair = 2 * ((uint64_t(1) << n) * (uint64_t)amp);
+            const uint64_t pair = (uint64_t)(S.width + 1) * ((uint64_t(1) << n) * (uint64_t)amp);
             if (!act.empty() && act_tiles + tiles > target) break;
             uint64_t reg;
             std::vector<uint64_t> &fl = free_pairs[n];
@@ -142,8 +143,10 @@ BatchSchedule build_batch_schedule(const std::vector<const Circuit *> &members,
             it.pass = (uint32_t)(pass_base[a.b] + p.col_pass_begin[a.col] + (int64_t)a.t);
             it.ntiles = tiles;
             it.partial_off = poff;
+            const uint64_t V = (uint64_t(1) << n) * (uint64_t)amp;
             it.regA = (void *)(uintptr_t)a.reg;
-            it.regB = (void *)(uintptr_t)(a.reg + (uint64_t(1) << n) * (uint64_t)amp);
+            it.regB = (void *)(uintptr_t)(a.reg + V);
+            it.regC = S.width > 1 ? (void *)(uintptr_t)(a.reg + 2 * V) : nullptr;
             S.items.push_back(it);
             ++L.n_items;
             L.total_tiles += tiles;
@@ -183,6 +186,7 @@ void upload_batch_images(const BatchSchedule &s, const BatchDevice &d, hipStream
     for (LaunchItem &it : items) {
         it.regA = d.arena + (uintptr_t)it.regA;
         it.regB = d.arena + (uintptr_t)it.regB;
+        if (s.width > 1) it.regC = d.arena + (uintptr_t)it.regC;
     }
     auto put = [&](size_t off, const void *src, size_t bytes) {
         if (bytes) BCHECK(hipMemcpyAsync(d.images + off, src, bytes, hipMemcpyHostToDevice, st));
@@ -246,14 +250,16 @@ void enqueue_batch_metric(const BatchSchedule &s, const std::vector<const Circui
             } else {
                 forward_to(pr.member, rs.pos);
             }
+            // lambda and the block's top phi register (its last one; the lower
+            // column's phi is seeded inside the block's sweep)
             char *lam = d.arena + pr.reg_off;
-            char *phi = lam + (size_t(1) << c.n) * (size_t)s.amp;
+            char *phi = lam + (size_t)s.width * (size_t(1) << c.n) * (size_t)s.amp;
             launch_advance_seed<R>(d.psi[pr.member], lam, phi, c.n, qr, mrow, rs.qubit, rs.axis, d.reduce_partials,
                                    d.traw[pr.member] + 2 * sidx, st);
         }
         if (events) BCHECK(hipEventRecord((*events)[2 * li], st));
         launch_sweep_pass<R>(items + L.item_begin, (int)L.n_items, L.total_tiles, passes, ops, maps, d.adj_mats,
-                             d.adj_mats32, d.partials, s.m, s.rb, reg_mode, 1, st, real_products);
+                             d.adj_mats32, d.partials, s.m, s.rb, reg_mode, s.width, st, real_products);
         if (events) BCHECK(hipEventRecord((*events)[2 * li + 1], st));
         launch_reduce_tasks(tasks + L.task_begin, (int)L.n_tasks, d.partials, d.lraw, st);
     }

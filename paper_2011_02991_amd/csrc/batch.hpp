@@ -33,9 +33,9 @@ struct BatchTuning {
     int target_tiles = 4096;    // work-groups per launch the admission aims for
 };
 
-struct BatchPrep {              // admission of column `col` of `member` into a register pair
+struct BatchPrep {              // admission of column block `col` of `member` into a register block
     int member, col;
-    uint64_t reg_off;           // byte offset of the pair (lambda, then phi) in the arena
+    uint64_t reg_off;           // byte offset of the block (lambda, then the width phi registers) in the arena
 };
 
 struct BatchLaunch {
@@ -44,12 +44,14 @@ struct BatchLaunch {
 
 struct BatchSchedule {
     int m = 0, rb = 0, amp = 0;
+    int width = 1;                                           // columns per lambda sweep (all members)
     std::vector<std::shared_ptr<const SweepPlan>> plans;     // per member
     std::vector<DevPass> passes;                             // merged images
     std::vector<DevOp> ops;
     std::vector<DevMap> maps;
     std::vector<int64_t> gate_base;                          // per member: first row of its matrices
-    std::vector<int64_t> lraw_base;                          // per member: first complex of its raw L
+    std::vector<int64_t> lraw_base;                          // per member: first complex of its raw L (P*P),
+                                                             // followed by its raw T (P)
     int64_t mat_rows = 0, lraw_elems = 0;
     std::vector<LaunchItem> items;                           // regA/regB: arena offsets
     std::vector<ReduceTask> tasks;
