@@ -214,10 +214,26 @@ void enqueue_batch_metric(const BatchSchedule &s, const std::vector<const Circui
     std::vector<int> pos(nb, 0);
     std::vector<char> started(nb, 0);
 
-    auto forward_to = [&](int b, int target) {
+    // forward gates of member b up to `target`; with a scratch register free,
+    // a run of three or more CNOTs is one gather and one copy back
+    auto forward_to = [&](int b, int target, void *scratch) {
         const Circuit &c = *members[b];
         for (; pos[b] < target; ++pos[b]) {
             const qng_gate &g = c.gates[pos[b]];
+            if (scratch && g.kind == QNG_CNOT) {
+                int ctl[kCnotRunMax], tgt[kCnotRunMax], k = 0;
+                while (pos[b] + k < target && k < kCnotRunMax && c.gates[pos[b] + k].kind == QNG_CNOT) {
+                    ctl[k] = c.gates[pos[b] + k].q0;
+                    tgt[k] = c.gates[pos[b] + k].q1;
+                    ++k;
+                }
+                if (k >= 3) {
+                    launch_cnot_run<R>(d.psi[b], scratch, c.n, ctl, tgt, k, st);
+                    launch_copy<R>(scratch, d.psi[b], c.n, st);
+                    pos[b] += k - 1;
+                    continue;
+                }
+            }
             if (g.kind == QNG_CNOT) launch_cnot<R>(d.psi[b], nullptr, c.n, g.q0, g.q1, st);
             else if (g.kind == QNG_CZ) launch_cz<R>(d.psi[b], nullptr, c.n, g.q0, g.q1, st);
             else launch_apply_1q_tab<R>(d.psi[b], nullptr, c.n, g.q0, d.fwd_mats + (s.gate_base[b] + pos[b]) * 8, st);
@@ -227,7 +243,7 @@ void enqueue_batch_metric(const BatchSchedule &s, const std::vector<const Circui
         if (started[b]) return;
         started[b] = 1;
         const Circuit &c = *members[b];
-        forward_to(b, c.rots[0].pos);
+        forward_to(b, c.rots[0].pos, nullptr);
         launch_pauli_prod<R>(d.psi[b], d.psi[b], c.n, c.rots[0].qubit, c.rots[0].axis, d.reduce_partials, d.traw[b],
                              st);
     };
@@ -241,19 +257,32 @@ void enqueue_batch_metric(const BatchSchedule &s, const std::vector<const Circui
             const Rot &rs = c.rots[sidx];
             const Rot &rp = c.rots[sidx - 1];
             start(pr.member);
-            int qr = -1;
-            const double *mrow = d.fwd_mats;
-            if (pos[pr.member] == rp.pos && rs.pos == rp.pos + 1) {
-                qr = rp.qubit;
-                mrow = d.fwd_mats + (s.gate_base[pr.member] + rp.pos) * 8;
-                pos[pr.member] = rs.pos;
-            } else {
-                forward_to(pr.member, rs.pos);
-            }
             // lambda and the block's top phi register (its last one; the lower
             // column's phi is seeded inside the block's sweep)
             char *lam = d.arena + pr.reg_off;
             char *phi = lam + (size_t)s.width * (size_t(1) << c.n) * (size_t)s.amp;
+            int &p = pos[pr.member];
+            const int64_t gb = s.gate_base[pr.member];
+            // two rotations before y_s on two other qubits: one pass, as in the single step
+            const int ra = p < c.M ? c.rot_at[p] : -1;
+            if (ra >= 0 && p + 1 == rp.pos && rs.pos == rp.pos + 1 && c.n >= 3 && c.rots[ra].qubit != rp.qubit &&
+                c.rots[ra].qubit != rs.qubit && rp.qubit != rs.qubit) {
+                launch_advance2_seed<R>(d.psi[pr.member], lam, phi, c.n, c.rots[ra].qubit, d.fwd_mats + (gb + p) * 8,
+                                        rp.qubit, d.fwd_mats + (gb + rp.pos) * 8, rs.qubit, rs.axis,
+                                        d.reduce_partials, d.traw[pr.member] + 2 * sidx, st);
+                p = rs.pos;
+                continue;
+            }
+            int qr = -1;
+            const double *mrow = d.fwd_mats;
+            forward_to(pr.member, rp.pos, lam);
+            if (p == rp.pos && rs.pos == rp.pos + 1) {
+                qr = rp.qubit;
+                mrow = d.fwd_mats + (gb + rp.pos) * 8;
+                p = rs.pos;
+            } else {
+                forward_to(pr.member, rs.pos, lam);
+            }
             launch_advance_seed<R>(d.psi[pr.member], lam, phi, c.n, qr, mrow, rs.qubit, rs.axis, d.reduce_partials,
                                    d.traw[pr.member] + 2 * sidx, st);
         }
