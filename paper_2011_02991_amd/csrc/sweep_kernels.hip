@@ -1009,7 +1009,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 1
     }
     const LaunchItem it = items[lo];
     const DevPass *pp = passes + it.pass;
-    const uint32_t tile = wg - it.tile_begin;
+    // consecutive passes of a column walk their tiles in opposite orders, so a
+    // pass starts on the tiles the previous one wrote last (still in the
+    // last-level cache)
+    const uint32_t tile = (it.pass & 1u) ? it.ntiles - 1 - (wg - it.tile_begin) : wg - it.tile_begin;
     const uint4 ph0 = *reinterpret_cast<const uint4 *>(pp);          // op_begin, n_ops, slots|m|n, nrest|zsum|rb
     const uint4 ph1 = *(reinterpret_cast<const uint4 *>(pp) + 1);    // map_load, pad, tile_q[0..7]
     const int m = (int)((ph0.z >> 16) & 0xffu);
