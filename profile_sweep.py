@@ -62,18 +62,27 @@ def _short(name: str) -> str:
 def _family(name: str) -> str:
     if "k_sweep_reg" in name:
         return "sweep"
-    if "copy" in name.lower():
-        return "copy"
     return _short(name)
 
 
 def _pmc(dbs):
+    """Counter sums per kernel family, plus the calibration copy on its own.
+
+    The calibration copy is the first dispatch of each profiled process (the
+    512 MiB device copy that run() issues before the step).  Only that one
+    dispatch calibrates: the step itself launches copies of the same size
+    (a state clone is a 512 MiB copy at n=26), which must not be summed in.
+    """
     agg = collections.defaultdict(lambda: collections.defaultdict(float))
     disp = collections.defaultdict(set)
     for db in dbs:
         con = sqlite3.connect(db)
-        for name, cn, v, d in con.execute("select name, counter_name, counter_value, dispatch_id from pmc_events"):
-            f = _family(name)
+        rows = list(con.execute("select name, counter_name, counter_value, dispatch_id from pmc_events"))
+        if not rows:
+            continue
+        first = min(d for _, _, _, d in rows)
+        for name, cn, v, d in rows:
+            f = "calib" if d == first else _family(name)
             agg[f][cn] += v
             disp[f].add(d)
     return agg, {k: len(v) for k, v in disp.items()}
@@ -100,13 +109,15 @@ def summarize(args):
         open(args.out, "w").write("\n".join(lines) + "\n")
     elif args.kind == "traffic":
         agg, nd = _pmc(dbs)
-        sw, cp = agg["sweep"], agg["copy"]
+        sw, cp = agg["sweep"], agg["calib"]
         f_fetch = COPY_BYTES / (cp["FETCH_SIZE"] * 1024) if cp.get("FETCH_SIZE") else None
         f_write = COPY_BYTES / (cp["WRITE_SIZE"] * 1024) if cp.get("WRITE_SIZE") else None
         n = nd.get("sweep", 1)
         fetch = sw.get("FETCH_SIZE", 0) * 1024 * (f_fetch or 1) / n
         write = sw.get("WRITE_SIZE", 0) * 1024 * (f_write or 1) / n
         out = {"kernel": "k_sweep_reg", "title": args.title, "command": cmd, "launches": n,
+               "raw_fetch_kib": sw.get("FETCH_SIZE", 0), "raw_write_kib": sw.get("WRITE_SIZE", 0),
+               "calib_fetch_kib": cp.get("FETCH_SIZE"), "calib_write_kib": cp.get("WRITE_SIZE"),
                "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
                "bytes_per_launch": fetch + write, "copy_scale_fetch": f_fetch, "copy_scale_write": f_write,
                "kernel_sha256": hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()}
