@@ -59,8 +59,6 @@ def _load():
     lib.oracle_apply_pauli_sum.argtypes = [c_int, c_int, c_p, c_p, c_p, c_p]
     lib.oracle_apply_pauli_letter.argtypes = [c_int, c_int, c_int, c_p]
     lib.oracle_apply_gate.argtypes = [c_int, c_p, c_p, c_int, c_p, c_p]
-    lib.oracle_inner.argtypes = [c_int, c_p, c_p, c_p]
-    lib.oracle_inner.restype = None
     _lib = lib
     return lib
 
@@ -181,13 +179,3 @@ def apply_pauli_letter(n: int, q: int, letter: int, psi: np.ndarray) -> np.ndarr
     out = np.ascontiguousarray(psi, dtype=np.complex128).copy()
     lib.oracle_apply_pauli_letter(n, q, letter, _ptr(out))
     return out
-
-
-def inner(a: np.ndarray, b: np.ndarray) -> complex:
-    lib = _load()
-    a = np.ascontiguousarray(a, dtype=np.complex128)
-    b = np.ascontiguousarray(b, dtype=np.complex128)
-    out = np.zeros(1, dtype=np.complex128)
-    n = int(np.log2(a.shape[0]))
-    lib.oracle_inner(n, _ptr(a), _ptr(b), _ptr(out))
-    return complex(out[0])

@@ -7,7 +7,9 @@ real sizes, which makes it a good independent check at n <= 4.
 
 * rotation: scipy's matrix exponential of +i theta sigma / 2 (the paper's
   convention, Sec. 2 rotation example);
-* its derivative: (i/2) sigma R(theta) (Sec. 2, Pauli-generator form);
+* its derivative: (i/2) sigma R(theta) (Sec. 2, Pauli-generator form); the
+  derivative of U by a parameter is the product-rule sum over the gates that
+  carry it (one term for a unique parameter, Sec. 2; several when shared);
 * CNOT and CZ: permutation / diagonal matrices written from their action on
   basis states;
 * controlled rotations (kinds 5/6/7, control q0, target q1): |0><0| (x) I +
@@ -90,14 +92,30 @@ def _input(problem) -> np.ndarray:
     return v
 
 
-def unitary(problem, deriv_param: int = -1) -> np.ndarray:
-    """U = G_M ... G_1 (or dU/dtheta_p when deriv_param = p)."""
+def unitary(problem) -> np.ndarray:
+    """U = G_M ... G_1, every gate in list order."""
     n = problem.n_qubits
     u = np.eye(2 ** n, dtype=np.complex128)
     for g in problem.gates:
-        u = gate_unitary(n, g, problem.theta, derivative=(int(g[3]) == deriv_param and deriv_param >= 0),
-                         strings=getattr(problem, "strings", None)) @ u
+        u = gate_unitary(n, g, problem.theta, strings=getattr(problem, "strings", None)) @ u
     return u
+
+
+def derivative_unitary(problem, p: int) -> np.ndarray:
+    """dU/dtheta_p by the product rule: one term per gate that carries p, that
+    gate replaced by its derivative and every other gate kept (a parameter
+    shared by several gates gives a sum of such terms)."""
+    n = problem.n_qubits
+    strings = getattr(problem, "strings", None)
+    total = np.zeros((2 ** n, 2 ** n), dtype=np.complex128)
+    for k, gk in enumerate(problem.gates):
+        if int(gk[3]) != p:
+            continue
+        u = np.eye(2 ** n, dtype=np.complex128)
+        for j, g in enumerate(problem.gates):
+            u = gate_unitary(n, g, problem.theta, derivative=(j == k), strings=strings) @ u
+        total += u
+    return total
 
 
 def brute_force(problem):
@@ -105,7 +123,7 @@ def brute_force(problem):
     vin = _input(problem)
     psi = unitary(problem) @ vin
     P = problem.n_params
-    D = np.stack([unitary(problem, p) @ vin for p in range(P)]) if P else np.zeros((0, psi.shape[0]))
+    D = np.stack([derivative_unitary(problem, p) @ vin for p in range(P)]) if P else np.zeros((0, psi.shape[0]))
     L = D.conj() @ D.T
     T = D @ psi.conj()
     G = L - np.outer(T.conj(), T)

@@ -43,8 +43,7 @@
  *
  * Loops over amplitudes may run on several OpenMP threads; every amplitude is
  * written by exactly one iteration, so the result does not depend on the
- * thread count.  There are no sums across amplitudes in this file except in
- * or_inner (a plain sequential sum).
+ * thread count.  There are no sums across amplitudes in this file.
  */
 #include <complex.h>
 #include <math.h>
@@ -306,13 +305,4 @@ int oracle_apply_gate(int n, const int32_t *gate, const double *theta, int deriv
 {
     or_apply_gate(psi, n, gate, theta, derivative, strings);
     return 0;
-}
-
-/* Plain sequential <a|b> = sum_x conj(a_x) b_x. */
-void oracle_inner(int n, const cplx *a, const cplx *b, cplx *out)
-{
-    const int64_t dim = (int64_t)1 << n;
-    cplx acc = 0;
-    for (int64_t x = 0; x < dim; ++x) acc += conj(a[x]) * b[x];
-    *out = acc;
 }

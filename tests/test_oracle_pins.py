@@ -369,6 +369,29 @@ def test_shared_parameters_contract_the_unshared_metric():
     np.testing.assert_allclose(gs, J.T @ g, atol=1e-13)
 
 
+def test_dense_route_sums_derivative_terms_of_a_shared_parameter():
+    """The dense brute force with shared angles: d U / d theta_a is the sum over
+    the gates carrying a (product rule), checked against central differences of
+    the dense unitary itself (error h^2/6 times the third derivative, at most
+    (k/2)^3 for k gates carrying the angle), and its G and gradient against the
+    oracle's C route on the same problem."""
+    pr = W.share_params(W.random_circuit(3, 16, 905, n_terms=4), 3, 906)
+    assert any(int((pr.gates[:, 3] == a).sum()) > 1 for a in range(pr.n_params))
+    h = 1e-5
+    for a in range(pr.n_params):
+        k = int((pr.gates[:, 3] == a).sum())
+        tp, tm = pr.theta.copy(), pr.theta.copy()
+        tp[a] += h
+        tm[a] -= h
+        fd = (dense.unitary(W.Problem(**{**pr.__dict__, "theta": tp}))
+              - dense.unitary(W.Problem(**{**pr.__dict__, "theta": tm}))) / (2 * h)
+        assert np.abs(dense.derivative_unitary(pr, a) - fd).max() < h * h / 6 * (k / 2) ** 3 + 1e-9
+    bf = dense.brute_force(pr)
+    st = oracle.step(pr)
+    np.testing.assert_allclose(st["G"], bf["G"], atol=1e-13)
+    np.testing.assert_allclose(st["grad"], bf["grad"], atol=1e-12)
+
+
 # ------------------------------------------------------ controlled rotations
 
 def test_controlled_rotation_on_basis_states():
