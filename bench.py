@@ -3,8 +3,10 @@
 Default workload: 26 qubits, 8 layers of [RY on every qubit, RZ on every qubit,
 CNOT chain], P = 416 parameters, 100-term random Pauli Hamiltonian, input
 |0...0>, dt = 0.1, Tikhonov shift 1e-4.  The timed precision is complex64
-state storage with FP64 inner products and FP64 solve ("chosen"); the same
-step in complex128 ("plain FP64") is timed beside it.
+state storage with every inner-product term formed and accumulated in FP64
+and an FP64 solve ("chosen"); the same step in complex128 ("plain FP64") is
+timed beside it, and the complex64 step with FP32 per-thread product shares as
+a labelled variant.
 
 Prints ONE JSON line (rank 0, N = 1 only; this build runs on a single GPU).
 """
@@ -44,12 +46,13 @@ def parse():
     ap.add_argument("--gate-qubits", type=int, default=26)
     ap.add_argument("--tile", type=int, default=0, help="tile qubits of the fused passes (0 = library default)")
     ap.add_argument("--f64-regs", type=int, default=0, help="complex64: compute sweep tiles in FP64 registers")
-    ap.add_argument("--exact-products", type=int, default=0,
-                    help="complex64 with FP32 registers: form every inner-product term in FP64")
+    ap.add_argument("--exact-products", type=int, default=1,
+                    help="complex64 with FP32 registers: 1 (default) every inner-product term formed in FP64, "
+                         "0 each thread's share formed in FP32")
     ap.add_argument("--no-with-g", action="store_true",
                     help="skip timing the step that also returns the complex G")
-    ap.add_argument("--no-exact", action="store_true",
-                    help="skip the complex64 leg with every inner-product term in FP64")
+    ap.add_argument("--no-shares", action="store_true",
+                    help="skip the complex64 leg with FP32 per-thread product shares")
     ap.add_argument("--variants", action="store_true",
                     help="also time the cheaper metric variants (block-diagonal per layer, L only) on the workload")
     ap.add_argument("--gateset", action="store_true",
@@ -94,19 +97,34 @@ def gate_apply_bandwidth(qng, ctx, n, prec):
     """Isolated single-gate apply at n qubits on one state, timed with HIP events
     on the library's stream.  Bytes: a rotation reads and writes every amplitude
     (2V); a CNOT swaps the half of the amplitudes whose control is 1 (V); a CZ
-    negates the quarter with both bits set (V/2)."""
+    negates the quarter with both bits set (V/2).  The attainable-bandwidth
+    reference is the library's own clone kernel (read V, write V) on the same
+    stream."""
     import numpy as np
     import torch
     dev = torch.device("cuda:0")
     dtype = torch.complex64 if prec == "c64" else torch.complex128
     state = torch.zeros(2 ** n, dtype=dtype, device=dev)
     state[0] = 1
+    other = torch.empty_like(state)
     amp = 8 if prec == "c64" else 16
     V = amp * 2 ** n
     moved = {0: 2 * V, 1: 2 * V, 2: 2 * V, 3: V, 4: V // 2}
     results = []
     s = torch.cuda.Stream()
     ctx.set_stream(s.cuda_stream)
+    reps = 5
+
+    def timed(fn):
+        fn()   # warm
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            fn()
+        e1.record(s)
+        s.synchronize()
+        return e0.elapsed_time(e1) / reps
+
     try:
         with torch.cuda.stream(s):
             for kind in (0, 1, 2, 3, 4):
@@ -114,36 +132,23 @@ def gate_apply_bandwidth(qng, ctx, n, prec):
                     g = [[kind, q, -1, 0]] if kind < 3 else [[kind, q, q + 1, -1]]
                     circ = qng.Circuit(n, np.array(g, dtype=np.int32))
                     th = [0.3] if kind < 3 else []
-                    ctx.apply_circuit_dev(circ, th, state.data_ptr(), prec=prec)   # warm
-                    reps = 5
-                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                    e0.record(s)
-                    for _ in range(reps):
-                        ctx.apply_circuit_dev(circ, th, state.data_ptr(), prec=prec)
-                    e1.record(s)
-                    s.synchronize()
-                    ms = e0.elapsed_time(e1) / reps
+                    ms = timed(lambda: ctx.apply_circuit_dev(circ, th, state.data_ptr(), prec=prec))
                     results.append((kind, q, moved[kind] / (ms * 1e-3) / 1e9))
+            copy_ms = timed(lambda: ctx.clone_state_dev(n, state.data_ptr(), other.data_ptr(), prec=prec))
     finally:
         torch.cuda.synchronize()
         ctx.set_stream(None)
-    # a plain device copy of one state (read V, write V) as the attainable reference
-    other = torch.empty_like(state)
-    other.copy_(state)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        other.copy_(state)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_GBps = 2 * V / (e0.elapsed_time(e1) / 5 * 1e-3) / 1e9
+    copy_GBps = 2 * V / (copy_ms * 1e-3) / 1e9
     rot = sorted(r[2] for r in results if r[0] < 3)
     fixed = sorted(r[2] for r in results if r[0] >= 3)
+    names = {0: "RX", 1: "RY", 2: "RZ", 3: "CNOT", 4: "CZ"}
+    per_q = {names[k]: [round(r[2], 1) for r in results if r[0] == k] for k in names}
     return {"rotation_median_GBps": rot[len(rot) // 2], "rotation_worst_GBps": rot[0],
             "rotation_best_GBps": rot[-1], "fixed_median_GBps": fixed[len(fixed) // 2] if fixed else None,
             "n": n, "gates_measured": len(results), "frac_of_8TBps": rot[len(rot) // 2] / HBM_PEAK_GBS,
-            "copy_GBps": copy_GBps, "rotation_median_frac_of_copy": rot[len(rot) // 2] / copy_GBps}
+            "worst_frac_of_8TBps": rot[0] / HBM_PEAK_GBS,
+            "copy_GBps": copy_GBps, "copy_kernel": "library clone (qng_clone_state_dev)",
+            "rotation_median_frac_of_copy": rot[len(rot) // 2] / copy_GBps, "per_q_GBps": per_q}
 
 
 def precision_report(pr, res, ref, prec, ref_prec):
@@ -163,34 +168,88 @@ def precision_report(pr, res, ref, prec, ref_prec):
             "rel_ddtheta": rel(res["dtheta"], ref["dtheta"]), "kappa_shifted_metric": float(np.linalg.cond(g))}
 
 
-def cpu_baseline(pr):
-    """The oracle, as it stands, on a bounded sample of the workload: its
-    forward state (every gate of the circuit applied gate by gate) and a few of
-    its inner products, timed, then extrapolated to the oracle's full step
-    (P derivative states built from a rolling prefix, the P x P Gram matrix,
-    H psi and the gradient) by its primitive counts."""
+def sample_params(P: int, seed: int):
+    """First, last and one run of two consecutive parameter indices."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    a = int(rng.integers(1, P - 2))
+    return sorted({0, P - 1, a, a + 1})
+
+
+def cpu_baseline(pr, gpu_results):
+    """The oracle, as it stands, on a bounded sample of the workload, by its own
+    route: derivative states of a few sampled parameters (rolling prefix, then
+    each state's suffix, gate by gate), their Gram matrix, T, H psi and the
+    gradient entries (numpy library products), timed on the host's cores.
+    The full step is extrapolated from the measured rates: gate applies by the
+    oracle's own count (the prefix walk plus every derivative state's suffix),
+    the P x P Gram matrix at the rate its library product reaches on a
+    32-state block, the gradient products linearly in P.  The sampled entries
+    also pin the GPU results (gpu_results: precision -> step results) to the
+    oracle."""
     import numpy as np
     import oracle
     cores = len(os.sched_getaffinity(0))
     n, M, P = pr.n_qubits, pr.n_gates, pr.n_params
-    rot_pos = [k for k in range(M) if pr.gates[k, 3] >= 0]
+    pos_of = {int(pr.gates[k, 3]): k for k in range(M) if pr.gates[k, 3] >= 0}
+    sel = sample_params(P, 7001)
     t0 = time.perf_counter()
-    psi = oracle.forward(pr)
-    t_apply = (time.perf_counter() - t0) / M
+    D, psi = oracle.derivative_states(pr, sel)
+    t_states = time.perf_counter() - t0
     t1 = time.perf_counter()
-    reps = 4
-    for _ in range(reps):
-        oracle.inner(psi, psi)
-    t_inner = (time.perf_counter() - t1) / reps
-    elapsed = time.perf_counter() - t0
-    applies = M + sum(M - k for k in rot_pos)      # prefix walk + suffix of every derivative state
-    inner = P * P + 2 * P                          # Gram matrix, T, gradient
-    est = applies * t_apply + inner * t_inner
-    del psi
-    return {"value": est, "unit": "s/step", "cores": cores, "kind": "oracle",
-            "sample": f"oracle forward state of all {M} gates plus {reps} inner products at n={n} (complex128, "
-                      f"{elapsed:.1f} s measured: {t_apply * 1e3:.1f} ms/gate apply, {t_inner * 1e3:.1f} ms/inner "
-                      f"product), extrapolated to its {applies} gate applies and {inner} inner products per step"}
+    G, T, _ = oracle.metric_from_states(D, psi)
+    t_gram_sample = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    hpsi = oracle.apply_hamiltonian(pr, psi)
+    t_h = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    E = float(np.vdot(psi, hpsi).real)
+    grad = 2.0 * (D @ hpsi.conj()).real
+    t_gradprod = (time.perf_counter() - t1) / len(sel)
+    del D, psi, hpsi
+    # Gram-matrix rate of the oracle's library product on a 32-state block
+    rng = np.random.default_rng(7002)
+    blk = rng.standard_normal((32, 2 ** min(n, 21))) + 1j * rng.standard_normal((32, 2 ** min(n, 21)))
+    blk_psi = blk[0].copy()
+    t1 = time.perf_counter()
+    oracle.metric_from_states(blk, blk_psi)
+    t_blk = time.perf_counter() - t1
+    gram_rate = 8.0 * 32 * 32 * blk.shape[1] / t_blk          # real flops per second
+    del blk, blk_psi
+    measured = time.perf_counter() - t0
+    applies_sample = M + sum(M - pos_of[p] for p in sel)
+    applies_full = M + sum(M - pos_of[p] for p in range(P))
+    t_apply = t_states / applies_sample
+    est = (applies_full * t_apply + 8.0 * P * P * (2 ** n) / gram_rate + t_h + P * t_gradprod)
+    errors = {}
+    ix = np.ix_(sel, sel)
+    for prec, res in gpu_results.items():
+        if res is None or res.get("G") is None:
+            continue
+        gs = res["G"][ix]
+        errors[prec] = {
+            "sampled_params": sel,
+            "rel_dG": float(np.abs(gs - G).max() / np.abs(G).max()),
+            "rel_dgrad": float(np.abs(res["grad"][sel] - grad).max() / np.abs(grad).max()),
+            "abs_dE": abs(res["E"] - E)}
+    base = {"value": est, "unit": "s/step", "cores": cores, "kind": "oracle",
+            "sample": f"oracle derivative states of parameters {sel} at n={n} (complex128: {applies_sample} gate "
+                      f"applies in {t_states:.1f} s, {t_apply * 1e3:.1f} ms each), their Gram matrix "
+                      f"({t_gram_sample:.2f} s), H psi ({t_h:.1f} s) and gradient entries; {measured:.1f} s "
+                      f"measured; extrapolated to the full step: {applies_full} gate applies, the {P}x{P} Gram "
+                      f"matrix at {gram_rate / 1e9:.1f} GFLOP/s (library product on a 32-state block), {P} "
+                      f"gradient products"}
+    return base, errors
+
+
+def full_oracle_small(W):
+    """The whole oracle step (every derivative state, Gram matrix, gradient,
+    solve) on the 10-qubit, 80-parameter workload, timed."""
+    import oracle
+    pr = W.config1()
+    t0 = time.perf_counter()
+    oracle.step(pr)
+    return {"workload": pr.name, "s_per_step": time.perf_counter() - t0}
 
 
 def metric_variants(qng, ctx, circ, pr, prec, reps=2):
@@ -341,9 +400,9 @@ def main():
     ctx.set_option(qng.OPT_EXACT_PRODUCTS, args.exact_products)
     ctx.set_option(qng.OPT_BLOCK_COLUMNS, args.block)
     t_chosen, res, st = time_steps(ctx, circ, pr, args.prec, args.steps, args.warmup, profile=True,
-                                   need_G=not args.no_plain)
+                                   need_G=not args.no_plain or not args.no_cpu)
     log(f"{args.prec}: {t_chosen:.3f} s/step  stats={st}")
-    plain = precision = None
+    plain = precision = res_other = None
     if not args.no_plain:
         other = "c128" if args.prec == "c64" else "c64"
         t_plain, res_other, st2 = time_steps(ctx, circ, pr, other, max(1, args.steps - 1), 1)
@@ -359,24 +418,31 @@ def main():
     if not args.no_with_g:
         t_with_G, _, _ = time_steps(ctx, circ, pr, args.prec, max(1, args.steps - 1), 0, want_G=True)
         log(f"{args.prec} with the G output: {t_with_G:.3f} s/step")
-    exact = None
-    if args.prec == "c64" and not args.f64_regs and not args.exact_products and not args.no_exact:
-        # the same step with every inner-product term formed in FP64
-        ctx.set_option(qng.OPT_EXACT_PRODUCTS, 1)
+    shares = None
+    if args.prec == "c64" and not args.f64_regs and args.exact_products and not args.no_shares:
+        # the narrower arithmetic: each thread's share of a product formed in FP32
+        ctx.set_option(qng.OPT_EXACT_PRODUCTS, 0)
         try:
-            t_exact, res_exact, _ = time_steps(ctx, circ, pr, "c64", max(1, args.steps - 1), 1)
+            t_sh, res_sh, _ = time_steps(ctx, circ, pr, "c64", max(1, args.steps - 1), 1)
         finally:
-            ctx.set_option(qng.OPT_EXACT_PRODUCTS, 0)
-        exact = {"s_per_step": t_exact,
-                 "precision_errors": precision_report(pr, res_exact, res_other, "c64", "c128") if plain else None}
-        log(f"c64 with FP64 products: {exact}")
+            ctx.set_option(qng.OPT_EXACT_PRODUCTS, args.exact_products)
+        shares = {"s_per_step": t_sh,
+                  "precision_errors": precision_report(pr, res_sh, res_other, "c64", "c128") if plain else None,
+                  "max_abs_dG_vs_exact_products": float(abs(res_sh["G"] - res["G"]).max())}
+        log(f"c64 with FP32 thread shares: {shares}")
     gate = None
     if args.gate_qubits > 0:
         gate = gate_apply_bandwidth(qng, ctx, min(args.gate_qubits, pr.n_qubits), args.prec)
         log(f"gate apply: {gate}")
     variants = metric_variants(qng, ctx, circ, pr, args.prec) if args.variants else None
     gateset = extended_gates(qng, ctx, args.prec) if args.gateset else None
-    cpu = None if args.no_cpu else cpu_baseline(pr)
+    cpu = oracle_errors = small = None
+    if not args.no_cpu:
+        cpu, oracle_errors = cpu_baseline(pr, {args.prec: res, **({plain["prec"]: res_other} if plain else {})})
+        small = full_oracle_small(W)
+        cpu["full_oracle_small_workload"] = small
+        log(f"cpu baseline: {cpu}")
+        log(f"oracle-pinned errors on sampled parameters: {oracle_errors}")
     roof = None
     if st.get("sweep_launches", 0) > 0 and st.get("sweep_ms", 0) > 0:
         nl = st["sweep_launches"]
@@ -404,7 +470,8 @@ def main():
                    "tile_qubits": args.tile or None, "f64_registers": bool(args.f64_regs),
                    "exact_products": bool(args.exact_products),
                    "block_columns": st.get("block_columns")},
-        "plain_fp64": plain, "precision_errors": precision, "c64_exact_fp64_products": exact,
+        "plain_fp64": plain, "precision_errors": precision, "oracle_pinned_errors": oracle_errors,
+        "c64_fp32_product_shares": shares,
         "step_with_G_output_s": t_with_G, "gate_apply": gate, "roofline": roof, "cpu_baseline": cpu,
         "metric_variants": variants, "extended_gates": gateset,
         "breakdown_ms": {k: st[k] / args.steps for k in ("metric_ms", "grad_ms", "solve_ms")},

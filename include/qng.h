@@ -74,11 +74,12 @@ typedef enum {
 } qng_gate_kind;
 
 /* Storage precision of the state vectors.  QNG_C64 keeps states and gate
- * matrices in complex64 (rounded from FP64) while the inner products are
- * accumulated in FP64 and the assembly of G and the solve stay in FP64.  In the
- * fused passes each thread forms its share of an inner product (at most 16
- * amplitudes) in the register precision before the FP64 sums; with
- * QNG_OPT_EXACT_PRODUCTS = 1 every product is formed in FP64 as well. */
+ * matrices in complex64 (rounded from FP64) while every product of an inner
+ * product is formed from the stored FP32 values in FP64 and accumulated in
+ * FP64, and the assembly of G and the solve stay in FP64.  With
+ * QNG_OPT_EXACT_PRODUCTS = 0 the fused passes form each thread's share of an
+ * inner product (at most 16 amplitudes) in FP32 instead, before the FP64 sums
+ * (faster, a narrower arithmetic). */
 typedef enum { QNG_C128 = 0, QNG_C64 = 1 } qng_precision;
 
 /* One gate.  Rotations (RX/RY/RZ): q0 = target, q1 = -1, param = its parameter
@@ -142,10 +143,10 @@ typedef enum {
     QNG_OPT_METRIC_KIND = 10,    /* 0 (default): G = L - T^* T; 1: L alone, L_ij = <d_i psi, d_j psi> (the
                                     coefficient matrix of imaginary-time evolution when psi's global phase does
                                     not depend on theta); T is still returned.  Metric and step entry points. */
-    QNG_OPT_EXACT_PRODUCTS = 11  /* complex64 with FP32 registers: 0 (default) = each thread forms its share of
-                                    an inner product (16 or fewer amplitudes) in FP32 and converts it to FP64, all
-                                    further sums FP64; 1 = every product formed and accumulated in FP64 (exact
-                                    products of the stored FP32 values; slower) */
+    QNG_OPT_EXACT_PRODUCTS = 11  /* complex64 with FP32 registers: 1 (default) = every product formed and
+                                    accumulated in FP64 (exact products of the stored FP32 values); 0 = each
+                                    thread forms its share of an inner product (16 or fewer amplitudes) in FP32
+                                    and converts it to FP64, all further sums FP64 (faster, narrower) */
 } qng_option;
 
 /* Counters of the last metric/energy/step call on a context. */
@@ -303,6 +304,39 @@ qng_status qng_energy_dev(qng_ctx *ctx, const qng_circuit *circ, const void *in_
 qng_status qng_energy_grad_from_state_dev(qng_ctx *ctx, const qng_circuit *circ,
                                           const qng_pauli_sum *ham, const double *theta,
                                           qng_precision prec, const void *psi_dev, void *grad_dev);
+
+/* Energy E = Re <psi|H|psi> and its gradient dE/dtheta (Sec. 1 definitions)
+ * with device outputs: the arguments of qng_energy_grad, in_state_dev a
+ * complex128 device state (NULL: |0...0>), E_dev one double and grad_dev P
+ * doubles (parameter order) in device memory.  O(P) gates by the reverse
+ * sweep; asynchronous on the context's stream. */
+qng_status qng_energy_grad_dev(qng_ctx *ctx, const qng_circuit *circ, const void *in_state_dev,
+                               const qng_pauli_sum *ham, const double *theta, qng_precision prec, void *E_dev,
+                               void *grad_dev);
+
+/* One natural-gradient step (Sec. 1: (Re G + eps I) dtheta = -dt grad E) with
+ * device outputs: the arguments of qng_step, in_state_dev a complex128 device
+ * state (NULL: |0...0>), dtheta_dev P doubles, G_dev 2*P*P doubles (NULL = not
+ * returned; then the metric's inner products keep their real parts, as in
+ * qng_step), grad_dev P doubles (nullable), E_dev one double (nullable), all
+ * in device memory.  The shifted system is solved on the device (FP64
+ * Cholesky), so nothing leaves the device.  status_dev (nullable) receives the
+ * solve's status as one int32 in device memory: QNG_OK, or QNG_E_NOT_SPD when
+ * Re G + eps I is not positive definite -- then none of the outputs is
+ * written.  With status_dev the call is asynchronous on the context's stream
+ * and returns QNG_OK once the work is enqueued; with status_dev = NULL it
+ * waits for its stream and returns QNG_E_NOT_SPD itself in that case. */
+qng_status qng_step_dev(qng_ctx *ctx, const qng_circuit *circ, const void *in_state_dev,
+                        const qng_pauli_sum *ham, const double *theta, double dt, double tikhonov,
+                        qng_precision prec, void *dtheta_dev, void *G_dev, void *grad_dev, void *E_dev,
+                        int32_t *status_dev);
+
+/* The clone primitive of the paper (appendix introduction: clone a state,
+ * apply a gate, take an inner product): dst_dev <- src_dev, 2^n_qubits
+ * amplitudes of the storage type of prec (complex128 or complex64), distinct
+ * device buffers.  Asynchronous on the context's stream; no workspace. */
+qng_status qng_clone_state_dev(qng_ctx *ctx, int32_t n_qubits, qng_precision prec, const void *src_dev,
+                               void *dst_dev);
 
 /* Apply the ansatz (every gate, in order) to a device state in place:
  * state_dev <- U(theta) state_dev (Sec. 2, psi = U|in>).  The state has the

@@ -103,6 +103,9 @@ def _load():
         "qng_energy_dev": [vp, vp, vp, vp, vp, ctypes.c_int, vp, vp],
         "qng_energy_grad_from_state_dev": [vp, vp, vp, vp, ctypes.c_int, vp, vp],
         "qng_apply_circuit_dev": [vp, vp, vp, ctypes.c_int, vp],
+        "qng_energy_grad_dev": [vp, vp, vp, vp, vp, ctypes.c_int, vp, vp],
+        "qng_step_dev": [vp, vp, vp, vp, vp, dbl, dbl, ctypes.c_int, vp, vp, vp, vp, vp],
+        "qng_clone_state_dev": [vp, i32, ctypes.c_int, vp, vp],
         "qng_plan_export": [vp, ctypes.c_int, ctypes.c_int, i32, vp, ctypes.c_int64, vp],
     }
     for name, args in sigs.items():
@@ -121,7 +124,8 @@ EXPORTED = ("qng_create", "qng_destroy", "qng_last_error", "qng_set_stream", "qn
             "qng_set_metric_blocks",
             "qng_get_stats", "qng_synchronize", "qng_validate", "qng_plan", "qng_solve_shifted", "qng_metric",
             "qng_energy_grad", "qng_step", "qng_step_batched", "qng_metric_dev", "qng_energy_dev",
-            "qng_energy_grad_from_state_dev", "qng_apply_circuit_dev", "qng_plan_export")
+            "qng_energy_grad_from_state_dev", "qng_apply_circuit_dev", "qng_plan_export", "qng_energy_grad_dev",
+            "qng_step_dev", "qng_clone_state_dev")
 
 
 def lib():
@@ -344,6 +348,23 @@ class Context:
         th = _theta(theta)
         self._c(_lib.qng_apply_circuit_dev(self._h, circ.cref, _ptr(th) if th.size else None, _prec(prec),
                                            state_dev_ptr))
+
+    def energy_grad_dev(self, circ: Circuit, theta, E_dev_ptr: int, grad_dev_ptr: int,
+                        in_state_dev_ptr: Optional[int] = None, prec="c128"):
+        th = _theta(theta)
+        self._c(_lib.qng_energy_grad_dev(self._h, circ.cref, in_state_dev_ptr, circ.href, _ptr(th), _prec(prec),
+                                         E_dev_ptr, grad_dev_ptr))
+
+    def step_dev(self, circ: Circuit, theta, dt: float, tikhonov: float, dtheta_dev_ptr: int,
+                 G_dev_ptr: Optional[int] = None, grad_dev_ptr: Optional[int] = None, E_dev_ptr: Optional[int] = None,
+                 status_dev_ptr: Optional[int] = None, in_state_dev_ptr: Optional[int] = None, prec="c128"):
+        th = _theta(theta)
+        self._c(_lib.qng_step_dev(self._h, circ.cref, in_state_dev_ptr, circ.href, _ptr(th), float(dt),
+                                  float(tikhonov), _prec(prec), dtheta_dev_ptr, G_dev_ptr, grad_dev_ptr, E_dev_ptr,
+                                  status_dev_ptr))
+
+    def clone_state_dev(self, n_qubits: int, src_dev_ptr: int, dst_dev_ptr: int, prec="c128"):
+        self._c(_lib.qng_clone_state_dev(self._h, int(n_qubits), _prec(prec), src_dev_ptr, dst_dev_ptr))
 
     def energy_grad_from_state_dev(self, circ: Circuit, theta, psi_dev_ptr: int, grad_dev_ptr: int, prec="c128"):
         th = _theta(theta)

@@ -38,6 +38,7 @@
 #include "circuit.hpp"
 #include "fused.hpp"
 #include "kernels.hpp"
+#include "solve_kernels.hpp"
 #include "sweep.hpp"
 
 namespace qng {
@@ -64,7 +65,7 @@ struct qng_ctx {
     bool own_stream = false;
     size_t mem_limit = 0;
     int opt_fusion = 1, opt_tile = 0, opt_streams = 0, opt_profile = 0, opt_small = 1, opt_f64_regs = 0;
-    int opt_exact_products = 0;
+    int opt_exact_products = 1;   // complex64: every inner-product term in FP64 (0: FP32 thread shares)
     int opt_graph = 1, opt_autotune = 0, opt_batch_tiles = 0, opt_block = 0, opt_metric_kind = 0;
     std::vector<int> metric_blocks;   // block id per parameter (block-diagonal metric); empty = full
     std::string last_error;
@@ -146,11 +147,12 @@ struct Layout {
     size_t partials = 0;    // reduction scratch
     size_t lraw = 0, traw = 0, graw = 0, eraw = 0, gout = 0, tout = 0, param_of = 0;
     size_t sweep = 0, sweep_bytes = 0;  // fused-sweep descriptors and partial sums
+    size_t solve = 0;       // device solve of the step: A (NP*NP), y, x, grad (NP each), status
     size_t total = 0;
 };
 
 Layout plan_layout(int n, int P, size_t param_map_ints, size_t amp_bytes, int n_states, bool staging,
-                   size_t sweep_bytes) {
+                   size_t sweep_bytes, int solve_params = -1) {
     Layout L;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
@@ -168,6 +170,7 @@ Layout plan_layout(int n, int P, size_t param_map_ints, size_t amp_bytes, int n_
     L.param_of = take(param_map_ints * 4 + 4);
     L.sweep_bytes = sweep_bytes;
     L.sweep = take(sweep_bytes + 16);
+    if (solve_params >= 0) L.solve = take(((size_t)solve_params * solve_params + 3 * (size_t)solve_params) * 8 + 16);
     L.total = off;
     return L;
 }
@@ -550,6 +553,7 @@ struct CallSpec {
     bool host_call = false;               // synchronous host-pointer entry point: time each phase
     const void *psi_final_dev = nullptr;  // gradient from a given final state (nullable)
     bool real_products = false;           // fused metric: real parts of L only (the caller needs Re G)
+    bool device_solve = false;            // reserve the workspace of the step's device solve
 };
 
 // Columns per lambda sweep of the fused metric.  Blocks of two columns need
@@ -589,6 +593,7 @@ struct CallResult {
     // device pointers into the workspace
     double *G = nullptr, *T = nullptr, *graw = nullptr, *eraw = nullptr;
     const int *param_of = nullptr;
+    char *solve = nullptr;                // CallSpec::device_solve: the solve's workspace
 };
 
 template <typename R>
@@ -639,7 +644,8 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
         if (step_width < 2) step_width = 0;     // the one-column loop needs 3 registers
         n_states = std::max(n_states, 2 + step_width);
     }
-    Layout L = plan_layout(n, c.P, param_map_ints(c), amp, n_states, spec.in_host != nullptr, scratch);
+    Layout L = plan_layout(n, c.P, param_map_ints(c), amp, n_states, spec.in_host != nullptr, scratch,
+                           spec.device_solve ? c.NP : -1);
     char *base = ensure_workspace(ctx, L.total);
     hipStream_t st = ctx->stream;
     char *sb = base + L.states;
@@ -666,6 +672,7 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
     res.graw = e.graw();
     res.param_of = (const int *)(base + L.param_of);
     res.eraw = e.eraw();
+    if (spec.device_solve) res.solve = base + L.solve;
     int pos = 0;
     if (spec.metric) {
         auto t0 = Clock::now();
@@ -737,6 +744,16 @@ template <typename F> void dispatch(qng_precision prec, F &&f) {
 void host_unpack_grad(const std::vector<double> &graw, const Problem &pb, double *grad) {
     for (int a = 0; a < pb.circ.NP; ++a) grad[a] = 0.0;
     for (size_t r = 0; r < pb.param_of.size(); ++r) grad[pb.param_of[r]] -= graw[2 * r + 1];
+}
+
+// The gradient in parameter order on the device, from the raw per-rotation
+// products of a run: -Im graw[r] into its parameter (summed over the rotations
+// of a shared parameter).
+void device_grad(const CallResult &r, const Problem &pb, double *grad, hipStream_t st) {
+    const int P = pb.circ.P;
+    if (!P) return;
+    if (!pb.circ.shared) launch_grad_from_raw(r.graw, r.param_of, P, grad, st);
+    else launch_grad_contract(r.graw, r.param_of + P, r.param_of + P + pb.circ.NP + 1, pb.circ.NP, grad, st);
 }
 
 // ------------------------------------------------------------ batched metric
@@ -930,7 +947,23 @@ BatchRun batch_metric(qng_ctx *ctx, const std::vector<Problem> &pbs, const doubl
         ctx->stats.elements += S.elements;
         run.launches += (int64_t)S.launches.size();
         const bool graph = allow_graph && !profile && st != nullptr;
-        std::vector<uint64_t> ptrs = {(uint64_t)(uintptr_t)base, (uint64_t)L.total};
+        // every device address the captured launches hold: the workspace, the
+        // class's buffers and each member's registers and T (members move when
+        // a batch lists its ansaetze in another order)
+        std::vector<uint64_t> ptrs = {(uint64_t)(uintptr_t)base,
+                                      (uint64_t)L.total,
+                                      (uint64_t)(uintptr_t)d.images,
+                                      (uint64_t)(uintptr_t)d.arena,
+                                      (uint64_t)(uintptr_t)d.fwd_mats,
+                                      (uint64_t)(uintptr_t)d.adj_mats,
+                                      (uint64_t)(uintptr_t)d.adj_mats32,
+                                      (uint64_t)(uintptr_t)d.partials,
+                                      (uint64_t)(uintptr_t)d.lraw,
+                                      (uint64_t)(uintptr_t)d.reduce_partials};
+        for (size_t i = 0; i < mem.size(); ++i) {
+            ptrs.push_back((uint64_t)(uintptr_t)d.psi[i]);
+            ptrs.push_back((uint64_t)(uintptr_t)d.traw[i]);
+        }
         if (graph) {
             if (!bc.graph || bc.graph_ptrs != ptrs) {
                 if (bc.graph) {
@@ -1473,20 +1506,31 @@ qng_status qng_step_batched(qng_ctx *ctx, int32_t B, const qng_circuit *circs, c
             ctx->stats.grad_ms = ms_since(t0);
         });
         auto t0 = Clock::now();
+        // every member is solved before any output is written, so a member
+        // whose shifted metric is not positive definite leaves all outputs
+        // untouched
+        std::vector<std::vector<double>> grads(B), xs(B);
         for (int b = 0; b < B; ++b) {
             const int NP = pbs[b].circ.NP;
-            std::vector<double> grad(NP + 1), rhs(NP + 1), x(NP + 1);
-            host_unpack_grad(graw[b], pbs[b], grad.data());
-            for (int i = 0; i < NP; ++i) rhs[i] = -dt * grad[i];
+            std::vector<double> rhs(NP + 1);
+            grads[b].assign(NP + 1, 0.0);
+            xs[b].assign(NP + 1, 0.0);
+            host_unpack_grad(graw[b], pbs[b], grads[b].data());
+            for (int i = 0; i < NP; ++i) rhs[i] = -dt * grads[b][i];
             if (NP) {
                 try {
-                    qng::solve_shifted(NP, G[b].data(), tikhonov, rhs.data(), x.data());
+                    qng::solve_shifted(NP, G[b].data(), tikhonov, rhs.data(), xs[b].data());
                 } catch (const Error &e) {
                     fail(e.status, "ansatz " + std::to_string(b) + ": " + e.msg);
                 }
-                std::memcpy(dtheta_out[b], x.data(), (size_t)NP * 8);
+            }
+        }
+        for (int b = 0; b < B; ++b) {
+            const int NP = pbs[b].circ.NP;
+            if (NP) {
+                std::memcpy(dtheta_out[b], xs[b].data(), (size_t)NP * 8);
                 if (G_out && G_out[b]) std::memcpy(G_out[b], G[b].data(), (size_t)NP * NP * 16);
-                if (grad_out && grad_out[b]) std::memcpy(grad_out[b], grad.data(), (size_t)NP * 8);
+                if (grad_out && grad_out[b]) std::memcpy(grad_out[b], grads[b].data(), (size_t)NP * 8);
             }
             if (E_out) E_out[b] = E[2 * b];
         }
@@ -1561,10 +1605,101 @@ qng_status qng_energy_grad_from_state_dev(qng_ctx *ctx, const qng_circuit *circ,
             spec.grad = true;
             spec.psi_final_dev = psi_dev;
             CallResult r = run<R>(ctx, pb, spec);
-            if (P && !pb.circ.shared) launch_grad_from_raw(r.graw, r.param_of, P, (double *)grad_dev, ctx->stream);
-            if (P && pb.circ.shared)
-                launch_grad_contract(r.graw, r.param_of + P, r.param_of + P + pb.circ.NP + 1, pb.circ.NP,
-                                     (double *)grad_dev, ctx->stream);
+            (void)P;
+            device_grad(r, pb, (double *)grad_dev, ctx->stream);
+        });
+    });
+}
+
+qng_status qng_energy_grad_dev(qng_ctx *ctx, const qng_circuit *circ, const void *in_state_dev,
+                               const qng_pauli_sum *ham, const double *theta, qng_precision prec, void *E_dev,
+                               void *grad_dev) {
+    return guarded(ctx, [&] {
+        require_ctx(ctx);
+        check_prec(prec);
+        validate_circuit(circ, max_qubits(prec));
+        validate_theta(circ, theta);
+        validate_hamiltonian(circ, ham);
+        if (!E_dev || (circ->n_params > 0 && !grad_dev)) fail(QNG_E_INVALID_ARG, "output is NULL");
+        reset_stats(ctx);
+        Problem pb = make_problem(circ, theta, ham);
+        dispatch(prec, [&](auto tag) {
+            using R = decltype(tag);
+            CallSpec spec;
+            spec.grad = true;
+            spec.in_dev = in_state_dev;
+            CallResult r = run<R>(ctx, pb, spec);
+            HIPCHECK(hipMemcpyAsync(E_dev, r.eraw, 8, hipMemcpyDeviceToDevice, ctx->stream));
+            device_grad(r, pb, (double *)grad_dev, ctx->stream);
+        });
+    });
+}
+
+qng_status qng_step_dev(qng_ctx *ctx, const qng_circuit *circ, const void *in_state_dev, const qng_pauli_sum *ham,
+                        const double *theta, double dt, double tikhonov, qng_precision prec, void *dtheta_dev,
+                        void *G_dev, void *grad_dev, void *E_dev, int32_t *status_dev) {
+    return guarded(ctx, [&] {
+        require_ctx(ctx);
+        check_prec(prec);
+        validate_circuit(circ, max_qubits(prec));
+        validate_theta(circ, theta);
+        validate_hamiltonian(circ, ham);
+        validate_scalar(dt, "dt");
+        validate_scalar(tikhonov, "tikhonov");
+        if (tikhonov < 0) fail(QNG_E_INVALID_ARG, "tikhonov < 0");
+        if (circ->n_params > 0 && !dtheta_dev) fail(QNG_E_INVALID_ARG, "dtheta_dev is NULL");
+        reset_stats(ctx);
+        Problem pb = make_problem(circ, theta, ham);
+        apply_metric_settings(ctx, pb);
+        const int NP = pb.circ.NP;
+        hipStream_t st = ctx->stream;
+        int32_t solve_status = 0;
+        dispatch(prec, [&](auto tag) {
+            using R = decltype(tag);
+            CallSpec spec;
+            spec.metric = true;
+            spec.grad = true;
+            spec.in_dev = in_state_dev;
+            spec.device_solve = true;
+            // the solve reads Re G only: without a G output the metric's inner
+            // products keep their real parts
+            spec.real_products = G_dev == nullptr;
+            CallResult r = run<R>(ctx, pb, spec);
+            // solve workspace: A (NP*NP), y, x, grad (NP each), status
+            double *A = (double *)r.solve;
+            double *y = A + (size_t)NP * NP, *x = y + NP, *grad = x + NP;
+            int32_t *status = (int32_t *)(grad + NP);
+            device_grad(r, pb, grad, st);
+            if (NP) launch_shifted_solve(r.G, NP, tikhonov, grad, dt, A, y, x, status, st);
+            else HIPCHECK(hipMemsetAsync(status, 0, sizeof(int32_t), st));
+            // every output follows the solve's status: nothing is written when
+            // Re G + eps I is not positive definite
+            launch_copy_if_ok(status, x, (double *)dtheta_dev, NP, st);
+            if (G_dev) launch_copy_if_ok(status, r.G, (double *)G_dev, 2 * (int64_t)NP * NP, st);
+            if (grad_dev) launch_copy_if_ok(status, grad, (double *)grad_dev, NP, st);
+            if (E_dev) launch_copy_if_ok(status, r.eraw, (double *)E_dev, 1, st);
+            if (status_dev) {
+                HIPCHECK(hipMemcpyAsync(status_dev, status, sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+            } else {
+                HIPCHECK(hipMemcpyAsync(&solve_status, status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+                HIPCHECK(hipStreamSynchronize(st));
+            }
+        });
+        if (!status_dev && solve_status != 0)
+            fail(QNG_E_NOT_SPD, "Re G + eps I is not positive definite (device solve); no output was written");
+    });
+}
+
+qng_status qng_clone_state_dev(qng_ctx *ctx, int32_t n_qubits, qng_precision prec, const void *src_dev,
+                               void *dst_dev) {
+    return guarded(ctx, [&] {
+        require_ctx(ctx);
+        check_prec(prec);
+        if (n_qubits < 0 || n_qubits > max_qubits(prec)) fail(QNG_E_INVALID_ARG, "n_qubits out of range");
+        if (!src_dev || !dst_dev) fail(QNG_E_INVALID_ARG, "state pointer is NULL");
+        dispatch(prec, [&](auto tag) {
+            using R = decltype(tag);
+            launch_copy<R>(src_dev, dst_dev, n_qubits, ctx->stream);
         });
     });
 }

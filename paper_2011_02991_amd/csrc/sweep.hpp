@@ -284,7 +284,8 @@ enum RegMode : int { REG_F32 = 0, REG_F64 = 1, REG_F32_EXACT = 2 };
 // in FP64 and FP32; the kernel reads the table of its register precision.
 // width: phi registers per item (the plan's column-block width).
 // real_products: keep only the real parts of the metric's inner products
-// (sweep_kernels_real.hip; the step needs Re G alone); not with REG_F32_EXACT.
+// (sweep_kernels_real.hip, or sweep_kernels_real_exact.hip for REG_F32_EXACT;
+// the step needs Re G alone).
 template <typename R>
 void launch_sweep_pass(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
                        const DevOp *ops, const DevMap *maps, const double *mats64, const float *mats32,
@@ -299,6 +300,11 @@ void launch_sweep_pass_real(const LaunchItem *items, int n_items, uint32_t total
 void launch_sweep_pass_exact(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
                              const DevOp *ops, const DevMap *maps, const float *mats32, double *partials, int m,
                              int rb, int width, hipStream_t st);
+// The REG_F32_EXACT kernels with the real parts of the metric's inner products
+// only (sweep_kernels_real_exact.hip).
+void launch_sweep_pass_real_exact(const LaunchItem *items, int n_items, uint32_t total_tiles,
+                                  const DevPass *passes, const DevOp *ops, const DevMap *maps, const float *mats32,
+                                  double *partials, int m, int rb, int width, hipStream_t st);
 void launch_reduce_tasks(const ReduceTask *tasks, int n_tasks, const double *partials, double *results,
                          hipStream_t st);
 

@@ -50,13 +50,32 @@ template <> struct Amp<float>  { using T = float2; };
 
 constexpr int kRows = kThreads / 16;   // DPP rows of 16 lanes per work-group
 
+// v + (v of lane l ^ 16) in every lane, by v_permlane16_swap (gfx950: odd rows
+// of the first operand trade places with even rows of the second).  With both
+// operands holding v, the two results hold v of rows (0, 0, 2, 2) and of rows
+// (1, 1, 3, 3), so their sum is the pair sum; the same with v_permlane32_swap
+// (upper half against lower half) gives lane l ^ 32.  Both are VALU moves, so
+// the sum needs no LDS round trip.
+template <bool HALVES>
+__device__ __forceinline__ double pair_sum(double v) {
+    const uint32_t lo = __double2loint(v), hi = __double2hiint(v);
+    if constexpr (HALVES) {
+        const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
+    } else {
+        const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
+    }
+}
+
 // Sum of a value over the four 16-lane rows of the wavefront (lane l with
-// l ^ 16, then l ^ 32): lane l of row 0 then holds the sum of lane l of every
-// row, added in the same order on every row.
+// l ^ 16, then l ^ 32): every lane l then holds the sum of lane l mod 16 of
+// every row, added in the same order on every lane.
 __device__ __forceinline__ double across_rows(double v) {
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
-    return v;
+    v = pair_sum<false>(v);
+    return pair_sum<true>(v);
 }
 
 // Row reduction with DPP: after row_shr by 1, 2, 4 and 8 (zero shifted in at
@@ -1334,7 +1353,16 @@ void launch_ct(const LaunchItem *items, int n_items, uint32_t total_tiles, const
 
 }  // namespace
 
-#if QNG_REAL_PRODUCTS
+#if QNG_REAL_PRODUCTS && QNG_EXACT_PRODUCTS
+void launch_sweep_pass_real_exact(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
+                                  const DevOp *ops, const DevMap *maps, const float *mats32, double *partials, int m,
+                                  int rb, int width, hipStream_t st) {
+    if (n_items <= 0 || total_tiles == 0) return;
+    launch_ct<float, float>(items, n_items, total_tiles, passes, ops, maps, mats32, partials, m, rb, width, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw e;
+}
+#elif QNG_REAL_PRODUCTS
 template <typename R>
 void launch_sweep_pass_real(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
                             const DevOp *ops, const DevMap *maps, const double *mats64, const float *mats32,
@@ -1366,9 +1394,13 @@ void launch_sweep_pass(const LaunchItem *items, int n_items, uint32_t total_tile
                        const DevOp *ops, const DevMap *maps, const double *mats64, const float *mats32,
                        double *partials, int m, int rb, int reg_mode, int width, hipStream_t st, bool real_products) {
     if (n_items <= 0 || total_tiles == 0) return;
-    if (real_products && reg_mode != REG_F32_EXACT) {
-        launch_sweep_pass_real<R>(items, n_items, total_tiles, passes, ops, maps, mats64, mats32, partials, m, rb,
-                                  reg_mode, width, st);
+    if (real_products) {
+        if (reg_mode == REG_F32_EXACT)
+            launch_sweep_pass_real_exact(items, n_items, total_tiles, passes, ops, maps, mats32, partials, m, rb,
+                                         width, st);
+        else
+            launch_sweep_pass_real<R>(items, n_items, total_tiles, passes, ops, maps, mats64, mats32, partials, m,
+                                      rb, reg_mode, width, st);
         return;
     }
     if constexpr (sizeof(R) == 8) {

@@ -4,9 +4,10 @@ Two modes:
 
   python profile_sweep.py run [--config 3] [--prec c64]
       One natural-gradient step of a workload without the G output (the passes
-      bench.py times), preceded by one plain device copy of 512 MiB (the
-      calibration kernel for FETCH_SIZE / WRITE_SIZE).  Meant to run under
-      rocprofv3 --pmc, one counter group per run.
+      bench.py times), preceded by one clone of a 512 MiB state with the
+      library's own copy kernel (the calibration kernel for FETCH_SIZE /
+      WRITE_SIZE).  Meant to run under rocprofv3 --pmc, one counter group per
+      run.
 
   python profile_sweep.py summarize --kind {stats,traffic,counters} --out FILE DB...
       Summarise rocprofv3 databases into short text under profiles/:
@@ -37,20 +38,23 @@ def run(args):
     import torch
     import paper_2011_02991_amd as qng
     import workloads as W
-    dst = torch.empty(COPY_BYTES // 8, dtype=torch.complex64, device="cuda")
-    src = torch.empty_like(dst)
+    ctx = qng.Context(0)
+    src = torch.zeros(COPY_BYTES // 8, dtype=torch.complex64, device="cuda")
+    dst = torch.empty_like(src)
     torch.cuda.synchronize()
-    dst.copy_(src)
-    torch.cuda.synchronize()
+    n_copy = (COPY_BYTES // 8).bit_length() - 1
+    ctx.clone_state_dev(n_copy, src.data_ptr(), dst.data_ptr(), prec="c64")
+    ctx.synchronize()
     del dst, src
     pr = W.CONFIGS[args.config]() if args.layers <= 0 else W.scaled(W.CONFIGS[args.config], 26, args.layers)
-    print(f"profiling a step of {pr.name} ({args.prec})", flush=True)
-    ctx = qng.Context(0)
+    print(f"profiling a step of {pr.name} ({args.prec}, exact products {args.exact_products})", flush=True)
     ctx.set_option(qng.OPT_TILE_QUBITS, args.tile)
     ctx.set_option(qng.OPT_F64_REGISTERS, args.f64_regs)
+    ctx.set_option(qng.OPT_EXACT_PRODUCTS, args.exact_products)
     ctx.step(qng.Circuit.from_problem(pr), pr.theta, pr.dt, pr.tikhonov, prec=args.prec, want_G=False)
     torch.cuda.synchronize()
     print(json.dumps({"workload": pr.name, "prec": args.prec, **ctx.stats()}), flush=True)
+    ctx.close()
 
 
 def _short(name: str) -> str:
@@ -69,7 +73,7 @@ def _pmc(dbs):
     """Counter sums per kernel family, plus the calibration copy on its own.
 
     The calibration copy is the first dispatch of each profiled process (the
-    512 MiB device copy that run() issues before the step).  Only that one
+    512 MiB state clone that run() issues before the step).  Only that one
     dispatch calibrates: the step itself launches copies of the same size
     (a state clone is a 512 MiB copy at n=26), which must not be summed in.
     """
@@ -143,6 +147,7 @@ def main():
     r.add_argument("--prec", default="c64")
     r.add_argument("--tile", type=int, default=0)
     r.add_argument("--f64-regs", type=int, default=0)
+    r.add_argument("--exact-products", type=int, default=1)
     r.add_argument("--layers", type=int, default=0, help="layers of a 26-qubit instance (0 = the full workload)")
     s = sub.add_parser("summarize")
     s.add_argument("--kind", choices=["stats", "traffic", "counters"], required=True)

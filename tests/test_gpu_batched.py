@@ -5,8 +5,9 @@ metric phase captured into a hipGraph and replayed, and the autotuner.
 Every member is compared with the oracle (complex128: 1e-10 normwise, as in
 the single-ansatz tests).  For the 64-ansatz workload (n in [12, 22], 2..8
 layers of RY, RZ + CNOT chain, 30-term Hamiltonians) each member is compared
-with the single-ansatz entry point on every entry and with the oracle on
-sampled parameters (first, last, one in the middle).
+with the single-ansatz entry point on every entry, with the full oracle when
+n <= 16 and with the oracle on sampled parameters (first, last, one in the
+middle) above that.
 """
 import sys
 
@@ -108,6 +109,28 @@ def test_graph_replays_match_eager(env):
             check_member(got[b], oracle.step(at), at, TOL, f"replay {rep} member {b}")
 
 
+def test_graph_replay_with_reordered_members(env):
+    """The same ansaetze in another order move every member's registers in the
+    workspace while each register class keeps its structure key: the captured
+    graph of a class must not be replayed with the old member addresses.  The
+    batch (members of three register classes) is run in one order and then
+    reversed, both through the graph, and every member is checked against an
+    eager run of the same order and the oracle."""
+    q, ctx = env
+    base = [W.scaled(W.config1, 9, 2, seed=7101), W.scaled(W.config3, 12, 2, seed=7102),
+            W.scaled(W.config2, 13, 1, seed=7103), W.scaled(W.config5, 10, 1, seed=7104)]
+    ctx.set_option(q.OPT_GRAPH, 1)
+    for order in (base, base[::-1], base, base[::-1]):
+        say(f"case: reordered batch {[p.n_qubits for p in order]}")
+        got = run_batch(q, ctx, order)
+        ctx.set_option(q.OPT_GRAPH, 0)
+        eager = run_batch(q, ctx, order)
+        ctx.set_option(q.OPT_GRAPH, 1)
+        for b, p in enumerate(order):
+            assert np.array_equal(got[b]["G"], eager[b]["G"]) and np.array_equal(got[b]["grad"], eager[b]["grad"])
+            check_member(got[b], oracle.step(p), p, TOL, f"order {[x.n_qubits for x in order]} member {b}")
+
+
 def test_autotuner(env):
     q, ctx = env
     probs = mixed_batch()[:3]
@@ -160,8 +183,12 @@ def test_64_ansatz_workload(env):
         assert abs(res2[b]["E"] - single[b]["E"]) <= 1e-12 * max(1.0, abs(single[b]["E"]))
         assert np.array_equal(res[b]["G"], res2[b]["G"])
     say(f"batched vs single: worst {worst:.2e}")
-    say("oracle on sampled parameters of every member")
+    say("oracle on every parameter of the members with n <= 16, on sampled parameters of the others")
     for b, p in enumerate(probs):
+        if p.n_qubits <= 16:
+            want = oracle.step(p)
+            check_member(res2[b], want, p, TOL, f"member {b} (n={p.n_qubits}, P={p.n_params}, full oracle)")
+            continue
         sel = np.array([0, p.n_params // 2, p.n_params - 1])
         D, psi = oracle.derivative_states(p, sel)
         Go, To, _ = oracle.metric_from_states(D, psi)
@@ -194,3 +221,35 @@ def test_batch_without_G_outputs(env):
             assert ed <= 1e-13, (rep, b, ed)
             assert np.array_equal(real[b]["grad"], full[b]["grad"]) and real[b]["E"] == full[b]["E"]
     say(f"replays {ctx.stats()['graph_replays']}")
+
+
+def test_small_register_batch_pays(env):
+    """Batches of small registers (n <= 16), where one ansatz alone cannot fill
+    the GPU: 48 ansaetze of n in [8, 16], 2..6 layers, batched (graph replay)
+    against one qng_step per ansatz; every member against the oracle."""
+    import time
+    q, ctx = env
+    rng = np.random.default_rng(7201)
+    probs = [W.make_problem(f"small{b}", int(rng.integers(8, 17)), int(rng.integers(2, 7)), (W.RY, W.RZ),
+                            "cnot_chain", 12, 7300 + b) for b in range(48)]
+    circs = [q.Circuit.from_problem(p) for p in probs]
+    ths = [p.theta for p in probs]
+    ctx.set_option(q.OPT_GRAPH, 1)
+    run_batch(q, ctx, probs)                  # builds and captures
+    ctx.synchronize()
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        res = ctx.step_batched(circs, ths, probs[0].dt, probs[0].tikhonov, want_G=False)
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        single = [ctx.step(c, t, p.dt, p.tikhonov, want_G=False) for c, t, p in zip(circs, ths, probs)]
+    t2 = time.perf_counter()
+    say(f"48 small ansaetze: batched {(t1 - t0) / reps * 1e3:.1f} ms per step of all, "
+        f"one call per ansatz {(t2 - t1) / reps * 1e3:.1f} ms")
+    for b, p in enumerate(probs):
+        want = oracle.step(p)
+        kappa = np.linalg.cond(want["G"].real + p.tikhonov * np.eye(p.n_params))
+        assert rel_err(res[b]["grad"], want["grad"]) <= TOL
+        assert rel_err(res[b]["dtheta"], want["dtheta"]) <= max(TOL, kappa * 1e-14)
+        assert rel_err(res[b]["dtheta"], single[b]["dtheta"]) <= max(1e-12, kappa * 1e-14)
