@@ -314,6 +314,22 @@ qng_status qng_energy_grad_dev(qng_ctx *ctx, const qng_circuit *circ, const void
                                const qng_pauli_sum *ham, const double *theta, qng_precision prec, void *E_dev,
                                void *grad_dev);
 
+/* qng_energy_grad_dev for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same arguments and results, but the call allocates
+ * nothing.  Its whole workspace is a fixed device scratch of 64 MiB that the
+ * library holds on every GPU it runs on until the process ends (looked up by
+ * qng_create on that device); the context's own workspace is not used.
+ * Fits complex128 registers up to n = 20 and complex64 up to n = 21 (two
+ * registers plus the gradient's plan and partial sums); a call that needs
+ * more fails with QNG_E_OUT_OF_MEMORY before any device work.  All calls on
+ * one GPU share that scratch: calls that overlap on one GPU (two contexts,
+ * two streams, two threads) race and must be ordered by the caller.  Kept
+ * state: none -- every buffer is written before it is read in each call. */
+qng_status qng_energy_grad_dev_noalloc(qng_ctx *ctx, const qng_circuit *circ, const void *in_state_dev,
+                                       const qng_pauli_sum *ham, const double *theta, qng_precision prec,
+                                       void *E_dev, void *grad_dev);
+
 /* One natural-gradient step (Sec. 1: (Re G + eps I) dtheta = -dt grad E) with
  * device outputs: the arguments of qng_step, in_state_dev a complex128 device
  * state (NULL: |0...0>), dtheta_dev P doubles, G_dev 2*P*P doubles (NULL = not

@@ -106,6 +106,7 @@ def _load():
         "qng_energy_grad_dev": [vp, vp, vp, vp, vp, ctypes.c_int, vp, vp],
         "qng_step_dev": [vp, vp, vp, vp, vp, dbl, dbl, ctypes.c_int, vp, vp, vp, vp, vp],
         "qng_clone_state_dev": [vp, i32, ctypes.c_int, vp, vp],
+        "qng_energy_grad_dev_noalloc": [vp, vp, vp, vp, vp, ctypes.c_int, vp, vp],
         "qng_plan_export": [vp, ctypes.c_int, ctypes.c_int, i32, vp, ctypes.c_int64, vp],
     }
     for name, args in sigs.items():
@@ -125,7 +126,7 @@ EXPORTED = ("qng_create", "qng_destroy", "qng_last_error", "qng_set_stream", "qn
             "qng_get_stats", "qng_synchronize", "qng_validate", "qng_plan", "qng_solve_shifted", "qng_metric",
             "qng_energy_grad", "qng_step", "qng_step_batched", "qng_metric_dev", "qng_energy_dev",
             "qng_energy_grad_from_state_dev", "qng_apply_circuit_dev", "qng_plan_export", "qng_energy_grad_dev",
-            "qng_step_dev", "qng_clone_state_dev")
+            "qng_step_dev", "qng_clone_state_dev", "qng_energy_grad_dev_noalloc")
 
 
 def lib():
@@ -354,6 +355,12 @@ class Context:
         th = _theta(theta)
         self._c(_lib.qng_energy_grad_dev(self._h, circ.cref, in_state_dev_ptr, circ.href, _ptr(th), _prec(prec),
                                          E_dev_ptr, grad_dev_ptr))
+
+    def energy_grad_dev_noalloc(self, circ: Circuit, theta, E_dev_ptr: int, grad_dev_ptr: int,
+                                in_state_dev_ptr: Optional[int] = None, prec="c128"):
+        th = _theta(theta)
+        self._c(_lib.qng_energy_grad_dev_noalloc(self._h, circ.cref, in_state_dev_ptr, circ.href, _ptr(th),
+                                                 _prec(prec), E_dev_ptr, grad_dev_ptr))
 
     def step_dev(self, circ: Circuit, theta, dt: float, tikhonov: float, dtheta_dev_ptr: int,
                  G_dev_ptr: Optional[int] = None, grad_dev_ptr: Optional[int] = None, E_dev_ptr: Optional[int] = None,

@@ -38,6 +38,7 @@
 #include "circuit.hpp"
 #include "fused.hpp"
 #include "kernels.hpp"
+#include "noalloc.hpp"
 #include "solve_kernels.hpp"
 #include "sweep.hpp"
 
@@ -72,6 +73,10 @@ struct qng_ctx {
     qng_stats stats{};
     void *ws = nullptr;
     size_t ws_bytes = 0;
+    // while set (the entry point that allocates nothing): the workspace is this
+    // fixed device scratch instead of ws, and nothing is allocated
+    char *fixed_ws = nullptr;
+    size_t fixed_ws_bytes = 0;
     SweepCache sweep_cache;
     std::map<std::vector<int32_t>, std::shared_ptr<BatchClass>> batch_classes;
     std::map<std::vector<int32_t>, BatchTuning> tuned;
@@ -176,6 +181,13 @@ Layout plan_layout(int n, int P, size_t param_map_ints, size_t amp_bytes, int n_
 }
 
 char *ensure_workspace(qng_ctx *ctx, size_t bytes) {
+    if (ctx->fixed_ws) {
+        if (bytes > ctx->fixed_ws_bytes)
+            fail(QNG_E_OUT_OF_MEMORY, "this call needs " + std::to_string(bytes) +
+                                          " bytes of device scratch; the fixed scratch of the entry point that "
+                                          "allocates nothing holds " + std::to_string(ctx->fixed_ws_bytes));
+        return ctx->fixed_ws;
+    }
     if (ctx->mem_limit && bytes > ctx->mem_limit)
         fail(QNG_E_OUT_OF_MEMORY, "workspace of " + std::to_string(bytes) + " bytes exceeds the context limit of " +
                                       std::to_string(ctx->mem_limit));
@@ -608,7 +620,7 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
     const SweepPlan *plan = nullptr;
     FusedRun fr;
     size_t scratch = 0;
-    int n_states = 4;
+    int n_states = spec.metric ? 4 : 2;   // the gradient alone needs psi and lambda = H psi
     if (fused) {
         const bool f64_regs = amp == 16 || ctx->opt_f64_regs;
         const bool blocked = !pb.rot_block.empty();
@@ -754,6 +766,29 @@ void device_grad(const CallResult &r, const Problem &pb, double *grad, hipStream
     if (!P) return;
     if (!pb.circ.shared) launch_grad_from_raw(r.graw, r.param_of, P, grad, st);
     else launch_grad_contract(r.graw, r.param_of + P, r.param_of + P + pb.circ.NP + 1, pb.circ.NP, grad, st);
+}
+
+// qng_energy_grad_dev and its variant on the fixed scratch: E and grad E in
+// device memory, asynchronous on the context's stream.
+void energy_grad_dev_call(qng_ctx *ctx, const qng_circuit *circ, const void *in_state_dev, const qng_pauli_sum *ham,
+                          const double *theta, qng_precision prec, void *E_dev, void *grad_dev) {
+    require_ctx(ctx);
+    check_prec(prec);
+    validate_circuit(circ, max_qubits(prec));
+    validate_theta(circ, theta);
+    validate_hamiltonian(circ, ham);
+    if (!E_dev || (circ->n_params > 0 && !grad_dev)) fail(QNG_E_INVALID_ARG, "output is NULL");
+    reset_stats(ctx);
+    Problem pb = make_problem(circ, theta, ham);
+    dispatch(prec, [&](auto tag) {
+        using R = decltype(tag);
+        CallSpec spec;
+        spec.grad = true;
+        spec.in_dev = in_state_dev;
+        CallResult r = run<R>(ctx, pb, spec);
+        HIPCHECK(hipMemcpyAsync(E_dev, r.eraw, 8, hipMemcpyDeviceToDevice, ctx->stream));
+        device_grad(r, pb, (double *)grad_dev, ctx->stream);
+    });
 }
 
 // ------------------------------------------------------------ batched metric
@@ -1100,6 +1135,9 @@ qng_status qng_create(qng_ctx **out, int device, void *hip_stream) {
         }
         if (device < 0 || device >= count) fail(QNG_E_DEVICE, "device index out of range");
         HIPCHECK(hipSetDevice(device));
+        // device address of the fixed scratch of qng_energy_grad_dev_noalloc
+        // on this device (looked up once per device)
+        HIPCHECK(noalloc_scratch_init(device));
         std::unique_ptr<qng_ctx> c(new qng_ctx);
         c->device = device;
         if (hip_stream) c->stream = (hipStream_t)hip_stream;
@@ -1614,24 +1652,28 @@ qng_status qng_energy_grad_from_state_dev(qng_ctx *ctx, const qng_circuit *circ,
 qng_status qng_energy_grad_dev(qng_ctx *ctx, const qng_circuit *circ, const void *in_state_dev,
                                const qng_pauli_sum *ham, const double *theta, qng_precision prec, void *E_dev,
                                void *grad_dev) {
+    return guarded(ctx, [&] { energy_grad_dev_call(ctx, circ, in_state_dev, ham, theta, prec, E_dev, grad_dev); });
+}
+
+qng_status qng_energy_grad_dev_noalloc(qng_ctx *ctx, const qng_circuit *circ, const void *in_state_dev,
+                                       const qng_pauli_sum *ham, const double *theta, qng_precision prec,
+                                       void *E_dev, void *grad_dev) {
     return guarded(ctx, [&] {
         require_ctx(ctx);
-        check_prec(prec);
-        validate_circuit(circ, max_qubits(prec));
-        validate_theta(circ, theta);
-        validate_hamiltonian(circ, ham);
-        if (!E_dev || (circ->n_params > 0 && !grad_dev)) fail(QNG_E_INVALID_ARG, "output is NULL");
-        reset_stats(ctx);
-        Problem pb = make_problem(circ, theta, ham);
-        dispatch(prec, [&](auto tag) {
-            using R = decltype(tag);
-            CallSpec spec;
-            spec.grad = true;
-            spec.in_dev = in_state_dev;
-            CallResult r = run<R>(ctx, pb, spec);
-            HIPCHECK(hipMemcpyAsync(E_dev, r.eraw, 8, hipMemcpyDeviceToDevice, ctx->stream));
-            device_grad(r, pb, (double *)grad_dev, ctx->stream);
-        });
+        char *fixed = (char *)noalloc_scratch(ctx->device);
+        if (!fixed) fail(QNG_E_DEVICE, "the fixed scratch of this device was not looked up (qng_create)");
+        // the context's own workspace is left alone; every buffer of this call
+        // is carved from the fixed scratch
+        struct Use {
+            qng_ctx *c;
+            ~Use() {
+                c->fixed_ws = nullptr;
+                c->fixed_ws_bytes = 0;
+            }
+        } use{ctx};
+        ctx->fixed_ws = fixed;
+        ctx->fixed_ws_bytes = kNoallocScratchBytes;
+        energy_grad_dev_call(ctx, circ, in_state_dev, ham, theta, prec, E_dev, grad_dev);
     });
 }
 
