@@ -53,6 +53,8 @@ def parse():
                     help="skip timing the step that also returns the complex G")
     ap.add_argument("--no-shares", action="store_true",
                     help="skip the complex64 leg with FP32 per-thread product shares")
+    ap.add_argument("--no-states", action="store_true",
+                    help="skip the derivative-state variant (P + 2 states kept, Gram matrix on the matrix cores)")
     ap.add_argument("--variants", action="store_true",
                     help="also time the cheaper metric variants (block-diagonal per layer, L only) on the workload")
     ap.add_argument("--gateset", action="store_true",
@@ -430,6 +432,25 @@ def main():
                   "precision_errors": precision_report(pr, res_sh, res_other, "c64", "c128") if plain else None,
                   "max_abs_dG_vs_exact_products": float(abs(res_sh["G"] - res["G"]).max())}
         log(f"c64 with FP32 thread shares: {shares}")
+    states = None
+    if not args.no_states:
+        # the derivative-state variant of the metric: the same step with every
+        # column's derivative state kept and all inner products as one Gram matrix
+        ctx.set_option(qng.OPT_METHOD, 1)
+        try:
+            t_st, res_st, st_st = time_steps(ctx, circ, pr, args.prec, max(1, args.steps - 1), 1, profile=True)
+            V = (8 if args.prec == "c64" else 16) * 2 ** pr.n_qubits
+            nst = max(1, args.steps - 1)
+            states = {"s_per_step": t_st, "kept_states_GiB": (pr.n_params + 2) * V / 2 ** 30,
+                      "sweep_ms_per_step": st_st["sweep_ms"] / nst, "metric_ms_per_step": st_st["metric_ms"] / nst,
+                      "max_abs_dG_vs_recurrence": float(abs(res_st["G"] - res["G"]).max()),
+                      "rel_ddtheta_vs_recurrence": float(abs(res_st["dtheta"] - res["dtheta"]).max()
+                                                         / abs(res["dtheta"]).max())}
+        except qng.QNGError as e:
+            states = {"error": str(e)}
+        finally:
+            ctx.set_option(qng.OPT_METHOD, 0)
+        log(f"derivative-state variant: {states}")
     gate = None
     if args.gate_qubits > 0:
         gate = gate_apply_bandwidth(qng, ctx, min(args.gate_qubits, pr.n_qubits), args.prec)
@@ -471,7 +492,7 @@ def main():
                    "exact_products": bool(args.exact_products),
                    "block_columns": st.get("block_columns")},
         "plain_fp64": plain, "precision_errors": precision, "oracle_pinned_errors": oracle_errors,
-        "c64_fp32_product_shares": shares,
+        "c64_fp32_product_shares": shares, "derivative_state_variant": states,
         "step_with_G_output_s": t_with_G, "gate_apply": gate, "roofline": roof, "cpu_baseline": cpu,
         "metric_variants": variants, "extended_gates": gateset,
         "breakdown_ms": {k: st[k] / args.steps for k in ("metric_ms", "grad_ms", "solve_ms")},

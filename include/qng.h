@@ -146,7 +146,17 @@ typedef enum {
     QNG_OPT_EXACT_PRODUCTS = 11  /* complex64 with FP32 registers: 1 (default) = every product formed and
                                     accumulated in FP64 (exact products of the stored FP32 values); 0 = each
                                     thread forms its share of an inner product (16 or fewer amplitudes) in FP32
-                                    and converts it to FP64, all further sums FP64 (faster, narrower) */
+                                    and converts it to FP64, all further sums FP64 (faster, narrower) */,
+    QNG_OPT_METHOD = 12          /* how the metric's inner products are taken: 0 (default) = the recurrence of
+                                    Sec. 3 (Alg. 1) with a constant number of states, each inner product formed
+                                    in the sweep; 1 = the appendix's derivative-state strategy (its last
+                                    algorithm: every derivative state prepared from a rolling prefix and kept):
+                                    the same tiled sweeps carry every column's derivative state to one common
+                                    frame without forming any product, the P + 1 states are kept (P + 2 states of
+                                    device memory in all, QNG_E_OUT_OF_MEMORY if they do not fit) and all
+                                    inner products are one Gram matrix on the matrix cores (FP64 products and
+                                    sums).  Method 1 takes the plain gate set and the full metric
+                                    (QNG_E_UNSUPPORTED otherwise); qng_step_batched uses method 0. */
 } qng_option;
 
 /* Counters of the last metric/energy/step call on a context. */

@@ -29,6 +29,7 @@ PRECISIONS = {"c128": C128, "complex128": C128, C128: C128, "c64": C64, "complex
 
 OPT_FUSION, OPT_TILE_QUBITS, OPT_COLUMN_STREAMS, OPT_PROFILE, OPT_SMALL_N_KERNEL, OPT_F64_REGISTERS = 0, 1, 2, 3, 4, 5
 OPT_GRAPH, OPT_AUTOTUNE, OPT_BATCH_TILES, OPT_BLOCK_COLUMNS, OPT_METRIC_KIND, OPT_EXACT_PRODUCTS = 6, 7, 8, 9, 10, 11
+OPT_METHOD = 12
 
 STATUS = {
     0: "QNG_OK", -1: "QNG_E_INVALID_ARG", -2: "QNG_E_BAD_CIRCUIT", -3: "QNG_E_BAD_PARAMS",

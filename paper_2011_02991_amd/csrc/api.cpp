@@ -37,6 +37,7 @@
 #include "batch.hpp"
 #include "circuit.hpp"
 #include "fused.hpp"
+#include "gram_kernels.hpp"
 #include "kernels.hpp"
 #include "noalloc.hpp"
 #include "solve_kernels.hpp"
@@ -68,6 +69,7 @@ struct qng_ctx {
     int opt_fusion = 1, opt_tile = 0, opt_streams = 0, opt_profile = 0, opt_small = 1, opt_f64_regs = 0;
     int opt_exact_products = 1;   // complex64: every inner-product term in FP64 (0: FP32 thread shares)
     int opt_graph = 1, opt_autotune = 0, opt_batch_tiles = 0, opt_block = 0, opt_metric_kind = 0;
+    int opt_method = 0;   // 0: recurrence with O(1) states; 1: P derivative states and their Gram matrix
     std::vector<int> metric_blocks;   // block id per parameter (block-diagonal metric); empty = full
     std::string last_error;
     qng_stats stats{};
@@ -617,10 +619,17 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
     // controlled and Pauli-string rotations: per-primitive kernels only (the
     // fused passes implement single-qubit rotations, CNOT and CZ)
     const bool fused = ctx->opt_fusion != 0 && spec.metric && c.P > 1 && !c.extended();
+    // derivative-state variant: every column's swept phi register is kept and
+    // the metric is their Gram matrix (P + 1 more states)
+    const bool states = ctx->opt_method == 1 && spec.metric && c.P > 1;
+    if (states && (!fused || !pb.rot_block.empty()))
+        fail(QNG_E_UNSUPPORTED, "the derivative-state variant takes the fused passes of single-qubit rotations, "
+                                "CNOT and CZ and the full metric");
     const SweepPlan *plan = nullptr;
     FusedRun fr;
-    size_t scratch = 0;
+    size_t scratch = 0, gram_bytes = 0;
     int n_states = spec.metric ? 4 : 2;   // the gradient alone needs psi and lambda = H psi
+    int n_block_states = 0;
     if (fused) {
         const bool f64_regs = amp == 16 || ctx->opt_f64_regs;
         const bool blocked = !pb.rot_block.empty();
@@ -629,9 +638,20 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
                                      blocked ? &pb.rot_block : nullptr);
         size_t free_b = 0, total_b = 0;
         HIPCHECK(hipMemGetInfo(&free_b, &total_b));
-        fr = fused_config(*plan, ctx->opt_streams, V, free_b + ctx->ws_bytes);
-        scratch = fused_scratch_bytes(*plan, fr, c.M);
-        n_states = std::max(4, 1 + (plan->width + 1) * fr.B);
+        size_t avail = free_b + ctx->ws_bytes;
+        if (states) {
+            const size_t need = (size_t)(c.P + 2) * V;
+            if (need > avail)
+                fail(QNG_E_OUT_OF_MEMORY, "the derivative-state variant keeps " + std::to_string(c.P + 2) +
+                                              " states of " + std::to_string(V) + " bytes; " +
+                                              std::to_string(avail) + " bytes are free");
+            avail -= need;
+            gram_bytes = align256(gram_partial_bytes(n, c.P + 1));
+        }
+        fr = fused_config(*plan, ctx->opt_streams, V, avail);
+        scratch = fused_scratch_bytes(*plan, fr, c.M) + gram_bytes;
+        n_block_states = std::max(4, 1 + (plan->width + 1) * fr.B);
+        n_states = n_block_states + (states ? c.P + 2 : 0);   // then the dummy phi and the P + 1 kept states
         ctx->stats.block_columns = plan->width;
     }
     std::shared_ptr<const SweepPlan> gplan;
@@ -699,6 +719,12 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
             fb.traw = e.traw();
             fb.lraw = e.lraw();
             fb.reduce_partials = e.partials();
+            if (states) {
+                fb.scratch_bytes = L.sweep_bytes - gram_bytes;
+                fb.gram_partials = (double *)(base + L.sweep + fb.scratch_bytes);
+                fb.dummy = base + L.states + (size_t)n_block_states * L.state_bytes;
+                fb.xi = fb.dummy + L.state_bytes;
+            }
             pos = run_fused_metric<R>(*plan, fr, c, pb.fwd, pb.adj, fb, st, &ctx->stats, ctx->opt_profile != 0,
                                       sweep_reg_mode(ctx, amp), spec.real_products);
         } else if (step_width > 0) {
@@ -1209,6 +1235,10 @@ qng_status qng_set_option(qng_ctx *ctx, int option, int value) {
         case QNG_OPT_BLOCK_COLUMNS:
             if (value < 0 || value > kMaxBlockWidth) fail(QNG_E_INVALID_ARG, "block columns outside [0, 2]");
             ctx->opt_block = value;
+            break;
+        case QNG_OPT_METHOD:
+            if (value < 0 || value > 1) fail(QNG_E_INVALID_ARG, "method must be 0 (recurrence) or 1 (derivative states)");
+            ctx->opt_method = value;
             break;
         case QNG_OPT_METRIC_KIND:
             if (value < 0 || value > 1) fail(QNG_E_INVALID_ARG, "metric kind must be 0 (G) or 1 (L)");

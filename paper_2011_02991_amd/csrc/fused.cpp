@@ -7,6 +7,8 @@
 
 #include "fused.hpp"
 
+#include "gram_kernels.hpp"
+
 namespace qng {
 
 namespace {
@@ -43,6 +45,7 @@ size_t fused_scratch_bytes(const SweepPlan &plan, const FusedRun &fr, int M) {
     b += align256(plan.dev_maps.size() * sizeof(DevMap) + 64);          // thread mappings
     b += align256(plan.dev_passes.size() * sizeof(LaunchItem) + 64);    // one item per pass
     b += align256(((size_t)plan.P * plan.P / 2 + plan.P) * sizeof(ReduceTask) + 64);  // elements and seeds
+    b += align256((size_t)plan.P + 1 + 64);                              // signs (derivative-state variant)
     b += align256(fr.partial_elems * 16);
     return b;
 }
@@ -60,8 +63,17 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
     if (W > 1 && buf.traw != buf.lraw + 2 * (size_t)c.P * c.P)
         fail(QNG_E_DEVICE, "fused sweep: T must follow L in memory for column blocks (internal)");
     auto state = [&](int k) -> void * { return buf.states + (size_t)k * V; };
+    const bool states = buf.xi != nullptr;   // derivative-state variant
     // block b of a group: lambda, then phi registers 0 .. W-1 (the top column's is W-1)
     auto reg = [&](int b, int k) -> void * { return state(1 + (W + 1) * b + k); };
+    // the phi register k of the block whose top column is s: the kept state of
+    // its column in the derivative-state variant (the lowest block's register
+    // below column 1 is never seeded and goes to the dummy state)
+    auto xi_of = [&](int s, int b, int k) -> void * {
+        if (!states) return reg(b, 1 + k);
+        const int col = s - (W - 1) + k;
+        return col >= 1 ? (void *)(buf.xi + (size_t)(1 + col) * V) : (void *)buf.dummy;
+    };
 
     // ---- launch schedule (host)
     std::vector<LaunchItem> items;
@@ -94,11 +106,20 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
                 it.ntiles = tiles;
                 it.partial_off = poff;
                 it.regA = reg(b, 0);
-                it.regB = reg(b, 1);
-                it.regC = W > 1 ? reg(b, 2) : nullptr;
+                it.regB = xi_of(cp.s, b, 0);
+                it.regC = W > 1 ? xi_of(cp.s, b, 1) : nullptr;
                 items.push_back(it);
                 ++L.n_items;
                 L.total_tiles += tiles;
+                if (states) {
+                    // no reduce tasks: n_tasks counts the elements the pass carries
+                    for (size_t k = 0; k < hp.slot_dest.size(); ++k)
+                        if (hp.slot_dest[k] < c.P * c.P) {
+                            ++elements;
+                            ++L.n_tasks;
+                        }
+                    continue;
+                }
                 for (size_t k = 0; k < hp.slot_dest.size(); ++k) {
                     tasks.push_back(ReduceTask{poff + (uint64_t)k * tiles, tiles, hp.slot_dest[k]});
                     ++L.n_tasks;
@@ -134,6 +155,30 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
     DevOp *d_ops = (DevOp *)take(plan.dev_ops.size() * sizeof(DevOp));
     DevMap *d_maps = (DevMap *)take(plan.dev_maps.size() * sizeof(DevMap));
     LaunchItem *d_items = (LaunchItem *)take(items.size() * sizeof(LaunchItem));
+    // derivative-state variant: the sign each kept state carries.  A rotation
+    // whose adjoint has cos(theta/2) < 0 is applied negated to every register
+    // of a sweep (circuit.hpp, adjoint_shear), which cancels in the recurrence's
+    // products but not between states of different blocks.  In the block with
+    // top column s, lambda (seeded unsigned at y_s) and the top phi register
+    // pass through the adjoints of rotations s-1 .. 1; a lower column s_b is
+    // seeded from lambda just after the adjoint of rotation s_b, so it carries
+    // the signs of rotations s-1 .. s_b from lambda and those of s_b - 1 .. 1
+    // after: every register of the block ends with the product of the signs of
+    // rotations 1 .. s-1.  lambda* and column 0's state carry none.
+    std::vector<int8_t> signs;
+    int8_t *d_signs = nullptr;
+    if (states) {
+        std::vector<int8_t> prefix((size_t)c.P + 1, 1);   // prefix[s]: signs of rotations 1 .. s-1
+        for (int s = 2; s <= c.P; ++s)
+            prefix[s] = (int8_t)(adj[c.rots[s - 1].pos].a.real() < 0 ? -prefix[s - 1] : prefix[s - 1]);
+        signs.assign((size_t)c.P + 1, 1);
+        for (const ColumnPlan &cp : plan.cols)
+            for (int k = 0; k < W; ++k) {
+                const int col = cp.s - (W - 1) + k;
+                if (col >= 1) signs[1 + col] = prefix[cp.s];
+            }
+        d_signs = (int8_t *)take(signs.size());
+    }
     ReduceTask *d_tasks = (ReduceTask *)take(tasks.size() * sizeof(ReduceTask));
     double *d_partials = (double *)p;
     if ((size_t)(p - buf.scratch) + fr.partial_elems * 16 > buf.scratch_bytes)
@@ -156,6 +201,7 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
         FCHECK(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(LaunchItem), hipMemcpyHostToDevice, st));
     if (!tasks.empty())
         FCHECK(hipMemcpyAsync(d_tasks, tasks.data(), tasks.size() * sizeof(ReduceTask), hipMemcpyHostToDevice, st));
+    if (d_signs) FCHECK(hipMemcpyAsync(d_signs, signs.data(), signs.size(), hipMemcpyHostToDevice, st));
     FCHECK(hipStreamSynchronize(st));   // host vectors are released at return
 
     // ---- profiling events
@@ -195,7 +241,17 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
         }
     };
     forward_to(c.rots[0].pos, nullptr);
-    launch_pauli_prod<R>(psi, psi, n, c.rots[0].qubit, c.rots[0].axis, buf.reduce_partials, buf.traw, st);
+    if (states) {
+        // the sweeps end in the frame just after rotation 0 (its adjoint is never
+        // applied): lambda* = R_0 y_0 there, and column 0's derivative state is
+        // sigma_0 lambda* (R_0 commutes with sigma_0)
+        const Rot &r0 = c.rots[0];
+        launch_advance_seed<R>(psi, buf.xi, buf.xi + V, n, r0.qubit, d_fmats + (size_t)r0.pos * 8, r0.qubit, r0.axis,
+                               buf.reduce_partials, buf.traw, st);
+        pos = r0.pos + 1;
+    } else {
+        launch_pauli_prod<R>(psi, psi, n, c.rots[0].qubit, c.rots[0].axis, buf.reduce_partials, buf.traw, st);
+    }
     stats->other_launches += 2;
     for (const Group &G : groups) {
         for (int col = G.col_begin; col < G.col_end; ++col) {
@@ -211,7 +267,8 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
             const int ra = pos < c.M ? c.rot_at[pos] : -1;
             if (ra >= 0 && pos + 1 == rp.pos && rs.pos == rp.pos + 1 && n >= 3 && c.rots[ra].qubit != rp.qubit &&
                 c.rots[ra].qubit != rs.qubit && rp.qubit != rs.qubit) {
-                launch_advance2_seed<R>(psi, reg(b, 0), reg(b, W), n, c.rots[ra].qubit, d_fmats + (size_t)pos * 8,
+                launch_advance2_seed<R>(psi, reg(b, 0), xi_of(s, b, W - 1), n, c.rots[ra].qubit,
+                                        d_fmats + (size_t)pos * 8,
                                         rp.qubit, d_fmats + (size_t)rp.pos * 8, rs.qubit, rs.axis,
                                         buf.reduce_partials, buf.traw + 2 * s, st);
                 stats->other_launches += 2;
@@ -221,30 +278,51 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
             forward_to(rp.pos, reg(b, 0));
             int qr = -1;
             const double *mrow = d_fmats;
-            if (rs.pos == rp.pos + 1) {
+            if (rs.pos == rp.pos + 1 && pos == rp.pos) {   // (the states variant has applied rotation 0 already)
                 qr = rp.qubit;
                 mrow = d_fmats + (size_t)rp.pos * 8;
                 pos = rs.pos;
             } else {
                 forward_to(rs.pos, reg(b, 0));
             }
-            launch_advance_seed<R>(psi, reg(b, 0), reg(b, W), n, qr, mrow, rs.qubit, rs.axis, buf.reduce_partials,
-                                   buf.traw + 2 * s, st);
+            launch_advance_seed<R>(psi, reg(b, 0), xi_of(s, b, W - 1), n, qr, mrow, rs.qubit, rs.axis,
+                                   buf.reduce_partials, buf.traw + 2 * s, st);
             stats->other_launches += 2;
         }
         for (size_t li = G.launch_begin; li < G.launch_end; ++li) {
             const Launch &L = launches[li];
             if (profile) FCHECK(hipEventRecord(ev[2 * li], st));
-            launch_sweep_pass<R>(d_items + L.item_begin, (int)L.n_items, L.total_tiles, d_passes, d_ops, d_maps,
-                                 d_mats, d_mats32, d_partials, plan.m, plan.rb, reg_mode, W, st, real_products);
+            if (states)
+                launch_sweep_pass_states<R>(d_items + L.item_begin, (int)L.n_items, L.total_tiles, d_passes, d_ops,
+                                            d_maps, d_mats, d_mats32, plan.m, plan.rb, W, st);
+            else
+                launch_sweep_pass<R>(d_items + L.item_begin, (int)L.n_items, L.total_tiles, d_passes, d_ops, d_maps,
+                                     d_mats, d_mats32, d_partials, plan.m, plan.rb, reg_mode, W, st, real_products);
             if (profile) FCHECK(hipEventRecord(ev[2 * li + 1], st));
-            launch_reduce_tasks(d_tasks + L.task_begin, (int)L.n_tasks, d_partials, buf.lraw, st);
             ++stats->sweep_launches;
-            ++stats->other_launches;
             stats->sweep_tiles += L.total_tiles;
             stats->sweep_bytes += (double)L.n_items * 2.0 * (W + 1) * (double)V;
+            if (states) {
+                // the adjoint rotations on the phi registers (6) and on lambda,
+                // shared by the block (6 / W), per amplitude per element
+                stats->sweep_flops += (6.0 + 6.0 / W) * (double)L.n_tasks * (double)((uint64_t)1 << n);
+                continue;
+            }
+            launch_reduce_tasks(d_tasks + L.task_begin, (int)L.n_tasks, d_partials, buf.lraw, st);
+            ++stats->other_launches;
             stats->sweep_flops +=
                 sweep_flops_per_amp(W, real_products) * (double)L.n_tasks * (double)((uint64_t)1 << n);
+        }
+    }
+    if (states) {
+        // every inner product at once: Re (and, for the complex G, Im) of the
+        // Gram matrix of lambda* and the P derivative states, on the matrix cores
+        const bool c64 = sizeof(R) == 4;
+        launch_gram(buf.xi, c64, n, c.P + 1, c.P, 0, d_signs, buf.gram_partials, buf.lraw, buf.traw, st);
+        stats->other_launches += 2;
+        if (!real_products) {
+            launch_gram(buf.xi, c64, n, c.P + 1, c.P, 1, d_signs, buf.gram_partials, buf.lraw, buf.traw, st);
+            stats->other_launches += 2;
         }
     }
     stats->elements += elements;

@@ -19,6 +19,16 @@ struct FusedBuffers {
     double *traw = nullptr;        // P complex: <y_s|sigma_s|y_s>
     double *lraw = nullptr;        // P*P complex: <lambda|sigma_r|phi> at (r, s)
     double *reduce_partials = nullptr;  // scratch of the per-primitive reductions
+    // Derivative-state variant (xi != nullptr): P + 1 states at xi, one after
+    // another -- the forward state lambda* in the sweeps' final frame, then the
+    // swept phi register of every column s (its derivative state, up to the
+    // factor i/2 and a unitary common to all columns) -- the passes take no
+    // inner product, and L and T come from the Gram matrix of those states
+    // (gram_partials: gram_partial_bytes of scratch).  dummy: one state for
+    // the unused phi register of the lowest block.
+    char *xi = nullptr;
+    char *dummy = nullptr;
+    double *gram_partials = nullptr;
 };
 
 size_t fused_scratch_bytes(const SweepPlan &plan, const FusedRun &fr, int M);

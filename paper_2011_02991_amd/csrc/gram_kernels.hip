@@ -1,0 +1,233 @@
+// gram_kernels.hip -- the Gram matrix of the explicit derivative states, on
+// the matrix cores (MFMA, FP64).
+//
+// The derivative-state variant of the metric (appendix: every derivative state
+// prepared and kept, then all (P^2 + P)/2 inner products) ends with Q = P + 1
+// states X_0 = lambda* (the forward state in the sweeps' final frame) and
+// X_{1+s} = the swept derivative state of column s, stored one after another
+// (each 2^n complex amplitudes, i.e. K = 2^(n+1) interleaved reals).  Every
+// inner product <X_a|X_b> is then one entry of a dense contraction over K:
+//   Re <X_a|X_b> = sum_k x_a[k] x_b[k]                 (mode 0),
+//   Im <X_a|X_b> = sum_k x_a[k] (J x_b)[k]              (mode 1),
+// with (J x)[2j] = x[2j+1], (J x)[2j+1] = -x[2j] (complex multiplication by -i
+// read as reals).  That is a symmetric (mode 0) or antisymmetric (mode 1) K x Q
+// by Q x K product with K far larger than Q, computed here with
+// v_mfma_f64_16x16x4_f64: every product is formed in FP64 (complex64 states
+// are converted, exactly, when a tile is staged) and accumulated in FP64.
+//
+// Work split: the Q columns are cut into tiles of 64; a work-group owns one
+// pair of tiles (ta <= tb) and one chunk of K, stages 32 reals of each of its
+// 128 columns per step in LDS (FP64) and accumulates a 64 x 64 block of the
+// result in the MFMA accumulators (4 wavefronts, 32 x 32 each, as 2 x 2 MFMA
+// blocks).  Pairs vary fastest over the work-groups, so the work-groups of one
+// chunk run together and share its columns in the caches.  Each work-group
+// writes its block to a partial buffer; k_gram_reduce adds the chunks of every
+// entry in a fixed order (bitwise reproducible) and writes the raw metric
+// entries in the layout of the recurrent method's raw L and T.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "gram_kernels.hpp"
+
+namespace qng {
+
+namespace {
+
+constexpr int kGramThreads = 256;
+constexpr int kTile = 64;         // columns per tile
+constexpr int kStep = 32;         // reals of K staged per step
+constexpr int kPad = kStep + 1;   // LDS row stride in doubles: lanes on 16 columns hit distinct banks
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void tile_pair(int pair, int ntile, int &ta, int &tb) {
+    ta = 0;
+    while (pair >= ntile - ta) {
+        pair -= ntile - ta;
+        ++ta;
+    }
+    tb = ta + pair;
+}
+
+// Eight consecutive reals of column q from real k (k a multiple of 8), as FP64;
+// zeros past the last column or past K (K = 2^(n+1) is a multiple of 8 from
+// n = 2 on; below that the tail is read element by element).
+__device__ __forceinline__ void load8(const float *X, uint64_t stride, int q, int Q, uint64_t k, uint64_t K,
+                                      double (&v)[8]) {
+    if (q < Q && k + 8 <= K) {
+        const float4 *p = (const float4 *)(X + (uint64_t)q * stride + k);
+        const float4 a = p[0], b = p[1];
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = (q < Q && k + j < K) ? (double)X[(uint64_t)q * stride + k + j] : 0.0;
+    }
+}
+__device__ __forceinline__ void load8(const double *X, uint64_t stride, int q, int Q, uint64_t k, uint64_t K,
+                                      double (&v)[8]) {
+    if (q < Q && k + 8 <= K) {
+        const double2 *p = (const double2 *)(X + (uint64_t)q * stride + k);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double2 a = p[j];
+            v[2 * j] = a.x;
+            v[2 * j + 1] = a.y;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = (q < Q && k + j < K) ? X[(uint64_t)q * stride + k + j] : 0.0;
+    }
+}
+
+// X: Q columns of K reals each, column q at X + q * stride.  kc: reals per chunk
+// (a multiple of kStep).  partials: [chunk][pair][64][64] doubles.
+template <typename R>
+__global__ __launch_bounds__(kGramThreads) void k_gram(const R *__restrict__ X, uint64_t stride, int Q, uint64_t K,
+                                                       uint64_t kc, int ntile, int npairs, int mode,
+                                                       double *__restrict__ partials) {
+    __shared__ double sA[kTile * kPad];
+    __shared__ double sB[kTile * kPad];
+    const int pair = (int)(blockIdx.x % (unsigned)npairs);
+    const int chunk = (int)(blockIdx.x / (unsigned)npairs);
+    int ta, tb;
+    tile_pair(pair, ntile, ta, tb);
+    const bool same = ta == tb && mode == 0;   // one tile serves both operands
+    const double *sBv = same ? sA : sB;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;   // this wave's 32 x 32 quarter of the block
+    const int lcol = tid >> 2, part = tid & 3;  // staging: column lcol, reals part*8 .. part*8+7 of the step
+
+    d4 acc00 = {0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
+    const uint64_t kbeg = (uint64_t)chunk * kc;
+    const uint64_t kend = kbeg + kc < K ? kbeg + kc : K;
+    for (uint64_t k0 = kbeg; k0 < kend; k0 += kStep) {
+        double v[8];
+        load8(X, stride, ta * kTile + lcol, Q, k0 + part * 8, K, v);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sA[lcol * kPad + part * 8 + j] = v[j];
+        if (!same) {
+            load8(X, stride, tb * kTile + lcol, Q, k0 + part * 8, K, v);
+            if (mode == 1) {
+#pragma unroll
+                for (int j = 0; j < 8; j += 2) {
+                    const double re = v[j], im = v[j + 1];
+                    v[j] = im;
+                    v[j + 1] = -re;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sB[lcol * kPad + part * 8 + j] = v[j];
+        }
+        __syncthreads();
+        // A(row = lane % 16, k = lane / 16), B(k = lane / 16, col = lane % 16)
+        const int r0 = wr * 32 + (lane & 15), c0 = wc * 32 + (lane & 15);
+#pragma unroll
+        for (int kk = 0; kk < kStep; kk += 4) {
+            const int kl = kk + (lane >> 4);
+            const double a0 = sA[r0 * kPad + kl], a1 = sA[(r0 + 16) * kPad + kl];
+            const double b0 = sBv[c0 * kPad + kl], b1 = sBv[(c0 + 16) * kPad + kl];
+            acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc00, 0, 0, 0);
+            acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc01, 0, 0, 0);
+            acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc10, 0, 0, 0);
+            acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc11, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // D(row = 4 i + lane / 16, col = lane % 16) of each 16 x 16 block (item i of
+    // the accumulator)
+    double *out = partials + ((uint64_t)chunk * npairs + pair) * (kTile * kTile);
+    const int rr = wr * 32 + (lane >> 4), cc = wc * 32 + (lane & 15);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        out[(rr + 4 * i) * kTile + cc] = acc00[i];
+        out[(rr + 4 * i) * kTile + cc + 16] = acc01[i];
+        out[(rr + 16 + 4 * i) * kTile + cc] = acc10[i];
+        out[(rr + 16 + 4 * i) * kTile + cc + 16] = acc11[i];
+    }
+}
+
+// One thread per entry of a computed block: the chunks' partials summed in
+// order, times sign[qa] sign[qb] (each kept state is its column's derivative
+// state up to a known sign), and entry (qa, qb), qa < qb, goes to the raw
+// metric: qa = 0 -> T of column qb - 1, qa >= 1 -> L of (qa - 1, qb - 1); the
+// real part (mode 0) or the imaginary part (mode 1) of the complex result.
+__global__ void k_gram_reduce(const double *__restrict__ partials, int npairs, int nchunks, int ntile, int Q, int P,
+                              int mode, const int8_t *__restrict__ sign, double *__restrict__ lraw,
+                              double *__restrict__ traw) {
+    const uint64_t idx = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (idx >= (uint64_t)npairs * kTile * kTile) return;
+    const int pair = (int)(idx / (kTile * kTile));
+    const int e = (int)(idx % (kTile * kTile));
+    int ta, tb;
+    tile_pair(pair, ntile, ta, tb);
+    const int qa = ta * kTile + e / kTile, qb = tb * kTile + e % kTile;
+    if (qa >= qb || qb >= Q) return;
+    double s = 0.0;
+    for (int c = 0; c < nchunks; ++c) s += partials[((uint64_t)c * npairs + pair) * (kTile * kTile) + e];
+    if (sign[qa] != sign[qb]) s = -s;
+    double *dst = qa == 0 ? traw + 2 * (uint64_t)(qb - 1) : lraw + 2 * ((uint64_t)(qa - 1) * P + (qb - 1));
+    dst[mode] = s;
+}
+
+inline void check_launch() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw e;
+}
+
+struct GramShape {
+    int ntile, npairs, nchunks;
+    uint64_t K, kc;
+};
+
+GramShape gram_shape(int n, int Q) {
+    GramShape g;
+    g.ntile = (Q + kTile - 1) / kTile;
+    g.npairs = g.ntile * (g.ntile + 1) / 2;
+    g.K = uint64_t(2) << n;
+    // about 3072 work-groups in all, chunks a power of two of at least kStep reals
+    uint64_t want = (3072 + (uint64_t)g.npairs - 1) / (uint64_t)g.npairs;
+    uint64_t nch = 1;
+    while (nch < want) nch <<= 1;
+    while (nch > 1 && g.K / nch < (uint64_t)kStep) nch >>= 1;
+    g.nchunks = (int)nch;
+    g.kc = g.K / nch;
+    if (g.kc < (uint64_t)kStep) g.kc = kStep;
+    return g;
+}
+
+}  // namespace
+
+size_t gram_partial_bytes(int n, int Q) {
+    const GramShape g = gram_shape(n, Q);
+    return (size_t)g.nchunks * g.npairs * kTile * kTile * sizeof(double);
+}
+
+void launch_gram(const void *X, bool complex64, int n, int Q, int P, int mode, const int8_t *sign, double *partials,
+                 double *lraw, double *traw, hipStream_t st) {
+    if (Q < 2) return;
+    const GramShape g = gram_shape(n, Q);
+    const uint64_t stride = g.K;
+    const unsigned blocks = (unsigned)((uint64_t)g.npairs * g.nchunks);
+    if (complex64)
+        hipLaunchKernelGGL(k_gram<float>, dim3(blocks), dim3(kGramThreads), 0, st, (const float *)X, stride, Q, g.K,
+                           g.kc, g.ntile, g.npairs, mode, partials);
+    else
+        hipLaunchKernelGGL(k_gram<double>, dim3(blocks), dim3(kGramThreads), 0, st, (const double *)X, stride, Q, g.K,
+                           g.kc, g.ntile, g.npairs, mode, partials);
+    check_launch();
+    const uint64_t entries = (uint64_t)g.npairs * kTile * kTile;
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, st, partials, g.npairs,
+                       g.nchunks, g.ntile, Q, P, mode, sign, lraw, traw);
+    check_launch();
+}
+
+double gram_flops(int n, int Q) {
+    const GramShape g = gram_shape(n, Q);
+    return 2.0 * (double)g.npairs * kTile * kTile * (double)g.K;
+}
+
+}  // namespace qng

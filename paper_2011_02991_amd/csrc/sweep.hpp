@@ -307,5 +307,12 @@ void launch_sweep_pass_real_exact(const LaunchItem *items, int n_items, uint32_t
                                   double *partials, int m, int rb, int width, hipStream_t st);
 void launch_reduce_tasks(const ReduceTask *tasks, int n_tasks, const double *partials, double *results,
                          hipStream_t st);
+// The passes without inner products (sweep_kernels_states.hip): lambda and
+// the phi registers go through the adjoint gates and the in-pass seeds only.
+template <typename R>
+void launch_sweep_pass_states(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
+                              const DevOp *ops, const DevMap *maps, const double *mats64, const float *mats32, int m,
+                              int rb, int width, hipStream_t st);
+
 
 }  // namespace qng

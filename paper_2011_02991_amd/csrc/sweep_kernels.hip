@@ -493,10 +493,26 @@ __device__ __forceinline__ void prodw_plain(const Regs<CT, T, W> &x, double (&pr
 // the others into the sink (no branch).
 // The stores come after the op's tile update, as in the one-register kernel
 // (its register allocation depends on that order).
+// Built with QNG_NO_PRODUCTS = 1 (sweep_kernels_states.hip), the passes take
+// no inner product at all: they only carry the registers through the adjoint
+// gates and the in-pass seeds, for the variant that keeps every column's phi
+// register as an explicit derivative state and forms the metric as their Gram
+// matrix afterwards.
+#ifndef QNG_NO_PRODUCTS
+#define QNG_NO_PRODUCTS 0
+#endif
+constexpr bool kNoProducts = QNG_NO_PRODUCTS != 0;
+// waves per SIMD the FP32 kernels without products are held to (four: at most
+// 128 VGPRs, a few values spill in the exchanges; three: 130 VGPRs, none)
+#ifndef QNG_STATES_WAVES
+#define QNG_STATES_WAVES 4
+#endif
+
 #define QNG_PRODS(PRODW)                                                                                     \
     double pr[W], pi[W];                                                                                     \
-    PRODW(x, pr, pi)
-#define QNG_STORE_PRODS() row_reduce_store<W>(sink, red, slot, fa, tid, pr, pi)
+    if constexpr (!kNoProducts) { PRODW(x, pr, pi); }
+#define QNG_STORE_PRODS()                                                                                    \
+    if constexpr (!kNoProducts) row_reduce_store<W>(sink, red, slot, fa, tid, pr, pi)
 
 // ------------------------------------------------------- gates on registers
 
@@ -1009,7 +1025,7 @@ __device__ __forceinline__ void tile_sums(const Regs<CT, T, W> &x, double2 *sink
 // with two phi registers it is held to 168 VGPRs (it needs 146; with every
 // product in FP64 a few values spill in the exchanges).
 template <typename R, typename CT, int RB, bool FULL, int W>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 1 ? (RB >= 4 ? 1 : 3) : 3, 8))) void k_sweep_reg(const LaunchItem *__restrict__ items, int n_items,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNoProducts ? (sizeof(CT) == 4 ? QNG_STATES_WAVES : 3) : W == 1 ? (RB >= 4 ? 1 : 3) : 3, 8))) void k_sweep_reg(const LaunchItem *__restrict__ items, int n_items,
                                                         const DevPass *__restrict__ passes,
                                                         const DevOp *__restrict__ ops,
                                                         const DevMap *__restrict__ maps,
@@ -1083,7 +1099,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 1
     double Sr[W], Si[W];
 #pragma unroll
     for (int b = 0; b < W; ++b) Sr[b] = Si[b] = 0.0;
-    if (pass_zsum) tile_sums<T, CT, W, 0, W>(x, sink, zs, tid, Sr, Si);
+    if (!kNoProducts && pass_zsum) tile_sums<T, CT, W, 0, W>(x, sink, zs, tid, Sr, Si);
 
     // ---- operations.  Each op carries a one-hot handler bit; the handlers run
     // under independent tests of that word (by group, register bit, kind),
@@ -1118,7 +1134,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 1
             if (hf & (hbit(HB_DIAG_UNI) | hbit(HB_PRODDIAG_UNI))) {
                 // the Z bit is common to all registers of the thread
                 const bool one = (op.b0() == kLocBase) ? ((base >> op.q0()) & 1u) : ((tid >> (op.b0() & 15)) & 1);
-                if (hf & hbit(HB_PRODDIAG_UNI)) {
+                if (!kNoProducts && (hf & hbit(HB_PRODDIAG_UNI))) {
                     const double sg = one ? -1.0 : 1.0;
                     const int slot = op.slot();
                     QNG_PRODS((prodw_plain<T, CT, W>));
@@ -1163,7 +1179,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 1
                 if (hf & prod_bits(2)) prod_handlers<2, RB, T, CT, W>(x, hf, sink, red, slot, fa, tid);
                 if (hf & prod_bits(3)) prod_handlers<3, RB, T, CT, W>(x, hf, sink, red, slot, fa, tid);
             }
-            if (hf & hbit(HB_PRODZ_UNI)) {
+            if (!kNoProducts && (hf & hbit(HB_PRODZ_UNI))) {
                 // Z bit held by the thread index or the tile base
                 const bool one =
                     (op.b0() == kLocBase) ? ((base >> op.q0()) & 1u) : ((tid >> (op.b0() & 15)) & 1);
@@ -1192,7 +1208,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 1
                     }
                 }
             }
-            if (hf & hbit(HB_ZSUM)) {
+            if (!kNoProducts && (hf & hbit(HB_ZSUM))) {
                 if (tid == 0) {
                     const double sg = ((base >> op.q0()) & 1u) ? -1.0 : 1.0;
 #pragma unroll
@@ -1210,10 +1226,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 1
                     // <lambda|phi> = <y|sigma|y> into the op's slot
                     static_assert(W == 2, "seeds are written for blocks of two columns");
                     seed_phi<0, RB, T, CT, W>(x, op.w0 >> 24, op.b0(), op.q0(), tid, base);
-                    double pr, pi;
-                    prod_plain<T, CT>(x.ar, x.ai, x.br[0], x.bi[0], pr, pi);
-                    row_store(sink, red, op.slot(), tid, pr, pi);
-                    if (pass_zsum) tile_sums<T, CT, W, 0, 1>(x, sink, zs, tid, Sr, Si);
+                    if constexpr (!kNoProducts) {
+                        double pr, pi;
+                        prod_plain<T, CT>(x.ar, x.ai, x.br[0], x.bi[0], pr, pi);
+                        row_store(sink, red, op.slot(), tid, pr, pi);
+                        if (pass_zsum) tile_sums<T, CT, W, 0, 1>(x, sink, zs, tid, Sr, Si);
+                    }
                 }
             }
             if (hf & hbit(HB_XPOSE)) {
@@ -1239,6 +1257,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 1
         }
     }
     // ---- per-tile partial sums
+    if constexpr (kNoProducts) return;
     __syncthreads();
     for (int k = tid; k < pass_slots; k += kThreads) {
         double xr = 0.0, xi = 0.0;
@@ -1290,7 +1309,8 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_tasks(const ReduceTas
 }
 
 template <typename CT> size_t smem_bytes(int m) {
-    return xbuf_bytes<typename Amp<CT>::T>(m) + (size_t)kLdsTailEntries * sizeof(double2);
+    // without products only the exchange buffer is used
+    return xbuf_bytes<typename Amp<CT>::T>(m) + (kNoProducts ? 0 : (size_t)kLdsTailEntries * sizeof(double2));
 }
 
 template <typename R, typename CT, int RB, bool FULL, int W>
@@ -1353,7 +1373,26 @@ void launch_ct(const LaunchItem *items, int n_items, uint32_t total_tiles, const
 
 }  // namespace
 
-#if QNG_REAL_PRODUCTS && QNG_EXACT_PRODUCTS
+#if QNG_NO_PRODUCTS
+template <typename R>
+void launch_sweep_pass_states(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
+                              const DevOp *ops, const DevMap *maps, const double *mats64, const float *mats32, int m,
+                              int rb, int width, hipStream_t st) {
+    if (n_items <= 0 || total_tiles == 0) return;
+    if constexpr (sizeof(R) == 8)
+        launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, nullptr, m, rb, width, st);
+    else
+        launch_ct<R, float>(items, n_items, total_tiles, passes, ops, maps, mats32, nullptr, m, rb, width, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw e;
+}
+template void launch_sweep_pass_states<double>(const LaunchItem *, int, uint32_t, const DevPass *, const DevOp *,
+                                               const DevMap *, const double *, const float *, int, int, int,
+                                               hipStream_t);
+template void launch_sweep_pass_states<float>(const LaunchItem *, int, uint32_t, const DevPass *, const DevOp *,
+                                              const DevMap *, const double *, const float *, int, int, int,
+                                              hipStream_t);
+#elif QNG_REAL_PRODUCTS && QNG_EXACT_PRODUCTS
 void launch_sweep_pass_real_exact(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
                                   const DevOp *ops, const DevMap *maps, const float *mats32, double *partials, int m,
                                   int rb, int width, hipStream_t st) {

@@ -1,0 +1,148 @@
+"""The derivative-state variant of the metric (QNG_OPT_METHOD = 1): the
+appendix's strategy of keeping every derivative state (its last algorithm: each
+derivative state prepared from a rolling prefix), here as the same tiled
+sweeps without inner products plus one Gram matrix of the P + 1 kept states on
+the matrix cores (FP64 products and sums).  Parity against the FP64 oracle
+(complex128, normwise 1e-10 for G, T, grad E; dtheta within max(1e-10,
+kappa 1e-14)), against the recurrent method on every entry, and on the edge
+cases: registers of 2 and 3 qubits (fewer reals per state than one staging
+step of the Gram kernel), two parameters, odd P, blocks of one and two
+columns, permuted and shared parameters, the complex G output (the Gram
+matrix's imaginary part) and the step without it."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+U32 = 2.0 ** -24
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch  # noqa: F401
+    import paper_2011_02991_amd as q
+    c = q.Context(0)
+    yield q, c
+    c.close()
+
+
+def rel_err(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max(initial=0.0) / max(np.abs(b).max(initial=0.0), 1e-300))
+
+
+def step(q, ctx, pr, method, prec="c128", want_G=True):
+    ctx.set_option(q.OPT_METHOD, method)
+    try:
+        circ = q.Circuit.from_problem(pr)
+        res = ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, in_state=pr.in_state, prec=prec, want_G=want_G)
+        _, T = ctx.metric(circ, pr.theta, in_state=pr.in_state, prec=prec)
+    finally:
+        ctx.set_option(q.OPT_METHOD, 0)
+    return res, T
+
+
+def small_cases():
+    cases = [W.random_circuit(2, 9, 8101, n_terms=3), W.random_circuit(3, 14, 8102, n_terms=4),
+             W.random_circuit(2, 2, 8103, fixed_fraction=0.0, n_terms=2),
+             W.config1(), W.scaled(W.config2, 9, 3, n_terms=6), W.random_circuit(12, 70, 8104, n_terms=6),
+             W.permute_params(W.scaled(W.config3, 13, 2, n_terms=8), 8105),
+             W.scaled(W.config5, 14, 1, n_terms=8), W.share_params(W.random_circuit(11, 60, 8106, n_terms=5), 9, 8107)]
+    cases[1].in_state = W.random_state(3, 8108)
+    cases[5].in_state = W.random_state(12, 8109)
+    return cases
+
+
+@pytest.mark.parametrize("idx", range(9))
+def test_states_vs_oracle(env, idx):
+    q, ctx = env
+    pr = small_cases()[idx]
+    say(f"case: {pr.name} n={pr.n_qubits} P={pr.n_params} derivative-state metric vs oracle")
+    res, T = step(q, ctx, pr, 1)
+    want = oracle.step(pr)
+    kappa = np.linalg.cond(want["G"].real + pr.tikhonov * np.eye(pr.n_params))
+    eG, eT = rel_err(res["G"], want["G"]), rel_err(T, want["T"])
+    eg, ed = rel_err(res["grad"], want["grad"]), rel_err(res["dtheta"], want["dtheta"])
+    say(f"{pr.name}: |dG|={eG:.2e} |dT|={eT:.2e} |dgrad|={eg:.2e} |ddtheta|={ed:.2e} kappa={kappa:.1e}")
+    assert max(eG, eT, eg) <= TOL and ed <= max(TOL, kappa * 1e-14)
+    # the recurrent method on every entry
+    rec, Tr = step(q, ctx, pr, 0)
+    assert rel_err(res["G"], rec["G"]) <= TOL and rel_err(T, Tr) <= TOL
+    # the step without the G output (real part of the Gram matrix only) solves the same system
+    real, _ = step(q, ctx, pr, 1, want_G=False)
+    assert rel_err(real["dtheta"], res["dtheta"]) <= 1e-13
+
+
+def test_states_complex64(env):
+    """complex64 storage: the kept states are FP32, the Gram matrix converts
+    them exactly and forms every product in FP64; against complex128 at the
+    random-walk rounding bound of the sweeps (8 sqrt(M) u, M gates)."""
+    q, ctx = env
+    pr = W.scaled(W.config3, 14, 3, n_terms=10)
+    r64, T64 = step(q, ctx, pr, 1, prec="c64")
+    r128, T128 = step(q, ctx, pr, 0, prec="c128")
+    bound = 8 * np.sqrt(pr.n_gates) * U32
+    eG, eT = rel_err(r64["G"], r128["G"]), rel_err(T64, T128)
+    say(f"{pr.name} c64 states vs c128: |dG|={eG:.2e} |dT|={eT:.2e} bound {bound:.1e}")
+    assert eG <= bound and eT <= bound
+
+
+def test_states_rejections(env):
+    q, ctx = env
+    pr = W.controlled_circuit(5, 20, 8110, n_terms=3)
+    with pytest.raises(q.QNGError) as e:
+        step(q, ctx, pr, 1)
+    assert e.value.name == "QNG_E_UNSUPPORTED"
+    pr = W.scaled(W.config1, 14, 2, n_terms=3)
+    # the P + 2 = 58 kept states of 256 KiB take 14.5 MiB, above a context limit of 8 MiB
+    ctx.set_mem_limit(8 << 20)
+    try:
+        with pytest.raises(q.QNGError) as e:
+            step(q, ctx, pr, 1)
+        assert e.value.name == "QNG_E_OUT_OF_MEMORY"
+    finally:
+        ctx.set_mem_limit(0)
+
+
+@pytest.mark.timeout(900)
+def test_states_n20_full_oracle(env):
+    q, ctx = env
+    pr = W.config2()
+    say(f"case: {pr.name} derivative-state metric, full oracle")
+    res, T = step(q, ctx, pr, 1)
+    D, psi = oracle.derivative_states(pr)
+    Go, To, _ = oracle.metric_from_states(D, psi)
+    Eo, go = oracle.energy_grad(pr, None, D=D, psi=psi)
+    del D, psi
+    dth = oracle.solve_step(Go, go, pr.dt, pr.tikhonov)
+    kappa = np.linalg.cond(Go.real + pr.tikhonov * np.eye(pr.n_params))
+    eG, eT, eg, ed = rel_err(res["G"], Go), rel_err(T, To), rel_err(res["grad"], go), rel_err(res["dtheta"], dth)
+    say(f"{pr.name}: |dG|={eG:.2e} |dT|={eT:.2e} |dgrad|={eg:.2e} |ddtheta|={ed:.2e} kappa={kappa:.1e}")
+    assert max(eG, eT, eg) <= TOL and ed <= max(TOL, kappa * 1e-14)
+
+
+@pytest.mark.timeout(900)
+def test_states_n24_against_recurrence(env):
+    """n=24, P=432 (108 GiB of kept states): every entry against the
+    recurrent method, which the full-size tests pin to the oracle."""
+    q, ctx = env
+    pr = W.config5()
+    say(f"case: {pr.name} derivative-state metric vs recurrence, every entry")
+    res, T = step(q, ctx, pr, 1)
+    rec, Tr = step(q, ctx, pr, 0)
+    eG, eT, eg = rel_err(res["G"], rec["G"]), rel_err(T, Tr), rel_err(res["grad"], rec["grad"])
+    kappa = np.linalg.cond(rec["G"].real + pr.tikhonov * np.eye(pr.n_params))
+    ed = rel_err(res["dtheta"], rec["dtheta"])
+    say(f"{pr.name}: |dG|={eG:.2e} |dT|={eT:.2e} |dgrad|={eg:.2e} |ddtheta|={ed:.2e} kappa={kappa:.1e}")
+    assert max(eG, eT, eg) <= TOL and ed <= max(TOL, kappa * 1e-14)
