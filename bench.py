@@ -26,6 +26,13 @@ HBM_PEAK_GBS = 8000.0
 # SIMD per clock): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 KERNEL_SRC = os.path.join(ROOT, "paper_2011_02991_amd", "csrc", "sweep_kernels.hip")
+# the sweep kernel the timed (no G output) steps launch, by storage and product setting
+def sweep_kernel_name(prec, f64_regs, exact_products):
+    if prec == "c64" and not f64_regs and exact_products:
+        return "k_sweep_reg_real_exact"
+    return "k_sweep_reg_real"
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_pass_cfg3_traffic.json")
 
 
@@ -367,15 +374,16 @@ def extended_gates(qng, ctx, prec, n_gate=26, n_step=24, layers=2, reps=2):
     return out
 
 
-def traffic_per_launch():
+def traffic_per_launch(kernel):
     """HBM bytes per sweep launch from the committed FETCH_SIZE/WRITE_SIZE counter
-    summary, if it was taken on the current kernel source (else None)."""
+    summary, if it was taken on the current kernel source and for this kernel
+    (else None)."""
     import hashlib
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
         h = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-        if t.get("kernel_sha256") != h:
+        if t.get("kernel_sha256") != h or t.get("kernel") != kernel:
             return None
         return t["bytes_per_launch"]
     except (OSError, ValueError, KeyError):
@@ -443,9 +451,10 @@ def main():
             nst = max(1, args.steps - 1)
             states = {"s_per_step": t_st, "kept_states_GiB": (pr.n_params + 2) * V / 2 ** 30,
                       "sweep_ms_per_step": st_st["sweep_ms"] / nst, "metric_ms_per_step": st_st["metric_ms"] / nst,
-                      "max_abs_dG_vs_recurrence": float(abs(res_st["G"] - res["G"]).max()),
                       "rel_ddtheta_vs_recurrence": float(abs(res_st["dtheta"] - res["dtheta"]).max()
                                                          / abs(res["dtheta"]).max())}
+            if res.get("G") is not None and res_st.get("G") is not None:
+                states["max_abs_dG_vs_recurrence"] = float(abs(res_st["G"] - res["G"]).max())
         except qng.QNGError as e:
             states = {"error": str(e)}
         finally:
@@ -465,6 +474,7 @@ def main():
         log(f"cpu baseline: {cpu}")
         log(f"oracle-pinned errors on sampled parameters: {oracle_errors}")
     roof = None
+    kname = sweep_kernel_name(args.prec, args.f64_regs, args.exact_products)
     if st.get("sweep_launches", 0) > 0 and st.get("sweep_ms", 0) > 0:
         nl = st["sweep_launches"]
         avg_ms = st["sweep_ms"] / nl
@@ -472,7 +482,7 @@ def main():
         bytes_ = st["sweep_bytes"] / nl
         achieved = flops / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / VALU_PEAK_TFLOPS, "traffic": traffic_per_launch(), "kernel": "k_sweep_reg",
+                "frac": achieved / VALU_PEAK_TFLOPS, "traffic": traffic_per_launch(kname), "kernel": kname,
                 "avg_launch_ms": avg_ms, "launches": nl, "algorithmic_flops_per_launch": flops,
                 "algorithmic_bytes_per_launch": bytes_,
                 "hbm_achieved_GBps": bytes_ / (avg_ms * 1e-3) / 1e9,

@@ -84,13 +84,24 @@ __device__ __forceinline__ void load8(const double *X, uint64_t stride, int q, i
 // X: Q columns of K reals each, column q at X + q * stride.  kc: reals per chunk
 // (a multiple of kStep).  partials: [chunk][pair][64][64] doubles.
 template <typename R>
-__global__ __launch_bounds__(kGramThreads) void k_gram(const R *__restrict__ X, uint64_t stride, int Q, uint64_t K,
+__global__ __launch_bounds__(kGramThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_gram(const R *__restrict__ X, uint64_t stride, int Q, uint64_t K,
                                                        uint64_t kc, int ntile, int npairs, int mode,
-                                                       double *__restrict__ partials) {
+                                                       bool nchunks_xcd, double *__restrict__ partials) {
     __shared__ double sA[kTile * kPad];
     __shared__ double sB[kTile * kPad];
-    const int pair = (int)(blockIdx.x % (unsigned)npairs);
-    const int chunk = (int)(blockIdx.x / (unsigned)npairs);
+    // Work-groups are dealt to the 8 XCDs round robin (work-group b runs on XCD
+    // b mod 8).  All tile pairs of one chunk go to one XCD, so the work-groups
+    // reading the same columns of a chunk share that XCD's L2: XCD x takes
+    // chunks x, x + 8, x + 16, ... (nchunks is a multiple of 8 when above 8).
+    int pair, chunk;
+    if (nchunks_xcd) {
+        const unsigned b = blockIdx.x, xcd = b & 7u, local = b >> 3;
+        pair = (int)(local % (unsigned)npairs);
+        chunk = (int)((local / (unsigned)npairs) * 8u + xcd);
+    } else {
+        pair = (int)(blockIdx.x % (unsigned)npairs);
+        chunk = (int)(blockIdx.x / (unsigned)npairs);
+    }
     int ta, tb;
     tile_pair(pair, ntile, ta, tb);
     const bool same = ta == tb && mode == 0;   // one tile serves both operands
@@ -104,25 +115,32 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const R *__restrict__ X, 
     d4 acc00 = {0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
     const uint64_t kbeg = (uint64_t)chunk * kc;
     const uint64_t kend = kbeg + kc < K ? kbeg + kc : K;
+    // the next step's reals are loaded into registers while the current step's
+    // MFMAs run, then written to LDS between the two barriers
+    double va[8], vb[8];
+    load8(X, stride, ta * kTile + lcol, Q, kbeg + part * 8, K, va);
+    if (!same) load8(X, stride, tb * kTile + lcol, Q, kbeg + part * 8, K, vb);
     for (uint64_t k0 = kbeg; k0 < kend; k0 += kStep) {
-        double v[8];
-        load8(X, stride, ta * kTile + lcol, Q, k0 + part * 8, K, v);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) sA[lcol * kPad + part * 8 + j] = v[j];
+        for (int j = 0; j < 8; ++j) sA[lcol * kPad + part * 8 + j] = va[j];
         if (!same) {
-            load8(X, stride, tb * kTile + lcol, Q, k0 + part * 8, K, v);
             if (mode == 1) {
 #pragma unroll
                 for (int j = 0; j < 8; j += 2) {
-                    const double re = v[j], im = v[j + 1];
-                    v[j] = im;
-                    v[j + 1] = -re;
+                    const double re = vb[j], im = vb[j + 1];
+                    vb[j] = im;
+                    vb[j + 1] = -re;
                 }
             }
 #pragma unroll
-            for (int j = 0; j < 8; ++j) sB[lcol * kPad + part * 8 + j] = v[j];
+            for (int j = 0; j < 8; ++j) sB[lcol * kPad + part * 8 + j] = vb[j];
         }
         __syncthreads();
+        const uint64_t kn = k0 + kStep;
+        if (kn < kend) {
+            load8(X, stride, ta * kTile + lcol, Q, kn + part * 8, K, va);
+            if (!same) load8(X, stride, tb * kTile + lcol, Q, kn + part * 8, K, vb);
+        }
         // A(row = lane % 16, k = lane / 16), B(k = lane / 16, col = lane % 16)
         const int r0 = wr * 32 + (lane & 15), c0 = wc * 32 + (lane & 15);
 #pragma unroll
@@ -212,12 +230,13 @@ void launch_gram(const void *X, bool complex64, int n, int Q, int P, int mode, c
     const GramShape g = gram_shape(n, Q);
     const uint64_t stride = g.K;
     const unsigned blocks = (unsigned)((uint64_t)g.npairs * g.nchunks);
+    const bool xcd = g.nchunks % 8 == 0;
     if (complex64)
         hipLaunchKernelGGL(k_gram<float>, dim3(blocks), dim3(kGramThreads), 0, st, (const float *)X, stride, Q, g.K,
-                           g.kc, g.ntile, g.npairs, mode, partials);
+                           g.kc, g.ntile, g.npairs, mode, xcd, partials);
     else
         hipLaunchKernelGGL(k_gram<double>, dim3(blocks), dim3(kGramThreads), 0, st, (const double *)X, stride, Q, g.K,
-                           g.kc, g.ntile, g.npairs, mode, partials);
+                           g.kc, g.ntile, g.npairs, mode, xcd, partials);
     check_launch();
     const uint64_t entries = (uint64_t)g.npairs * kTile * kTile;
     hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, st, partials, g.npairs,

@@ -502,6 +502,22 @@ __device__ __forceinline__ void prodw_plain(const Regs<CT, T, W> &x, double (&pr
 #define QNG_NO_PRODUCTS 0
 #endif
 constexpr bool kNoProducts = QNG_NO_PRODUCTS != 0;
+
+// Each build names its kernel after its arithmetic, so kernel traces tell them
+// apart: k_sweep_reg (complex products), k_sweep_reg_real (real parts),
+// k_sweep_reg_exact / k_sweep_reg_real_exact (every product in FP64 from FP32
+// registers), k_sweep_reg_states (no products).
+#if QNG_NO_PRODUCTS
+#define QNG_SWEEP_KERNEL k_sweep_reg_states
+#elif QNG_REAL_PRODUCTS && QNG_EXACT_PRODUCTS
+#define QNG_SWEEP_KERNEL k_sweep_reg_real_exact
+#elif QNG_REAL_PRODUCTS
+#define QNG_SWEEP_KERNEL k_sweep_reg_real
+#elif QNG_EXACT_PRODUCTS
+#define QNG_SWEEP_KERNEL k_sweep_reg_exact
+#else
+#define QNG_SWEEP_KERNEL k_sweep_reg
+#endif
 // waves per SIMD the FP32 kernels without products are held to (four: at most
 // 128 VGPRs, a few values spill in the exchanges; three: 130 VGPRs, none)
 #ifndef QNG_STATES_WAVES
@@ -1025,7 +1041,7 @@ __device__ __forceinline__ void tile_sums(const Regs<CT, T, W> &x, double2 *sink
 // with two phi registers it is held to 168 VGPRs (it needs 146; with every
 // product in FP64 a few values spill in the exchanges).
 template <typename R, typename CT, int RB, bool FULL, int W>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNoProducts ? (sizeof(CT) == 4 ? QNG_STATES_WAVES : 3) : W == 1 ? (RB >= 4 ? 1 : 3) : 3, 8))) void k_sweep_reg(const LaunchItem *__restrict__ items, int n_items,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNoProducts ? (sizeof(CT) == 4 ? QNG_STATES_WAVES : 3) : W == 1 ? (RB >= 4 ? 1 : 3) : 3, 8))) void QNG_SWEEP_KERNEL(const LaunchItem *__restrict__ items, int n_items,
                                                         const DevPass *__restrict__ passes,
                                                         const DevOp *__restrict__ ops,
                                                         const DevMap *__restrict__ maps,
@@ -1319,12 +1335,12 @@ void launch_full(const LaunchItem *items, int n_items, uint32_t total_tiles, con
     const size_t smem = smem_bytes<CT>(m);
     static size_t attr_set = 0;
     if (smem > attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_sweep_reg<R, CT, RB, FULL, W>,
+        (void)hipFuncSetAttribute((const void *)QNG_SWEEP_KERNEL<R, CT, RB, FULL, W>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         (void)hipGetLastError();
         attr_set = smem;
     }
-    hipLaunchKernelGGL((k_sweep_reg<R, CT, RB, FULL, W>), dim3(total_tiles), dim3(kThreads), smem, st, items,
+    hipLaunchKernelGGL((QNG_SWEEP_KERNEL<R, CT, RB, FULL, W>), dim3(total_tiles), dim3(kThreads), smem, st, items,
                        n_items, passes, ops, maps, (const void *)mats, (double2 *)partials);
 }
 

@@ -1,4 +1,4 @@
-"""Profiling helper for the fused sweep-pass kernel (k_sweep_reg).
+"""Profiling helper for the fused sweep-pass kernels (k_sweep_reg and its builds).
 
 Two modes:
 
@@ -64,9 +64,11 @@ def _short(name: str) -> str:
 
 
 def _family(name: str) -> str:
-    if "k_sweep_reg" in name:
-        return "sweep"
-    return _short(name)
+    """The kernel's name without template arguments (each build of the sweep
+    kernel has its own name: k_sweep_reg_real_exact, k_sweep_reg_states, ...)."""
+    import re
+    m = re.search(r"(k_\w+)", name)
+    return m.group(1) if m else name[:60]
 
 
 def _pmc(dbs):
@@ -113,13 +115,13 @@ def summarize(args):
         open(args.out, "w").write("\n".join(lines) + "\n")
     elif args.kind == "traffic":
         agg, nd = _pmc(dbs)
-        sw, cp = agg["sweep"], agg["calib"]
+        sw, cp = agg[args.kernel], agg["calib"]
         f_fetch = COPY_BYTES / (cp["FETCH_SIZE"] * 1024) if cp.get("FETCH_SIZE") else None
         f_write = COPY_BYTES / (cp["WRITE_SIZE"] * 1024) if cp.get("WRITE_SIZE") else None
-        n = nd.get("sweep", 1)
+        n = nd.get(args.kernel, 1)
         fetch = sw.get("FETCH_SIZE", 0) * 1024 * (f_fetch or 1) / n
         write = sw.get("WRITE_SIZE", 0) * 1024 * (f_write or 1) / n
-        out = {"kernel": "k_sweep_reg", "title": args.title, "command": cmd, "launches": n,
+        out = {"kernel": args.kernel, "title": args.title, "command": cmd, "launches": n,
                "raw_fetch_kib": sw.get("FETCH_SIZE", 0), "raw_write_kib": sw.get("WRITE_SIZE", 0),
                "calib_fetch_kib": cp.get("FETCH_SIZE"), "calib_write_kib": cp.get("WRITE_SIZE"),
                "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
@@ -128,10 +130,11 @@ def summarize(args):
         json.dump(out, open(args.out, "w"), indent=1)
     else:
         agg, nd = _pmc(dbs)
-        sw = agg["sweep"]
+        sw = agg[args.kernel]
         waves = sw.get("SQ_WAVES", 0) or 1
         lines = [f"# Sweep-kernel counters: {args.title}", "", f"Command: `{cmd}`", "",
-                 f"Launches: {nd.get('sweep', 0)}; values per wave (SQ_WAVES = {waves:.0f})", "",
+                 f"Kernel `{args.kernel}`, launches: {nd.get(args.kernel, 0)}; values per wave "
+                 f"(SQ_WAVES = {waves:.0f})", "",
                  "| counter | per wave |", "|---|---|"]
         for k, v in sorted(sw.items()):
             lines.append(f"| {k} | {v / waves:.1f} |")
@@ -154,6 +157,8 @@ def main():
     s.add_argument("--out", required=True)
     s.add_argument("--title", default="")
     s.add_argument("--command", default="")
+    s.add_argument("--kernel", default="k_sweep_reg_real_exact",
+                   help="traffic / counters: the kernel (name without template arguments)")
     s.add_argument("dbs", nargs="+")
     a = ap.parse_args()
     run(a) if a.mode == "run" else summarize(a)

@@ -20,13 +20,15 @@ def test_more_than_one_gpu_is_refused():
 
 def test_traffic_profile_matches_kernel_source():
     """The committed HBM-traffic counters are used only while they belong to the
-    current sweep-kernel source (SHA-256), else the bench reports null."""
+    current sweep-kernel source (SHA-256) and to the kernel the bench times,
+    else the bench reports null."""
     sys.path.insert(0, ROOT)
     import bench
     prof = json.load(open(os.path.join(ROOT, "profiles", "sweep_pass_cfg3_traffic.json")))
     src = open(os.path.join(ROOT, "paper_2011_02991_amd", "csrc", "sweep_kernels.hip"), "rb").read()
-    same = prof["kernel_sha256"] == hashlib.sha256(src).hexdigest()
-    t = bench.traffic_per_launch()
+    same = prof["kernel_sha256"] == hashlib.sha256(src).hexdigest() and prof.get("kernel") == "k_sweep_reg_real_exact"
+    t = bench.traffic_per_launch(bench.sweep_kernel_name("c64", 0, 1))
     assert (t is not None) == same
+    assert bench.traffic_per_launch("k_sweep_reg_states") is None
     if same:
         assert abs(t - prof["bytes_per_launch"]) <= 1e-6 * prof["bytes_per_launch"]

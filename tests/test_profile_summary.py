@@ -29,15 +29,16 @@ def test_traffic_calibrates_on_first_dispatch_only(tmp_path):
     # step's own 512 MiB clone (k_copy) and small runtime copies follow.
     _db(tmp_path / "fetch.db", "FETCH_SIZE", [
         ("__amd_rocclr_copyBuffer", copy_kib / 2, 1),
-        ("void k_sweep_reg<float, float, 4, true, 2>(...)", 1000.0, 5),
-        ("void k_sweep_reg<float, float, 4, true, 2>(...)", 3000.0, 6),
+        ("void k_sweep_reg_real_exact<float, float, 4, true, 2>(...)", 1000.0, 5),
+        ("void k_sweep_reg_real_exact<float, float, 4, true, 2>(...)", 3000.0, 6),
         ("void k_copy<float>(...)", copy_kib / 2, 7),
         ("__amd_rocclr_copyBuffer", 4.0, 8),
+        ("void k_sweep_reg_states<float, float, 4, true, 2>(...)", 9000.0, 9),
     ])
     _db(tmp_path / "write.db", "WRITE_SIZE", [
         ("__amd_rocclr_copyBuffer", copy_kib, 1),
-        ("void k_sweep_reg<float, float, 4, true, 2>(...)", 2000.0, 5),
-        ("void k_sweep_reg<float, float, 4, true, 2>(...)", 2000.0, 6),
+        ("void k_sweep_reg_real_exact<float, float, 4, true, 2>(...)", 2000.0, 5),
+        ("void k_sweep_reg_real_exact<float, float, 4, true, 2>(...)", 2000.0, 6),
         ("void k_copy<float>(...)", copy_kib, 7),
     ])
     out = tmp_path / "traffic.json"
