@@ -498,9 +498,11 @@ template <typename R> struct Engine {
     }
 
     // From psi at gate position pos: finish the forward pass, lambda = H psi,
-    // E = <psi|lambda>, then the reverse sweep for the gradient.  If keep_psi,
-    // the final state is copied to state(3) before the sweep modifies psi.
-    void energy_grad_unfused(int pos, bool want_grad, void *psi_copy_c128) {
+    // E = <psi|lambda>, then the reverse sweep for the gradient (the fused
+    // passes of the gradient plan when one is set, one kernel per sweep step for
+    // the extended gate set, else one kernel per primitive).  psi_copy_c128
+    // (nullable) receives the final state before the sweep modifies psi.
+    void finish_energy_grad(int pos, bool want_grad, void *psi_copy_c128) {
         const Circuit &c = pb.circ;
         void *psi = state(0), *lam = state(1);
         for (; pos < c.M; ++pos) apply(pos, false, psi, nullptr);
@@ -746,7 +748,7 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
             e.init(in_c128);
             pos = 0;
         }
-        e.energy_grad_unfused(pos, true, spec.psi_out_dev);
+        e.finish_energy_grad(pos, true, spec.psi_out_dev);
         if (spec.host_call || ctx->opt_profile) HIPCHECK(hipStreamSynchronize(st));
         ctx->stats.grad_ms = ms_since(t0);
     } else if (spec.psi_out_dev) {
@@ -755,7 +757,7 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
             e.init(in_c128);
             pos = 0;
         }
-        e.energy_grad_unfused(pos, false, spec.psi_out_dev);
+        e.finish_energy_grad(pos, false, spec.psi_out_dev);
     }
     return res;
 }
@@ -1556,7 +1558,7 @@ qng_status qng_step_batched(qng_ctx *ctx, int32_t B, const qng_circuit *circs, c
                     e.gscratch_bytes = L.gscratch_bytes;
                     e.reg_mode = sweep_reg_mode(ctx, amp);
                 }
-                e.energy_grad_unfused(batch_final_pos(pb.circ), true, nullptr);
+                e.finish_energy_grad(batch_final_pos(pb.circ), true, nullptr);
             }
             for (int b = 0; b < B; ++b) {
                 const int P = pbs[b].circ.P, NP = pbs[b].circ.NP;
