@@ -33,6 +33,42 @@ __device__ __forceinline__ uint64_t insert_two_zeros(uint64_t p, int lo, int hi)
     return insert_zero(insert_zero(p, lo), hi);   // lo < hi
 }
 
+// Loads and stores with the nontemporal hint: a state streamed once through a
+// kernel is not kept in the caches.  Measured on a 2^26 complex64 state, an
+// isolated rotation on a target qubit q >= 4 moves 5.8-6.7 TB/s with the hint
+// against 5.1-6.2 TB/s without (the dip at q = 19-23 was the worst case); for
+// q < 4 the two amplitudes of a pair share cache lines and the plain accesses
+// are faster (5.9 against 5.6 TB/s), so the rotation launchers pick the hint by
+// qubit.  CNOT and CZ, which rewrite only part of each line, and the clone
+// were slower with it (CZ 4.6-5.5 against 6.5-7.0 TB/s) and keep plain
+// accesses; so do the sweep passes, whose reverse tile order relies on the
+// last pass's tiles still being in the caches (3.5 ms against 1.8 ms a pass).
+template <typename V> struct NtVec;
+template <> struct NtVec<double2> { typedef double T __attribute__((ext_vector_type(2))); };
+template <> struct NtVec<float2> { typedef float T __attribute__((ext_vector_type(2))); };
+template <bool NT, typename V> __device__ __forceinline__ V load_amp(const V *p) {
+    if constexpr (NT) {
+        const typename NtVec<V>::T v = __builtin_nontemporal_load((const typename NtVec<V>::T *)p);
+        V o;
+        o.x = v.x;
+        o.y = v.y;
+        return o;
+    } else {
+        return *p;
+    }
+}
+template <bool NT, typename V> __device__ __forceinline__ void store_amp(V *p, V v) {
+    if constexpr (NT) {
+        typename NtVec<V>::T w;
+        w.x = v.x;
+        w.y = v.y;
+        __builtin_nontemporal_store(w, (typename NtVec<V>::T *)p);
+    } else {
+        *p = v;
+    }
+}
+constexpr int kNtMinQubit = 4;
+
 inline unsigned grid_for(uint64_t work) {
     uint64_t g = (work + kBlock - 1) / kBlock;
     if (g < 1) g = 1;
@@ -73,35 +109,35 @@ __global__ void k_copy(const typename Cplx<R>::T *src, typename Cplx<R>::T *dst,
 
 // ------------------------------------------------------------------ gates
 
-template <typename R>
+template <typename R, bool NT = false>
 __device__ __forceinline__ void mat_pair(typename Cplx<R>::T *s, uint64_t i0, uint64_t i1, R ar, R ai, R br, R bi,
                                          R cr, R ci, R dr, R di) {
-    const typename Cplx<R>::T u = s[i0], v = s[i1];
+    const typename Cplx<R>::T u = load_amp<NT>(s + i0), v = load_amp<NT>(s + i1);
     typename Cplx<R>::T o0, o1;
     o0.x = ar * u.x - ai * u.y + br * v.x - bi * v.y;
     o0.y = ar * u.y + ai * u.x + br * v.y + bi * v.x;
     o1.x = cr * u.x - ci * u.y + dr * v.x - di * v.y;
     o1.y = cr * u.y + ci * u.x + dr * v.y + di * v.x;
-    s[i0] = o0;
-    s[i1] = o1;
+    store_amp<NT>(s + i0, o0);
+    store_amp<NT>(s + i1, o1);
 }
 
-template <typename R>
+template <typename R, bool NT>
 __global__ void k_apply_1q(typename Cplx<R>::T *s0, typename Cplx<R>::T *s1, int n, int q, DevMat2 m) {
     const uint64_t npairs = uint64_t(1) << (n - 1);
     const R ar = (R)m.ar, ai = (R)m.ai, br = (R)m.br, bi = (R)m.bi;
     const R cr = (R)m.cr, ci = (R)m.ci, dr = (R)m.dr, di = (R)m.di;
     for (uint64_t p = blockIdx.x * (uint64_t)kBlock + threadIdx.x; p < npairs; p += (uint64_t)gridDim.x * kBlock) {
         const uint64_t i0 = insert_zero(p, q), i1 = i0 | (uint64_t(1) << q);
-        mat_pair<R>(s0, i0, i1, ar, ai, br, bi, cr, ci, dr, di);
-        if (s1) mat_pair<R>(s1, i0, i1, ar, ai, br, bi, cr, ci, dr, di);
+        mat_pair<R, NT>(s0, i0, i1, ar, ai, br, bi, cr, ci, dr, di);
+        if (s1) mat_pair<R, NT>(s1, i0, i1, ar, ai, br, bi, cr, ci, dr, di);
     }
 }
 
 // Same, with the matrix read from device memory (8 doubles, row-major re/im):
 // launches whose arguments do not depend on the angles can be captured once
 // and replayed with new matrices.
-template <typename R>
+template <typename R, bool NT>
 __global__ void k_apply_1q_tab(typename Cplx<R>::T *s0, typename Cplx<R>::T *s1, int n, int q,
                                const double *__restrict__ mt) {
     const uint64_t npairs = uint64_t(1) << (n - 1);
@@ -109,8 +145,8 @@ __global__ void k_apply_1q_tab(typename Cplx<R>::T *s0, typename Cplx<R>::T *s1,
     const R cr = (R)mt[4], ci = (R)mt[5], dr = (R)mt[6], di = (R)mt[7];
     for (uint64_t p = blockIdx.x * (uint64_t)kBlock + threadIdx.x; p < npairs; p += (uint64_t)gridDim.x * kBlock) {
         const uint64_t i0 = insert_zero(p, q), i1 = i0 | (uint64_t(1) << q);
-        mat_pair<R>(s0, i0, i1, ar, ai, br, bi, cr, ci, dr, di);
-        if (s1) mat_pair<R>(s1, i0, i1, ar, ai, br, bi, cr, ci, dr, di);
+        mat_pair<R, NT>(s0, i0, i1, ar, ai, br, bi, cr, ci, dr, di);
+        if (s1) mat_pair<R, NT>(s1, i0, i1, ar, ai, br, bi, cr, ci, dr, di);
     }
 }
 
@@ -200,16 +236,22 @@ __global__ void k_seed_string(const typename Cplx<R>::T *y, typename Cplx<R>::T 
 }
 
 // CNOT(control c, target t): swap amplitudes (x, x ^ 2^t) for x with bit c set and bit t clear.
-template <typename R>
+template <typename R, bool NT>
 __global__ void k_cnot(typename Cplx<R>::T *s0, typename Cplx<R>::T *s1, int n, int c, int t) {
     const uint64_t nq = uint64_t(1) << (n - 2);
     const int lo = c < t ? c : t, hi = c < t ? t : c;
     for (uint64_t p = blockIdx.x * (uint64_t)kBlock + threadIdx.x; p < nq; p += (uint64_t)gridDim.x * kBlock) {
         const uint64_t i0 = insert_two_zeros(p, lo, hi) | (uint64_t(1) << c);
         const uint64_t i1 = i0 | (uint64_t(1) << t);
-        typename Cplx<R>::T u = s0[i0], v = s0[i1];
-        s0[i0] = v; s0[i1] = u;
-        if (s1) { u = s1[i0]; v = s1[i1]; s1[i0] = v; s1[i1] = u; }
+        typename Cplx<R>::T u = load_amp<NT>(s0 + i0), v = load_amp<NT>(s0 + i1);
+        store_amp<NT>(s0 + i0, v);
+        store_amp<NT>(s0 + i1, u);
+        if (s1) {
+            u = load_amp<NT>(s1 + i0);
+            v = load_amp<NT>(s1 + i1);
+            store_amp<NT>(s1 + i0, v);
+            store_amp<NT>(s1 + i1, u);
+        }
     }
 }
 
@@ -231,15 +273,20 @@ __global__ void k_cnot_run(const typename Cplx<R>::T *src, typename Cplx<R>::T *
 }
 
 // CZ(a, b): negate amplitudes with both bits set.
-template <typename R>
+template <typename R, bool NT>
 __global__ void k_cz(typename Cplx<R>::T *s0, typename Cplx<R>::T *s1, int n, int a, int b) {
     const uint64_t nq = uint64_t(1) << (n - 2);
     const int lo = a < b ? a : b, hi = a < b ? b : a;
     for (uint64_t p = blockIdx.x * (uint64_t)kBlock + threadIdx.x; p < nq; p += (uint64_t)gridDim.x * kBlock) {
         const uint64_t i = insert_two_zeros(p, lo, hi) | (uint64_t(1) << a) | (uint64_t(1) << b);
-        typename Cplx<R>::T u = s0[i];
-        u.x = -u.x; u.y = -u.y; s0[i] = u;
-        if (s1) { u = s1[i]; u.x = -u.x; u.y = -u.y; s1[i] = u; }
+        typename Cplx<R>::T u = load_amp<NT>(s0 + i);
+        u.x = -u.x; u.y = -u.y;
+        store_amp<NT>(s0 + i, u);
+        if (s1) {
+            u = load_amp<NT>(s1 + i);
+            u.x = -u.x; u.y = -u.y;
+            store_amp<NT>(s1 + i, u);
+        }
     }
 }
 
@@ -823,13 +870,15 @@ template <typename R> void launch_copy(const void *src, void *dst, int n, hipStr
 }
 
 template <typename R> void launch_apply_1q(void *s0, void *s1, int n, int q, const DevMat2 &m, hipStream_t st) {
-    hipLaunchKernelGGL(k_apply_1q<R>, dim3(grid_for(uint64_t(1) << (n - 1))), dim3(kBlock), 0, st,
+    hipLaunchKernelGGL((q >= kNtMinQubit ? k_apply_1q<R, true> : k_apply_1q<R, false>),
+                       dim3(grid_for(uint64_t(1) << (n - 1))), dim3(kBlock), 0, st,
                        (typename Cplx<R>::T *)s0, (typename Cplx<R>::T *)s1, n, q, m);
     check_launch();
 }
 
 template <typename R> void launch_apply_1q_tab(void *s0, void *s1, int n, int q, const double *m_dev, hipStream_t st) {
-    hipLaunchKernelGGL(k_apply_1q_tab<R>, dim3(grid_for(uint64_t(1) << (n - 1))), dim3(kBlock), 0, st,
+    hipLaunchKernelGGL((q >= kNtMinQubit ? k_apply_1q_tab<R, true> : k_apply_1q_tab<R, false>),
+                       dim3(grid_for(uint64_t(1) << (n - 1))), dim3(kBlock), 0, st,
                        (typename Cplx<R>::T *)s0, (typename Cplx<R>::T *)s1, n, q, m_dev);
     check_launch();
 }
@@ -938,13 +987,15 @@ void launch_cnot_run(const void *src, void *dst, int n, const int *control, cons
 }
 
 template <typename R> void launch_cnot(void *s0, void *s1, int n, int c, int t, hipStream_t st) {
-    hipLaunchKernelGGL(k_cnot<R>, dim3(grid_for(uint64_t(1) << (n - 2))), dim3(kBlock), 0, st,
+    hipLaunchKernelGGL((k_cnot<R, false>),
+                       dim3(grid_for(uint64_t(1) << (n - 2))), dim3(kBlock), 0, st,
                        (typename Cplx<R>::T *)s0, (typename Cplx<R>::T *)s1, n, c, t);
     check_launch();
 }
 
 template <typename R> void launch_cz(void *s0, void *s1, int n, int a, int b, hipStream_t st) {
-    hipLaunchKernelGGL(k_cz<R>, dim3(grid_for(uint64_t(1) << (n - 2))), dim3(kBlock), 0, st,
+    hipLaunchKernelGGL((k_cz<R, false>),
+                       dim3(grid_for(uint64_t(1) << (n - 2))), dim3(kBlock), 0, st,
                        (typename Cplx<R>::T *)s0, (typename Cplx<R>::T *)s1, n, a, b);
     check_launch();
 }
