@@ -93,9 +93,12 @@ typedef enum { QNG_C128 = 0, QNG_C64 = 1 } qng_precision;
  * exp(i theta S/2) = cos(theta/2) + i sin(theta/2) S for the tensor product S
  * of the string's letters, so its column has the generator S and, as S^2 = 1,
  * the diagonal L_ii = 1/4.
- * Circuits with controlled or Pauli-string rotations run on the per-primitive
- * kernels whatever QNG_OPT_FUSION says; qng_plan with fusion, qng_plan_export
- * and qng_step_batched reject them with QNG_E_UNSUPPORTED.
+ * Controlled rotations run on the fused sweep passes like the others (their
+ * control may be any qubit, their target is brought into the pass's tile).
+ * Circuits with Pauli-string rotations sweep one kernel per step instead;
+ * qng_plan with fusion and qng_plan_export reject them with QNG_E_UNSUPPORTED.
+ * qng_step_batched and the derivative-state variant (QNG_OPT_METHOD = 1)
+ * reject both kinds with QNG_E_UNSUPPORTED.
  * Gates act in array order: gates[0] first. */
 typedef struct { int32_t kind, q0, q1, param; } qng_gate;
 
@@ -242,7 +245,10 @@ qng_status qng_plan(const qng_circuit *circ, int fusion, int tile_qubits, qng_pl
  * (CNOT: control), qubit q1 (CNOT target / CZ second qubit, else -1), gate
  * position of the adjoint (or -1), destination of an inner product (or -1),
  * Pauli axis of the inner product or seed (0 X, 1 Y, 2 Z; or -1), tile-qubit
- * mask bits 0..30, bits 31..61}.
+ * mask bits 0..30, bits 31..61}.  A controlled rotation's adjoint row holds
+ * its control in q0 and its target in q1 (as in the gate list); its inner
+ * product and seed rows hold the target in q0 and the control in q1 (the
+ * generator |1><1| on q1 times the axis's Pauli on q0; q1 = -1 for a plain one).
  * sweep = 0: the metric's columns s = 1..P-1 (Sec. 3, Alg. 1 inner loops),
  * destination r*P + s of <lambda|sigma_r|phi>; sweep = 2: the same metric with
  * blocks of two columns s-1, s sharing one lambda sweep (rows keyed by the top

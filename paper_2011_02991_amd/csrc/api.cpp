@@ -446,8 +446,8 @@ template <typename R> struct Engine {
         return pos;
     }
 
-    // Recurrent metric for circuits the fused passes do not take (controlled
-    // and Pauli-string rotations): columns in blocks of up to `width`
+    // Recurrent metric for circuits the fused passes do not take (Pauli-string
+    // rotations): columns in blocks of up to `width`
     // consecutive rotations share one lambda sweep, as in the fused passes --
     // lambda swept back from the top column is the forward state y_r at every
     // rotation r, so the block's lower columns are seeded from it on the way
@@ -618,13 +618,13 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
     const int n = c.n;
     const size_t amp = 2 * sizeof(R);
     const size_t V = (size_t(1) << n) * amp;
-    // controlled and Pauli-string rotations: per-primitive kernels only (the
-    // fused passes implement single-qubit rotations, CNOT and CZ)
-    const bool fused = ctx->opt_fusion != 0 && spec.metric && c.P > 1 && !c.extended();
+    // the fused passes take single-qubit and controlled rotations, CNOT and CZ;
+    // Pauli-string rotations run one kernel per sweep step
+    const bool fused = ctx->opt_fusion != 0 && spec.metric && c.P > 1 && !c.has_strings;
     // derivative-state variant: every column's swept phi register is kept and
     // the metric is their Gram matrix (P + 1 more states)
     const bool states = ctx->opt_method == 1 && spec.metric && c.P > 1;
-    if (states && (!fused || !pb.rot_block.empty()))
+    if (states && (!fused || c.controlled || !pb.rot_block.empty()))
         fail(QNG_E_UNSUPPORTED, "the derivative-state variant takes the fused passes of single-qubit rotations, "
                                 "CNOT and CZ and the full metric");
     const SweepPlan *plan = nullptr;
@@ -658,14 +658,14 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
     }
     std::shared_ptr<const SweepPlan> gplan;
     const bool f64_regs = amp == 16 || ctx->opt_f64_regs;
-    if (ctx->opt_fusion != 0 && spec.grad && c.P > 0 && !c.extended()) {
+    if (ctx->opt_fusion != 0 && spec.grad && c.P > 0 && !c.has_strings) {
         gplan = ctx->sweep_cache.get_gradient(c, ctx->opt_tile, (int)amp, f64_regs);
         scratch = std::max(scratch, fused_gradient_scratch_bytes(*gplan, c.M));
     }
     // circuits the fused passes do not take: one kernel per sweep step, with up
     // to kStepMaxPhi columns per lambda sweep as memory allows (half of what is
     // free, and the context's limit)
-    const bool stepped = ctx->opt_fusion != 0 && c.extended();
+    const bool stepped = ctx->opt_fusion != 0 && c.has_strings;
     int step_width = 0;
     if (stepped && spec.metric && pb.rot_block.empty() && c.P > 1) {
         size_t free_b = 0, total_b = 0;
@@ -1293,8 +1293,7 @@ qng_status qng_plan(const qng_circuit *circ, int fusion, int tile_qubits, qng_pl
         Circuit c = compile_circuit(circ);
         *out = qng_plan_info{};
         out->elements = (int64_t)c.P * (c.P - 1) / 2;
-        if (fusion && c.extended())
-            fail(QNG_E_UNSUPPORTED, "fused sweep passes do not take controlled or Pauli-string rotations");
+        if (fusion && c.has_strings) fail(QNG_E_UNSUPPORTED, "fused sweep passes do not take Pauli-string rotations");
         if (!fusion) {
             for (int s = 1; s < c.P; ++s) out->ops += c.rots[s].pos - c.rots[0].pos + (s);
             out->passes = 0;
@@ -1313,8 +1312,7 @@ qng_status qng_plan_export(const qng_circuit *circ, int tile_qubits, int amp_byt
         if (sweep < 0 || sweep > 2) fail(QNG_E_INVALID_ARG, "sweep must be 0 or 2 (metric) or 1 (gradient)");
         validate_circuit(circ, kMaxQubitsC64);
         Circuit c = compile_circuit(circ);
-        if (c.extended())
-            fail(QNG_E_UNSUPPORTED, "fused sweep passes do not take controlled or Pauli-string rotations");
+        if (c.has_strings) fail(QNG_E_UNSUPPORTED, "fused sweep passes do not take Pauli-string rotations");
         SweepPlan plan = sweep == 1 ? build_gradient_plan(c, tile_qubits, amp_bytes, amp_bytes == 16)
                                     : build_sweep_plan(c, tile_qubits, amp_bytes, 1, amp_bytes == 16, sweep == 2 ? 2 : 1);
         int64_t k = 0;
@@ -1342,25 +1340,34 @@ qng_status qng_plan_export(const qng_circuit *circ, int tile_qubits, int amp_byt
                 for (uint8_t q : hp.tile) mask |= uint64_t(1) << q;
                 for (const DevOp &op : hp.ops) {
                     if (op.type == OP_XPOSE) continue;
-                    if (op.type == OP_SEED) {
-                        emit(cp, pi, mask, 3, op.q0, -1, -1, hp.slot_dest[op.slot], op.axis);
+                    if (op.type == OP_SEED || op.type == OP_CSEED) {
+                        emit(cp, pi, mask, 3, op.q0, op.type == OP_CSEED ? op.q1 : -1, -1, hp.slot_dest[op.slot],
+                             op.axis);
                         continue;
                     }
-                    const bool prod = op.type == OP_PRODROT || op.type == OP_PROD || op.type == OP_ZSUM ||
+                    const bool cprod = op.type == OP_PRODCROT || op.type == OP_PRODC || op.type == OP_PRODCDIAG ||
+                                       op.type == OP_PRODCZ;
+                    const bool prod = cprod || op.type == OP_PRODROT || op.type == OP_PROD || op.type == OP_ZSUM ||
                                       op.type == OP_PRODZ || op.type == OP_PRODDIAG;
                     const bool adj = op.type == OP_ROT || op.type == OP_PRODROT || op.type == OP_CNOT ||
-                                     op.type == OP_CZ || op.type == OP_DIAG || op.type == OP_PRODDIAG;
-                    const int q1 = (op.type == OP_CNOT || op.type == OP_CZ) ? op.q1 : -1;
+                                     op.type == OP_CZ || op.type == OP_DIAG || op.type == OP_PRODDIAG ||
+                                     op.type == OP_CROT || op.type == OP_PRODCROT || op.type == OP_CDIAG ||
+                                     op.type == OP_PRODCDIAG;
                     if (!prod) {
-                        emit(cp, pi, mask, 0, op.q0, q1, op.gate, -1, -1);
+                        // controlled rotations as in the gate list: q0 the control, q1 the target
+                        if (op.type == OP_CROT || op.type == OP_CDIAG)
+                            emit(cp, pi, mask, 0, op.q1, op.q0, op.gate, -1, -1);
+                        else
+                            emit(cp, pi, mask, 0, op.q0, (op.type == OP_CNOT || op.type == OP_CZ) ? op.q1 : -1,
+                                 op.gate, -1, -1);
                         continue;
                     }
                     // one row per active phi register; the adjoint (if any) rides on the last
                     const int nprod = plan.width - op.aux;
                     for (int b = 0; b < nprod; ++b) {
                         const bool last = b + 1 == nprod;
-                        emit(cp, pi, mask, (last && adj) ? 1 : 2, op.q0, -1, (last && adj) ? op.gate : -1,
-                             hp.slot_dest[op.slot + b], op.axis);
+                        emit(cp, pi, mask, (last && adj) ? 1 : 2, op.q0, cprod ? op.q1 : -1,
+                             (last && adj) ? op.gate : -1, hp.slot_dest[op.slot + b], op.axis);
                     }
                 }
             }

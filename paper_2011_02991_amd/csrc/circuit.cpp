@@ -158,6 +158,16 @@ Shear adjoint_shear(int axis, const Mat2 &adj) {
     return Shear{s / (1.0 + c), -s};
 }
 
+PlaneRot adjoint_plane(int axis, const Mat2 &adj) {
+    double s;
+    switch (axis) {
+    case AX_X: s = -adj.b.imag(); break;
+    case AX_Y: s = adj.b.real(); break;
+    default: s = -adj.a.imag(); break;
+    }
+    return PlaneRot{adj.a.real(), s};
+}
+
 std::vector<PauliTerm> compile_hamiltonian(const qng_circuit *c, const qng_pauli_sum *h) {
     std::vector<PauliTerm> out(h->n_terms);
     for (int t = 0; t < h->n_terms; ++t) {

@@ -86,6 +86,12 @@ struct Shear {
     double u, w;
 };
 Shear adjoint_shear(int axis, const Mat2 &adj);
+// The same plane rotation as (c, s) without the negation: a controlled rotation
+// acts on half of the amplitudes only, so a sign on it would not be global.
+struct PlaneRot {
+    double c, s;
+};
+PlaneRot adjoint_plane(int axis, const Mat2 &adj);
 
 // Pauli string in bit-mask form: (sigma psi)[x] = (-i)^{nY} (-1)^{popcount(x & zy)} psi[x ^ flip],
 // with flip = positions of X and Y letters, zy = positions of Z and Y letters

@@ -144,6 +144,11 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
         const Shear sh = adjoint_shear(r.axis, adj[r.pos]);
         mats[(size_t)r.pos * 8 + 0] = sh.u;
         mats[(size_t)r.pos * 8 + 1] = sh.w;
+        if (r.ctrl >= 0) {
+            const PlaneRot pl = adjoint_plane(r.axis, adj[r.pos]);
+            mats[(size_t)r.pos * 8 + 2] = pl.c;
+            mats[(size_t)r.pos * 8 + 3] = pl.s;
+        }
     }
     std::vector<float> mats32(mats.begin(), mats.end());
     char *p = buf.scratch;
@@ -214,11 +219,29 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
     // ---- execute
     void *psi = state(0);
     int pos = 0;
+    // A controlled rotation r has the diagonal element <y_r|(|1><1| on its
+    // control)|y_r> (Sec. 2) instead of a constant: taken once, wherever psi
+    // holds y_r (at its column's seed, or just before the forward pass applies it).
+    std::vector<uint8_t> diag_done((size_t)c.P, 0);
+    auto control_diag = [&](int r) {
+        const Rot &rr = c.rots[r];
+        if (rr.ctrl < 0 || diag_done[r]) return;
+        launch_pauli_prod<R>(psi, psi, n, rr.ctrl, -1, buf.reduce_partials, buf.lraw + 2 * ((size_t)r * c.P + r), st,
+                             rr.ctrl);
+        stats->other_launches += 2;
+        diag_done[r] = 1;
+    };
     // forward gates up to `target`; a run of three or more CNOTs goes through
     // `scratch` (a register free at this point) as one gather and one copy
     auto forward_to = [&](int target, void *scratch) {
         for (; pos < target; ++pos) {
             const qng_gate &g = c.gates[pos];
+            if (g.kind >= QNG_CRX && g.kind <= QNG_CRZ) {
+                control_diag(c.rot_at[pos]);
+                launch_apply_c1q<R>(psi, nullptr, n, g.q0, g.q1, to_dev(fwd[pos]), st);
+                ++stats->other_launches;
+                continue;
+            }
             if (scratch && g.kind == QNG_CNOT) {
                 int ctl[kCnotRunMax], tgt[kCnotRunMax], k = 0;
                 while (pos + k < target && k < kCnotRunMax && c.gates[pos + k].kind == QNG_CNOT) {
@@ -250,7 +273,9 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
                                buf.reduce_partials, buf.traw, st);
         pos = r0.pos + 1;
     } else {
-        launch_pauli_prod<R>(psi, psi, n, c.rots[0].qubit, c.rots[0].axis, buf.reduce_partials, buf.traw, st);
+        launch_pauli_prod<R>(psi, psi, n, c.rots[0].qubit, c.rots[0].axis, buf.reduce_partials, buf.traw, st,
+                             c.rots[0].ctrl);
+        control_diag(0);
     }
     stats->other_launches += 2;
     for (const Group &G : groups) {
@@ -264,9 +289,20 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
             // lower columns of a block are seeded inside its sweep).  When the
             // gate before rotation s-1 is a rotation too, on a third qubit, the
             // same pass applies both.
+            if (rs.ctrl >= 0 || rp.ctrl >= 0) {
+                // a controlled rotation at either end: the forward pass applies
+                // every gate up to y_s, then the column is seeded with its generator
+                forward_to(rs.pos, reg(b, 0));
+                launch_seed<R>(psi, reg(b, 0), xi_of(s, b, W - 1), n, rs.qubit, rs.axis, st, rs.ctrl);
+                launch_pauli_prod<R>(psi, psi, n, rs.qubit, rs.axis, buf.reduce_partials, buf.traw + 2 * s, st,
+                                     rs.ctrl);
+                control_diag(s);
+                stats->other_launches += 3;
+                continue;
+            }
             const int ra = pos < c.M ? c.rot_at[pos] : -1;
-            if (ra >= 0 && pos + 1 == rp.pos && rs.pos == rp.pos + 1 && n >= 3 && c.rots[ra].qubit != rp.qubit &&
-                c.rots[ra].qubit != rs.qubit && rp.qubit != rs.qubit) {
+            if (ra >= 0 && c.rots[ra].ctrl < 0 && pos + 1 == rp.pos && rs.pos == rp.pos + 1 && n >= 3 &&
+                c.rots[ra].qubit != rp.qubit && c.rots[ra].qubit != rs.qubit && rp.qubit != rs.qubit) {
                 launch_advance2_seed<R>(psi, reg(b, 0), xi_of(s, b, W - 1), n, c.rots[ra].qubit,
                                         d_fmats + (size_t)pos * 8,
                                         rp.qubit, d_fmats + (size_t)rp.pos * 8, rs.qubit, rs.axis,
@@ -297,7 +333,8 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
                                             d_maps, d_mats, d_mats32, plan.m, plan.rb, W, st);
             else
                 launch_sweep_pass<R>(d_items + L.item_begin, (int)L.n_items, L.total_tiles, d_passes, d_ops, d_maps,
-                                     d_mats, d_mats32, d_partials, plan.m, plan.rb, reg_mode, W, st, real_products);
+                                     d_mats, d_mats32, d_partials, plan.m, plan.rb, reg_mode, W, st, real_products,
+                                     plan.ctrl);
             if (profile) FCHECK(hipEventRecord(ev[2 * li + 1], st));
             ++stats->sweep_launches;
             stats->sweep_tiles += L.total_tiles;
@@ -382,6 +419,11 @@ void run_fused_gradient(const SweepPlan &g, const Circuit &c, const std::vector<
         const Shear sh = adjoint_shear(r.axis, adj[r.pos]);
         mats[(size_t)r.pos * 8 + 0] = sh.u;
         mats[(size_t)r.pos * 8 + 1] = sh.w;
+        if (r.ctrl >= 0) {
+            const PlaneRot pl = adjoint_plane(r.axis, adj[r.pos]);
+            mats[(size_t)r.pos * 8 + 2] = pl.c;
+            mats[(size_t)r.pos * 8 + 3] = pl.s;
+        }
     }
     std::vector<float> mats32(mats.begin(), mats.end());
     char *p = scratch;
@@ -416,7 +458,7 @@ void run_fused_gradient(const SweepPlan &g, const Circuit &c, const std::vector<
     for (size_t t = 0; t < items.size(); ++t) {
         if (profile) FCHECK(hipEventRecord(ev[2 * t], st));
         launch_sweep_pass<R>(d_items + t, 1, tiles, d_passes, d_ops, d_maps, d_mats, d_mats32, d_partials, g.m, g.rb,
-                             reg_mode, 1, st);
+                             reg_mode, 1, st, false, g.ctrl);
         if (profile) FCHECK(hipEventRecord(ev[2 * t + 1], st));
         const uint32_t nt = task_begin[t + 1] - task_begin[t];
         launch_reduce_tasks(d_tasks + task_begin[t], (int)nt, d_partials, graw, st);

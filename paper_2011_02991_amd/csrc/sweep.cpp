@@ -40,10 +40,16 @@ Event unapply_event(const Circuit &c, int pos) {
     case QNG_RY: e.nq = 1; e.q[0] = g.q0; e.type[0] = TY_Y; break;
     case QNG_RZ: e.nq = 1; e.q[0] = g.q0; e.type[0] = TY_Z; break;
     case QNG_CNOT: e.nq = 2; e.q[0] = g.q0; e.type[0] = TY_Z; e.q[1] = g.q1; e.type[1] = TY_X; break;
+    // controlled rotations: Z-type on the control q0, sigma-type on the target q1
+    case QNG_CRX: e.nq = 2; e.q[0] = g.q0; e.type[0] = TY_Z; e.q[1] = g.q1; e.type[1] = TY_X; break;
+    case QNG_CRY: e.nq = 2; e.q[0] = g.q0; e.type[0] = TY_Z; e.q[1] = g.q1; e.type[1] = TY_Y; break;
+    case QNG_CRZ: e.nq = 2; e.q[0] = g.q0; e.type[0] = TY_Z; e.q[1] = g.q1; e.type[1] = TY_Z; break;
     default: e.nq = 2; e.q[0] = g.q0; e.type[0] = TY_Z; e.q[1] = g.q1; e.type[1] = TY_Z; break;
     }
     return e;
 }
+
+bool is_controlled_gate(int kind) { return kind == QNG_CRX || kind == QNG_CRY || kind == QNG_CRZ; }
 
 Event prod_event(const Circuit &c, int r) {
     Event e{};
@@ -51,6 +57,11 @@ Event prod_event(const Circuit &c, int r) {
     e.nq = 1;
     e.q[0] = c.rots[r].qubit;
     e.type[0] = (uint8_t)c.rots[r].axis;   // AX_X/AX_Y/AX_Z == TY_X/TY_Y/TY_Z
+    if (c.rots[r].ctrl >= 0) {             // generator |1><1|_c (x) sigma_t: Z-type on the control too
+        e.nq = 2;
+        e.q[1] = c.rots[r].ctrl;
+        e.type[1] = TY_Z;
+    }
     e.pos = c.rots[r].pos;
     e.rot = r;
     e.gkind = -1;
@@ -124,9 +135,15 @@ std::vector<Event> gradient_events(const Circuit &c) {
 }
 
 bool executable(const Event &e, const std::vector<uint8_t> &in_tile) {
+    // an X/Y product or seed needs its target in the tile; a Z one runs on any
+    // bit (outside the tile: a tile sum, or for a controlled one a sign from
+    // the tile base); a control may lie anywhere
     if (e.kind == EV_PROD || e.kind == EV_SEED) return e.type[0] == TY_Z || in_tile[e.q[0]];
     switch (e.gkind) {
-    case QNG_CNOT: return in_tile[e.q[1]];
+    case QNG_CNOT:
+    case QNG_CRX:
+    case QNG_CRY:
+    case QNG_CRZ: return in_tile[e.q[1]];
     case QNG_CZ: return in_tile[e.q[0]] || in_tile[e.q[1]];
     default: return in_tile[e.q[0]];
     }
@@ -215,7 +232,8 @@ int choose_and_emit(const std::vector<Event> &ev, std::vector<uint8_t> &done, st
                 if (done[idx] || added >= w) continue;
                 const Event &e = ev[idx];
                 if (bl.ready(e) && !executable(e, cand)) {
-                    const int need = (e.kind == EV_UNAPPLY && e.gkind == QNG_CNOT) ? e.q[1] : e.q[0];
+                    const int need =
+                        (e.kind == EV_UNAPPLY && (e.gkind == QNG_CNOT || is_controlled_gate(e.gkind))) ? e.q[1] : e.q[0];
                     if (!cand[need]) { cand[need] = 1; ++added; }
                 }
                 bl.block(e);
@@ -259,7 +277,9 @@ int needs_register(const Event &e, const std::vector<int> &local) {
     switch (e.gkind) {
     case QNG_RX:
     case QNG_RY: return local[e.q[0]];
-    case QNG_CNOT: return local[e.q[1]];
+    case QNG_CNOT:
+    case QNG_CRX:
+    case QNG_CRY: return local[e.q[1]];
     default: return -1;
     }
 }
@@ -406,7 +426,11 @@ HostPass make_pass(const Circuit &c, const SlotDest &sd, const std::vector<Event
             op.gate = -1;
             if (e.kind == EV_SEED) {
                 const int q = e.q[0];
-                op.type = OP_SEED;
+                op.type = e.nq == 2 ? OP_CSEED : OP_SEED;
+                if (e.nq == 2) {
+                    op.q1 = (uint8_t)e.q[1];
+                    op.b1 = loc_of_qubit(e.q[1]);
+                }
                 op.slot = (uint16_t)hp.slot_dest.size();
                 hp.slot_dest.push_back((int32_t)(sd.t_base + sd.col0 + e.sb));
                 op.axis = e.type[0];
@@ -423,7 +447,14 @@ HostPass make_pass(const Circuit &c, const SlotDest &sd, const std::vector<Event
                 op.q0 = (uint8_t)q;
                 const bool fuse = k + 1 < order.size() && ev[order[k + 1]].kind == EV_UNAPPLY &&
                                   ev[order[k + 1]].pos == e.pos;
-                if (local[q] < 0) {
+                if (e.nq == 2) {
+                    // controlled: target in the tile (executable), control anywhere
+                    op.b0 = loc_of_qubit(q);
+                    op.q1 = (uint8_t)e.q[1];
+                    op.b1 = loc_of_qubit(e.q[1]);
+                    if (e.type[0] == TY_Z) op.type = fuse ? OP_PRODCDIAG : OP_PRODCZ;
+                    else op.type = fuse ? OP_PRODCROT : OP_PRODC;
+                } else if (local[q] < 0) {
                     op.type = OP_ZSUM;
                 } else if (e.type[0] == TY_Z) {
                     op.b0 = loc_of_qubit(q);
@@ -453,6 +484,13 @@ HostPass make_pass(const Circuit &c, const SlotDest &sd, const std::vector<Event
                 } else if (g.kind == QNG_RZ) {
                     op.type = OP_DIAG;
                     op.b0 = loc_of_qubit(g.q0);
+                } else if (is_controlled_gate(g.kind)) {
+                    op.type = g.kind == QNG_CRZ ? OP_CDIAG : OP_CROT;
+                    op.axis = g.kind == QNG_CRX ? TY_X : g.kind == QNG_CRY ? TY_Y : TY_Z;
+                    op.q0 = (uint8_t)g.q1;            // target
+                    op.q1 = (uint8_t)g.q0;            // control
+                    op.b0 = loc_of_qubit(g.q1);
+                    op.b1 = loc_of_qubit(g.q0);
                 } else {
                     op.type = OP_ROT;
                     op.axis = g.kind == QNG_RX ? TY_X : TY_Y;
@@ -544,9 +582,17 @@ void flatten(SweepPlan &plan, const Circuit &c) {
                 if (op.type == OP_CNOT) has_cnot = true;
                 if (op.type == OP_XPOSE) op.aux += (int32_t)map_base;
                 op.type = device_opcode(op);
-                const uint64_t hb = uint64_t(1) << device_handler(op.type);
-                op.hlo = (uint32_t)hb;
-                op.hhi = (uint32_t)(hb >> 32);
+                const int h2 = device_handler2(op.type);
+                if (h2 >= 0) {
+                    op.hlo = op.hhi = 0;
+                    op.h2 = 1u << h2;
+                    plan.ctrl = true;
+                } else {
+                    const uint64_t hb = uint64_t(1) << device_handler(op.type);
+                    op.hlo = (uint32_t)hb;
+                    op.hhi = (uint32_t)(hb >> 32);
+                    op.h2 = 0;
+                }
                 plan.dev_ops.push_back(op);
             }
             for (const DevMap &mp : hp.maps) plan.dev_maps.push_back(mp);
@@ -630,6 +676,17 @@ uint8_t device_opcode(const DevOp &op) {
     case OP_ZSUM: return OPC_ZSUM;
     case OP_XPOSE: return OPC_XPOSE;
     case OP_SEED: return OPC_SEED;
+    case OP_CROT:
+    case OP_PRODCROT:
+    case OP_PRODC: {
+        if (!reg0) fail(QNG_E_DEVICE, "device op: controlled X/Y operation off the registers (internal)");
+        const int base = op.type == OP_CROT ? OPC_CROT_X : op.type == OP_PRODCROT ? OPC_PRODCROT_X : OPC_PRODC_X;
+        return (uint8_t)(base + (op.axis == 0 ? 0 : 4) + j);
+    }
+    case OP_CDIAG: return OPC_CDIAG;
+    case OP_PRODCDIAG: return OPC_PRODCDIAG;
+    case OP_PRODCZ: return OPC_PRODCZ;
+    case OP_CSEED: return OPC_CSEED;
     default: fail(QNG_E_DEVICE, "device op: unknown kind (internal)");
     }
     return 0;
@@ -661,6 +718,16 @@ int device_handler(uint8_t c) {
     if (c == OPC_SEED) return HB_SEED;
     fail(QNG_E_DEVICE, "device handler: unknown op code (internal)");
     return 0;
+}
+
+int device_handler2(uint8_t c) {
+    // the controlled-rotation codes map onto the second word in order
+    if (c < OPC_CROT_X) return -1;
+    if (c > OPC_CSEED) fail(QNG_E_DEVICE, "device handler: unknown op code (internal)");
+    static_assert(OPC_CSEED - OPC_CROT_X == HB2_CSEED && OPC_PRODC_Y - OPC_CROT_X == HB2_PRODC_Y &&
+                      OPC_CDIAG - OPC_CROT_X == HB2_CDIAG,
+                  "second handler word follows the op codes");
+    return c - OPC_CROT_X;
 }
 
 void append_structure_key(const Circuit &c, std::vector<int32_t> &key) {

@@ -54,8 +54,17 @@ enum : uint8_t {
     OP_PRODZ = 7,     // Z inner product on location b0
     OP_PRODDIAG = 8,  // Z inner product on location b0, then the RZ adjoint there
     OP_XPOSE = 9,     // exchange through LDS to the thread mapping `aux`
-    OP_SEED = 10      // column block: phi register `aux` <- sigma lambda (sigma on qubit q0, location b0),
+    OP_SEED = 10,     // column block: phi register `aux` <- sigma lambda (sigma on qubit q0, location b0),
                       // then <lambda|phi> into the op's slot
+    // controlled rotations (generator |1><1|_c (x) sigma_t): target qubit q0 at
+    // location b0, control qubit q1 at location b1
+    OP_CROT = 11,     // X/Y controlled rotation adjoint, target on register position b0
+    OP_PRODCROT = 12, // X/Y inner product <A|K|B>, then the adjoint
+    OP_PRODC = 13,    // X/Y inner product <A|K|B>
+    OP_CDIAG = 14,    // CRZ adjoint (target at any location in the tile)
+    OP_PRODCDIAG = 15,   // Z inner product <A|K|B>, then the CRZ adjoint
+    OP_PRODCZ = 16,   // Z inner product <A|K|B>
+    OP_CSEED = 17     // column block: phi register `aux` <- K lambda, then <lambda|phi> into the slot
 };
 
 // Device op codes.  In the flattened device images (SweepPlan::dev_ops and
@@ -85,7 +94,18 @@ enum : uint8_t {
     OPC_CZ = 72,
     OPC_ZSUM = 73,
     OPC_XPOSE = 74,
-    OPC_SEED = 75
+    OPC_SEED = 75,
+    // controlled rotations (second handler word, HB2_* below)
+    OPC_CROT_X = 76,          // + j
+    OPC_CROT_Y = 80,          // + j
+    OPC_PRODCROT_X = 84,      // + j
+    OPC_PRODCROT_Y = 88,      // + j
+    OPC_PRODC_X = 92,         // + j
+    OPC_PRODC_Y = 96,         // + j
+    OPC_CDIAG = 100,
+    OPC_PRODCDIAG = 101,
+    OPC_PRODCZ = 102,
+    OPC_CSEED = 103
 };
 
 // Location of a local bit in the current thread mapping: a register position
@@ -107,7 +127,8 @@ struct DevOp {  // 32 bytes
     int32_t aux;      // OP_XPOSE: mapping index; inner products: first active phi register;
                       // OP_SEED: the phi register seeded
     uint32_t hlo, hhi;   // device images: one-hot handler bit (HB_* below), low and high word
-    uint32_t pad0, pad1;
+    uint32_t h2;         // device images: one-hot bit of the controlled-rotation handlers (HB2_*), or 0
+    uint32_t pad1;
 };
 
 struct DevPass {  // 64 bytes, read through a pointer with scalar loads
@@ -159,6 +180,22 @@ enum : int {
     HB_SEED = 62
 };
 int device_handler(uint8_t opcode);
+// Handler bits of the controlled-rotation ops, in the second handler word that
+// only the kernels built for circuits with controlled rotations test.
+enum : int {
+    HB2_CROT_X = 0,          // + j
+    HB2_CROT_Y = 4,          // + j
+    HB2_PRODCROT_X = 8,      // + j
+    HB2_PRODCROT_Y = 12,     // + j
+    HB2_PRODC_X = 16,        // + j
+    HB2_PRODC_Y = 20,        // + j
+    HB2_CDIAG = 24,
+    HB2_PRODCDIAG = 25,
+    HB2_PRODCZ = 26,
+    HB2_CSEED = 27
+};
+// -1 for an op code of the first word
+int device_handler2(uint8_t opcode);
 static_assert(sizeof(DevOp) == 32, "DevOp layout");
 static_assert(sizeof(DevMap) == 16, "DevMap layout");
 
@@ -190,6 +227,7 @@ struct SweepPlan {
     std::vector<DevOp> dev_ops;
     std::vector<DevMap> dev_maps;
     int rb = 0;                         // register bits per thread (all passes)
+    bool ctrl = false;                  // some op is a controlled rotation (kernels with the second handler word)
     int64_t transposes = 0;
     std::vector<int64_t> col_pass_begin;   // per column: index of its first pass in dev_passes
     int64_t total_passes = 0, total_ops = 0, max_slots = 0, load_maps = 0;
@@ -280,31 +318,35 @@ enum RegMode : int { REG_F32 = 0, REG_F64 = 1, REG_F32_EXACT = 2 };
 
 // Kernel launchers (sweep_kernels.hip).
 // mats64 / mats32: per gate position 8 values, of which the first two are the
-// shear parameters (u, w) of the gate's adjoint (circuit.hpp, adjoint_shear),
-// in FP64 and FP32; the kernel reads the table of its register precision.
+// shear parameters (u, w) of the gate's adjoint (circuit.hpp, adjoint_shear)
+// and, for a controlled rotation, the third and fourth its plane rotation
+// (c, s) (adjoint_plane), in FP64 and FP32; the kernel reads the table of its
+// register precision.
 // width: phi registers per item (the plan's column-block width).
 // real_products: keep only the real parts of the metric's inner products
 // (sweep_kernels_real.hip, or sweep_kernels_real_exact.hip for REG_F32_EXACT;
 // the step needs Re G alone).
+// ctrl: the plan holds controlled rotations (SweepPlan::ctrl): the kernels with
+// the second handler word run.
 template <typename R>
 void launch_sweep_pass(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
                        const DevOp *ops, const DevMap *maps, const double *mats64, const float *mats32,
                        double *partials, int m, int rb, int reg_mode, int width, hipStream_t st,
-                       bool real_products = false);
+                       bool real_products = false, bool ctrl = false);
 template <typename R>
 void launch_sweep_pass_real(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
                             const DevOp *ops, const DevMap *maps, const double *mats64, const float *mats32,
-                            double *partials, int m, int rb, int reg_mode, int width, hipStream_t st);
+                            double *partials, int m, int rb, int reg_mode, int width, hipStream_t st, bool ctrl);
 // The REG_F32_EXACT kernels (sweep_kernels_exact.hip: the same source built
 // with every product in FP64), complex64 storage only.
 void launch_sweep_pass_exact(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
                              const DevOp *ops, const DevMap *maps, const float *mats32, double *partials, int m,
-                             int rb, int width, hipStream_t st);
+                             int rb, int width, hipStream_t st, bool ctrl);
 // The REG_F32_EXACT kernels with the real parts of the metric's inner products
 // only (sweep_kernels_real_exact.hip).
 void launch_sweep_pass_real_exact(const LaunchItem *items, int n_items, uint32_t total_tiles,
                                   const DevPass *passes, const DevOp *ops, const DevMap *maps, const float *mats32,
-                                  double *partials, int m, int rb, int width, hipStream_t st);
+                                  double *partials, int m, int rb, int width, hipStream_t st, bool ctrl);
 void launch_reduce_tasks(const ReduceTask *tasks, int n_tasks, const double *partials, double *results,
                          hipStream_t st);
 // The passes without inner products (sweep_kernels_states.hip): lambda and

@@ -686,6 +686,7 @@ struct OpD {
     uint32_t w0, w1;
     int32_t gate, aux;
     uint64_t hf;   // one-hot handler bit (sweep.hpp, HB_*)
+    uint32_t h2;   // one-hot bit of the second word (HB2_*), or 0
     __device__ __forceinline__ int type() const { return (int)(w0 & 0xffu); }
     __device__ __forceinline__ uint8_t b0() const { return (uint8_t)((w0 >> 8) & 0xffu); }
     __device__ __forceinline__ uint8_t b1() const { return (uint8_t)((w0 >> 16) & 0xffu); }
@@ -697,7 +698,7 @@ struct OpD {
 __device__ __forceinline__ OpD load_op(const DevOp *p) {
     const uint4 v = *reinterpret_cast<const uint4 *>(p);
     const uint4 h = *(reinterpret_cast<const uint4 *>(p) + 1);
-    return OpD{v.x, v.y, (int32_t)v.z, (int32_t)v.w, (uint64_t)h.x | ((uint64_t)h.y << 32)};
+    return OpD{v.x, v.y, (int32_t)v.z, (int32_t)v.w, (uint64_t)h.x | ((uint64_t)h.y << 32), h.z};
 }
 
 constexpr uint64_t hbit(int b) { return uint64_t(1) << b; }
@@ -948,6 +949,114 @@ __device__ __forceinline__ void seed_phi(Regs<CT, T, W> &x, int axis, uint8_t lo
 #undef QNG_SEED_XY
 }
 
+// ------------------------------------------------------- controlled rotations
+//
+// A controlled rotation acts where its control bit is 1.  The control may sit
+// at any location (register, thread or tile-base bit), so its value per
+// register is a mask `on` (bit i for register i).  The adjoint is the plane
+// rotation (c, s) on the same pairs of reals as the plain rotation's, taken as
+// (1, 0) where the control is 0: there it leaves the values exactly as they
+// are.  (Three shears cannot take the sign trick of the plain rotations here,
+// since a sign on half of the amplitudes is not common to the registers.)  The
+// generator |1><1|_c (x) sigma enters an inner product as lambda with its
+// amplitudes of control 0 set to zero.
+
+#define QNG_PLANE(A, B, C, S)                       \
+    do {                                            \
+        const CT a_ = A, b_ = B;                    \
+        A = fmadd(C, a_, (S) * b_);                 \
+        B = fmadd(C, b_, -(S) * a_);                \
+    } while (0)
+
+template <int J, int AX, int T, typename CT>
+__device__ __forceinline__ void crot_xy1(CT (&re)[T], CT (&im)[T], uint32_t on, CT c, CT s) {
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        if (i & (1 << J)) continue;
+        const int k = i | (1 << J);   // the control (not bit J) is the same for i and k
+        const bool o = (on >> i) & 1u;
+        const CT ci = sel<CT>(o, c, (CT)1), si = sel<CT>(o, s, (CT)0);
+        if (AX == 0) {
+            QNG_PLANE(re[i], im[k], ci, si);
+            QNG_PLANE(re[k], im[i], ci, si);
+        } else {
+            QNG_PLANE(re[i], re[k], ci, si);
+            QNG_PLANE(im[i], im[k], ci, si);
+        }
+    }
+}
+template <int J, int AX, int T, typename CT, int W>
+__device__ __forceinline__ void crot_xy(Regs<CT, T, W> &x, uint32_t on, CT c, CT s) {
+    crot_xy1<J, AX, T, CT>(x.ar, x.ai, on, c, s);
+#pragma unroll
+    for (int b = 0; b < W; ++b) crot_xy1<J, AX, T, CT>(x.br[b], x.bi[b], on, c, s);
+}
+
+// CRZ adjoint: where the control is 1, (re, im) rotated by (c, s) for target
+// bit 0 and by (c, -s) for target bit 1 (`one`: mask of the target bit)
+template <int T, typename CT, int W>
+__device__ __forceinline__ void cdiag(Regs<CT, T, W> &x, uint32_t on, uint32_t one, CT c, CT s) {
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        const bool o = (on >> i) & 1u;
+        const CT ci = sel<CT>(o, c, (CT)1);
+        const CT si = sel<CT>(o, sel<CT>((one >> i) & 1u, -s, s), (CT)0);
+        QNG_PLANE(x.ar[i], x.ai[i], ci, si);
+#pragma unroll
+        for (int b = 0; b < W; ++b) QNG_PLANE(x.br[b][i], x.bi[b][i], ci, si);
+    }
+}
+
+// The tile with lambda's amplitudes of control 0 set to zero and those with
+// bit `neg` set negated (f in {0, 1, -1}: exact in any precision); the phi
+// registers as they are.  A value copy: the products read it, the tile itself
+// is left in place.
+template <int T, typename CT, int W>
+__device__ __forceinline__ Regs<CT, T, W> masked_lambda(const Regs<CT, T, W> &x, uint32_t on, uint32_t neg) {
+    Regs<CT, T, W> y;
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        const CT f = sel<CT>((on >> i) & 1u, sel<CT>((neg >> i) & 1u, (CT)-1, (CT)1), (CT)0);
+        y.ar[i] = x.ar[i] * f;
+        y.ai[i] = x.ai[i] * f;
+#pragma unroll
+        for (int b = 0; b < W; ++b) {
+            y.br[b][i] = x.br[b][i];
+            y.bi[b][i] = x.bi[b][i];
+        }
+    }
+    return y;
+}
+
+constexpr uint32_t h2bit(int b) { return uint32_t(1) << b; }
+constexpr uint32_t crot_bits(int j) {
+    return h2bit(HB2_CROT_X + j) | h2bit(HB2_CROT_Y + j) | h2bit(HB2_PRODCROT_X + j) | h2bit(HB2_PRODCROT_Y + j) |
+           h2bit(HB2_PRODC_X + j) | h2bit(HB2_PRODC_Y + j);
+}
+
+// Controlled X/Y operations with the target on register bit J: products of
+// the generator (alone or before the adjoint), adjoints
+template <int J, int RB, int T, typename CT, int W>
+__device__ __forceinline__ void crot_handlers(Regs<CT, T, W> &x, uint32_t h2, uint32_t on, CT c, CT s,
+                                              double2 *sink, double2 *red, int slot, int fa, int tid) {
+    if constexpr (J < RB) {
+        if (h2 & (h2bit(HB2_PRODCROT_X + J) | h2bit(HB2_PRODC_X + J))) {
+            const Regs<CT, T, W> y = masked_lambda<T, CT, W>(x, on, 0u);
+            double pr[W], pi[W];
+            prodw_xy<J, 0, T, CT, W>(y, pr, pi);
+            row_reduce_store<W>(sink, red, slot, fa, tid, pr, pi);
+        }
+        if (h2 & (h2bit(HB2_PRODCROT_Y + J) | h2bit(HB2_PRODC_Y + J))) {
+            const Regs<CT, T, W> y = masked_lambda<T, CT, W>(x, on, 0u);
+            double pr[W], pi[W];
+            prodw_xy<J, 1, T, CT, W>(y, pr, pi);
+            row_reduce_store<W>(sink, red, slot, fa, tid, pr, pi);
+        }
+        if (h2 & (h2bit(HB2_PRODCROT_X + J) | h2bit(HB2_CROT_X + J))) crot_xy<J, 0, T, CT, W>(x, on, c, s);
+        if (h2 & (h2bit(HB2_PRODCROT_Y + J) | h2bit(HB2_CROT_Y + J))) crot_xy<J, 1, T, CT, W>(x, on, c, s);
+    }
+}
+
 // One register of the tile through the exchange buffer, from mapping `from`
 // to mapping `to`.  With RECOMPUTE the slots are recomputed for every
 // register from an opaque copy of the thread index (the kernels with two phi
@@ -1040,7 +1149,7 @@ __device__ __forceinline__ void tile_sums(const Regs<CT, T, W> &x, double2 *sink
 // it by itself (114 VGPRs; 158 with every product in FP64) and gets no bound;
 // with two phi registers it is held to 168 VGPRs (it needs 146; with every
 // product in FP64 a few values spill in the exchanges).
-template <typename R, typename CT, int RB, bool FULL, int W>
+template <typename R, typename CT, int RB, bool FULL, int W, bool CTRL>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNoProducts ? (sizeof(CT) == 4 ? QNG_STATES_WAVES : 3) : W == 1 ? (RB >= 4 ? 1 : 3) : 3, 8))) void QNG_SWEEP_KERNEL(const LaunchItem *__restrict__ items, int n_items,
                                                         const DevPass *__restrict__ passes,
                                                         const DevOp *__restrict__ ops,
@@ -1209,6 +1318,48 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNoPro
                 QNG_STORE_PRODS();
             }
         }
+        if constexpr (CTRL && !kNoProducts) {
+            // controlled rotations (second handler word): the control's value per
+            // register, the adjoint's plane rotation from the table's third and
+            // fourth entries
+            const uint32_t h2 = op.h2;
+            if (h2) {
+                const uint32_t on = loc_mask<T>(op.b1(), op.q1(), tid, base);
+                const CT c = mrow[2], s = mrow[3];
+                const int slot = op.slot();
+                if (h2 & crot_bits(0)) crot_handlers<0, RB, T, CT, W>(x, h2, on, c, s, sink, red, slot, fa, tid);
+                if (h2 & crot_bits(1)) crot_handlers<1, RB, T, CT, W>(x, h2, on, c, s, sink, red, slot, fa, tid);
+                if (h2 & crot_bits(2)) crot_handlers<2, RB, T, CT, W>(x, h2, on, c, s, sink, red, slot, fa, tid);
+                if (h2 & crot_bits(3)) crot_handlers<3, RB, T, CT, W>(x, h2, on, c, s, sink, red, slot, fa, tid);
+                if (h2 & (h2bit(HB2_CDIAG) | h2bit(HB2_PRODCDIAG) | h2bit(HB2_PRODCZ))) {
+                    const uint32_t one = loc_mask<T>(op.b0(), op.q0(), tid, base);
+                    if (h2 & (h2bit(HB2_PRODCDIAG) | h2bit(HB2_PRODCZ))) {
+                        const Regs<CT, T, W> y = masked_lambda<T, CT, W>(x, on, one);
+                        double pr[W], pi[W];
+                        prodw_plain<T, CT, W>(y, pr, pi);
+                        row_reduce_store<W>(sink, red, slot, fa, tid, pr, pi);
+                    }
+                    if (h2 & (h2bit(HB2_CDIAG) | h2bit(HB2_PRODCDIAG))) cdiag<T, CT, W>(x, on, one, c, s);
+                }
+                if constexpr (W > 1) {
+                    if (h2 & h2bit(HB2_CSEED)) {
+                        // phi register 0 <- K lambda: sigma on the target, then the
+                        // amplitudes of control 0 cleared; <lambda|phi> into the slot
+                        seed_phi<0, RB, T, CT, W>(x, op.w0 >> 24, op.b0(), op.q0(), tid, base);
+#pragma unroll
+                        for (int i = 0; i < T; ++i) {
+                            const CT f = sel<CT>((on >> i) & 1u, (CT)1, (CT)0);
+                            x.br[0][i] *= f;
+                            x.bi[0][i] *= f;
+                        }
+                        double pr, pi;
+                        prod_plain<T, CT>(x.ar, x.ai, x.br[0], x.bi[0], pr, pi);
+                        row_store(sink, red, slot, tid, pr, pi);
+                        if (pass_zsum) tile_sums<T, CT, W, 0, 1>(x, sink, zs, tid, Sr, Si);
+                    }
+                }
+            }
+        }
         if (hf & (hbit(HB_XPOSE) | hbit(HB_CZ) | hbit(HB_ZSUM) | hbit(HB_SEED))) {
             if (hf & hbit(HB_CZ)) {
                 const uint32_t neg = loc_mask<T>(op.b0(), op.q0(), tid, base) & loc_mask<T>(op.b1(), op.q1(), tid, base);
@@ -1329,19 +1480,35 @@ template <typename CT> size_t smem_bytes(int m) {
     return xbuf_bytes<typename Amp<CT>::T>(m) + (kNoProducts ? 0 : (size_t)kLdsTailEntries * sizeof(double2));
 }
 
-template <typename R, typename CT, int RB, bool FULL, int W>
+template <typename R, typename CT, int RB, bool FULL, int W, bool CTRL>
 void launch_full(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes, const DevOp *ops,
                  const DevMap *maps, const CT *mats, double *partials, int m, hipStream_t st) {
     const size_t smem = smem_bytes<CT>(m);
     static size_t attr_set = 0;
     if (smem > attr_set) {
-        (void)hipFuncSetAttribute((const void *)QNG_SWEEP_KERNEL<R, CT, RB, FULL, W>,
+        (void)hipFuncSetAttribute((const void *)QNG_SWEEP_KERNEL<R, CT, RB, FULL, W, CTRL>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         (void)hipGetLastError();
         attr_set = smem;
     }
-    hipLaunchKernelGGL((QNG_SWEEP_KERNEL<R, CT, RB, FULL, W>), dim3(total_tiles), dim3(kThreads), smem, st, items,
-                       n_items, passes, ops, maps, (const void *)mats, (double2 *)partials);
+    hipLaunchKernelGGL((QNG_SWEEP_KERNEL<R, CT, RB, FULL, W, CTRL>), dim3(total_tiles), dim3(kThreads), smem, st,
+                       items, n_items, passes, ops, maps, (const void *)mats, (double2 *)partials);
+}
+
+// The kernels with the second handler word (controlled rotations) are built
+// apart, so plans without controlled rotations keep the plain op loop.
+template <typename R, typename CT, int RB, bool FULL, int W>
+void launch_ctrl(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes, const DevOp *ops,
+                 const DevMap *maps, const CT *mats, double *partials, int m, bool ctrl, hipStream_t st) {
+    if constexpr (!kNoProducts) {
+        if (ctrl) {
+            launch_full<R, CT, RB, FULL, W, true>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m,
+                                                  st);
+            return;
+        }
+    }
+    if (ctrl) throw hipErrorInvalidValue;
+    launch_full<R, CT, RB, FULL, W, false>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st);
 }
 
 // Every pass of a launch has the launch's tile width m (one plan, or one
@@ -1350,36 +1517,38 @@ void launch_full(const LaunchItem *items, int n_items, uint32_t total_tiles, con
 // 16 amplitudes per thread (registers of at least 11 qubits).
 template <typename R, typename CT, int RB>
 void launch_rb(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes, const DevOp *ops,
-               const DevMap *maps, const CT *mats, double *partials, int m, int width, hipStream_t st) {
+               const DevMap *maps, const CT *mats, double *partials, int m, int width, bool ctrl, hipStream_t st) {
     const bool full = m - RB == 8;
     if (width == 2) {
         if constexpr (RB >= 3) {
             if (full) {
-                launch_full<R, CT, RB, true, 2>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st);
+                launch_ctrl<R, CT, RB, true, 2>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m,
+                                                ctrl, st);
                 return;
             }
         }
         throw hipErrorInvalidValue;
     }
     if (full)
-        launch_full<R, CT, RB, true, 1>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st);
+        launch_ctrl<R, CT, RB, true, 1>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, ctrl, st);
     else
-        launch_full<R, CT, RB, false, 1>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st);
+        launch_ctrl<R, CT, RB, false, 1>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, ctrl, st);
 }
 
 template <typename R, typename CT>
 void launch_ct(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes, const DevOp *ops,
-               const DevMap *maps, const CT *mats, double *partials, int m, int rb, int width, hipStream_t st) {
+               const DevMap *maps, const CT *mats, double *partials, int m, int rb, int width, bool ctrl,
+               hipStream_t st) {
     switch (rb) {
-    case 1: launch_rb<R, CT, 1>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, width, st); break;
-    case 2: launch_rb<R, CT, 2>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, width, st); break;
-    case 3: launch_rb<R, CT, 3>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, width, st); break;
+    case 1: launch_rb<R, CT, 1>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, width, ctrl, st); break;
+    case 2: launch_rb<R, CT, 2>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, width, ctrl, st); break;
+    case 3: launch_rb<R, CT, 3>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, width, ctrl, st); break;
     case 4:
         // FP64 registers stop at 8 amplitudes per thread: at 16 the kernel
         // needs 178-226 VGPRs (two waves per SIMD) and measured 1.8-2.2x slower
         // per pass at n = 26
         if constexpr (sizeof(CT) == 4) {
-            launch_rb<R, CT, 4>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, width, st);
+            launch_rb<R, CT, 4>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, width, ctrl, st);
             break;
         }
         [[fallthrough]];
@@ -1396,9 +1565,9 @@ void launch_sweep_pass_states(const LaunchItem *items, int n_items, uint32_t tot
                               int rb, int width, hipStream_t st) {
     if (n_items <= 0 || total_tiles == 0) return;
     if constexpr (sizeof(R) == 8)
-        launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, nullptr, m, rb, width, st);
+        launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, nullptr, m, rb, width, false, st);
     else
-        launch_ct<R, float>(items, n_items, total_tiles, passes, ops, maps, mats32, nullptr, m, rb, width, st);
+        launch_ct<R, float>(items, n_items, total_tiles, passes, ops, maps, mats32, nullptr, m, rb, width, false, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) throw e;
 }
@@ -1411,9 +1580,9 @@ template void launch_sweep_pass_states<float>(const LaunchItem *, int, uint32_t,
 #elif QNG_REAL_PRODUCTS && QNG_EXACT_PRODUCTS
 void launch_sweep_pass_real_exact(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
                                   const DevOp *ops, const DevMap *maps, const float *mats32, double *partials, int m,
-                                  int rb, int width, hipStream_t st) {
+                                  int rb, int width, hipStream_t st, bool ctrl) {
     if (n_items <= 0 || total_tiles == 0) return;
-    launch_ct<float, float>(items, n_items, total_tiles, passes, ops, maps, mats32, partials, m, rb, width, st);
+    launch_ct<float, float>(items, n_items, total_tiles, passes, ops, maps, mats32, partials, m, rb, width, ctrl, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) throw e;
 }
@@ -1421,16 +1590,16 @@ void launch_sweep_pass_real_exact(const LaunchItem *items, int n_items, uint32_t
 template <typename R>
 void launch_sweep_pass_real(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
                             const DevOp *ops, const DevMap *maps, const double *mats64, const float *mats32,
-                            double *partials, int m, int rb, int reg_mode, int width, hipStream_t st) {
+                            double *partials, int m, int rb, int reg_mode, int width, hipStream_t st, bool ctrl) {
     if (n_items <= 0 || total_tiles == 0) return;
     if constexpr (sizeof(R) == 8) {
         (void)reg_mode;
-        launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, partials, m, rb, width, st);
+        launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, partials, m, rb, width, ctrl, st);
     } else {
         if (reg_mode == REG_F64)
-            launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, partials, m, rb, width, st);
+            launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, partials, m, rb, width, ctrl, st);
         else if (reg_mode == REG_F32)
-            launch_ct<R, float>(items, n_items, total_tiles, passes, ops, maps, mats32, partials, m, rb, width, st);
+            launch_ct<R, float>(items, n_items, total_tiles, passes, ops, maps, mats32, partials, m, rb, width, ctrl, st);
         else
             throw hipErrorInvalidValue;
     }
@@ -1439,36 +1608,37 @@ void launch_sweep_pass_real(const LaunchItem *items, int n_items, uint32_t total
 }
 template void launch_sweep_pass_real<double>(const LaunchItem *, int, uint32_t, const DevPass *, const DevOp *,
                                              const DevMap *, const double *, const float *, double *, int, int, int,
-                                             int, hipStream_t);
+                                             int, hipStream_t, bool);
 template void launch_sweep_pass_real<float>(const LaunchItem *, int, uint32_t, const DevPass *, const DevOp *,
                                             const DevMap *, const double *, const float *, double *, int, int, int,
-                                            int, hipStream_t);
+                                            int, hipStream_t, bool);
 #elif !QNG_EXACT_PRODUCTS
 template <typename R>
 void launch_sweep_pass(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
                        const DevOp *ops, const DevMap *maps, const double *mats64, const float *mats32,
-                       double *partials, int m, int rb, int reg_mode, int width, hipStream_t st, bool real_products) {
+                       double *partials, int m, int rb, int reg_mode, int width, hipStream_t st, bool real_products,
+                       bool ctrl) {
     if (n_items <= 0 || total_tiles == 0) return;
     if (real_products) {
         if (reg_mode == REG_F32_EXACT)
             launch_sweep_pass_real_exact(items, n_items, total_tiles, passes, ops, maps, mats32, partials, m, rb,
-                                         width, st);
+                                         width, st, ctrl);
         else
             launch_sweep_pass_real<R>(items, n_items, total_tiles, passes, ops, maps, mats64, mats32, partials, m,
-                                      rb, reg_mode, width, st);
+                                      rb, reg_mode, width, st, ctrl);
         return;
     }
     if constexpr (sizeof(R) == 8) {
         (void)reg_mode;
-        launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, partials, m, rb, width, st);
+        launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, partials, m, rb, width, ctrl, st);
     } else {
         if (reg_mode == REG_F64)
-            launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, partials, m, rb, width, st);
+            launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, partials, m, rb, width, ctrl, st);
         else if (reg_mode == REG_F32_EXACT)
             launch_sweep_pass_exact(items, n_items, total_tiles, passes, ops, maps, mats32, partials, m, rb, width,
-                                    st);
+                                    st, ctrl);
         else
-            launch_ct<R, float>(items, n_items, total_tiles, passes, ops, maps, mats32, partials, m, rb, width, st);
+            launch_ct<R, float>(items, n_items, total_tiles, passes, ops, maps, mats32, partials, m, rb, width, ctrl, st);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) throw e;
@@ -1485,16 +1655,16 @@ void launch_reduce_tasks(const ReduceTask *tasks, int n_tasks, const double *par
 
 template void launch_sweep_pass<double>(const LaunchItem *, int, uint32_t, const DevPass *, const DevOp *,
                                         const DevMap *, const double *, const float *, double *, int, int, int, int,
-                                        hipStream_t, bool);
+                                        hipStream_t, bool, bool);
 template void launch_sweep_pass<float>(const LaunchItem *, int, uint32_t, const DevPass *, const DevOp *,
                                        const DevMap *, const double *, const float *, double *, int, int, int, int,
-                                       hipStream_t, bool);
+                                       hipStream_t, bool, bool);
 #else
 void launch_sweep_pass_exact(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
                              const DevOp *ops, const DevMap *maps, const float *mats32, double *partials, int m,
-                             int rb, int width, hipStream_t st) {
+                             int rb, int width, hipStream_t st, bool ctrl) {
     if (n_items <= 0 || total_tiles == 0) return;
-    launch_ct<float, float>(items, n_items, total_tiles, passes, ops, maps, mats32, partials, m, rb, width, st);
+    launch_ct<float, float>(items, n_items, total_tiles, passes, ops, maps, mats32, partials, m, rb, width, ctrl, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) throw e;
 }

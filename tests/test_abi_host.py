@@ -108,17 +108,25 @@ def test_validate_pauli_string_rotations(qng):
     assert e.value.name == "QNG_E_INVALID_ARG"
 
 
-def test_controlled_rotations_not_planned_for_fused_passes(qng):
-    """Controlled and Pauli-string rotations: the per-primitive plan counts
-    them; the fused-pass planner and its export reject them (QNG_E_UNSUPPORTED)."""
-    for pr in (W.controlled_layers(6, 2, 4, 23), W.string_layers(6, 2, 4, 24)):
-        c = _circ(qng, pr)
-        info = qng.plan(c, fusion=0)
-        assert info["elements"] == pr.n_params * (pr.n_params - 1) // 2
-        for call in (lambda: qng.plan(c, fusion=1), lambda: qng.plan_export(c)):
-            with pytest.raises(qng.QNGError) as e:
-                call()
-            assert e.value.name == "QNG_E_UNSUPPORTED"
+def test_fused_planner_takes_controlled_rotations_not_strings(qng):
+    """Controlled rotations are planned onto the fused passes (every element
+    once); Pauli-string rotations: the per-primitive plan counts them, the
+    fused-pass planner and its export reject them (QNG_E_UNSUPPORTED)."""
+    pr = W.controlled_layers(6, 2, 4, 23)
+    c = _circ(qng, pr)
+    P = pr.n_params
+    for fusion in (0, 1):
+        assert qng.plan(c, fusion=fusion)["elements"] == P * (P - 1) // 2
+    assert qng.plan(c, fusion=1)["passes"] > 0
+    assert len(qng.plan_export(c)) > 0
+    pr = W.string_layers(6, 2, 4, 24)
+    c = _circ(qng, pr)
+    info = qng.plan(c, fusion=0)
+    assert info["elements"] == pr.n_params * (pr.n_params - 1) // 2
+    for call in (lambda: qng.plan(c, fusion=1), lambda: qng.plan_export(c)):
+        with pytest.raises(qng.QNGError) as e:
+            call()
+        assert e.value.name == "QNG_E_UNSUPPORTED"
 
 
 def test_validate_two_qubit_gate_same_qubit(qng):

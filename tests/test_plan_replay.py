@@ -7,6 +7,11 @@ applying its operations, in order, to the whole register.  These tests replay
 the exported plan that way with the oracle's own gate and Pauli routines and
 compare the resulting G and T with the oracle's definition-based values; they
 also check that every operation is executable in its pass's tile.
+
+Controlled rotations (generator |1><1| on the control times the Pauli on the
+target, diagonal 1/4 Prob(control = 1), Sec. 2) are replayed the same way: an
+inner-product or seed row names the control in q1, an adjoint row is the
+gate's own adjoint from the gate list.
 """
 import numpy as np
 import pytest
@@ -24,6 +29,45 @@ def qng():
     return q
 
 
+def generator_of(gates, k):
+    """(target, control or -1, axis) of the rotation at gate position k."""
+    kind, q0, q1 = (int(v) for v in gates[k, :3])
+    if kind >= W.CRX:
+        return q1, q0, kind - W.CRX
+    return q0, -1, kind
+
+
+def apply_generator(n, q, ctl, axis, v):
+    """K v for K = sigma_q (ctl < 0) or |1><1|_ctl (x) sigma_q."""
+    w = oracle.apply_pauli_letter(n, q, LETTER[axis], v)
+    if ctl >= 0:
+        w = w * ((np.arange(2 ** n) >> ctl) & 1)
+    return w
+
+
+def diagonal(n, ys, gates, rot_pos):
+    """L_ss of every rotation: 1/4, or 1/4 <y_s|(|1><1| on the control)|y_s>."""
+    d = np.full(len(rot_pos), 0.25, dtype=np.complex128)
+    for s, k in enumerate(rot_pos):
+        _, ctl, _ = generator_of(gates, k)
+        if ctl >= 0:
+            d[s] = 0.25 * np.sum(np.abs(ys[s][((np.arange(2 ** n) >> ctl) & 1) == 1]) ** 2)
+    return d
+
+
+def check_adjoint_row(gates, g, q0, q1, inside):
+    gk = int(gates[g, 0])
+    if gk == W.CNOT:
+        assert inside(q1) and int(gates[g, 2]) == q1
+    elif gk == W.CZ:
+        assert inside(q0) or inside(q1)
+    elif gk >= W.CRX:
+        # control anywhere, target in the tile; rows as in the gate list
+        assert inside(q1) and int(gates[g, 1]) == q0 and int(gates[g, 2]) == q1
+    else:
+        assert inside(q0) and int(gates[g, 1]) == q0
+
+
 def replay(qng, pr, tile_qubits, prec="c128"):
     circ = qng.Circuit.from_problem(pr)
     rows = qng.plan_export(circ, tile_qubits, prec)
@@ -36,8 +80,8 @@ def replay(qng, pr, tile_qubits, prec="c128"):
     def unapply(state, pos):
         return oracle.apply_gate(n, gates[pos], neg, state)
 
-    def prod(a, b, q, axis):
-        return np.vdot(a, oracle.apply_pauli_letter(n, q, LETTER[axis], b))
+    def prod(a, b, q, axis, ctl=-1):
+        return np.vdot(a, apply_generator(n, q, ctl, axis, b))
 
     # states just before each rotation
     ys = []
@@ -58,10 +102,9 @@ def replay(qng, pr, tile_qubits, prec="c128"):
     for r in rows:
         cols.setdefault(int(r[0]), []).append(r)
     for s, ops in cols.items():
-        q_s = int(gates[rot_pos[s], 1])
-        ax_s = int(gates[rot_pos[s], 0])
+        q_s, c_s, ax_s = generator_of(gates, rot_pos[s])
         lam = ys[s].copy()
-        phi = oracle.apply_pauli_letter(n, q_s, LETTER[ax_s], ys[s])
+        phi = apply_generator(n, q_s, c_s, ax_s, ys[s])
         for r in ops:
             kind, q0, q1, g, dest, axis = (int(v) for v in r[2:8])
             mask = int(r[8]) | (int(r[9]) << 31)
@@ -72,28 +115,23 @@ def replay(qng, pr, tile_qubits, prec="c128"):
                 assert axis == 2 or inside(q0)
                 rr, ss = divmod(dest, P)
                 assert ss == s and rr < s and not seen[rr, ss]
+                assert (q0, q1, axis) == generator_of(gates, rot_pos[rr])
                 seen[rr, ss] = True
-                Lraw[rr, ss] = prod(lam, phi, q0, axis)
+                Lraw[rr, ss] = prod(lam, phi, q0, axis, q1)
                 if kind == KIND_PROD_ADJ:
                     assert rot_of_pos[g] == rr and inside(q0)
                     lam, phi = unapply(lam, g), unapply(phi, g)
             else:
                 assert kind == KIND_ADJ
-                gk = int(gates[g, 0])
-                if gk == W.CNOT:
-                    assert inside(q1) and int(gates[g, 2]) == q1
-                elif gk == W.CZ:
-                    assert inside(q0) or inside(q1)
-                else:
-                    assert inside(q0) and int(gates[g, 1]) == q0
+                check_adjoint_row(gates, g, q0, q1, inside)
                 lam, phi = unapply(lam, g), unapply(phi, g)
     # every element r < s evaluated exactly once
     assert seen.sum() == P * (P - 1) // 2
     assert np.all(np.triu(seen, 1) == seen)
-    # assemble G from the recurrence (L_rs = <lam|sigma_r|phi>/4, T_s = (i/2)<y_s|sigma_s|y_s>)
-    T = np.array([0.5j * prod(ys[s], ys[s], int(gates[rot_pos[s], 1]), int(gates[rot_pos[s], 0])) for s in range(P)])
+    # assemble G from the recurrence (L_rs = <lam|K_r|phi>/4, T_s = (i/2)<y_s|K_s|y_s>)
+    T = np.array([0.5j * np.vdot(ys[s], apply_generator(n, *generator_of(gates, rot_pos[s]), ys[s])) for s in range(P)])
     Lb = 0.25 * Lraw
-    L = np.triu(Lb, 1) + np.triu(Lb, 1).conj().T + 0.25 * np.eye(P)
+    L = np.triu(Lb, 1) + np.triu(Lb, 1).conj().T + np.diag(diagonal(n, ys, gates, rot_pos))
     Gb = L - np.outer(T.conj(), T)
     perm = gates[rot_pos, 3]
     G = np.empty_like(Gb)
@@ -157,8 +195,7 @@ def replay_blocks(qng, pr, tile_qubits, prec="c128"):
     rot_pos = [k for k in range(len(gates)) if gates[k, 3] >= 0]
     rot_of_pos = {k: r for r, k in enumerate(rot_pos)}
     neg = -pr.theta
-    letter = lambda s: LETTER[int(gates[rot_pos[s], 0])]
-    qubit = lambda s: int(gates[rot_pos[s], 1])
+    gen = lambda s: generator_of(gates, rot_pos[s])
     ys = []
     psi = np.zeros(2 ** n, dtype=np.complex128)
     psi[0] = 1
@@ -179,7 +216,7 @@ def replay_blocks(qng, pr, tile_qubits, prec="c128"):
     assert sorted(blocks) == list(range(P - 1, 0, -2))[::-1]
     for s, ops in blocks.items():
         lam = ys[s].copy()
-        phis = {s: oracle.apply_pauli_letter(n, qubit(s), letter(s), ys[s])}
+        phis = {s: apply_generator(n, *gen(s), ys[s])}
         Traw[s] = np.vdot(ys[s], phis[s])
         for r in ops:
             kind, q0, q1, g, dest, axis = (int(v) for v in r[2:8])
@@ -187,28 +224,31 @@ def replay_blocks(qng, pr, tile_qubits, prec="c128"):
             inside = lambda q: (mask >> q) & 1
             if kind == KIND_SEED:
                 sb = dest - P * P
-                assert sb == s - 1 and sb not in phis and q0 == qubit(sb) and LETTER[axis] == letter(sb)
+                assert sb == s - 1 and sb not in phis and (q0, q1, axis) == gen(sb)
                 assert axis == 2 or inside(q0)
-                phis[sb] = oracle.apply_pauli_letter(n, q0, LETTER[axis], lam)
+                phis[sb] = apply_generator(n, q0, q1, axis, lam)
                 Traw[sb] = np.vdot(lam, phis[sb])
                 continue
             if kind in (KIND_PROD, KIND_PROD_ADJ):
                 assert axis == 2 or inside(q0)
                 rr, ss = divmod(dest, P)
                 assert ss in (s - 1, s) and ss in phis and rr < ss and not seen[rr, ss]
+                assert (q0, q1, axis) == gen(rr)
                 seen[rr, ss] = True
-                Lraw[rr, ss] = np.vdot(lam, oracle.apply_pauli_letter(n, q0, LETTER[axis], phis[ss]))
+                Lraw[rr, ss] = np.vdot(lam, apply_generator(n, q0, q1, axis, phis[ss]))
                 if kind == KIND_PROD:
                     continue
                 assert rot_of_pos[g] == rr and inside(q0)
+            else:
+                check_adjoint_row(gates, g, q0, q1, inside)
             lam = oracle.apply_gate(n, gates[g], neg, lam)
             for k in phis:
                 phis[k] = oracle.apply_gate(n, gates[g], neg, phis[k])
     assert seen.sum() == P * (P - 1) // 2
     T = 0.5j * Traw[1:]
     Lb = 0.25 * Lraw
-    L = np.triu(Lb, 1) + np.triu(Lb, 1).conj().T + 0.25 * np.eye(P)
-    T0 = 0.5j * np.vdot(ys[0], oracle.apply_pauli_letter(n, qubit(0), letter(0), ys[0]))
+    L = np.triu(Lb, 1) + np.triu(Lb, 1).conj().T + np.diag(diagonal(n, ys, gates, rot_pos))
+    T0 = 0.5j * np.vdot(ys[0], apply_generator(n, *gen(0), ys[0]))
     Tall = np.concatenate([[T0], T])
     Gb = L - np.outer(Tall.conj(), Tall)
     perm = gates[rot_pos, 3]
@@ -283,13 +323,14 @@ def replay_gradient(qng, pr, tile_qubits, prec="c128"):
         inside = lambda q: (mask >> q) & 1
         if kind in (KIND_PROD, KIND_PROD_ADJ):
             assert axis == 2 or inside(q0)
-            assert not seen[dest]
+            assert not seen[dest] and (q0, q1, axis) == generator_of(gates, rot_pos[dest])
             seen[dest] = True
-            graw[dest] = np.vdot(lam, oracle.apply_pauli_letter(n, q0, LETTER[axis], phi))
+            graw[dest] = np.vdot(lam, apply_generator(n, q0, q1, axis, phi))
             if kind == KIND_PROD_ADJ:
                 assert rot_of_pos[g] == dest
                 lam, phi = oracle.apply_gate(n, gates[g], neg, lam), oracle.apply_gate(n, gates[g], neg, phi)
         else:
+            check_adjoint_row(gates, g, q0, q1, inside)
             lam, phi = oracle.apply_gate(n, gates[g], neg, lam), oracle.apply_gate(n, gates[g], neg, phi)
     assert seen.all()
     grad = np.empty(P)
@@ -317,3 +358,57 @@ def test_gradient_plan_replay_random_circuits(qng, seed):
     grad = replay_gradient(qng, pr, 5)
     _, want = oracle.energy_grad(pr)
     np.testing.assert_allclose(grad, want, atol=1e-12)
+
+
+# ---------------------------------------------------------------- controlled rotations
+
+
+def controlled_cases():
+    cases = [W.controlled_circuit(7, 50, 300 + k, n_terms=5) for k in range(6)]
+    for k, pr in enumerate(cases):
+        if k % 2:
+            pr.in_state = W.random_state(7, 310 + k)
+    cases[3] = W.permute_params(cases[3], 313)
+    cases.append(W.controlled_layers(8, 2, 5, 320))
+    # controls outside the tile of 5 qubits, targets inside and outside
+    cases.append(W.controlled_layers(9, 2, 5, 321))
+    return cases
+
+
+@pytest.mark.parametrize("idx", range(8))
+def test_plan_replay_controlled(qng, idx):
+    pr = controlled_cases()[idx]
+    assert (pr.gates[:, 0] >= W.CRX).any()
+    G, T, max_tile, rows = replay(qng, pr, 5)
+    Gw, Tw = oracle.metric(pr)
+    np.testing.assert_allclose(G, Gw, atol=1e-13)
+    np.testing.assert_allclose(T, Tw, atol=1e-13)
+    # some controlled inner product ran with its control outside the tile
+    ctl_rows = rows[(rows[:, 2] != KIND_ADJ) & (rows[:, 4] >= 0)]
+    outside = [r for r in ctl_rows if not ((int(r[8]) | (int(r[9]) << 31)) >> int(r[4])) & 1]
+    if idx == 7:
+        assert outside
+
+
+@pytest.mark.parametrize("idx", range(8))
+def test_block_plan_replay_controlled(qng, idx):
+    pr = controlled_cases()[idx]
+    G, T, rows = replay_blocks(qng, pr, 5)
+    Gw, Tw = oracle.metric(pr)
+    np.testing.assert_allclose(G, Gw, atol=1e-13)
+    np.testing.assert_allclose(T, Tw, atol=1e-13)
+
+
+@pytest.mark.parametrize("idx", [0, 1, 6, 7])
+def test_gradient_plan_replay_controlled(qng, idx):
+    pr = controlled_cases()[idx]
+    grad = replay_gradient(qng, pr, 5)
+    _, want = oracle.energy_grad(pr)
+    np.testing.assert_allclose(grad, want, atol=1e-12)
+
+
+def test_plan_export_rejects_strings(qng):
+    pr = W.string_circuit(6, 30, 330)
+    with pytest.raises(qng.QNGError) as e:
+        qng.plan_export(qng.Circuit.from_problem(pr), 5)
+    assert e.value.name == "QNG_E_UNSUPPORTED"
