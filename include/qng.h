@@ -93,12 +93,17 @@ typedef enum { QNG_C128 = 0, QNG_C64 = 1 } qng_precision;
  * exp(i theta S/2) = cos(theta/2) + i sin(theta/2) S for the tensor product S
  * of the string's letters, so its column has the generator S and, as S^2 = 1,
  * the diagonal L_ii = 1/4.
- * Controlled rotations run on the fused sweep passes like the others (their
- * control may be any qubit, their target is brought into the pass's tile).
- * Circuits with Pauli-string rotations sweep one kernel per step instead;
- * qng_plan with fusion and qng_plan_export reject them with QNG_E_UNSUPPORTED.
- * qng_step_batched and the derivative-state variant (QNG_OPT_METHOD = 1)
- * reject both kinds with QNG_E_UNSUPPORTED.
+ * With fusion on (QNG_OPT_FUSION = 1), controlled rotations run on the fused
+ * sweep passes like the others (their control may be any qubit, their target
+ * is brought into the pass's tile), and every Pauli-string rotation is
+ * rewritten as the same unitary made of fixed basis rotations, CNOTs onto its
+ * lowest qubit and an RZ there that carries its parameter (the state, and so
+ * G, T, E and the gradient, are the same functions of theta), which the fused
+ * passes take too; a string with no letter (a global phase) keeps the circuit
+ * on one kernel per sweep step.  With fusion off, one kernel per primitive
+ * with the string kernels.  qng_plan_export rejects circuits with strings,
+ * qng_step_batched both kinds, and the derivative-state variant
+ * (QNG_OPT_METHOD = 1) controlled rotations, with QNG_E_UNSUPPORTED.
  * Gates act in array order: gates[0] first. */
 typedef struct { int32_t kind, q0, q1, param; } qng_gate;
 

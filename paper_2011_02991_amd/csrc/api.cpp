@@ -236,9 +236,13 @@ struct Problem {
 inline size_t param_map_ints(const Circuit &c) { return (size_t)4 * c.P + c.NP + 1; }
 inline size_t rot_ctrl_offset(const Circuit &c) { return (size_t)3 * c.P + c.NP + 1; }
 
-Problem make_problem(const qng_circuit *c, const double *theta, const qng_pauli_sum *h) {
+// lower: rewrite Pauli-string rotations as fixed rotations, CNOTs and an RZ
+// (lower_strings) so that the fused passes take the circuit; asked for by the
+// entry points that sweep when fusion is on.
+Problem make_problem(const qng_circuit *c, const double *theta, const qng_pauli_sum *h, bool lower = false) {
     Problem p;
     p.circ = compile_circuit(c);
+    if (lower && p.circ.has_strings && strings_lowerable(p.circ)) p.circ = lower_strings(p.circ);
     p.fwd.resize(p.circ.M);
     p.adj.resize(p.circ.M);
     for (const Rot &r : p.circ.rots) {
@@ -246,6 +250,12 @@ Problem make_problem(const qng_circuit *c, const double *theta, const qng_pauli_
         p.adj[r.pos] = adjoint(p.fwd[r.pos]);
         p.param_of.push_back(r.param);
     }
+    for (int pos = 0; pos < p.circ.M; ++pos)
+        if (p.circ.is_fixed_rotation(pos)) {
+            const int kind = p.circ.gates[pos].kind;
+            p.fwd[pos] = rotation(kind == QNG_RX ? AX_X : kind == QNG_RY ? AX_Y : AX_Z, p.circ.fixed_angle[pos]);
+            p.adj[pos] = adjoint(p.fwd[pos]);
+        }
     const int P = p.circ.P, NP = p.circ.NP;
     p.param_map = p.param_of;
     std::vector<int> count(NP + 1, 0);
@@ -500,7 +510,7 @@ template <typename R> struct Engine {
     // From psi at gate position pos: finish the forward pass, lambda = H psi,
     // E = <psi|lambda>, then the reverse sweep for the gradient (the fused
     // passes of the gradient plan when one is set, one kernel per sweep step for
-    // the extended gate set, else one kernel per primitive).  psi_copy_c128
+    // Pauli-string rotations left as they are, else one kernel per primitive).  psi_copy_c128
     // (nullable) receives the final state before the sweep modifies psi.
     void finish_energy_grad(int pos, bool want_grad, void *psi_copy_c128) {
         const Circuit &c = pb.circ;
@@ -807,7 +817,7 @@ void energy_grad_dev_call(qng_ctx *ctx, const qng_circuit *circ, const void *in_
     validate_hamiltonian(circ, ham);
     if (!E_dev || (circ->n_params > 0 && !grad_dev)) fail(QNG_E_INVALID_ARG, "output is NULL");
     reset_stats(ctx);
-    Problem pb = make_problem(circ, theta, ham);
+    Problem pb = make_problem(circ, theta, ham, ctx->opt_fusion != 0);
     dispatch(prec, [&](auto tag) {
         using R = decltype(tag);
         CallSpec spec;
@@ -1293,7 +1303,11 @@ qng_status qng_plan(const qng_circuit *circ, int fusion, int tile_qubits, qng_pl
         Circuit c = compile_circuit(circ);
         *out = qng_plan_info{};
         out->elements = (int64_t)c.P * (c.P - 1) / 2;
-        if (fusion && c.has_strings) fail(QNG_E_UNSUPPORTED, "fused sweep passes do not take Pauli-string rotations");
+        if (fusion && c.has_strings) {
+            if (!strings_lowerable(c))
+                fail(QNG_E_UNSUPPORTED, "fused sweep passes do not take Pauli-string rotations without letters");
+            c = lower_strings(c);
+        }
         if (!fusion) {
             for (int s = 1; s < c.P; ++s) out->ops += c.rots[s].pos - c.rots[0].pos + (s);
             out->passes = 0;
@@ -1312,7 +1326,9 @@ qng_status qng_plan_export(const qng_circuit *circ, int tile_qubits, int amp_byt
         if (sweep < 0 || sweep > 2) fail(QNG_E_INVALID_ARG, "sweep must be 0 or 2 (metric) or 1 (gradient)");
         validate_circuit(circ, kMaxQubitsC64);
         Circuit c = compile_circuit(circ);
-        if (c.has_strings) fail(QNG_E_UNSUPPORTED, "fused sweep passes do not take Pauli-string rotations");
+        if (c.has_strings)
+            fail(QNG_E_UNSUPPORTED, "plans of circuits with Pauli-string rotations run on a rewritten gate list "
+                                    "and are not exported");
         SweepPlan plan = sweep == 1 ? build_gradient_plan(c, tile_qubits, amp_bytes, amp_bytes == 16)
                                     : build_sweep_plan(c, tile_qubits, amp_bytes, 1, amp_bytes == 16, sweep == 2 ? 2 : 1);
         int64_t k = 0;
@@ -1395,7 +1411,7 @@ qng_status qng_metric(qng_ctx *ctx, const qng_circuit *circ, const double *in_st
         if (circ->n_params > 0 && !G_out) fail(QNG_E_INVALID_ARG, "G_out is NULL");
         check_in_state_host(circ->n_qubits, in_state);
         reset_stats(ctx);
-        Problem pb = make_problem(circ, theta, nullptr);
+        Problem pb = make_problem(circ, theta, nullptr, ctx->opt_fusion != 0);
         apply_metric_settings(ctx, pb);
         const int NP = pb.circ.NP;
         dispatch(prec, [&](auto tag) {
@@ -1425,7 +1441,7 @@ qng_status qng_energy_grad(qng_ctx *ctx, const qng_circuit *circ, const double *
         if (!E_out || (circ->n_params > 0 && !grad_out)) fail(QNG_E_INVALID_ARG, "output is NULL");
         check_in_state_host(circ->n_qubits, in_state);
         reset_stats(ctx);
-        Problem pb = make_problem(circ, theta, ham);
+        Problem pb = make_problem(circ, theta, ham, ctx->opt_fusion != 0);
         const int P = pb.circ.P;
         dispatch(prec, [&](auto tag) {
             using R = decltype(tag);
@@ -1459,7 +1475,7 @@ qng_status qng_step(qng_ctx *ctx, const qng_circuit *circ, const double *in_stat
         if (circ->n_params > 0 && !dtheta_out) fail(QNG_E_INVALID_ARG, "dtheta_out is NULL");
         check_in_state_host(circ->n_qubits, in_state);
         reset_stats(ctx);
-        Problem pb = make_problem(circ, theta, ham);
+        Problem pb = make_problem(circ, theta, ham, ctx->opt_fusion != 0);
         apply_metric_settings(ctx, pb);
         const int P = pb.circ.P, NP = pb.circ.NP;
         std::vector<double> G(2 * (size_t)NP * NP + 2), graw(2 * (size_t)P + 2), e(2), grad(NP + 1);
@@ -1624,7 +1640,7 @@ qng_status qng_metric_dev(qng_ctx *ctx, const qng_circuit *circ, const void *in_
         validate_theta(circ, theta);
         if (circ->n_params > 0 && !G_dev) fail(QNG_E_INVALID_ARG, "G_dev is NULL");
         reset_stats(ctx);
-        Problem pb = make_problem(circ, theta, nullptr);
+        Problem pb = make_problem(circ, theta, nullptr, ctx->opt_fusion != 0);
         apply_metric_settings(ctx, pb);
         const int NP = pb.circ.NP;
         dispatch(prec, [&](auto tag) {
@@ -1674,7 +1690,7 @@ qng_status qng_energy_grad_from_state_dev(qng_ctx *ctx, const qng_circuit *circ,
         validate_hamiltonian(circ, ham);
         if (!psi_dev || (circ->n_params > 0 && !grad_dev)) fail(QNG_E_INVALID_ARG, "pointer is NULL");
         reset_stats(ctx);
-        Problem pb = make_problem(circ, theta, ham);
+        Problem pb = make_problem(circ, theta, ham, ctx->opt_fusion != 0);
         const int P = pb.circ.P;
         dispatch(prec, [&](auto tag) {
             using R = decltype(tag);
@@ -1730,7 +1746,7 @@ qng_status qng_step_dev(qng_ctx *ctx, const qng_circuit *circ, const void *in_st
         if (tikhonov < 0) fail(QNG_E_INVALID_ARG, "tikhonov < 0");
         if (circ->n_params > 0 && !dtheta_dev) fail(QNG_E_INVALID_ARG, "dtheta_dev is NULL");
         reset_stats(ctx);
-        Problem pb = make_problem(circ, theta, ham);
+        Problem pb = make_problem(circ, theta, ham, ctx->opt_fusion != 0);
         apply_metric_settings(ctx, pb);
         const int NP = pb.circ.NP;
         hipStream_t st = ctx->stream;

@@ -131,6 +131,66 @@ Circuit compile_circuit(const qng_circuit *c) {
     return k;
 }
 
+bool strings_lowerable(const Circuit &c) {
+    for (const Rot &r : c.rots)
+        if (r.string >= 0 && (r.flip | r.zy) == 0) return false;
+    return true;
+}
+
+Circuit lower_strings(const Circuit &c) {
+    Circuit k;
+    k.n = c.n;
+    k.NP = c.NP;
+    k.shared = c.shared;
+    k.controlled = c.controlled;
+    k.lowered = true;
+    const double half_pi = 2.0 * std::atan(1.0);
+    auto push = [&](int kind, int q0, int q1, int param, double angle) {
+        k.gates.push_back(qng_gate{kind, q0, q1, param});
+        k.fixed_angle.push_back(angle);
+    };
+    for (int pos = 0; pos < c.M; ++pos) {
+        const qng_gate &g = c.gates[pos];
+        const int r = c.rot_at[pos];
+        if (g.kind != QNG_RPAULI) {
+            if (r >= 0) {
+                Rot rr = c.rots[r];
+                rr.pos = (int)k.gates.size();
+                k.rots.push_back(rr);
+            }
+            push(g.kind, g.q0, g.q1, g.param, 0.0);
+            continue;
+        }
+        const Rot &rs = c.rots[r];
+        const uint64_t supp = rs.flip | rs.zy;
+        if (!supp) fail(QNG_E_DEVICE, "lower_strings: string without letters (internal)");
+        int pivot = 0;
+        while (!((supp >> pivot) & 1)) ++pivot;
+        auto basis = [&](bool inverse) {
+            for (int q = 0; q < c.n; ++q) {
+                const bool x = (rs.flip >> q) & 1, z = (rs.zy >> q) & 1;
+                if (x && !z) push(QNG_RY, q, -1, -1, inverse ? -half_pi : half_pi);   // X letter
+                if (x && z) push(QNG_RX, q, -1, -1, inverse ? half_pi : -half_pi);   // Y letter
+            }
+        };
+        basis(false);
+        for (int q = 0; q < c.n; ++q)
+            if (((supp >> q) & 1) && q != pivot) push(QNG_CNOT, q, pivot, -1, 0.0);
+        Rot z{AX_Z, pivot, rs.param, (int)k.gates.size()};
+        k.rots.push_back(z);
+        push(QNG_RZ, pivot, -1, rs.param, 0.0);
+        for (int q = c.n - 1; q >= 0; --q)
+            if (((supp >> q) & 1) && q != pivot) push(QNG_CNOT, q, pivot, -1, 0.0);
+        basis(true);
+    }
+    k.M = (int)k.gates.size();
+    k.P = (int)k.rots.size();
+    k.rot_at.assign(k.M, -1);
+    for (int r = 0; r < k.P; ++r) k.rot_at[k.rots[r].pos] = r;
+    if (k.P != c.P) fail(QNG_E_DEVICE, "lower_strings: rotation count changed (internal)");
+    return k;
+}
+
 // R_sigma(theta) = cos(theta/2) I + i sin(theta/2) sigma.
 Mat2 rotation(int axis, double theta) {
     const double c = std::cos(0.5 * theta), s = std::sin(0.5 * theta);

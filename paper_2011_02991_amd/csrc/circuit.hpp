@@ -56,11 +56,15 @@ struct Circuit {
     bool shared = false;    // some parameter is carried by several rotations
     bool controlled = false;  // some rotation is a controlled rotation
     bool has_strings = false; // some rotation is a Pauli-string rotation
-    // rotations other than single-qubit ones: only the per-primitive kernels take them
-    bool extended() const { return controlled || has_strings; }
+    bool lowered = false;     // Pauli-string rotations rewritten (lower_strings)
     std::vector<qng_gate> gates;
     std::vector<int> rot_at;   // gate position -> rotation index (list order) or -1
     std::vector<Rot> rots;     // rotations in list order
+    // Fixed single-qubit rotations exist in lowered circuits only: an RX/RY/RZ
+    // gate with param = -1 turns by fixed_angle[pos] (0 at every other position;
+    // empty when there are none).
+    std::vector<double> fixed_angle;
+    bool is_fixed_rotation(int pos) const { return gates[pos].kind <= QNG_RZ && gates[pos].param < 0; }
 };
 
 // Validation rules shared by every entry point (all before any device work).
@@ -70,6 +74,18 @@ void validate_hamiltonian(const qng_circuit *c, const qng_pauli_sum *h);
 void validate_scalar(double v, const char *name);
 
 Circuit compile_circuit(const qng_circuit *c);
+
+// A Pauli-string rotation exp(i theta S/2) is U^dagger exp(i theta Z_p/2) U
+// for U = C B: B turns each X letter into Z with RY(pi/2) and each Y letter
+// with RX(-pi/2) (so B S B^dagger is Z on the whole support), and C, CNOTs from
+// every other support qubit onto the pivot p (the lowest one), leaves Z_p
+// alone.  lower_strings rewrites every string rotation as that gate sequence
+// (B, C, RZ_p(theta), C, B^dagger): the state is the same function of the
+// parameters, so are G, T, E and its gradient, and the rotation keeps its
+// place in the rotation order with Z_p as its generator in the rewritten frame.
+// Strings with no letter (a global phase) cannot be rewritten this way.
+bool strings_lowerable(const Circuit &c);
+Circuit lower_strings(const Circuit &c);
 
 // R(theta) and R(theta)^dagger for a rotation axis.
 Mat2 rotation(int axis, double theta);

@@ -25,6 +25,17 @@ DevMat2 to_dev(const Mat2 &m) {
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// The shears of the fixed rotations of a lowered circuit (rows by gate position).
+void fill_fixed_shears(const Circuit &c, const std::vector<Mat2> &adj, std::vector<double> &mats) {
+    for (int pos = 0; pos < c.M; ++pos) {
+        if (!c.is_fixed_rotation(pos)) continue;
+        const int kind = c.gates[pos].kind;
+        const Shear sh = adjoint_shear(kind == QNG_RX ? AX_X : kind == QNG_RY ? AX_Y : AX_Z, adj[pos]);
+        mats[(size_t)pos * 8 + 0] = sh.u;
+        mats[(size_t)pos * 8 + 1] = sh.w;
+    }
+}
+
 struct Launch {
     uint32_t item_begin = 0, n_items = 0, total_tiles = 0, task_begin = 0, n_tasks = 0;
 };
@@ -150,6 +161,7 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
             mats[(size_t)r.pos * 8 + 3] = pl.s;
         }
     }
+    fill_fixed_shears(c, adj, mats);
     std::vector<float> mats32(mats.begin(), mats.end());
     char *p = buf.scratch;
     auto take = [&](size_t bytes) { char *o = p; p += align256(bytes + 64); return o; };
@@ -425,6 +437,7 @@ void run_fused_gradient(const SweepPlan &g, const Circuit &c, const std::vector<
             mats[(size_t)r.pos * 8 + 3] = pl.s;
         }
     }
+    fill_fixed_shears(c, adj, mats);
     std::vector<float> mats32(mats.begin(), mats.end());
     char *p = scratch;
     auto take = [&](size_t bytes) { char *o = p; p += align256(bytes + 64); return o; };

@@ -108,10 +108,12 @@ def test_validate_pauli_string_rotations(qng):
     assert e.value.name == "QNG_E_INVALID_ARG"
 
 
-def test_fused_planner_takes_controlled_rotations_not_strings(qng):
+def test_fused_planner_takes_controlled_rotations_and_strings(qng):
     """Controlled rotations are planned onto the fused passes (every element
-    once); Pauli-string rotations: the per-primitive plan counts them, the
-    fused-pass planner and its export reject them (QNG_E_UNSUPPORTED)."""
+    once), and so are Pauli-string rotations, rewritten as basis rotations,
+    CNOTs and an RZ (more gates, the same elements); the export of a plan with
+    strings (whose rows would name positions of the rewritten list) and the
+    fused plan of a string without letters are rejected (QNG_E_UNSUPPORTED)."""
     pr = W.controlled_layers(6, 2, 4, 23)
     c = _circ(qng, pr)
     P = pr.n_params
@@ -121,12 +123,20 @@ def test_fused_planner_takes_controlled_rotations_not_strings(qng):
     assert len(qng.plan_export(c)) > 0
     pr = W.string_layers(6, 2, 4, 24)
     c = _circ(qng, pr)
-    info = qng.plan(c, fusion=0)
-    assert info["elements"] == pr.n_params * (pr.n_params - 1) // 2
-    for call in (lambda: qng.plan(c, fusion=1), lambda: qng.plan_export(c)):
-        with pytest.raises(qng.QNGError) as e:
-            call()
-        assert e.value.name == "QNG_E_UNSUPPORTED"
+    P = pr.n_params
+    for fusion in (0, 1):
+        assert qng.plan(c, fusion=fusion)["elements"] == P * (P - 1) // 2
+    assert qng.plan(c, fusion=1)["passes"] > 0
+    with pytest.raises(qng.QNGError) as e:
+        qng.plan_export(c)
+    assert e.value.name == "QNG_E_UNSUPPORTED"
+    table = np.zeros((1, 3), dtype=np.uint8)
+    g = np.array([[W.RY, 0, -1, 0], [W.RPAULI, 0, -1, 1], [W.RY, 1, -1, 2]], dtype=np.int32)
+    c = qng.Circuit(3, g, 3, strings=table)
+    assert qng.plan(c, fusion=0)["elements"] == 3
+    with pytest.raises(qng.QNGError) as e:
+        qng.plan(c, fusion=1)
+    assert e.value.name == "QNG_E_UNSUPPORTED"
 
 
 def test_validate_two_qubit_gate_same_qubit(qng):

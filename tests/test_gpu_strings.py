@@ -2,16 +2,21 @@
 
 The column of a Pauli-string rotation uses the string S itself as generator
 (seed phi = S y, products <lambda|S|phi>), and S^2 = 1 keeps the diagonal at
-1/4 (Sec. 2).  These circuits run on the per-primitive kernels whatever the
-fusion option says.  complex128 results must match the oracle to 1e-10
-normwise (Delta theta: kappa(Re G + eps I) * 1e-14 when larger); complex64 to
-4 M 2^-24.
+1/4 (Sec. 2).  With fusion on, the library rewrites every string rotation as
+basis rotations, CNOTs onto the string's lowest qubit and an RZ there carrying
+the parameter (the same unitary), and the fused passes take the circuit; with
+fusion off, the per-primitive string kernels run.  complex128 results must
+match the oracle to 1e-10 normwise (Delta theta: kappa(Re G + eps I) * 1e-14
+when larger), and the two routes each other to 1e-12; complex64 the oracle to
+4 M' 2^-24 with M' the gates of the rewritten list.
 
 Workloads: random circuits with strings of 1..4 letters among plain
 rotations, CNOT and CZ (n = 2 .. 14, input states, permuted parameters); the
 layered ansatz of RX, ZZ ladders and an X Y..Y X string; strings together with
 controlled rotations and shared angles; the L-only variant; the device entry
-points with the autograd energy; and n = 22 sampled entries.
+points with the autograd energy; n = 22 sampled entries; both routes with one
+and two columns per sweep, FP32 shares and exact products, and the
+derivative-state variant.
 """
 import sys
 
@@ -66,6 +71,20 @@ def combined(n, seed):
                      theta=np.concatenate([a.theta, b.theta]), pauli=a.pauli, coeff=a.coeff, strings=a.strings)
 
 
+def rewritten_gates(pr):
+    """Gates of the rewritten list: a string of k letters, x of them X or Y,
+    becomes 2 x basis rotations, 2 (k - 1) CNOTs and one RZ."""
+    m = 0
+    for g in pr.gates:
+        if int(g[0]) != W.RPAULI:
+            m += 1
+            continue
+        letters = pr.strings[int(g[1])]
+        k, x = int((letters > 0).sum()), int(((letters == 1) | (letters == 2)).sum())
+        m += 2 * x + 2 * (k - 1) + 1
+    return m
+
+
 CASES = [(2, 12, 5301), (3, 24, 5302), (5, 40, 5303), (7, 60, 5304), (10, 70, 5305), (14, 50, 5306)]
 
 
@@ -82,7 +101,7 @@ def test_random_string_circuits(env, n, ngates, seed):
     assert ns > 0
     circ = q.Circuit.from_problem(pr)
     res = ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, in_state=pr.in_state)
-    assert ctx.stats()["sweep_launches"] == 0
+    assert ctx.stats()["sweep_launches"] > 0 or pr.n_params < 2
     want = oracle.step(pr)
     check(res, want, pr, TOL, pr.name)
     G, T = ctx.metric(circ, pr.theta, in_state=pr.in_state)
@@ -101,13 +120,18 @@ def test_string_layers(env, n, layers):
 def test_strings_complex64_bound(env):
     torch, q, ctx = env
     pr = W.string_layers(12, 2, 9, 5320)
-    res = ctx.step(q.Circuit.from_problem(pr), pr.theta, pr.dt, pr.tikhonov, prec="c64")
     want = oracle.step(pr)
-    bound = 4 * pr.n_gates * 2.0 ** -24
-    eG, eg = rel_err(res["G"], want["G"]), rel_err(res["grad"], want["grad"])
-    eE = abs(res["E"] - want["E"]) / max(1.0, abs(want["E"]))
-    say(f"c64 strings: |dG|={eG:.2e} |dgrad|={eg:.2e} |dE|={eE:.2e} (bound {bound:.1e})")
-    assert eG <= bound and eg <= bound and eE <= bound
+    bound = 4 * rewritten_gates(pr) * 2.0 ** -24
+    for fusion in (1, 0):
+        ctx.set_option(q.OPT_FUSION, fusion)
+        try:
+            res = ctx.step(q.Circuit.from_problem(pr), pr.theta, pr.dt, pr.tikhonov, prec="c64")
+        finally:
+            ctx.set_option(q.OPT_FUSION, 1)
+        eG, eg = rel_err(res["G"], want["G"]), rel_err(res["grad"], want["grad"])
+        eE = abs(res["E"] - want["E"]) / max(1.0, abs(want["E"]))
+        say(f"c64 strings (fusion {fusion}): |dG|={eG:.2e} |dgrad|={eg:.2e} |dE|={eE:.2e} (bound {bound:.1e})")
+        assert eG <= bound and eg <= bound and eE <= bound
 
 
 def test_strings_with_controlled_rotations_and_shared_angles(env):
@@ -195,3 +219,65 @@ def test_strings_n22_sampled(env):
     eE = abs(res["E"] - Eo) / max(1.0, abs(Eo))
     say(f"n22 strings: |dG|={eG:.2e} |dgrad|={eg:.2e} |dE|={eE:.2e}")
     assert eG <= TOL and eg <= TOL and eE <= TOL
+
+
+FUSED_CASES = [
+    ("layers n13", lambda: W.string_layers(13, 2, 6, 5380)),
+    ("random n14 in-state", lambda: W.string_circuit(14, 90, 5381, string_fraction=0.5, max_support=6, n_terms=6)),
+    ("strings+controlled n12 in-state", lambda: combined(12, 5382)),
+    ("layers n15 shared", lambda: W.share_params(W.string_layers(15, 2, 6, 5383), 30, 5384)),
+]
+
+
+@pytest.mark.parametrize("label,make", FUSED_CASES, ids=[c[0] for c in FUSED_CASES])
+def test_rewritten_strings_on_fused_passes(env, label, make):
+    """The rewritten circuit on the fused passes against the string kernels
+    (fusion off) and the oracle: complex128 with one and two columns per
+    sweep; complex64 with exact FP64 products and with FP32 shares; the
+    derivative-state variant where the circuit has no controlled rotation."""
+    torch, q, ctx = env
+    pr = make()
+    if "in-state" in label:
+        pr.in_state = W.random_state(pr.n_qubits, 5385)
+    circ = q.Circuit.from_problem(pr)
+    say(f"case: {pr.name} ({label}, P={pr.n_params}, M={pr.n_gates}, rewritten {rewritten_gates(pr)})")
+    want = oracle.step(pr)
+    ctx.set_option(q.OPT_FUSION, 0)
+    try:
+        ref = ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, in_state=pr.in_state)
+        Gref, Tref = ctx.metric(circ, pr.theta, in_state=pr.in_state)
+    finally:
+        ctx.set_option(q.OPT_FUSION, 1)
+    check(ref, want, pr, TOL, label + " string kernels")
+    for block in (1, 2):
+        ctx.set_option(q.OPT_BLOCK_COLUMNS, block)
+        try:
+            res = ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, in_state=pr.in_state)
+            st = ctx.stats()
+            G, T = ctx.metric(circ, pr.theta, in_state=pr.in_state)
+        finally:
+            ctx.set_option(q.OPT_BLOCK_COLUMNS, 0)
+        assert st["sweep_launches"] > 0 and st["block_columns"] == block
+        eG, eT, eg = rel_err(G, Gref), rel_err(T, Tref), rel_err(res["grad"], ref["grad"])
+        say(f"fused (block {block}) vs string kernels: |dG|={eG:.2e} |dT|={eT:.2e} |dgrad|={eg:.2e}")
+        assert eG <= 1e-12 and eT <= 1e-12 and eg <= 1e-12
+        check(res, want, pr, TOL, f"{label} fused block {block}")
+    bound = 4 * rewritten_gates(pr) * 2.0 ** -24
+    for exact in (1, 0):
+        ctx.set_option(q.OPT_EXACT_PRODUCTS, exact)
+        try:
+            r64 = ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, in_state=pr.in_state, prec="c64")
+            assert ctx.stats()["sweep_launches"] > 0
+        finally:
+            ctx.set_option(q.OPT_EXACT_PRODUCTS, 1)
+        eG, eg = rel_err(r64["G"], want["G"]), rel_err(r64["grad"], want["grad"])
+        say(f"c64 fused (exact products {exact}): |dG|={eG:.2e} |dgrad|={eg:.2e} bound {bound:.1e}")
+        assert eG <= bound and eg <= bound
+    if "controlled" in label:
+        return
+    ctx.set_option(q.OPT_METHOD, 1)
+    try:
+        rs = ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, in_state=pr.in_state)
+    finally:
+        ctx.set_option(q.OPT_METHOD, 0)
+    check(rs, want, pr, TOL, label + " derivative states")
