@@ -74,8 +74,9 @@ def _family(name: str) -> str:
 def _pmc(dbs):
     """Counter sums per kernel family, plus the calibration copy on its own.
 
-    The calibration copy is the first dispatch of each profiled process (the
-    512 MiB state clone that run() issues before the step).  Only that one
+    The calibration copy is the first dispatch of the library's copy kernel
+    in each profiled process (the 512 MiB state clone that run() issues before
+    the step; torch's fill of its source comes before it).  Only that one
     dispatch calibrates: the step itself launches copies of the same size
     (a state clone is a 512 MiB copy at n=26), which must not be summed in.
     """
@@ -86,7 +87,8 @@ def _pmc(dbs):
         rows = list(con.execute("select name, counter_name, counter_value, dispatch_id from pmc_events"))
         if not rows:
             continue
-        first = min(d for _, _, _, d in rows)
+        copies = [d for name, _, _, d in rows if _family(name) == "k_copy"]
+        first = min(copies) if copies else None
         for name, cn, v, d in rows:
             f = "calib" if d == first else _family(name)
             agg[f][cn] += v
