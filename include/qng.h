@@ -146,8 +146,11 @@ typedef enum {
     QNG_OPT_AUTOTUNE = 7,        /* qng_step_batched: 1 = time candidate tile widths and launch sizes on the
                                     first call for a batch structure and keep the fastest; 0 (default) = fixed */
     QNG_OPT_BATCH_TILES = 8,     /* qng_step_batched: work-groups per sweep launch to aim for (0 = 4096) */
-    QNG_OPT_BLOCK_COLUMNS = 9,   /* fused metric: columns sharing one lambda sweep, 1 or 2 (0 = default); 2 needs
-                                    tiles of >= 11 qubits (registers of >= 11 qubits), else 1 is used */
+    QNG_OPT_BLOCK_COLUMNS = 9,   /* fused metric: columns sharing one lambda sweep, 1, 2 or 4 (0 = default: 4
+                                    where it applies, else 2, else 1).  4 needs complex64 storage in FP32
+                                    registers, tiles of 11 qubits (registers of >= 11 qubits), no controlled
+                                    rotation, the recurrent method and a single ansatz; 2 needs tiles of >= 11
+                                    qubits; where the choice does not apply the next smaller one is used */
     QNG_OPT_METRIC_KIND = 10,    /* 0 (default): G = L - T^* T; 1: L alone, L_ij = <d_i psi, d_j psi> (the
                                     coefficient matrix of imaginary-time evolution when psi's global phase does
                                     not depend on theta); T is still returned.  Metric and step entry points. */
@@ -255,13 +258,14 @@ qng_status qng_plan(const qng_circuit *circ, int fusion, int tile_qubits, qng_pl
  * product and seed rows hold the target in q0 and the control in q1 (the
  * generator |1><1| on q1 times the axis's Pauli on q0; q1 = -1 for a plain one).
  * sweep = 0: the metric's columns s = 1..P-1 (Sec. 3, Alg. 1 inner loops),
- * destination r*P + s of <lambda|sigma_r|phi>; sweep = 2: the same metric with
- * blocks of two columns s-1, s sharing one lambda sweep (rows keyed by the top
- * column s; an inner product for both columns gives one row per destination,
- * the adjoint on the last; a seed row sets phi of column s_b to sigma lambda,
- * sigma on qubit q0 with the row's axis, and carries destination P*P + s_b of
- * <lambda|phi>, i.e. <y_{s_b}|sigma|y_{s_b}>); sweep = 1: the reverse sweep of
- * the energy gradient from the last gate (one column, s = P), destination r.
+ * destination r*P + s of <lambda|sigma_r|phi>; sweep = 2 (or 4): the same
+ * metric with blocks of two (four) columns s-1, s (s-3 .. s) sharing one
+ * lambda sweep (rows keyed by the top column s; an inner product for several
+ * columns gives one row per destination, the adjoint on the last; a seed row
+ * sets phi of column s_b to sigma lambda, sigma on qubit q0 with the row's
+ * axis, and carries destination P*P + s_b of <lambda|phi>, i.e.
+ * <y_{s_b}|sigma|y_{s_b}>); sweep = 1: the reverse sweep of the energy gradient
+ * from the last gate (one column, s = P), destination r.
  * amp_bytes: 16 for complex128 plans, 8 for complex64.  With rows = NULL only
  * *n_rows is set. */
 qng_status qng_plan_export(const qng_circuit *circ, int tile_qubits, int amp_bytes, int32_t sweep, int32_t *rows,

@@ -218,12 +218,12 @@ def plan(circ: Circuit, fusion: int = 1, tile_qubits: int = 0) -> dict:
 def plan_export(circ: Circuit, tile_qubits: int = 0, prec="c128", gradient: bool = False,
                 block: int = 1) -> np.ndarray:
     """Host-only: a fused sweep plan as rows of 10 int32 (see qng_plan_export);
-    the metric's columns (block=2: two columns per lambda sweep), or the
-    gradient's reverse sweep."""
+    the metric's columns (block=2 or 4: that many columns per lambda sweep), or
+    the gradient's reverse sweep."""
     amp = 16 if _prec(prec) == C128 else 8
-    if block not in (1, 2):
-        raise ValueError("block must be 1 or 2")
-    sw = 1 if gradient else (2 if block == 2 else 0)
+    if block not in (1, 2, 4):
+        raise ValueError("block must be 1, 2 or 4")
+    sw = 1 if gradient else (block if block > 1 else 0)
     n = ctypes.c_int64()
     _check(_lib.qng_plan_export(circ.cref, tile_qubits, amp, sw, None, 0, ctypes.byref(n)))
     rows = np.zeros((n.value, 10), dtype=np.int32)

@@ -610,7 +610,7 @@ void flatten(SweepPlan &plan, const Circuit &c) {
 
 SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int /*small*/, bool reg_f64,
                            int width, const std::vector<int> *rot_block) {
-    if (width < 1 || width > kMaxBlockWidth) fail(QNG_E_INVALID_ARG, "column block width must be 1 or 2");
+    if (width != 1 && width != 2 && width != 4) fail(QNG_E_INVALID_ARG, "column block width must be 1, 2 or 4");
     if (rot_block && width != 1) fail(QNG_E_INVALID_ARG, "a block-diagonal metric sweeps one column at a time");
     SweepPlan plan;
     plan.width = width;

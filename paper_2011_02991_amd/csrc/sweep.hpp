@@ -116,7 +116,7 @@ constexpr uint8_t kLocBase = 0xFF;
 constexpr int kMaxSlots = 256;      // inner products per pass
 constexpr int kMaxTileQubits = 13;
 constexpr int kMaxRest = 24;        // qubits outside a tile
-constexpr int kMaxBlockWidth = 2;   // columns sharing one lambda sweep
+constexpr int kMaxBlockWidth = 4;   // columns sharing one lambda sweep
 constexpr int kDefaultBlockWidth = 2;   // measured at n = 26: 8-11 % less sweep time than 1
 
 struct DevOp {  // 32 bytes
@@ -273,7 +273,7 @@ struct SweepCache {
 void append_structure_key(const Circuit &c, std::vector<int32_t> &key);
 
 // Device-side launch item: one pass of one column over all its tiles.
-struct LaunchItem {  // 48 bytes
+struct LaunchItem {  // 64 bytes
     uint32_t tile_begin;    // first work-group of this item in the launch
     uint32_t pass;          // index into the pass array
     uint32_t ntiles;
@@ -282,6 +282,8 @@ struct LaunchItem {  // 48 bytes
     void *regA;             // lambda
     void *regB;             // phi register 0
     void *regC;             // phi register 1 (blocks of two columns)
+    uint64_t phi_stride;    // blocks of four columns: phi register b at regB + b * phi_stride bytes
+    uint64_t pad1;
 };
 
 struct ReduceTask {  // 16 bytes: sum partials[off .. off+count) -> results[dest]

@@ -149,50 +149,90 @@ constexpr bool kRealProducts = QNG_REAL_PRODUCTS != 0;
 template <int W>
 __device__ __forceinline__ void row_reduce_store(double2 *sink, double2 *red, int slot, int fa, int tid,
                                                  const double (&pr)[W], const double (&pi)[W]) {
-    static_assert(W == 1 || W == 2, "one or two phi registers");
+    static_assert(W == 1 || W == 2 || W == 4, "one, two or four phi registers");
     const int lane = tid & 15;
     const bool h8 = lane & 8;
-    if constexpr (kRealProducts) {
-        // W = 1: every lane ends with the row's sum; W = 2: lanes 0-7 with
-        // register 0's, lanes 8-15 with register 1's
-        double v = W == 1 ? pr[0] : (h8 ? pr[W - 1] : pr[0]) + dpp_xchg<kDppRowMirror>(h8 ? pr[0] : pr[W - 1]);
-        if constexpr (W == 1) v += dpp_xchg<kDppRowMirror>(v);
-        v += dpp_xchg<kDppRowHalfMirror>(v);
+    if constexpr (W == 4) {
+        // lanes 0-7 keep registers 0 and 1, lanes 8-15 registers 2 and 3; then
+        // each quarter of the row one register (real and imaginary parts
+        // together when complex), then (complex) the lower pair of each
+        // quarter the real part
+        const bool h4 = lane & 4;
+        const double a = (h8 ? pr[2] : pr[0]) + dpp_xchg<kDppRowMirror>(h8 ? pr[0] : pr[2]);
+        const double b = (h8 ? pr[3] : pr[1]) + dpp_xchg<kDppRowMirror>(h8 ? pr[1] : pr[3]);
+        double v;
+        int part = 0;
+        if constexpr (kRealProducts) {
+            v = (h4 ? b : a) + dpp_xchg<kDppRowHalfMirror>(h4 ? a : b);
+            v += dpp_xchg<kDppXor2>(v);
+        } else {
+            const double ai = (h8 ? pi[2] : pi[0]) + dpp_xchg<kDppRowMirror>(h8 ? pi[0] : pi[2]);
+            const double bi = (h8 ? pi[3] : pi[1]) + dpp_xchg<kDppRowMirror>(h8 ? pi[1] : pi[3]);
+            const double re = (h4 ? b : a) + dpp_xchg<kDppRowHalfMirror>(h4 ? a : b);
+            const double im = (h4 ? bi : ai) + dpp_xchg<kDppRowHalfMirror>(h4 ? ai : bi);
+            // i ^ 2 pairs lanes of one quarter: the lower pair keeps re, the upper im
+            const bool h2 = lane & 2;
+            v = (h2 ? im : re) + dpp_xchg<kDppXor2>(h2 ? re : im);
+            part = h2 ? 1 : 0;
+        }
+        v += dpp_xchg<kDppXor1>(v);
+        v = across_rows(v);
+        // quarter q of the row holds register q (h8 picks the pair, then h4 within it)
+        const int reg = (lane >> 3) * 2 + ((lane >> 2) & 1);
+        const bool keep = reg >= fa;
+        if constexpr (kRealProducts) {
+            const bool last = (lane & 3) == 3 && (tid & 63) < 16;
+            double2 *p = (last && keep) ? &red[(slot + reg - fa) * kWaves + (tid >> 6)] : sink;
+            *p = make_double2(v, 0.0);
+        } else {
+            const bool last = (lane & 1) == 1 && (tid & 63) < 16;
+            double *p = (last && keep) ? &red[(slot + reg - fa) * kWaves + (tid >> 6)].x + part : (double *)sink;
+            *p = v;
+        }
+        return;
+    } else {
+        if constexpr (kRealProducts) {
+            // W = 1: every lane ends with the row's sum; W = 2: lanes 0-7 with
+            // register 0's, lanes 8-15 with register 1's
+            double v = W == 1 ? pr[0] : (h8 ? pr[W - 1] : pr[0]) + dpp_xchg<kDppRowMirror>(h8 ? pr[0] : pr[W - 1]);
+            if constexpr (W == 1) v += dpp_xchg<kDppRowMirror>(v);
+            v += dpp_xchg<kDppRowHalfMirror>(v);
+            v += dpp_xchg<kDppXor2>(v);
+            v += dpp_xchg<kDppXor1>(v);
+            v = across_rows(v);
+            const int b = W == 1 ? 0 : lane >> 3;
+            const bool last = (lane & 7) == 7 && (tid & 63) < 16;
+            const bool keep = W == 1 ? lane == 15 : b >= fa;
+            double2 *p = (last && keep) ? &red[(slot + b - fa) * kWaves + (tid >> 6)] : sink;
+            *p = make_double2(v, 0.0);
+            return;
+        }
+        double v;
+        if constexpr (W == 1) {
+            // lanes 0-7 keep the real part, lanes 8-15 the imaginary part
+            v = (h8 ? pi[0] : pr[0]) + dpp_xchg<kDppRowMirror>(h8 ? pr[0] : pi[0]);
+        } else {
+            // lanes 0-7 keep register 0's pair, lanes 8-15 register 1's ...
+            const double a = (h8 ? pr[1] : pr[0]) + dpp_xchg<kDppRowMirror>(h8 ? pr[0] : pr[1]);
+            const double b = (h8 ? pi[1] : pi[0]) + dpp_xchg<kDppRowMirror>(h8 ? pi[0] : pi[1]);
+            // ... then the lower quarter of each half the real part
+            const bool h4 = lane & 4;
+            v = (h4 ? b : a) + dpp_xchg<kDppRowHalfMirror>(h4 ? a : b);
+        }
+        if constexpr (W == 1) v += dpp_xchg<kDppRowHalfMirror>(v);
         v += dpp_xchg<kDppXor2>(v);
         v += dpp_xchg<kDppXor1>(v);
         v = across_rows(v);
+        // W = 1: lane 7 holds the real sum, lane 15 the imaginary one; W = 2: lanes
+        // 3, 7 hold register 0's, lanes 11, 15 register 1's (those of the
+        // wavefront's first row store the wavefront's sums)
         const int b = W == 1 ? 0 : lane >> 3;
-        const bool last = (lane & 7) == 7 && (tid & 63) < 16;
-        const bool keep = W == 1 ? lane == 15 : b >= fa;
-        double2 *p = (last && keep) ? &red[(slot + b - fa) * kWaves + (tid >> 6)] : sink;
-        *p = make_double2(v, 0.0);
-        return;
+        const bool last = (W == 1 ? (lane & 7) == 7 : (lane & 3) == 3) && (tid & 63) < 16;
+        const bool keep = W == 1 || b >= fa;
+        const int part = W == 1 ? lane >> 3 : (lane >> 2) & 1;
+        double *p = (last && keep) ? &red[(slot + b - fa) * kWaves + (tid >> 6)].x + part : (double *)sink;
+        *p = v;
     }
-    double v;
-    if constexpr (W == 1) {
-        // lanes 0-7 keep the real part, lanes 8-15 the imaginary part
-        v = (h8 ? pi[0] : pr[0]) + dpp_xchg<kDppRowMirror>(h8 ? pr[0] : pi[0]);
-    } else {
-        // lanes 0-7 keep register 0's pair, lanes 8-15 register 1's ...
-        const double a = (h8 ? pr[1] : pr[0]) + dpp_xchg<kDppRowMirror>(h8 ? pr[0] : pr[1]);
-        const double b = (h8 ? pi[1] : pi[0]) + dpp_xchg<kDppRowMirror>(h8 ? pi[0] : pi[1]);
-        // ... then the lower quarter of each half the real part
-        const bool h4 = lane & 4;
-        v = (h4 ? b : a) + dpp_xchg<kDppRowHalfMirror>(h4 ? a : b);
-    }
-    if constexpr (W == 1) v += dpp_xchg<kDppRowHalfMirror>(v);
-    v += dpp_xchg<kDppXor2>(v);
-    v += dpp_xchg<kDppXor1>(v);
-    v = across_rows(v);
-    // W = 1: lane 7 holds the real sum, lane 15 the imaginary one; W = 2: lanes
-    // 3, 7 hold register 0's, lanes 11, 15 register 1's (those of the
-    // wavefront's first row store the wavefront's sums)
-    const int b = W == 1 ? 0 : lane >> 3;
-    const bool last = (W == 1 ? (lane & 7) == 7 : (lane & 3) == 3) && (tid & 63) < 16;
-    const bool keep = W == 1 || b >= fa;
-    const int part = W == 1 ? lane >> 3 : (lane >> 2) & 1;
-    double *p = (last && keep) ? &red[(slot + b - fa) * kWaves + (tid >> 6)].x + part : (double *)sink;
-    *p = v;
 }
 
 // The tile is kept as four arrays of T scalars per thread: real and imaginary
@@ -1144,6 +1184,26 @@ __device__ __forceinline__ void tile_sums(const Regs<CT, T, W> &x, double2 *sink
     __syncthreads();   // zs lies in the exchange buffer: read before the next exchange
 }
 
+// Seed of a lower column of a block: phi register SB <- sigma lambda when the
+// op names register SB, then <lambda|phi> into the op's slot and the pass's
+// tile sums of that register (uniform control flow: contains barriers).
+template <int SB, int RB, int T, typename CT, int W>
+__device__ __forceinline__ void seed_handler(Regs<CT, T, W> &x, const OpD &op, int tid, uint64_t base,
+                                             double2 *sink, double2 *red, double2 *zs, bool pass_zsum,
+                                             double (&Sr)[W], double (&Si)[W]) {
+    if constexpr (SB + 1 < W) {
+        if (op.aux == SB) {
+            seed_phi<SB, RB, T, CT, W>(x, op.w0 >> 24, op.b0(), op.q0(), tid, base);
+            if constexpr (!kNoProducts) {
+                double pr, pi;
+                prod_plain<T, CT>(x.ar, x.ai, x.br[SB], x.bi[SB], pr, pi);
+                row_store(sink, red, op.slot(), tid, pr, pi);
+                if (pass_zsum) tile_sums<T, CT, W, SB, SB + 1>(x, sink, zs, tid, Sr, Si);
+            }
+        }
+    }
+}
+
 // Occupancy target: three waves per SIMD (the 53 KB of LDS of a work-group
 // allow three per CU).  The 16-amplitude kernel with one phi register reaches
 // it by itself (114 VGPRs; 158 with every product in FP64) and gets no bound;
@@ -1198,7 +1258,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNoPro
     for (int k = 0; k < kMaxRest; ++k)
         if (k < pass_nrest) base |= (uint64_t)((tile >> k) & 1u) << pbytes.rest(k);
 
-    void *gphi[2] = {it.regB, it.regC};
+    // phi registers: two given apiece, or (four-column blocks) consecutive
+    // registers from regB at phi_stride bytes
+    void *gphi[W];
+#pragma unroll
+    for (int b = 0; b < W; ++b)
+        gphi[b] = W <= 2 ? (b == 0 ? it.regB : it.regC) : (void *)((char *)it.regB + (uint64_t)b * it.phi_stride);
     Regs<CT, T, W> x;
 
     // ---- load
@@ -1391,13 +1456,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNoPro
                 if (hf & hbit(HB_SEED)) {
                     // phi register op.aux (below the top one) <- sigma lambda;
                     // <lambda|phi> = <y|sigma|y> into the op's slot
-                    static_assert(W == 2, "seeds are written for blocks of two columns");
-                    seed_phi<0, RB, T, CT, W>(x, op.w0 >> 24, op.b0(), op.q0(), tid, base);
-                    if constexpr (!kNoProducts) {
-                        double pr, pi;
-                        prod_plain<T, CT>(x.ar, x.ai, x.br[0], x.bi[0], pr, pi);
-                        row_store(sink, red, op.slot(), tid, pr, pi);
-                        if (pass_zsum) tile_sums<T, CT, W, 0, 1>(x, sink, zs, tid, Sr, Si);
+                    seed_handler<0, RB, T, CT, W>(x, op, tid, base, sink, red, zs, pass_zsum, Sr, Si);
+                    if constexpr (W > 2) {
+                        seed_handler<1, RB, T, CT, W>(x, op, tid, base, sink, red, zs, pass_zsum, Sr, Si);
+                        seed_handler<2, RB, T, CT, W>(x, op, tid, base, sink, red, zs, pass_zsum, Sr, Si);
                     }
                 }
             }
@@ -1524,6 +1586,18 @@ void launch_rb(const LaunchItem *items, int n_items, uint32_t total_tiles, const
             if (full) {
                 launch_ctrl<R, CT, RB, true, 2>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m,
                                                 ctrl, st);
+                return;
+            }
+        }
+        throw hipErrorInvalidValue;
+    }
+    if (width == 4) {
+        // four-column blocks: 8 amplitudes per thread, FP32 registers, with
+        // products, no controlled rotations
+        if constexpr (RB == 3 && sizeof(CT) == 4 && !kNoProducts) {
+            if (full && !ctrl) {
+                launch_full<R, CT, RB, true, 4, false>(items, n_items, total_tiles, passes, ops, maps, mats, partials,
+                                                       m, st);
                 return;
             }
         }

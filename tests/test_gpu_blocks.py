@@ -1,9 +1,10 @@
-"""Blocks of two metric columns sharing one lambda sweep (QNG_OPT_BLOCK_COLUMNS
-= 2) against the FP64 CPU oracle.
+"""Blocks of two and of four metric columns sharing one lambda sweep
+(QNG_OPT_BLOCK_COLUMNS = 2 or 4) against the FP64 CPU oracle.
 
-Column s and s - 1 are swept together: lambda is swept once, phi of column
-s - 1 is seeded inside the sweep as sigma lambda where lambda reaches y_{s-1}
-(with <lambda|phi> there giving T_{s-1}).  complex128 results must match the
+Columns s and s - 1 (s - 3 .. s) are swept together: lambda is swept once,
+phi of each lower column is seeded inside the sweep as sigma lambda where
+lambda reaches its y (with <lambda|phi> there giving its T).  Four-column
+blocks run in tiles of 11 qubits with FP32 registers (complex64 storage).  complex128 results must match the
 oracle as in the single-column tests (1e-10 normwise); complex64 results are
 checked against the same bound as the single-column complex64 path and
 against the single-column complex64 result.  The workloads have registers of
@@ -60,7 +61,7 @@ def step(ctx, qng, pr, prec, block, tile=0, f64=0, exact=0):
         ctx.set_option(qng.OPT_BLOCK_COLUMNS, 0)
         ctx.set_option(qng.OPT_TILE_QUBITS, 0)
         ctx.set_option(qng.OPT_F64_REGISTERS, 0)
-        ctx.set_option(qng.OPT_EXACT_PRODUCTS, 0)
+        ctx.set_option(qng.OPT_EXACT_PRODUCTS, 1)
 
 
 def check(res, want, pr, label):
@@ -155,3 +156,58 @@ def test_step_without_G_output(ctx, qng, label, make, prec):
     kappa = np.linalg.cond(want["G"].real + pr.tikhonov * np.eye(pr.n_params))
     bound = TOL if prec == "c128" else 4 * pr.gates.shape[0] * 2.0 ** -24
     assert rel_err(real["dtheta"], want["dtheta"]) <= max(bound, kappa * bound if prec == "c64" else kappa * 1e-14)
+
+
+FOUR = [
+    ("cfg3 n=12 L=2", lambda: with_state(W.scaled(W.config3, 12, 2, n_terms=9), 4201)),
+    ("cfg2 n=13 L=3", lambda: W.scaled(W.config2, 13, 3, n_terms=9)),
+    ("cfg5 n=11 L=2", lambda: W.scaled(W.config5, 11, 2, n_terms=9)),
+    ("random n=14 permuted P%4=3", lambda: with_state(W.permute_params(W.random_circuit(14, 80, 4202, n_terms=6), 5), 4203)),
+    ("random n=15 P%4=3", lambda: with_state(W.random_circuit(15, 61, 4204, n_terms=6, fixed_fraction=0.2), 4206)),
+]
+
+
+@pytest.mark.parametrize("exact", [1, 0])
+@pytest.mark.parametrize("label,make", FOUR, ids=[c[0] for c in FOUR])
+def test_four_column_blocks_complex64(ctx, qng, label, make, exact):
+    """Four columns per sweep (tiles of 11 qubits, FP32 registers): against the
+    oracle at the complex64 bound and against two columns per sweep (the same
+    bound: both round the stored states the same number of times), with the
+    complex G (complex products) and the step without it (real parts)."""
+    pr = make()
+    say(f"case: {label} (n={pr.n_qubits}, P={pr.n_params}, P % 4 = {pr.n_params % 4}) c64 exact={exact} block=4")
+    four = step(ctx, qng, pr, "c64", 4, 0, 0, exact)
+    assert ctx.stats()["block_columns"] == 4
+    two = step(ctx, qng, pr, "c64", 2, 0, 0, exact)
+    want = oracle.step(pr)
+    bound = 4 * pr.gates.shape[0] * 2.0 ** -24
+    for key in ("G", "grad"):
+        e4, e2 = rel_err(four[key], want[key]), rel_err(two[key], want[key])
+        say(f"  {key}: block=4 {e4:.2e}, block=2 {e2:.2e} (bound {bound:.1e})")
+        assert e4 <= bound and rel_err(four[key], two[key]) <= bound
+    ctx.set_option(qng.OPT_BLOCK_COLUMNS, 4)
+    ctx.set_option(qng.OPT_EXACT_PRODUCTS, exact)
+    try:
+        real = ctx.step(qng.Circuit.from_problem(pr), pr.theta, pr.dt, pr.tikhonov, in_state=pr.in_state,
+                        prec="c64", want_G=False)
+    finally:
+        ctx.set_option(qng.OPT_BLOCK_COLUMNS, 0)
+        ctx.set_option(qng.OPT_EXACT_PRODUCTS, 1)
+    kappa = np.linalg.cond(want["G"].real + pr.tikhonov * np.eye(pr.n_params))
+    ed = rel_err(real["dtheta"], four["dtheta"])
+    say(f"  step without G vs with G (block=4): |ddtheta|={ed:.2e} kappa={kappa:.1e}")
+    assert ed <= max(bound, kappa * bound)
+
+
+def test_four_column_blocks_not_taken(ctx, qng):
+    """Four columns per sweep only where they apply: complex128 and FP64
+    registers, tiles other than 11 qubits, registers below 11 qubits and
+    circuits with controlled rotations fall back to two columns (or one)."""
+    pr = W.scaled(W.config3, 12, 1, n_terms=4)
+    for prec, f64, tile in (("c128", 0, 0), ("c64", 1, 0), ("c64", 0, 12)):
+        step(ctx, qng, pr, prec, 4, tile, f64, 1)
+        assert ctx.stats()["block_columns"] == 2, (prec, f64, tile)
+    step(ctx, qng, W.scaled(W.config3, 10, 1, n_terms=4), "c64", 4, 0, 0, 1)
+    assert ctx.stats()["block_columns"] != 4
+    step(ctx, qng, W.controlled_layers(12, 1, 4, 4205), "c64", 4, 0, 0, 1)
+    assert ctx.stats()["block_columns"] == 2

@@ -182,14 +182,15 @@ def test_plan_sizes_of_workloads(qng):
 KIND_SEED = 3
 
 
-def replay_blocks(qng, pr, tile_qubits, prec="c128"):
-    """Replay a plan of two-column blocks: lambda starts at y_s of the top
-    column s and phi_s = sigma_s y_s; a seed row creates phi of a lower column
-    from the current lambda (sigma lambda) and gives <lambda|phi> = <y|sigma|y>
-    there; an inner product reads the phi of its destination's column, which
-    must already exist; adjoints act on lambda and every existing phi."""
+def replay_blocks(qng, pr, tile_qubits, prec="c128", block=2):
+    """Replay a plan of blocks of `block` columns: lambda starts at y_s of the
+    top column s and phi_s = sigma_s y_s; a seed row creates phi of a lower
+    column from the current lambda (sigma lambda) and gives <lambda|phi> =
+    <y|sigma|y> there; an inner product reads the phi of its destination's
+    column, which must already exist; adjoints act on lambda and every
+    existing phi."""
     circ = qng.Circuit.from_problem(pr)
-    rows = qng.plan_export(circ, tile_qubits, prec, block=2)
+    rows = qng.plan_export(circ, tile_qubits, prec, block=block)
     n, P = pr.n_qubits, pr.n_params
     gates = pr.gates
     rot_pos = [k for k in range(len(gates)) if gates[k, 3] >= 0]
@@ -213,7 +214,7 @@ def replay_blocks(qng, pr, tile_qubits, prec="c128"):
     blocks = {}
     for r in rows:
         blocks.setdefault(int(r[0]), []).append(r)
-    assert sorted(blocks) == list(range(P - 1, 0, -2))[::-1]
+    assert sorted(blocks) == list(range(P - 1, 0, -block))[::-1]
     for s, ops in blocks.items():
         lam = ys[s].copy()
         phis = {s: apply_generator(n, *gen(s), ys[s])}
@@ -224,7 +225,7 @@ def replay_blocks(qng, pr, tile_qubits, prec="c128"):
             inside = lambda q: (mask >> q) & 1
             if kind == KIND_SEED:
                 sb = dest - P * P
-                assert sb == s - 1 and sb not in phis and (q0, q1, axis) == gen(sb)
+                assert s - block < sb < s and sb >= 1 and sb not in phis and (q0, q1, axis) == gen(sb)
                 assert axis == 2 or inside(q0)
                 phis[sb] = apply_generator(n, q0, q1, axis, lam)
                 Traw[sb] = np.vdot(lam, phis[sb])
@@ -232,7 +233,7 @@ def replay_blocks(qng, pr, tile_qubits, prec="c128"):
             if kind in (KIND_PROD, KIND_PROD_ADJ):
                 assert axis == 2 or inside(q0)
                 rr, ss = divmod(dest, P)
-                assert ss in (s - 1, s) and ss in phis and rr < ss and not seen[rr, ss]
+                assert s - block < ss <= s and ss in phis and rr < ss and not seen[rr, ss]
                 assert (q0, q1, axis) == gen(rr)
                 seen[rr, ss] = True
                 Lraw[rr, ss] = np.vdot(lam, apply_generator(n, q0, q1, axis, phis[ss]))
@@ -412,3 +413,32 @@ def test_plan_export_rejects_strings(qng):
     with pytest.raises(qng.QNGError) as e:
         qng.plan_export(qng.Circuit.from_problem(pr), 5)
     assert e.value.name == "QNG_E_UNSUPPORTED"
+
+
+@pytest.mark.parametrize("cfg,n,layers,tile", [
+    (W.config3, 12, 2, 11), (W.config2, 11, 3, 11), (W.config5, 13, 2, 11), (W.config1, 12, 3, 11),
+])
+def test_four_column_block_plan_replay(qng, cfg, n, layers, tile):
+    """Blocks of four columns (the four-register sweep of complex64 FP32 tiles):
+    three seeds per block below its top column, every element once."""
+    pr = W.scaled(cfg, n, layers)
+    G, T, rows = replay_blocks(qng, pr, tile, "c64", block=4)
+    Gw, Tw = oracle.metric(pr)
+    np.testing.assert_allclose(G, Gw, atol=1e-13)
+    np.testing.assert_allclose(T, Tw, atol=1e-13)
+    P = pr.n_params
+    tops = list(range(P - 1, 0, -4))
+    assert (rows[:, 2] == KIND_SEED).sum() == sum(min(3, s - 1) for s in tops)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_four_column_block_plan_replay_random(qng, seed):
+    pr = W.random_circuit(12, 70 + seed, seed=400 + seed, fixed_fraction=0.3)
+    if seed % 2:
+        pr.in_state = W.random_state(12, seed)
+    if seed % 3 == 0:
+        pr = W.permute_params(pr, seed)
+    G, T, _ = replay_blocks(qng, pr, 11, "c64", block=4)
+    Gw, Tw = oracle.metric(pr)
+    np.testing.assert_allclose(G, Gw, atol=1e-13)
+    np.testing.assert_allclose(T, Tw, atol=1e-13)
