@@ -57,6 +57,15 @@ size_t fused_scratch_bytes(const SweepPlan &plan, const FusedRun &fr, int M) {
     b += align256(plan.dev_passes.size() * sizeof(LaunchItem) + 64);    // one item per pass
     b += align256(((size_t)plan.P * plan.P / 2 + plan.P) * sizeof(ReduceTask) + 64);  // elements and seeds
     b += align256((size_t)plan.P + 1 + 64);                              // signs (derivative-state variant)
+    if (plan.forward) {
+        const SweepPlan &fp = *plan.forward;
+        b += align256((size_t)M * 64 + 64);                              // the gates' own shears (FP64)
+        b += align256((size_t)M * 32 + 64);                              // (FP32)
+        b += align256(fp.dev_passes.size() * sizeof(DevPass) + 64);
+        b += align256(fp.dev_ops.size() * sizeof(DevOp) + 64);
+        b += align256(fp.dev_maps.size() * sizeof(DevMap) + 64);
+        b += align256(fp.dev_passes.size() * sizeof(LaunchItem) + 64);
+    }
     b += align256(fr.partial_elems * 16);
     return b;
 }
@@ -198,6 +207,55 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
         d_signs = (int8_t *)take(signs.size());
     }
     ReduceTask *d_tasks = (ReduceTask *)take(tasks.size() * sizeof(ReduceTask));
+    // the forward register's way between block tops as tile passes (the
+    // recurrence only): the gates' own shears, one item per pass on psi.  A
+    // gate with cos(theta/2) < 0 is applied negated (as in the sweeps), so psi
+    // may carry a sign; every product and T, E and the gradient are quadratic
+    // in it, and psi is put right at the end of the metric phase.
+    const SweepPlan *fp = (!states && plan.forward) ? plan.forward.get() : nullptr;
+    std::vector<double> fshear;
+    std::vector<LaunchItem> fitems;
+    std::vector<uint8_t> seg_neg;
+    double *d_fsh = nullptr;
+    float *d_fsh32 = nullptr;
+    DevPass *d_fpasses = nullptr;
+    DevOp *d_fops = nullptr;
+    DevMap *d_fmaps = nullptr;
+    LaunchItem *d_fitems = nullptr;
+    if (fp) {
+        fshear.assign((size_t)c.M * 8, 0.0);
+        std::vector<uint8_t> neg((size_t)c.M, 0);
+        for (int pos = 0; pos < c.M; ++pos) {
+            const int kind = c.gates[pos].kind;
+            if (kind > QNG_RZ) continue;
+            const int axis = kind == QNG_RX ? AX_X : kind == QNG_RY ? AX_Y : AX_Z;
+            const Shear sh = adjoint_shear(axis, fwd[pos]);
+            fshear[(size_t)pos * 8 + 0] = sh.u;
+            fshear[(size_t)pos * 8 + 1] = sh.w;
+            neg[pos] = fwd[pos].a.real() < 0;
+        }
+        int from = c.rots[0].pos;
+        for (const ColumnPlan &cp : fp->cols) {
+            uint8_t parity = 0;
+            for (int k = from; k < c.rots[cp.s].pos; ++k) parity ^= neg[k];
+            seg_neg.push_back(parity);
+            from = c.rots[cp.s].pos;
+        }
+        for (size_t t = 0; t < fp->dev_passes.size(); ++t) {
+            LaunchItem it{};
+            it.pass = (uint32_t)t;
+            it.ntiles = tiles;
+            it.regA = state(0);
+            fitems.push_back(it);
+        }
+        d_fsh = (double *)take(fshear.size() * 8);
+        d_fsh32 = (float *)take(fshear.size() * 4);
+        d_fpasses = (DevPass *)take(fp->dev_passes.size() * sizeof(DevPass));
+        d_fops = (DevOp *)take(fp->dev_ops.size() * sizeof(DevOp));
+        d_fmaps = (DevMap *)take(fp->dev_maps.size() * sizeof(DevMap));
+        d_fitems = (LaunchItem *)take(fitems.size() * sizeof(LaunchItem));
+    }
+    std::vector<float> fshear32(fshear.begin(), fshear.end());
     double *d_partials = (double *)p;
     if ((size_t)(p - buf.scratch) + fr.partial_elems * 16 > buf.scratch_bytes)
         fail(QNG_E_DEVICE, "fused sweep: scratch too small (internal)");
@@ -220,6 +278,20 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
     if (!tasks.empty())
         FCHECK(hipMemcpyAsync(d_tasks, tasks.data(), tasks.size() * sizeof(ReduceTask), hipMemcpyHostToDevice, st));
     if (d_signs) FCHECK(hipMemcpyAsync(d_signs, signs.data(), signs.size(), hipMemcpyHostToDevice, st));
+    if (fp) {
+        FCHECK(hipMemcpyAsync(d_fsh, fshear.data(), fshear.size() * 8, hipMemcpyHostToDevice, st));
+        FCHECK(hipMemcpyAsync(d_fsh32, fshear32.data(), fshear32.size() * 4, hipMemcpyHostToDevice, st));
+        if (!fp->dev_passes.empty()) {
+            FCHECK(hipMemcpyAsync(d_fpasses, fp->dev_passes.data(), fp->dev_passes.size() * sizeof(DevPass),
+                                  hipMemcpyHostToDevice, st));
+            FCHECK(hipMemcpyAsync(d_fops, fp->dev_ops.data(), fp->dev_ops.size() * sizeof(DevOp),
+                                  hipMemcpyHostToDevice, st));
+            FCHECK(hipMemcpyAsync(d_fmaps, fp->dev_maps.data(), fp->dev_maps.size() * sizeof(DevMap),
+                                  hipMemcpyHostToDevice, st));
+            FCHECK(hipMemcpyAsync(d_fitems, fitems.data(), fitems.size() * sizeof(LaunchItem), hipMemcpyHostToDevice,
+                                  st));
+        }
+    }
     FCHECK(hipStreamSynchronize(st));   // host vectors are released at return
 
     // ---- profiling events
@@ -291,12 +363,30 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
         control_diag(0);
     }
     stats->other_launches += 2;
+    uint8_t psi_negated = 0;
     for (const Group &G : groups) {
         for (int col = G.col_begin; col < G.col_end; ++col) {
             const int s = plan.cols[col].s;    // top column of the block
             const Rot &rs = c.rots[s];
             const Rot &rp = c.rots[s - 1];
             const int b = col - G.col_begin;
+            if (fp) {
+                // the gates up to the top rotation in the forward plan's passes,
+                // then lambda = psi = y_s, phi = sigma_s y_s and T_s in one pass
+                const int64_t t0 = fp->col_pass_begin[col];
+                const int64_t t1 = col + 1 < (int)fp->cols.size() ? fp->col_pass_begin[col + 1] : fp->total_passes;
+                for (int64_t t = t0; t < t1; ++t) {
+                    launch_sweep_pass_states<R>(d_fitems + t, 1, tiles, d_fpasses, d_fops, d_fmaps, d_fsh, d_fsh32,
+                                                fp->m, fp->rb, 0, st);
+                    ++stats->other_launches;
+                }
+                psi_negated ^= seg_neg[col];
+                pos = rs.pos;
+                launch_advance_seed<R>(psi, reg(b, 0), xi_of(s, b, W - 1), n, -1, d_fmats, rs.qubit, rs.axis,
+                                       buf.reduce_partials, buf.traw + 2 * s, st);
+                stats->other_launches += 2;
+                continue;
+            }
             // y_s = R_{s-1} y_{s-1} when rotation s-1 is the only gate in between:
             // one pass advances psi, seeds the top column and takes T_s (the
             // lower columns of a block are seeded inside its sweep).  When the
@@ -363,6 +453,10 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
             stats->sweep_flops +=
                 sweep_flops_per_amp(W, real_products) * (double)L.n_tasks * (double)((uint64_t)1 << n);
         }
+    }
+    if (psi_negated) {
+        launch_apply_1q<R>(psi, nullptr, n, 0, DevMat2{-1, 0, 0, 0, 0, 0, -1, 0}, st);
+        ++stats->other_launches;
     }
     if (states) {
         // every inner product at once: Re (and, for the complex G, Im) of the

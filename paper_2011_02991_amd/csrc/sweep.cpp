@@ -608,6 +608,29 @@ void flatten(SweepPlan &plan, const Circuit &c) {
 
 }  // namespace
 
+// The forward plan of a metric plan: column k applies the gates at positions
+// [from_k, rots[tops[k]].pos) to the forward register, from_0 = rots[0].pos and
+// from_k = rots[tops[k-1]].pos, in tiles of the metric plan's width.  Its ops
+// are the metric sweep's gate ops (OP_ROT, OP_DIAG, OP_CNOT, OP_CZ) ordered
+// forward; given the shears of the gates themselves instead of their adjoints,
+// the kernel applies the gates.
+SweepPlan build_forward_plan(const Circuit &c, const std::vector<int> &tops, int tile_qubits, int amp_bytes,
+                             bool reg_f64) {
+    SweepPlan plan;
+    plan.width = 0;
+    plan_shape(plan, c, tile_qubits, amp_bytes, reg_f64);
+    int from = c.rots[0].pos;
+    for (int s : tops) {
+        const int to = c.rots[s].pos;
+        std::vector<Event> ev;
+        for (int k = from; k < to; ++k) ev.push_back(unapply_event(c, k));
+        plan.cols.push_back(plan_column(c, plan, s, ev, SlotDest{1, 0, 0}));
+        from = to;
+    }
+    flatten(plan, c);
+    return plan;
+}
+
 SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int /*small*/, bool reg_f64,
                            int width, const std::vector<int> *rot_block) {
     if (width != 1 && width != 2 && width != 4) fail(QNG_E_INVALID_ARG, "column block width must be 1, 2 or 4");
@@ -624,6 +647,8 @@ SweepPlan build_sweep_plan(const Circuit &c, int tile_qubits, int amp_bytes, int
         plan.cols.push_back(plan_column(c, plan, s, block_events(c, s, width, rot_block),
                                         SlotDest{c.P, s - width + 1, c.P * c.P}));
     flatten(plan, c);
+    if (!c.controlled && !tops.empty())
+        plan.forward = std::make_shared<SweepPlan>(build_forward_plan(c, tops, plan.m, amp_bytes, reg_f64));
     return plan;
 }
 

@@ -231,6 +231,12 @@ struct SweepPlan {
     int64_t transposes = 0;
     std::vector<int64_t> col_pass_begin;   // per column: index of its first pass in dev_passes
     int64_t total_passes = 0, total_ops = 0, max_slots = 0, load_maps = 0;
+    // Metric plans: the forward register's way between block tops as tile
+    // passes (a plan of width 0 whose column k applies the gates at positions
+    // from rots[0].pos, then from the previous top's rotation, up to block k's
+    // top rotation, in order), or null where the passes cannot take it
+    // (controlled rotations).
+    std::shared_ptr<const SweepPlan> forward;
 
     size_t device_bytes() const;        // passes + ops (the rest is per call)
     void fill_info(qng_plan_info *out) const;
@@ -353,6 +359,8 @@ void launch_reduce_tasks(const ReduceTask *tasks, int n_tasks, const double *par
                          hipStream_t st);
 // The passes without inner products (sweep_kernels_states.hip): lambda and
 // the phi registers go through the adjoint gates and the in-pass seeds only.
+// width 0: lambda alone (the forward plans: the table then holds the shears
+// of the gates themselves, and the kernel applies them).
 template <typename R>
 void launch_sweep_pass_states(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
                               const DevOp *ops, const DevMap *maps, const double *mats64, const float *mats32, int m,

@@ -244,7 +244,7 @@ __device__ __forceinline__ void row_reduce_store(double2 *sink, double2 *red, in
 template <typename CT, int T, int W>
 struct Regs {
     CT ar[T], ai[T];           // lambda
-    CT br[W][T], bi[W][T];     // phi registers
+    CT br[W > 0 ? W : 1][T], bi[W > 0 ? W : 1][T];     // phi registers (W = 0: none; HIP has no empty arrays)
 };
 
 // 2x2 complex matrix entries of the gate table in the register precision
@@ -565,7 +565,7 @@ constexpr bool kNoProducts = QNG_NO_PRODUCTS != 0;
 #endif
 
 #define QNG_PRODS(PRODW)                                                                                     \
-    double pr[W], pi[W];                                                                                     \
+    double pr[W > 0 ? W : 1], pi[W > 0 ? W : 1];                                                             \
     if constexpr (!kNoProducts) { PRODW(x, pr, pi); }
 #define QNG_STORE_PRODS()                                                                                    \
     if constexpr (!kNoProducts) row_reduce_store<W>(sink, red, slot, fa, tid, pr, pi)
@@ -1160,9 +1160,9 @@ __device__ __forceinline__ void store_reg(void *g, const uint64_t (&off)[T], con
 
 // Tile sums <lambda|phi_b>_tile of phi registers B0 .. B1-1, summed over the
 // work-group (uniform control flow: contains barriers).
-template <int T, typename CT, int W, int B0, int B1>
+template <int T, typename CT, int W, int B0, int B1, int N>
 __device__ __forceinline__ void tile_sums(const Regs<CT, T, W> &x, double2 *sink, double2 *zs, int tid,
-                                          double (&Sr)[W], double (&Si)[W]) {
+                                          double (&Sr)[N], double (&Si)[N]) {
     __syncthreads();   // earlier readers of zs are done
 #pragma unroll
     for (int b = B0; b < B1; ++b) {
@@ -1260,7 +1260,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNoPro
 
     // phi registers: two given apiece, or (four-column blocks) consecutive
     // registers from regB at phi_stride bytes
-    void *gphi[W];
+    void *gphi[W > 0 ? W : 1];
 #pragma unroll
     for (int b = 0; b < W; ++b)
         gphi[b] = W <= 2 ? (b == 0 ? it.regB : it.regC) : (void *)((char *)it.regB + (uint64_t)b * it.phi_stride);
@@ -1286,7 +1286,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNoPro
     }
     // plain tile sums <A|B_b>_tile for Z inner products on qubits outside the
     // tile (a phi register seeded in this pass gets its sum at the seed)
-    double Sr[W], Si[W];
+    double Sr[W > 0 ? W : 1], Si[W > 0 ? W : 1];
 #pragma unroll
     for (int b = 0; b < W; ++b) Sr[b] = Si[b] = 0.0;
     if (!kNoProducts && pass_zsum) tile_sums<T, CT, W, 0, W>(x, sink, zs, tid, Sr, Si);
@@ -1581,6 +1581,21 @@ template <typename R, typename CT, int RB>
 void launch_rb(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes, const DevOp *ops,
                const DevMap *maps, const CT *mats, double *partials, int m, int width, bool ctrl, hipStream_t st) {
     const bool full = m - RB == 8;
+    if (width == 0) {
+        // lambda alone (forward plans), passes without products only
+        if constexpr (kNoProducts) {
+            if (!ctrl) {
+                if (full)
+                    launch_full<R, CT, RB, true, 0, false>(items, n_items, total_tiles, passes, ops, maps, mats,
+                                                           partials, m, st);
+                else
+                    launch_full<R, CT, RB, false, 0, false>(items, n_items, total_tiles, passes, ops, maps, mats,
+                                                            partials, m, st);
+                return;
+            }
+        }
+        throw hipErrorInvalidValue;
+    }
     if (width == 2) {
         if constexpr (RB >= 3) {
             if (full) {
