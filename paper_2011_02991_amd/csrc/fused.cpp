@@ -370,23 +370,6 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
             const Rot &rs = c.rots[s];
             const Rot &rp = c.rots[s - 1];
             const int b = col - G.col_begin;
-            if (fp) {
-                // the gates up to the top rotation in the forward plan's passes,
-                // then lambda = psi = y_s, phi = sigma_s y_s and T_s in one pass
-                const int64_t t0 = fp->col_pass_begin[col];
-                const int64_t t1 = col + 1 < (int)fp->cols.size() ? fp->col_pass_begin[col + 1] : fp->total_passes;
-                for (int64_t t = t0; t < t1; ++t) {
-                    launch_sweep_pass_states<R>(d_fitems + t, 1, tiles, d_fpasses, d_fops, d_fmaps, d_fsh, d_fsh32,
-                                                fp->m, fp->rb, 0, st);
-                    ++stats->other_launches;
-                }
-                psi_negated ^= seg_neg[col];
-                pos = rs.pos;
-                launch_advance_seed<R>(psi, reg(b, 0), xi_of(s, b, W - 1), n, -1, d_fmats, rs.qubit, rs.axis,
-                                       buf.reduce_partials, buf.traw + 2 * s, st);
-                stats->other_launches += 2;
-                continue;
-            }
             // y_s = R_{s-1} y_{s-1} when rotation s-1 is the only gate in between:
             // one pass advances psi, seeds the top column and takes T_s (the
             // lower columns of a block are seeded inside its sweep).  When the
@@ -412,6 +395,24 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
                                         buf.reduce_partials, buf.traw + 2 * s, st);
                 stats->other_launches += 2;
                 pos = rs.pos;
+                continue;
+            }
+            if (fp && !(pos == rp.pos && rs.pos == rp.pos + 1)) {
+                // more than the one rotation before the top: the gates up to the
+                // top rotation in the forward plan's passes (usually one), then
+                // lambda = psi = y_s, phi = sigma_s y_s and T_s in one pass
+                const int64_t t0 = fp->col_pass_begin[col];
+                const int64_t t1 = col + 1 < (int)fp->cols.size() ? fp->col_pass_begin[col + 1] : fp->total_passes;
+                for (int64_t t = t0; t < t1; ++t) {
+                    launch_sweep_pass_states<R>(d_fitems + t, 1, tiles, d_fpasses, d_fops, d_fmaps, d_fsh, d_fsh32,
+                                                fp->m, fp->rb, 0, st);
+                    ++stats->other_launches;
+                }
+                psi_negated ^= seg_neg[col];
+                pos = rs.pos;
+                launch_advance_seed<R>(psi, reg(b, 0), xi_of(s, b, W - 1), n, -1, d_fmats, rs.qubit, rs.axis,
+                                       buf.reduce_partials, buf.traw + 2 * s, st);
+                stats->other_launches += 2;
                 continue;
             }
             forward_to(rp.pos, reg(b, 0));
