@@ -657,9 +657,7 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
     if (fused) {
         const bool f64_regs = amp == 16 || ctx->opt_f64_regs;
         const bool blocked = !pb.rot_block.empty();
-        // the derivative-state variant keeps two columns per sweep at most
-        const int width =
-            blocked ? 1 : block_width(ctx->opt_block, c, ctx->opt_tile, (int)amp, f64_regs, states ? 2 : kMaxBlockWidth);
+        const int width = blocked ? 1 : block_width(ctx->opt_block, c, ctx->opt_tile, (int)amp, f64_regs);
         plan = &ctx->sweep_cache.get(c, plan_tile(width, ctx->opt_tile), (int)amp, ctx->opt_small, f64_regs, width,
                                      blocked ? &pb.rot_block : nullptr);
         size_t free_b = 0, total_b = 0;

@@ -128,7 +128,8 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
                 it.regA = reg(b, 0);
                 it.regB = xi_of(cp.s, b, 0);
                 it.regC = W > 1 ? xi_of(cp.s, b, 1) : nullptr;
-                it.phi_stride = V;   // four-column blocks: the phi registers follow one another
+                it.regD = W > 2 ? xi_of(cp.s, b, 2) : nullptr;
+                it.regE = W > 3 ? xi_of(cp.s, b, 3) : nullptr;
                 items.push_back(it);
                 ++L.n_items;
                 L.total_tiles += tiles;

@@ -287,9 +287,9 @@ struct LaunchItem {  // 64 bytes
     uint64_t partial_off;   // in complex doubles
     void *regA;             // lambda
     void *regB;             // phi register 0
-    void *regC;             // phi register 1 (blocks of two columns)
-    uint64_t phi_stride;    // blocks of four columns: phi register b at regB + b * phi_stride bytes
-    uint64_t pad1;
+    void *regC;             // phi register 1 (blocks of two or four columns)
+    void *regD;             // phi registers 2 and 3 (blocks of four columns)
+    void *regE;
 };
 
 struct ReduceTask {  // 16 bytes: sum partials[off .. off+count) -> results[dest]

@@ -1258,12 +1258,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNoPro
     for (int k = 0; k < kMaxRest; ++k)
         if (k < pass_nrest) base |= (uint64_t)((tile >> k) & 1u) << pbytes.rest(k);
 
-    // phi registers: two given apiece, or (four-column blocks) consecutive
-    // registers from regB at phi_stride bytes
     void *gphi[W > 0 ? W : 1];
 #pragma unroll
-    for (int b = 0; b < W; ++b)
-        gphi[b] = W <= 2 ? (b == 0 ? it.regB : it.regC) : (void *)((char *)it.regB + (uint64_t)b * it.phi_stride);
+    for (int b = 0; b < W; ++b) gphi[b] = b == 0 ? it.regB : b == 1 ? it.regC : b == 2 ? it.regD : it.regE;
     Regs<CT, T, W> x;
 
     // ---- load
@@ -1607,9 +1604,9 @@ void launch_rb(const LaunchItem *items, int n_items, uint32_t total_tiles, const
         throw hipErrorInvalidValue;
     }
     if (width == 4) {
-        // four-column blocks: 8 amplitudes per thread, FP32 registers, with
-        // products, no controlled rotations
-        if constexpr (RB == 3 && sizeof(CT) == 4 && !kNoProducts) {
+        // four-column blocks: 8 amplitudes per thread, FP32 registers, no
+        // controlled rotations
+        if constexpr (RB == 3 && sizeof(CT) == 4) {
             if (full && !ctrl) {
                 launch_full<R, CT, RB, true, 4, false>(items, n_items, total_tiles, passes, ops, maps, mats, partials,
                                                        m, st);

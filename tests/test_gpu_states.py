@@ -6,8 +6,8 @@ the matrix cores (FP64 products and sums).  Parity against the FP64 oracle
 (complex128, normwise 1e-10 for G, T, grad E; dtheta within max(1e-10,
 kappa 1e-14)), against the recurrent method on every entry, and on the edge
 cases: registers of 2 and 3 qubits (fewer reals per state than one staging
-step of the Gram kernel), two parameters, odd P, blocks of one and two
-columns, permuted and shared parameters, the complex G output (the Gram
+step of the Gram kernel), two parameters, odd P, blocks of one, two and
+four columns, permuted and shared parameters, the complex G output (the Gram
 matrix's imaginary part) and the step without it."""
 import sys
 
@@ -84,13 +84,21 @@ def test_states_vs_oracle(env, idx):
     assert rel_err(real["dtheta"], res["dtheta"]) <= 1e-13
 
 
-def test_states_complex64(env):
+@pytest.mark.parametrize("make", [lambda: W.scaled(W.config3, 14, 3, n_terms=10),
+                                  lambda: W.scaled(W.config2, 13, 3, n_terms=10),
+                                  lambda: W.permute_params(W.scaled(W.config5, 12, 2, n_terms=10), 8111)],
+                         ids=["cfg3 n14 P84", "cfg2 n13 P78", "cfg5 n12 P72 permuted"])
+def test_states_complex64(env, make):
     """complex64 storage: the kept states are FP32, the Gram matrix converts
     them exactly and forms every product in FP64; against complex128 at the
-    random-walk rounding bound of the sweeps (8 sqrt(M) u, M gates)."""
+    random-walk rounding bound of the sweeps (8 sqrt(M) u, M gates).  FP32
+    registers sweep four columns at a time; the lowest block then has one to
+    three columns below column 1 (P = 84: top 3; P = 78: top 1; P = 72: top 3),
+    whose phi registers go to the dummy state."""
     q, ctx = env
-    pr = W.scaled(W.config3, 14, 3, n_terms=10)
+    pr = make()
     r64, T64 = step(q, ctx, pr, 1, prec="c64")
+    assert ctx.stats()["block_columns"] == 4
     r128, T128 = step(q, ctx, pr, 0, prec="c128")
     bound = 8 * np.sqrt(pr.n_gates) * U32
     eG, eT = rel_err(r64["G"], r128["G"]), rel_err(T64, T128)
