@@ -303,9 +303,10 @@ def extended_gates(qng, ctx, prec, n_gate=26, n_step=24, layers=2, reps=2):
     a controlled rotation reads and writes the half of the amplitudes whose
     control is 1 (V bytes); a string rotation reads and writes every amplitude
     (2V).  Then the step at n_step qubits for the controlled ring ansatz and the
-    ZZ / X Y..Y X string ansatz (both per-primitive kernels), next to a plain
-    RY/RZ + CNOT ansatz with the same P on the per-primitive kernels and on the
-    fused passes."""
+    ZZ / X Y..Y X string ansatz (both on the fused passes: controlled rotations
+    with their own handlers, strings rewritten into basis rotations, CNOTs and
+    an RZ), next to a plain RY/RZ + CNOT ansatz with the same P on the
+    per-primitive kernels and on the fused passes."""
     import numpy as np
     import torch
     import workloads as W
