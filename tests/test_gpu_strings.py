@@ -281,3 +281,24 @@ def test_rewritten_strings_on_fused_passes(env, label, make):
     finally:
         ctx.set_option(q.OPT_METHOD, 0)
     check(rs, want, pr, TOL, label + " derivative states")
+
+
+def test_letterless_string_keeps_the_stepped_route(env):
+    """A string with no letter (a global phase: its row and column of G are
+    zero) cannot be rewritten into gates the fused passes take; such a circuit
+    sweeps one kernel per step (no fused sweep launch), several columns per
+    lambda sweep, against the oracle."""
+    torch, q, ctx = env
+    pr = W.string_circuit(9, 50, 5390, n_terms=6)
+    assert len(pr.strings) > 1
+    pr.strings = pr.strings.copy()
+    pr.strings[0, :] = 0
+    pr.in_state = W.random_state(9, 5391)
+    circ = q.Circuit.from_problem(pr)
+    say(f"case: {pr.name} with string 0 the identity (P={pr.n_params})")
+    res = ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, in_state=pr.in_state)
+    assert ctx.stats()["sweep_launches"] == 0
+    want = oracle.step(pr)
+    check(res, want, pr, TOL, pr.name + " stepped")
+    p0 = int(pr.gates[pr.gates[:, 0] == W.RPAULI][0, 3])
+    assert np.abs(res["G"][p0]).max() <= 1e-14 and np.abs(res["G"][:, p0]).max() <= 1e-14
