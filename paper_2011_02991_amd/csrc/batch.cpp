@@ -21,8 +21,10 @@ namespace {
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+constexpr uint64_t kSeedBlocksMax = 64;   // work-groups per seed in a round (the rest by grid stride)
+
 struct ImageLayout {
-    size_t passes, ops, maps, items, tasks, total;
+    size_t passes, ops, maps, items, tasks, seed_items, seed_tasks, total;
 };
 
 ImageLayout image_layout(const BatchSchedule &s) {
@@ -34,6 +36,8 @@ ImageLayout image_layout(const BatchSchedule &s) {
     L.maps = take(s.maps.size() * sizeof(DevMap));
     L.items = take(s.items.size() * sizeof(LaunchItem));
     L.tasks = take(s.tasks.size() * sizeof(ReduceTask));
+    L.seed_items = take(s.seeds.size() * sizeof(SeedItem));
+    L.seed_tasks = take(s.seed_tasks.size() * sizeof(ReduceTask));
     L.total = off;
     return L;
 }
@@ -174,6 +178,76 @@ BatchSchedule build_batch_schedule(const std::vector<const Circuit *> &members,
         act.swap(next);
     }
     S.arena_bytes = bump;
+
+    // the seeds of every launch in rounds, the forward registers' positions
+    // followed as the executor moves them
+    std::vector<int> fpos(nb, -1);
+    for (BatchLaunch &L : S.launches) {
+        L.round_begin = (uint32_t)S.rounds.size();
+        std::map<int, int> seen;
+        std::vector<int> ridx(L.n_preps);
+        int nr = 0;
+        for (uint32_t k = 0; k < L.n_preps; ++k) {
+            ridx[k] = seen[S.preps[L.prep_begin + k].member]++;
+            nr = std::max(nr, ridx[k] + 1);
+        }
+        for (int r = 0; r < nr; ++r) {
+            BatchRound R{(uint32_t)S.seeds.size(), 0, 0, 0};
+            // registers of >= 3 qubits first (the one kernel's items), then the rest
+            for (int big = 1; big >= 0; --big)
+            for (uint32_t k = 0; k < L.n_preps; ++k) {
+                if (ridx[k] != r || (members[S.preps[L.prep_begin + k].member]->n >= 3) != (big == 1)) continue;
+                const BatchPrep &pr = S.preps[L.prep_begin + k];
+                const Circuit &c = *members[pr.member];
+                const int sidx = plans[pr.member]->cols[pr.col].s;
+                const Rot &rs = c.rots[sidx];
+                const Rot &rp = c.rots[sidx - 1];
+                int &p = fpos[pr.member];
+                if (p < 0) p = c.rots[0].pos;
+                BatchSeed sd{};
+                sd.member = pr.member;
+                sd.fwd_to = -1;
+                sd.qa = sd.qb = sd.pa = sd.pb = -1;
+                sd.qs = rs.qubit;
+                sd.axis = rs.axis;
+                sd.s = sidx;
+                sd.lam_off = pr.reg_off;
+                sd.phi_off = pr.reg_off + (uint64_t)S.width * (uint64_t(1) << c.n) * (uint64_t)amp;
+                const int ra = p < c.M ? c.rot_at[p] : -1;
+                if (ra >= 0 && p + 1 == rp.pos && rs.pos == rp.pos + 1 && c.n >= 3 && c.rots[ra].qubit != rp.qubit &&
+                    c.rots[ra].qubit != rs.qubit && rp.qubit != rs.qubit) {
+                    sd.qa = c.rots[ra].qubit;   // two rotations before y_s
+                    sd.pa = p;
+                    sd.qb = rp.qubit;
+                    sd.pb = rp.pos;
+                } else if (rs.pos == rp.pos + 1) {
+                    sd.fwd_to = rp.pos;          // the gates up to rotation s - 1, then that rotation
+                    sd.qa = rp.qubit;
+                    sd.pa = rp.pos;
+                } else {
+                    sd.fwd_to = rs.pos;          // every gate up to y_s
+                }
+                p = rs.pos;
+                if (c.n >= 3) {
+                    const uint64_t groups = uint64_t(1) << (c.n - 3);
+                    sd.nblocks = (uint32_t)std::min<uint64_t>(kSeedBlocksMax, (groups + 255) / 256);
+                    sd.block_begin = R.total_blocks;
+                    R.total_blocks += sd.nblocks;
+                    S.seed_tasks.push_back(ReduceTask{(uint64_t)sd.block_begin, sd.nblocks,
+                                                      (int32_t)(S.lraw_base[pr.member] + (int64_t)c.P * c.P + sidx)});
+                    ++R.n_multi;
+                } else {
+                    sd.nblocks = 0;   // seeded on its own; its task is never launched
+                    S.seed_tasks.push_back(ReduceTask{0, 0, 0});
+                }
+                S.seeds.push_back(sd);
+                ++R.n_seeds;
+            }
+            S.partial_elems = std::max<uint64_t>(S.partial_elems, R.total_blocks);
+            S.rounds.push_back(R);
+        }
+        L.n_rounds = (uint32_t)nr;
+    }
     S.partial_elems += 16;
     return S;
 }
@@ -196,7 +270,26 @@ void upload_batch_images(const BatchSchedule &s, const BatchDevice &d, hipStream
     put(L.maps, s.maps.data(), s.maps.size() * sizeof(DevMap));
     put(L.items, items.data(), items.size() * sizeof(LaunchItem));
     put(L.tasks, s.tasks.data(), s.tasks.size() * sizeof(ReduceTask));
-    BCHECK(hipStreamSynchronize(st));   // `items` is released at return
+    std::vector<SeedItem> seeds(s.seeds.size());
+    for (size_t k = 0; k < s.seeds.size(); ++k) {
+        const BatchSeed &sd = s.seeds[k];
+        SeedItem &it = seeds[k];
+        it.psi = d.psi[sd.member];
+        it.lam = d.arena + sd.lam_off;
+        it.phi = d.arena + sd.phi_off;
+        it.ma = sd.qa >= 0 ? d.fwd_mats + (s.gate_base[sd.member] + sd.pa) * 8 : nullptr;
+        it.mb = sd.qb >= 0 ? d.fwd_mats + (s.gate_base[sd.member] + sd.pb) * 8 : nullptr;
+        it.qa = sd.qa;
+        it.qb = sd.qb;
+        it.qs = sd.qs;
+        it.axis = sd.axis;
+        it.n = s.plans[sd.member]->n;
+        it.block_begin = sd.block_begin;
+        it.nblocks = sd.nblocks;
+    }
+    put(L.seed_items, seeds.data(), seeds.size() * sizeof(SeedItem));
+    put(L.seed_tasks, s.seed_tasks.data(), s.seed_tasks.size() * sizeof(ReduceTask));
+    BCHECK(hipStreamSynchronize(st));   // `items` and `seeds` are released at return
 }
 
 int batch_final_pos(const Circuit &c) { return c.P ? c.rots[c.P - 1].pos : 0; }
@@ -248,43 +341,32 @@ void enqueue_batch_metric(const BatchSchedule &s, const std::vector<const Circui
                              st);
     };
     for (int b : s.singles) start(b);
+    const SeedItem *seed_items = (const SeedItem *)(d.images + IL.seed_items);
+    const ReduceTask *seed_tasks = (const ReduceTask *)(d.images + IL.seed_tasks);
     for (size_t li = 0; li < s.launches.size(); ++li) {
         const BatchLaunch &L = s.launches[li];
-        for (uint32_t k = 0; k < L.n_preps; ++k) {
-            const BatchPrep &pr = s.preps[L.prep_begin + k];
-            const Circuit &c = *members[pr.member];
-            const int sidx = s.plans[pr.member]->cols[pr.col].s;
-            const Rot &rs = c.rots[sidx];
-            const Rot &rp = c.rots[sidx - 1];
-            start(pr.member);
-            // lambda and the block's top phi register (its last one; the lower
-            // column's phi is seeded inside the block's sweep)
-            char *lam = d.arena + pr.reg_off;
-            char *phi = lam + (size_t)s.width * (size_t(1) << c.n) * (size_t)s.amp;
-            int &p = pos[pr.member];
-            const int64_t gb = s.gate_base[pr.member];
-            // two rotations before y_s on two other qubits: one pass, as in the single step
-            const int ra = p < c.M ? c.rot_at[p] : -1;
-            if (ra >= 0 && p + 1 == rp.pos && rs.pos == rp.pos + 1 && c.n >= 3 && c.rots[ra].qubit != rp.qubit &&
-                c.rots[ra].qubit != rs.qubit && rp.qubit != rs.qubit) {
-                launch_advance2_seed<R>(d.psi[pr.member], lam, phi, c.n, c.rots[ra].qubit, d.fwd_mats + (gb + p) * 8,
-                                        rp.qubit, d.fwd_mats + (gb + rp.pos) * 8, rs.qubit, rs.axis,
-                                        d.reduce_partials, d.traw[pr.member] + 2 * sidx, st);
-                p = rs.pos;
-                continue;
+        for (uint32_t r = L.round_begin; r < L.round_begin + L.n_rounds; ++r) {
+            // a round: the gates its seeds need first (one kernel per gate), then
+            // all its seeds in one kernel and their T in one reduction
+            const BatchRound &rd = s.rounds[r];
+            for (uint32_t k = rd.seed_begin; k < rd.seed_begin + rd.n_seeds; ++k) {
+                const BatchSeed &sd = s.seeds[k];
+                start(sd.member);
+                char *lam = d.arena + sd.lam_off;
+                if (sd.fwd_to >= 0) forward_to(sd.member, sd.fwd_to, lam);
+                if (sd.nblocks == 0) {
+                    // a register below 3 qubits: seeded on its own
+                    const Circuit &c = *members[sd.member];
+                    const double *mrow = sd.qa >= 0 ? d.fwd_mats + (s.gate_base[sd.member] + sd.pa) * 8 : d.fwd_mats;
+                    launch_advance_seed<R>(d.psi[sd.member], lam, d.arena + sd.phi_off, c.n, sd.qa, mrow, sd.qs,
+                                            sd.axis, d.reduce_partials, d.traw[sd.member] + 2 * sd.s, st);
+                }
+                pos[sd.member] = members[sd.member]->rots[sd.s].pos;
             }
-            int qr = -1;
-            const double *mrow = d.fwd_mats;
-            forward_to(pr.member, rp.pos, lam);
-            if (p == rp.pos && rs.pos == rp.pos + 1) {
-                qr = rp.qubit;
-                mrow = d.fwd_mats + (gb + rp.pos) * 8;
-                p = rs.pos;
-            } else {
-                forward_to(pr.member, rs.pos, lam);
+            if (rd.n_multi) {
+                launch_seed_multi<R>(seed_items + rd.seed_begin, (int)rd.n_multi, rd.total_blocks, d.partials, st);
+                launch_reduce_tasks(seed_tasks + rd.seed_begin, (int)rd.n_multi, d.partials, d.lraw, st);
             }
-            launch_advance_seed<R>(d.psi[pr.member], lam, phi, c.n, qr, mrow, rs.qubit, rs.axis, d.reduce_partials,
-                                   d.traw[pr.member] + 2 * sidx, st);
         }
         if (events) BCHECK(hipEventRecord((*events)[2 * li], st));
         launch_sweep_pass<R>(items + L.item_begin, (int)L.n_items, L.total_tiles, passes, ops, maps, d.adj_mats,

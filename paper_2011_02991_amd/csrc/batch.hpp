@@ -40,6 +40,25 @@ struct BatchPrep {              // admission of column block `col` of `member` i
 
 struct BatchLaunch {
     uint32_t item_begin, n_items, total_tiles, task_begin, n_tasks, prep_begin, n_preps;
+    uint32_t round_begin, n_rounds;   // the launch's column seeds, in rounds
+};
+
+// The column seeds before a launch go in rounds: a round holds at most one
+// seed per member (a member's seeds depend on each other through its forward
+// register), and all of a round's seeds run as one kernel (launch_seed_multi)
+// and one reduction of their T.  A seed may first need gates the seed kernel
+// does not apply (one kernel per gate, up to fwd_to).
+struct BatchSeed {
+    int member;
+    int fwd_to;                  // gate position the forward register is brought to first, or -1
+    int qa, pa, qb, pb;          // rotations the seed kernel applies (qubit, gate position; -1: none)
+    int qs, axis, s;             // the seeded column
+    uint64_t lam_off, phi_off;   // arena offsets of lambda and the block's top phi register
+    uint32_t block_begin, nblocks;   // work-groups within the round (0: seeded on its own, register < 3 qubits)
+};
+struct BatchRound {
+    uint32_t seed_begin, n_seeds, total_blocks;
+    uint32_t n_multi;   // the first n_multi seeds run in the one kernel (registers of >= 3 qubits)
 };
 
 struct BatchSchedule {
@@ -56,6 +75,9 @@ struct BatchSchedule {
     std::vector<LaunchItem> items;                           // regA/regB: arena offsets
     std::vector<ReduceTask> tasks;
     std::vector<BatchPrep> preps;
+    std::vector<BatchSeed> seeds;
+    std::vector<BatchRound> rounds;
+    std::vector<ReduceTask> seed_tasks;                      // per seed: its T from the round's partials
     std::vector<BatchLaunch> launches;
     std::vector<int> singles;                                // members with P == 1 (no columns)
     uint64_t arena_bytes = 0;

@@ -469,6 +469,102 @@ __global__ void k_advance_seed(typename Cplx<R>::T *psi, typename Cplx<R>::T *la
     block_reduce_store(sr, si, partials + 2 * blockIdx.x);
 }
 
+// Column seeds of many registers in one launch (the batched metric): item k
+// applies up to two forward rotations (qa then qb; -1: none) to its register
+// psi, then writes lam = psi, phi = sigma_qs psi and its work-groups' partial
+// sums of <psi|sigma_qs|psi>.  A thread walks the groups of eight amplitudes
+// over three distinct bits: qs, the rotations' qubits and, where those are
+// fewer, the lowest other qubits (registers of at least 3 qubits).  The work-
+// groups of item k are block_begin .. block_begin + nblocks - 1; each writes
+// one partial at its own index.
+// (the matrix entries in the register's precision, as in k_advance_seed)
+template <typename R, typename C>
+__device__ __forceinline__ void rot_pair(const double *m, C &u, C &v) {
+    const C a = u, b = v;
+    const R m0 = (R)m[0], m1 = (R)m[1], m2 = (R)m[2], m3 = (R)m[3];
+    const R m4 = (R)m[4], m5 = (R)m[5], m6 = (R)m[6], m7 = (R)m[7];
+    u.x = m0 * a.x - m1 * a.y + m2 * b.x - m3 * b.y;
+    u.y = m0 * a.y + m1 * a.x + m2 * b.y + m3 * b.x;
+    v.x = m4 * a.x - m5 * a.y + m6 * b.x - m7 * b.y;
+    v.y = m4 * a.y + m5 * a.x + m6 * b.y + m7 * b.x;
+}
+// the rotation m on bit j (0, 1, 2) of a group of eight
+template <typename R, typename C>
+__device__ __forceinline__ void rot_group(const double *m, int j, C (&v)[8]) {
+    switch (j) {
+    case 0: rot_pair<R>(m, v[0], v[1]); rot_pair<R>(m, v[2], v[3]); rot_pair<R>(m, v[4], v[5]); rot_pair<R>(m, v[6], v[7]); break;
+    case 1: rot_pair<R>(m, v[0], v[2]); rot_pair<R>(m, v[1], v[3]); rot_pair<R>(m, v[4], v[6]); rot_pair<R>(m, v[5], v[7]); break;
+    default: rot_pair<R>(m, v[0], v[4]); rot_pair<R>(m, v[1], v[5]); rot_pair<R>(m, v[2], v[6]); rot_pair<R>(m, v[3], v[7]); break;
+    }
+}
+template <typename C>
+__device__ __forceinline__ void pauli_group(int axis, int j, const C (&v)[8], C (&o)[8]) {
+    switch (j) {
+    case 0: pauli_pair(axis, v[0], v[1], o[0], o[1]); pauli_pair(axis, v[2], v[3], o[2], o[3]);
+            pauli_pair(axis, v[4], v[5], o[4], o[5]); pauli_pair(axis, v[6], v[7], o[6], o[7]); break;
+    case 1: pauli_pair(axis, v[0], v[2], o[0], o[2]); pauli_pair(axis, v[1], v[3], o[1], o[3]);
+            pauli_pair(axis, v[4], v[6], o[4], o[6]); pauli_pair(axis, v[5], v[7], o[5], o[7]); break;
+    default: pauli_pair(axis, v[0], v[4], o[0], o[4]); pauli_pair(axis, v[1], v[5], o[1], o[5]);
+             pauli_pair(axis, v[2], v[6], o[2], o[6]); pauli_pair(axis, v[3], v[7], o[3], o[7]); break;
+    }
+}
+
+template <typename R>
+__global__ void k_seed_multi(const SeedItem *__restrict__ items, int n_items, double *partials) {
+    using C = typename Cplx<R>::T;
+    const uint32_t wg = blockIdx.x;
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].block_begin <= wg) lo = mid;
+        else hi = mid - 1;
+    }
+    const SeedItem it = items[lo];
+    C *psi = (C *)it.psi, *lam = (C *)it.lam, *phi = (C *)it.phi;
+    // the three bits of a group, ascending, and where qa, qb, qs sit among them
+    int bit[3], k = 0;
+    auto add = [&](int q) {
+        if (q < 0) return;
+        for (int i = 0; i < k; ++i)
+            if (bit[i] == q) return;
+        bit[k++] = q;
+    };
+    add(it.qs);
+    add(it.qa);
+    add(it.qb);
+    for (int q = 0; k < 3; ++q) add(q);
+    if (bit[0] > bit[1]) { const int t = bit[0]; bit[0] = bit[1]; bit[1] = t; }
+    if (bit[1] > bit[2]) { const int t = bit[1]; bit[1] = bit[2]; bit[2] = t; }
+    if (bit[0] > bit[1]) { const int t = bit[0]; bit[0] = bit[1]; bit[1] = t; }
+    auto slot = [&](int q) { return q == bit[0] ? 0 : q == bit[1] ? 1 : 2; };
+    const int js = slot(it.qs), ja = it.qa >= 0 ? slot(it.qa) : -1, jb = it.qb >= 0 ? slot(it.qb) : -1;
+    const uint64_t m0 = uint64_t(1) << bit[0], m1 = uint64_t(1) << bit[1], m2 = uint64_t(1) << bit[2];
+    double sr = 0.0, si = 0.0;
+    const uint64_t ngroups = uint64_t(1) << (it.n - 3);
+    const uint64_t stride = (uint64_t)it.nblocks * kBlock;
+    for (uint64_t p = (uint64_t)(wg - it.block_begin) * kBlock + threadIdx.x; p < ngroups; p += stride) {
+        const uint64_t b = insert_zero(insert_zero(insert_zero(p, bit[0]), bit[1]), bit[2]);
+        uint64_t idx[8];
+#pragma unroll
+        for (int g = 0; g < 8; ++g) idx[g] = b | ((g & 1) ? m0 : 0) | ((g & 2) ? m1 : 0) | ((g & 4) ? m2 : 0);
+        C v[8];
+#pragma unroll
+        for (int g = 0; g < 8; ++g) v[g] = psi[idx[g]];
+        if (ja >= 0) rot_group<R>(it.ma, ja, v);
+        if (jb >= 0) rot_group<R>(it.mb, jb, v);
+        C o[8];
+        pauli_group(it.axis, js, v, o);
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+            if (ja >= 0) psi[idx[g]] = v[g];
+            lam[idx[g]] = v[g];
+            phi[idx[g]] = o[g];
+            cmac(sr, si, v[g].x, v[g].y, o[g].x, o[g].y);
+        }
+    }
+    block_reduce_store(sr, si, partials + 2 * wg);
+}
+
 // ------------------------------------------------------------------ sweep steps
 //
 // One step of the recurrence's back sweep over lambda and several phi
@@ -1031,6 +1127,13 @@ void launch_advance_seed(void *psi, void *lam, void *phi, int n, int qr, const d
 }
 
 template <typename R>
+void launch_seed_multi(const SeedItem *items, int n_items, uint32_t total_blocks, double *partials, hipStream_t st) {
+    if (n_items <= 0 || total_blocks == 0) return;
+    hipLaunchKernelGGL(k_seed_multi<R>, dim3(total_blocks), dim3(kBlock), 0, st, items, n_items, partials);
+    check_launch();
+}
+
+template <typename R>
 void launch_advance2_seed(void *psi, void *lam, void *phi, int n, int qa, const double *ma, int qb, const double *mb,
                           int qc, int axis, double *partials, double *dest, hipStream_t st) {
     if (n < 3 || qa == qb || qa == qc || qb == qc) throw hipErrorInvalidValue;
@@ -1151,6 +1254,7 @@ void launch_grad_from_raw(const double *graw, const int *param_of, int P, double
                                        int);                                                                      \
     template void launch_advance_seed<R>(void *, void *, void *, int, int, const double *, int, int, double *,       \
                                          double *, hipStream_t);                                                  \
+    template void launch_seed_multi<R>(const SeedItem *, int, uint32_t, double *, hipStream_t);                      \
     template void launch_pauli_term<R>(const void *, void *, int, uint64_t, uint64_t, int, double, int, hipStream_t); \
     template void launch_pauli_sum<R>(const void *, void *, int, const HamTerm *, int, double *, double *, hipStream_t); \
     template void launch_advance2_seed<R>(void *, void *, void *, int, int, const double *, int, const double *, int, \

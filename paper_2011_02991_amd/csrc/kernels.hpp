@@ -101,6 +101,21 @@ template <typename R>
 void launch_advance_seed(void *psi, void *lam, void *phi, int n, int qr, const double *m_dev, int qs, int axis,
                          double *partials, double *dest, hipStream_t st);
 
+// Column seeds of several registers in one launch (the batched metric): item
+// k applies its forward rotations qa (matrix ma) then qb (mb) (-1: none) to
+// psi, then lam = psi, phi = sigma_qs psi, and its work-groups write partial
+// sums of <psi|sigma_qs|psi> at partials[2 * (block_begin .. block_begin +
+// nblocks - 1)] (sum them with launch_reduce_tasks).  Registers of >= 3 qubits;
+// block_begin ascending, total_blocks = the last item's end.
+struct SeedItem {
+    void *psi, *lam, *phi;
+    const double *ma, *mb;   // 8 doubles each (a, b, c, d as re, im), device
+    int32_t qa, qb, qs, axis, n;
+    uint32_t block_begin, nblocks;
+    int32_t pad;
+};
+template <typename R>
+void launch_seed_multi(const SeedItem *items, int n_items, uint32_t total_blocks, double *partials, hipStream_t st);
 // The same with two rotations before y_s (qa, ma first, then qb, mb; three
 // distinct qubits qa, qb, qc = the seeded column's qubit, n >= 3): one pass.
 template <typename R>
