@@ -93,7 +93,7 @@ def time_steps(ctx, circ, pr, prec, steps, warmup, profile=False, want_G=False, 
         res = ctx.step(circ, pr.theta, pr.dt, pr.tikhonov, prec=prec, want_G=want_G)
         for k, v in ctx.stats().items():
             # counters add up over the steps; settings are the last step's
-            acc[k] = v if k in ("block_columns", "tile_qubits", "target_tiles") else acc.get(k, 0) + v
+            acc[k] = v if k in ("block_columns", "tile_qubits", "target_tiles", "state_chunks") else acc.get(k, 0) + v
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     ctx.set_option(qng.OPT_PROFILE, 0)
@@ -456,9 +456,19 @@ def main():
                                                          / abs(res["dtheta"]).max())}
             if res.get("G") is not None and res_st.get("G") is not None:
                 states["max_abs_dG_vs_recurrence"] = float(abs(res_st["G"] - res["G"]).max())
+            # the memory dial: a quarter of the columns per chunk (two chunks
+            # kept at once), chunk i paired with every lower chunk
+            chunk = -(-(pr.n_params - 1) // 4)
+            ctx.set_option(qng.OPT_STATE_CHUNK, chunk)
+            t_ch, res_ch, st_ch = time_steps(ctx, circ, pr, args.prec, 1, 1, need_G=False)
+            states["chunked"] = {"chunk_columns": chunk, "chunks": st_ch["state_chunks"],
+                                 "kept_states_GiB": (2 * chunk + 3) * V / 2 ** 30, "s_per_step": t_ch,
+                                 "rel_ddtheta_vs_unchunked": float(abs(res_ch["dtheta"] - res_st["dtheta"]).max()
+                                                                   / abs(res_st["dtheta"]).max())}
         except qng.QNGError as e:
             states = {"error": str(e)}
         finally:
+            ctx.set_option(qng.OPT_STATE_CHUNK, 0)
             ctx.set_option(qng.OPT_METHOD, 0)
         log(f"derivative-state variant: {states}")
     gate = None

@@ -164,10 +164,20 @@ typedef enum {
                                     algorithm: every derivative state prepared from a rolling prefix and kept):
                                     the same tiled sweeps carry every column's derivative state to one common
                                     frame without forming any product, the P + 1 states are kept (P + 2 states of
-                                    device memory in all, QNG_E_OUT_OF_MEMORY if they do not fit) and all
-                                    inner products are one Gram matrix on the matrix cores (FP64 products and
-                                    sums).  Method 1 takes the plain gate set and the full metric
-                                    (QNG_E_UNSUPPORTED otherwise); qng_step_batched uses method 0. */
+                                    device memory in all) and all inner products are one Gram matrix on the
+                                    matrix cores (FP64 products and sums).  Where they do not fit (free device
+                                    memory, qng_set_mem_limit) or QNG_OPT_STATE_CHUNK asks for it, the columns
+                                    are prepared in chunks (see there).  Method 1 takes the plain gate set and
+                                    the full metric (QNG_E_UNSUPPORTED otherwise); qng_step_batched uses
+                                    method 0. */,
+    QNG_OPT_STATE_CHUNK = 13     /* method 1: at most this many derivative states per chunk (0 = automatic: all
+                                    P when they fit, else the most that fit).  With K > 1 chunks (whole column
+                                    blocks, two chunks kept at once: 2 x chunk + 3 states) chunk i's states are
+                                    paired with every chunk above it, which is prepared again each time:
+                                    1 + K (K - 1) / 2 preparations of a chunk's states in place of K, and the
+                                    same products.  QNG_E_OUT_OF_MEMORY when not even a chunk of one column
+                                    block fits.  Results agree with the unchunked run to rounding (the Gram
+                                    sums run in another order). */
 } qng_option;
 
 /* Counters of the last metric/energy/step call on a context. */
@@ -192,7 +202,8 @@ typedef struct {
     double  tune_ms;             /* qng_step_batched: wall-clock spent autotuning in this call */
     int64_t graph_replays;       /* qng_step_batched: register classes run as a replay of a captured graph */
     int32_t block_columns;       /* fused metric: columns per lambda sweep of the last call (0: none ran) */
-    int32_t reserved;
+    int32_t state_chunks;        /* derivative-state variant: chunks its columns were prepared in (1: every
+                                    state kept at once; 0: the variant did not run) */
 } qng_stats;
 
 /* Plan of a circuit under the current options (host only, no device work). */

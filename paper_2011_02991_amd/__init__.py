@@ -30,6 +30,7 @@ PRECISIONS = {"c128": C128, "complex128": C128, C128: C128, "c64": C64, "complex
 OPT_FUSION, OPT_TILE_QUBITS, OPT_COLUMN_STREAMS, OPT_PROFILE, OPT_SMALL_N_KERNEL, OPT_F64_REGISTERS = 0, 1, 2, 3, 4, 5
 OPT_GRAPH, OPT_AUTOTUNE, OPT_BATCH_TILES, OPT_BLOCK_COLUMNS, OPT_METRIC_KIND, OPT_EXACT_PRODUCTS = 6, 7, 8, 9, 10, 11
 OPT_METHOD = 12
+OPT_STATE_CHUNK = 13
 
 STATUS = {
     0: "QNG_OK", -1: "QNG_E_INVALID_ARG", -2: "QNG_E_BAD_CIRCUIT", -3: "QNG_E_BAD_PARAMS",
@@ -63,7 +64,7 @@ class Stats(ctypes.Structure):
                 ("sweep_bytes", ctypes.c_double), ("sweep_flops", ctypes.c_double), ("elements", ctypes.c_int64), ("other_launches", ctypes.c_int64),
                 ("metric_ms", ctypes.c_double), ("grad_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
                 ("tile_qubits", ctypes.c_int32), ("target_tiles", ctypes.c_int32), ("tune_ms", ctypes.c_double),
-                ("graph_replays", ctypes.c_int64), ("block_columns", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("graph_replays", ctypes.c_int64), ("block_columns", ctypes.c_int32), ("state_chunks", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -70,6 +70,7 @@ struct qng_ctx {
     int opt_exact_products = 1;   // complex64: every inner-product term in FP64 (0: FP32 thread shares)
     int opt_graph = 1, opt_autotune = 0, opt_batch_tiles = 0, opt_block = 0, opt_metric_kind = 0;
     int opt_method = 0;   // 0: recurrence with O(1) states; 1: P derivative states and their Gram matrix
+    int opt_state_chunk = 0;   // method 1: derivative states per chunk (0: automatic)
     std::vector<int> metric_blocks;   // block id per parameter (block-diagonal metric); empty = full
     std::string last_error;
     qng_stats stats{};
@@ -652,6 +653,7 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
     const SweepPlan *plan = nullptr;
     FusedRun fr;
     size_t scratch = 0, gram_bytes = 0;
+    int chunk_cols = 0;
     int n_states = spec.metric ? 4 : 2;   // the gradient alone needs psi and lambda = H psi
     int n_block_states = 0;
     if (fused) {
@@ -662,20 +664,35 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
                                      blocked ? &pb.rot_block : nullptr);
         size_t free_b = 0, total_b = 0;
         HIPCHECK(hipMemGetInfo(&free_b, &total_b));
-        size_t avail = free_b + ctx->ws_bytes;
+        const size_t avail = free_b + ctx->ws_bytes;
+        const size_t cap = ctx->mem_limit ? std::min(avail, ctx->mem_limit) : avail;
+        // the derivative-state variant: chunk_cols columns per chunk (all P - 1
+        // columns above column 0 when they fit), kept after the block registers
+        auto configure = [&](int cols) {
+            const size_t kept = states ? kept_states(c.P, cols) * V : 0;
+            fr = fused_config(*plan, ctx->opt_streams, V, cap > kept ? cap - kept : 0);
+            gram_bytes = states ? states_gram_bytes(n, c.P, cols) : 0;
+            scratch = fused_scratch_bytes(*plan, fr, c.M) + gram_bytes;
+            n_block_states = std::max(4, 1 + (plan->width + 1) * fr.B);
+            n_states = n_block_states + (states ? (int)kept_states(c.P, cols) : 0);
+            return plan_layout(n, c.P, param_map_ints(c), amp, n_states, spec.in_host != nullptr, scratch,
+                               spec.device_solve ? c.NP : -1).total;
+        };
         if (states) {
-            const size_t need = (size_t)(c.P + 2) * V;
-            if (need > avail)
-                fail(QNG_E_OUT_OF_MEMORY, "the derivative-state variant keeps " + std::to_string(c.P + 2) +
-                                              " states of " + std::to_string(V) + " bytes; " +
-                                              std::to_string(avail) + " bytes are free");
-            avail -= need;
-            gram_bytes = align256(gram_partial_bytes(n, c.P + 1));
+            const int all = c.P - 1;
+            chunk_cols = ctx->opt_state_chunk > 0 ? std::min(ctx->opt_state_chunk, all) : all;
+            if (ctx->opt_state_chunk == 0) {
+                // the most columns per chunk that fit (two chunks held at once below all)
+                while (chunk_cols >= plan->width && configure(chunk_cols) > cap)
+                    chunk_cols = chunk_cols == all ? all / 2 : chunk_cols - 1;
+                if (chunk_cols < plan->width)
+                    fail(QNG_E_OUT_OF_MEMORY, "the derivative-state variant needs at least " +
+                                                  std::to_string(kept_states(c.P, plan->width)) + " states of " +
+                                                  std::to_string(V) + " bytes (chunks of one column block); " +
+                                                  std::to_string(cap) + " bytes are available");
+            }
         }
-        fr = fused_config(*plan, ctx->opt_streams, V, avail);
-        scratch = fused_scratch_bytes(*plan, fr, c.M) + gram_bytes;
-        n_block_states = std::max(4, 1 + (plan->width + 1) * fr.B);
-        n_states = n_block_states + (states ? c.P + 2 : 0);   // then the dummy phi and the P + 1 kept states
+        configure(chunk_cols);
         ctx->stats.block_columns = plan->width;
     }
     std::shared_ptr<const SweepPlan> gplan;
@@ -733,7 +750,9 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
     if (spec.metric) {
         auto t0 = Clock::now();
         e.init(in_c128);
-        if (c.P) HIPCHECK(hipMemsetAsync(e.lraw(), 0, (size_t)c.P * c.P * 16, st));
+        // raw L and T (T right after L); the derivative-state variant without
+        // the complex G writes the real parts of T alone
+        if (c.P) HIPCHECK(hipMemsetAsync(e.lraw(), 0, ((size_t)c.P * c.P + c.P) * 16, st));
         if (fused) {
             FusedBuffers fb;
             fb.states = base + L.states;
@@ -746,11 +765,15 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
             if (states) {
                 fb.scratch_bytes = L.sweep_bytes - gram_bytes;
                 fb.gram_partials = (double *)(base + L.sweep + fb.scratch_bytes);
+                fb.gram_signs = (int8_t *)(base + L.sweep + L.sweep_bytes) - align256((size_t)c.P + 1 + 64);
                 fb.dummy = base + L.states + (size_t)n_block_states * L.state_bytes;
                 fb.xi = fb.dummy + L.state_bytes;
+                pos = run_states_metric<R>(*plan, fr, c, pb.fwd, pb.adj, fb, chunk_cols, [&] { e.init(in_c128); }, st,
+                                           &ctx->stats, ctx->opt_profile != 0, spec.real_products);
+            } else {
+                pos = run_fused_metric<R>(*plan, fr, c, pb.fwd, pb.adj, fb, st, &ctx->stats, ctx->opt_profile != 0,
+                                          sweep_reg_mode(ctx, amp), spec.real_products);
             }
-            pos = run_fused_metric<R>(*plan, fr, c, pb.fwd, pb.adj, fb, st, &ctx->stats, ctx->opt_profile != 0,
-                                      sweep_reg_mode(ctx, amp), spec.real_products);
         } else if (step_width > 0) {
             pos = e.metric_stepped(step_width);
         } else {
@@ -1264,6 +1287,10 @@ qng_status qng_set_option(qng_ctx *ctx, int option, int value) {
         case QNG_OPT_METHOD:
             if (value < 0 || value > 1) fail(QNG_E_INVALID_ARG, "method must be 0 (recurrence) or 1 (derivative states)");
             ctx->opt_method = value;
+            break;
+        case QNG_OPT_STATE_CHUNK:
+            if (value < 0) fail(QNG_E_INVALID_ARG, "state chunk < 0");
+            ctx->opt_state_chunk = value;
             break;
         case QNG_OPT_METRIC_KIND:
             if (value < 0 || value > 1) fail(QNG_E_INVALID_ARG, "metric kind must be 0 (G) or 1 (L)");

@@ -89,11 +89,13 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
     // the phi register k of the block whose top column is s: the kept state of
     // its column in the derivative-state variant (the lowest block's register
     // below column 1 is never seeded and goes to the dummy state)
+    char *const xi_chunk = buf.xi_chunk ? buf.xi_chunk : buf.xi + 2 * V;
     auto xi_of = [&](int s, int b, int k) -> void * {
         if (!states) return reg(b, 1 + k);
         const int col = s - (W - 1) + k;
-        return col >= 1 ? (void *)(buf.xi + (size_t)(1 + col) * V) : (void *)buf.dummy;
+        return col >= 1 ? (void *)(xi_chunk + (size_t)(col - buf.chunk_col0) * V) : (void *)buf.dummy;
     };
+    const int blk_begin = buf.blk_begin, blk_end = buf.blk_end < 0 ? ncols : std::min(buf.blk_end, ncols);
 
     // ---- launch schedule (host)
     std::vector<LaunchItem> items;
@@ -102,10 +104,10 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
     std::vector<Group> groups;
     int64_t elements = 0;
     items.reserve(plan.dev_passes.size());
-    for (int g0 = 0; g0 < ncols; g0 += B) {
+    for (int g0 = blk_begin; g0 < blk_end; g0 += B) {
         Group G;
         G.col_begin = g0;
-        G.col_end = std::min(ncols, g0 + B);
+        G.col_end = std::min(blk_end, g0 + B);
         G.launch_begin = launches.size();
         size_t maxp = 0;
         for (int col = G.col_begin; col < G.col_end; ++col) maxp = std::max(maxp, plan.cols[col].passes.size());
@@ -183,30 +185,6 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
     DevOp *d_ops = (DevOp *)take(plan.dev_ops.size() * sizeof(DevOp));
     DevMap *d_maps = (DevMap *)take(plan.dev_maps.size() * sizeof(DevMap));
     LaunchItem *d_items = (LaunchItem *)take(items.size() * sizeof(LaunchItem));
-    // derivative-state variant: the sign each kept state carries.  A rotation
-    // whose adjoint has cos(theta/2) < 0 is applied negated to every register
-    // of a sweep (circuit.hpp, adjoint_shear), which cancels in the recurrence's
-    // products but not between states of different blocks.  In the block with
-    // top column s, lambda (seeded unsigned at y_s) and the top phi register
-    // pass through the adjoints of rotations s-1 .. 1; a lower column s_b is
-    // seeded from lambda just after the adjoint of rotation s_b, so it carries
-    // the signs of rotations s-1 .. s_b from lambda and those of s_b - 1 .. 1
-    // after: every register of the block ends with the product of the signs of
-    // rotations 1 .. s-1.  lambda* and column 0's state carry none.
-    std::vector<int8_t> signs;
-    int8_t *d_signs = nullptr;
-    if (states) {
-        std::vector<int8_t> prefix((size_t)c.P + 1, 1);   // prefix[s]: signs of rotations 1 .. s-1
-        for (int s = 2; s <= c.P; ++s)
-            prefix[s] = (int8_t)(adj[c.rots[s - 1].pos].a.real() < 0 ? -prefix[s - 1] : prefix[s - 1]);
-        signs.assign((size_t)c.P + 1, 1);
-        for (const ColumnPlan &cp : plan.cols)
-            for (int k = 0; k < W; ++k) {
-                const int col = cp.s - (W - 1) + k;
-                if (col >= 1) signs[1 + col] = prefix[cp.s];
-            }
-        d_signs = (int8_t *)take(signs.size());
-    }
     ReduceTask *d_tasks = (ReduceTask *)take(tasks.size() * sizeof(ReduceTask));
     // the forward register's way between block tops as tile passes (the
     // recurrence only): the gates' own shears, one item per pass on psi.  A
@@ -278,7 +256,6 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
         FCHECK(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(LaunchItem), hipMemcpyHostToDevice, st));
     if (!tasks.empty())
         FCHECK(hipMemcpyAsync(d_tasks, tasks.data(), tasks.size() * sizeof(ReduceTask), hipMemcpyHostToDevice, st));
-    if (d_signs) FCHECK(hipMemcpyAsync(d_signs, signs.data(), signs.size(), hipMemcpyHostToDevice, st));
     if (fp) {
         FCHECK(hipMemcpyAsync(d_fsh, fshear.data(), fshear.size() * 8, hipMemcpyHostToDevice, st));
         FCHECK(hipMemcpyAsync(d_fsh32, fshear32.data(), fshear32.size() * 4, hipMemcpyHostToDevice, st));
@@ -460,17 +437,6 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
         launch_apply_1q<R>(psi, nullptr, n, 0, DevMat2{-1, 0, 0, 0, 0, 0, -1, 0}, st);
         ++stats->other_launches;
     }
-    if (states) {
-        // every inner product at once: Re (and, for the complex G, Im) of the
-        // Gram matrix of lambda* and the P derivative states, on the matrix cores
-        const bool c64 = sizeof(R) == 4;
-        launch_gram(buf.xi, c64, n, c.P + 1, c.P, 0, d_signs, buf.gram_partials, buf.lraw, buf.traw, st);
-        stats->other_launches += 2;
-        if (!real_products) {
-            launch_gram(buf.xi, c64, n, c.P + 1, c.P, 1, d_signs, buf.gram_partials, buf.lraw, buf.traw, st);
-            stats->other_launches += 2;
-        }
-    }
     stats->elements += elements;
     if (profile) {
         FCHECK(hipStreamSynchronize(st));
@@ -482,6 +448,137 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
         }
         stats->sweep_ms += tot;
         for (auto &e : ev) (void)hipEventDestroy(e);
+    }
+    return pos;
+}
+
+std::vector<StateChunk> state_chunks(const SweepPlan &plan, int max_cols) {
+    const int W = plan.width;
+    std::vector<StateChunk> out;
+    int prev_hi = 0;
+    for (int k = 0; k < (int)plan.cols.size(); ++k) {
+        const int hi = plan.cols[k].s, lo = std::max(1, hi - W + 1);
+        if (lo != prev_hi + 1) fail(QNG_E_DEVICE, "derivative states: column blocks out of order (internal)");
+        prev_hi = hi;
+        if (hi - lo + 1 > max_cols)
+            fail(QNG_E_OUT_OF_MEMORY, "derivative states: a block of " + std::to_string(hi - lo + 1) +
+                                          " columns does not fit in a chunk of " + std::to_string(max_cols));
+        if (out.empty() || hi - out.back().col_lo + 1 > max_cols) out.push_back(StateChunk{k, k, lo, hi});
+        out.back().blk_end = k + 1;
+        out.back().col_hi = hi;
+    }
+    return out;
+}
+
+size_t kept_states(int P, int max_cols) {
+    const int all = P - 1;
+    return max_cols >= all ? (size_t)all + 3 : 2 * (size_t)max_cols + 3;
+}
+
+size_t states_gram_bytes(int n, int P, int max_cols) {
+    const int all = P - 1;
+    const int cmax = std::min(max_cols, all);
+    // the largest of the calls' buffers (a smaller operand may take more chunks
+    // of K): the shape depends on the operands' tile counts alone
+    size_t b = 0;
+    for (int t = 1; t <= (2 + cmax + 63) / 64; ++t) b = std::max(b, gram_partial_bytes(n, 64 * t, 0));
+    if (cmax < all)
+        for (int ta = 1; ta <= (cmax + 63) / 64; ++ta)
+            for (int tb = 1; tb <= (cmax + 63) / 64; ++tb) b = std::max(b, gram_partial_bytes(n, 64 * ta, 64 * tb));
+    return align256(b + 64) + align256((size_t)P + 1 + 64);
+}
+
+template <typename R>
+int run_states_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c, const std::vector<Mat2> &fwd,
+                      const std::vector<Mat2> &adj, const FusedBuffers &buf, int max_cols,
+                      const std::function<void()> &restart, hipStream_t st, qng_stats *stats, bool profile,
+                      bool real_products) {
+    const size_t V = buf.state_bytes;
+    const int W = plan.width;
+    const std::vector<StateChunk> ch = state_chunks(plan, max_cols);
+    const int K = (int)ch.size();
+    // The sign each kept state carries.  A rotation whose adjoint has
+    // cos(theta/2) < 0 is applied negated to every register of a sweep
+    // (circuit.hpp, adjoint_shear), which cancels in the recurrence's products
+    // but not between states of different blocks.  In the block with top
+    // column s, lambda (seeded unsigned at y_s) and the top phi register pass
+    // through the adjoints of rotations s-1 .. 1; a lower column s_b is seeded
+    // from lambda just after the adjoint of rotation s_b, so it carries the
+    // signs of rotations s-1 .. s_b from lambda and those of s_b - 1 .. 1
+    // after: every register of the block ends with the product of the signs of
+    // rotations 1 .. s-1.  lambda* and column 0's state carry none.  Indexed
+    // by column + 1.
+    std::vector<int8_t> prefix((size_t)c.P + 1, 1);   // prefix[s]: signs of rotations 1 .. s-1
+    for (int s = 2; s <= c.P; ++s)
+        prefix[s] = (int8_t)(adj[c.rots[s - 1].pos].a.real() < 0 ? -prefix[s - 1] : prefix[s - 1]);
+    std::vector<int8_t> signs((size_t)c.P + 1, 1);
+    for (const ColumnPlan &cp : plan.cols)
+        for (int k = 0; k < W; ++k) {
+            const int col = cp.s - (W - 1) + k;
+            if (col >= 1) signs[1 + col] = prefix[cp.s];
+        }
+    FCHECK(hipMemcpyAsync(buf.gram_signs, signs.data(), signs.size(), hipMemcpyHostToDevice, st));
+    FCHECK(hipStreamSynchronize(st));   // `signs` is released at return
+    stats->state_chunks = K;
+
+    const bool c64 = sizeof(R) == 4;
+    int cmax = 0;
+    for (const StateChunk &k : ch) cmax = std::max(cmax, k.col_hi - k.col_lo + 1);
+    char *ra = buf.xi + 2 * V;             // the chunk whose own products are taken next
+    char *rb = ra + (size_t)cmax * V;      // the chunks paired with it
+    int pos = 0;
+    bool first = true;
+    auto ncol = [&](int k) { return ch[k].col_hi - ch[k].col_lo + 1; };
+    auto prep = [&](int k, char *region) {
+        if (!first) restart();
+        first = false;
+        FusedBuffers b = buf;
+        b.blk_begin = ch[k].blk_begin;
+        b.blk_end = ch[k].blk_end;
+        b.xi_chunk = region;
+        b.chunk_col0 = ch[k].col_lo;
+        pos = run_fused_metric<R>(plan, fr, c, fwd, adj, b, st, stats, profile, 0, real_products);
+    };
+    // Re (and, for the complex G, Im) of the inner products, on the matrix cores
+    auto gram = [&](const GramSet &A, const GramSet *B) {
+        for (int mode = 0; mode < (real_products ? 1 : 2); ++mode) {
+            launch_gram(A, B, c64, c.n, c.P, mode, buf.gram_signs, buf.gram_partials, buf.lraw, buf.traw, st);
+            stats->other_launches += 2;
+        }
+    };
+    // lambda*, column 0 and chunk k among themselves
+    auto own = [&](int k, char *region) {
+        GramSet A;
+        A.p1 = buf.xi;
+        A.n1 = 2;
+        A.p2 = region;
+        A.n = 2 + ncol(k);
+        A.col1 = -1;
+        A.col2 = ch[k].col_lo;
+        gram(A, nullptr);
+    };
+    auto chunk_set = [&](int k, char *region) {
+        GramSet S;
+        S.p1 = region;
+        S.n1 = S.n = ncol(k);
+        S.col1 = ch[k].col_lo;
+        return S;
+    };
+    // The top chunk first; chunk i is paired with every chunk below it, the
+    // lowest first, so that the last one prepared (chunk i - 1) is the next to
+    // take its own products: 1 + K (K - 1) / 2 preparations in all, the
+    // repeated ones those of the lower chunks, whose sweeps are the shorter.
+    // The forward state is left where the last preparation leaves it (pos).
+    prep(K - 1, ra);
+    own(K - 1, ra);
+    for (int i = K - 1; i > 0; --i) {
+        for (int j = 0; j < i; ++j) {
+            prep(j, rb);
+            const GramSet A = chunk_set(j, rb), B = chunk_set(i, ra);
+            gram(A, &B);
+        }
+        std::swap(ra, rb);
+        own(i - 1, ra);
     }
     return pos;
 }
@@ -600,5 +697,12 @@ template int run_fused_metric<double>(const SweepPlan &, const FusedRun &, const
 template int run_fused_metric<float>(const SweepPlan &, const FusedRun &, const Circuit &, const std::vector<Mat2> &,
                                      const std::vector<Mat2> &, const FusedBuffers &, hipStream_t, qng_stats *, bool, int,
                                      bool);
+
+template int run_states_metric<double>(const SweepPlan &, const FusedRun &, const Circuit &, const std::vector<Mat2> &,
+                                       const std::vector<Mat2> &, const FusedBuffers &, int,
+                                       const std::function<void()> &, hipStream_t, qng_stats *, bool, bool);
+template int run_states_metric<float>(const SweepPlan &, const FusedRun &, const Circuit &, const std::vector<Mat2> &,
+                                      const std::vector<Mat2> &, const FusedBuffers &, int,
+                                      const std::function<void()> &, hipStream_t, qng_stats *, bool, bool);
 
 }  // namespace qng

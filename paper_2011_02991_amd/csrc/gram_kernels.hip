@@ -16,7 +16,7 @@
 // are converted, exactly, when a tile is staged) and accumulated in FP64.
 //
 // Work split: the Q columns are cut into tiles of 64; a work-group owns one
-// pair of tiles (ta <= tb) and one chunk of K, stages 32 reals of each of its
+// pair of tiles (ta <= tb; with two operands, a tile of each) and one chunk of K, stages 32 reals of each of its
 // 128 columns per step in LDS (FP64) and accumulates a 64 x 64 block of the
 // result in the MFMA accumulators (4 wavefronts, 32 x 32 each, as 2 x 2 MFMA
 // blocks).  Pairs vary fastest over the work-groups, so the work-groups of one
@@ -26,6 +26,7 @@
 // entries in the layout of the recurrent method's raw L and T.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "gram_kernels.hpp"
@@ -50,25 +51,36 @@ __device__ __forceinline__ void tile_pair(int pair, int ntile, int &ta, int &tb)
     tb = ta + pair;
 }
 
-// Eight consecutive reals of column q from real k (k a multiple of 8), as FP64;
-// zeros past the last column or past K (K = 2^(n+1) is a multiple of 8 from
-// n = 2 on; below that the tail is read element by element).
-__device__ __forceinline__ void load8(const float *X, uint64_t stride, int q, int Q, uint64_t k, uint64_t K,
+// An operand's states on the device (see GramSet): position q at p1 + q *
+// stride below n1, else at p2 + (q - n1) * stride.
+template <typename R> struct DevSet {
+    const R *p1, *p2;
+    int n1, n;
+};
+template <typename R>
+__device__ __forceinline__ const R *state_ptr(const DevSet<R> &s, int q, uint64_t stride) {
+    return q < s.n1 ? s.p1 + (uint64_t)q * stride : s.p2 + (uint64_t)(q - s.n1) * stride;
+}
+
+// Eight consecutive reals of position q from real k (k a multiple of 8), as
+// FP64; zeros past the last position or past K (K = 2^(n+1) is a multiple of
+// 8 from n = 2 on; below that the tail is read element by element).
+__device__ __forceinline__ void load8(const DevSet<float> &s, uint64_t stride, int q, uint64_t k, uint64_t K,
                                       double (&v)[8]) {
-    if (q < Q && k + 8 <= K) {
-        const float4 *p = (const float4 *)(X + (uint64_t)q * stride + k);
+    if (q < s.n && k + 8 <= K) {
+        const float4 *p = (const float4 *)(state_ptr(s, q, stride) + k);
         const float4 a = p[0], b = p[1];
         v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
         v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
     } else {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = (q < Q && k + j < K) ? (double)X[(uint64_t)q * stride + k + j] : 0.0;
+        for (int j = 0; j < 8; ++j) v[j] = (q < s.n && k + j < K) ? (double)state_ptr(s, q, stride)[k + j] : 0.0;
     }
 }
-__device__ __forceinline__ void load8(const double *X, uint64_t stride, int q, int Q, uint64_t k, uint64_t K,
+__device__ __forceinline__ void load8(const DevSet<double> &s, uint64_t stride, int q, uint64_t k, uint64_t K,
                                       double (&v)[8]) {
-    if (q < Q && k + 8 <= K) {
-        const double2 *p = (const double2 *)(X + (uint64_t)q * stride + k);
+    if (q < s.n && k + 8 <= K) {
+        const double2 *p = (const double2 *)(state_ptr(s, q, stride) + k);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const double2 a = p[j];
@@ -77,16 +89,18 @@ __device__ __forceinline__ void load8(const double *X, uint64_t stride, int q, i
         }
     } else {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = (q < Q && k + j < K) ? X[(uint64_t)q * stride + k + j] : 0.0;
+        for (int j = 0; j < 8; ++j) v[j] = (q < s.n && k + j < K) ? state_ptr(s, q, stride)[k + j] : 0.0;
     }
 }
 
-// X: Q columns of K reals each, column q at X + q * stride.  kc: reals per chunk
-// (a multiple of kStep).  partials: [chunk][pair][64][64] doubles.
+// A, B: the operands (B read only when rect), K reals per state, states
+// `stride` reals apart.  kc: reals per chunk (a multiple of kStep).  rect: the
+// tile pairs are every (ta, tb) of A's ntA and B's ntB tiles; else the pairs
+// ta <= tb of A's.  partials: [chunk][pair][64][64] doubles.
 template <typename R>
-__global__ __launch_bounds__(kGramThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_gram(const R *__restrict__ X, uint64_t stride, int Q, uint64_t K,
-                                                       uint64_t kc, int ntile, int npairs, int mode,
-                                                       bool nchunks_xcd, double *__restrict__ partials) {
+__global__ __launch_bounds__(kGramThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_gram(
+    const DevSet<R> A, const DevSet<R> B, bool rect, uint64_t stride, uint64_t K, uint64_t kc, int ntA, int ntB,
+    int npairs, int mode, bool nchunks_xcd, double *__restrict__ partials) {
     __shared__ double sA[kTile * kPad];
     __shared__ double sB[kTile * kPad];
     // Work-groups are dealt to the 8 XCDs round robin (work-group b runs on XCD
@@ -103,8 +117,14 @@ __global__ __launch_bounds__(kGramThreads) __attribute__((amdgpu_waves_per_eu(4,
         chunk = (int)(blockIdx.x / (unsigned)npairs);
     }
     int ta, tb;
-    tile_pair(pair, ntile, ta, tb);
-    const bool same = ta == tb && mode == 0;   // one tile serves both operands
+    if (rect) {
+        ta = pair / ntB;
+        tb = pair % ntB;
+    } else {
+        tile_pair(pair, ntA, ta, tb);
+    }
+    const DevSet<R> &SB = rect ? B : A;
+    const bool same = !rect && ta == tb && mode == 0;   // one tile serves both operands
     const double *sBv = same ? sA : sB;
 
     const int tid = threadIdx.x;
@@ -118,8 +138,8 @@ __global__ __launch_bounds__(kGramThreads) __attribute__((amdgpu_waves_per_eu(4,
     // the next step's reals are loaded into registers while the current step's
     // MFMAs run, then written to LDS between the two barriers
     double va[8], vb[8];
-    load8(X, stride, ta * kTile + lcol, Q, kbeg + part * 8, K, va);
-    if (!same) load8(X, stride, tb * kTile + lcol, Q, kbeg + part * 8, K, vb);
+    load8(A, stride, ta * kTile + lcol, kbeg + part * 8, K, va);
+    if (!same) load8(SB, stride, tb * kTile + lcol, kbeg + part * 8, K, vb);
     for (uint64_t k0 = kbeg; k0 < kend; k0 += kStep) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) sA[lcol * kPad + part * 8 + j] = va[j];
@@ -138,8 +158,8 @@ __global__ __launch_bounds__(kGramThreads) __attribute__((amdgpu_waves_per_eu(4,
         __syncthreads();
         const uint64_t kn = k0 + kStep;
         if (kn < kend) {
-            load8(X, stride, ta * kTile + lcol, Q, kn + part * 8, K, va);
-            if (!same) load8(X, stride, tb * kTile + lcol, Q, kn + part * 8, K, vb);
+            load8(A, stride, ta * kTile + lcol, kn + part * 8, K, va);
+            if (!same) load8(SB, stride, tb * kTile + lcol, kn + part * 8, K, vb);
         }
         // A(row = lane % 16, k = lane / 16), B(k = lane / 16, col = lane % 16)
         const int r0 = wr * 32 + (lane & 15), c0 = wc * 32 + (lane & 15);
@@ -168,26 +188,39 @@ __global__ __launch_bounds__(kGramThreads) __attribute__((amdgpu_waves_per_eu(4,
     }
 }
 
+// Positions and columns of an operand (see GramSet).
+struct SetCols {
+    int n1, n, col1, col2;
+};
+__device__ __forceinline__ int column_of(const SetCols &s, int q) { return q < s.n1 ? s.col1 + q : s.col2 + q - s.n1; }
+
 // One thread per entry of a computed block: the chunks' partials summed in
-// order, times sign[qa] sign[qb] (each kept state is its column's derivative
-// state up to a known sign), and entry (qa, qb), qa < qb, goes to the raw
-// metric: qa = 0 -> T of column qb - 1, qa >= 1 -> L of (qa - 1, qb - 1); the
-// real part (mode 0) or the imaginary part (mode 1) of the complex result.
-__global__ void k_gram_reduce(const double *__restrict__ partials, int npairs, int nchunks, int ntile, int Q, int P,
-                              int mode, const int8_t *__restrict__ sign, double *__restrict__ lraw,
-                              double *__restrict__ traw) {
+// order, times sign[ca + 1] sign[cb + 1] (each kept state is its column's
+// derivative state up to a known sign), and the entry of columns ca < cb goes
+// to the raw metric: ca = -1 -> T of column cb, else L of (ca, cb); the real
+// part (mode 0) or the imaginary part (mode 1) of the complex result.
+__global__ void k_gram_reduce(const double *__restrict__ partials, int npairs, int nchunks, bool rect, int ntA,
+                              int ntB, SetCols A, SetCols B, int P, int mode, const int8_t *__restrict__ sign,
+                              double *__restrict__ lraw, double *__restrict__ traw) {
     const uint64_t idx = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     if (idx >= (uint64_t)npairs * kTile * kTile) return;
     const int pair = (int)(idx / (kTile * kTile));
     const int e = (int)(idx % (kTile * kTile));
     int ta, tb;
-    tile_pair(pair, ntile, ta, tb);
+    if (rect) {
+        ta = pair / ntB;
+        tb = pair % ntB;
+    } else {
+        tile_pair(pair, ntA, ta, tb);
+    }
+    const SetCols &SB = rect ? B : A;
     const int qa = ta * kTile + e / kTile, qb = tb * kTile + e % kTile;
-    if (qa >= qb || qb >= Q) return;
+    if (qa >= A.n || qb >= SB.n || (!rect && qa >= qb)) return;
+    const int ca = column_of(A, qa), cb = column_of(SB, qb);
     double s = 0.0;
     for (int c = 0; c < nchunks; ++c) s += partials[((uint64_t)c * npairs + pair) * (kTile * kTile) + e];
-    if (sign[qa] != sign[qb]) s = -s;
-    double *dst = qa == 0 ? traw + 2 * (uint64_t)(qb - 1) : lraw + 2 * ((uint64_t)(qa - 1) * P + (qb - 1));
+    if (sign[ca + 1] != sign[cb + 1]) s = -s;
+    double *dst = ca < 0 ? traw + 2 * (uint64_t)cb : lraw + 2 * ((uint64_t)ca * P + cb);
     dst[mode] = s;
 }
 
@@ -197,55 +230,67 @@ inline void check_launch() {
 }
 
 struct GramShape {
-    int ntile, npairs, nchunks;
+    int ntA, ntB, npairs, nchunks;
     uint64_t K, kc;
 };
 
-GramShape gram_shape(int n, int Q) {
+GramShape gram_shape(int n, int QA, int QB) {
     GramShape g;
-    g.ntile = (Q + kTile - 1) / kTile;
-    g.npairs = g.ntile * (g.ntile + 1) / 2;
+    g.ntA = (QA + kTile - 1) / kTile;
+    g.ntB = QB > 0 ? (QB + kTile - 1) / kTile : g.ntA;
+    g.npairs = QB > 0 ? g.ntA * g.ntB : g.ntA * (g.ntA + 1) / 2;
     g.K = uint64_t(2) << n;
     // about 3072 work-groups in all, chunks a power of two of at least kStep reals
     uint64_t want = (3072 + (uint64_t)g.npairs - 1) / (uint64_t)g.npairs;
     uint64_t nch = 1;
     while (nch < want) nch <<= 1;
     while (nch > 1 && g.K / nch < (uint64_t)kStep) nch >>= 1;
+    // partial sums within max(32 bytes per amplitude, 8 MiB): next to nothing
+    // beside the states from 22 qubits on, and small registers stay small
+    const uint64_t cap = std::max<uint64_t>(uint64_t(32) << n, uint64_t(8) << 20) / (kTile * kTile * sizeof(double));
+    while (nch > 1 && nch * (uint64_t)g.npairs > cap) nch >>= 1;
     g.nchunks = (int)nch;
     g.kc = g.K / nch;
     if (g.kc < (uint64_t)kStep) g.kc = kStep;
     return g;
 }
 
+template <typename R> DevSet<R> dev_set(const GramSet &s) {
+    return DevSet<R>{(const R *)s.p1, (const R *)s.p2, s.n1, s.n};
+}
+
 }  // namespace
 
-size_t gram_partial_bytes(int n, int Q) {
-    const GramShape g = gram_shape(n, Q);
+size_t gram_partial_bytes(int n, int QA, int QB) {
+    const GramShape g = gram_shape(n, QA, QB);
     return (size_t)g.nchunks * g.npairs * kTile * kTile * sizeof(double);
 }
 
-void launch_gram(const void *X, bool complex64, int n, int Q, int P, int mode, const int8_t *sign, double *partials,
-                 double *lraw, double *traw, hipStream_t st) {
-    if (Q < 2) return;
-    const GramShape g = gram_shape(n, Q);
+void launch_gram(const GramSet &A, const GramSet *B, bool complex64, int n, int P, int mode, const int8_t *sign,
+                 double *partials, double *lraw, double *traw, hipStream_t st) {
+    const bool rect = B != nullptr;
+    if (rect ? (A.n < 1 || B->n < 1) : A.n < 2) return;
+    const GramSet &Bs = rect ? *B : A;
+    const GramShape g = gram_shape(n, A.n, rect ? Bs.n : 0);
     const uint64_t stride = g.K;
     const unsigned blocks = (unsigned)((uint64_t)g.npairs * g.nchunks);
     const bool xcd = g.nchunks % 8 == 0;
     if (complex64)
-        hipLaunchKernelGGL(k_gram<float>, dim3(blocks), dim3(kGramThreads), 0, st, (const float *)X, stride, Q, g.K,
-                           g.kc, g.ntile, g.npairs, mode, xcd, partials);
+        hipLaunchKernelGGL(k_gram<float>, dim3(blocks), dim3(kGramThreads), 0, st, dev_set<float>(A),
+                           dev_set<float>(Bs), rect, stride, g.K, g.kc, g.ntA, g.ntB, g.npairs, mode, xcd, partials);
     else
-        hipLaunchKernelGGL(k_gram<double>, dim3(blocks), dim3(kGramThreads), 0, st, (const double *)X, stride, Q, g.K,
-                           g.kc, g.ntile, g.npairs, mode, xcd, partials);
+        hipLaunchKernelGGL(k_gram<double>, dim3(blocks), dim3(kGramThreads), 0, st, dev_set<double>(A),
+                           dev_set<double>(Bs), rect, stride, g.K, g.kc, g.ntA, g.ntB, g.npairs, mode, xcd, partials);
     check_launch();
     const uint64_t entries = (uint64_t)g.npairs * kTile * kTile;
     hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, st, partials, g.npairs,
-                       g.nchunks, g.ntile, Q, P, mode, sign, lraw, traw);
+                       g.nchunks, rect, g.ntA, g.ntB, SetCols{A.n1, A.n, A.col1, A.col2},
+                       SetCols{Bs.n1, Bs.n, Bs.col1, Bs.col2}, P, mode, sign, lraw, traw);
     check_launch();
 }
 
-double gram_flops(int n, int Q) {
-    const GramShape g = gram_shape(n, Q);
+double gram_flops(int n, int QA, int QB) {
+    const GramShape g = gram_shape(n, QA, QB);
     return 2.0 * (double)g.npairs * kTile * kTile * (double)g.K;
 }
 

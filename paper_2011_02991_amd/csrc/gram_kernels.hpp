@@ -9,19 +9,31 @@
 
 namespace qng {
 
-// Bytes of the partial-sum buffer launch_gram needs for Q states of n qubits.
-size_t gram_partial_bytes(int n, int Q);
+// One operand of launch_gram: positions 0 .. n1-1 are the states at p1 (one
+// after another, 2^n complex amplitudes each), positions n1 .. n-1 those at
+// p2; position q holds the state of column col1 + q (q < n1) or of column
+// col2 + q - n1, where column -1 stands for the forward state lambda*.
+struct GramSet {
+    const void *p1 = nullptr, *p2 = nullptr;
+    int n1 = 0, n = 0;
+    int col1 = 0, col2 = 0;
+};
 
-// X: Q states of 2^n complex amplitudes one after another (complex64 or
-// complex128), X_0 the forward state lambda* and X_{1+s} the derivative state
-// of column s, all in one frame, each up to the sign sign[q] (+-1, device).
-// mode 0 writes Re and mode 1 Im of sign[a] sign[b] <X_a|X_b> for a < b: a = 0
-// into traw[b-1] (complex, that part only), a >= 1 into lraw[(a-1)*P + (b-1)]
-// (complex, that part only).
-void launch_gram(const void *X, bool complex64, int n, int Q, int P, int mode, const int8_t *sign, double *partials,
-                 double *lraw, double *traw, hipStream_t st);
+// Bytes of the partial-sum buffer launch_gram needs for QA x QB states of n
+// qubits (QB = 0: the symmetric product of QA states).
+size_t gram_partial_bytes(int n, int QA, int QB);
+
+// The inner products of kept states (complex64 or complex128, each up to the
+// sign sign[column + 1] = +-1, device).  B == nullptr: every pair of positions
+// a < b of A, whose columns ascend with the position; else every pair of a
+// position of A and one of B, every column of B above every column of A.  For
+// each pair, columns ca < cb, mode 0 writes Re and mode 1 Im of sign[ca + 1]
+// sign[cb + 1] <X_a|X_b>: ca = -1 into traw[cb] (complex, that part only),
+// else into lraw[ca * P + cb] (complex, that part only).
+void launch_gram(const GramSet &A, const GramSet *B, bool complex64, int n, int P, int mode, const int8_t *sign,
+                 double *partials, double *lraw, double *traw, hipStream_t st);
 
 // Multiply-add flops (2 per term) of one launch_gram mode, tiles included.
-double gram_flops(int n, int Q);
+double gram_flops(int n, int QA, int QB);
 
 }  // namespace qng

@@ -8,7 +8,8 @@ kappa 1e-14)), against the recurrent method on every entry, and on the edge
 cases: registers of 2 and 3 qubits (fewer reals per state than one staging
 step of the Gram kernel), two parameters, odd P, blocks of one, two and
 four columns, permuted and shared parameters, the complex G output (the Gram
-matrix's imaginary part) and the step without it."""
+matrix's imaginary part) and the step without it; and the same a chunk of
+column blocks at a time (chunks forced, and chosen under a memory limit)."""
 import sys
 
 import numpy as np
@@ -113,14 +114,117 @@ def test_states_rejections(env):
         step(q, ctx, pr, 1)
     assert e.value.name == "QNG_E_UNSUPPORTED"
     pr = W.scaled(W.config1, 14, 2, n_terms=3)
-    # the P + 2 = 58 kept states of 256 KiB take 14.5 MiB, above a context limit of 8 MiB
-    ctx.set_mem_limit(8 << 20)
+    # the Gram matrix's partial sums alone take 8 MiB at 14 qubits
+    ctx.set_mem_limit(4 << 20)
     try:
         with pytest.raises(q.QNGError) as e:
             step(q, ctx, pr, 1)
         assert e.value.name == "QNG_E_OUT_OF_MEMORY"
+        with pytest.raises(q.QNGError) as e:
+            ctx.set_option(q.OPT_STATE_CHUNK, -1)
+        assert e.value.name == "QNG_E_INVALID_ARG"
     finally:
         ctx.set_mem_limit(0)
+
+
+def chunked(q, ctx, pr, chunk, prec, want_G=True):
+    ctx.set_option(q.OPT_STATE_CHUNK, chunk)
+    try:
+        res, T = step(q, ctx, pr, 1, prec=prec, want_G=want_G)
+        chunks = ctx.stats()["state_chunks"]   # of the last call (the metric)
+    finally:
+        ctx.set_option(q.OPT_STATE_CHUNK, 0)
+    return res, T, chunks
+
+
+def expected_chunks(P, width, chunk):
+    """Whole column blocks of `width` from the top column P - 1 down, the lowest
+    block cut at column 1, grouped from the bottom into chunks of at most
+    `chunk` columns."""
+    blocks, top = [], P - 1
+    while top >= 1:
+        blocks.append(top - max(1, top - width + 1) + 1)
+        top -= width
+    blocks.reverse()
+    if chunk == 0 or chunk >= P - 1:
+        return 1
+    n, cur = 0, None
+    for b in blocks:
+        if cur is None or cur + b > chunk:
+            n, cur = n + 1, 0
+        cur += b
+    return n
+
+
+@pytest.mark.parametrize("make,chunk,prec", [
+    (lambda: W.scaled(W.config2, 13, 3, n_terms=10), 5, "c128"),
+    (lambda: W.scaled(W.config3, 14, 3, n_terms=10), 10, "c64"),
+    (lambda: W.permute_params(W.scaled(W.config5, 12, 2, n_terms=10), 8111), 36, "c64"),
+    (lambda: W.random_circuit(3, 14, 8102, n_terms=4), 2, "c128"),
+    (lambda: W.share_params(W.random_circuit(11, 60, 8106, n_terms=5), 9, 8107), 7, "c128")],
+    ids=["cfg2 n13 P78 small chunks", "cfg3 n14 P84 c64 chunks of 8", "cfg5 n12 P72 c64 two chunks",
+         "n3 chunks of <= 2", "shared n11 small chunks"])
+def test_states_chunked(env, make, chunk, prec):
+    """The derivative-state variant a chunk of column blocks at a time: chunk i's
+    states paired with every lower chunk's (prepared again for each), against
+    the oracle, against the unchunked run (every entry, to rounding: the Gram
+    sums run in another order) and with the step without the G output."""
+    q, ctx = env
+    pr = make()
+    if pr.n_qubits == 3:
+        pr.in_state = W.random_state(3, 8108)
+    res, T, k = chunked(q, ctx, pr, chunk, prec)
+    width = ctx.stats()["block_columns"]
+    assert width in (1, 2, 4) and width <= chunk and (prec == "c128" or width == 4)
+    n_rot = int((pr.gates[:, 3] >= 0).sum())   # columns: one per parameterised gate
+    want_k = expected_chunks(n_rot, width, chunk)
+    say(f"{pr.name} {prec}: chunks of <= {chunk} columns -> {k} chunks (expected {want_k})")
+    assert k == want_k and k > 1
+    full, Tf, k1 = chunked(q, ctx, pr, 0, prec)
+    assert k1 == 1
+    eG, eT = rel_err(res["G"], full["G"]), rel_err(T, Tf)
+    eg = rel_err(res["grad"], full["grad"])
+    say(f"{pr.name}: chunked vs unchunked |dG|={eG:.2e} |dT|={eT:.2e} |dgrad|={eg:.2e}")
+    # the forward state reaches a chunk's first block through other kernels than
+    # in the unchunked run (and leaves the metric phase at another gate): the
+    # same up to rounding, FP32 rounding for complex64 (the sweeps' random-walk
+    # bound, as for complex64 against complex128)
+    tol = 1e-12 if prec == "c128" else 8 * np.sqrt(pr.n_gates) * U32
+    assert eG <= tol and eT <= tol and eg <= tol
+    if prec == "c128":
+        want = oracle.step(pr)
+        kappa = np.linalg.cond(want["G"].real + pr.tikhonov * np.eye(pr.n_params))
+        eG, eT = rel_err(res["G"], want["G"]), rel_err(T, want["T"])
+        ed = rel_err(res["dtheta"], want["dtheta"])
+        say(f"{pr.name}: chunked vs oracle |dG|={eG:.2e} |dT|={eT:.2e} |ddtheta|={ed:.2e}")
+        assert eG <= TOL and eT <= TOL and ed <= max(TOL, kappa * 1e-14)
+    # the step without the G output: the same real parts; T's imaginary parts
+    # (zero but for rounding, since <y|sigma|y> is real) are then not taken
+    # from the Gram matrix, which moves Re G by their products (u^2 for complex64)
+    real, _, _ = chunked(q, ctx, pr, chunk, prec, want_G=False)
+    kappa = np.linalg.cond(res["G"].real + pr.tikhonov * np.eye(pr.n_params))
+    tol = 1e-13 if prec == "c128" else max(1e-13, kappa * (8 * np.sqrt(pr.n_gates) * U32) ** 2)
+    assert rel_err(real["dtheta"], res["dtheta"]) <= tol
+
+
+def test_states_chunked_by_memory(env):
+    """With a memory limit under what P + 2 kept states need, the chunks are
+    chosen to fit (two chunks and three more states kept at once)."""
+    q, ctx = env
+    pr = W.scaled(W.config1, 14, 2, n_terms=3)
+    full, Tf, k1 = chunked(q, ctx, pr, 0, "c128")
+    assert k1 == 1
+    # 58 kept states of 256 KiB (14.5 MiB) and 8 MiB of Gram partial sums do not fit in 16 MiB
+    ctx.set_mem_limit(16 << 20)
+    try:
+        res, T, k = chunked(q, ctx, pr, 0, "c128")
+    finally:
+        ctx.set_mem_limit(0)
+    say(f"{pr.name}: 16 MiB limit -> {k} chunks")
+    assert k > 2
+    assert rel_err(res["G"], full["G"]) <= 1e-12 and rel_err(T, Tf) <= 1e-12
+    want = oracle.step(pr)
+    assert rel_err(res["G"], want["G"]) <= TOL
 
 
 @pytest.mark.timeout(900)
