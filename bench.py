@@ -68,7 +68,7 @@ def parse():
                     help="also measure controlled and Pauli-string rotations (isolated gate bandwidth at n=26 and "
                          "the step at n=24 next to plain rotations)")
     ap.add_argument("--block", type=int, default=0,
-                    help="metric columns sharing one lambda sweep (1 or 2; 0 = library default)")
+                    help="metric columns sharing one lambda sweep (1, 2 or 4; 0 = library default)")
     return ap.parse_args()
 
 
