@@ -123,7 +123,9 @@ __global__ __launch_bounds__(kGramThreads) __attribute__((amdgpu_waves_per_eu(4,
     } else {
         tile_pair(pair, ntA, ta, tb);
     }
-    const DevSet<R> &SB = rect ? B : A;
+    // (field by field: a reference chosen between the two arguments would put
+    // them in scratch memory)
+    const DevSet<R> SB{rect ? B.p1 : A.p1, rect ? B.p2 : A.p2, rect ? B.n1 : A.n1, rect ? B.n : A.n};
     const bool same = !rect && ta == tb && mode == 0;   // one tile serves both operands
     const double *sBv = same ? sA : sB;
 
@@ -213,7 +215,7 @@ __global__ void k_gram_reduce(const double *__restrict__ partials, int npairs, i
     } else {
         tile_pair(pair, ntA, ta, tb);
     }
-    const SetCols &SB = rect ? B : A;
+    const SetCols SB{rect ? B.n1 : A.n1, rect ? B.n : A.n, rect ? B.col1 : A.col1, rect ? B.col2 : A.col2};
     const int qa = ta * kTile + e / kTile, qb = tb * kTile + e % kTile;
     if (qa >= A.n || qb >= SB.n || (!rect && qa >= qb)) return;
     const int ca = column_of(A, qa), cb = column_of(SB, qb);

@@ -472,11 +472,13 @@ __global__ void k_advance_seed(typename Cplx<R>::T *psi, typename Cplx<R>::T *la
 // Column seeds of many registers in one launch (the batched metric): item k
 // applies up to two forward rotations (qa then qb; -1: none) to its register
 // psi, then writes lam = psi, phi = sigma_qs psi and its work-groups' partial
-// sums of <psi|sigma_qs|psi>.  A thread walks the groups of eight amplitudes
-// over three distinct bits: qs, the rotations' qubits and, where those are
-// fewer, the lowest other qubits (registers of at least 3 qubits).  The work-
-// groups of item k are block_begin .. block_begin + nblocks - 1; each writes
-// one partial at its own index.
+// sums of <psi|sigma_qs|psi>.  A thread walks groups of eight amplitudes over
+// three distinct bits in fixed slots -- slot 0 the seeded qubit qs, slot 1 qa
+// (unless it is qs), slot 2 qb, the lowest other qubits where those are fewer
+// (registers of at least 3 qubits) -- so that every amplitude index within a
+// group is a constant and the group stays in registers.  The work-groups of
+// item k are block_begin .. block_begin + nblocks - 1; each writes one partial
+// at its own index.
 // (the matrix entries in the register's precision, as in k_advance_seed)
 template <typename R, typename C>
 __device__ __forceinline__ void rot_pair(const double *m, C &u, C &v) {
@@ -488,29 +490,16 @@ __device__ __forceinline__ void rot_pair(const double *m, C &u, C &v) {
     v.x = m4 * a.x - m5 * a.y + m6 * b.x - m7 * b.y;
     v.y = m4 * a.y + m5 * a.x + m6 * b.y + m7 * b.x;
 }
-// the rotation m on bit j (0, 1, 2) of a group of eight
-template <typename R, typename C>
-__device__ __forceinline__ void rot_group(const double *m, int j, C (&v)[8]) {
-    switch (j) {
-    case 0: rot_pair<R>(m, v[0], v[1]); rot_pair<R>(m, v[2], v[3]); rot_pair<R>(m, v[4], v[5]); rot_pair<R>(m, v[6], v[7]); break;
-    case 1: rot_pair<R>(m, v[0], v[2]); rot_pair<R>(m, v[1], v[3]); rot_pair<R>(m, v[4], v[6]); rot_pair<R>(m, v[5], v[7]); break;
-    default: rot_pair<R>(m, v[0], v[4]); rot_pair<R>(m, v[1], v[5]); rot_pair<R>(m, v[2], v[6]); rot_pair<R>(m, v[3], v[7]); break;
-    }
-}
-template <typename C>
-__device__ __forceinline__ void pauli_group(int axis, int j, const C (&v)[8], C (&o)[8]) {
-    switch (j) {
-    case 0: pauli_pair(axis, v[0], v[1], o[0], o[1]); pauli_pair(axis, v[2], v[3], o[2], o[3]);
-            pauli_pair(axis, v[4], v[5], o[4], o[5]); pauli_pair(axis, v[6], v[7], o[6], o[7]); break;
-    case 1: pauli_pair(axis, v[0], v[2], o[0], o[2]); pauli_pair(axis, v[1], v[3], o[1], o[3]);
-            pauli_pair(axis, v[4], v[6], o[4], o[6]); pauli_pair(axis, v[5], v[7], o[5], o[7]); break;
-    default: pauli_pair(axis, v[0], v[4], o[0], o[4]); pauli_pair(axis, v[1], v[5], o[1], o[5]);
-             pauli_pair(axis, v[2], v[6], o[2], o[6]); pauli_pair(axis, v[3], v[7], o[3], o[7]); break;
-    }
+// the rotation m on slot J of a group of eight
+template <int J, typename R, typename C>
+__device__ __forceinline__ void rot_slot(const double *m, C (&v)[8]) {
+#pragma unroll
+    for (int g = 0; g < 8; ++g)
+        if (!(g & (1 << J))) rot_pair<R>(m, v[g], v[g | (1 << J)]);
 }
 
 template <typename R>
-__global__ void k_seed_multi(const SeedItem *__restrict__ items, int n_items, double *partials) {
+__global__ __launch_bounds__(kBlock) void k_seed_multi(const SeedItem *__restrict__ items, int n_items, double *partials) {
     using C = typename Cplx<R>::T;
     const uint32_t wg = blockIdx.x;
     int lo = 0, hi = n_items - 1;
@@ -521,44 +510,43 @@ __global__ void k_seed_multi(const SeedItem *__restrict__ items, int n_items, do
     }
     const SeedItem it = items[lo];
     C *psi = (C *)it.psi, *lam = (C *)it.lam, *phi = (C *)it.phi;
-    // the three bits of a group, ascending, and where qa, qb, qs sit among them
-    int bit[3], k = 0;
-    auto add = [&](int q) {
-        if (q < 0) return;
-        for (int i = 0; i < k; ++i)
-            if (bit[i] == q) return;
-        bit[k++] = q;
-    };
-    add(it.qs);
-    add(it.qa);
-    add(it.qb);
-    for (int q = 0; k < 3; ++q) add(q);
-    if (bit[0] > bit[1]) { const int t = bit[0]; bit[0] = bit[1]; bit[1] = t; }
-    if (bit[1] > bit[2]) { const int t = bit[1]; bit[1] = bit[2]; bit[2] = t; }
-    if (bit[0] > bit[1]) { const int t = bit[0]; bit[0] = bit[1]; bit[1] = t; }
-    auto slot = [&](int q) { return q == bit[0] ? 0 : q == bit[1] ? 1 : 2; };
-    const int js = slot(it.qs), ja = it.qa >= 0 ? slot(it.qa) : -1, jb = it.qb >= 0 ? slot(it.qb) : -1;
-    const uint64_t m0 = uint64_t(1) << bit[0], m1 = uint64_t(1) << bit[1], m2 = uint64_t(1) << bit[2];
+    // the qubits of the three slots (qb, when given, differs from qs and qa)
+    const int s0 = it.qs;
+    int s1 = (it.qa >= 0 && it.qa != s0) ? it.qa : -1;
+    int s2 = it.qb;
+    int f = 0;   // lowest qubit not taken yet
+    if (s1 < 0) {
+        while (f == s0 || f == s2) ++f;
+        s1 = f++;
+    }
+    if (s2 < 0) {
+        while (f == s0 || f == s1) ++f;
+        s2 = f;
+    }
+    const int ja = it.qa < 0 ? -1 : (it.qa == s0 ? 0 : 1);   // slot of rotation a
+    // ascending for the zero insertions
+    const int b0 = min(s0, min(s1, s2)), b2 = max(s0, max(s1, s2)), b1 = s0 + s1 + s2 - b0 - b2;
+    const uint64_t m0 = uint64_t(1) << s0, m1 = uint64_t(1) << s1, m2 = uint64_t(1) << s2;
     double sr = 0.0, si = 0.0;
     const uint64_t ngroups = uint64_t(1) << (it.n - 3);
     const uint64_t stride = (uint64_t)it.nblocks * kBlock;
     for (uint64_t p = (uint64_t)(wg - it.block_begin) * kBlock + threadIdx.x; p < ngroups; p += stride) {
-        const uint64_t b = insert_zero(insert_zero(insert_zero(p, bit[0]), bit[1]), bit[2]);
-        uint64_t idx[8];
-#pragma unroll
-        for (int g = 0; g < 8; ++g) idx[g] = b | ((g & 1) ? m0 : 0) | ((g & 2) ? m1 : 0) | ((g & 4) ? m2 : 0);
+        const uint64_t b = insert_zero(insert_zero(insert_zero(p, b0), b1), b2);
         C v[8];
 #pragma unroll
-        for (int g = 0; g < 8; ++g) v[g] = psi[idx[g]];
-        if (ja >= 0) rot_group<R>(it.ma, ja, v);
-        if (jb >= 0) rot_group<R>(it.mb, jb, v);
+        for (int g = 0; g < 8; ++g) v[g] = psi[b | ((g & 1) ? m0 : 0) | ((g & 2) ? m1 : 0) | ((g & 4) ? m2 : 0)];
+        if (ja == 0) rot_slot<0, R>(it.ma, v);
+        else if (ja == 1) rot_slot<1, R>(it.ma, v);
+        if (it.qb >= 0) rot_slot<2, R>(it.mb, v);
         C o[8];
-        pauli_group(it.axis, js, v, o);
+#pragma unroll
+        for (int g = 0; g < 8; g += 2) pauli_pair(it.axis, v[g], v[g + 1], o[g], o[g + 1]);
 #pragma unroll
         for (int g = 0; g < 8; ++g) {
-            if (ja >= 0) psi[idx[g]] = v[g];
-            lam[idx[g]] = v[g];
-            phi[idx[g]] = o[g];
+            const uint64_t x = b | ((g & 1) ? m0 : 0) | ((g & 2) ? m1 : 0) | ((g & 4) ? m2 : 0);
+            if (ja >= 0) psi[x] = v[g];
+            lam[x] = v[g];
+            phi[x] = o[g];
             cmac(sr, si, v[g].x, v[g].y, o[g].x, o[g].y);
         }
     }
