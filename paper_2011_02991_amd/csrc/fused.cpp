@@ -51,6 +51,7 @@ size_t fused_scratch_bytes(const SweepPlan &plan, const FusedRun &fr, int M) {
     b += align256((size_t)M * 64 + 64);                                  // matrix table (FP64)
     b += align256((size_t)M * 32 + 64);                                  // matrix table (FP32)
     b += align256((size_t)M * 64 + 64);                                  // forward matrices (FP64)
+    b += align256((size_t)(M + 1) * 64 + 64);                            // the same negated, and -I
     b += align256(plan.dev_passes.size() * sizeof(DevPass) + 64);       // passes
     b += align256(plan.dev_ops.size() * sizeof(DevOp) + 64);            // ops
     b += align256(plan.dev_maps.size() * sizeof(DevMap) + 64);          // thread mappings
@@ -181,6 +182,15 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
     double *d_mats = (double *)take(mats.size() * 8);
     float *d_mats32 = (float *)take(mats32.size() * 4);
     double *d_fmats = (double *)take(fmats.size() * 8);
+    // the forward matrices negated, then -I (row M): a seed that finds psi
+    // negated (by the forward plan's passes) applies one of them instead, so
+    // that the derivative-state variant's kept states carry no sign of psi
+    std::vector<double> nfmats(fmats.size() + 8);
+    for (size_t k = 0; k < fmats.size(); ++k) nfmats[k] = -fmats[k];
+    nfmats[fmats.size()] = -1.0;
+    nfmats[fmats.size() + 6] = -1.0;
+    double *d_nfmats = (double *)take(nfmats.size() * 8);
+    const double *d_negI = d_nfmats + fmats.size();
     DevPass *d_passes = (DevPass *)take(plan.dev_passes.size() * sizeof(DevPass));
     DevOp *d_ops = (DevOp *)take(plan.dev_ops.size() * sizeof(DevOp));
     DevMap *d_maps = (DevMap *)take(plan.dev_maps.size() * sizeof(DevMap));
@@ -191,7 +201,7 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
     // gate with cos(theta/2) < 0 is applied negated (as in the sweeps), so psi
     // may carry a sign; every product and T, E and the gradient are quadratic
     // in it, and psi is put right at the end of the metric phase.
-    const SweepPlan *fp = (!states && plan.forward) ? plan.forward.get() : nullptr;
+    const SweepPlan *fp = plan.forward ? plan.forward.get() : nullptr;
     std::vector<double> fshear;
     std::vector<LaunchItem> fitems;
     std::vector<uint8_t> seg_neg;
@@ -242,6 +252,7 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
         FCHECK(hipMemcpyAsync(d_mats, mats.data(), mats.size() * 8, hipMemcpyHostToDevice, st));
         FCHECK(hipMemcpyAsync(d_mats32, mats32.data(), mats32.size() * 4, hipMemcpyHostToDevice, st));
         FCHECK(hipMemcpyAsync(d_fmats, fmats.data(), fmats.size() * 8, hipMemcpyHostToDevice, st));
+        FCHECK(hipMemcpyAsync(d_nfmats, nfmats.data(), nfmats.size() * 8, hipMemcpyHostToDevice, st));
     }
     if (!plan.dev_passes.empty())
         FCHECK(hipMemcpyAsync(d_passes, plan.dev_passes.data(), plan.dev_passes.size() * sizeof(DevPass),
@@ -342,12 +353,27 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
     }
     stats->other_launches += 2;
     uint8_t psi_negated = 0;
+    // segment k of the forward plan takes psi from the top of block k - 1 (from
+    // rotation 0 for k = 0) to the top of block k; psi is at the start of
+    // segment at_seg (the derivative-state variant has applied rotation 0 of
+    // segment 0 already)
+    int at_seg = 0;
+    // the first rotation a seed applies to psi (row of the forward table), or
+    // -I when psi is negated and the seed applies none: the derivative-state
+    // variant's kept states must not carry psi's sign
+    auto seed_row = [&](int gate_pos) -> const double * {
+        const bool fix = states && psi_negated;
+        if (fix) psi_negated = 0;
+        if (gate_pos < 0) return fix ? d_negI : d_fmats;
+        return (fix ? d_nfmats : d_fmats) + (size_t)gate_pos * 8;
+    };
     for (const Group &G : groups) {
         for (int col = G.col_begin; col < G.col_end; ++col) {
             const int s = plan.cols[col].s;    // top column of the block
             const Rot &rs = c.rots[s];
             const Rot &rp = c.rots[s - 1];
             const int b = col - G.col_begin;
+            const int seg_next = col + 1;     // psi leaves the seed at the start of this segment
             // y_s = R_{s-1} y_{s-1} when rotation s-1 is the only gate in between:
             // one pass advances psi, seeds the top column and takes T_s (the
             // lower columns of a block are seeded inside its sweep).  When the
@@ -362,50 +388,66 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
                                      rs.ctrl);
                 control_diag(s);
                 stats->other_launches += 3;
+                at_seg = seg_next;
                 continue;
             }
             const int ra = pos < c.M ? c.rot_at[pos] : -1;
             if (ra >= 0 && c.rots[ra].ctrl < 0 && pos + 1 == rp.pos && rs.pos == rp.pos + 1 && n >= 3 &&
                 c.rots[ra].qubit != rp.qubit && c.rots[ra].qubit != rs.qubit && rp.qubit != rs.qubit) {
-                launch_advance2_seed<R>(psi, reg(b, 0), xi_of(s, b, W - 1), n, c.rots[ra].qubit,
-                                        d_fmats + (size_t)pos * 8,
+                launch_advance2_seed<R>(psi, reg(b, 0), xi_of(s, b, W - 1), n, c.rots[ra].qubit, seed_row(pos),
                                         rp.qubit, d_fmats + (size_t)rp.pos * 8, rs.qubit, rs.axis,
                                         buf.reduce_partials, buf.traw + 2 * s, st);
                 stats->other_launches += 2;
                 pos = rs.pos;
+                at_seg = seg_next;
                 continue;
             }
-            if (fp && !(pos == rp.pos && rs.pos == rp.pos + 1)) {
+            // (the derivative-state variant is past the start of segment 0)
+            if (fp && !(pos == rp.pos && rs.pos == rp.pos + 1) && !(states && col == 0)) {
                 // more than the one rotation before the top: the gates up to the
-                // top rotation in the forward plan's passes (usually one), then
-                // lambda = psi = y_s, phi = sigma_s y_s and T_s in one pass
-                const int64_t t0 = fp->col_pass_begin[col];
-                const int64_t t1 = col + 1 < (int)fp->cols.size() ? fp->col_pass_begin[col + 1] : fp->total_passes;
-                for (int64_t t = t0; t < t1; ++t) {
-                    launch_sweep_pass_states<R>(d_fitems + t, 1, tiles, d_fpasses, d_fops, d_fmaps, d_fsh, d_fsh32,
-                                                fp->m, fp->rb, 0, st);
-                    ++stats->other_launches;
+                // top rotation in the forward plan's passes (usually one segment;
+                // the first block of a later chunk of the derivative-state
+                // variant is several segments on, and the rest of segment 0 runs
+                // gate by gate), then lambda = psi = y_s, phi = sigma_s y_s and
+                // T_s in one pass
+                if (at_seg == 0 && states) {
+                    forward_to(c.rots[plan.cols[0].s].pos, reg(b, 0));
+                    at_seg = 1;
                 }
-                psi_negated ^= seg_neg[col];
+                for (; at_seg <= col; ++at_seg) {
+                    const int64_t t0 = fp->col_pass_begin[at_seg];
+                    const int64_t t1 =
+                        at_seg + 1 < (int)fp->cols.size() ? fp->col_pass_begin[at_seg + 1] : fp->total_passes;
+                    for (int64_t t = t0; t < t1; ++t) {
+                        launch_sweep_pass_states<R>(d_fitems + t, 1, tiles, d_fpasses, d_fops, d_fmaps, d_fsh,
+                                                    d_fsh32, fp->m, fp->rb, 0, st);
+                        ++stats->other_launches;
+                    }
+                    psi_negated ^= seg_neg[at_seg];
+                }
                 pos = rs.pos;
-                launch_advance_seed<R>(psi, reg(b, 0), xi_of(s, b, W - 1), n, -1, d_fmats, rs.qubit, rs.axis,
-                                       buf.reduce_partials, buf.traw + 2 * s, st);
+                const double *mrow = seed_row(-1);
+                launch_advance_seed<R>(psi, reg(b, 0), xi_of(s, b, W - 1), n, mrow == d_negI ? rs.qubit : -1, mrow,
+                                       rs.qubit, rs.axis, buf.reduce_partials, buf.traw + 2 * s, st);
                 stats->other_launches += 2;
                 continue;
             }
             forward_to(rp.pos, reg(b, 0));
             int qr = -1;
-            const double *mrow = d_fmats;
+            const double *mrow = nullptr;
             if (rs.pos == rp.pos + 1 && pos == rp.pos) {   // (the states variant has applied rotation 0 already)
                 qr = rp.qubit;
-                mrow = d_fmats + (size_t)rp.pos * 8;
+                mrow = seed_row(rp.pos);
                 pos = rs.pos;
             } else {
                 forward_to(rs.pos, reg(b, 0));
+                mrow = seed_row(-1);
+                if (mrow == d_negI) qr = rs.qubit;
             }
             launch_advance_seed<R>(psi, reg(b, 0), xi_of(s, b, W - 1), n, qr, mrow, rs.qubit, rs.axis,
                                    buf.reduce_partials, buf.traw + 2 * s, st);
             stats->other_launches += 2;
+            at_seg = seg_next;
         }
         for (size_t li = G.launch_begin; li < G.launch_end; ++li) {
             const Launch &L = launches[li];

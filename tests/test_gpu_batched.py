@@ -84,6 +84,29 @@ def test_mixed_batch_vs_oracle(env):
     ctx.set_option(q.OPT_GRAPH, 1)
 
 
+@pytest.mark.parametrize("graph", [0, 1])
+def test_tiny_registers_batch(env, graph):
+    """Members of 2, 3 and 4 qubits beside larger ones: the column seeds of a
+    launch run as one kernel per round over groups of eight amplitudes, which
+    a 3-qubit register fills exactly; a 2-qubit register is seeded on its own.
+    Layered members put two rotations on one qubit back to back (the seed's
+    rotation on the seeded qubit itself)."""
+    q, ctx = env
+    probs = [W.random_circuit(2, 12, 7201, n_terms=3), W.random_circuit(3, 16, 7202, n_terms=3),
+             W.scaled(W.config2, 3, 2, seed=7203), W.random_circuit(4, 20, 7204, n_terms=4),
+             W.scaled(W.config3, 10, 2, seed=7205), W.scaled(W.config2, 2, 3, seed=7206)]
+    probs[1].in_state = W.random_state(3, 7207)
+    say(f"case: tiny registers batch, graph {graph} ({[(p.n_qubits, p.n_params) for p in probs]})")
+    ctx.set_option(q.OPT_GRAPH, graph)
+    try:
+        for rep in range(2 if graph else 1):
+            res = run_batch(q, ctx, probs)
+            for b, (r, p) in enumerate(zip(res, probs)):
+                check_member(r, oracle.step(p), p, TOL, f"rep {rep} member {b}")
+    finally:
+        ctx.set_option(q.OPT_GRAPH, 1)
+
+
 def test_graph_replays_match_eager(env):
     """The metric phase is captured on the first call and replayed with new
     angles; eager calls and host work run between the replays, and every
