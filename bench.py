@@ -64,6 +64,9 @@ def parse():
                     help="skip the derivative-state variant (P + 2 states kept, Gram matrix on the matrix cores)")
     ap.add_argument("--variants", action="store_true",
                     help="also time the cheaper metric variants (block-diagonal per layer, L only) on the workload")
+    ap.add_argument("--batch", action="store_true",
+                    help="also time the batched step (64-ansatz workload, n 12..22, and 48 ansaetze of n 8..16) "
+                         "against one step call per ansatz")
     ap.add_argument("--gateset", action="store_true",
                     help="also measure controlled and Pauli-string rotations (isolated gate bandwidth at n=26 and "
                          "the step at n=24 next to plain rotations)")
@@ -296,6 +299,46 @@ def metric_variants(qng, ctx, circ, pr, prec, reps=2):
     return out
 
 
+def batched_steps(qng, ctx, prec, reps=2):
+    """qng_step_batched (graph replay, no G outputs) against one qng_step per
+    ansatz, wall time per step of all members after one warm-up call each way:
+    the 64-ansatz workload (n 12..22, 2..8 layers of RY, RZ, CNOT chain, 30
+    terms) and 48 ansaetze of n 8..16 (2..6 layers), where one ansatz alone
+    cannot fill the GPU."""
+    import numpy as np
+    import torch
+    import workloads as W
+    rng = np.random.default_rng(7201)
+    small = [W.make_problem(f"small{b}", int(rng.integers(8, 17)), int(rng.integers(2, 7)), (W.RY, W.RZ),
+                            "cnot_chain", 12, 7300 + b) for b in range(48)]
+    out = {}
+    ctx.set_option(qng.OPT_GRAPH, 1)
+    for name, probs in (("cfg4_64_ansaetze_n12_22", W.config4()), ("small_48_ansaetze_n8_16", small)):
+        circs = [qng.Circuit.from_problem(p) for p in probs]
+        ths = [p.theta for p in probs]
+        dt, eps = probs[0].dt, probs[0].tikhonov
+
+        def batched():
+            ctx.step_batched(circs, ths, dt, eps, prec=prec, want_G=False)
+
+        def singles():
+            for c, t, p in zip(circs, ths, probs):
+                ctx.step(c, t, p.dt, p.tikhonov, prec=prec, want_G=False)
+
+        times = {}
+        for key, fn in (("batched_s", batched), ("one_call_per_ansatz_s", singles)):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            times[key] = (time.perf_counter() - t0) / reps
+        out[name] = {"members": len(probs), "params": int(sum(p.n_params for p in probs)), "prec": prec, **times,
+                     "speedup": times["one_call_per_ansatz_s"] / times["batched_s"]}
+    return out
+
+
 def extended_gates(qng, ctx, prec, n_gate=26, n_step=24, layers=2, reps=2):
     """Controlled (CRX/CRY/CRZ) and Pauli-string rotations.
 
@@ -477,6 +520,9 @@ def main():
         log(f"gate apply: {gate}")
     variants = metric_variants(qng, ctx, circ, pr, args.prec) if args.variants else None
     gateset = extended_gates(qng, ctx, args.prec) if args.gateset else None
+    batch = batched_steps(qng, ctx, "c128") if args.batch else None
+    if batch:
+        log(f"batched steps: {batch}")
     cpu = oracle_errors = small = None
     if not args.no_cpu:
         cpu, oracle_errors = cpu_baseline(pr, {args.prec: res, **({plain["prec"]: res_other} if plain else {})})
@@ -515,7 +561,7 @@ def main():
         "plain_fp64": plain, "precision_errors": precision, "oracle_pinned_errors": oracle_errors,
         "c64_fp32_product_shares": shares, "derivative_state_variant": states,
         "step_with_G_output_s": t_with_G, "gate_apply": gate, "roofline": roof, "cpu_baseline": cpu,
-        "metric_variants": variants, "extended_gates": gateset,
+        "metric_variants": variants, "extended_gates": gateset, "batched_steps": batch,
         "breakdown_ms": {k: st[k] / args.steps for k in ("metric_ms", "grad_ms", "solve_ms")},
     }
     print(json.dumps(line), flush=True)
