@@ -21,7 +21,7 @@ namespace {
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-constexpr uint64_t kSeedBlocksMax = 64;   // work-groups per seed in a round (the rest by grid stride)
+constexpr uint64_t kSeedBlocksMax = 1024;   // work-groups per seed in a round (the rest by grid stride)
 
 struct ImageLayout {
     size_t passes, ops, maps, items, tasks, seed_items, seed_tasks, total;
