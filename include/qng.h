@@ -170,8 +170,9 @@ typedef enum {
                                     are prepared in chunks (see there).  Method 1 takes the plain gate set and
                                     the full metric (QNG_E_UNSUPPORTED otherwise); qng_step_batched uses
                                     method 0. */,
-    QNG_OPT_STATE_CHUNK = 13     /* method 1: at most this many derivative states per chunk (0 = automatic: all
-                                    P when they fit, else the most that fit).  With K > 1 chunks (whole column
+    QNG_OPT_STATE_CHUNK = 13     /* method 1: at most this many derivative states per chunk, but at least one
+                                    column block (0 = automatic: all P when they fit, else the most that
+                                    fit).  With K > 1 chunks (whole column
                                     blocks, two chunks kept at once: 2 x chunk + 3 states) chunk i's states are
                                     paired with every chunk above it, which is prepared again each time:
                                     1 + K (K - 1) / 2 preparations of a chunk's states in place of K, and the

@@ -680,7 +680,8 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
         };
         if (states) {
             const int all = c.P - 1;
-            chunk_cols = ctx->opt_state_chunk > 0 ? std::min(ctx->opt_state_chunk, all) : all;
+            // (a chunk holds whole column blocks: at least one)
+            chunk_cols = ctx->opt_state_chunk > 0 ? std::min(std::max(ctx->opt_state_chunk, plan->width), all) : all;
             if (ctx->opt_state_chunk == 0) {
                 // the most columns per chunk that fit (two chunks held at once below all)
                 while (chunk_cols >= plan->width && configure(chunk_cols) > cap)
