@@ -245,13 +245,16 @@ def test_states_n20_full_oracle(env):
 
 
 @pytest.mark.timeout(900)
-def test_states_n24_against_recurrence(env):
-    """n=24, P=432 (108 GiB of kept states): every entry against the
-    recurrent method, which the full-size tests pin to the oracle."""
+@pytest.mark.parametrize("chunk", [0, 144], ids=["all kept", "chunks of 144"])
+def test_states_n24_against_recurrence(env, chunk):
+    """n=24, P=432 (108 GiB of kept states; in chunks of 144 columns, 291
+    states or 73 GiB): every entry against the recurrent method, which the
+    full-size tests pin to the oracle."""
     q, ctx = env
     pr = W.config5()
-    say(f"case: {pr.name} derivative-state metric vs recurrence, every entry")
-    res, T = step(q, ctx, pr, 1)
+    say(f"case: {pr.name} derivative-state metric (chunk {chunk}) vs recurrence, every entry")
+    res, T, k = chunked(q, ctx, pr, chunk, "c128")
+    assert k == (1 if chunk == 0 else 3)
     rec, Tr = step(q, ctx, pr, 0)
     eG, eT, eg = rel_err(res["G"], rec["G"]), rel_err(T, Tr), rel_err(res["grad"], rec["grad"])
     kappa = np.linalg.cond(rec["G"].real + pr.tikhonov * np.eye(pr.n_params))
