@@ -14,10 +14,15 @@
 // by Q x K product with K far larger than Q, computed here with
 // v_mfma_f64_16x16x4_f64: every product is formed in FP64 (complex64 states
 // are converted, exactly, when a tile is staged) and accumulated in FP64.
+// When the states are kept a chunk of columns at a time, the same kernel takes
+// one chunk with lambda* and column 0 (symmetric) or two chunks against each
+// other (rectangular: every pair of a state of each), with the columns of each
+// operand's positions passed along, so the entries land where they belong.
 //
 // Work split: the Q columns are cut into tiles of 64; a work-group owns one
-// pair of tiles (ta <= tb; with two operands, a tile of each) and one chunk of K, stages 32 reals of each of its
-// 128 columns per step in LDS (FP64) and accumulates a 64 x 64 block of the
+// pair of tiles (ta <= tb, or a tile of each operand) and one chunk of K,
+// stages 32 reals of each of its 128 columns per step in LDS (FP64) and
+// accumulates a 64 x 64 block of the
 // result in the MFMA accumulators (4 wavefronts, 32 x 32 each, as 2 x 2 MFMA
 // blocks).  Pairs vary fastest over the work-groups, so the work-groups of one
 // chunk run together and share its columns in the caches.  Each work-group
