@@ -64,11 +64,11 @@ def check_member(res, want, pr, tol, label):
     assert ed <= max(tol, kappa * 1e-14), (label, ed, kappa)
 
 
-def run_batch(q, ctx, probs, thetas=None):
+def run_batch(q, ctx, probs, thetas=None, prec="c128"):
     circs = [q.Circuit.from_problem(p) for p in probs]
     ths = thetas if thetas is not None else [p.theta for p in probs]
     return ctx.step_batched(circs, ths, probs[0].dt, probs[0].tikhonov,
-                            in_states=[p.in_state for p in probs])
+                            in_states=[p.in_state for p in probs], prec=prec)
 
 
 def test_mixed_batch_vs_oracle(env):
@@ -105,6 +105,39 @@ def test_tiny_registers_batch(env, graph):
                 check_member(r, oracle.step(p), p, TOL, f"rep {rep} member {b}")
     finally:
         ctx.set_option(q.OPT_GRAPH, 1)
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_complex64_batch(env, graph):
+    """complex64 storage (FP32 registers, every product formed in FP64): the
+    mixed batch and registers of 2 to 4 qubits, each member against its
+    complex128 batch result and the oracle at the random-walk rounding bound of
+    its sweeps (8 sqrt(M) u, M gates, u = 2^-24), and against the complex64
+    single-ansatz step (the same FP32 arithmetic, other kernels and
+    reduction orders: the same bound)."""
+    q, ctx = env
+    probs = mixed_batch() + [W.random_circuit(2, 12, 7201, n_terms=3), W.random_circuit(3, 16, 7202, n_terms=3),
+                             W.random_circuit(4, 20, 7204, n_terms=4)]
+    say(f"case: complex64 batch, graph {graph} ({[(p.n_qubits, p.n_params) for p in probs]})")
+    ctx.set_option(q.OPT_GRAPH, graph)
+    try:
+        res = run_batch(q, ctx, probs, prec="c64")
+        if graph:
+            res = run_batch(q, ctx, probs, prec="c64")   # a replay
+        ref = run_batch(q, ctx, probs, prec="c128")
+    finally:
+        ctx.set_option(q.OPT_GRAPH, 1)
+    for b, p in enumerate(probs):
+        if not p.n_params:
+            continue
+        bound = 8 * np.sqrt(p.n_gates) * 2.0 ** -24
+        single = ctx.step(q.Circuit.from_problem(p), p.theta, p.dt, p.tikhonov, in_state=p.in_state, prec="c64")
+        want = oracle.step(p)
+        for key in ("G", "grad"):
+            e_ref, e_or = rel_err(res[b][key], ref[b][key]), rel_err(res[b][key], want[key])
+            e_single = rel_err(res[b][key], single[key])
+            assert e_ref <= bound and e_or <= bound and e_single <= bound, (b, key, e_ref, e_or, e_single, bound)
+        assert abs(res[b]["E"] - want["E"]) <= bound * max(1.0, abs(want["E"]))
 
 
 def test_graph_replays_match_eager(env):
