@@ -148,9 +148,10 @@ typedef enum {
     QNG_OPT_BATCH_TILES = 8,     /* qng_step_batched: work-groups per sweep launch to aim for (0 = 4096) */
     QNG_OPT_BLOCK_COLUMNS = 9,   /* fused metric: columns sharing one lambda sweep, 1, 2 or 4 (0 = default: 4
                                     where it applies, else 2, else 1).  4 needs complex64 storage in FP32
-                                    registers, tiles of 11 qubits (registers of >= 11 qubits), no controlled
-                                    rotation, the recurrent method and a single ansatz; 2 needs tiles of >= 11
-                                    qubits; where the choice does not apply the next smaller one is used */
+                                    registers, tiles of 11 qubits (registers of >= 11 qubits) and no
+                                    controlled rotation (in qng_step_batched, per member); 2 needs tiles of
+                                    >= 11 qubits; where the choice does not apply the next smaller one is
+                                    used */
     QNG_OPT_METRIC_KIND = 10,    /* 0 (default): G = L - T^* T; 1: L alone, L_ij = <d_i psi, d_j psi> (the
                                     coefficient matrix of imaginary-time evolution when psi's global phase does
                                     not depend on theta); T is still returned.  Metric and step entry points. */

@@ -588,10 +588,9 @@ struct CallSpec {
 // value 0 picks the default.
 // Columns per lambda sweep (QNG_OPT_BLOCK_COLUMNS, 0 = automatic): four for
 // FP32 registers in tiles of 11 qubits (8 amplitudes per thread; measured at
-// n = 26, complex64: 7 % less sweep time than two columns in tiles of 12), in
-// the recurrent method without controlled rotations and outside the batched
-// step (max_width 2); else two for full tiles of 8 or 16 amplitudes per
-// thread; else one.
+// n = 26, complex64: 7 % less sweep time than two columns in tiles of 12)
+// without controlled rotations; else two for full tiles of 8 or 16
+// amplitudes per thread; else one.
 int block_width(int opt_block, const Circuit &c, int opt_tile, int amp, bool f64, int max_width = kMaxBlockWidth) {
     int m = opt_tile > 0 ? opt_tile : default_tile_qubits(c.n, amp, f64);
     if (m > (f64 ? 11 : 12)) m = f64 ? 11 : 12;
@@ -601,6 +600,9 @@ int block_width(int opt_block, const Circuit &c, int opt_tile, int amp, bool f64
     if (want == 4 && four) return 4;
     return (want >= 2 && register_bits(m, amp) >= 3 && m - register_bits(m, amp) == 8) ? 2 : 1;
 }
+
+// Smallest register for which the batched step picks four-column blocks by itself.
+constexpr int kBatchFourMinQubits = 18;
 
 // Tile width a plan of `width` columns per sweep is built for: four-column
 // blocks take tiles of 11 qubits (8 amplitudes per thread in FP32 registers).
@@ -903,16 +905,25 @@ BatchRun batch_metric(qng_ctx *ctx, const std::vector<Problem> &pbs, const doubl
     run.G.assign(B, nullptr);
     run.T.assign(B, nullptr);
 
-    // register classes: members whose plans share the tile width
-    std::map<int, std::vector<int>> by_m;
-    for (int b = 0; b < B; ++b) by_m[member_tile(pbs[b].circ, tun.tile_qubits, amp, f64)].push_back(b);
+    // register classes: members whose plans share the tile width and the
+    // columns per lambda sweep (as in the single step: four for FP32 registers
+    // in tiles of 11 qubits, else two for full tiles, else one; chosen
+    // automatically, four only for registers of >= kBatchFourMinQubits qubits:
+    // the smaller ones run launch-bound, where two columns in tiles of 12
+    // measured 10 % faster)
+    std::map<std::pair<int, int>, std::vector<int>> by_m;
+    for (int b = 0; b < B; ++b) {
+        const int maxw = ctx->opt_block == 0 && pbs[b].circ.n < kBatchFourMinQubits ? 2 : kMaxBlockWidth;
+        const int w = block_width(ctx->opt_block, pbs[b].circ, tun.tile_qubits, amp, f64, maxw);
+        by_m[{member_tile(pbs[b].circ, plan_tile(w, tun.tile_qubits), amp, f64), w}].push_back(b);
+    }
     size_t free_b = 0, total_b = 0;
     HIPCHECK(hipMemGetInfo(&free_b, &total_b));
     const uint64_t arena_cap = (uint64_t)(free_b + ctx->ws_bytes) / 4;
     for (auto &kv : by_m) {
-        // columns per lambda sweep: blocks of two for full tiles, as in the single step
-        const int width = block_width(ctx->opt_block, pbs[kv.second[0]].circ, tun.tile_qubits, amp, f64, 2);
-        std::vector<int32_t> key = {kv.first, amp, sweep_reg_mode(ctx, amp), tun.tile_qubits, tun.target_tiles,
+        const int width = kv.first.second;
+        const int tile = plan_tile(width, tun.tile_qubits);
+        std::vector<int32_t> key = {kv.first.first, amp, sweep_reg_mode(ctx, amp), tun.tile_qubits, tun.target_tiles,
                                     real_products ? 1 : 0, width};
         for (int b : kv.second) append_structure_key(pbs[b].circ, key);
         auto it = ctx->batch_classes.find(key);
@@ -924,7 +935,7 @@ BatchRun batch_metric(qng_ctx *ctx, const std::vector<Problem> &pbs, const doubl
             std::vector<std::shared_ptr<const SweepPlan>> plans;
             for (int b : kv.second) {
                 mem.push_back(&pbs[b].circ);
-                plans.push_back(ctx->sweep_cache.get_shared(pbs[b].circ, tun.tile_qubits, amp, 1, f64, width));
+                plans.push_back(ctx->sweep_cache.get_shared(pbs[b].circ, tile, amp, 1, f64, width));
             }
             bc = std::make_shared<BatchClass>();
             bc->sched = std::make_shared<BatchSchedule>(build_batch_schedule(mem, plans, amp, tun, arena_cap));

@@ -151,6 +151,8 @@ BatchSchedule build_batch_schedule(const std::vector<const Circuit *> &members,
             it.regA = (void *)(uintptr_t)a.reg;
             it.regB = (void *)(uintptr_t)(a.reg + V);
             it.regC = S.width > 1 ? (void *)(uintptr_t)(a.reg + 2 * V) : nullptr;
+            it.regD = S.width > 2 ? (void *)(uintptr_t)(a.reg + 3 * V) : nullptr;
+            it.regE = S.width > 3 ? (void *)(uintptr_t)(a.reg + 4 * V) : nullptr;
             S.items.push_back(it);
             ++L.n_items;
             L.total_tiles += tiles;
@@ -261,6 +263,8 @@ void upload_batch_images(const BatchSchedule &s, const BatchDevice &d, hipStream
         it.regA = d.arena + (uintptr_t)it.regA;
         it.regB = d.arena + (uintptr_t)it.regB;
         if (s.width > 1) it.regC = d.arena + (uintptr_t)it.regC;
+        if (s.width > 2) it.regD = d.arena + (uintptr_t)it.regD;
+        if (s.width > 3) it.regE = d.arena + (uintptr_t)it.regE;
     }
     auto put = [&](size_t off, const void *src, size_t bytes) {
         if (bytes) BCHECK(hipMemcpyAsync(d.images + off, src, bytes, hipMemcpyHostToDevice, st));
