@@ -148,6 +148,41 @@ def test_step_dev_complex64(ctx, qng):
     assert rel_err(dth.cpu().numpy(), h["dtheta"]) <= kappa * 1e-14
 
 
+@pytest.mark.parametrize("chunk", [0, 8], ids=["all kept", "chunks of 8"])
+def test_step_dev_derivative_states(ctx, qng, chunk):
+    """The derivative-state variant (QNG_OPT_METHOD = 1, the kept states in
+    chunks or all at once) through the device step: the host step's G and
+    gradient bitwise, dtheta to the solve's rounding, and the oracle."""
+    import torch
+    pr = W.scaled(W.config2, 11, 3, n_terms=8)
+    P = pr.n_params
+    circ = qng.Circuit.from_problem(pr)
+    dev = torch.device("cuda:0")
+    dth = torch.zeros(P, dtype=torch.float64, device=dev)
+    G = torch.zeros((P, P), dtype=torch.complex128, device=dev)
+    g = torch.zeros(P, dtype=torch.float64, device=dev)
+    ctx.set_option(qng.OPT_METHOD, 1)
+    ctx.set_option(qng.OPT_STATE_CHUNK, chunk)
+    ctx.set_stream(torch.cuda.current_stream().cuda_stream)
+    try:
+        ctx.step_dev(circ, pr.theta, pr.dt, pr.tikhonov, dth.data_ptr(), G.data_ptr(), g.data_ptr())
+        torch.cuda.synchronize()
+        chunks = ctx.stats()["state_chunks"]
+        ctx.set_stream(None)
+        h = ctx.step(circ, pr.theta, pr.dt, pr.tikhonov)
+    finally:
+        ctx.set_stream(None)
+        ctx.set_option(qng.OPT_METHOD, 0)
+        ctx.set_option(qng.OPT_STATE_CHUNK, 0)
+    assert chunks == 1 if chunk == 0 else chunks > 1
+    want = oracle.step(pr)
+    kappa = np.linalg.cond(want["G"].real + pr.tikhonov * np.eye(P))
+    assert np.array_equal(h["G"], G.cpu().numpy()) and np.array_equal(h["grad"], g.cpu().numpy())
+    assert rel_err(dth.cpu().numpy(), h["dtheta"]) <= kappa * 1e-14
+    assert rel_err(G.cpu().numpy(), want["G"]) <= TOL and rel_err(g.cpu().numpy(), want["grad"]) <= TOL
+    assert rel_err(dth.cpu().numpy(), want["dtheta"]) <= max(TOL, kappa * 1e-14)
+
+
 def test_step_dev_not_spd_writes_nothing(ctx, qng):
     """eps = 0 with a zero row of G (a leading RZ on |0>): the device solve
     finds a zero pivot; the status says QNG_E_NOT_SPD and no output changes."""
