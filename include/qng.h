@@ -101,9 +101,10 @@ typedef enum { QNG_C128 = 0, QNG_C64 = 1 } qng_precision;
  * G, T, E and the gradient, are the same functions of theta), which the fused
  * passes take too; a string with no letter (a global phase) keeps the circuit
  * on one kernel per sweep step.  With fusion off, one kernel per primitive
- * with the string kernels.  qng_plan_export rejects circuits with strings,
- * qng_step_batched both kinds, and the derivative-state variant
- * (QNG_OPT_METHOD = 1) controlled rotations, with QNG_E_UNSUPPORTED.
+ * with the string kernels.  qng_step_batched rewrites the strings the same
+ * way (always); with QNG_E_UNSUPPORTED it rejects controlled rotations and a
+ * string with no letter, qng_plan_export circuits with strings, and the
+ * derivative-state variant (QNG_OPT_METHOD = 1) controlled rotations.
  * Gates act in array order: gates[0] first. */
 typedef struct { int32_t kind, q0, q1, param; } qng_gate;
 

@@ -1043,6 +1043,19 @@ BatchRun batch_metric(qng_ctx *ctx, const std::vector<Problem> &pbs, const doubl
                 am[(size_t)(S.gate_base[i] + r.pos) * 8 + 0] = sh.u;
                 am[(size_t)(S.gate_base[i] + r.pos) * 8 + 1] = sh.w;
             }
+            // the fixed rotations of rewritten Pauli strings: the forward
+            // matrix and the adjoint's shear, as for the parameterised ones
+            for (int pos = 0; pos < pb.circ.M; ++pos) {
+                if (!pb.circ.is_fixed_rotation(pos)) continue;
+                const int kind = pb.circ.gates[pos].kind;
+                const Mat2 &m = pb.fwd[pos];
+                double *o = &fm[(size_t)(S.gate_base[i] + pos) * 8];
+                o[0] = m.a.real(); o[1] = m.a.imag(); o[2] = m.b.real(); o[3] = m.b.imag();
+                o[4] = m.c.real(); o[5] = m.c.imag(); o[6] = m.d.real(); o[7] = m.d.imag();
+                const Shear sh = adjoint_shear(kind == QNG_RX ? AX_X : kind == QNG_RY ? AX_Y : AX_Z, pb.adj[pos]);
+                am[(size_t)(S.gate_base[i] + pos) * 8 + 0] = sh.u;
+                am[(size_t)(S.gate_base[i] + pos) * 8 + 1] = sh.w;
+            }
         }
         std::vector<float> am32(am.begin(), am.end());
         if (S.mat_rows) {
@@ -1580,9 +1593,8 @@ qng_status qng_step_batched(qng_ctx *ctx, int32_t B, const qng_circuit *circs, c
             try {
                 validate_circuit(&circs[b], max_qubits(prec));
                 for (int k = 0; k < circs[b].n_gates; ++k)
-                    if (circs[b].gates[k].kind >= QNG_CRX)
-                        fail(QNG_E_UNSUPPORTED,
-                             "controlled and Pauli-string rotations are not available in qng_step_batched");
+                    if (circs[b].gates[k].kind >= QNG_CRX && circs[b].gates[k].kind <= QNG_CRZ)
+                        fail(QNG_E_UNSUPPORTED, "controlled rotations are not available in qng_step_batched");
                 validate_theta(&circs[b], thetas[b]);
                 validate_hamiltonian(&circs[b], &hams[b]);
                 if (circs[b].n_params > 0 && !dtheta_out[b]) fail(QNG_E_INVALID_ARG, "dtheta_out is NULL");
@@ -1598,7 +1610,12 @@ qng_status qng_step_batched(qng_ctx *ctx, int32_t B, const qng_circuit *circs, c
         if (!ctx->metric_blocks.empty())
             fail(QNG_E_INVALID_ARG, "the block-diagonal metric is not available in qng_step_batched");
         for (int b = 0; b < B; ++b) {
-            pbs.push_back(make_problem(&circs[b], thetas[b], &hams[b]));
+            // Pauli-string rotations rewritten onto gates the passes take
+            pbs.push_back(make_problem(&circs[b], thetas[b], &hams[b], true));
+            if (pbs.back().circ.has_strings)
+                fail(QNG_E_UNSUPPORTED, "ansatz " + std::to_string(b) +
+                                            ": a Pauli-string rotation with no letter is not available in "
+                                            "qng_step_batched");
             apply_metric_settings(ctx, pbs.back());
         }
         std::vector<std::vector<double>> G(B), graw(B);

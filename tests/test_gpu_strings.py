@@ -189,12 +189,37 @@ def test_strings_device_entry_points(env):
     assert abs(E.item() - Eo) <= TOL * max(1.0, abs(Eo))
 
 
-def test_strings_rejected_by_batched(env):
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_strings_in_batched(env, prec):
+    """qng_step_batched rewrites Pauli-string rotations as the single step does
+    (fixed basis rotations from the circuit's forward table, the passes' fixed
+    shears): members with strings beside plain ones, eager and replayed,
+    against the oracle (complex128 at 1e-10, complex64 at the FP32 rounding
+    bound of the rewritten gate count) and against the single step; a string
+    with no letter is rejected."""
     torch, q, ctx = env
-    probs = [W.scaled(W.config1, 6, 1, seed=5360), W.string_layers(5, 1, 4, 5361)]
+    probs = [W.scaled(W.config1, 6, 1, seed=5360), W.string_layers(5, 1, 4, 5361),
+             W.string_circuit(7, 40, 5362, n_terms=5), W.string_layers(12, 1, 6, 5363),
+             W.string_circuit(3, 12, 5364, n_terms=3)]
     circs = [q.Circuit.from_problem(p) for p in probs]
+    ths = [p.theta for p in probs]
+    for rep in range(2):   # the second call replays the captured graph
+        res = ctx.step_batched(circs, ths, 0.1, 1e-4, prec=prec)
+        for b, p in enumerate(probs):
+            want = oracle.step(p)
+            tol = TOL if prec == "c128" else 8 * np.sqrt(4 * p.n_gates) * 2.0 ** -24
+            eG, eg = rel_err(res[b]["G"], want["G"]), rel_err(res[b]["grad"], want["grad"])
+            say(f"{prec} rep {rep} member {b} ({p.name}): |dG|={eG:.2e} |dgrad|={eg:.2e}")
+            assert eG <= tol and eg <= tol, (b, eG, eg, tol)
+            single = ctx.step(circs[b], ths[b], 0.1, 1e-4, prec=prec)
+            assert rel_err(res[b]["G"], single["G"]) <= (1e-12 if prec == "c128" else tol)
+    # a string with no letter (a global phase) is not rewritten
+    bad = W.string_circuit(9, 50, 5390, n_terms=6)
+    bad.strings = bad.strings.copy()
+    bad.strings[0, :] = 0
     with pytest.raises(q.QNGError) as e:
-        ctx.step_batched(circs, [p.theta for p in probs], 0.1, 1e-4)
+        ctx.step_batched([q.Circuit.from_problem(probs[0]), q.Circuit.from_problem(bad)],
+                         [probs[0].theta, bad.theta], 0.1, 1e-4)
     assert e.value.name == "QNG_E_UNSUPPORTED"
 
 
