@@ -101,10 +101,11 @@ typedef enum { QNG_C128 = 0, QNG_C64 = 1 } qng_precision;
  * G, T, E and the gradient, are the same functions of theta), which the fused
  * passes take too; a string with no letter (a global phase) keeps the circuit
  * on one kernel per sweep step.  With fusion off, one kernel per primitive
- * with the string kernels.  qng_step_batched rewrites the strings the same
- * way (always); with QNG_E_UNSUPPORTED it rejects controlled rotations and a
- * string with no letter, qng_plan_export circuits with strings, and the
- * derivative-state variant (QNG_OPT_METHOD = 1) controlled rotations.
+ * with the string kernels.  qng_step_batched takes controlled rotations on
+ * the fused passes and rewrites the strings the same way (always); with
+ * QNG_E_UNSUPPORTED it rejects a string with no letter, qng_plan_export
+ * circuits with strings, and the derivative-state variant (QNG_OPT_METHOD =
+ * 1) controlled rotations.
  * Gates act in array order: gates[0] first. */
 typedef struct { int32_t kind, q0, q1, param; } qng_gate;
 

@@ -1042,6 +1042,12 @@ BatchRun batch_metric(qng_ctx *ctx, const std::vector<Problem> &pbs, const doubl
                 const Shear sh = adjoint_shear(r.axis, pb.adj[r.pos]);
                 am[(size_t)(S.gate_base[i] + r.pos) * 8 + 0] = sh.u;
                 am[(size_t)(S.gate_base[i] + r.pos) * 8 + 1] = sh.w;
+                if (r.ctrl >= 0) {
+                    // controlled rotations: the adjoint as a plane rotation
+                    const PlaneRot pl = adjoint_plane(r.axis, pb.adj[r.pos]);
+                    am[(size_t)(S.gate_base[i] + r.pos) * 8 + 2] = pl.c;
+                    am[(size_t)(S.gate_base[i] + r.pos) * 8 + 3] = pl.s;
+                }
             }
             // the fixed rotations of rewritten Pauli strings: the forward
             // matrix and the adjoint's shear, as for the parameterised ones
@@ -1592,9 +1598,6 @@ qng_status qng_step_batched(qng_ctx *ctx, int32_t B, const qng_circuit *circs, c
         for (int b = 0; b < B; ++b) {
             try {
                 validate_circuit(&circs[b], max_qubits(prec));
-                for (int k = 0; k < circs[b].n_gates; ++k)
-                    if (circs[b].gates[k].kind >= QNG_CRX && circs[b].gates[k].kind <= QNG_CRZ)
-                        fail(QNG_E_UNSUPPORTED, "controlled rotations are not available in qng_step_batched");
                 validate_theta(&circs[b], thetas[b]);
                 validate_hamiltonian(&circs[b], &hams[b]);
                 if (circs[b].n_params > 0 && !dtheta_out[b]) fail(QNG_E_INVALID_ARG, "dtheta_out is NULL");

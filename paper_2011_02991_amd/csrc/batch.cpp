@@ -61,9 +61,11 @@ BatchSchedule build_batch_schedule(const std::vector<const Circuit *> &members,
             S.m = p.m;
             S.rb = p.rb;
             S.width = p.width;
+            S.ctrl = false;
         } else if (p.m != S.m || p.rb != S.rb || p.width != S.width) {
             fail(QNG_E_DEVICE, "batch schedule: members of one class differ in tile or block width (internal)");
         }
+        S.ctrl = S.ctrl || p.ctrl;
         pass_base[b] = (int64_t)S.passes.size();
         const uint32_t op_base = (uint32_t)S.ops.size(), map_base = (uint32_t)S.maps.size();
         S.gate_base[b] = S.mat_rows;
@@ -195,10 +197,17 @@ BatchSchedule build_batch_schedule(const std::vector<const Circuit *> &members,
         }
         for (int r = 0; r < nr; ++r) {
             BatchRound R{(uint32_t)S.seeds.size(), 0, 0, 0};
-            // registers of >= 3 qubits first (the one kernel's items), then the rest
+            // the one kernel's items first (registers of >= 3 qubits, no controlled
+            // rotation at the seed), then the seeds run on their own
+            auto multi = [&](uint32_t k) {
+                const BatchPrep &pr = S.preps[L.prep_begin + k];
+                const Circuit &c = *members[pr.member];
+                const int sidx = plans[pr.member]->cols[pr.col].s;
+                return c.n >= 3 && c.rots[sidx].ctrl < 0 && c.rots[sidx - 1].ctrl < 0;
+            };
             for (int big = 1; big >= 0; --big)
             for (uint32_t k = 0; k < L.n_preps; ++k) {
-                if (ridx[k] != r || (members[S.preps[L.prep_begin + k].member]->n >= 3) != (big == 1)) continue;
+                if (ridx[k] != r || multi(k) != (big == 1)) continue;
                 const BatchPrep &pr = S.preps[L.prep_begin + k];
                 const Circuit &c = *members[pr.member];
                 const int sidx = plans[pr.member]->cols[pr.col].s;
@@ -216,8 +225,11 @@ BatchSchedule build_batch_schedule(const std::vector<const Circuit *> &members,
                 sd.lam_off = pr.reg_off;
                 sd.phi_off = pr.reg_off + (uint64_t)S.width * (uint64_t(1) << c.n) * (uint64_t)amp;
                 const int ra = p < c.M ? c.rot_at[p] : -1;
-                if (ra >= 0 && p + 1 == rp.pos && rs.pos == rp.pos + 1 && c.n >= 3 && c.rots[ra].qubit != rp.qubit &&
-                    c.rots[ra].qubit != rs.qubit && rp.qubit != rs.qubit) {
+                if (rs.ctrl >= 0 || rp.ctrl >= 0) {
+                    sd.fwd_to = rs.pos;          // every gate up to y_s, then the generator's seed
+                    sd.ctrl = 1;
+                } else if (ra >= 0 && c.rots[ra].ctrl < 0 && p + 1 == rp.pos && rs.pos == rp.pos + 1 && c.n >= 3 &&
+                           c.rots[ra].qubit != rp.qubit && c.rots[ra].qubit != rs.qubit && rp.qubit != rs.qubit) {
                     sd.qa = c.rots[ra].qubit;   // two rotations before y_s
                     sd.pa = p;
                     sd.qb = rp.qubit;
@@ -230,7 +242,7 @@ BatchSchedule build_batch_schedule(const std::vector<const Circuit *> &members,
                     sd.fwd_to = rs.pos;          // every gate up to y_s
                 }
                 p = rs.pos;
-                if (c.n >= 3) {
+                if (c.n >= 3 && !sd.ctrl) {
                     const uint64_t groups = uint64_t(1) << (c.n - 3);
                     sd.nblocks = (uint32_t)std::min<uint64_t>(kSeedBlocksMax, (groups + 255) / 256);
                     sd.block_begin = R.total_blocks;
@@ -310,6 +322,21 @@ void enqueue_batch_metric(const BatchSchedule &s, const std::vector<const Circui
     const int nb = (int)members.size();
     std::vector<int> pos(nb, 0);
     std::vector<char> started(nb, 0);
+    std::vector<std::vector<uint8_t>> diag_done(nb);
+
+    // A controlled rotation r has the diagonal element <y_r|(|1><1| on its
+    // control)|y_r> (Sec. 2) instead of a constant: taken once, where the
+    // forward register of its member holds y_r.
+    auto control_diag = [&](int b, int r) {
+        const Circuit &c = *members[b];
+        const Rot &rr = c.rots[r];
+        if (rr.ctrl < 0) return;
+        if (diag_done[b].empty()) diag_done[b].assign((size_t)c.P, 0);
+        if (diag_done[b][r]) return;
+        diag_done[b][r] = 1;
+        launch_pauli_prod<R>(d.psi[b], d.psi[b], c.n, rr.ctrl, -1, d.reduce_partials,
+                             d.lraw + 2 * (s.lraw_base[b] + (int64_t)r * c.P + r), st, rr.ctrl);
+    };
 
     // forward gates of member b up to `target`; with a scratch register free,
     // a run of three or more CNOTs is one gather and one copy back
@@ -331,9 +358,17 @@ void enqueue_batch_metric(const BatchSchedule &s, const std::vector<const Circui
                     continue;
                 }
             }
-            if (g.kind == QNG_CNOT) launch_cnot<R>(d.psi[b], nullptr, c.n, g.q0, g.q1, st);
-            else if (g.kind == QNG_CZ) launch_cz<R>(d.psi[b], nullptr, c.n, g.q0, g.q1, st);
-            else launch_apply_1q_tab<R>(d.psi[b], nullptr, c.n, g.q0, d.fwd_mats + (s.gate_base[b] + pos[b]) * 8, st);
+            if (g.kind == QNG_CNOT) {
+                launch_cnot<R>(d.psi[b], nullptr, c.n, g.q0, g.q1, st);
+            } else if (g.kind == QNG_CZ) {
+                launch_cz<R>(d.psi[b], nullptr, c.n, g.q0, g.q1, st);
+            } else if (g.kind >= QNG_CRX && g.kind <= QNG_CRZ) {
+                control_diag(b, c.rot_at[pos[b]]);   // (q0 the control, q1 the target)
+                launch_apply_c1q_tab<R>(d.psi[b], nullptr, c.n, g.q0, g.q1,
+                                        d.fwd_mats + (s.gate_base[b] + pos[b]) * 8, st);
+            } else {
+                launch_apply_1q_tab<R>(d.psi[b], nullptr, c.n, g.q0, d.fwd_mats + (s.gate_base[b] + pos[b]) * 8, st);
+            }
         }
     };
     auto start = [&](int b) {
@@ -342,7 +377,8 @@ void enqueue_batch_metric(const BatchSchedule &s, const std::vector<const Circui
         const Circuit &c = *members[b];
         forward_to(b, c.rots[0].pos, nullptr);
         launch_pauli_prod<R>(d.psi[b], d.psi[b], c.n, c.rots[0].qubit, c.rots[0].axis, d.reduce_partials, d.traw[b],
-                             st);
+                             st, c.rots[0].ctrl);
+        control_diag(b, 0);
     };
     for (int b : s.singles) start(b);
     const SeedItem *seed_items = (const SeedItem *)(d.images + IL.seed_items);
@@ -358,7 +394,15 @@ void enqueue_batch_metric(const BatchSchedule &s, const std::vector<const Circui
                 start(sd.member);
                 char *lam = d.arena + sd.lam_off;
                 if (sd.fwd_to >= 0) forward_to(sd.member, sd.fwd_to, lam);
-                if (sd.nblocks == 0) {
+                if (sd.ctrl) {
+                    // a controlled rotation at either end: psi = y_s, seeded with the generator
+                    const Circuit &c = *members[sd.member];
+                    const Rot &rs = c.rots[sd.s];
+                    launch_seed<R>(d.psi[sd.member], lam, d.arena + sd.phi_off, c.n, rs.qubit, rs.axis, st, rs.ctrl);
+                    launch_pauli_prod<R>(d.psi[sd.member], d.psi[sd.member], c.n, rs.qubit, rs.axis, d.reduce_partials,
+                                         d.traw[sd.member] + 2 * sd.s, st, rs.ctrl);
+                    control_diag(sd.member, sd.s);
+                } else if (sd.nblocks == 0) {
                     // a register below 3 qubits: seeded on its own
                     const Circuit &c = *members[sd.member];
                     const double *mrow = sd.qa >= 0 ? d.fwd_mats + (s.gate_base[sd.member] + sd.pa) * 8 : d.fwd_mats;
@@ -374,7 +418,7 @@ void enqueue_batch_metric(const BatchSchedule &s, const std::vector<const Circui
         }
         if (events) BCHECK(hipEventRecord((*events)[2 * li], st));
         launch_sweep_pass<R>(items + L.item_begin, (int)L.n_items, L.total_tiles, passes, ops, maps, d.adj_mats,
-                             d.adj_mats32, d.partials, s.m, s.rb, reg_mode, s.width, st, real_products);
+                             d.adj_mats32, d.partials, s.m, s.rb, reg_mode, s.width, st, real_products, s.ctrl);
         if (events) BCHECK(hipEventRecord((*events)[2 * li + 1], st));
         launch_reduce_tasks(tasks + L.task_begin, (int)L.n_tasks, d.partials, d.lraw, st);
     }

@@ -54,7 +54,10 @@ struct BatchSeed {
     int qa, pa, qb, pb;          // rotations the seed kernel applies (qubit, gate position; -1: none)
     int qs, axis, s;             // the seeded column
     uint64_t lam_off, phi_off;   // arena offsets of lambda and the block's top phi register
-    uint32_t block_begin, nblocks;   // work-groups within the round (0: seeded on its own, register < 3 qubits)
+    uint32_t block_begin, nblocks;   // work-groups within the round (0: seeded on its own, see ctrl)
+    int ctrl;                    // 1: rotation s or s - 1 is controlled; the forward register is brought to
+                                 // y_s gate by gate and the column seeded with its generator (nblocks 0;
+                                 // also 0 for registers below 3 qubits)
 };
 struct BatchRound {
     uint32_t seed_begin, n_seeds, total_blocks;
@@ -64,6 +67,7 @@ struct BatchRound {
 struct BatchSchedule {
     int m = 0, rb = 0, amp = 0;
     int width = 1;                                           // columns per lambda sweep (all members)
+    bool ctrl = false;                                       // some member has controlled rotations
     std::vector<std::shared_ptr<const SweepPlan>> plans;     // per member
     std::vector<DevPass> passes;                             // merged images
     std::vector<DevOp> ops;

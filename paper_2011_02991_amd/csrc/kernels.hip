@@ -166,6 +166,21 @@ __global__ void k_apply_c1q(typename Cplx<R>::T *s0, typename Cplx<R>::T *s1, in
     }
 }
 
+// Same, with the matrix read from device memory (as k_apply_1q_tab).
+template <typename R>
+__global__ void k_apply_c1q_tab(typename Cplx<R>::T *s0, typename Cplx<R>::T *s1, int n, int c, int q,
+                                const double *__restrict__ mt) {
+    const uint64_t nq = uint64_t(1) << (n - 2);
+    const int lo = c < q ? c : q, hi = c < q ? q : c;
+    const R ar = (R)mt[0], ai = (R)mt[1], br = (R)mt[2], bi = (R)mt[3];
+    const R cr = (R)mt[4], ci = (R)mt[5], dr = (R)mt[6], di = (R)mt[7];
+    for (uint64_t p = blockIdx.x * (uint64_t)kBlock + threadIdx.x; p < nq; p += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t i0 = insert_two_zeros(p, lo, hi) | (uint64_t(1) << c), i1 = i0 | (uint64_t(1) << q);
+        mat_pair<R>(s0, i0, i1, ar, ai, br, bi, cr, ci, dr, di);
+        if (s1) mat_pair<R>(s1, i0, i1, ar, ai, br, bi, cr, ci, dr, di);
+    }
+}
+
 // Pauli string S in mask form: (S psi)[x] = w (-1)^{popcount(x & zy)} psi[x ^ flip],
 // w = (-i)^{n_y}.  A rotation c + kappa S' with S' the string without w (the
 // host folds w and i sin into kappa): out[x] = c psi[x] + kappa sgn(x) psi[x ^ flip].
@@ -974,6 +989,13 @@ void launch_apply_c1q(void *s0, void *s1, int n, int c, int q, const DevMat2 &m,
     check_launch();
 }
 
+template <typename R>
+void launch_apply_c1q_tab(void *s0, void *s1, int n, int c, int q, const double *m_dev, hipStream_t st) {
+    hipLaunchKernelGGL(k_apply_c1q_tab<R>, dim3(grid_for(uint64_t(1) << (n - 2))), dim3(kBlock), 0, st,
+                       (typename Cplx<R>::T *)s0, (typename Cplx<R>::T *)s1, n, c, q, m_dev);
+    check_launch();
+}
+
 // w = (-i)^{n_y}
 inline void string_phase(int n_y, double &wr, double &wi) {
     wr = 1.0;
@@ -1226,6 +1248,7 @@ void launch_grad_from_raw(const double *graw, const int *param_of, int P, double
     template void launch_apply_1q<R>(void *, void *, int, int, const DevMat2 &, hipStream_t);                     \
     template void launch_apply_1q_tab<R>(void *, void *, int, int, const double *, hipStream_t);                  \
     template void launch_apply_c1q<R>(void *, void *, int, int, int, const DevMat2 &, hipStream_t);               \
+    template void launch_apply_c1q_tab<R>(void *, void *, int, int, int, const double *, hipStream_t);            \
     template void launch_apply_string<R>(void *, void *, int, uint64_t, uint64_t, int, double, double, double,      \
                                          hipStream_t);                                                            \
     template void launch_seed_string<R>(const void *, void *, void *, int, uint64_t, uint64_t, int, hipStream_t);  \

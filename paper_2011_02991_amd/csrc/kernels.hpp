@@ -64,6 +64,9 @@ template <typename R> void launch_apply_1q_tab(void *s0, void *s1, int n, int q,
 // Controlled: the matrix acts on qubit q where qubit c (!= q) is 1.
 template <typename R>
 void launch_apply_c1q(void *s0, void *s1, int n, int c, int q, const DevMat2 &m, hipStream_t st);
+// The same with the matrix in device memory (8 doubles), for captured graphs.
+template <typename R>
+void launch_apply_c1q_tab(void *s0, void *s1, int n, int c, int q, const double *m_dev, hipStream_t st);
 template <typename R> void launch_cnot(void *s0, void *s1, int n, int control, int target, hipStream_t st);
 
 // A run of CNOTs (control[k], target[k], k = 0 .. count-1, applied in that

@@ -195,13 +195,32 @@ def test_controlled_device_entry_points(env):
     assert abs(E.item() - Eo) <= TOL * max(1.0, abs(Eo))
 
 
-def test_controlled_rejected_by_batched(env):
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_controlled_in_batched(env, prec):
+    """qng_step_batched with controlled rotations beside plain members: the
+    batch's forward registers apply them from the gate table and take their
+    diagonals (1/4 Prob(control = 1)) on the way, a column whose top or the
+    rotation below it is controlled is seeded on its own with its generator,
+    and the sweeps run the kernels with the controlled handlers.  Eager and
+    replayed, against the oracle (complex128 at 1e-10, complex64 at the FP32
+    rounding bound) and against the single step."""
     torch, q, ctx = env
-    probs = [W.scaled(W.config1, 6, 1, seed=5260), W.controlled_layers(5, 1, 4, 5261)]
+    probs = [W.scaled(W.config1, 6, 1, seed=5260), W.controlled_layers(5, 1, 4, 5261),
+             W.controlled_circuit(7, 40, 5262, n_terms=5), W.controlled_layers(12, 2, 6, 5263),
+             W.controlled_circuit(3, 14, 5264, n_terms=3), W.controlled_layers(2, 2, 3, 5265)]
+    probs[2].in_state = W.random_state(7, 5266)
     circs = [q.Circuit.from_problem(p) for p in probs]
-    with pytest.raises(q.QNGError) as e:
-        ctx.step_batched(circs, [p.theta for p in probs], 0.1, 1e-4)
-    assert e.value.name == "QNG_E_UNSUPPORTED"
+    ths = [p.theta for p in probs]
+    for rep in range(2):   # the second call replays the captured graph
+        res = ctx.step_batched(circs, ths, 0.1, 1e-4, in_states=[p.in_state for p in probs], prec=prec)
+        for b, p in enumerate(probs):
+            want = oracle.step(p)
+            tol = TOL if prec == "c128" else 8 * np.sqrt(p.n_gates) * 2.0 ** -24
+            eG, eg = rel_err(res[b]["G"], want["G"]), rel_err(res[b]["grad"], want["grad"])
+            say(f"{prec} rep {rep} member {b} ({p.name}): |dG|={eG:.2e} |dgrad|={eg:.2e}")
+            assert eG <= tol and eg <= tol, (b, eG, eg, tol)
+            single = ctx.step(circs[b], ths[b], 0.1, 1e-4, in_state=p.in_state, prec=prec)
+            assert rel_err(res[b]["G"], single["G"]) <= (1e-12 if prec == "c128" else tol)
 
 
 @pytest.mark.timeout(600)
