@@ -101,11 +101,10 @@ typedef enum { QNG_C128 = 0, QNG_C64 = 1 } qng_precision;
  * G, T, E and the gradient, are the same functions of theta), which the fused
  * passes take too; a string with no letter (a global phase) keeps the circuit
  * on one kernel per sweep step.  With fusion off, one kernel per primitive
- * with the string kernels.  qng_step_batched takes controlled rotations on
- * the fused passes and rewrites the strings the same way (always); with
- * QNG_E_UNSUPPORTED it rejects a string with no letter, qng_plan_export
- * circuits with strings, and the derivative-state variant (QNG_OPT_METHOD =
- * 1) controlled rotations.
+ * with the string kernels.  qng_step_batched and the derivative-state
+ * variant (QNG_OPT_METHOD = 1) take controlled rotations on the fused passes
+ * and rewrite the strings the same way; with QNG_E_UNSUPPORTED both reject a
+ * string with no letter, and qng_plan_export circuits with strings.
  * Gates act in array order: gates[0] first. */
 typedef struct { int32_t kind, q0, q1, param; } qng_gate;
 
@@ -170,9 +169,9 @@ typedef enum {
                                     device memory in all) and all inner products are one Gram matrix on the
                                     matrix cores (FP64 products and sums).  Where they do not fit (free device
                                     memory, qng_set_mem_limit) or QNG_OPT_STATE_CHUNK asks for it, the columns
-                                    are prepared in chunks (see there).  Method 1 takes the plain gate set and
-                                    the full metric (QNG_E_UNSUPPORTED otherwise); qng_step_batched uses
-                                    method 0. */,
+                                    are prepared in chunks (see there).  Method 1 takes the fused passes'
+                                    gate set (no string without a letter) and the full metric
+                                    (QNG_E_UNSUPPORTED otherwise); qng_step_batched uses method 0. */,
     QNG_OPT_STATE_CHUNK = 13     /* method 1: at most this many derivative states per chunk, but at least one
                                     column block (0 = automatic: all P when they fit, else the most that
                                     fit).  With K > 1 chunks (whole column

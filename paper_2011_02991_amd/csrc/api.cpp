@@ -649,9 +649,9 @@ CallResult run(qng_ctx *ctx, const Problem &pb, const CallSpec &spec) {
     // derivative-state variant: every column's swept phi register is kept and
     // the metric is their Gram matrix (P + 1 more states)
     const bool states = ctx->opt_method == 1 && spec.metric && c.P > 1;
-    if (states && (!fused || c.controlled || !pb.rot_block.empty()))
-        fail(QNG_E_UNSUPPORTED, "the derivative-state variant takes the fused passes of single-qubit rotations, "
-                                "CNOT and CZ and the full metric");
+    if (states && (!fused || !pb.rot_block.empty()))
+        fail(QNG_E_UNSUPPORTED, "the derivative-state variant takes the fused passes (no Pauli string without a "
+                                "letter) and the full metric");
     const SweepPlan *plan = nullptr;
     FusedRun fr;
     size_t scratch = 0, gram_bytes = 0;

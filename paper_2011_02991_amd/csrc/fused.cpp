@@ -343,8 +343,16 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
         // applied): lambda* = R_0 y_0 there, and column 0's derivative state is
         // sigma_0 lambda* (R_0 commutes with sigma_0)
         const Rot &r0 = c.rots[0];
-        launch_advance_seed<R>(psi, buf.xi, buf.xi + V, n, r0.qubit, d_fmats + (size_t)r0.pos * 8, r0.qubit, r0.axis,
-                               buf.reduce_partials, buf.traw, st);
+        if (r0.ctrl >= 0) {
+            // a controlled rotation 0: its diagonal at y_0, then the gate, and
+            // column 0's state K_0 lambda* (K_0 commutes with the gate)
+            control_diag(0);
+            launch_apply_c1q<R>(psi, nullptr, n, r0.ctrl, r0.qubit, to_dev(fwd[r0.pos]), st);
+            launch_seed<R>(psi, buf.xi, buf.xi + V, n, r0.qubit, r0.axis, st, r0.ctrl);
+        } else {
+            launch_advance_seed<R>(psi, buf.xi, buf.xi + V, n, r0.qubit, d_fmats + (size_t)r0.pos * 8, r0.qubit,
+                                   r0.axis, buf.reduce_partials, buf.traw, st);
+        }
         pos = r0.pos + 1;
     } else {
         launch_pauli_prod<R>(psi, psi, n, c.rots[0].qubit, c.rots[0].axis, buf.reduce_partials, buf.traw, st,
@@ -454,7 +462,7 @@ int run_fused_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &c
             if (profile) FCHECK(hipEventRecord(ev[2 * li], st));
             if (states)
                 launch_sweep_pass_states<R>(d_items + L.item_begin, (int)L.n_items, L.total_tiles, d_passes, d_ops,
-                                            d_maps, d_mats, d_mats32, plan.m, plan.rb, W, st);
+                                            d_maps, d_mats, d_mats32, plan.m, plan.rb, W, st, plan.ctrl);
             else
                 launch_sweep_pass<R>(d_items + L.item_begin, (int)L.n_items, L.total_tiles, d_passes, d_ops, d_maps,
                                      d_mats, d_mats32, d_partials, plan.m, plan.rb, reg_mode, W, st, real_products,
@@ -550,9 +558,13 @@ int run_states_metric(const SweepPlan &plan, const FusedRun &fr, const Circuit &
     // after: every register of the block ends with the product of the signs of
     // rotations 1 .. s-1.  lambda* and column 0's state carry none.  Indexed
     // by column + 1.
+    // (a controlled rotation's adjoint is applied as an exact plane rotation:
+    // no sign)
     std::vector<int8_t> prefix((size_t)c.P + 1, 1);   // prefix[s]: signs of rotations 1 .. s-1
-    for (int s = 2; s <= c.P; ++s)
-        prefix[s] = (int8_t)(adj[c.rots[s - 1].pos].a.real() < 0 ? -prefix[s - 1] : prefix[s - 1]);
+    for (int s = 2; s <= c.P; ++s) {
+        const Rot &r = c.rots[s - 1];
+        prefix[s] = (int8_t)(r.ctrl < 0 && adj[r.pos].a.real() < 0 ? -prefix[s - 1] : prefix[s - 1]);
+    }
     std::vector<int8_t> signs((size_t)c.P + 1, 1);
     for (const ColumnPlan &cp : plan.cols)
         for (int k = 0; k < W; ++k) {

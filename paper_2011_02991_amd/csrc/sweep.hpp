@@ -364,7 +364,7 @@ void launch_reduce_tasks(const ReduceTask *tasks, int n_tasks, const double *par
 template <typename R>
 void launch_sweep_pass_states(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
                               const DevOp *ops, const DevMap *maps, const double *mats64, const float *mats32, int m,
-                              int rb, int width, hipStream_t st);
+                              int rb, int width, hipStream_t st, bool ctrl = false);
 
 
 }  // namespace qng

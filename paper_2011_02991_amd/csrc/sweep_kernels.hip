@@ -1080,17 +1080,19 @@ template <int J, int RB, int T, typename CT, int W>
 __device__ __forceinline__ void crot_handlers(Regs<CT, T, W> &x, uint32_t h2, uint32_t on, CT c, CT s,
                                               double2 *sink, double2 *red, int slot, int fa, int tid) {
     if constexpr (J < RB) {
-        if (h2 & (h2bit(HB2_PRODCROT_X + J) | h2bit(HB2_PRODC_X + J))) {
-            const Regs<CT, T, W> y = masked_lambda<T, CT, W>(x, on, 0u);
-            double pr[W], pi[W];
-            prodw_xy<J, 0, T, CT, W>(y, pr, pi);
-            row_reduce_store<W>(sink, red, slot, fa, tid, pr, pi);
-        }
-        if (h2 & (h2bit(HB2_PRODCROT_Y + J) | h2bit(HB2_PRODC_Y + J))) {
-            const Regs<CT, T, W> y = masked_lambda<T, CT, W>(x, on, 0u);
-            double pr[W], pi[W];
-            prodw_xy<J, 1, T, CT, W>(y, pr, pi);
-            row_reduce_store<W>(sink, red, slot, fa, tid, pr, pi);
+        if constexpr (!kNoProducts) {
+            if (h2 & (h2bit(HB2_PRODCROT_X + J) | h2bit(HB2_PRODC_X + J))) {
+                const Regs<CT, T, W> y = masked_lambda<T, CT, W>(x, on, 0u);
+                double pr[W], pi[W];
+                prodw_xy<J, 0, T, CT, W>(y, pr, pi);
+                row_reduce_store<W>(sink, red, slot, fa, tid, pr, pi);
+            }
+            if (h2 & (h2bit(HB2_PRODCROT_Y + J) | h2bit(HB2_PRODC_Y + J))) {
+                const Regs<CT, T, W> y = masked_lambda<T, CT, W>(x, on, 0u);
+                double pr[W], pi[W];
+                prodw_xy<J, 1, T, CT, W>(y, pr, pi);
+                row_reduce_store<W>(sink, red, slot, fa, tid, pr, pi);
+            }
         }
         if (h2 & (h2bit(HB2_PRODCROT_X + J) | h2bit(HB2_CROT_X + J))) crot_xy<J, 0, T, CT, W>(x, on, c, s);
         if (h2 & (h2bit(HB2_PRODCROT_Y + J) | h2bit(HB2_CROT_Y + J))) crot_xy<J, 1, T, CT, W>(x, on, c, s);
@@ -1380,10 +1382,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNoPro
                 QNG_STORE_PRODS();
             }
         }
-        if constexpr (CTRL && !kNoProducts) {
+        if constexpr (CTRL) {
             // controlled rotations (second handler word): the control's value per
             // register, the adjoint's plane rotation from the table's third and
-            // fourth entries
+            // fourth entries (without products: the adjoints and seeds alone)
             const uint32_t h2 = op.h2;
             if (h2) {
                 const uint32_t on = loc_mask<T>(op.b1(), op.q1(), tid, base);
@@ -1395,7 +1397,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNoPro
                 if (h2 & crot_bits(3)) crot_handlers<3, RB, T, CT, W>(x, h2, on, c, s, sink, red, slot, fa, tid);
                 if (h2 & (h2bit(HB2_CDIAG) | h2bit(HB2_PRODCDIAG) | h2bit(HB2_PRODCZ))) {
                     const uint32_t one = loc_mask<T>(op.b0(), op.q0(), tid, base);
-                    if (h2 & (h2bit(HB2_PRODCDIAG) | h2bit(HB2_PRODCZ))) {
+                    if (!kNoProducts && (h2 & (h2bit(HB2_PRODCDIAG) | h2bit(HB2_PRODCZ)))) {
                         const Regs<CT, T, W> y = masked_lambda<T, CT, W>(x, on, one);
                         double pr[W], pi[W];
                         prodw_plain<T, CT, W>(y, pr, pi);
@@ -1414,10 +1416,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kNoPro
                             x.br[0][i] *= f;
                             x.bi[0][i] *= f;
                         }
-                        double pr, pi;
-                        prod_plain<T, CT>(x.ar, x.ai, x.br[0], x.bi[0], pr, pi);
-                        row_store(sink, red, slot, tid, pr, pi);
-                        if (pass_zsum) tile_sums<T, CT, W, 0, 1>(x, sink, zs, tid, Sr, Si);
+                        if constexpr (!kNoProducts) {
+                            double pr, pi;
+                            prod_plain<T, CT>(x.ar, x.ai, x.br[0], x.bi[0], pr, pi);
+                            row_store(sink, red, slot, tid, pr, pi);
+                            if (pass_zsum) tile_sums<T, CT, W, 0, 1>(x, sink, zs, tid, Sr, Si);
+                        }
                     }
                 }
             }
@@ -1559,14 +1563,10 @@ void launch_full(const LaunchItem *items, int n_items, uint32_t total_tiles, con
 template <typename R, typename CT, int RB, bool FULL, int W>
 void launch_ctrl(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes, const DevOp *ops,
                  const DevMap *maps, const CT *mats, double *partials, int m, bool ctrl, hipStream_t st) {
-    if constexpr (!kNoProducts) {
-        if (ctrl) {
-            launch_full<R, CT, RB, FULL, W, true>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m,
-                                                  st);
-            return;
-        }
+    if (ctrl) {
+        launch_full<R, CT, RB, FULL, W, true>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st);
+        return;
     }
-    if (ctrl) throw hipErrorInvalidValue;
     launch_full<R, CT, RB, FULL, W, false>(items, n_items, total_tiles, passes, ops, maps, mats, partials, m, st);
 }
 
@@ -1648,21 +1648,21 @@ void launch_ct(const LaunchItem *items, int n_items, uint32_t total_tiles, const
 template <typename R>
 void launch_sweep_pass_states(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
                               const DevOp *ops, const DevMap *maps, const double *mats64, const float *mats32, int m,
-                              int rb, int width, hipStream_t st) {
+                              int rb, int width, hipStream_t st, bool ctrl) {
     if (n_items <= 0 || total_tiles == 0) return;
     if constexpr (sizeof(R) == 8)
-        launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, nullptr, m, rb, width, false, st);
+        launch_ct<R, double>(items, n_items, total_tiles, passes, ops, maps, mats64, nullptr, m, rb, width, ctrl, st);
     else
-        launch_ct<R, float>(items, n_items, total_tiles, passes, ops, maps, mats32, nullptr, m, rb, width, false, st);
+        launch_ct<R, float>(items, n_items, total_tiles, passes, ops, maps, mats32, nullptr, m, rb, width, ctrl, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) throw e;
 }
 template void launch_sweep_pass_states<double>(const LaunchItem *, int, uint32_t, const DevPass *, const DevOp *,
                                                const DevMap *, const double *, const float *, int, int, int,
-                                               hipStream_t);
+                                               hipStream_t, bool);
 template void launch_sweep_pass_states<float>(const LaunchItem *, int, uint32_t, const DevPass *, const DevOp *,
                                               const DevMap *, const double *, const float *, int, int, int,
-                                              hipStream_t);
+                                              hipStream_t, bool);
 #elif QNG_REAL_PRODUCTS && QNG_EXACT_PRODUCTS
 void launch_sweep_pass_real_exact(const LaunchItem *items, int n_items, uint32_t total_tiles, const DevPass *passes,
                                   const DevOp *ops, const DevMap *maps, const float *mats32, double *partials, int m,

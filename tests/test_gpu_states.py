@@ -109,10 +109,15 @@ def test_states_complex64(env, make):
 
 def test_states_rejections(env):
     q, ctx = env
-    pr = W.controlled_circuit(5, 20, 8110, n_terms=3)
-    with pytest.raises(q.QNGError) as e:
-        step(q, ctx, pr, 1)
-    assert e.value.name == "QNG_E_UNSUPPORTED"
+    pr = W.scaled(W.config1, 6, 2, n_terms=3)
+    # the block-diagonal metric keeps to the recurrence
+    ctx.set_metric_blocks([b % 2 for b in range(pr.n_params)])
+    try:
+        with pytest.raises(q.QNGError) as e:
+            step(q, ctx, pr, 1)
+        assert e.value.name == "QNG_E_UNSUPPORTED"
+    finally:
+        ctx.set_metric_blocks(None)
     pr = W.scaled(W.config1, 14, 2, n_terms=3)
     # the Gram matrix's partial sums alone take 8 MiB at 14 qubits
     ctx.set_mem_limit(4 << 20)
@@ -125,6 +130,39 @@ def test_states_rejections(env):
         assert e.value.name == "QNG_E_INVALID_ARG"
     finally:
         ctx.set_mem_limit(0)
+
+
+@pytest.mark.parametrize("make,chunk", [
+    (lambda: W.controlled_circuit(7, 40, 8120, n_terms=5), 0),
+    (lambda: W.controlled_layers(12, 2, 6, 8121), 0),
+    (lambda: W.controlled_layers(11, 2, 6, 8122), 9),
+    (lambda: W.controlled_circuit(3, 14, 8123, n_terms=3), 0)],
+    ids=["random n7", "ring n12", "ring n11 chunks of 9", "random n3"])
+def test_states_controlled(env, make, chunk):
+    """Controlled rotations in the derivative-state variant: the no-product
+    sweeps with the controlled handlers (exact plane rotations, so they add no
+    sign to the kept states), columns whose top or the rotation below it is
+    controlled seeded with the generator, the diagonals 1/4 Prob(control = 1)
+    taken on the forward register; against the oracle, and the recurrence on
+    every entry."""
+    q, ctx = env
+    pr = make()
+    if pr.n_qubits == 7:
+        pr.in_state = W.random_state(7, 8124)
+    res, T, k = chunked(q, ctx, pr, chunk, "c128")
+    assert k == 1 if chunk == 0 else k > 1
+    want = oracle.step(pr)
+    kappa = np.linalg.cond(want["G"].real + pr.tikhonov * np.eye(pr.n_params))
+    eG, eT = rel_err(res["G"], want["G"]), rel_err(T, want["T"])
+    eg, ed = rel_err(res["grad"], want["grad"]), rel_err(res["dtheta"], want["dtheta"])
+    say(f"{pr.name} (chunk {chunk}): |dG|={eG:.2e} |dT|={eT:.2e} |dgrad|={eg:.2e} |ddtheta|={ed:.2e}")
+    assert max(eG, eT, eg) <= TOL and ed <= max(TOL, kappa * 1e-14)
+    rec, Tr = step(q, ctx, pr, 0)
+    assert rel_err(res["G"], rec["G"]) <= TOL and rel_err(T, Tr) <= TOL
+    # complex64 against complex128 at the sweeps' rounding bound
+    r64, T64, _ = chunked(q, ctx, pr, chunk, "c64")
+    bound = 8 * np.sqrt(pr.n_gates) * U32
+    assert rel_err(r64["G"], res["G"]) <= bound and rel_err(T64, T) <= bound
 
 
 def chunked(q, ctx, pr, chunk, prec, want_G=True):
